@@ -1,0 +1,323 @@
+/*
+ * nep.h -- C ABI of the MI355X contour-integral moment library (libnep).
+ *
+ * Problem statement.  A nonlinear eigenvalue problem T(lambda) x = 0 is given
+ * in split form T(z) = sum_{i=1..ell} A_i f_i(z) (Campos & Roman, Section 2,
+ * eq. (split)), with constant n x n matrices A_i and scalar functions f_i
+ * described with the semantics of the paper's FN object (Section 3.2.2).
+ *
+ * The library computes, for a closed contour Gamma (a circle or an ellipse,
+ * the RG regions of Section 3.2.4), the moments
+ *
+ *     S_p = sum_j w_j zeta_j^p T(z_j)^{-1} V ,   p = 0 .. 2K-1,
+ *
+ * a trapezoid discretization of (1/(2 pi i)) oint phi(z)^p T(z)^{-1} V dz with
+ * phi(z) = (z-c)/rho.  By Keldysh's expansion of the resolvent (Section 2,
+ * eq. (resolvent)) only the eigenvalues inside Gamma contribute.  From the
+ * block-Hankel matrices of the moments it extracts a minimal invariant pair
+ * (Section 2, eqs. (invpair), (invpair-split)): the eigenvalues inside Gamma
+ * and their eigenvectors, with the backward error of eq. (sressplit) in
+ * infinity norms (Section 6).
+ *
+ * Conventions common to every call.
+ *   - Every call returns a nep_status: 0 (NEP_OK) or a negative error code.
+ *     No call aborts the process.  nep_last_error() returns a thread-local
+ *     message describing the last failure on the calling thread.
+ *   - Complex numbers are interleaved (re, im) pairs of doubles, compatible
+ *     with C99 double _Complex and with numpy complex128.
+ *   - Matrices passed in are column-major with a leading dimension.
+ *   - "device" pointers are HIP device memory on the current device (for
+ *     example the data_ptr() of a PyTorch tensor); "host" pointers are
+ *     ordinary process memory.  The library never frees caller memory.
+ *   - Streams are hipStream_t values passed as void*; NULL is the default
+ *     stream.
+ *   - Handles are not thread-safe: calls that use the same handle must not
+ *     overlap.  Distinct handles may be used concurrently on distinct
+ *     streams.
+ */
+#ifndef NEP_H
+#define NEP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int nep_status;
+
+enum {
+  NEP_OK = 0,
+  NEP_ERR_ARG = -1,             /* invalid argument (message says which)        */
+  NEP_ERR_OOM = -2,             /* device or host allocation failed             */
+  NEP_ERR_SINGULAR = -3,        /* exact zero pivot in T(z_j); node in stats    */
+  NEP_ERR_NOT_HOLOMORPHIC = -4, /* a node lies on a pole or branch cut of f_i   */
+  NEP_ERR_REFINE = -5,          /* refinement did not converge, fallback off    */
+  NEP_ERR_RANK = -6,            /* moment rank == K*L: increase L or K          */
+  NEP_ERR_DEVICE = -7,          /* HIP runtime error                            */
+  NEP_ERR_BUSY = -8             /* server: no slot or memory for the query now  */
+};
+
+/* ------------------------------------------------------------------------ */
+/* Scalar functions (FN semantics, Section 3.2.2)                            */
+/* ------------------------------------------------------------------------ */
+
+typedef enum {
+  NEP_FN_RATIONAL = 0, /* p(x)/q(x), coefficient lists highest degree first     */
+  NEP_FN_EXP = 1,      /* e^x                                                    */
+  NEP_FN_LOG = 2,      /* principal log, cut on (-inf, 0]                        */
+  NEP_FN_SQRT = 3,     /* principal square root, cut on (-inf, 0]                */
+  NEP_FN_INVSQRT = 4,  /* 1/sqrt(x), principal branch                            */
+  NEP_FN_PHI = 5,      /* phi_k: phi_0 = e^x, phi_k = (phi_{k-1} - 1/(k-1)!)/x   */
+  NEP_FN_COMBINE = 6   /* two functions combined by comb_op                      */
+} nep_fn_type;
+
+typedef enum {
+  NEP_COMB_ADD = 0,    /* a(x) + b(x)                                            */
+  NEP_COMB_MUL = 1,    /* a(x) * b(x)                                            */
+  NEP_COMB_DIV = 2,    /* a(x) / b(x)                                            */
+  NEP_COMB_COMPOSE = 3 /* b(a(x)): a is applied first                            */
+} nep_comb_op;
+
+/* f(z) = beta * g(alpha * z)  (the argument and result scaling of FNSetScale).
+ * Coefficient arrays, phi_k and the combine children are read during
+ * nep_split_create and copied; the caller may free them afterwards.
+ * A tree may hold at most 64 nodes and rational degrees at most 32. */
+typedef struct nep_fn {
+  int type;                      /* nep_fn_type                                  */
+  double alpha[2];               /* complex argument scale (1,0 for none)        */
+  double beta[2];                /* complex result scale (1,0 for none)          */
+  int nnum, nden;                /* RATIONAL: coefficient counts (nden may be 0) */
+  const double* num;             /* RATIONAL: host, nnum complex, highest first  */
+  const double* den;             /* RATIONAL: host, nden complex, highest first  */
+  int phi_k;                     /* PHI: k >= 0                                  */
+  int comb_op;                   /* COMBINE: nep_comb_op                         */
+  const struct nep_fn* comb_a;   /* COMBINE: first operand (host)                */
+  const struct nep_fn* comb_b;   /* COMBINE: second operand (host)               */
+} nep_fn;
+
+/* ------------------------------------------------------------------------ */
+/* Split operator handle (NEPSetSplitOperator, Section 3.2.2)                */
+/* ------------------------------------------------------------------------ */
+
+typedef enum {
+  NEP_MAT_REAL_F64 = 0,    /* real double, column-major                          */
+  NEP_MAT_COMPLEX_F64 = 1  /* complex double (interleaved), column-major         */
+} nep_mat_type;
+
+typedef struct {
+  int type;                /* nep_mat_type                                        */
+  const void* data;        /* n x n column-major matrix, leading dimension ld     */
+  long long ld;            /* >= n, in elements                                   */
+  int on_device;           /* 0: host pointer, 1: device pointer                  */
+} nep_mat;
+
+typedef struct nep_split_s* nep_split;
+
+/* Creates a handle for T(z) = sum_i f_i(z) A_i.
+ *   n      : matrix size, 1 <= n <= 8192.
+ *   ell    : number of terms, 1 <= ell <= 16.
+ *   A      : host array of ell matrix descriptors; the data are copied to the
+ *            device (stored row-major there) before the call returns.
+ *   f      : host array of ell function descriptors (copied).
+ *   stream : stream used by every call on this handle (NULL = default).
+ *   out    : receives the handle.
+ * Errors: NEP_ERR_ARG for bad sizes or descriptors, NEP_ERR_OOM,
+ * NEP_ERR_DEVICE. */
+nep_status nep_split_create(int n, int ell, const nep_mat* A, const nep_fn* f,
+                            void* stream, nep_split* out);
+
+/* Frees the handle, its device copies of A_i and its resident workspace
+ * (factors, solves), and sets *h = NULL (NEPDestroy(&nep) style). */
+nep_status nep_split_destroy(nep_split* h);
+
+/* Size n and term count ell of a handle. */
+nep_status nep_split_info(nep_split h, int* n, int* ell);
+
+/* ------------------------------------------------------------------------ */
+/* Moments                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Contour (RG region, Section 3.2.4).
+ *   kind 0: circle  z = c + rho e^{i theta}
+ *   kind 1: ellipse z = c + rho (cos theta + i v sin theta), v > 0
+ * Nodes sit at theta_j = 2 pi (j + 1/2)/N (counter-clockwise); weights
+ * w_j = rho (v cos theta_j + i sin theta_j)/N (v = 1 for a circle). */
+typedef struct {
+  int kind;
+  double c[2];   /* complex centre                                            */
+  double rho;    /* radius / horizontal semi-axis, > 0                        */
+  double v;      /* ellipse: vertical/horizontal semi-axis ratio, > 0         */
+} nep_contour;
+
+typedef enum {
+  NEP_PREC_FP64 = 0,     /* plain: complex FP64 assembly, LU (FP64 MFMA), solve */
+  NEP_PREC_C32_IR64 = 1  /* mixed: complex FP32 LU and solves on FP32 MFMA with
+                            FP64 residuals, corrections and moments             */
+} nep_precision;
+
+typedef struct {
+  int N;             /* quadrature nodes, 2 <= N <= 1024                        */
+  int L;             /* probe columns, 1 <= L <= 64                             */
+  int K;             /* Hankel block rows; moments p = 0..2K-1; 2K-1 <= N-1     */
+  int prec;          /* nep_precision                                          */
+  int max_refine;    /* refinement sweeps (mixed); 0..20, default 5             */
+  int fp64_fallback; /* 1: nodes whose refinement stalls are re-solved in FP64  */
+  double refine_tol; /* stop when ||R||_inf <= tol (||T||_inf ||Y||_inf + ||V||_inf)
+                        per probe column; 0 selects 1e-14                     */
+  void* stream;      /* NULL: the handle's stream                               */
+} nep_ciss_opts;
+
+typedef struct {
+  int N;                  /* nodes processed                                     */
+  int refine_sweeps;      /* sweeps run (max over nodes)                         */
+  int n_fallback;         /* nodes re-solved in FP64                             */
+  int n_unconverged;      /* nodes not meeting refine_tol after all sweeps       */
+  int singular_node;      /* first node with an exact zero pivot, or -1          */
+  int bad_node;           /* first node on a pole/branch cut, or -1              */
+  double max_rel_residual;/* max over nodes/columns of the final scaled residual */
+  float ms_total;         /* device time of the call (events), if synchronous    */
+} nep_ciss_stats;
+
+/* S_p = sum_j w_j zeta_j^p T(z_j)^{-1} V for p = 0..2K-1.
+ *   V : device, complex n x L, column-major (ld = n), caller-owned.
+ *   S : device, complex n x L x 2K, column-major; block p (n x L) starts at
+ *       S + p*n*L complex entries.  Overwritten.
+ *   st: if non-NULL the call waits for the stream, fills *st and returns
+ *       device-detected errors (NEP_ERR_SINGULAR, NEP_ERR_NOT_HOLOMORPHIC,
+ *       NEP_ERR_REFINE).  If NULL the call returns after enqueueing the work;
+ *       device-detected errors are then returned by nep_ciss_wait.
+ * The factors of T(z_j) stay resident in the handle until the next call with
+ * different (N, prec) or until destroy. */
+nep_status nep_ciss_moments(nep_split h, const nep_contour* g,
+                            const nep_ciss_opts* o, const void* V, void* S,
+                            nep_ciss_stats* st);
+
+/* Waits for the last nep_ciss_moments on h and reports its status/stats. */
+nep_status nep_ciss_wait(nep_split h, nep_ciss_stats* st);
+
+/* ------------------------------------------------------------------------ */
+/* Extraction (minimal invariant pair, Section 2)                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  double rank_tol;  /* keep singular values > rank_tol * sigma_1; 0 -> 1e-12    */
+  int max_eigs;     /* capacity of the output arrays (>= 1)                     */
+} nep_extract_opts;
+
+/* From S (as written by nep_ciss_moments with the same g and o) computes the
+ * eigenpairs of the minimal invariant pair carried by the moments.
+ *   m      : host, number of eigenpairs returned (= the numerical rank).
+ *   lambda : host, 2*max_eigs doubles: complex eigenvalues, sorted by
+ *            (Re, Im).
+ *   X      : device, complex n x max_eigs column-major: eigenvectors,
+ *            ||x||_2 = 1, largest-modulus entry real positive.
+ *   eta    : host, max_eigs doubles: backward error eq. (sressplit), inf-norms.
+ *   inside : host, max_eigs ints: 1 if the eigenvalue lies inside the contour.
+ *   sigma  : host, optional (may be NULL), K*L doubles: singular values of the
+ *            block-Hankel matrix B0.
+ * Synchronous.  NEP_ERR_RANK if every one of the K*L singular values is
+ * significant (the contour holds more eigenvalues than K*L can resolve);
+ * NEP_ERR_ARG if the rank exceeds max_eigs. */
+nep_status nep_extract(nep_split h, const nep_contour* g, const nep_ciss_opts* o,
+                       const void* S, const nep_extract_opts* e, int* m,
+                       double* lambda, void* X, double* eta, int* inside,
+                       double* sigma);
+
+/* Backward errors eq. (sressplit) (inf-norms) of m given pairs.
+ *   lambda: host, m complex; X: device, complex n x m column-major;
+ *   eta: host, m doubles. */
+nep_status nep_backward_error(nep_split h, int m, const double* lambda,
+                              const void* X, double* eta);
+
+/* Values f_i(z) for ell functions at m host points (complex): out[i*m + k]
+ * (host, ell*m complex).  Points on a pole or cut give NEP_ERR_NOT_HOLOMORPHIC. */
+nep_status nep_fn_eval(nep_split h, int m, const double* z, double* out);
+
+/* ------------------------------------------------------------------------ */
+/* Batched moments: many problems of uneven n in one plan                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct nep_batch_s* nep_batch;
+
+/* Plans the moments of nprob problems sharing (N, L, K, prec) into one set of
+ * batched launches over every (problem, node) pair, sorted by size, and
+ * captures the launch sequence in a HIP graph.  V[p] and S[p] are device
+ * buffers as in nep_ciss_moments; they are bound to the plan (the graph reads
+ * and writes exactly these buffers on every run).
+ *   use_graph: 1 = capture and replay a HIP graph, 0 = eager launches. */
+nep_status nep_batch_create(int nprob, const nep_split* h,
+                            const nep_contour* g, const nep_ciss_opts* o,
+                            const void* const* V, void* const* S,
+                            int use_graph, void* stream, nep_batch* out);
+
+/* Runs the plan.  st (optional, nprob entries) as in nep_ciss_moments; if
+ * non-NULL the call is synchronous. */
+nep_status nep_batch_run(nep_batch b, nep_ciss_stats* st);
+
+nep_status nep_batch_destroy(nep_batch* b);
+
+/* One-shot: create, run synchronously, destroy. */
+nep_status nep_ciss_moments_batch(int nprob, const nep_split* h,
+                                  const nep_contour* g, const nep_ciss_opts* o,
+                                  const void* const* V, void* const* S,
+                                  nep_ciss_stats* st);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: "eigenvalues inside this contour" queries, continuous batching   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct nep_server_s* nep_server;
+
+typedef struct {
+  long long hbm_budget;  /* bytes of device memory the server may hold for
+                            per-query workspaces (factors, solves, moments)   */
+  int max_inflight;      /* queries on the device at once (>= 1)              */
+  int nstreams;          /* device streams used to overlap queries (>= 1)     */
+} nep_server_opts;
+
+typedef struct {
+  int status;            /* nep_status of the query                            */
+  int m;                 /* eigenpairs returned                                */
+  int n_inside;          /* of which inside the contour                        */
+  double t_submit, t_start, t_done;  /* seconds on the server clock            */
+} nep_query_info;
+
+nep_status nep_server_create(const nep_server_opts* o, nep_server* out);
+
+/* Queues a query: moments and extraction of h inside g.
+ *   V: host, complex n x L column-major (copied before the call returns).
+ *   Results are written to the host arrays lambda (2*max_eigs), eta
+ *   (max_eigs), inside (max_eigs) and, if X is non-NULL, to host X
+ *   (complex n x max_eigs), when the query completes; they must stay valid
+ *   until then.  *ticket identifies the query.
+ * Returns NEP_ERR_BUSY only if the query can never fit the HBM budget. */
+nep_status nep_server_submit(nep_server s, nep_split h, const nep_contour* g,
+                             const nep_ciss_opts* o, const nep_extract_opts* e,
+                             const void* V, double* lambda, double* eta,
+                             int* inside, void* X, long long* ticket);
+
+/* Non-blocking: returns 1 in *done when the query has finished. */
+nep_status nep_server_poll(nep_server s, long long ticket, int* done,
+                           nep_query_info* info);
+
+/* Blocks until the query has finished. */
+nep_status nep_server_wait(nep_server s, long long ticket, nep_query_info* info);
+
+/* Current clock of the server (seconds), for latency accounting. */
+double nep_server_clock(nep_server s);
+
+/* Drains every queued query and frees the server. */
+nep_status nep_server_destroy(nep_server* s);
+
+/* ------------------------------------------------------------------------ */
+
+/* Thread-local description of the last error on the calling thread. */
+const char* nep_last_error(void);
+
+/* Library version string. */
+const char* nep_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEP_H */

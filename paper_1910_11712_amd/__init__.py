@@ -1,0 +1,81 @@
+"""MI355X contour-integral moments for split-form nonlinear eigenproblems.
+
+The product is the HIP library libnep.so (C ABI in include/nep.h).  This
+package is its thin Python binding: `binding` mirrors the C entry points
+(same names) and `SplitOperator` wraps a handle for convenience.  PyTorch is
+used for device memory and streams only.
+"""
+import numpy as np
+
+from . import binding
+from .binding import (NepError, nep_split_create, nep_split_destroy, nep_ciss_moments, nep_ciss_wait,
+                      nep_extract, nep_backward_error, nep_fn_eval, opts_struct, contour_struct)
+
+__all__ = ["NepError", "SplitOperator", "binding", "nep_split_create", "nep_split_destroy",
+           "nep_ciss_moments", "nep_ciss_wait", "nep_extract", "nep_backward_error", "nep_fn_eval",
+           "device_probes", "moments_to_numpy"]
+
+
+def device_probes(V, device="cuda"):
+    """numpy (n x L) complex -> CUDA tensor holding the column-major block."""
+    import torch
+    V = np.asarray(V, dtype=np.complex128)
+    return torch.from_numpy(np.ascontiguousarray(V.T)).to(device)
+
+
+def moments_to_numpy(S):
+    """CUDA tensor (2K, L, n) of column-major blocks -> numpy (2K, n, L)."""
+    return np.ascontiguousarray(S.cpu().numpy().transpose(0, 2, 1))
+
+
+class SplitOperator:
+    """T(z) = sum_i f_i(z) A_i held on the device (nep_split handle)."""
+
+    def __init__(self, mats, fns, stream=None):
+        self.n = int(mats[0].shape[0])
+        self.ell = len(mats)
+        self.h = nep_split_create(mats, fns, stream)
+
+    @classmethod
+    def from_problem(cls, problem, stream=None):
+        return cls(problem.mats, problem.fns, stream)
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            nep_split_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def moments(self, contour, V, N, L, K, prec="mixed", max_refine=None, fallback=True, tol=0.0, S=None,
+                sync=True, stream=None):
+        """Returns (S tensor (2K, L, n), stats).  V: CUDA tensor (L, n)."""
+        import torch
+        if S is None:
+            S = torch.empty((2 * K, L, self.n), dtype=torch.complex128, device=V.device)
+        o = opts_struct(N, L, K, prec, max_refine, fallback, tol, stream)
+        st = nep_ciss_moments(self.h, contour, o, V, S, sync=sync)
+        return S, st
+
+    def wait(self):
+        return nep_ciss_wait(self.h)
+
+    def extract(self, contour, S, N, L, K, prec="mixed", max_eigs=64, rank_tol=0.0, X=None, stream=None):
+        import torch
+        if X is None:
+            X = torch.zeros((max_eigs, self.n), dtype=torch.complex128, device=S.device)
+        o = opts_struct(N, L, K, prec, None, True, 0.0, stream)
+        r = nep_extract(self.h, contour, o, S, X, max_eigs, rank_tol)
+        r["X_dev"] = X
+        r["X"] = X[: r["m"]].cpu().numpy().T.copy()
+        return r
+
+    def backward_error(self, lam, X):
+        return nep_backward_error(self.h, lam, X)
+
+    def fn_eval(self, z):
+        return nep_fn_eval(self.h, self.ell, z)

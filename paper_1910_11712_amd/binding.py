@@ -1,0 +1,293 @@
+"""Thin ctypes binding of libnep (include/nep.h).
+
+Argument marshalling only: every step of the moment path runs in the HIP
+library.  PyTorch provides device memory (tensor data pointers) and streams.
+If the library is missing the import of this module fails loudly; there is
+no CPU fallback.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnep.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "nep.h")
+
+NEP_OK = 0
+ERRORS = {-1: "NEP_ERR_ARG", -2: "NEP_ERR_OOM", -3: "NEP_ERR_SINGULAR",
+          -4: "NEP_ERR_NOT_HOLOMORPHIC", -5: "NEP_ERR_REFINE", -6: "NEP_ERR_RANK",
+          -7: "NEP_ERR_DEVICE", -8: "NEP_ERR_BUSY"}
+FN_TYPES = {"rational": 0, "exp": 1, "log": 2, "sqrt": 3, "invsqrt": 4, "phi": 5, "combine": 6}
+PREC = {"fp64": 0, "mixed": 1}
+
+
+class NepError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class nep_fn(C.Structure):
+    pass
+
+
+nep_fn._fields_ = [("type", C.c_int), ("alpha", C.c_double * 2), ("beta", C.c_double * 2),
+                   ("nnum", C.c_int), ("nden", C.c_int),
+                   ("num", C.POINTER(C.c_double)), ("den", C.POINTER(C.c_double)),
+                   ("phi_k", C.c_int), ("comb_op", C.c_int),
+                   ("comb_a", C.POINTER(nep_fn)), ("comb_b", C.POINTER(nep_fn))]
+
+
+class nep_mat(C.Structure):
+    _fields_ = [("type", C.c_int), ("data", C.c_void_p), ("ld", C.c_longlong), ("on_device", C.c_int)]
+
+
+class nep_contour(C.Structure):
+    _fields_ = [("kind", C.c_int), ("c", C.c_double * 2), ("rho", C.c_double), ("v", C.c_double)]
+
+
+class nep_ciss_opts(C.Structure):
+    _fields_ = [("N", C.c_int), ("L", C.c_int), ("K", C.c_int), ("prec", C.c_int),
+                ("max_refine", C.c_int), ("fp64_fallback", C.c_int), ("refine_tol", C.c_double),
+                ("stream", C.c_void_p)]
+
+
+class nep_ciss_stats(C.Structure):
+    _fields_ = [("N", C.c_int), ("refine_sweeps", C.c_int), ("n_fallback", C.c_int),
+                ("n_unconverged", C.c_int), ("singular_node", C.c_int), ("bad_node", C.c_int),
+                ("max_rel_residual", C.c_double), ("ms_total", C.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class nep_extract_opts(C.Structure):
+    _fields_ = [("rank_tol", C.c_double), ("max_eigs", C.c_int)]
+
+
+class nep_server_opts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_longlong), ("max_inflight", C.c_int), ("nstreams", C.c_int)]
+
+
+class nep_query_info(C.Structure):
+    _fields_ = [("status", C.c_int), ("m", C.c_int), ("n_inside", C.c_int),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+_lib = None
+
+
+def declared_symbols():
+    """Function names declared in include/nep.h."""
+    with open(HEADER) as fh:
+        txt = fh.read()
+    return sorted(set(re.findall(r"\b(nep_[a-z0-9_]+)\s*\(", txt)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libnep.so not built ({LIB_PATH}); run paper_1910_11712_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, ip = C.c_void_p, C.c_int
+        L.nep_last_error.restype = C.c_char_p
+        L.nep_version.restype = C.c_char_p
+        L.nep_split_create.argtypes = [ip, ip, C.POINTER(nep_mat), C.POINTER(nep_fn), vp, C.POINTER(vp)]
+        L.nep_split_destroy.argtypes = [C.POINTER(vp)]
+        L.nep_split_info.argtypes = [vp, C.POINTER(ip), C.POINTER(ip)]
+        L.nep_ciss_moments.argtypes = [vp, C.POINTER(nep_contour), C.POINTER(nep_ciss_opts), vp, vp,
+                                       C.POINTER(nep_ciss_stats)]
+        L.nep_ciss_wait.argtypes = [vp, C.POINTER(nep_ciss_stats)]
+        L.nep_extract.argtypes = [vp, C.POINTER(nep_contour), C.POINTER(nep_ciss_opts), vp,
+                                  C.POINTER(nep_extract_opts), C.POINTER(ip), C.POINTER(C.c_double), vp,
+                                  C.POINTER(C.c_double), C.POINTER(ip), C.POINTER(C.c_double)]
+        L.nep_backward_error.argtypes = [vp, ip, C.POINTER(C.c_double), vp, C.POINTER(C.c_double)]
+        L.nep_fn_eval.argtypes = [vp, ip, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.nep_batch_create.argtypes = [ip, C.POINTER(vp), C.POINTER(nep_contour), C.POINTER(nep_ciss_opts),
+                                       C.POINTER(vp), C.POINTER(vp), ip, vp, C.POINTER(vp)]
+        L.nep_batch_run.argtypes = [vp, C.POINTER(nep_ciss_stats)]
+        L.nep_batch_destroy.argtypes = [C.POINTER(vp)]
+        L.nep_ciss_moments_batch.argtypes = [ip, C.POINTER(vp), C.POINTER(nep_contour), C.POINTER(nep_ciss_opts),
+                                             C.POINTER(vp), C.POINTER(vp), C.POINTER(nep_ciss_stats)]
+        if not hasattr(L, "nep_server_create"):
+            _lib = L
+            return _lib
+        L.nep_server_create.argtypes = [C.POINTER(nep_server_opts), C.POINTER(vp)]
+        L.nep_server_submit.argtypes = [vp, vp, C.POINTER(nep_contour), C.POINTER(nep_ciss_opts),
+                                        C.POINTER(nep_extract_opts), vp, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(ip), vp, C.POINTER(C.c_longlong)]
+        L.nep_server_poll.argtypes = [vp, C.c_longlong, C.POINTER(ip), C.POINTER(nep_query_info)]
+        L.nep_server_wait.argtypes = [vp, C.c_longlong, C.POINTER(nep_query_info)]
+        L.nep_server_clock.argtypes = [vp]
+        L.nep_server_clock.restype = C.c_double
+        L.nep_server_destroy.argtypes = [C.POINTER(vp)]
+        _lib = L
+    return _lib
+
+
+def check(code):
+    if code != NEP_OK:
+        raise NepError(code, lib().nep_last_error().decode())
+    return code
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+
+def _cplx_array(vals):
+    a = np.zeros(2 * max(1, len(vals)), dtype=np.float64)
+    for i, v in enumerate(vals):
+        a[2 * i], a[2 * i + 1] = complex(v).real, complex(v).imag
+    return a
+
+
+def make_fn(desc, keep):
+    """workloads FN descriptor (dict) -> nep_fn; `keep` holds the buffers."""
+    f = nep_fn()
+    f.type = FN_TYPES[desc["type"]]
+    a, b = complex(desc.get("alpha", 1.0)), complex(desc.get("beta", 1.0))
+    f.alpha[0], f.alpha[1] = a.real, a.imag
+    f.beta[0], f.beta[1] = b.real, b.imag
+    if desc["type"] == "rational":
+        num, den = _cplx_array(desc["num"]), _cplx_array(desc["den"])
+        keep += [num, den]
+        f.nnum, f.nden = len(desc["num"]), len(desc["den"])
+        f.num = num.ctypes.data_as(C.POINTER(C.c_double))
+        f.den = den.ctypes.data_as(C.POINTER(C.c_double))
+    elif desc["type"] == "phi":
+        f.phi_k = int(desc["k"])
+    elif desc["type"] == "combine":
+        f.comb_op = int(desc["op"])
+        fa, fb = make_fn(desc["a"], keep), make_fn(desc["b"], keep)
+        keep += [fa, fb]
+        f.comb_a = C.pointer(fa)
+        f.comb_b = C.pointer(fb)
+    return f
+
+
+def contour_struct(con):
+    g = nep_contour()
+    g.kind = int(con.kind)
+    g.c[0], g.c[1] = complex(con.c).real, complex(con.c).imag
+    g.rho = float(con.rho)
+    g.v = float(con.v)
+    return g
+
+
+def opts_struct(N, L, K, prec="mixed", max_refine=None, fallback=True, tol=0.0, stream=None):
+    o = nep_ciss_opts()
+    o.N, o.L, o.K = int(N), int(L), int(K)
+    o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    if max_refine is None:
+        max_refine = 5 if o.prec == PREC["mixed"] else 0
+    o.max_refine = int(max_refine)
+    o.fp64_fallback = 1 if fallback else 0
+    o.refine_tol = float(tol)
+    o.stream = stream
+    return o
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream)
+
+
+# ---------------------------------------------------------------------------
+# C-ABI names
+# ---------------------------------------------------------------------------
+
+def nep_split_create(mats, fns, stream=None):
+    """mats: list of numpy (n x n, float64 or complex128); fns: FN dicts."""
+    n = int(mats[0].shape[0])
+    ell = len(mats)
+    keep = []
+    marr = (nep_mat * ell)()
+    for i, A in enumerate(mats):
+        if np.iscomplexobj(A):
+            A = np.asfortranarray(A, dtype=np.complex128)
+            marr[i].type = 1
+        else:
+            A = np.asfortranarray(A, dtype=np.float64)
+            marr[i].type = 0
+        keep.append(A)
+        marr[i].data = A.ctypes.data
+        marr[i].ld = n
+        marr[i].on_device = 0
+    farr = (nep_fn * ell)()
+    for i, d in enumerate(fns):
+        farr[i] = make_fn(d, keep)
+    h = C.c_void_p()
+    check(lib().nep_split_create(n, ell, marr, farr, _stream_ptr(stream), C.byref(h)))
+    return h
+
+
+def nep_split_destroy(h):
+    hh = C.c_void_p(h.value if isinstance(h, C.c_void_p) else h)
+    check(lib().nep_split_destroy(C.byref(hh)))
+
+
+def nep_ciss_moments(h, contour, opts, V, S, sync=True):
+    """V, S: CUDA complex128 tensors (n x L and 2K x L x n views of
+    column-major storage, see Split.moments)."""
+    st = nep_ciss_stats() if sync else None
+    code = lib().nep_ciss_moments(h, C.byref(contour_struct(contour)), C.byref(opts), C.c_void_p(V.data_ptr()),
+                                  C.c_void_p(S.data_ptr()), C.byref(st) if st is not None else None)
+    check(code)
+    return st.as_dict() if st is not None else None
+
+
+def nep_ciss_wait(h):
+    st = nep_ciss_stats()
+    check(lib().nep_ciss_wait(h, C.byref(st)))
+    return st.as_dict()
+
+
+def nep_extract(h, contour, opts, S, X, max_eigs=64, rank_tol=0.0):
+    e = nep_extract_opts()
+    e.rank_tol, e.max_eigs = float(rank_tol), int(max_eigs)
+    m = C.c_int(0)
+    lam = np.zeros(2 * max_eigs)
+    eta = np.zeros(max_eigs)
+    ins = np.zeros(max_eigs, dtype=np.int32)
+    sig = np.zeros(opts.K * opts.L)
+    code = lib().nep_extract(h, C.byref(contour_struct(contour)), C.byref(opts), C.c_void_p(S.data_ptr()),
+                             C.byref(e), C.byref(m), lam.ctypes.data_as(C.POINTER(C.c_double)),
+                             C.c_void_p(X.data_ptr()), eta.ctypes.data_as(C.POINTER(C.c_double)),
+                             ins.ctypes.data_as(C.POINTER(C.c_int)), sig.ctypes.data_as(C.POINTER(C.c_double)))
+    k = m.value
+    if code != NEP_OK:
+        err = NepError(code, lib().nep_last_error().decode())
+        err.m = k
+        err.sigma = sig
+        raise err
+    lam_c = lam[0:2 * k:2] + 1j * lam[1:2 * k:2]
+    return {"m": k, "lam": lam_c, "eta": eta[:k].copy(), "inside": ins[:k].astype(bool), "sigma": sig}
+
+
+def nep_backward_error(h, lam, X):
+    lam = np.asarray(lam, dtype=np.complex128)
+    m = len(lam)
+    la = np.zeros(2 * m)
+    la[0::2], la[1::2] = lam.real, lam.imag
+    eta = np.zeros(m)
+    check(lib().nep_backward_error(h, m, la.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(X.data_ptr()),
+                                   eta.ctypes.data_as(C.POINTER(C.c_double))))
+    return eta
+
+
+def nep_fn_eval(h, ell, z):
+    z = np.asarray(z, dtype=np.complex128).ravel()
+    m = len(z)
+    zi = np.zeros(2 * m)
+    zi[0::2], zi[1::2] = z.real, z.imag
+    out = np.zeros(2 * m * ell)
+    check(lib().nep_fn_eval(h, m, zi.ctypes.data_as(C.POINTER(C.c_double)),
+                            out.ctypes.data_as(C.POINTER(C.c_double))))
+    return (out[0::2] + 1j * out[1::2]).reshape(ell, m)

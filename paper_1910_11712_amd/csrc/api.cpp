@@ -1,0 +1,301 @@
+// C ABI of libnep: split-operator handles, moments, batches (see nep.h).
+#include <cstdarg>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "handle.hpp"
+
+namespace nep {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+const char* last_error() { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// FN trees -> flat node array (children before use; depth-limited)
+// ---------------------------------------------------------------------------
+static nep_status flatten(const nep_fn* f, int depth, std::vector<FnNode>& nodes, std::vector<c128>& coef,
+                          int* out_index) {
+  NEP_CHECK(f != nullptr, NEP_ERR_ARG, "null function descriptor");
+  NEP_CHECK(depth <= kMaxFnDepth, NEP_ERR_ARG, "function tree deeper than %d", kMaxFnDepth);
+  NEP_CHECK((int)nodes.size() < kMaxFnNodes, NEP_ERR_ARG, "function tree larger than %d nodes", kMaxFnNodes);
+  FnNode nd{};
+  nd.type = f->type;
+  nd.alpha = c128{f->alpha[0], f->alpha[1]};
+  nd.beta = c128{f->beta[0], f->beta[1]};
+  nd.a = nd.b = -1;
+  switch (f->type) {
+    case NEP_FN_RATIONAL:
+      NEP_CHECK(f->nnum >= 1 && f->nnum <= kMaxCoeffs && f->nden >= 0 && f->nden <= kMaxCoeffs, NEP_ERR_ARG,
+                "rational function: need 1..%d numerator and 0..%d denominator coefficients", kMaxCoeffs,
+                kMaxCoeffs);
+      NEP_CHECK(f->num != nullptr && (f->nden == 0 || f->den != nullptr), NEP_ERR_ARG,
+                "rational function: null coefficient array");
+      nd.num_off = (int)coef.size();
+      nd.nnum = f->nnum;
+      for (int i = 0; i < f->nnum; ++i) coef.push_back(c128{f->num[2 * i], f->num[2 * i + 1]});
+      nd.den_off = (int)coef.size();
+      nd.nden = f->nden;
+      for (int i = 0; i < f->nden; ++i) coef.push_back(c128{f->den[2 * i], f->den[2 * i + 1]});
+      if (f->nden > 0) {
+        bool allzero = true;
+        for (int i = 0; i < f->nden; ++i) allzero &= (f->den[2 * i] == 0.0 && f->den[2 * i + 1] == 0.0);
+        NEP_CHECK(!allzero, NEP_ERR_ARG, "rational function: zero denominator polynomial");
+      }
+      break;
+    case NEP_FN_EXP:
+    case NEP_FN_LOG:
+    case NEP_FN_SQRT:
+    case NEP_FN_INVSQRT:
+      break;
+    case NEP_FN_PHI:
+      NEP_CHECK(f->phi_k >= 0 && f->phi_k <= 20, NEP_ERR_ARG, "phi_k: k must be in 0..20");
+      nd.phi_k = f->phi_k;
+      break;
+    case NEP_FN_COMBINE: {
+      NEP_CHECK(f->comb_op >= NEP_COMB_ADD && f->comb_op <= NEP_COMB_COMPOSE, NEP_ERR_ARG, "bad combine op %d",
+                f->comb_op);
+      nd.op = f->comb_op;
+      int ia, ib;
+      NEP_TRY(flatten(f->comb_a, depth + 1, nodes, coef, &ia));
+      NEP_TRY(flatten(f->comb_b, depth + 1, nodes, coef, &ib));
+      nd.a = ia;
+      nd.b = ib;
+      break;
+    }
+    default:
+      NEP_CHECK(false, NEP_ERR_ARG, "unknown function type %d", f->type);
+  }
+  *out_index = (int)nodes.size();
+  nodes.push_back(nd);
+  return NEP_OK;
+}
+
+hipError_t to_rowmajor(const void* in, long long ld, int n, int cplx, void* out, hipStream_t st);
+hipError_t inf_norm(const void* A, int n, int cplx, unsigned long long* scratch, double* out, hipStream_t st);
+hipError_t fn_points(const FnNode* nodes, const c128* coef, const int* roots, int ell, const c128* z, int m,
+                     c128* out, int* bad, hipStream_t st);
+
+nep_status Split::init(int n_, int ell_, const nep_mat* A, const nep_fn* f, hipStream_t st) {
+  stream = st;
+  op.n = n_;
+  op.ell = ell_;
+  NEP_TRY(configure_kernels());
+  // functions
+  std::vector<FnNode> nodes;
+  std::vector<c128> coef;
+  for (int i = 0; i < ell_; ++i) NEP_TRY(flatten(&f[i], 1, nodes, coef, &op.fn_root[i]));
+  if (coef.empty()) coef.push_back(c128{0.0, 0.0});
+  NEP_TRY(fn_nodes.alloc(sizeof(FnNode) * nodes.size()));
+  NEP_TRY(fn_coef.alloc(sizeof(c128) * coef.size()));
+  NEP_TRY(fn_roots.alloc(sizeof(int) * kMaxTerms));
+  NEP_HIP(hipMemcpy(fn_nodes.p, nodes.data(), sizeof(FnNode) * nodes.size(), hipMemcpyHostToDevice));
+  NEP_HIP(hipMemcpy(fn_coef.p, coef.data(), sizeof(c128) * coef.size(), hipMemcpyHostToDevice));
+  NEP_HIP(hipMemcpy(fn_roots.p, op.fn_root, sizeof(int) * kMaxTerms, hipMemcpyHostToDevice));
+  op.dfn_nodes = fn_nodes.as<FnNode>();
+  op.dfn_coef = fn_coef.as<c128>();
+  // matrices: upload column-major, convert to row-major on the device
+  NEP_TRY(norms.alloc(sizeof(double) * kMaxTerms + sizeof(unsigned long long) * 2));
+  op.dnormA = norms.as<double>();
+  unsigned long long* scratch = reinterpret_cast<unsigned long long*>(norms.as<char>() + sizeof(double) * kMaxTerms);
+  op.a_cplx = 0;
+  for (int i = 0; i < ell_; ++i) {
+    const int cplx = A[i].type == NEP_MAT_COMPLEX_F64;
+    op.is_cplx[i] = cplx;
+    op.a_cplx |= cplx;
+    const size_t words = cplx ? 2 : 1;
+    const size_t bytes = (size_t)n_ * n_ * words * sizeof(double);
+    mats[i] = std::make_unique<DevMem>();
+    NEP_TRY(mats[i]->alloc(bytes));
+    const void* src = A[i].data;
+    DevMem staging;
+    if (!A[i].on_device) {
+      NEP_TRY(staging.alloc((size_t)A[i].ld * n_ * words * sizeof(double)));
+      NEP_HIP(hipMemcpyAsync(staging.p, A[i].data, (size_t)A[i].ld * n_ * words * sizeof(double),
+                             hipMemcpyHostToDevice, stream));
+      src = staging.p;
+    }
+    NEP_HIP(to_rowmajor(src, A[i].ld, n_, cplx, mats[i]->p, stream));
+    NEP_HIP(inf_norm(mats[i]->p, n_, cplx, scratch, norms.as<double>() + i, stream));
+    NEP_HIP(hipStreamSynchronize(stream));  // staging is released at scope end
+    op.dA[i] = mats[i]->p;
+  }
+  op.normA.assign(ell_, 0.0);
+  NEP_HIP(hipMemcpy(op.normA.data(), op.dnormA, sizeof(double) * ell_, hipMemcpyDeviceToHost));
+  return NEP_OK;
+}
+
+nep_status Split::eval_fns(int m, const c128* zh, std::vector<c128>& out, std::vector<int>& bad) {
+  DevMem dz, dout, dbad;
+  NEP_TRY(dz.alloc(sizeof(c128) * m));
+  NEP_TRY(dout.alloc(sizeof(c128) * m * op.ell));
+  NEP_TRY(dbad.alloc(sizeof(int) * m));
+  NEP_HIP(hipMemcpyAsync(dz.p, zh, sizeof(c128) * m, hipMemcpyHostToDevice, stream));
+  NEP_HIP(fn_points(op.dfn_nodes, op.dfn_coef, fn_roots.as<int>(), op.ell, dz.as<c128>(), m, dout.as<c128>(),
+                    dbad.as<int>(), stream));
+  out.resize((size_t)m * op.ell);
+  bad.resize(m);
+  NEP_HIP(hipMemcpyAsync(out.data(), dout.p, sizeof(c128) * m * op.ell, hipMemcpyDeviceToHost, stream));
+  NEP_HIP(hipMemcpyAsync(bad.data(), dbad.p, sizeof(int) * m, hipMemcpyDeviceToHost, stream));
+  NEP_HIP(hipStreamSynchronize(stream));
+  return NEP_OK;
+}
+
+nep_status check_contour(const nep_contour* g) {
+  NEP_CHECK(g != nullptr, NEP_ERR_ARG, "null contour");
+  NEP_CHECK(g->kind == 0 || g->kind == 1, NEP_ERR_ARG, "contour kind must be 0 (circle) or 1 (ellipse)");
+  NEP_CHECK(g->rho > 0.0 && std::isfinite(g->rho), NEP_ERR_ARG, "contour radius must be positive");
+  NEP_CHECK(g->kind == 0 || (g->v > 0.0 && std::isfinite(g->v)), NEP_ERR_ARG, "ellipse ratio v must be positive");
+  NEP_CHECK(std::isfinite(g->c[0]) && std::isfinite(g->c[1]), NEP_ERR_ARG, "contour centre must be finite");
+  return NEP_OK;
+}
+
+nep_status check_opts(const nep_ciss_opts* o, PlanOptions& po) {
+  NEP_CHECK(o != nullptr, NEP_ERR_ARG, "null options");
+  NEP_CHECK(o->N >= 2 && o->N <= 1024, NEP_ERR_ARG, "N must be in 2..1024");
+  NEP_CHECK(o->L >= 1 && o->L <= 64, NEP_ERR_ARG, "L must be in 1..64");
+  NEP_CHECK(o->K >= 1 && 2 * o->K <= kMaxMoments, NEP_ERR_ARG, "K must be in 1..%d", kMaxMoments / 2);
+  NEP_CHECK(2 * o->K - 1 <= o->N - 1, NEP_ERR_ARG, "need 2K-1 <= N-1 (moments beyond the trapezoid's exactness)");
+  NEP_CHECK(o->prec == NEP_PREC_FP64 || o->prec == NEP_PREC_C32_IR64, NEP_ERR_ARG, "unknown precision %d", o->prec);
+  NEP_CHECK(o->max_refine >= 0 && o->max_refine <= 20, NEP_ERR_ARG, "max_refine must be in 0..20");
+  NEP_CHECK(o->refine_tol >= 0.0, NEP_ERR_ARG, "refine_tol must be >= 0");
+  po.N = o->N;
+  po.L = o->L;
+  po.K = o->K;
+  po.prec = o->prec;
+  po.max_refine = o->max_refine;
+  po.fallback = o->fp64_fallback ? 1 : 0;
+  po.tol = o->refine_tol > 0.0 ? o->refine_tol : 1e-14;
+  return NEP_OK;
+}
+
+nep_status Split::moments(const nep_contour* g, const nep_ciss_opts* o, const void* V, void* S,
+                          nep_ciss_stats* st) {
+  NEP_TRY(check_contour(g));
+  PlanOptions po;
+  NEP_TRY(check_opts(o, po));
+  NEP_CHECK(V != nullptr && S != nullptr, NEP_ERR_ARG, "null V or S");
+  hipStream_t s = o->stream ? (hipStream_t)o->stream : stream;
+  std::vector<PlanProblem> probs{PlanProblem{&op, *g, (const c128*)V, (c128*)S}};
+  if (!plan || !plan->matches(probs, po) || plan->opt.max_refine != po.max_refine ||
+      plan->opt.fallback != po.fallback) {
+    plan = std::make_unique<MomentsPlan>();
+    nep_status bs = plan->build(probs, po);
+    if (bs != NEP_OK) {
+      plan.reset();
+      return bs;
+    }
+  } else {
+    plan->opt.tol = po.tol;
+    NEP_TRY(plan->rebind(probs));
+  }
+  last_stream = s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (st) {
+    NEP_HIP(hipEventCreate(&e0));
+    NEP_HIP(hipEventCreate(&e1));
+    NEP_HIP(hipEventRecord(e0, s));
+  }
+  nep_status rs = plan->enqueue(s, true);
+  if (rs != NEP_OK) return rs;
+  pending = true;
+  if (!st) return NEP_OK;
+  NEP_HIP(hipEventRecord(e1, s));
+  nep_status ws = wait(st);
+  float ms = 0.f;
+  if (hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  st->ms_total = ms;
+  return ws;
+}
+
+nep_status Split::wait(nep_ciss_stats* st) {
+  NEP_CHECK(plan != nullptr && pending, NEP_ERR_ARG, "no moments call pending on this handle");
+  RunResult rr;
+  nep_status s = plan->finish(last_stream, rr, true);
+  pending = false;
+  if (st && !rr.stats.empty()) *st = rr.stats[0];
+  return s;
+}
+
+}  // namespace nep
+
+using namespace nep;
+
+extern "C" {
+
+const char* nep_last_error(void) { return nep::last_error(); }
+const char* nep_version(void) { return "libnep 0.1 (gfx950)"; }
+
+nep_status nep_split_create(int n, int ell, const nep_mat* A, const nep_fn* f, void* stream, nep_split* out) {
+  NEP_CHECK(out != nullptr, NEP_ERR_ARG, "null output handle");
+  *out = nullptr;
+  NEP_CHECK(n >= 1 && n <= 4096, NEP_ERR_ARG, "n must be in 1..4096");
+  NEP_CHECK(ell >= 1 && ell <= kMaxTerms, NEP_ERR_ARG, "ell must be in 1..%d", kMaxTerms);
+  NEP_CHECK(A != nullptr && f != nullptr, NEP_ERR_ARG, "null matrix or function array");
+  for (int i = 0; i < ell; ++i) {
+    NEP_CHECK(A[i].type == NEP_MAT_REAL_F64 || A[i].type == NEP_MAT_COMPLEX_F64, NEP_ERR_ARG,
+              "matrix %d: unknown type %d", i, A[i].type);
+    NEP_CHECK(A[i].data != nullptr, NEP_ERR_ARG, "matrix %d: null data", i);
+    NEP_CHECK(A[i].ld >= n, NEP_ERR_ARG, "matrix %d: ld < n", i);
+  }
+  auto h = std::make_unique<nep_split_s>();
+  nep_status s = h->impl.init(n, ell, A, f, (hipStream_t)stream);
+  if (s != NEP_OK) return s;
+  *out = h.release();
+  return NEP_OK;
+}
+
+nep_status nep_split_destroy(nep_split* h) {
+  NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle pointer");
+  if (*h) {
+    (void)hipStreamSynchronize((*h)->impl.stream);
+    delete *h;
+  }
+  *h = nullptr;
+  return NEP_OK;
+}
+
+nep_status nep_split_info(nep_split h, int* n, int* ell) {
+  NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle");
+  if (n) *n = h->impl.op.n;
+  if (ell) *ell = h->impl.op.ell;
+  return NEP_OK;
+}
+
+nep_status nep_ciss_moments(nep_split h, const nep_contour* g, const nep_ciss_opts* o, const void* V, void* S,
+                            nep_ciss_stats* st) {
+  NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle");
+  return h->impl.moments(g, o, V, S, st);
+}
+
+nep_status nep_ciss_wait(nep_split h, nep_ciss_stats* st) {
+  NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle");
+  return h->impl.wait(st);
+}
+
+nep_status nep_fn_eval(nep_split h, int m, const double* z, double* out) {
+  NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle");
+  NEP_CHECK(m >= 1 && z != nullptr && out != nullptr, NEP_ERR_ARG, "bad point arrays");
+  std::vector<c128> vals;
+  std::vector<int> bad;
+  NEP_TRY(h->impl.eval_fns(m, reinterpret_cast<const c128*>(z), vals, bad));
+  std::memcpy(out, vals.data(), sizeof(c128) * vals.size());
+  for (int k = 0; k < m; ++k)
+    NEP_CHECK(bad[k] == 0, NEP_ERR_NOT_HOLOMORPHIC, "point %d lies on a pole or branch cut of some f_i", k);
+  return NEP_OK;
+}
+
+}  // extern "C"

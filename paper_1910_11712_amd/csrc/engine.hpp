@@ -1,0 +1,109 @@
+// Moment engine: device descriptors and kernel launchers shared by the
+// single-problem call, the batched plan and the server.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+#include "fn_device.hpp"
+#include "lu.hpp"
+
+namespace nep {
+
+constexpr int kMaxTerms = 16;
+constexpr int kMaxMoments = 32;  // 2K
+constexpr int kSolveBlk = 64;    // triangular-solve block rows
+constexpr int kNormStride = 64;  // per-node stride of the column-norm arrays (L <= 64)
+
+// Per-problem descriptor (device resident).
+struct ProbDesc {
+  int n, ell, N, L, KK;   // KK = 2K moments
+  int a_cplx;             // 1 if any A_i is complex
+  int node0;              // global index of node 0 of this problem
+  int ld;                 // factor leading dimension
+  long long offT0;        // factor block of node 0 (elements)
+  long long strideT;      // between consecutive nodes
+  long long offW0;        // solve work (n*L per node)
+  long long offY;         // Y / R blocks: n x N*L complex, row-major
+  int offRow0;            // row maps: offRow0 + j*n
+  int kind;               // contour kind
+  c128 c;                 // contour centre
+  double rho, v;
+  const void* A[kMaxTerms];        // device row-major A_i (double or c128)
+  const double* normA;             // device, ell inf-norms
+  const FnNode* fn_nodes;
+  const c128* fn_coef;
+  int fn_root[kMaxTerms];
+  int a_is_cplx[kMaxTerms];
+  const c128* V;          // caller probes, column-major n x L
+  c128* S;                // caller moments, column-major n x L x KK
+};
+
+// Per-node arrays (global node index g).
+struct NodeArrays {
+  c128* z;        // nodes
+  c128* zeta;     // (z - c)/rho
+  c128* w;        // quadrature weights
+  c128* fz;       // f_i(z_g) at [g*kMaxTerms + i]
+  double* fnorm;  // sum_i |f_i(z_g)| ||A_i||_inf
+  c128* mcoef;    // w_g zeta_g^p at [g*kMaxMoments + p]
+  int* prob;      // problem of node g
+  int* jnode;     // node index within the problem
+};
+
+// Per-node refinement state.
+struct IrState {
+  unsigned long long* rnorm;  // max |R| per (g, c) at g*kNormStride + c, double bits
+  unsigned long long* ynorm;  // max |Y| per (g, c)
+  double* vnorm;              // max |V| per (problem, c), index prob*64 + c
+  double* rho;                // last scaled residual per node
+  int* conv;                  // 1 when converged (skip further work)
+  int* stalled;               // 1 when the residual stopped decreasing
+  int* sweeps;                // sweeps run per node
+  int* counters;              // [0] unconverged, [1] bad fn, [2] spare, [3] first bad node
+};
+
+// Launch tables of a batch (host copies; uploaded into one device buffer).
+struct Table {
+  int off = 0, cnt = 0, total = 0;  // prefix at off (cnt+1 ints), sum = total
+};
+
+struct SolvePlan {
+  int nblk_max = 0;
+  std::vector<Table> fwd, bwd;  // per block step s
+  Table gather;                 // tiles of n*L per matrix
+};
+
+struct ProblemTables {
+  Table assemble;  // element tiles per problem
+  Table resid;     // residual GEMM tiles per problem
+  Table moments;   // n*L tiles per problem
+};
+
+void build_prefix(std::vector<int>& buf, Table& t, const std::vector<int>& counts);
+
+// Kernel launchers (all asynchronous on st).
+hipError_t launch_coef(const ProbDesc* pd, const NodeArrays& na, int nnodes, IrState ir, hipStream_t st);
+template <typename P>
+hipError_t launch_assemble(const ProbDesc* pd, const int* prefix, const Table& t, const NodeArrays& na,
+                           cx<P>* T, const int* skip, hipStream_t st);
+hipError_t launch_moments(const ProbDesc* pd, const int* prefix, const Table& t, const NodeArrays& na,
+                          const c128* Y, hipStream_t st);
+hipError_t launch_vnorm(const ProbDesc* pd, int nprob, IrState ir, hipStream_t st);
+
+template <typename P>
+hipError_t solve_run(const SolvePlan& sp, const int* d_prefix, const ProbDesc* pd, const MatDesc* md,
+                     const NodeArrays& na, const cx<P>* T, const int* rows, cx<P>* Wk, const c128* R, c128* Y,
+                     bool refine, const int* conv, IrState ir, int Lmax, hipStream_t st);
+void SolvePlan_build(SolvePlan& sp, std::vector<int>& buf, const std::vector<MatDesc>& sorted,
+                     const std::vector<int>& Lof);
+hipError_t solve_configure();
+
+hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const NodeArrays& na, const c128* Y,
+                     c128* R, IrState ir, int nnodes, hipStream_t st);
+hipError_t ir_control(const ProbDesc* pd, const NodeArrays& na, IrState ir, int nnodes, int sweep, double tol,
+                      hipStream_t st);
+hipError_t ir_reset(IrState ir, int nnodes, hipStream_t st);
+hipError_t engine_configure();
+
+}  // namespace nep

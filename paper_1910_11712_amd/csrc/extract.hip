@@ -1,0 +1,446 @@
+// Extraction of the eigenpairs inside the contour from the moments.
+//
+// With B0 = [S_{r+s}] and B1 = [S_{r+s+1}] (r, s = 0..K-1, each Kn x KL), the
+// Keldysh expansion (eq. (resolvent)) gives B0 = V_K(X, M) W and
+// B1 = V_K(X, M) M W with V_K the block matrix of eq. (invpair-split).  If
+// B0 = V0 Sigma0 W0^H is its rank-m truncated SVD, V0^H B1 W0 Sigma0^{-1} is
+// similar to M (the eigenvalues mu_i = (lambda_i - c)/rho inside); an
+// eigenvector s gives V0 s = [x; mu x; ...], whose first block is x.  The pair
+// (X, c + rho M) is a minimal invariant pair (Section 2).
+//
+// Device: Householder QR of B0 (one reflector at a time), Q applied to the
+// small singular vectors, V0^H B1, the eigenvectors, and the split-form
+// residual T(lambda) x for the backward error of eq. (sressplit) (inf-norms).
+// Host: one-sided Jacobi SVD of the K*L x K*L factor R and the m x m
+// eigenproblem (sequential small dense work, as for the projected problems
+// of the paper's solvers, Section 5).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "dense.hpp"
+#include "handle.hpp"
+
+namespace nep {
+
+struct ExtractWork {
+  DevMem B0, B1, tau, V0, P, smat, X0, Rt, norms;
+  size_t cap_rows = 0, cap_cols = 0;
+};
+
+// ---------------------------------------------------------------------------
+__global__ void k_hankel(const c128* __restrict__ S, int n, int L, int K, c128* __restrict__ B0,
+                         c128* __restrict__ B1) {
+  const long long M = (long long)K * n, KL = (long long)K * L;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * KL) return;
+  const long long col = e / M, row = e - col * M;
+  const int r = (int)(row / n), i = (int)(row - (long long)r * n);
+  const int s = (int)(col / L), c = (int)(col - (long long)s * L);
+  const long long off = (long long)c * n + i;
+  B0[e] = S[(long long)(r + s) * n * L + off];
+  B1[e] = S[(long long)(r + s + 1) * n * L + off];
+}
+
+// block sum over 1024 threads
+__device__ __forceinline__ c128 block_sum(c128 v, c128* red) {
+  for (int o = 32; o >= 1; o >>= 1) {
+    v.re += __shfl_xor(v.re, o, 64);
+    v.im += __shfl_xor(v.im, o, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  c128 s = {0.0, 0.0};
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s = s + red[i];
+  return s;
+}
+
+// Householder vector of column k (zlarfg convention): H^H x = beta e_1 with
+// H = I - tau v v^H, v_0 = 1, beta real.  v overwrites x below the diagonal.
+__global__ __launch_bounds__(1024) void k_house_vec(c128* __restrict__ B, long long M, int k, c128* __restrict__ tau) {
+  __shared__ c128 red[16];
+  c128* x = B + (long long)k * M;
+  double ss = 0.0;
+  for (long long i = k + 1 + threadIdx.x; i < M; i += blockDim.x) ss += norm2(x[i]);
+  const c128 tot = block_sum(c128{ss, 0.0}, red);
+  const double sigma2 = tot.re;
+  const c128 alpha = x[k];
+  __syncthreads();
+  if (sigma2 == 0.0 && alpha.im == 0.0) {
+    if (threadIdx.x == 0) tau[k] = c128{0.0, 0.0};
+    return;
+  }
+  const double nrm = sqrt(norm2(alpha) + sigma2);
+  const double beta = alpha.re >= 0.0 ? -nrm : nrm;
+  const c128 t = {(beta - alpha.re) / beta, -alpha.im / beta};
+  const c128 scal = cdiv(c128{1.0, 0.0}, c128{alpha.re - beta, alpha.im});
+  for (long long i = k + 1 + threadIdx.x; i < M; i += blockDim.x) x[i] = x[i] * scal;
+  if (threadIdx.x == 0) {
+    tau[k] = t;
+    x[k] = c128{beta, 0.0};
+  }
+}
+
+// b <- H^H b = b - conj(tau) v (v^H b) for columns k+1.. (one group each)
+__global__ __launch_bounds__(1024) void k_house_apply(c128* __restrict__ B, long long M, int k, int ncol,
+                                                      const c128* __restrict__ tau) {
+  __shared__ c128 red[16];
+  const int col = k + 1 + blockIdx.x;
+  if (col >= ncol) return;
+  const c128* v = B + (long long)k * M;
+  c128* b = B + (long long)col * M;
+  c128 acc = {0.0, 0.0};
+  if (threadIdx.x == 0) acc = b[k];  // v_k = 1
+  for (long long i = k + 1 + threadIdx.x; i < M; i += blockDim.x) acc = acc + conj(v[i]) * b[i];
+  const c128 w = block_sum(acc, red);
+  const c128 f = conj(tau[k]) * w;
+  if (threadIdx.x == 0) b[k] = b[k] - f;
+  for (long long i = k + 1 + threadIdx.x; i < M; i += blockDim.x) b[i] = b[i] - v[i] * f;
+}
+
+// X <- Q X = H_0 H_1 ... H_{r-1} X, one group per column of X (M x m)
+__global__ __launch_bounds__(1024) void k_apply_q(const c128* __restrict__ B, long long M, int r,
+                                                  const c128* __restrict__ tau, c128* __restrict__ X) {
+  __shared__ c128 red[16];
+  c128* x = X + (long long)blockIdx.x * M;
+  for (int k = r - 1; k >= 0; --k) {
+    const c128* v = B + (long long)k * M;
+    c128 acc = {0.0, 0.0};
+    if (threadIdx.x == 0) acc = x[k];
+    for (long long i = k + 1 + threadIdx.x; i < M; i += blockDim.x) acc = acc + conj(v[i]) * x[i];
+    const c128 w = block_sum(acc, red);
+    const c128 f = tau[k] * w;
+    __syncthreads();
+    if (threadIdx.x == 0) x[k] = x[k] - f;
+    for (long long i = k + 1 + threadIdx.x; i < M; i += blockDim.x) x[i] = x[i] - v[i] * f;
+    __syncthreads();
+  }
+}
+
+// P[i + j*m] = sum_r conj(V0[r, i]) B1[r, j]; one group per (i, j)
+__global__ __launch_bounds__(256) void k_vhb(const c128* __restrict__ V0, const c128* __restrict__ B1, long long M,
+                                             int m, c128* __restrict__ P) {
+  __shared__ c128 red[16];
+  const int i = blockIdx.x % m, j = blockIdx.x / m;
+  const c128* a = V0 + (long long)i * M;
+  const c128* b = B1 + (long long)j * M;
+  c128 acc = {0.0, 0.0};
+  for (long long r = threadIdx.x; r < M; r += blockDim.x) acc = acc + conj(a[r]) * b[r];
+  const c128 s = block_sum(acc, red);
+  if (threadIdx.x == 0) P[(long long)j * m + i] = s;
+}
+
+// X[:, q] = V0[0:n, :] s[:, q], normalized (2-norm 1, largest entry real > 0)
+__global__ __launch_bounds__(256) void k_eigvec(const c128* __restrict__ V0, long long M, int n, int m,
+                                                const c128* __restrict__ smat, c128* __restrict__ X) {
+  __shared__ c128 red[16];
+  __shared__ double rmax[4];
+  __shared__ int ridx[4];
+  const int q = blockIdx.x;
+  c128* x = X + (long long)q * n;
+  double ss = 0.0;
+  double bm = -1.0;
+  int bi = 0x7fffffff;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    c128 acc = {0.0, 0.0};
+    for (int j = 0; j < m; ++j) acc = acc + V0[(long long)j * M + r] * smat[(long long)q * m + j];
+    x[r] = acc;
+    const double a2 = norm2(acc);
+    ss += a2;
+    if (a2 > bm) { bm = a2; bi = r; }
+  }
+  const c128 tot = block_sum(c128{ss, 0.0}, red);
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double ov = __shfl_xor(bm, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ov > bm || (ov == bm && oi < bi)) { bm = ov; bi = oi; }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) { rmax[w] = bm; ridx[w] = bi; }
+  __syncthreads();
+  bm = rmax[0];
+  bi = ridx[0];
+  for (int i = 1; i < 4; ++i)
+    if (rmax[i] > bm || (rmax[i] == bm && ridx[i] < bi)) { bm = rmax[i]; bi = ridx[i]; }
+  const double nrm = sqrt(tot.re);
+  const c128 piv = x[bi];
+  const double ap = sqrt(norm2(piv));
+  // scale = conj(piv)/|piv| / nrm
+  const c128 scale = (ap > 0.0 && nrm > 0.0) ? c128{piv.re / (ap * nrm), -piv.im / (ap * nrm)} : c128{0.0, 0.0};
+  __syncthreads();
+  for (int r = threadIdx.x; r < n; r += blockDim.x) x[r] = x[r] * scale;
+}
+
+// Rt[row, q] = sum_i coef[i*m + q] (A_i x_q)[row]  (split-form T(lambda_q) x_q)
+// One group per (row tile of 64, q tile of 16); A tile staged through LDS.
+__global__ __launch_bounds__(256) void k_split_apply(const ProbDesc* __restrict__ pd_unused, int n, int ell, int m,
+                                                     const double* const* __restrict__ A, const int* __restrict__ cplx,
+                                                     const c128* __restrict__ coef, const c128* __restrict__ X,
+                                                     c128* __restrict__ Rt) {
+  __shared__ c128 As[64][33];
+  __shared__ c128 Xs[32][17];
+  const int row0 = blockIdx.x * 64, q0 = blockIdx.y * 16;
+  const int tr = threadIdx.x >> 2, tq = (threadIdx.x & 3) * 4;  // 64 rows x 4 groups of 4 columns
+  c128 out[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  for (int i = 0; i < ell; ++i) {
+    c128 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    for (int s0 = 0; s0 < n; s0 += 32) {
+      for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+        const int r = e >> 5, s = e & 31;
+        const int gr = row0 + r, gs = s0 + s;
+        c128 a = {0.0, 0.0};
+        if (gr < n && gs < n) {
+          if (cplx[i]) a = reinterpret_cast<const c128*>(A[i])[(long long)gr * n + gs];
+          else a.re = A[i][(long long)gr * n + gs];
+        }
+        As[r][s] = a;
+      }
+      for (int e = threadIdx.x; e < 32 * 16; e += 256) {
+        const int s = e >> 4, q = e & 15;
+        const int gs = s0 + s, gq = q0 + q;
+        Xs[s][q] = (gs < n && gq < m) ? X[(long long)gq * n + gs] : c128{0.0, 0.0};
+      }
+      __syncthreads();
+      for (int s = 0; s < 32; ++s) {
+        const c128 a = As[tr][s];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = acc[u] + a * Xs[s][tq + u];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int gq = q0 + tq + u;
+      if (gq < m) out[u] = out[u] + coef[(long long)i * m + gq] * acc[u];
+    }
+  }
+  const int gr = row0 + tr;
+  if (gr < n)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int gq = q0 + tq + u;
+      if (gq < m) Rt[(long long)gq * n + gr] = out[u];
+    }
+}
+
+// per column: max |Rt|, max |X|
+__global__ void k_colmax2(const c128* __restrict__ Rt, const c128* __restrict__ X, int n, double* __restrict__ out) {
+  __shared__ double r1[256], r2[256];
+  const int q = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    a = fmax(a, sqrt(norm2(Rt[(long long)q * n + r])));
+    b = fmax(b, sqrt(norm2(X[(long long)q * n + r])));
+  }
+  r1[threadIdx.x] = a;
+  r2[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      r1[threadIdx.x] = fmax(r1[threadIdx.x], r1[threadIdx.x + s]);
+      r2[threadIdx.x] = fmax(r2[threadIdx.x], r2[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * q] = r1[0];
+    out[2 * q + 1] = r2[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+static nep_status grow(DevMem& m, size_t bytes) {
+  if (m.bytes >= bytes) return NEP_OK;
+  return m.alloc(bytes);
+}
+
+// eta for m pairs: X device (n x m column-major), lambda host.
+static nep_status backward_errors(Split& h, int m, const std::vector<zc>& lam, const c128* X, std::vector<double>& eta,
+                                  ExtractWork& w, hipStream_t st) {
+  const int n = h.op.n, ell = h.op.ell;
+  std::vector<c128> fv;
+  std::vector<int> bad;
+  NEP_TRY(h.eval_fns(m, reinterpret_cast<const c128*>(lam.data()), fv, bad));
+  NEP_TRY(grow(w.Rt, sizeof(c128) * (size_t)n * m));
+  NEP_TRY(grow(w.norms, sizeof(double) * 2 * m + sizeof(c128) * (size_t)ell * m + sizeof(void*) * kMaxTerms +
+                            sizeof(int) * kMaxTerms));
+  char* base = w.norms.as<char>();
+  double* dnorm = reinterpret_cast<double*>(base);
+  c128* dcoef = reinterpret_cast<c128*>(base + sizeof(double) * 2 * m);
+  const double** dA = reinterpret_cast<const double**>(base + sizeof(double) * 2 * m + sizeof(c128) * ell * m);
+  int* dcp = reinterpret_cast<int*>(reinterpret_cast<char*>(dA) + sizeof(void*) * kMaxTerms);
+  const double* hA[kMaxTerms];
+  for (int i = 0; i < ell; ++i) hA[i] = reinterpret_cast<const double*>(h.op.dA[i]);
+  NEP_HIP(hipMemcpyAsync(dcoef, fv.data(), sizeof(c128) * ell * m, hipMemcpyHostToDevice, st));
+  NEP_HIP(hipMemcpyAsync(dA, hA, sizeof(void*) * ell, hipMemcpyHostToDevice, st));
+  NEP_HIP(hipMemcpyAsync(dcp, h.op.is_cplx, sizeof(int) * ell, hipMemcpyHostToDevice, st));
+  dim3 grid(ceil_div(n, 64), ceil_div(m, 16));
+  hipLaunchKernelGGL(k_split_apply, grid, dim3(256), 0, st, nullptr, n, ell, m, dA, dcp, dcoef, X, w.Rt.as<c128>());
+  NEP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_colmax2, dim3(m), dim3(256), 0, st, w.Rt.as<c128>(), X, n, dnorm);
+  NEP_HIP(hipGetLastError());
+  std::vector<double> hn(2 * m);
+  NEP_HIP(hipMemcpyAsync(hn.data(), dnorm, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, st));
+  NEP_HIP(hipStreamSynchronize(st));
+  eta.assign(m, 0.0);
+  for (int q = 0; q < m; ++q) {
+    if (bad[q]) {
+      eta[q] = NAN;
+      continue;
+    }
+    double den = 0.0;
+    for (int i = 0; i < ell; ++i) {
+      const c128 f = fv[(size_t)i * m + q];
+      den += std::sqrt(f.re * f.re + f.im * f.im) * h.op.normA[i];
+    }
+    den *= hn[2 * q + 1];
+    eta[q] = den > 0.0 ? hn[2 * q] / den : NAN;
+  }
+  return NEP_OK;
+}
+
+static nep_status extract(Split& h, const nep_contour* g, const nep_ciss_opts* o, const void* S,
+                          const nep_extract_opts* e, int* m_out, double* lambda, void* X, double* eta, int* inside,
+                          double* sigma) {
+  NEP_TRY(check_contour(g));
+  PlanOptions po;
+  NEP_TRY(check_opts(o, po));
+  NEP_CHECK(e != nullptr && e->max_eigs >= 1, NEP_ERR_ARG, "extract options: max_eigs must be >= 1");
+  NEP_CHECK(S != nullptr && X != nullptr && m_out && lambda && eta && inside, NEP_ERR_ARG, "null output array");
+  const int n = h.op.n, L = po.L, K = po.K;
+  const long long M = (long long)K * n;
+  const int KL = K * L;
+  NEP_CHECK(KL <= M, NEP_ERR_ARG, "K*L exceeds K*n");
+  hipStream_t st = o->stream ? (hipStream_t)o->stream : h.stream;
+  if (!h.xw) h.xw = std::make_shared<ExtractWork>();
+  ExtractWork& w = *h.xw;
+  NEP_TRY(grow(w.B0, sizeof(c128) * M * KL));
+  NEP_TRY(grow(w.B1, sizeof(c128) * M * KL));
+  NEP_TRY(grow(w.tau, sizeof(c128) * KL));
+  c128* B0 = w.B0.as<c128>();
+  c128* B1 = w.B1.as<c128>();
+  c128* tau = w.tau.as<c128>();
+  const long long tot = M * KL;
+  hipLaunchKernelGGL(k_hankel, dim3((unsigned)ceil_div_ll(tot, 256)), dim3(256), 0, st, (const c128*)S, n, L, K, B0,
+                     B1);
+  NEP_HIP(hipGetLastError());
+  for (int k = 0; k < KL; ++k) {
+    hipLaunchKernelGGL(k_house_vec, dim3(1), dim3(1024), 0, st, B0, M, k, tau);
+    NEP_HIP(hipGetLastError());
+    if (k + 1 < KL) {
+      hipLaunchKernelGGL(k_house_apply, dim3(KL - k - 1), dim3(1024), 0, st, B0, M, k, KL, tau);
+      NEP_HIP(hipGetLastError());
+    }
+  }
+  // R (upper KL x KL) to host
+  std::vector<zc> R((size_t)KL * KL, zc(0.0, 0.0));
+  {
+    std::vector<zc> tmp((size_t)KL * KL);
+    NEP_HIP(hipMemcpy2DAsync(tmp.data(), sizeof(zc) * KL, B0, sizeof(c128) * M, sizeof(zc) * KL, KL,
+                             hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipStreamSynchronize(st));
+    for (int j = 0; j < KL; ++j)
+      for (int i = 0; i <= j; ++i) R[(size_t)j * KL + i] = tmp[(size_t)j * KL + i];
+  }
+  std::vector<double> sv;
+  std::vector<zc> Ur, Wr;
+  jacobi_svd(KL, R, sv, Ur, Wr);
+  if (sigma)
+    for (int i = 0; i < KL; ++i) sigma[i] = sv[i];
+  const double tol = (e->rank_tol > 0.0 ? e->rank_tol : 1e-12) * sv[0];
+  int m = 0;
+  while (m < KL && sv[m] > tol) ++m;
+  *m_out = m;
+  NEP_CHECK(m > 0, NEP_ERR_RANK, "all moments vanish: no eigenvalue inside the contour is visible");
+  NEP_CHECK(m < KL, NEP_ERR_RANK, "moment rank %d == K*L: the contour holds more eigenvalues than K*L=%d can "
+            "resolve; increase L or K", m, KL);
+  NEP_CHECK(m <= e->max_eigs, NEP_ERR_ARG, "rank %d exceeds max_eigs %d", m, e->max_eigs);
+  // V0 = Q [Ur0; 0]
+  NEP_TRY(grow(w.V0, sizeof(c128) * M * m));
+  c128* V0 = w.V0.as<c128>();
+  {
+    std::vector<zc> X0((size_t)M * m, zc(0.0, 0.0));
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < KL; ++i) X0[(size_t)j * M + i] = Ur[(size_t)j * KL + i];
+    NEP_HIP(hipMemcpyAsync(V0, X0.data(), sizeof(c128) * M * m, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_apply_q, dim3(m), dim3(1024), 0, st, B0, M, KL, tau, V0);
+    NEP_HIP(hipGetLastError());
+    NEP_HIP(hipStreamSynchronize(st));  // X0 leaves scope
+  }
+  // Mt = V0^H B1 W0 Sigma0^{-1}
+  NEP_TRY(grow(w.P, sizeof(c128) * (size_t)m * KL));
+  hipLaunchKernelGGL(k_vhb, dim3(m * KL), dim3(256), 0, st, V0, B1, M, m, w.P.as<c128>());
+  NEP_HIP(hipGetLastError());
+  std::vector<zc> P((size_t)m * KL);
+  NEP_HIP(hipMemcpyAsync(P.data(), w.P.p, sizeof(c128) * m * KL, hipMemcpyDeviceToHost, st));
+  NEP_HIP(hipStreamSynchronize(st));
+  std::vector<zc> Mt((size_t)m * m, zc(0.0, 0.0));
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) {
+      zc acc = 0.0;
+      for (int k = 0; k < KL; ++k) acc += P[(size_t)k * m + i] * Wr[(size_t)j * KL + k];
+      Mt[(size_t)j * m + i] = acc / sv[j];
+    }
+  std::vector<zc> mu, Sv;
+  NEP_CHECK(eig_general(m, Mt, mu, Sv), NEP_ERR_RANK, "QR iteration on the projected matrix did not converge");
+  // order by (Re lambda, Im lambda)
+  const zc c0(g->c[0], g->c[1]);
+  std::vector<zc> lam(m);
+  for (int i = 0; i < m; ++i) lam[i] = c0 + g->rho * mu[i];
+  std::vector<int> ord(m);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    if (lam[a].real() != lam[b].real()) return lam[a].real() < lam[b].real();
+    return lam[a].imag() < lam[b].imag();
+  });
+  std::vector<zc> lam_s(m), Ss((size_t)m * m);
+  for (int q = 0; q < m; ++q) {
+    lam_s[q] = lam[ord[q]];
+    for (int i = 0; i < m; ++i) Ss[(size_t)q * m + i] = Sv[(size_t)ord[q] * m + i];
+  }
+  NEP_TRY(grow(w.smat, sizeof(c128) * (size_t)m * m));
+  NEP_HIP(hipMemcpyAsync(w.smat.p, Ss.data(), sizeof(c128) * m * m, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_eigvec, dim3(m), dim3(256), 0, st, V0, M, n, m, w.smat.as<c128>(), (c128*)X);
+  NEP_HIP(hipGetLastError());
+  NEP_HIP(hipStreamSynchronize(st));
+  std::vector<double> et;
+  NEP_TRY(backward_errors(h, m, lam_s, (const c128*)X, et, w, st));
+  for (int q = 0; q < m; ++q) {
+    lambda[2 * q] = lam_s[q].real();
+    lambda[2 * q + 1] = lam_s[q].imag();
+    eta[q] = et[q];
+    const zc mu_q = (lam_s[q] - c0) / g->rho;
+    inside[q] = g->kind == 0 ? (std::abs(mu_q) < 1.0)
+                             : (mu_q.real() * mu_q.real() + (mu_q.imag() / g->v) * (mu_q.imag() / g->v) < 1.0);
+  }
+  return NEP_OK;
+}
+
+}  // namespace nep
+
+using namespace nep;
+
+extern "C" {
+
+nep_status nep_extract(nep_split h, const nep_contour* g, const nep_ciss_opts* o, const void* S,
+                       const nep_extract_opts* e, int* m, double* lambda, void* X, double* eta, int* inside,
+                       double* sigma) {
+  NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle");
+  return nep::extract(h->impl, g, o, S, e, m, lambda, X, eta, inside, sigma);
+}
+
+nep_status nep_backward_error(nep_split h, int m, const double* lambda, const void* X, double* eta) {
+  NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle");
+  NEP_CHECK(m >= 1 && lambda && X && eta, NEP_ERR_ARG, "bad arguments");
+  if (!h->impl.xw) h->impl.xw = std::make_shared<ExtractWork>();
+  std::vector<zc> lam(m);
+  for (int q = 0; q < m; ++q) lam[q] = zc(lambda[2 * q], lambda[2 * q + 1]);
+  std::vector<double> et;
+  NEP_TRY(backward_errors(h->impl, m, lam, (const c128*)X, et, *h->impl.xw, h->impl.stream));
+  for (int q = 0; q < m; ++q) eta[q] = et[q];
+  return NEP_OK;
+}
+
+}  // extern "C"

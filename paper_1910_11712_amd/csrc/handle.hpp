@@ -1,0 +1,37 @@
+// Split-operator handle (behind the opaque nep_split of the C ABI).
+#pragma once
+
+#include <cmath>
+#include <memory>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace nep {
+
+struct ExtractWork;  // extraction workspace (extract.cpp)
+
+struct Split {
+  SplitOperator op;
+  hipStream_t stream = nullptr;
+  hipStream_t last_stream = nullptr;
+  std::unique_ptr<DevMem> mats[kMaxTerms];
+  DevMem norms, fn_nodes, fn_coef, fn_roots;
+  std::unique_ptr<MomentsPlan> plan;  // resident factors of the last call
+  std::shared_ptr<ExtractWork> xw;
+  bool pending = false;
+
+  nep_status init(int n, int ell, const nep_mat* A, const nep_fn* f, hipStream_t st);
+  nep_status moments(const nep_contour* g, const nep_ciss_opts* o, const void* V, void* S, nep_ciss_stats* st);
+  nep_status wait(nep_ciss_stats* st);
+  nep_status eval_fns(int m, const c128* zh, std::vector<c128>& out, std::vector<int>& bad);
+};
+
+nep_status check_contour(const nep_contour* g);
+nep_status check_opts(const nep_ciss_opts* o, PlanOptions& po);
+
+}  // namespace nep
+
+struct nep_split_s {
+  nep::Split impl;
+};

@@ -1,0 +1,687 @@
+// Batched complex LU with partial pivoting (P T = L U) for gfx950.
+//
+// The factorizations of T(z_j) at every quadrature node (and, for batches, of
+// every problem) are the dominant cost of the contour-integral path; the
+// paper likewise reports factorizations as the dominant cost of its solvers
+// (Sections 4 and 5, and the "PC build" column of its accuracy table).
+//
+// Storage: every matrix is row-major with leading dimension ld.  Pivoting is
+// done through a logical-to-physical row map (row_at); no row is ever moved,
+// so every kernel reads logical row r from physical row row_at[r].  Rows are
+// contiguous, so gathered row segments stay coalesced.
+//
+// Right-looking blocked algorithm, one step per panel of jb columns:
+//   k_lu_panel : one work-group per matrix factors the n-k0 by jb panel; leaves
+//                of W columns live in registers (one logical row per thread and
+//                slot), pivots are found by a wave shuffle + LDS reduction,
+//                modulus |Re|+|Im|, ties to the lowest row.
+//   k_lu_trsm  : U12 = L11^{-1} A12 for 64-column tiles of the trailing block,
+//                L11 in LDS, one wave per right-hand column at a time.
+//   k_lu_gemm  : A22 -= L21 U12 on the matrix cores.  Complex products use the
+//                real 2x2 embedding [ar -ai; ai ar] built in the operand
+//                registers, so one real MFMA k-pair is one complex k.
+//                c64: v_mfma_f32_32x32x2f32, 128x128 complex tile per group.
+//                c128: v_mfma_f64_16x16x4f64, 128x64 complex tile per group.
+#include "lu.hpp"
+
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+namespace nep {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPanelThreads = 512;
+constexpr int kMaxPanelRows = 4096;  // n - k0 held by one panel group
+
+// ---------------------------------------------------------------------------
+// init: row_at = identity, info = n (no zero pivot)
+// ---------------------------------------------------------------------------
+__global__ void k_lu_init(const MatDesc* __restrict__ md, int nmat, int* __restrict__ rowb,
+                          int* __restrict__ info) {
+  const int b = blockIdx.x;
+  if (b >= nmat) return;
+  const MatDesc d = md[b];
+  for (int r = threadIdx.x; r < d.n; r += blockDim.x) rowb[d.offRow + r] = r;
+  if (threadIdx.x == 0) info[d.node] = d.n;
+}
+
+// ---------------------------------------------------------------------------
+// Panel
+// ---------------------------------------------------------------------------
+template <typename P>
+__device__ __forceinline__ P shfl_xor_p(P v, int m) { return __shfl_xor(v, m, 64); }
+
+template <typename P, int W, int RPT>
+__global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __restrict__ md, int k0, int jbmax,
+                                                           cx<P>* __restrict__ Tb, int* __restrict__ rowb,
+                                                           int* __restrict__ info,
+                                                           const int* __restrict__ skip) {
+  const MatDesc d = md[blockIdx.x];
+  const int n = d.n;
+  if (k0 >= n) return;
+  if (skip != nullptr && skip[d.node]) return;
+  const int jb = min(jbmax, n - k0);
+  cx<P>* __restrict__ T = Tb + d.offT;
+  const int ld = d.ld;
+  int* __restrict__ rowg = rowb + d.offRow;
+
+  __shared__ int rat[kMaxPanelRows];
+  __shared__ P redv[2][kPanelThreads / 64];
+  __shared__ int redi[2][kPanelThreads / 64];
+  __shared__ cx<P> xbuf[2][2][W];
+  __shared__ cx<P> Ltop[W][W];
+  __shared__ cx<P> Utop[W][kLuMaxJB];
+  __shared__ int zero_pivot;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int m = n - k0;
+  for (int r = tid; r < m; r += kPanelThreads) rat[r] = rowg[k0 + r];
+  if (tid == 0) zero_pivot = n;
+  __syncthreads();
+
+  int par = 0;
+  for (int c0 = k0; c0 < k0 + jb; c0 += W) {
+    const int wc = min(W, k0 + jb - c0);
+    cx<P> a[RPT][W];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = c0 + tid + i * kPanelThreads;
+#pragma unroll
+      for (int w = 0; w < W; ++w) a[i][w] = cx<P>{P(0), P(0)};
+      if (r < n) {
+        const cx<P>* src = T + (long long)rat[r - k0] * ld + c0;
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+          if (w < wc) a[i][w] = src[w];
+      }
+    }
+
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      if (w < wc) {
+        const int c = c0 + w;
+        // ---- pivot search: max |Re|+|Im| over logical rows >= c, lowest row on ties
+        P bv = P(-1);
+        int bi = INT_MAX;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const int r = c0 + tid + i * kPanelThreads;
+          if (r >= c && r < n) {
+            const P v = abs1(a[i][w]);
+            if (v > bv) { bv = v; bi = r; }
+          }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          const P ov = shfl_xor_p(bv, off);
+          const int oi = __shfl_xor(bi, off, 64);
+          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if (lane == 0) { redv[par][wave] = bv; redi[par][wave] = bi; }
+        __syncthreads();
+        bv = redv[par][0];
+        bi = redi[par][0];
+#pragma unroll
+        for (int q = 1; q < kPanelThreads / 64; ++q) {
+          const P ov = redv[par][q];
+          const int oi = redi[par][q];
+          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        const int p = bi;
+        const int oc = (c - c0) % kPanelThreads, ic = (c - c0) / kPanelThreads;
+        const int op = (p - c0) % kPanelThreads, ip = (p - c0) / kPanelThreads;
+        // ---- exchange logical rows c and p (registers only; row_at records it)
+        if (tid == op) {
+#pragma unroll
+          for (int i = 0; i < RPT; ++i)
+            if (i == ip) {
+#pragma unroll
+              for (int v = 0; v < W; ++v) xbuf[par][0][v] = a[i][v];
+            }
+        }
+        if (tid == oc && p != c) {
+#pragma unroll
+          for (int i = 0; i < RPT; ++i)
+            if (i == ic) {
+#pragma unroll
+              for (int v = 0; v < W; ++v) xbuf[par][1][v] = a[i][v];
+            }
+        }
+        __syncthreads();
+        cx<P> prow[W];
+#pragma unroll
+        for (int v = 0; v < W; ++v) prow[v] = xbuf[par][0][v];
+        if (p != c) {
+          if (tid == oc) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+              if (i == ic) {
+#pragma unroll
+                for (int v = 0; v < W; ++v) a[i][v] = prow[v];
+              }
+          }
+          if (tid == op) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+              if (i == ip) {
+#pragma unroll
+                for (int v = 0; v < W; ++v) a[i][v] = xbuf[par][1][v];
+              }
+          }
+        }
+        if (tid == 0) {
+          const int t = rat[c - k0];
+          rat[c - k0] = rat[p - k0];
+          rat[p - k0] = t;
+          if (bv == P(0) && zero_pivot == n) zero_pivot = c;
+        }
+        // ---- scale the column and update the rest of the leaf
+        const cx<P> inv = recip(prow[w]);
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const int r = c0 + tid + i * kPanelThreads;
+          if (r > c && r < n) {
+            const cx<P> l = a[i][w] * inv;
+            a[i][w] = l;
+#pragma unroll
+            for (int v = w + 1; v < W; ++v) a[i][v] = fms(a[i][v], l, prow[v]);
+          }
+        }
+        par ^= 1;
+      }
+    }
+    __syncthreads();  // row_at swaps visible
+
+    // ---- write the leaf back
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = c0 + tid + i * kPanelThreads;
+      if (r < n) {
+        cx<P>* dst = T + (long long)rat[r - k0] * ld + c0;
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+          if (w < wc) dst[w] = a[i][w];
+      }
+    }
+
+    // ---- update the panel columns right of the leaf
+    const int rc0 = c0 + wc;
+    const int nr = k0 + jb - rc0;
+    if (nr > 0) {
+      if (tid < wc) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) Ltop[tid][w] = a[0][w];
+      }
+      __syncthreads();
+      for (int j = tid; j < nr; j += kPanelThreads) {
+        cx<P> x[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+          if (w < wc) x[w] = T[(long long)rat[c0 + w - k0] * ld + rc0 + j];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          if (w < wc) {
+#pragma unroll
+            for (int v = 0; v < w; ++v) x[w] = fms(x[w], Ltop[w][v], x[v]);
+            T[(long long)rat[c0 + w - k0] * ld + rc0 + j] = x[w];
+            Utop[w][j] = x[w];
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = c0 + tid + i * kPanelThreads;
+        if (r >= rc0 && r < n) {
+          cx<P>* row = T + (long long)rat[r - k0] * ld + rc0;
+          for (int j = 0; j < nr; ++j) {
+            cx<P> acc = row[j];
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+              if (w < wc) acc = fms(acc, a[i][w], Utop[w][j]);
+            row[j] = acc;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int r = tid; r < m; r += kPanelThreads) rowg[k0 + r] = rat[r];
+  if (tid == 0 && zero_pivot < n) atomicMin(&info[d.node], zero_pivot);
+}
+
+// ---------------------------------------------------------------------------
+// TRSM: U12 = L11^{-1} A12 on 64-column tiles (unit lower L11, jb x jb)
+// ---------------------------------------------------------------------------
+constexpr int kTrsmCols = 64;
+
+template <typename P>
+__global__ __launch_bounds__(256) void k_lu_trsm(const MatDesc* __restrict__ md, const int* __restrict__ prefix,
+                                                 int nact, int total, int k0, int jbmax, cx<P>* __restrict__ Tb,
+                                                 const int* __restrict__ rowb, const int* __restrict__ skip) {
+  const int v = xcd_remap(blockIdx.x, gridDim.x, total);
+  if (v < 0) return;
+  const int b = find_slot(prefix, nact, v);
+  const int tile = v - prefix[b];
+  const MatDesc d = md[b];
+  if (skip != nullptr && skip[d.node]) return;
+  const int n = d.n;
+  const int jb = min(jbmax, n - k0);
+  const int j0 = k0 + jb + tile * kTrsmCols;
+  const int ncol = min(kTrsmCols, n - j0);
+  if (ncol <= 0) return;
+  cx<P>* __restrict__ T = Tb + d.offT;
+  const int ld = d.ld;
+  const int* __restrict__ rat = rowb + d.offRow + k0;
+
+  extern __shared__ unsigned char smem_raw[];
+  cx<P>* Ls = reinterpret_cast<cx<P>*>(smem_raw);  // jb x (jb+1) padded
+  const int lds = jb + 1;
+  for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) {
+    const int r = e / jb, s = e - r * jb;
+    Ls[r * lds + s] = (s < r) ? T[(long long)rat[r] * ld + k0 + s] : cx<P>{P(0), P(0)};
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int kRowSlots = kLuMaxJB / 64;
+  for (int col = wave; col < ncol; col += 4) {
+    cx<P> x[kRowSlots];
+#pragma unroll
+    for (int q = 0; q < kRowSlots; ++q) {
+      const int r = lane + 64 * q;
+      x[q] = (r < jb) ? T[(long long)rat[r] * ld + j0 + col] : cx<P>{P(0), P(0)};
+    }
+#pragma unroll
+    for (int qs = 0; qs < kRowSlots; ++qs) {
+      for (int s = 0; s < 64; ++s) {
+        const int sg = qs * 64 + s;
+        if (sg >= jb) break;
+        cx<P> xs;
+        xs.re = __shfl(x[qs].re, s, 64);
+        xs.im = __shfl(x[qs].im, s, 64);
+#pragma unroll
+        for (int q = qs; q < kRowSlots; ++q) {
+          const int r = lane + 64 * q;
+          if (r > sg && r < jb) x[q] = fms(x[q], Ls[r * lds + sg], xs);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kRowSlots; ++q) {
+      const int r = lane + 64 * q;
+      if (r < jb) T[(long long)rat[r] * ld + j0 + col] = x[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: A22 -= L21 * U12  (complex, on the matrix cores)
+// ---------------------------------------------------------------------------
+// c64 variant: 256 threads = 4 waves (2 x 2), each wave 64 x 64 complex.
+constexpr int kG32TM = 128, kG32TN = 128, kG32KC = 16;
+
+__global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restrict__ md, const int* __restrict__ prefix,
+                                                     int nact, int total, int k0, int jbmax, c64* __restrict__ Tb,
+                                                     const int* __restrict__ rowb, const int* __restrict__ skip) {
+  const int v = xcd_remap(blockIdx.x, gridDim.x, total);
+  if (v < 0) return;
+  const int b = find_slot(prefix, nact, v);
+  const int t = v - prefix[b];
+  const MatDesc d = md[b];
+  if (skip != nullptr && skip[d.node]) return;
+  const int n = d.n;
+  const int jb = min(jbmax, n - k0);
+  const int s0 = k0 + jb;          // first trailing row/col
+  const int mt = n - s0;           // trailing size
+  const int tiles_n = (mt + kG32TN - 1) / kG32TN;
+  const int tm = t / tiles_n, tn = t - tm * tiles_n;
+  const int row0 = s0 + tm * kG32TM, col0 = s0 + tn * kG32TN;
+  c64* __restrict__ T = Tb + d.offT;
+  const int ld = d.ld;
+  const int* __restrict__ rat = rowb + d.offRow;
+
+  // LDS: A as [k][row] complex (stride kG32TM+2), B as re/im planes [k][col].
+  __shared__ float As[2][kG32KC][2 * kG32TM + 4];
+  __shared__ float Bs[2][kG32KC][2][kG32TN + 4];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 64, wcn = (wave & 1) * 64;
+
+  // global -> register staging (each thread: 4 float4 of A, 4 float4 of B)
+  // A tile: 128 rows x 16 k complex = 128 rows x 8 float4; thread -> (row, kp)
+  // B tile: 16 k x 128 cols complex = 16 rows x 64 float4
+  float4 ra[4], rb[4];
+  auto load_tile = [&](int kk) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;        // 0..1023
+      const int r = e >> 3, kp = e & 7;   // A: row, k-pair
+      const int gr = row0 + r, gk = kk + 2 * kp;
+      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gr < n && gk < k0 + jb) {
+        const c64* src = T + (long long)rat[gr] * ld + gk;
+        if (gk + 1 < k0 + jb) val = *reinterpret_cast<const float4*>(src);
+        else val = make_float4(src->re, src->im, 0.f, 0.f);
+      }
+      ra[q] = val;
+      const int kr = e >> 6, cp = e & 63;  // B: k row, column pair
+      const int gk2 = kk + kr, gc = col0 + 2 * cp;
+      float4 vb = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gk2 < k0 + jb && gc < n) {
+        const c64* src = T + (long long)rat[gk2] * ld + gc;
+        if (gc + 1 < n) vb = *reinterpret_cast<const float4*>(src);
+        else vb = make_float4(src->re, src->im, 0.f, 0.f);
+      }
+      rb[q] = vb;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      const int r = e >> 3, kp = e & 7;
+      As[buf][2 * kp][2 * r] = ra[q].x;
+      As[buf][2 * kp][2 * r + 1] = ra[q].y;
+      As[buf][2 * kp + 1][2 * r] = ra[q].z;
+      As[buf][2 * kp + 1][2 * r + 1] = ra[q].w;
+      const int kr = e >> 6, cp = e & 63;
+      Bs[buf][kr][0][2 * cp] = rb[q].x;
+      Bs[buf][kr][1][2 * cp] = rb[q].y;
+      Bs[buf][kr][0][2 * cp + 1] = rb[q].z;
+      Bs[buf][kr][1][2 * cp + 1] = rb[q].w;
+    }
+  };
+
+  floatx16 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  // operand lane roles: A row (l%32)/2 with component t=l%2; k-half u=l/32
+  const int at = lane & 1, au = lane >> 5, arow = (lane & 31) >> 1;
+  const int acomp = at ^ au;                      // 0: re, 1: im
+  const float asign = (at == 0 && au == 1) ? -1.f : 1.f;
+  const int bcol = lane & 31, bu = lane >> 5;
+
+  const int nk = (jb + kG32KC - 1) / kG32KC;
+  load_tile(k0);
+  store_tile(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) load_tile(k0 + (kc + 1) * kG32KC);
+#pragma unroll
+    for (int k = 0; k < kG32KC; ++k) {
+      float af[4], bf[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = asign * As[buf][k][2 * (wr + i * 16 + arow) + acomp];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = Bs[buf][k][bu][wcn + j * 32 + bcol];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (kc + 1 < nk) {
+      store_tile(buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // epilogue: C -= acc.  acc reg r: real row 8(r/4) + 4(l/32) + r%4, col l%32
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int gc = col0 + wcn + j * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; r += 2) {
+        const int crow = 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
+        const int gr = row0 + wr + i * 16 + crow;
+        if (gr < n && gc < n) {
+          c64* p = T + (long long)rat[gr] * ld + gc;
+          c64 cv = *p;
+          cv.re -= acc[i][j][r];
+          cv.im -= acc[i][j][r + 1];
+          *p = cv;
+        }
+      }
+    }
+}
+
+// c128 variant: 256 threads = 4 waves (2 x 2), each wave 64 x 32 complex.
+constexpr int kG64TM = 128, kG64TN = 64, kG64KC = 8;
+
+__global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restrict__ md, const int* __restrict__ prefix,
+                                                      int nact, int total, int k0, int jbmax, c128* __restrict__ Tb,
+                                                      const int* __restrict__ rowb, const int* __restrict__ skip) {
+  const int v = xcd_remap(blockIdx.x, gridDim.x, total);
+  if (v < 0) return;
+  const int b = find_slot(prefix, nact, v);
+  const int t = v - prefix[b];
+  const MatDesc d = md[b];
+  if (skip != nullptr && skip[d.node]) return;
+  const int n = d.n;
+  const int jb = min(jbmax, n - k0);
+  const int s0 = k0 + jb;
+  const int mt = n - s0;
+  const int tiles_n = (mt + kG64TN - 1) / kG64TN;
+  const int tm = t / tiles_n, tn = t - tm * tiles_n;
+  const int row0 = s0 + tm * kG64TM, col0 = s0 + tn * kG64TN;
+  c128* __restrict__ T = Tb + d.offT;
+  const int ld = d.ld;
+  const int* __restrict__ rat = rowb + d.offRow;
+
+  __shared__ double As[2][kG64KC][2 * kG64TM + 2];
+  __shared__ double Bs[2][kG64KC][2][kG64TN + 2];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 64, wcn = (wave & 1) * 32;
+
+  // A tile: 128 rows x 8 k complex (16 B each) -> 1024 elements, 4 per thread
+  // B tile: 8 k x 64 cols complex -> 512 elements, 2 per thread
+  double2 ra[4], rb[2];
+  auto load_tile = [&](int kk) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      const int r = e >> 3, kq = e & 7;
+      const int gr = row0 + r, gk = kk + kq;
+      double2 val = make_double2(0.0, 0.0);
+      if (gr < n && gk < k0 + jb) val = *reinterpret_cast<const double2*>(T + (long long)rat[gr] * ld + gk);
+      ra[q] = val;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + q * 256;
+      const int kr = e >> 6, c = e & 63;
+      const int gk = kk + kr, gc = col0 + c;
+      double2 val = make_double2(0.0, 0.0);
+      if (gk < k0 + jb && gc < n) val = *reinterpret_cast<const double2*>(T + (long long)rat[gk] * ld + gc);
+      rb[q] = val;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      const int r = e >> 3, kq = e & 7;
+      As[buf][kq][2 * r] = ra[q].x;
+      As[buf][kq][2 * r + 1] = ra[q].y;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + q * 256;
+      const int kr = e >> 6, c = e & 63;
+      Bs[buf][kr][0][c] = rb[q].x;
+      Bs[buf][kr][1][c] = rb[q].y;
+    }
+  };
+
+  doublex4 acc[8][2];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+
+  // f64 16x16x4 operand roles: A real row l%16 -> complex row (l%16)/2, t=l%2;
+  // real k l/16 -> complex k (l/16)/2 within the pair, u=(l/16)%2.
+  const int at = lane & 1, arow = (lane & 15) >> 1;
+  const int kq = lane >> 4, ak = kq >> 1, au = kq & 1;
+  const int acomp = at ^ au;
+  const double asign = (at == 0 && au == 1) ? -1.0 : 1.0;
+  const int bcol = lane & 15;
+
+  const int nk = (jb + kG64KC - 1) / kG64KC;
+  load_tile(k0);
+  store_tile(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) load_tile(k0 + (kc + 1) * kG64KC);
+#pragma unroll
+    for (int k2 = 0; k2 < kG64KC; k2 += 2) {
+      double af[8], bf[2];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) af[i] = asign * As[buf][k2 + ak][2 * (wr + i * 8 + arow) + acomp];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = Bs[buf][k2 + ak][au][wcn + j * 16 + bcol];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (kc + 1 < nk) {
+      store_tile(buf ^ 1);
+      __syncthreads();
+    }
+  }
+  // epilogue: acc reg r of lane l: real row l/16 + 4r -> complex row (l/16)/2 + 2r,
+  // component (l/16)%2; col l%16.
+  const int tcomp = (lane >> 4) & 1, rbase = (lane >> 4) >> 1;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int gc = col0 + wcn + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + wr + i * 8 + rbase + 2 * r;
+        if (gr < n && gc < n) {
+          double* p = reinterpret_cast<double*>(T + (long long)rat[gr] * ld + gc) + tcomp;
+          *p -= acc[i][j][r];
+        }
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+template <typename P, int W>
+static hipError_t launch_panel(int rpt, int nact, const MatDesc* md, int k0, int jb, cx<P>* T, int* rows, int* info,
+                               const int* skip, hipStream_t st) {
+  dim3 g(nact), blk(kPanelThreads);
+  switch (rpt) {
+    case 1: hipLaunchKernelGGL((k_lu_panel<P, W, 1>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    case 2: hipLaunchKernelGGL((k_lu_panel<P, W, 2>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    case 4: hipLaunchKernelGGL((k_lu_panel<P, W, 4>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    default: hipLaunchKernelGGL((k_lu_panel<P, W, 8>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+  }
+  return hipGetLastError();
+}
+
+int lu_jb(int prec) { return prec == NEP_PREC_FP64 ? 64 : 128; }
+
+void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
+  prec = prec_;
+  jb = lu_jb(prec);
+  nmat = (int)sorted.size();
+  nmax = nmat ? sorted[0].n : 0;
+  steps.clear();
+  prefix.clear();
+  for (int k0 = 0; k0 < nmax; k0 += jb) {
+    Step s;
+    s.k0 = k0;
+    int nact = 0;
+    while (nact < nmat && sorted[nact].n > k0) ++nact;
+    s.nact = nact;
+    int rmax = sorted[0].n - k0;
+    s.rpt = rmax <= 512 ? 1 : rmax <= 1024 ? 2 : rmax <= 2048 ? 4 : 8;
+    // trsm and gemm tile prefixes
+    s.off_trsm = (int)prefix.size();
+    int acc = 0;
+    prefix.push_back(0);
+    for (int b = 0; b < nact; ++b) {
+      const int n = sorted[b].n, jbb = std::min(jb, n - k0), mt = n - k0 - jbb;
+      acc += mt > 0 ? ceil_div(mt, kTrsmCols) : 0;
+      prefix.push_back(acc);
+    }
+    s.tot_trsm = acc;
+    s.off_gemm = (int)prefix.size();
+    acc = 0;
+    prefix.push_back(0);
+    for (int b = 0; b < nact; ++b) {
+      const int n = sorted[b].n, jbb = std::min(jb, n - k0), mt = n - k0 - jbb;
+      const int TM = prec == NEP_PREC_FP64 ? kG64TM : kG32TM, TN = prec == NEP_PREC_FP64 ? kG64TN : kG32TN;
+      acc += mt > 0 ? ceil_div(mt, TM) * ceil_div(mt, TN) : 0;
+      prefix.push_back(acc);
+    }
+    s.tot_gemm = acc;
+    steps.push_back(s);
+  }
+}
+
+template <typename P>
+hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* info,
+                  const int* skip, hipStream_t st) {
+  hipError_t e;
+  hipLaunchKernelGGL(k_lu_init, dim3(plan.nmat), dim3(256), 0, st, d_md, plan.nmat, rows, info);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  constexpr int W = sizeof(P) == 4 ? 8 : 4;
+  const size_t trsm_lds = (size_t)plan.jb * (plan.jb + 1) * sizeof(cx<P>);
+  for (const auto& s : plan.steps) {
+    if ((e = launch_panel<P, W>(s.rpt, s.nact, d_md, s.k0, plan.jb, T, rows, info, skip, st)) != hipSuccess) return e;
+    if (s.tot_trsm > 0) {
+      hipLaunchKernelGGL(k_lu_trsm<P>, dim3(xcd_grid(s.tot_trsm)), dim3(256), trsm_lds, st, d_md,
+                         d_prefix + s.off_trsm, s.nact, s.tot_trsm, s.k0, plan.jb, T, rows, skip);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (s.tot_gemm > 0) {
+      if constexpr (sizeof(P) == 4)
+        hipLaunchKernelGGL(k_lu_gemm_c64, dim3(xcd_grid(s.tot_gemm)), dim3(256), 0, st, d_md, d_prefix + s.off_gemm,
+                           s.nact, s.tot_gemm, s.k0, plan.jb, T, rows, skip);
+      else
+        hipLaunchKernelGGL(k_lu_gemm_c128, dim3(xcd_grid(s.tot_gemm)), dim3(256), 0, st, d_md,
+                           d_prefix + s.off_gemm, s.nact, s.tot_gemm, s.k0, plan.jb, T, rows, skip);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t lu_configure() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_lu_trsm<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     128 * 129 * sizeof(c64));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_lu_trsm<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             64 * 65 * sizeof(c128));
+}
+
+template hipError_t lu_run<float>(const LuPlan&, const MatDesc*, const int*, c64*, int*, int*, const int*,
+                                  hipStream_t);
+template hipError_t lu_run<double>(const LuPlan&, const MatDesc*, const int*, c128*, int*, int*, const int*,
+                                   hipStream_t);
+
+}  // namespace nep

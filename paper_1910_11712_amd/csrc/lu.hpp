@@ -1,0 +1,32 @@
+// Batched complex LU (row-major, pivoting through a row map) -- host API.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace nep {
+
+constexpr int kLuMaxJB = 128;
+
+// Launch plan of a (possibly ragged) batch: matrices sorted by n, descending.
+struct LuPlan {
+  struct Step {
+    int k0, nact, rpt;
+    int off_trsm, tot_trsm;
+    int off_gemm, tot_gemm;
+  };
+  int jb = 128, prec = NEP_PREC_C32_IR64, nmat = 0, nmax = 0;
+  std::vector<Step> steps;
+  std::vector<int> prefix;  // uploaded once; offsets above index into it
+  void build(const std::vector<MatDesc>& sorted, int prec);
+};
+
+int lu_jb(int prec);
+hipError_t lu_configure();
+
+template <typename P>
+hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* info,
+                  const int* skip, hipStream_t st);
+
+}  // namespace nep

@@ -1,0 +1,365 @@
+// Moment plan: layout, tables, buffers and the launch sequence of the
+// contour-integral moment path for one or many problems.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+
+namespace nep {
+
+nep_status DevMem::alloc(size_t b) {
+  release();
+  if (b == 0) return NEP_OK;
+  hipError_t e = hipMalloc(&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    set_error("device allocation of %zu bytes failed: %s", b, hipGetErrorString(e));
+    return NEP_ERR_OOM;
+  }
+  bytes = b;
+  return NEP_OK;
+}
+
+void DevMem::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+static int pad_ld(int n) {
+  int ld = (n + 15) / 16 * 16;
+  if (ld % 512 == 0) ld += 16;  // avoid power-of-two row strides
+  return ld;
+}
+
+static size_t elem_size(int prec) { return prec == NEP_PREC_FP64 ? sizeof(c128) : sizeof(c64); }
+
+size_t MomentsPlan::estimate_bytes(int n, int N, int L, int prec) {
+  const size_t ld = pad_ld(n);
+  size_t b = (size_t)N * ld * n * elem_size(prec);        // factors
+  b += (size_t)N * n * sizeof(int);                        // row maps
+  b += (size_t)N * n * L * elem_size(prec);                // solve work
+  b += 2 * (size_t)n * N * L * sizeof(c128);               // Y, R
+  b += (size_t)N * (kMaxTerms + kMaxMoments + 8) * sizeof(c128) + (size_t)N * kNormStride * 16;
+  return b;
+}
+
+bool MomentsPlan::matches(const std::vector<PlanProblem>& probs, const PlanOptions& o) const {
+  if ((int)probs.size() != nprob) return false;
+  if (o.N != opt.N || o.L != opt.L || o.K != opt.K || o.prec != opt.prec) return false;
+  for (int p = 0; p < nprob; ++p)
+    if (probs[p].op->n != hpd_[p].n || probs[p].op->ell != hpd_[p].ell) return false;
+  return true;
+}
+
+nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs) {
+  for (int p = 0; p < nprob; ++p) {
+    ProbDesc& D = hpd_[p];
+    const PlanProblem& q = probs[p];
+    D.kind = q.g.kind;
+    D.c = c128{q.g.c[0], q.g.c[1]};
+    D.rho = q.g.rho;
+    D.v = q.g.kind == 1 ? q.g.v : 1.0;
+    D.V = q.V;
+    D.S = q.S;
+    D.ell = q.op->ell;
+    D.a_cplx = q.op->a_cplx;
+    for (int i = 0; i < kMaxTerms; ++i) {
+      D.A[i] = i < q.op->ell ? q.op->dA[i] : nullptr;
+      D.a_is_cplx[i] = i < q.op->ell ? q.op->is_cplx[i] : 0;
+      D.fn_root[i] = i < q.op->ell ? q.op->fn_root[i] : 0;
+    }
+    D.normA = q.op->dnormA;
+    D.fn_nodes = q.op->dfn_nodes;
+    D.fn_coef = q.op->dfn_coef;
+  }
+  NEP_HIP(hipMemcpy(dpd_.p, hpd_.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice));
+  return NEP_OK;
+}
+
+nep_status MomentsPlan::rebind(const std::vector<PlanProblem>& probs) {
+  NEP_CHECK((int)probs.size() == nprob, NEP_ERR_ARG, "rebind: problem count changed");
+  return upload_problems(probs);
+}
+
+nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanOptions& o) {
+  opt = o;
+  nprob = (int)probs.size();
+  Lmax = o.L;
+  hpd_.assign(nprob, ProbDesc{});
+  std::vector<int> hprob, hj;
+  std::vector<MatDesc> all;
+  long long offT = 0, offW = 0, offY = 0;
+  int offRow = 0, g = 0;
+  for (int p = 0; p < nprob; ++p) {
+    const int n = probs[p].op->n;
+    ProbDesc& D = hpd_[p];
+    D.n = n;
+    D.N = o.N;
+    D.L = o.L;
+    D.KK = 2 * o.K;
+    D.node0 = g;
+    D.ld = pad_ld(n);
+    D.offT0 = offT;
+    D.strideT = (long long)D.ld * n;
+    D.offW0 = offW;
+    D.offY = offY;
+    D.offRow0 = offRow;
+    for (int j = 0; j < o.N; ++j, ++g) {
+      MatDesc m;
+      m.n = n;
+      m.ld = D.ld;
+      m.offT = offT + (long long)j * D.strideT;
+      m.offRow = offRow + j * n;
+      m.node = g;
+      all.push_back(m);
+      hprob.push_back(p);
+      hj.push_back(j);
+    }
+    offT += (long long)o.N * D.strideT;
+    offW += (long long)o.N * n * o.L;
+    offY += (long long)n * o.N * o.L;
+    offRow += o.N * n;
+  }
+  nnodes = g;
+  t_elems_ = offT;
+  w_elems_ = offW;
+  y_elems_ = offY;
+  rows_total_ = offRow;
+  sorted_ = all;
+  std::stable_sort(sorted_.begin(), sorted_.end(), [](const MatDesc& a, const MatDesc& b) { return a.n > b.n; });
+
+  lu_.build(sorted_, o.prec);
+  const bool mixed = o.prec == NEP_PREC_C32_IR64;
+  if (mixed && o.fallback) lu64_.build(sorted_, NEP_PREC_FP64);
+
+  hprefix_.clear();
+  SolvePlan_build(sp_, hprefix_, sorted_, std::vector<int>(sorted_.size(), o.L));
+  {
+    std::vector<int> ca, cr, cm;
+    for (int p = 0; p < nprob; ++p) {
+      const long long n = hpd_[p].n;
+      ca.push_back((int)ceil_div_ll(n * n, 256));
+      cr.push_back(ceil_div((int)n, 64) * ceil_div(2 * o.N * o.L, 64));
+      cm.push_back(ceil_div((int)n * o.L, 256));
+    }
+    build_prefix(hprefix_, pt_.assemble, ca);
+    build_prefix(hprefix_, pt_.resid, cr);
+    build_prefix(hprefix_, pt_.moments, cm);
+  }
+
+  const size_t es = elem_size(o.prec);
+  total_bytes_ = 0;
+  auto A = [&](DevMem& m, size_t b) -> nep_status {
+    nep_status s = m.alloc(b);
+    total_bytes_ += b;
+    return s;
+  };
+  NEP_TRY(A(dpd_, sizeof(ProbDesc) * nprob));
+  NEP_TRY(A(dmd_, sizeof(MatDesc) * sorted_.size()));
+  NEP_TRY(A(dprefix_, sizeof(int) * hprefix_.size()));
+  NEP_TRY(A(dlu_prefix_, sizeof(int) * std::max<size_t>(1, lu_.prefix.size())));
+  if (mixed && o.fallback) NEP_TRY(A(dlu64_prefix_, sizeof(int) * std::max<size_t>(1, lu64_.prefix.size())));
+  NEP_TRY(A(dT_, es * (size_t)t_elems_));
+  NEP_TRY(A(drows_, sizeof(int) * (size_t)rows_total_));
+  NEP_TRY(A(dinfo_, sizeof(int) * (size_t)nnodes));
+  NEP_TRY(A(dWk_, es * (size_t)w_elems_));
+  NEP_TRY(A(dY_, sizeof(c128) * (size_t)y_elems_));
+  NEP_TRY(A(dR_, sizeof(c128) * (size_t)y_elems_));
+  const size_t G = nnodes;
+  const size_t node_bytes = G * (3 + kMaxTerms + kMaxMoments) * sizeof(c128) + G * sizeof(double) + 2 * G * sizeof(int);
+  NEP_TRY(A(dnode_, node_bytes));
+  const size_t ir_bytes = 2 * G * kNormStride * 8 + (size_t)nprob * 64 * 8 + G * 8 + 3 * G * 4 + 8 * 4;
+  NEP_TRY(A(dir_, ir_bytes));
+
+  {
+    char* q = dnode_.as<char>();
+    na_.z = reinterpret_cast<c128*>(q); q += G * sizeof(c128);
+    na_.zeta = reinterpret_cast<c128*>(q); q += G * sizeof(c128);
+    na_.w = reinterpret_cast<c128*>(q); q += G * sizeof(c128);
+    na_.fz = reinterpret_cast<c128*>(q); q += G * kMaxTerms * sizeof(c128);
+    na_.mcoef = reinterpret_cast<c128*>(q); q += G * kMaxMoments * sizeof(c128);
+    na_.fnorm = reinterpret_cast<double*>(q); q += G * sizeof(double);
+    na_.prob = reinterpret_cast<int*>(q); q += G * sizeof(int);
+    na_.jnode = reinterpret_cast<int*>(q);
+    char* r = dir_.as<char>();
+    ir_.rnorm = reinterpret_cast<unsigned long long*>(r); r += G * kNormStride * 8;
+    ir_.ynorm = reinterpret_cast<unsigned long long*>(r); r += G * kNormStride * 8;
+    ir_.vnorm = reinterpret_cast<double*>(r); r += (size_t)nprob * 64 * 8;
+    ir_.rho = reinterpret_cast<double*>(r); r += G * 8;
+    ir_.conv = reinterpret_cast<int*>(r); r += G * 4;
+    ir_.stalled = reinterpret_cast<int*>(r); r += G * 4;
+    ir_.sweeps = reinterpret_cast<int*>(r); r += G * 4;
+    ir_.counters = reinterpret_cast<int*>(r);
+  }
+  if (!hcounter_) NEP_HIP(hipHostMalloc((void**)&hcounter_, 64, hipHostMallocDefault));
+
+  NEP_HIP(hipMemcpy(dmd_.p, sorted_.data(), sizeof(MatDesc) * sorted_.size(), hipMemcpyHostToDevice));
+  NEP_HIP(hipMemcpy(dprefix_.p, hprefix_.data(), sizeof(int) * hprefix_.size(), hipMemcpyHostToDevice));
+  if (!lu_.prefix.empty())
+    NEP_HIP(hipMemcpy(dlu_prefix_.p, lu_.prefix.data(), sizeof(int) * lu_.prefix.size(), hipMemcpyHostToDevice));
+  if (mixed && o.fallback && !lu64_.prefix.empty())
+    NEP_HIP(hipMemcpy(dlu64_prefix_.p, lu64_.prefix.data(), sizeof(int) * lu64_.prefix.size(),
+                      hipMemcpyHostToDevice));
+  NEP_HIP(hipMemcpy(na_.prob, hprob.data(), sizeof(int) * G, hipMemcpyHostToDevice));
+  NEP_HIP(hipMemcpy(na_.jnode, hj.data(), sizeof(int) * G, hipMemcpyHostToDevice));
+  dT64_.release();
+  dWk64_.release();
+  return upload_problems(probs);
+}
+
+template <typename P>
+nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
+  const ProbDesc* pd = dpd_.as<ProbDesc>();
+  const MatDesc* md = dmd_.as<MatDesc>();
+  const int* pre = dprefix_.as<int>();
+  cx<P>* T = dT_.as<cx<P>>();
+  cx<P>* Wk = dWk_.as<cx<P>>();
+  c128* Y = dY_.as<c128>();
+  c128* R = dR_.as<c128>();
+  int* rows = drows_.as<int>();
+  int* info = dinfo_.as<int>();
+  NEP_HIP(ir_reset(ir_, nnodes, st));
+  NEP_HIP(launch_vnorm(pd, nprob, ir_, st));
+  NEP_HIP(launch_coef(pd, na_, nnodes, ir_, st));
+  NEP_HIP(launch_assemble<P>(pd, pre, pt_.assemble, na_, T, nullptr, st));
+  NEP_HIP(lu_run<P>(lu_, md, dlu_prefix_.as<int>(), T, rows, info, nullptr, st));
+  NEP_HIP(solve_run<P>(sp_, pre, pd, md, na_, T, rows, Wk, nullptr, Y, false, nullptr, ir_, Lmax, st));
+  sweeps_run_ = 0;
+  if (opt.max_refine > 0) {
+    for (int s = 0; s <= opt.max_refine; ++s) {
+      NEP_HIP(resid_run(pd, pre, pt_.resid, na_, Y, R, ir_, nnodes, st));
+      NEP_HIP(ir_control(pd, na_, ir_, nnodes, s, opt.tol, st));
+      sweeps_run_ = s;
+      if (eager) {
+        NEP_HIP(hipMemcpyAsync(hcounter_, ir_.counters, sizeof(int), hipMemcpyDeviceToHost, st));
+        NEP_HIP(hipStreamSynchronize(st));
+        if (hcounter_[0] == 0) break;
+      }
+      if (s == opt.max_refine) break;
+      NEP_HIP(solve_run<P>(sp_, pre, pd, md, na_, T, rows, Wk, R, Y, true, ir_.conv, ir_, Lmax, st));
+    }
+    if (eager && hcounter_[0] > 0 && opt.fallback && sizeof(P) == 4) NEP_TRY(run_fallback<double>(st));
+  }
+  NEP_HIP(launch_moments(pd, pre, pt_.moments, na_, Y, st));
+  return NEP_OK;
+}
+
+// FP64 re-solve of the nodes whose refinement did not converge: assemble in
+// complex FP64, factor on the FP64 matrix cores, solve, overwrite Y.
+template <typename P>
+nep_status MomentsPlan::run_fallback(hipStream_t st) {
+  static_assert(sizeof(P) == 8, "fallback runs in FP64");
+  if (!dT64_.p) {
+    NEP_TRY(dT64_.alloc(sizeof(c128) * (size_t)t_elems_));
+    NEP_TRY(dWk64_.alloc(sizeof(c128) * (size_t)w_elems_));
+  }
+  const ProbDesc* pd = dpd_.as<ProbDesc>();
+  const MatDesc* md = dmd_.as<MatDesc>();
+  const int* pre = dprefix_.as<int>();
+  c128* T = dT64_.as<c128>();
+  c128* Wk = dWk64_.as<c128>();
+  const int* skip = ir_.conv;
+  {
+    std::vector<int> conv(nnodes);
+    NEP_HIP(hipMemcpy(conv.data(), ir_.conv, sizeof(int) * nnodes, hipMemcpyDeviceToHost));
+    fallback_count_.assign(nprob, 0);
+    for (int p = 0; p < nprob; ++p)
+      for (int j = 0; j < opt.N; ++j) fallback_count_[p] += conv[hpd_[p].node0 + j] ? 0 : 1;
+  }
+  NEP_HIP(launch_assemble<double>(pd, pre, pt_.assemble, na_, T, skip, st));
+  NEP_HIP(lu_run<double>(lu64_, md, dlu64_prefix_.as<int>(), T, drows_.as<int>(), dinfo_.as<int>(), skip, st));
+  NEP_HIP(solve_run<double>(sp_, pre, pd, md, na_, T, drows_.as<int>(), Wk, nullptr, dY_.as<c128>(), false, skip,
+                            ir_, Lmax, st));
+  // check the residual of the re-solved nodes once
+  NEP_HIP(resid_run(pd, pre, pt_.resid, na_, dY_.as<c128>(), dR_.as<c128>(), ir_, nnodes, st));
+  NEP_HIP(ir_control(pd, na_, ir_, nnodes, opt.max_refine + 1, opt.tol, st));
+  fallback_pending_ = true;
+  return NEP_OK;
+}
+
+nep_status MomentsPlan::enqueue(hipStream_t st, bool eager) {
+  fallback_pending_ = false;
+  if (opt.prec == NEP_PREC_FP64) return enqueue_t<double>(st, eager);
+  return enqueue_t<float>(st, eager);
+}
+
+nep_status MomentsPlan::finish(hipStream_t st, RunResult& out, bool /*allow_fallback*/) {
+  NEP_HIP(hipStreamSynchronize(st));
+  const int G = nnodes;
+  std::vector<int> info(G), conv(G), stalled(G), sweeps(G), counters(4);
+  std::vector<double> rho(G);
+  NEP_HIP(hipMemcpy(info.data(), dinfo_.p, sizeof(int) * G, hipMemcpyDeviceToHost));
+  NEP_HIP(hipMemcpy(conv.data(), ir_.conv, sizeof(int) * G, hipMemcpyDeviceToHost));
+  NEP_HIP(hipMemcpy(stalled.data(), ir_.stalled, sizeof(int) * G, hipMemcpyDeviceToHost));
+  NEP_HIP(hipMemcpy(sweeps.data(), ir_.sweeps, sizeof(int) * G, hipMemcpyDeviceToHost));
+  NEP_HIP(hipMemcpy(rho.data(), ir_.rho, sizeof(double) * G, hipMemcpyDeviceToHost));
+  NEP_HIP(hipMemcpy(counters.data(), ir_.counters, sizeof(int) * 4, hipMemcpyDeviceToHost));
+  out.stats.assign(nprob, nep_ciss_stats{});
+  out.status = NEP_OK;
+  std::vector<int> hprob(G);
+  for (int p = 0; p < nprob; ++p)
+    for (int j = 0; j < opt.N; ++j) hprob[hpd_[p].node0 + j] = p;
+  for (int p = 0; p < nprob; ++p) {
+    nep_ciss_stats& s = out.stats[p];
+    s.N = opt.N;
+    s.singular_node = -1;
+    s.bad_node = -1;
+    s.max_rel_residual = opt.max_refine > 0 ? 0.0 : -1.0;
+  }
+  const bool refined = opt.max_refine > 0;
+  if (fallback_pending_)
+    for (int p = 0; p < nprob; ++p) out.stats[p].n_fallback = fallback_count_[p];
+  for (int g = 0; g < G; ++g) {
+    const int p = hprob[g];
+    nep_ciss_stats& s = out.stats[p];
+    const int j = g - hpd_[p].node0;
+    if (info[g] < hpd_[p].n && s.singular_node < 0) s.singular_node = j;
+    if (refined) {
+      s.refine_sweeps = std::max(s.refine_sweeps, std::min(sweeps[g] - 1, opt.max_refine));
+      if (!conv[g]) s.n_unconverged++;
+      if (std::isfinite(rho[g])) s.max_rel_residual = std::max(s.max_rel_residual, rho[g]);
+    }
+  }
+  if (counters[1] > 0) {
+    const int g = counters[3];
+    const int p = (g >= 0 && g < G) ? hprob[g] : 0;
+    out.stats[p].bad_node = g - hpd_[p].node0;
+    set_error("quadrature node %d of problem %d lies on a pole or branch cut of some f_i", g - hpd_[p].node0, p);
+    out.status = NEP_ERR_NOT_HOLOMORPHIC;
+    return out.status;
+  }
+  for (int p = 0; p < nprob; ++p) {
+    if (out.stats[p].singular_node >= 0) {
+      set_error("T(z_j) has an exact zero pivot at node %d of problem %d", out.stats[p].singular_node, p);
+      out.status = NEP_ERR_SINGULAR;
+      return out.status;
+    }
+  }
+  for (int p = 0; p < nprob; ++p) {
+    if (out.stats[p].n_unconverged > 0 && refined && opt.prec == NEP_PREC_C32_IR64) {
+      set_error("refinement did not reach the tolerance at %d node(s) of problem %d", out.stats[p].n_unconverged,
+                p);
+      out.status = NEP_ERR_REFINE;
+      return out.status;
+    }
+  }
+  return NEP_OK;
+}
+
+nep_status configure_kernels() {
+  static int done = 0;
+  if (done) return NEP_OK;
+  NEP_HIP(lu_configure());
+  NEP_HIP(solve_configure());
+  done = 1;
+  return NEP_OK;
+}
+
+template nep_status MomentsPlan::enqueue_t<float>(hipStream_t, bool);
+template nep_status MomentsPlan::enqueue_t<double>(hipStream_t, bool);
+
+}  // namespace nep

@@ -1,0 +1,114 @@
+// Host-side moment plan: layout of a batch of problems x nodes on the device,
+// launch tables, buffers, and the launch sequence (eager or captured).
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "engine.hpp"
+
+namespace nep {
+
+// Device memory block owned by a plan or a handle.
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  ~DevMem() { release(); }
+  nep_status alloc(size_t b);
+  void release();
+  template <typename T>
+  T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// What the operator handle contributes to a plan.
+struct SplitOperator {
+  int n = 0, ell = 0;
+  int a_cplx = 0;
+  int is_cplx[kMaxTerms] = {0};
+  const void* dA[kMaxTerms] = {nullptr};  // device row-major copies
+  const double* dnormA = nullptr;
+  std::vector<double> normA;
+  const FnNode* dfn_nodes = nullptr;
+  const c128* dfn_coef = nullptr;
+  int fn_root[kMaxTerms] = {0};
+};
+
+struct PlanProblem {
+  const SplitOperator* op;
+  nep_contour g;
+  const c128* V;
+  c128* S;
+};
+
+struct PlanOptions {
+  int N = 32, L = 8, K = 2, prec = NEP_PREC_C32_IR64;
+  int max_refine = 5, fallback = 1;
+  double tol = 1e-14;
+};
+
+struct RunResult {
+  nep_status status = NEP_OK;
+  std::vector<nep_ciss_stats> stats;  // per problem
+};
+
+class MomentsPlan {
+ public:
+  MomentsPlan() = default;
+  MomentsPlan(const MomentsPlan&) = delete;
+  MomentsPlan& operator=(const MomentsPlan&) = delete;
+  ~MomentsPlan() {
+    if (hcounter_) (void)hipHostFree(hcounter_);
+  }
+  // Builds layout, tables and buffers.  Problems may differ in n (ragged).
+  nep_status build(const std::vector<PlanProblem>& probs, const PlanOptions& o);
+  // Enqueues the whole moment path on st.  eager=true lets the host stop the
+  // refinement loop early (one small read-back per sweep); eager=false runs a
+  // fixed number of sweeps with device-side skipping (graph capture safe).
+  nep_status enqueue(hipStream_t st, bool eager);
+  // Waits, reads back device status, runs the FP64 fallback for nodes whose
+  // refinement stalled (if enabled), and fills per-problem stats.
+  nep_status finish(hipStream_t st, RunResult& out, bool allow_fallback);
+  // Device buffers shared with extraction and the server.
+  const c128* Y() const { return dY_.as<c128>(); }
+  // Rebinds caller buffers (V, S) and contours without rebuilding.
+  nep_status rebind(const std::vector<PlanProblem>& probs);
+  bool matches(const std::vector<PlanProblem>& probs, const PlanOptions& o) const;
+  size_t device_bytes() const { return total_bytes_; }
+  static size_t estimate_bytes(int n, int N, int L, int prec);
+
+  PlanOptions opt;
+  int nprob = 0, nnodes = 0, Lmax = 0;
+
+ private:
+  nep_status upload_problems(const std::vector<PlanProblem>& probs);
+  template <typename P>
+  nep_status enqueue_t(hipStream_t st, bool eager);
+  template <typename P>
+  nep_status run_fallback(hipStream_t st);
+
+  std::vector<ProbDesc> hpd_;
+  std::vector<MatDesc> sorted_;
+  std::vector<int> prob_of_sorted_;
+  LuPlan lu_, lu64_;
+  SolvePlan sp_;
+  ProblemTables pt_;
+  std::vector<int> hprefix_;
+  DevMem dpd_, dmd_, dprefix_, dlu_prefix_, dlu64_prefix_;
+  DevMem dT_, drows_, dinfo_, dWk_, dY_, dR_, dnode_, dir_, dT64_, dWk64_;
+  NodeArrays na_{};
+  IrState ir_{};
+  int* hcounter_ = nullptr;  // pinned host read-back
+  size_t total_bytes_ = 0;
+  long long t_elems_ = 0, w_elems_ = 0, y_elems_ = 0;
+  int rows_total_ = 0;
+  int sweeps_run_ = 0;
+  bool fallback_pending_ = false;
+  std::vector<int> fallback_count_;  // per problem, nodes re-solved in FP64
+};
+
+nep_status configure_kernels();
+
+}  // namespace nep

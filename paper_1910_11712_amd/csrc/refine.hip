@@ -1,0 +1,233 @@
+// FP64 iterative refinement of the node solves.
+//
+// Residual in split form (the way the paper evaluates T(lambda) x for a split
+// operator, Section 5): R_j = V - sum_i A_i (f_i(z_j) Y_j), computed for every
+// node at once as one FP64 GEMM per term over all N*L columns [Y_1 .. Y_N], on
+// the FP64 matrix cores (v_mfma_f64_16x16x4f64).  The complex columns are
+// viewed as pairs of real columns (re, im); for a real A_i this is a plain
+// real GEMM, for a complex A_i the 2x2 real embedding is built in the B tile.
+// The scalar f_i(z_j) of each column block is applied while staging Y.
+//
+// Control: a node is converged when, for every probe column c,
+//   ||r_c||_inf <= tol (sum_i |f_i(z_j)| ||A_i||_inf ||y_c||_inf + ||v_c||_inf),
+// a normwise backward-error test (moduli of complex entries).  A node whose
+// scaled residual does not at least halve in a sweep is marked stalled.
+#include <climits>
+
+#include "engine.hpp"
+
+namespace nep {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int kRTM = 64;   // rows per tile
+constexpr int kRTQ = 64;   // real columns per tile (32 complex)
+constexpr int kRKC = 16;   // real k per stage
+
+template <bool ACPLX>
+__global__ __launch_bounds__(256) void k_resid(const ProbDesc* __restrict__ pd, const int* __restrict__ prefix,
+                                               int cnt, int total, NodeArrays na, const c128* __restrict__ Y,
+                                               c128* __restrict__ R, IrState ir) {
+  const int v = xcd_remap(blockIdx.x, gridDim.x, total);
+  if (v < 0) return;
+  const int p = find_slot(prefix, cnt, v);
+  const ProbDesc& D = pd[p];
+  if (ACPLX != (D.a_cplx != 0)) return;
+  const int t = v - prefix[p];
+  const int n = D.n, L = D.L, NL = D.N * D.L, Q = 2 * NL;
+  const int tiles_q = (Q + kRTQ - 1) / kRTQ;
+  const int tm = t / tiles_q, tq = t - tm * tiles_q;
+  const int row0 = tm * kRTM, q0 = tq * kRTQ;
+  // skip when every node covered by this column tile has converged
+  {
+    const int cc0 = q0 / 2, cc1 = min(NL, cc0 + kRTQ / 2) - 1;
+    bool any = false;
+    for (int j = cc0 / L; j <= cc1 / L; ++j) any |= (ir.conv[D.node0 + j] == 0);
+    if (!any) return;
+  }
+  __shared__ double As[kRKC][kRTM + 1];
+  __shared__ double Bs[kRKC][kRTQ + 2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wq = (wave & 1) * 32;
+  const double* __restrict__ Yd = reinterpret_cast<const double*>(Y + D.offY);
+
+  doublex4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+
+  for (int term = 0; term < D.ell; ++term) {
+    const double* __restrict__ A = reinterpret_cast<const double*>(D.A[term]);
+    const int acplx = ACPLX ? D.a_is_cplx[term] : 0;
+    const int Kd = acplx ? 2 * n : n;            // real k extent of this term
+    const int lda = acplx ? 2 * n : n;
+    for (int k0 = 0; k0 < Kd; k0 += kRKC) {
+      // A tile: 64 rows x 16 k
+      for (int e = tid; e < kRTM * kRKC; e += 256) {
+        const int r = e >> 4, k = e & 15;
+        const int gr = row0 + r, gk = k0 + k;
+        As[k][r] = (gr < n && gk < Kd) ? A[(long long)gr * lda + gk] : 0.0;
+      }
+      if (!acplx) {
+        // B tile: 16 rows s of Y x 32 complex columns -> re/im real columns
+        for (int e = tid; e < kRKC * (kRTQ / 2); e += 256) {
+          const int k = e >> 5, cl = e & 31;
+          const int s = k0 + k, cc = q0 / 2 + cl;
+          double br = 0.0, bi = 0.0;
+          if (s < n && cc < NL) {
+            const c128 y = {Yd[2 * ((long long)s * NL + cc)], Yd[2 * ((long long)s * NL + cc) + 1]};
+            const c128 f = na.fz[(long long)(D.node0 + cc / L) * kMaxTerms + term];
+            const c128 fy = f * y;
+            br = fy.re;
+            bi = fy.im;
+          }
+          Bs[k][2 * cl] = br;
+          Bs[k][2 * cl + 1] = bi;
+        }
+      } else {
+        // complex A: real k = (s, u); B[(s,u)][(cc,t)] = [[re, im], [-im, re]]
+        for (int e = tid; e < (kRKC / 2) * (kRTQ / 2); e += 256) {
+          const int ks = e >> 5, cl = e & 31;
+          const int s = k0 / 2 + ks, cc = q0 / 2 + cl;
+          double br = 0.0, bi = 0.0;
+          if (s < n && cc < NL) {
+            const c128 y = {Yd[2 * ((long long)s * NL + cc)], Yd[2 * ((long long)s * NL + cc) + 1]};
+            const c128 f = na.fz[(long long)(D.node0 + cc / L) * kMaxTerms + term];
+            const c128 fy = f * y;
+            br = fy.re;
+            bi = fy.im;
+          }
+          Bs[2 * ks][2 * cl] = br;
+          Bs[2 * ks][2 * cl + 1] = bi;
+          Bs[2 * ks + 1][2 * cl] = -bi;
+          Bs[2 * ks + 1][2 * cl + 1] = br;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kRKC; kk += 4) {
+        double af[2], bf[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) af[i] = As[kk + (lane >> 4)][wr + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bf[j] = Bs[kk + (lane >> 4)][wq + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  // epilogue: lane l, reg r -> row (l/16) + 4r, real column l%16 of the block
+  double* __restrict__ Rd = reinterpret_cast<double*>(R + D.offY);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int q = q0 + wq + j * 16 + (lane & 15);
+    const int cc = q >> 1, tcomp = q & 1;
+    const int node = cc / L, c = cc - node * L;
+    double cm = 0.0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + wr + i * 16 + (lane >> 4) + 4 * r;
+        double val = 0.0;
+        if (gr < n && q < Q) {
+          const c128 vv = D.V[(long long)c * n + gr];
+          val = (tcomp ? vv.im : vv.re) - acc[i][j][r];
+          Rd[(long long)gr * Q + q] = val;
+        }
+        const double other = __shfl_xor(val, 1, 64);
+        cm = fmax(cm, sqrt(val * val + other * other));
+      }
+    cm = fmax(cm, __shfl_xor(cm, 16, 64));
+    cm = fmax(cm, __shfl_xor(cm, 32, 64));
+    if (lane < 16 && tcomp == 0 && q < Q)
+      atomicMax(&ir.rnorm[(long long)(D.node0 + node) * kNormStride + c], (unsigned long long)__double_as_longlong(cm));
+  }
+}
+
+hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const NodeArrays& na, const c128* Y,
+                     c128* R, IrState ir, int /*nnodes*/, hipStream_t st) {
+  if (t.total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_resid<false>, dim3(xcd_grid(t.total)), dim3(256), 0, st, pd, prefix + t.off, t.cnt, t.total,
+                     na, Y, R, ir);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_resid<true>, dim3(xcd_grid(t.total)), dim3(256), 0, st, pd, prefix + t.off, t.cnt, t.total,
+                     na, Y, R, ir);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_ir_control(const ProbDesc* __restrict__ pd, NodeArrays na, IrState ir, int nnodes, int sweep,
+                             double tol) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nnodes) return;
+  if (ir.conv[g]) return;
+  const int p = na.prob[g];
+  const ProbDesc& D = pd[p];
+  const double fn = na.fnorm[g];
+  double rho = 0.0;
+  for (int c = 0; c < D.L; ++c) {
+    const double rn = __longlong_as_double((long long)ir.rnorm[(long long)g * kNormStride + c]);
+    const double yn = __longlong_as_double((long long)ir.ynorm[(long long)g * kNormStride + c]);
+    const double den = fn * yn + ir.vnorm[p * 64 + c];
+    const double q = den > 0.0 ? rn / den : (rn > 0.0 ? 1e300 : 0.0);
+    rho = fmax(rho, q);
+    ir.rnorm[(long long)g * kNormStride + c] = 0ull;
+    ir.ynorm[(long long)g * kNormStride + c] = 0ull;
+  }
+  const double prev = ir.rho[g];
+  ir.rho[g] = rho;
+  ir.sweeps[g] = sweep + 1;
+  if (rho <= tol) {
+    ir.conv[g] = 1;
+  } else {
+    if (sweep > 0 && !(rho <= 0.5 * prev)) ir.stalled[g] = 1;
+    atomicAdd(&ir.counters[0], 1);
+  }
+}
+
+__global__ void k_ir_reset(IrState ir, int nnodes) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nnodes * kNormStride) {
+    ir.rnorm[i] = 0ull;
+    ir.ynorm[i] = 0ull;
+  }
+  if (i < nnodes) {
+    ir.conv[i] = 0;
+    ir.stalled[i] = 0;
+    ir.sweeps[i] = 0;
+    ir.rho[i] = 1e300;
+  }
+  if (i == 0) {
+    ir.counters[0] = 0;
+    ir.counters[1] = 0;
+    ir.counters[2] = 0;
+    ir.counters[3] = INT_MAX;
+  }
+}
+
+__global__ void k_zero_int(int* p, int cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) p[i] = 0;
+}
+
+hipError_t ir_control(const ProbDesc* pd, const NodeArrays& na, IrState ir, int nnodes, int sweep, double tol,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, ir.counters, 1);
+  hipLaunchKernelGGL(k_ir_control, dim3(ceil_div(nnodes, 64)), dim3(64), 0, st, pd, na, ir, nnodes, sweep, tol);
+  return hipGetLastError();
+}
+
+hipError_t ir_reset(IrState ir, int nnodes, hipStream_t st) {
+  hipLaunchKernelGGL(k_ir_reset, dim3(ceil_div(std::max(nnodes * kNormStride, 1), 256)), dim3(256), 0, st, ir, nnodes);
+  return hipGetLastError();
+}
+
+}  // namespace nep

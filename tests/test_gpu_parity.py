@@ -1,0 +1,117 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: moments ||S_gpu - S_oracle||_F / ||S_oracle||_F <= 1e-10 for every
+p (both precisions); eigenvalues |dl|/|l| <= 1e-10 with eta <= 1e-10 for the
+pairs inside the contour.  The mixed path refines every node to a normwise
+backward error of 1e-14, so its moments carry the error of FP64 solves.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from workloads import Contour, Problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def nep():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1910_11712_amd as P
+    P.binding.lib()
+    return P
+
+
+def _rel_fro(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _run_moments(P, prob, con, N, L, K, V, prec, **kw):
+    op = P.SplitOperator.from_problem(prob)
+    Vd = P.device_probes(V)
+    S, st = op.moments(con, Vd, N, L, K, prec=prec, **kw)
+    return op, S, P.moments_to_numpy(S), st
+
+
+def _check_moments(Sg, So, tol=1e-10):
+    for p in range(So.shape[0]):
+        assert _rel_fro(Sg[p], So[p]) <= tol, (p, _rel_fro(Sg[p], So[p]))
+
+
+def _match_inside(got_lam, ref_lam, tol):
+    got = list(np.asarray(got_lam))
+    assert len(got) == len(ref_lam), (got_lam, ref_lam)
+    for r in ref_lam:
+        k = int(np.argmin([abs(g - r) for g in got]))
+        assert abs(got[k] - r) <= tol * max(abs(r), 1e-2), (got[k], r)
+        got.pop(k)
+
+
+# ---------------------------------------------------------------------------
+
+def test_fn_eval_matches_oracle(nep):
+    rng = np.random.default_rng(1)
+    z = rng.standard_normal(64) * 50 + 1j * rng.standard_normal(64) * 50 + 100
+    fns = [wl.fn_rational([1.0, -2.0, 3.0], [1.0, 0.5j]), wl.fn_exp(alpha=-0.7 + 0.1j, beta=2.0),
+           wl.fn_log(), wl.fn_sqrt(beta=1j), wl.fn_invsqrt(alpha=2.0),
+           wl.fn_phi(0), wl.fn_phi(1), wl.fn_phi(3, alpha=0.01),
+           wl.fn_combine(wl.COMB_COMPOSE, wl.fn_rational([1.0, -108.8 ** 2]), wl.fn_sqrt(), beta=1j),
+           wl.fn_combine(wl.COMB_DIV, wl.fn_exp(alpha=0.01), wl.fn_rational([1.0, 3.0]))]
+    mats = [np.eye(3)] * len(fns)
+    op = nep.SplitOperator(mats, fns)
+    got = op.fn_eval(z)
+    for i, f in enumerate(fns):
+        ref = np.array([oracle.fn_value(f, zz) for zz in z])
+        assert np.max(np.abs(got[i] - ref) / np.maximum(np.abs(ref), 1e-300)) < 1e-13, i
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_config0_moments(nep, prec):
+    cfg = wl.config0()
+    p, con = cfg["problem"], cfg["contour"]
+    So = oracle.ciss_moments(p, con, cfg["N"], cfg["K"], cfg["V"])
+    op, S, Sg, st = _run_moments(nep, p, con, cfg["N"], cfg["L"], cfg["K"], cfg["V"], prec)
+    print(prec, st)
+    _check_moments(Sg, So)
+    if prec == "mixed":
+        assert st["n_unconverged"] == 0
+        assert st["max_rel_residual"] <= 1e-14
+
+
+@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 130, 200, 257, 520])
+def test_ragged_sizes_complex_terms(nep, n):
+    """Dense complex terms, sizes spanning several tiles and ragged tails."""
+    rng = np.random.default_rng(n)
+    A0 = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A1 = np.eye(n)
+    A2 = rng.standard_normal((n, n)) / np.sqrt(n)
+    prob = Problem("rand", [A0, A1, A2],
+                   [wl.fn_rational([1.0]), wl.fn_rational([-1.0, 0.0]), wl.fn_exp(alpha=-0.5)])
+    con = Contour.circle(0.5 + 0.2j, 1.5 * np.sqrt(n) + 0.3)
+    N, L, K = 16, 3, 2
+    V = wl.probes(n, L, 5)
+    So = oracle.ciss_moments(prob, con, N, K, V)
+    for prec in ("mixed", "fp64"):
+        _, _, Sg, st = _run_moments(nep, prob, con, N, L, K, V, prec)
+        _check_moments(Sg, So, 1e-10 if prec == "fp64" else 1e-9)
+
+
+def test_config0_extract(nep):
+    cfg = wl.config0()
+    p, con = cfg["problem"], cfg["contour"]
+    So = oracle.ciss_moments(p, con, cfg["N"], cfg["K"], cfg["V"])
+    ro = oracle.extract(p, con, So, cfg["K"])
+    op, S, Sg, st = _run_moments(nep, p, con, cfg["N"], cfg["L"], cfg["K"], cfg["V"], "mixed")
+    r = op.extract(con, S, cfg["N"], cfg["L"], cfg["K"], max_eigs=16)
+    ins = r["inside"]
+    _match_inside(r["lam"][ins], ro["lam"][ro["inside"]], 1e-10)
+    assert np.all(r["eta"][ins] <= 1e-10), r["eta"]
+    # eigenvectors agree with the oracle's (same normalization)
+    for lam, x in zip(r["lam"][ins], r["X"][:, ins].T):
+        k = int(np.argmin(np.abs(ro["lam"] - lam)))
+        assert np.linalg.norm(x - ro["X"][:, k]) < 1e-8
+    assert r["m"] == ro["m"]
