@@ -113,7 +113,7 @@ typedef struct {
 typedef struct nep_split_s* nep_split;
 
 /* Creates a handle for T(z) = sum_i f_i(z) A_i.
- *   n      : matrix size, 1 <= n <= 8192.
+ *   n      : matrix size, 1 <= n <= 4096.
  *   ell    : number of terms, 1 <= ell <= 16.
  *   A      : host array of ell matrix descriptors; the data are copied to the
  *            device (stored row-major there) before the call returns.
@@ -309,6 +309,21 @@ double nep_server_clock(nep_server s);
 nep_status nep_server_destroy(nep_server* s);
 
 /* ------------------------------------------------------------------------ */
+
+/* ------------------------------------------------------------------------ */
+/* Instrumentation                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Enables (1) or disables (0) HIP-event timing of every trailing-update GEMM
+ * launch of the LU (k_lu_gemm_c64 / k_lu_gemm_c128) on the stream it runs on.
+ * Enabling clears earlier records.  Process-wide; not thread-safe. */
+nep_status nep_prof_enable(int on);
+
+/* Reads the records: for kind 0 (complex FP32 GEMM) or 1 (complex FP64 GEMM),
+ * *launches = number of launches, *ms = summed device time of the launches
+ * (synchronizes their events), *flops = summed algorithmic flops of the
+ * launches (8 real flops per complex multiply-add). */
+nep_status nep_prof_read(int kind, int* launches, double* ms, double* flops);
 
 /* Thread-local description of the last error on the calling thread. */
 const char* nep_last_error(void);

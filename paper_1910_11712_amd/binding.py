@@ -113,6 +113,8 @@ def lib():
         L.nep_batch_destroy.argtypes = [C.POINTER(vp)]
         L.nep_ciss_moments_batch.argtypes = [ip, C.POINTER(vp), C.POINTER(nep_contour), C.POINTER(nep_ciss_opts),
                                              C.POINTER(vp), C.POINTER(vp), C.POINTER(nep_ciss_stats)]
+        L.nep_prof_enable.argtypes = [ip]
+        L.nep_prof_read.argtypes = [ip, C.POINTER(ip), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         if not hasattr(L, "nep_server_create"):
             _lib = L
             return _lib
@@ -291,3 +293,14 @@ def nep_fn_eval(h, ell, z):
     check(lib().nep_fn_eval(h, m, zi.ctypes.data_as(C.POINTER(C.c_double)),
                             out.ctypes.data_as(C.POINTER(C.c_double))))
     return (out[0::2] + 1j * out[1::2]).reshape(ell, m)
+
+
+def nep_prof_enable(on):
+    check(lib().nep_prof_enable(1 if on else 0))
+
+
+def nep_prof_read(kind):
+    """(launches, ms, flops) of the LU trailing-update GEMM launches."""
+    n, ms, fl = C.c_int(0), C.c_double(0), C.c_double(0)
+    check(lib().nep_prof_read(int(kind), C.byref(n), C.byref(ms), C.byref(fl)))
+    return n.value, ms.value, fl.value

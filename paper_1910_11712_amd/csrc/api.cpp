@@ -299,3 +299,38 @@ nep_status nep_fn_eval(nep_split h, int m, const double* z, double* out) {
 }
 
 }  // extern "C"
+
+extern "C" {
+
+nep_status nep_prof_enable(int on) {
+  KernelProf& p = kernel_prof();
+  for (auto& r : p.recs) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  p.recs.clear();
+  p.on = on != 0;
+  return NEP_OK;
+}
+
+nep_status nep_prof_read(int kind, int* launches, double* ms, double* flops) {
+  NEP_CHECK(launches && ms && flops, NEP_ERR_ARG, "null output");
+  KernelProf& p = kernel_prof();
+  int cnt = 0;
+  double t = 0.0, f = 0.0;
+  for (auto& r : p.recs) {
+    if (r.kind != kind) continue;
+    NEP_HIP(hipEventSynchronize(r.e1));
+    float x = 0.f;
+    NEP_HIP(hipEventElapsedTime(&x, r.e0, r.e1));
+    t += x;
+    f += r.flops;
+    ++cnt;
+  }
+  *launches = cnt;
+  *ms = t;
+  *flops = f;
+  return NEP_OK;
+}
+
+}  // extern "C"

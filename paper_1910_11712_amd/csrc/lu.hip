@@ -608,6 +608,8 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
   prec = prec_;
   jb = lu_jb(prec);
   nmat = (int)sorted.size();
+  nvec.clear();
+  for (const auto& m : sorted) nvec.push_back(m.n);
   nmax = nmat ? sorted[0].n : 0;
   steps.clear();
   prefix.clear();
@@ -643,6 +645,12 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Optional kernel timing (events around each trailing-update GEMM launch).
+// ---------------------------------------------------------------------------
+static KernelProf g_prof;
+KernelProf& kernel_prof() { return g_prof; }
+
 template <typename P>
 hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* info,
                   const int* skip, hipStream_t st) {
@@ -659,6 +667,12 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (s.tot_gemm > 0) {
+      hipEvent_t ev0 = nullptr, ev1 = nullptr;
+      if (g_prof.on) {
+        (void)hipEventCreate(&ev0);
+        (void)hipEventCreate(&ev1);
+        (void)hipEventRecord(ev0, st);
+      }
       if constexpr (sizeof(P) == 4)
         hipLaunchKernelGGL(k_lu_gemm_c64, dim3(xcd_grid(s.tot_gemm)), dim3(256), 0, st, d_md, d_prefix + s.off_gemm,
                            s.nact, s.tot_gemm, s.k0, plan.jb, T, rows, skip);
@@ -666,6 +680,15 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
         hipLaunchKernelGGL(k_lu_gemm_c128, dim3(xcd_grid(s.tot_gemm)), dim3(256), 0, st, d_md,
                            d_prefix + s.off_gemm, s.nact, s.tot_gemm, s.k0, plan.jb, T, rows, skip);
       if ((e = hipGetLastError()) != hipSuccess) return e;
+      if (g_prof.on) {
+        (void)hipEventRecord(ev1, st);
+        double flops = 0.0;  // 8 real flops per complex multiply-add of the update
+        for (int b = 0; b < s.nact; ++b) {
+          const int n = plan.nvec[b], jbb = std::min(plan.jb, n - s.k0), mt = n - s.k0 - jbb;
+          if (mt > 0) flops += 8.0 * mt * (double)mt * jbb;
+        }
+        g_prof.add(sizeof(P) == 4 ? 0 : 1, ev0, ev1, flops);
+      }
     }
   }
   return hipSuccess;

@@ -19,8 +19,22 @@ struct LuPlan {
   int jb = 128, prec = NEP_PREC_C32_IR64, nmat = 0, nmax = 0;
   std::vector<Step> steps;
   std::vector<int> prefix;  // uploaded once; offsets above index into it
+  std::vector<int> nvec;    // sizes of the sorted matrices
   void build(const std::vector<MatDesc>& sorted, int prec);
 };
+
+// Event timing of the trailing-update GEMM launches (kind 0: c64, 1: c128).
+struct KernelProf {
+  bool on = false;
+  struct Rec {
+    int kind;
+    hipEvent_t e0, e1;
+    double flops;
+  };
+  std::vector<Rec> recs;
+  void add(int kind, hipEvent_t a, hipEvent_t b, double f) { recs.push_back(Rec{kind, a, b, f}); }
+};
+KernelProf& kernel_prof();
 
 int lu_jb(int prec);
 hipError_t lu_configure();
