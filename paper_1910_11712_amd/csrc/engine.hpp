@@ -69,9 +69,10 @@ struct Table {
 };
 
 struct SolvePlan {
-  int nblk_max = 0;
-  std::vector<Table> fwd, bwd;  // per block step s
-  Table gather;                 // tiles of n*L per matrix
+  int nmat = 0;     // matrices (sorted order)
+  int lg = 4;       // right-hand columns per group
+  int groups = 1;   // column groups per matrix
+  Table diag;       // diagonal-block inversions: 2 * nblk per matrix
 };
 
 struct ProblemTables {
@@ -92,11 +93,14 @@ hipError_t launch_moments(const ProbDesc* pd, const int* prefix, const Table& t,
 hipError_t launch_vnorm(const ProbDesc* pd, int nprob, IrState ir, hipStream_t st);
 
 template <typename P>
-hipError_t solve_run(const SolvePlan& sp, const int* d_prefix, const ProbDesc* pd, const MatDesc* md,
-                     const NodeArrays& na, const cx<P>* T, const int* rows, cx<P>* Wk, const c128* R, c128* Y,
-                     bool refine, const int* conv, IrState ir, int Lmax, hipStream_t st);
-void SolvePlan_build(SolvePlan& sp, std::vector<int>& buf, const std::vector<MatDesc>& sorted,
-                     const std::vector<int>& Lof);
+hipError_t diag_inv_run(const SolvePlan& sp, const int* d_prefix, const MatDesc* md, const cx<P>* T,
+                        const int* rows, cx<P>* Dinv, const long long* dinv_off, const int* skip, hipStream_t st);
+template <typename P>
+hipError_t solve_run(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md, const NodeArrays& na,
+                     const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off, cx<P>* Wk,
+                     const c128* R, c128* Y, bool refine, const int* conv, IrState ir, hipStream_t st);
+void SolvePlan_build(SolvePlan& sp, std::vector<int>& buf, const std::vector<MatDesc>& sorted, int L,
+                     std::vector<long long>& dinv_off, long long& dinv_elems);
 hipError_t solve_configure();
 
 hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const NodeArrays& na, const c128* Y,

@@ -15,9 +15,10 @@
 //                of W columns live in registers (one logical row per thread and
 //                slot), pivots are found by a wave shuffle + LDS reduction,
 //                modulus |Re|+|Im|, ties to the lowest row.
-//   k_lu_trsm  : U12 = L11^{-1} A12 for 64-column tiles of the trailing block,
-//                L11 in LDS, one wave per right-hand column at a time.
-//   k_lu_gemm  : A22 -= L21 U12 on the matrix cores.  Complex products use the
+//                The panel group also inverts its unit lower diagonal block
+//                L11 (FP64, stored in the factor precision).
+//   k_lu_gemm<1>: U12 = L11^{-1} A12 on the matrix cores (block-row solve).
+//   k_lu_gemm<0>: A22 -= L21 U12 on the matrix cores.  Complex products use the
 //                real 2x2 embedding [ar -ai; ai ar] built in the operand
 //                registers, so one real MFMA k-pair is one complex k.
 //                c64: v_mfma_f32_32x32x2f32, 128x128 complex tile per group.
@@ -58,7 +59,8 @@ template <typename P, int W, int RPT>
 __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __restrict__ md, int k0, int jbmax,
                                                            cx<P>* __restrict__ Tb, int* __restrict__ rowb,
                                                            int* __restrict__ info,
-                                                           const int* __restrict__ skip) {
+                                                           const int* __restrict__ skip,
+                                                           cx<P>* __restrict__ Linv) {
   const MatDesc d = md[blockIdx.x];
   const int n = d.n;
   if (k0 >= n) return;
@@ -74,6 +76,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
   __shared__ cx<P> xbuf[2][2][W];
   __shared__ cx<P> Ltop[W][W];
   __shared__ cx<P> Utop[W][kLuMaxJB];
+  __shared__ cx<P> Lc[kPanelThreads][W];
   __shared__ int zero_pivot;
 
   const int tid = threadIdx.x;
@@ -233,89 +236,69 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
         }
       }
       __syncthreads();
+      // rows >= rc0: A[r][right] -= L[r][leaf] U[leaf][right], 512 rows at a
+      // time; the leaf values go through LDS so that each wave updates whole
+      // contiguous row segments (lanes along the columns).
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        const int r = c0 + tid + i * kPanelThreads;
-        if (r >= rc0 && r < n) {
+        const int rbase = c0 + i * kPanelThreads;
+        if (rbase >= n) break;
+#pragma unroll
+        for (int w = 0; w < W; ++w) Lc[tid][w] = a[i][w];
+        __syncthreads();
+        const int rlo = max(rbase, rc0), rhi = min(n, rbase + kPanelThreads);
+        for (int r = rlo + wave; r < rhi; r += kPanelThreads / 64) {
           cx<P>* row = T + (long long)rat[r - k0] * ld + rc0;
-          for (int j = 0; j < nr; ++j) {
+          const int lr = r - rbase;
+          for (int j = lane; j < nr; j += 64) {
             cx<P> acc = row[j];
 #pragma unroll
             for (int w = 0; w < W; ++w)
-              if (w < wc) acc = fms(acc, a[i][w], Utop[w][j]);
+              if (w < wc) acc = fms(acc, Lc[lr][w], Utop[w][j]);
             row[j] = acc;
           }
         }
+        __syncthreads();
       }
-      __syncthreads();
+    }
+  }
+  // ---- inverse of the unit lower diagonal block L11 (for the block-row
+  // update U12 = L11^{-1} A12 on the matrix cores); one wave per column,
+  // rows over lanes, computed in FP64.
+  __syncthreads();
+  if (Linv != nullptr) {
+    cx<P>* __restrict__ Li = Linv + (long long)blockIdx.x * kLuMaxJB * kLuMaxJB;
+    for (int c = wave; c < jb; c += kPanelThreads / 64) {
+      c128 x[kLuMaxJB / 64];
+#pragma unroll
+      for (int q = 0; q < kLuMaxJB / 64; ++q) x[q] = c128{(lane + 64 * q == c) ? 1.0 : 0.0, 0.0};
+      for (int s2 = c; s2 < jb; ++s2) {
+        const int qs = s2 >> 6, ls = s2 & 63;
+        c128 xs;
+#pragma unroll
+        for (int q = 0; q < kLuMaxJB / 64; ++q)
+          if (q == qs) {
+            xs.re = __shfl(x[q].re, ls, 64);
+            xs.im = __shfl(x[q].im, ls, 64);
+          }
+#pragma unroll
+        for (int q = 0; q < kLuMaxJB / 64; ++q) {
+          const int r = lane + 64 * q;
+          if (r > s2 && r < jb) {
+            const cx<P> l = T[(long long)rat[r] * ld + k0 + s2];
+            x[q] = fms(x[q], c128{double(l.re), double(l.im)}, xs);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kLuMaxJB / 64; ++q) {
+        const int r = lane + 64 * q;
+        if (r < jb) Li[(long long)r * kLuMaxJB + c] = cx<P>{P(x[q].re), P(x[q].im)};
+      }
     }
   }
   for (int r = tid; r < m; r += kPanelThreads) rowg[k0 + r] = rat[r];
   if (tid == 0 && zero_pivot < n) atomicMin(&info[d.node], zero_pivot);
-}
-
-// ---------------------------------------------------------------------------
-// TRSM: U12 = L11^{-1} A12 on 64-column tiles (unit lower L11, jb x jb)
-// ---------------------------------------------------------------------------
-constexpr int kTrsmCols = 64;
-
-template <typename P>
-__global__ __launch_bounds__(256) void k_lu_trsm(const MatDesc* __restrict__ md, const int* __restrict__ prefix,
-                                                 int nact, int total, int k0, int jbmax, cx<P>* __restrict__ Tb,
-                                                 const int* __restrict__ rowb, const int* __restrict__ skip) {
-  const int v = xcd_remap(blockIdx.x, gridDim.x, total);
-  if (v < 0) return;
-  const int b = find_slot(prefix, nact, v);
-  const int tile = v - prefix[b];
-  const MatDesc d = md[b];
-  if (skip != nullptr && skip[d.node]) return;
-  const int n = d.n;
-  const int jb = min(jbmax, n - k0);
-  const int j0 = k0 + jb + tile * kTrsmCols;
-  const int ncol = min(kTrsmCols, n - j0);
-  if (ncol <= 0) return;
-  cx<P>* __restrict__ T = Tb + d.offT;
-  const int ld = d.ld;
-  const int* __restrict__ rat = rowb + d.offRow + k0;
-
-  extern __shared__ unsigned char smem_raw[];
-  cx<P>* Ls = reinterpret_cast<cx<P>*>(smem_raw);  // jb x (jb+1) padded
-  const int lds = jb + 1;
-  for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) {
-    const int r = e / jb, s = e - r * jb;
-    Ls[r * lds + s] = (s < r) ? T[(long long)rat[r] * ld + k0 + s] : cx<P>{P(0), P(0)};
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int kRowSlots = kLuMaxJB / 64;
-  for (int col = wave; col < ncol; col += 4) {
-    cx<P> x[kRowSlots];
-#pragma unroll
-    for (int q = 0; q < kRowSlots; ++q) {
-      const int r = lane + 64 * q;
-      x[q] = (r < jb) ? T[(long long)rat[r] * ld + j0 + col] : cx<P>{P(0), P(0)};
-    }
-#pragma unroll
-    for (int qs = 0; qs < kRowSlots; ++qs) {
-      for (int s = 0; s < 64; ++s) {
-        const int sg = qs * 64 + s;
-        if (sg >= jb) break;
-        cx<P> xs;
-        xs.re = __shfl(x[qs].re, s, 64);
-        xs.im = __shfl(x[qs].im, s, 64);
-#pragma unroll
-        for (int q = qs; q < kRowSlots; ++q) {
-          const int r = lane + 64 * q;
-          if (r > sg && r < jb) x[q] = fms(x[q], Ls[r * lds + sg], xs);
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kRowSlots; ++q) {
-      const int r = lane + 64 * q;
-      if (r < jb) T[(long long)rat[r] * ld + j0 + col] = x[q];
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -324,9 +307,14 @@ __global__ __launch_bounds__(256) void k_lu_trsm(const MatDesc* __restrict__ md,
 // c64 variant: 256 threads = 4 waves (2 x 2), each wave 64 x 64 complex.
 constexpr int kG32TM = 128, kG32TN = 128, kG32KC = 16;
 
+// MODE 0: trailing update A22 -= L21 U12 (rows/cols >= k0+jb).
+// MODE 1: block-row solve U12 = L11^{-1} A12 with the stored inverse (rows
+//         k0..k0+jb-1, cols >= k0+jb), result stored in place.
+template <int MODE>
 __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restrict__ md, const int* __restrict__ prefix,
                                                      int nact, int total, int k0, int jbmax, c64* __restrict__ Tb,
-                                                     const int* __restrict__ rowb, const int* __restrict__ skip) {
+                                                     const int* __restrict__ rowb, const int* __restrict__ skip,
+                                                     const c64* __restrict__ Linv) {
   const int v = xcd_remap(blockIdx.x, gridDim.x, total);
   if (v < 0) return;
   const int b = find_slot(prefix, nact, v);
@@ -339,10 +327,12 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
   const int mt = n - s0;           // trailing size
   const int tiles_n = (mt + kG32TN - 1) / kG32TN;
   const int tm = t / tiles_n, tn = t - tm * tiles_n;
-  const int row0 = s0 + tm * kG32TM, col0 = s0 + tn * kG32TN;
+  const int row0 = (MODE == 0 ? s0 : k0) + tm * kG32TM, col0 = s0 + tn * kG32TN;
+  const int row_end = MODE == 0 ? n : k0 + jb;
   c64* __restrict__ T = Tb + d.offT;
   const int ld = d.ld;
   const int* __restrict__ rat = rowb + d.offRow;
+  const c64* __restrict__ Li = MODE == 1 ? Linv + (long long)b * kLuMaxJB * kLuMaxJB : nullptr;
 
   // LDS: A as [k][row] complex (stride kG32TM+2), B as re/im planes [k][col].
   __shared__ float As[2][kG32KC][2 * kG32TM + 4];
@@ -362,8 +352,9 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
       const int r = e >> 3, kp = e & 7;   // A: row, k-pair
       const int gr = row0 + r, gk = kk + 2 * kp;
       float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gr < n && gk < k0 + jb) {
-        const c64* src = T + (long long)rat[gr] * ld + gk;
+      if (gr < row_end && gk < k0 + jb) {
+        const c64* src = MODE == 0 ? T + (long long)rat[gr] * ld + gk
+                                   : Li + (long long)(gr - k0) * kLuMaxJB + (gk - k0);
         if (gk + 1 < k0 + jb) val = *reinterpret_cast<const float4*>(src);
         else val = make_float4(src->re, src->im, 0.f, 0.f);
       }
@@ -446,12 +437,16 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
       for (int r = 0; r < 16; r += 2) {
         const int crow = 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
         const int gr = row0 + wr + i * 16 + crow;
-        if (gr < n && gc < n) {
+        if (gr < row_end && gc < n) {
           c64* p = T + (long long)rat[gr] * ld + gc;
-          c64 cv = *p;
-          cv.re -= acc[i][j][r];
-          cv.im -= acc[i][j][r + 1];
-          *p = cv;
+          if (MODE == 0) {
+            c64 cv = *p;
+            cv.re -= acc[i][j][r];
+            cv.im -= acc[i][j][r + 1];
+            *p = cv;
+          } else {
+            *p = c64{acc[i][j][r], acc[i][j][r + 1]};
+          }
         }
       }
     }
@@ -460,9 +455,11 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
 // c128 variant: 256 threads = 4 waves (2 x 2), each wave 64 x 32 complex.
 constexpr int kG64TM = 128, kG64TN = 64, kG64KC = 8;
 
+template <int MODE>
 __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restrict__ md, const int* __restrict__ prefix,
                                                       int nact, int total, int k0, int jbmax, c128* __restrict__ Tb,
-                                                      const int* __restrict__ rowb, const int* __restrict__ skip) {
+                                                      const int* __restrict__ rowb, const int* __restrict__ skip,
+                                                      const c128* __restrict__ Linv) {
   const int v = xcd_remap(blockIdx.x, gridDim.x, total);
   if (v < 0) return;
   const int b = find_slot(prefix, nact, v);
@@ -475,10 +472,12 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
   const int mt = n - s0;
   const int tiles_n = (mt + kG64TN - 1) / kG64TN;
   const int tm = t / tiles_n, tn = t - tm * tiles_n;
-  const int row0 = s0 + tm * kG64TM, col0 = s0 + tn * kG64TN;
+  const int row0 = (MODE == 0 ? s0 : k0) + tm * kG64TM, col0 = s0 + tn * kG64TN;
+  const int row_end = MODE == 0 ? n : k0 + jb;
   c128* __restrict__ T = Tb + d.offT;
   const int ld = d.ld;
   const int* __restrict__ rat = rowb + d.offRow;
+  const c128* __restrict__ Li = MODE == 1 ? Linv + (long long)b * kLuMaxJB * kLuMaxJB : nullptr;
 
   __shared__ double As[2][kG64KC][2 * kG64TM + 2];
   __shared__ double Bs[2][kG64KC][2][kG64TN + 2];
@@ -496,7 +495,9 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
       const int r = e >> 3, kq = e & 7;
       const int gr = row0 + r, gk = kk + kq;
       double2 val = make_double2(0.0, 0.0);
-      if (gr < n && gk < k0 + jb) val = *reinterpret_cast<const double2*>(T + (long long)rat[gr] * ld + gk);
+      if (gr < row_end && gk < k0 + jb)
+        val = *reinterpret_cast<const double2*>(MODE == 0 ? T + (long long)rat[gr] * ld + gk
+                                                          : Li + (long long)(gr - k0) * kLuMaxJB + (gk - k0));
       ra[q] = val;
     }
 #pragma unroll
@@ -578,9 +579,10 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gr = row0 + wr + i * 8 + rbase + 2 * r;
-        if (gr < n && gc < n) {
+        if (gr < row_end && gc < n) {
           double* p = reinterpret_cast<double*>(T + (long long)rat[gr] * ld + gc) + tcomp;
-          *p -= acc[i][j][r];
+          if (MODE == 0) *p -= acc[i][j][r];
+          else *p = acc[i][j][r];
         }
       }
     }
@@ -591,13 +593,13 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
 // ---------------------------------------------------------------------------
 template <typename P, int W>
 static hipError_t launch_panel(int rpt, int nact, const MatDesc* md, int k0, int jb, cx<P>* T, int* rows, int* info,
-                               const int* skip, hipStream_t st) {
+                               const int* skip, cx<P>* Linv, hipStream_t st) {
   dim3 g(nact), blk(kPanelThreads);
   switch (rpt) {
-    case 1: hipLaunchKernelGGL((k_lu_panel<P, W, 1>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
-    case 2: hipLaunchKernelGGL((k_lu_panel<P, W, 2>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
-    case 4: hipLaunchKernelGGL((k_lu_panel<P, W, 4>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
-    default: hipLaunchKernelGGL((k_lu_panel<P, W, 8>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    case 1: hipLaunchKernelGGL((k_lu_panel<P, W, 1>), g, blk, 0, st, md, k0, jb, T, rows, info, skip, Linv); break;
+    case 2: hipLaunchKernelGGL((k_lu_panel<P, W, 2>), g, blk, 0, st, md, k0, jb, T, rows, info, skip, Linv); break;
+    case 4: hipLaunchKernelGGL((k_lu_panel<P, W, 4>), g, blk, 0, st, md, k0, jb, T, rows, info, skip, Linv); break;
+    default: hipLaunchKernelGGL((k_lu_panel<P, W, 8>), g, blk, 0, st, md, k0, jb, T, rows, info, skip, Linv); break;
   }
   return hipGetLastError();
 }
@@ -625,9 +627,10 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
     s.off_trsm = (int)prefix.size();
     int acc = 0;
     prefix.push_back(0);
+    const int TNs = prec == NEP_PREC_FP64 ? kG64TN : kG32TN;
     for (int b = 0; b < nact; ++b) {
       const int n = sorted[b].n, jbb = std::min(jb, n - k0), mt = n - k0 - jbb;
-      acc += mt > 0 ? ceil_div(mt, kTrsmCols) : 0;
+      acc += mt > 0 ? ceil_div(mt, TNs) : 0;
       prefix.push_back(acc);
     }
     s.tot_trsm = acc;
@@ -653,19 +656,24 @@ KernelProf& kernel_prof() { return g_prof; }
 
 template <typename P>
 hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* info,
-                  const int* skip, hipStream_t st) {
+                  const int* skip, cx<P>* Linv, hipStream_t st) {
   hipError_t e;
   hipLaunchKernelGGL(k_lu_init, dim3(plan.nmat), dim3(256), 0, st, d_md, plan.nmat, rows, info);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   constexpr int W = sizeof(P) == 4 ? 8 : 4;
-  const size_t trsm_lds = (size_t)plan.jb * (plan.jb + 1) * sizeof(cx<P>);
   for (const auto& s : plan.steps) {
-    if ((e = launch_panel<P, W>(s.rpt, s.nact, d_md, s.k0, plan.jb, T, rows, info, skip, st)) != hipSuccess) return e;
-    if (s.tot_trsm > 0) {
-      hipLaunchKernelGGL(k_lu_trsm<P>, dim3(xcd_grid(s.tot_trsm)), dim3(256), trsm_lds, st, d_md,
-                         d_prefix + s.off_trsm, s.nact, s.tot_trsm, s.k0, plan.jb, T, rows, skip);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    const bool more = s.tot_trsm > 0;
+    if ((e = launch_panel<P, W>(s.rpt, s.nact, d_md, s.k0, plan.jb, T, rows, info, skip, more ? Linv : nullptr,
+                                st)) != hipSuccess)
+      return e;
+    if (!more) continue;
+    if constexpr (sizeof(P) == 4)
+      hipLaunchKernelGGL(k_lu_gemm_c64<1>, dim3(xcd_grid(s.tot_trsm)), dim3(256), 0, st, d_md, d_prefix + s.off_trsm,
+                         s.nact, s.tot_trsm, s.k0, plan.jb, T, rows, skip, Linv);
+    else
+      hipLaunchKernelGGL(k_lu_gemm_c128<1>, dim3(xcd_grid(s.tot_trsm)), dim3(256), 0, st, d_md,
+                         d_prefix + s.off_trsm, s.nact, s.tot_trsm, s.k0, plan.jb, T, rows, skip, Linv);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (s.tot_gemm > 0) {
       hipEvent_t ev0 = nullptr, ev1 = nullptr;
       if (g_prof.on) {
@@ -674,11 +682,11 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
         (void)hipEventRecord(ev0, st);
       }
       if constexpr (sizeof(P) == 4)
-        hipLaunchKernelGGL(k_lu_gemm_c64, dim3(xcd_grid(s.tot_gemm)), dim3(256), 0, st, d_md, d_prefix + s.off_gemm,
-                           s.nact, s.tot_gemm, s.k0, plan.jb, T, rows, skip);
+        hipLaunchKernelGGL(k_lu_gemm_c64<0>, dim3(xcd_grid(s.tot_gemm)), dim3(256), 0, st, d_md,
+                           d_prefix + s.off_gemm, s.nact, s.tot_gemm, s.k0, plan.jb, T, rows, skip, Linv);
       else
-        hipLaunchKernelGGL(k_lu_gemm_c128, dim3(xcd_grid(s.tot_gemm)), dim3(256), 0, st, d_md,
-                           d_prefix + s.off_gemm, s.nact, s.tot_gemm, s.k0, plan.jb, T, rows, skip);
+        hipLaunchKernelGGL(k_lu_gemm_c128<0>, dim3(xcd_grid(s.tot_gemm)), dim3(256), 0, st, d_md,
+                           d_prefix + s.off_gemm, s.nact, s.tot_gemm, s.k0, plan.jb, T, rows, skip, Linv);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       if (g_prof.on) {
         (void)hipEventRecord(ev1, st);
@@ -694,17 +702,11 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
   return hipSuccess;
 }
 
-hipError_t lu_configure() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_lu_trsm<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     128 * 129 * sizeof(c64));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_lu_trsm<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             64 * 65 * sizeof(c128));
-}
+hipError_t lu_configure() { return hipSuccess; }
 
-template hipError_t lu_run<float>(const LuPlan&, const MatDesc*, const int*, c64*, int*, int*, const int*,
+template hipError_t lu_run<float>(const LuPlan&, const MatDesc*, const int*, c64*, int*, int*, const int*, c64*,
                                   hipStream_t);
-template hipError_t lu_run<double>(const LuPlan&, const MatDesc*, const int*, c128*, int*, int*, const int*,
+template hipError_t lu_run<double>(const LuPlan&, const MatDesc*, const int*, c128*, int*, int*, const int*, c128*,
                                    hipStream_t);
 
 }  // namespace nep

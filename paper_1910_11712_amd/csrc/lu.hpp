@@ -39,8 +39,9 @@ KernelProf& kernel_prof();
 int lu_jb(int prec);
 hipError_t lu_configure();
 
+// Linv: workspace of nact * kLuMaxJB^2 elements (inverses of the L11 blocks).
 template <typename P>
 hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* info,
-                  const int* skip, hipStream_t st);
+                  const int* skip, cx<P>* Linv, hipStream_t st);
 
 }  // namespace nep

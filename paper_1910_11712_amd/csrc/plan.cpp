@@ -42,6 +42,8 @@ size_t MomentsPlan::estimate_bytes(int n, int N, int L, int prec) {
   size_t b = (size_t)N * ld * n * elem_size(prec);        // factors
   b += (size_t)N * n * sizeof(int);                        // row maps
   b += (size_t)N * n * L * elem_size(prec);                // solve work
+  b += (size_t)N * ((n + 63) / 64) * 2 * 64 * 64 * elem_size(prec);  // diagonal-block inverses
+  b += (size_t)N * kLuMaxJB * kLuMaxJB * elem_size(prec);            // panel inverses
   b += 2 * (size_t)n * N * L * sizeof(c128);               // Y, R
   b += (size_t)N * (kMaxTerms + kMaxMoments + 8) * sizeof(c128) + (size_t)N * kNormStride * 16;
   return b;
@@ -137,7 +139,7 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   if (mixed && o.fallback) lu64_.build(sorted_, NEP_PREC_FP64);
 
   hprefix_.clear();
-  SolvePlan_build(sp_, hprefix_, sorted_, std::vector<int>(sorted_.size(), o.L));
+  SolvePlan_build(sp_, hprefix_, sorted_, o.L, dinv_off_, dinv_elems_);
   {
     std::vector<int> ca, cr, cm;
     for (int p = 0; p < nprob; ++p) {
@@ -167,6 +169,9 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   NEP_TRY(A(drows_, sizeof(int) * (size_t)rows_total_));
   NEP_TRY(A(dinfo_, sizeof(int) * (size_t)nnodes));
   NEP_TRY(A(dWk_, es * (size_t)w_elems_));
+  NEP_TRY(A(ddinv_, es * (size_t)dinv_elems_));
+  NEP_TRY(A(dlinv_, es * (size_t)sorted_.size() * kLuMaxJB * kLuMaxJB));
+  NEP_TRY(A(ddinv_off_, sizeof(long long) * dinv_off_.size()));
   NEP_TRY(A(dY_, sizeof(c128) * (size_t)y_elems_));
   NEP_TRY(A(dR_, sizeof(c128) * (size_t)y_elems_));
   const size_t G = nnodes;
@@ -204,10 +209,13 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   if (mixed && o.fallback && !lu64_.prefix.empty())
     NEP_HIP(hipMemcpy(dlu64_prefix_.p, lu64_.prefix.data(), sizeof(int) * lu64_.prefix.size(),
                       hipMemcpyHostToDevice));
+  NEP_HIP(hipMemcpy(ddinv_off_.p, dinv_off_.data(), sizeof(long long) * dinv_off_.size(), hipMemcpyHostToDevice));
   NEP_HIP(hipMemcpy(na_.prob, hprob.data(), sizeof(int) * G, hipMemcpyHostToDevice));
   NEP_HIP(hipMemcpy(na_.jnode, hj.data(), sizeof(int) * G, hipMemcpyHostToDevice));
   dT64_.release();
   dWk64_.release();
+  ddinv64_.release();
+  dlinv64_.release();
   return upload_problems(probs);
 }
 
@@ -226,8 +234,11 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
   NEP_HIP(launch_vnorm(pd, nprob, ir_, st));
   NEP_HIP(launch_coef(pd, na_, nnodes, ir_, st));
   NEP_HIP(launch_assemble<P>(pd, pre, pt_.assemble, na_, T, nullptr, st));
-  NEP_HIP(lu_run<P>(lu_, md, dlu_prefix_.as<int>(), T, rows, info, nullptr, st));
-  NEP_HIP(solve_run<P>(sp_, pre, pd, md, na_, T, rows, Wk, nullptr, Y, false, nullptr, ir_, Lmax, st));
+  NEP_HIP(lu_run<P>(lu_, md, dlu_prefix_.as<int>(), T, rows, info, nullptr, dlinv_.as<cx<P>>(), st));
+  cx<P>* Dinv = ddinv_.as<cx<P>>();
+  const long long* doff = ddinv_off_.as<long long>();
+  NEP_HIP(diag_inv_run<P>(sp_, pre, md, T, rows, Dinv, doff, nullptr, st));
+  NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, Wk, nullptr, Y, false, nullptr, ir_, st));
   sweeps_run_ = 0;
   if (opt.max_refine > 0) {
     for (int s = 0; s <= opt.max_refine; ++s) {
@@ -240,7 +251,7 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
         if (hcounter_[0] == 0) break;
       }
       if (s == opt.max_refine) break;
-      NEP_HIP(solve_run<P>(sp_, pre, pd, md, na_, T, rows, Wk, R, Y, true, ir_.conv, ir_, Lmax, st));
+      NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, Wk, R, Y, true, ir_.conv, ir_, st));
     }
     if (eager && hcounter_[0] > 0 && opt.fallback && sizeof(P) == 4) NEP_TRY(run_fallback<double>(st));
   }
@@ -256,6 +267,8 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
   if (!dT64_.p) {
     NEP_TRY(dT64_.alloc(sizeof(c128) * (size_t)t_elems_));
     NEP_TRY(dWk64_.alloc(sizeof(c128) * (size_t)w_elems_));
+    NEP_TRY(ddinv64_.alloc(sizeof(c128) * (size_t)dinv_elems_));
+    NEP_TRY(dlinv64_.alloc(sizeof(c128) * (size_t)sorted_.size() * kLuMaxJB * kLuMaxJB));
   }
   const ProbDesc* pd = dpd_.as<ProbDesc>();
   const MatDesc* md = dmd_.as<MatDesc>();
@@ -271,9 +284,13 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
       for (int j = 0; j < opt.N; ++j) fallback_count_[p] += conv[hpd_[p].node0 + j] ? 0 : 1;
   }
   NEP_HIP(launch_assemble<double>(pd, pre, pt_.assemble, na_, T, skip, st));
-  NEP_HIP(lu_run<double>(lu64_, md, dlu64_prefix_.as<int>(), T, drows_.as<int>(), dinfo_.as<int>(), skip, st));
-  NEP_HIP(solve_run<double>(sp_, pre, pd, md, na_, T, drows_.as<int>(), Wk, nullptr, dY_.as<c128>(), false, skip,
-                            ir_, Lmax, st));
+  NEP_HIP(lu_run<double>(lu64_, md, dlu64_prefix_.as<int>(), T, drows_.as<int>(), dinfo_.as<int>(), skip,
+                         dlinv64_.as<c128>(), st));
+  c128* Dinv = ddinv64_.as<c128>();
+  const long long* doff = ddinv_off_.as<long long>();
+  NEP_HIP(diag_inv_run<double>(sp_, pre, md, T, drows_.as<int>(), Dinv, doff, skip, st));
+  NEP_HIP(solve_run<double>(sp_, pd, md, na_, T, drows_.as<int>(), Dinv, doff, Wk, nullptr, dY_.as<c128>(), false,
+                            skip, ir_, st));
   // check the residual of the re-solved nodes once
   NEP_HIP(resid_run(pd, pre, pt_.resid, na_, dY_.as<c128>(), dR_.as<c128>(), ir_, nnodes, st));
   NEP_HIP(ir_control(pd, na_, ir_, nnodes, opt.max_refine + 1, opt.tol, st));

@@ -98,6 +98,9 @@ class MomentsPlan {
   std::vector<int> hprefix_;
   DevMem dpd_, dmd_, dprefix_, dlu_prefix_, dlu64_prefix_;
   DevMem dT_, drows_, dinfo_, dWk_, dY_, dR_, dnode_, dir_, dT64_, dWk64_;
+  DevMem ddinv_, ddinv_off_, ddinv64_, dlinv_, dlinv64_;
+  std::vector<long long> dinv_off_;
+  long long dinv_elems_ = 0;
   NodeArrays na_{};
   IrState ir_{};
   int* hcounter_ = nullptr;  // pinned host read-back

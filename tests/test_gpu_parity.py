@@ -115,3 +115,95 @@ def test_config0_extract(nep):
         k = int(np.argmin(np.abs(ro["lam"] - lam)))
         assert np.linalg.norm(x - ro["X"][:, k]) < 1e-8
     assert r["m"] == ro["m"]
+
+
+def test_config1_full_size_moments(nep):
+    """Delay problem at its full size (n=1000, N=64, L=16, K=16), both paths."""
+    cfg = wl.config1()
+    p, con = cfg["problem"], cfg["contour"]
+    So = oracle.ciss_moments(p, con, cfg["N"], cfg["K"], cfg["V"])
+    for prec in ("mixed", "fp64"):
+        _, _, Sg, st = _run_moments(nep, p, con, cfg["N"], cfg["L"], cfg["K"], cfg["V"], prec)
+        print(prec, st)
+        _check_moments(Sg, So)
+
+
+def test_config2_reduced_extract(nep):
+    """Square-root problem (two sqrt terms, complex T) at n=1024: moments and
+    the eigenpairs inside the ellipse against the oracle."""
+    cfg = wl.config2(1024)
+    p, con = cfg["problem"], cfg["contour"]
+    So = oracle.ciss_moments(p, con, cfg["N"], cfg["K"], cfg["V"])
+    ro = oracle.extract(p, con, So, cfg["K"])
+    op, S, Sg, st = _run_moments(nep, p, con, cfg["N"], cfg["L"], cfg["K"], cfg["V"], "mixed")
+    print(st)
+    _check_moments(Sg, So)
+    r = op.extract(con, S, cfg["N"], cfg["L"], cfg["K"], max_eigs=64)
+    band = np.abs(np.abs((ro["lam"] - con.c) / con.rho) - 1) > 1e-6
+    ref = ro["lam"][ro["inside"] & band]
+    assert len(ref) >= 20
+    _match_inside(r["lam"][r["inside"]], ref, 1e-10)
+    assert np.all(r["eta"][r["inside"]] <= 1e-10)
+
+
+def test_error_singular_node(nep):
+    prob = Problem("sing", [np.diag([1.0, 0.0, 2.0])], [wl.fn_rational([1.0])])
+    V = wl.probes(3, 2, 0)
+    for prec in ("mixed", "fp64"):
+        with pytest.raises(nep.NepError) as ei:
+            _run_moments(nep, prob, Contour.circle(0.0, 1.0), 8, 2, 1, V, prec)
+        assert ei.value.name == "NEP_ERR_SINGULAR"
+
+
+def test_error_branch_cut(nep):
+    f = wl.fn_combine(wl.COMB_COMPOSE, wl.fn_rational([-1.0]), wl.fn_sqrt())   # sqrt(-1): on the cut
+    prob = Problem("cut", [np.eye(3), np.eye(3)], [wl.fn_rational([1.0]), f])
+    with pytest.raises(nep.NepError) as ei:
+        _run_moments(nep, prob, Contour.circle(0.0, 1.0), 8, 2, 1, wl.probes(3, 2, 0), "mixed")
+    assert ei.value.name == "NEP_ERR_NOT_HOLOMORPHIC"
+
+
+def test_error_rank_saturated(nep):
+    d = np.array([0.1, -0.2j, 0.3 + 0.1j, 5.0])
+    prob = Problem("diag", [np.diag(d).astype(complex), np.eye(4)],
+                   [wl.fn_rational([1.0]), wl.fn_rational([-1.0, 0.0])])
+    con = Contour.circle(0.0, 1.0)
+    op, S, Sg, st = _run_moments(nep, prob, con, 32, 2, 1, wl.probes(4, 2, 0), "fp64")
+    with pytest.raises(nep.NepError) as ei:
+        op.extract(con, S, 32, 2, 1, max_eigs=8)
+    assert ei.value.name == "NEP_ERR_RANK"
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_batch_equals_single_calls(nep, use_graph):
+    """A ragged batch (one plan, one set of launches or one graph) gives
+    bitwise the same moments as one call per problem."""
+    import ctypes as C
+    cfg = wl.config3(nprob=6, nmin=64, nmax=300)
+    con, N, L, K = cfg["contour"], cfg["N"], cfg["L"], cfg["K"]
+    ops, Vs, Ss, singles = [], [], [], []
+    for p, V in zip(cfg["problems"], cfg["V"]):
+        op, S1, Sg1, st = _run_moments(nep, p, con, N, L, K, V, "mixed")
+        ops.append(op)
+        singles.append(Sg1)
+        Vs.append(nep.device_probes(V))
+        Ss.append(torch.zeros((2 * K, L, p.n), dtype=torch.complex128, device="cuda"))
+    B = nep.binding
+    n = len(ops)
+    harr = (C.c_void_p * n)(*[o.h.value for o in ops])
+    garr = (B.nep_contour * n)(*[B.contour_struct(con) for _ in ops])
+    o = B.opts_struct(N, L, K, "mixed")
+    varr = (C.c_void_p * n)(*[v.data_ptr() for v in Vs])
+    sarr = (C.c_void_p * n)(*[s.data_ptr() for s in Ss])
+    bh = C.c_void_p()
+    B.check(B.lib().nep_batch_create(n, harr, garr, C.byref(o), varr, sarr, use_graph, None, C.byref(bh)))
+    st = (B.nep_ciss_stats * n)()
+    for rep in range(2):   # replays see the same result
+        for s in Ss:
+            s.zero_()
+        torch.cuda.synchronize()
+        B.check(B.lib().nep_batch_run(bh, st))
+        for k in range(n):
+            Sg = nep.moments_to_numpy(Ss[k])
+            assert np.array_equal(Sg, singles[k]), (rep, k, np.abs(Sg - singles[k]).max())
+    B.check(B.lib().nep_batch_destroy(C.byref(bh)))
