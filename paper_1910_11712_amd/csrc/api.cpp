@@ -127,6 +127,31 @@ nep_status Split::init(int n_, int ell_, const nep_mat* A, const nep_fn* f, hipS
       src = staging.p;
     }
     NEP_HIP(to_rowmajor(src, A[i].ld, n_, cplx, mats[i]->p, stream));
+    if (!A[i].on_device) {  // diagonal terms skip the dense residual product
+      const double* h = static_cast<const double*>(A[i].data);
+      bool diag = true;
+      for (long long c = 0; c < n_ && diag; ++c)
+        for (long long r = 0; r < n_; ++r) {
+          if (r == c) continue;
+          const double* e = h + (r + c * A[i].ld) * words;
+          if (e[0] != 0.0 || (cplx && e[1] != 0.0)) {
+            diag = false;
+            break;
+          }
+        }
+      if (diag) {
+        std::vector<c128> dv(n_);
+        for (long long r = 0; r < n_; ++r) {
+          const double* e = h + (r + r * A[i].ld) * words;
+          dv[r] = c128{e[0], cplx ? e[1] : 0.0};
+        }
+        diags[i] = std::make_unique<DevMem>();
+        NEP_TRY(diags[i]->alloc(sizeof(c128) * n_));
+        NEP_HIP(hipMemcpy(diags[i]->p, dv.data(), sizeof(c128) * n_, hipMemcpyHostToDevice));
+        op.is_diag[i] = 1;
+        op.dDiag[i] = diags[i]->as<c128>();
+      }
+    }
     NEP_HIP(inf_norm(mats[i]->p, n_, cplx, scratch, norms.as<double>() + i, stream));
     NEP_HIP(hipStreamSynchronize(stream));  // staging is released at scope end
     op.dA[i] = mats[i]->p;

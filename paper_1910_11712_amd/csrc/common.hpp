@@ -37,10 +37,17 @@ template <typename P>
 __host__ __device__ __forceinline__ cx<P> operator-(cx<P> a) { return {-a.re, -a.im}; }
 template <typename P>
 __host__ __device__ __forceinline__ cx<P> conj(cx<P> a) { return {a.re, -a.im}; }
+__host__ __device__ __forceinline__ float pfma(float a, float b, float c) { return fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double pfma(double a, double b, double c) { return fma(a, b, c); }
 // a - b*c  (the update step of every elimination / substitution)
 template <typename P>
 __host__ __device__ __forceinline__ cx<P> fms(cx<P> a, cx<P> b, cx<P> c) {
-  return {a.re - b.re * c.re + b.im * c.im, a.im - b.re * c.im - b.im * c.re};
+  return {pfma(-b.re, c.re, pfma(b.im, c.im, a.re)), pfma(-b.re, c.im, pfma(-b.im, c.re, a.im))};
+}
+// acc + a*b as four fused multiply-adds
+template <typename P>
+__host__ __device__ __forceinline__ cx<P> cmac(cx<P> acc, cx<P> a, cx<P> b) {
+  return {pfma(a.re, b.re, pfma(-a.im, b.im, acc.re)), pfma(a.re, b.im, pfma(a.im, b.re, acc.im))};
 }
 template <typename P>
 __host__ __device__ __forceinline__ P abs1(cx<P> a) {  // |Re| + |Im|

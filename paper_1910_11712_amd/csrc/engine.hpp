@@ -35,6 +35,8 @@ struct ProbDesc {
   const c128* fn_coef;
   int fn_root[kMaxTerms];
   int a_is_cplx[kMaxTerms];
+  int a_is_diag[kMaxTerms];        // diagonal A_i: residual applies d_r f_i y_r
+  const c128* Adiag[kMaxTerms];
   const c128* V;          // caller probes, column-major n x L
   c128* S;                // caller moments, column-major n x L x KK
 };
@@ -72,6 +74,7 @@ struct SolvePlan {
   int nmat = 0;     // matrices (sorted order)
   int lg = 4;       // right-hand columns per group
   int groups = 1;   // column groups per matrix
+  int rpt = 1;      // rows per thread of the solve kernel (n <= 512 * rpt)
   Table diag;       // diagonal-block inversions: 2 * nblk per matrix
 };
 

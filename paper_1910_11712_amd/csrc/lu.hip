@@ -59,8 +59,7 @@ template <typename P, int W, int RPT>
 __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __restrict__ md, int k0, int jbmax,
                                                            cx<P>* __restrict__ Tb, int* __restrict__ rowb,
                                                            int* __restrict__ info,
-                                                           const int* __restrict__ skip,
-                                                           cx<P>* __restrict__ Linv) {
+                                                           const int* __restrict__ skip) {
   const MatDesc d = md[blockIdx.x];
   const int n = d.n;
   if (k0 >= n) return;
@@ -74,6 +73,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
   __shared__ P redv[2][kPanelThreads / 64];
   __shared__ int redi[2][kPanelThreads / 64];
   __shared__ cx<P> xbuf[2][2][W];
+  __shared__ cx<P> wrow[2][kPanelThreads / 64][W];
   __shared__ cx<P> Ltop[W][W];
   __shared__ cx<P> Utop[W][kLuMaxJB];
   __shared__ cx<P> Lc[kPanelThreads][W];
@@ -113,40 +113,33 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
           const int r = c0 + tid + i * kPanelThreads;
-          if (r >= c && r < n) {
-            const P v = abs1(a[i][w]);
-            if (v > bv) { bv = v; bi = r; }
-          }
+          const P v = (r >= c && r < n) ? abs1(a[i][w]) : P(-1);
+          const bool take = v > bv;
+          bv = take ? v : bv;
+          bi = take ? r : bi;
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
           const P ov = shfl_xor_p(bv, off);
           const int oi = __shfl_xor(bi, off, 64);
-          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+          const bool take = ov > bv || (ov == bv && oi < bi);
+          bv = take ? ov : bv;
+          bi = take ? oi : bi;
         }
-        if (lane == 0) { redv[par][wave] = bv; redi[par][wave] = bi; }
-        __syncthreads();
-        bv = redv[par][0];
-        bi = redi[par][0];
-#pragma unroll
-        for (int q = 1; q < kPanelThreads / 64; ++q) {
-          const P ov = redv[par][q];
-          const int oi = redi[par][q];
-          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-        }
-        const int p = bi;
+        // one barrier per column: every wave publishes its candidate value,
+        // index and row; the owner of row c publishes row c
         const int oc = (c - c0) % kPanelThreads, ic = (c - c0) / kPanelThreads;
-        const int op = (p - c0) % kPanelThreads, ip = (p - c0) / kPanelThreads;
-        // ---- exchange logical rows c and p (registers only; row_at records it)
-        if (tid == op) {
+        if (lane == 0) { redv[par][wave] = bv; redi[par][wave] = bi; }
+        if (bi != INT_MAX && tid == (bi - c0) % kPanelThreads) {
+          const int ib = (bi - c0) / kPanelThreads;
 #pragma unroll
           for (int i = 0; i < RPT; ++i)
-            if (i == ip) {
+            if (i == ib) {
 #pragma unroll
-              for (int v = 0; v < W; ++v) xbuf[par][0][v] = a[i][v];
+              for (int v = 0; v < W; ++v) wrow[par][wave][v] = a[i][v];
             }
         }
-        if (tid == oc && p != c) {
+        if (tid == oc) {
 #pragma unroll
           for (int i = 0; i < RPT; ++i)
             if (i == ic) {
@@ -155,9 +148,24 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
             }
         }
         __syncthreads();
+        bv = redv[par][0];
+        bi = redi[par][0];
+        int wq = 0;
+#pragma unroll
+        for (int q = 1; q < kPanelThreads / 64; ++q) {
+          const P ov = redv[par][q];
+          const int oi = redi[par][q];
+          const bool take = ov > bv || (ov == bv && oi < bi);
+          bv = take ? ov : bv;
+          bi = take ? oi : bi;
+          wq = take ? q : wq;
+        }
+        const int p = bi;
+        const int op = (p - c0) % kPanelThreads, ip = (p - c0) / kPanelThreads;
         cx<P> prow[W];
 #pragma unroll
-        for (int v = 0; v < W; ++v) prow[v] = xbuf[par][0][v];
+        for (int v = 0; v < W; ++v) prow[v] = wrow[par][wq][v];
+        // ---- exchange logical rows c and p (registers only; row_at records it)
         if (p != c) {
           if (tid == oc) {
 #pragma unroll
@@ -182,17 +190,17 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
           rat[p - k0] = t;
           if (bv == P(0) && zero_pivot == n) zero_pivot = c;
         }
-        // ---- scale the column and update the rest of the leaf
+        // ---- scale the column and update the rest of the leaf (selects, no branches)
         const cx<P> inv = recip(prow[w]);
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
           const int r = c0 + tid + i * kPanelThreads;
-          if (r > c && r < n) {
-            const cx<P> l = a[i][w] * inv;
-            a[i][w] = l;
+          const bool below = r > c && r < n;
+          const cx<P> l = a[i][w] * inv;
+          const cx<P> lm = below ? l : cx<P>{P(0), P(0)};
+          a[i][w] = below ? l : a[i][w];
 #pragma unroll
-            for (int v = w + 1; v < W; ++v) a[i][v] = fms(a[i][v], l, prow[v]);
-          }
+          for (int v = w + 1; v < W; ++v) a[i][v] = fms(a[i][v], lm, prow[v]);
         }
         par ^= 1;
       }
@@ -247,58 +255,94 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
         for (int w = 0; w < W; ++w) Lc[tid][w] = a[i][w];
         __syncthreads();
         const int rlo = max(rbase, rc0), rhi = min(n, rbase + kPanelThreads);
-        for (int r = rlo + wave; r < rhi; r += kPanelThreads / 64) {
-          cx<P>* row = T + (long long)rat[r - k0] * ld + rc0;
-          const int lr = r - rbase;
+        // each wave takes kRows rows at a time so that their loads are in
+        // flight together; full leaves and full row batches run branch-free
+        constexpr int kRows = 8;
+        for (int r0 = rlo + wave * kRows; r0 < rhi; r0 += (kPanelThreads / 64) * kRows) {
+          const int nrow = min(kRows, rhi - r0);
           for (int j = lane; j < nr; j += 64) {
-            cx<P> acc = row[j];
+            long long off[kRows];
+            cx<P> acc[kRows];
 #pragma unroll
-            for (int w = 0; w < W; ++w)
-              if (w < wc) acc = fms(acc, Lc[lr][w], Utop[w][j]);
-            row[j] = acc;
+            for (int u = 0; u < kRows; ++u) {
+              const int r = r0 + min(u, nrow - 1);
+              off[u] = (long long)rat[r - k0] * ld + rc0 + j;
+            }
+#pragma unroll
+            for (int u = 0; u < kRows; ++u) acc[u] = T[off[u]];
+            if (wc == W) {
+#pragma unroll
+              for (int u = 0; u < kRows; ++u) {
+                const int lr = r0 + min(u, nrow - 1) - rbase;
+#pragma unroll
+                for (int w = 0; w < W; ++w) acc[u] = fms(acc[u], Lc[lr][w], Utop[w][j]);
+              }
+            } else {
+#pragma unroll
+              for (int u = 0; u < kRows; ++u) {
+                const int lr = r0 + min(u, nrow - 1) - rbase;
+                for (int w = 0; w < wc; ++w) acc[u] = fms(acc[u], Lc[lr][w], Utop[w][j]);
+              }
+            }
+            // duplicated tail rows compute identical values, so storing them
+            // twice is harmless
+#pragma unroll
+            for (int u = kRows - 1; u >= 0; --u) T[off[u]] = acc[u];
           }
         }
         __syncthreads();
       }
     }
   }
-  // ---- inverse of the unit lower diagonal block L11 (for the block-row
-  // update U12 = L11^{-1} A12 on the matrix cores); one wave per column,
-  // rows over lanes, computed in FP64.
-  __syncthreads();
-  if (Linv != nullptr) {
-    cx<P>* __restrict__ Li = Linv + (long long)blockIdx.x * kLuMaxJB * kLuMaxJB;
-    for (int c = wave; c < jb; c += kPanelThreads / 64) {
-      c128 x[kLuMaxJB / 64];
-#pragma unroll
-      for (int q = 0; q < kLuMaxJB / 64; ++q) x[q] = c128{(lane + 64 * q == c) ? 1.0 : 0.0, 0.0};
-      for (int s2 = c; s2 < jb; ++s2) {
-        const int qs = s2 >> 6, ls = s2 & 63;
-        c128 xs;
-#pragma unroll
-        for (int q = 0; q < kLuMaxJB / 64; ++q)
-          if (q == qs) {
-            xs.re = __shfl(x[q].re, ls, 64);
-            xs.im = __shfl(x[q].im, ls, 64);
-          }
-#pragma unroll
-        for (int q = 0; q < kLuMaxJB / 64; ++q) {
-          const int r = lane + 64 * q;
-          if (r > s2 && r < jb) {
-            const cx<P> l = T[(long long)rat[r] * ld + k0 + s2];
-            x[q] = fms(x[q], c128{double(l.re), double(l.im)}, xs);
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kLuMaxJB / 64; ++q) {
-        const int r = lane + 64 * q;
-        if (r < jb) Li[(long long)r * kLuMaxJB + c] = cx<P>{P(x[q].re), P(x[q].im)};
-      }
-    }
-  }
   for (int r = tid; r < m; r += kPanelThreads) rowg[k0 + r] = rat[r];
   if (tid == 0 && zero_pivot < n) atomicMin(&info[d.node], zero_pivot);
+}
+
+// ---------------------------------------------------------------------------
+// Inverse of the unit lower diagonal block L11 of the current panel, for the
+// block-row solve U12 = L11^{-1} A12 on the matrix cores.  L11 is held in
+// LDS and inverted in place row by row: for i > c,
+//   X[i][c] = -(L[i][c] + sum_{c<j<i} L[i][j] X[j][c]),
+// two lanes per column (alternate j), one barrier per row.
+// ---------------------------------------------------------------------------
+template <typename P>
+__global__ __launch_bounds__(256) void k_l11_inv(const MatDesc* __restrict__ md, int k0, int jbmax,
+                                                 const cx<P>* __restrict__ Tb, const int* __restrict__ rowb,
+                                                 cx<P>* __restrict__ Linv, const int* __restrict__ skip) {
+  const MatDesc d = md[blockIdx.x];
+  const int n = d.n;
+  if (k0 >= n) return;
+  if (skip != nullptr && skip[d.node]) return;
+  const int jb = min(jbmax, n - k0);
+  if (n - k0 - jb <= 0) return;  // no trailing columns: inverse not needed
+  const cx<P>* __restrict__ T = Tb + d.offT;
+  const int ld = d.ld;
+  const int* __restrict__ rat = rowb + d.offRow + k0;
+  extern __shared__ unsigned char smem_raw[];
+  cx<P>* X = reinterpret_cast<cx<P>*>(smem_raw);  // jb x (jb+1)
+  const int lx = jb + 1;
+  for (int e = threadIdx.x; e < jb * jb; e += 256) {
+    const int i = e / jb, k = e - i * jb;
+    X[i * lx + k] = k < i ? T[(long long)rat[i] * ld + k0 + k] : cx<P>{P(0), P(0)};
+  }
+  __syncthreads();
+  const int c = threadIdx.x >> 1, h = threadIdx.x & 1;
+  for (int i = 1; i < jb; ++i) {
+    cx<P> s = {P(0), P(0)};
+    if (c < i) {
+      for (int jj = c + 1 + h; jj < i; jj += 2) s = cmac(s, X[i * lx + jj], X[jj * lx + c]);
+    }
+    s.re += __shfl_xor(s.re, 1, 64);
+    s.im += __shfl_xor(s.im, 1, 64);
+    __syncthreads();  // every lane has read row i
+    if (c < i && h == 0) X[i * lx + c] = -(X[i * lx + c] + s);
+    __syncthreads();
+  }
+  cx<P>* __restrict__ Li = Linv + (long long)blockIdx.x * kLuMaxJB * kLuMaxJB;
+  for (int e = threadIdx.x; e < jb * jb; e += 256) {
+    const int i = e / jb, k = e - i * jb;
+    Li[(long long)i * kLuMaxJB + k] = k < i ? X[i * lx + k] : (k == i ? cx<P>{P(1), P(0)} : cx<P>{P(0), P(0)});
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -593,13 +637,13 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
 // ---------------------------------------------------------------------------
 template <typename P, int W>
 static hipError_t launch_panel(int rpt, int nact, const MatDesc* md, int k0, int jb, cx<P>* T, int* rows, int* info,
-                               const int* skip, cx<P>* Linv, hipStream_t st) {
+                               const int* skip, hipStream_t st) {
   dim3 g(nact), blk(kPanelThreads);
   switch (rpt) {
-    case 1: hipLaunchKernelGGL((k_lu_panel<P, W, 1>), g, blk, 0, st, md, k0, jb, T, rows, info, skip, Linv); break;
-    case 2: hipLaunchKernelGGL((k_lu_panel<P, W, 2>), g, blk, 0, st, md, k0, jb, T, rows, info, skip, Linv); break;
-    case 4: hipLaunchKernelGGL((k_lu_panel<P, W, 4>), g, blk, 0, st, md, k0, jb, T, rows, info, skip, Linv); break;
-    default: hipLaunchKernelGGL((k_lu_panel<P, W, 8>), g, blk, 0, st, md, k0, jb, T, rows, info, skip, Linv); break;
+    case 1: hipLaunchKernelGGL((k_lu_panel<P, W, 1>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    case 2: hipLaunchKernelGGL((k_lu_panel<P, W, 2>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    case 4: hipLaunchKernelGGL((k_lu_panel<P, W, 4>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    default: hipLaunchKernelGGL((k_lu_panel<P, W, 8>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
   }
   return hipGetLastError();
 }
@@ -663,10 +707,12 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
   constexpr int W = sizeof(P) == 4 ? 8 : 4;
   for (const auto& s : plan.steps) {
     const bool more = s.tot_trsm > 0;
-    if ((e = launch_panel<P, W>(s.rpt, s.nact, d_md, s.k0, plan.jb, T, rows, info, skip, more ? Linv : nullptr,
-                                st)) != hipSuccess)
+    if ((e = launch_panel<P, W>(s.rpt, s.nact, d_md, s.k0, plan.jb, T, rows, info, skip, st)) != hipSuccess)
       return e;
     if (!more) continue;
+    hipLaunchKernelGGL(k_l11_inv<P>, dim3(s.nact), dim3(256), (size_t)plan.jb * (plan.jb + 1) * sizeof(cx<P>), st,
+                       d_md, s.k0, plan.jb, T, rows, Linv, skip);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if constexpr (sizeof(P) == 4)
       hipLaunchKernelGGL(k_lu_gemm_c64<1>, dim3(xcd_grid(s.tot_trsm)), dim3(256), 0, st, d_md, d_prefix + s.off_trsm,
                          s.nact, s.tot_trsm, s.k0, plan.jb, T, rows, skip, Linv);
@@ -702,7 +748,13 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
   return hipSuccess;
 }
 
-hipError_t lu_configure() { return hipSuccess; }
+hipError_t lu_configure() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_l11_inv<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(kLuMaxJB * (kLuMaxJB + 1) * sizeof(c64)));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_l11_inv<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(64 * 65 * sizeof(c128)));
+}
 
 template hipError_t lu_run<float>(const LuPlan&, const MatDesc*, const int*, c64*, int*, int*, const int*, c64*,
                                   hipStream_t);

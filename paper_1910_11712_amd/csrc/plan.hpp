@@ -29,6 +29,8 @@ struct SplitOperator {
   int a_cplx = 0;
   int is_cplx[kMaxTerms] = {0};
   const void* dA[kMaxTerms] = {nullptr};  // device row-major copies
+  int is_diag[kMaxTerms] = {0};           // A_i diagonal (detected at creation)
+  const c128* dDiag[kMaxTerms] = {nullptr};  // its diagonal (n complex)
   const double* dnormA = nullptr;
   std::vector<double> normA;
   const FnNode* dfn_nodes = nullptr;

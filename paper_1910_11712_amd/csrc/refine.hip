@@ -60,6 +60,7 @@ __global__ __launch_bounds__(256) void k_resid(const ProbDesc* __restrict__ pd, 
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
 
   for (int term = 0; term < D.ell; ++term) {
+    if (D.a_is_diag[term]) continue;  // applied in the epilogue
     const double* __restrict__ A = reinterpret_cast<const double*>(D.A[term]);
     const int acplx = ACPLX ? D.a_is_cplx[term] : 0;
     const int Kd = acplx ? 2 * n : n;            // real k extent of this term
@@ -138,7 +139,15 @@ __global__ __launch_bounds__(256) void k_resid(const ProbDesc* __restrict__ pd, 
         double val = 0.0;
         if (gr < n && q < Q) {
           const c128 vv = D.V[(long long)c * n + gr];
-          val = (tcomp ? vv.im : vv.re) - acc[i][j][r];
+          double s = acc[i][j][r];
+          for (int term = 0; term < D.ell; ++term) {
+            if (!D.a_is_diag[term]) continue;
+            const c128 y = {Yd[2 * ((long long)gr * NL + cc)], Yd[2 * ((long long)gr * NL + cc) + 1]};
+            const c128 f = na.fz[(long long)(D.node0 + node) * kMaxTerms + term];
+            const c128 dy = (f * D.Adiag[term][gr]) * y;
+            s += tcomp ? dy.im : dy.re;
+          }
+          val = (tcomp ? vv.im : vv.re) - s;
           Rd[(long long)gr * Q + q] = val;
         }
         const double other = __shfl_xor(val, 1, 64);

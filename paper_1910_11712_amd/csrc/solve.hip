@@ -19,7 +19,7 @@
 
 namespace nep {
 
-constexpr int kTrsvThreads = 256;
+constexpr int kTrsvThreads = 512;
 constexpr int kInvBlk = kSolveBlk;  // 64
 
 // ---------------------------------------------------------------------------
@@ -85,17 +85,55 @@ __global__ __launch_bounds__(256) void k_diag_inv(const MatDesc* __restrict__ md
 
 // ---------------------------------------------------------------------------
 // Fused forward + backward substitution.
+// The finished part of each 64-row block is streamed through LDS in chunks
+// of SCH columns (coalesced loads, double-buffered so the next chunk is in
+// flight while the current one is multiplied); thread (row, quarter) keeps
+// LG/4 right-hand columns.
 // ---------------------------------------------------------------------------
-template <typename P, int LG>
+// Right-looking substitution with the accumulators in registers: thread t
+// owns the logical rows t, t+512, ...  For each 64-row block (in order for
+// L, reversed for U):
+//   1. the owners of the block's rows publish t = acc (their pending sums)
+//      and the group stages the stored inverse of the diagonal block;
+//   2. x_q = Dinv_q t (all threads, 64 rows x LG columns);
+//   3. every row not yet solved pulls its 64-wide segment of the factor and
+//      subtracts segment * x_q from its accumulators.
+// Step 3 issues many independent row loads, so the solve streams the factor
+// instead of waiting on one dependent chain.
+// 16 consecutive elements of a factor row; the segment starts at a multiple
+// of 64 elements of a row whose stride is a multiple of 16, so it is 16-byte
+// aligned.
+__device__ __forceinline__ void load_seg16(const c64* __restrict__ s, c64 (&v)[16]) {
+  const float4* q = reinterpret_cast<const float4*>(s);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const float4 t = q[u];
+    v[2 * u] = {t.x, t.y};
+    v[2 * u + 1] = {t.z, t.w};
+  }
+}
+__device__ __forceinline__ void load_seg16(const c128* __restrict__ s, c128 (&v)[16]) {
+  const double2* q = reinterpret_cast<const double2*>(s);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const double2 t = q[u];
+    v[u] = {t.x, t.y};
+  }
+}
+
+template <typename P, int LG, int RPT>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict__ md, int nmat, int groups,
                                                       const ProbDesc* __restrict__ pd, NodeArrays na,
                                                       const cx<P>* __restrict__ Tb, const int* __restrict__ rows,
                                                       const cx<P>* __restrict__ Dinv,
-                                                      const long long* __restrict__ dinv_off, cx<P>* __restrict__ Wk,
+                                                      const long long* __restrict__ dinv_off,
                                                       const c128* __restrict__ R, c128* __restrict__ Y, int refine,
                                                       const int* __restrict__ conv, IrState ir) {
-  const int b = blockIdx.x / groups, grp = blockIdx.x - b * groups;
-  if (b >= nmat) return;
+  constexpr int B = kSolveBlk;  // 64
+  // the column groups of one matrix run on one XCD and share its L2
+  const int v = xcd_remap(blockIdx.x, gridDim.x, nmat * groups);
+  if (v < 0) return;
+  const int b = v / groups, grp = v - b * groups;
   const MatDesc d = md[b];
   const int g = d.node;
   if (conv != nullptr && conv[g]) return;
@@ -108,13 +146,30 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
   const cx<P>* __restrict__ T = Tb + d.offT;
   const int* __restrict__ rat = rows + d.offRow;
   const cx<P>* __restrict__ Di = Dinv + dinv_off[b];
-  cx<P>* __restrict__ W = Wk + D.offW0 + (long long)j * n * L;  // n x L, row-major
-  const int nblk = (n + kSolveBlk - 1) / kSolveBlk;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nblk = (n + B - 1) / B;
+  const int tid = threadIdx.x;
 
-  __shared__ cx<P> red[3][kSolveBlk][LG];
-  __shared__ double cmax[4][LG];
+  __shared__ cx<P> Ds[B][B + 1];   // diagonal-block inverse
+  __shared__ cx<P> Ts[B][LG];      // block right-hand side
+  __shared__ cx<P> Xs[B][LG];      // block solution
+  __shared__ double cmax[kTrsvThreads / 64][LG];
 
+  // right-hand side P b gathered into the owners' accumulators
+  cx<P> acc[RPT][LG];
+  long long rowoff[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = tid + i * kTrsvThreads;
+    const int pr = r < n ? rat[r] : 0;
+    rowoff[i] = (long long)pr * ld;
+#pragma unroll
+    for (int c = 0; c < LG; ++c) {
+      c128 bv = {0.0, 0.0};
+      if (r < n && c < nc)
+        bv = refine ? R[D.offY + (long long)pr * D.N * L + (long long)j * L + c0 + c] : D.V[(long long)(c0 + c) * n + pr];
+      acc[i][c] = cvt<P>(bv);
+    }
+  }
   double ymax[LG];
 #pragma unroll
   for (int c = 0; c < LG; ++c) ymax[c] = 0.0;
@@ -122,71 +177,84 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
   for (int pass = 0; pass < 2; ++pass) {  // 0: L y = P b, 1: U x = y
     for (int qq = 0; qq < nblk; ++qq) {
       const int q = pass == 0 ? qq : nblk - 1 - qq;
-      const int R0 = q * kSolveBlk, nr = min(kSolveBlk, n - R0);
-      const int row = R0 + lane;
-      // inner dimension of the finished part, split over the four waves
-      const int s_lo = pass == 0 ? 0 : R0 + nr;
-      const int s_hi = pass == 0 ? R0 : n;
-      cx<P> acc[LG];
+      const int R0 = q * B, nr = min(B, n - R0);
+      // 1. publish the block's pending sums; stage the inverse
 #pragma unroll
-      for (int c = 0; c < LG; ++c) acc[c] = cx<P>{P(0), P(0)};
-      if (lane < nr && s_hi > s_lo) {
-        const cx<P>* __restrict__ trow = T + (long long)rat[row] * ld;
-        for (int s = s_lo + wave; s < s_hi; s += 4) {
-          const cx<P> a = trow[s];
-          const cx<P>* __restrict__ ys = W + (long long)s * L + c0;
+      for (int i = 0; i < RPT; ++i) {
+        const int r = tid + i * kTrsvThreads;
+        if (r >= R0 && r < R0 + B) {
 #pragma unroll
-          for (int c = 0; c < LG; ++c)
-            if (c < nc) acc[c] = acc[c] + a * ys[c];
+          for (int c = 0; c < LG; ++c) Ts[r - R0][c] = r < n ? acc[i][c] : cx<P>{P(0), P(0)};
         }
       }
-      if (wave > 0) {
-#pragma unroll
-        for (int c = 0; c < LG; ++c) red[wave - 1][lane][c] = acc[c];
+      const cx<P>* __restrict__ inv = Di + ((long long)q * 2 + pass) * B * B;
+      for (int e = tid; e < B * B; e += kTrsvThreads) {
+        const int i = e / B, k = e - i * B;
+        Ds[i][k] = k < nr ? inv[e] : cx<P>{P(0), P(0)};
       }
       __syncthreads();
-      // right-hand side of the block: t = rhs - sum
-      if (wave == 0) {
+      // 2. x_q = Dinv_q t
+      for (int e = tid; e < B * LG; e += kTrsvThreads) {
+        const int i = e / LG, c = e - i * LG;
+        cx<P> x = {P(0), P(0)};
+#pragma unroll 16
+        for (int k = 0; k < B; ++k) x = cmac(x, Ds[i][k], Ts[k][c]);
+        Xs[i][c] = x;
+      }
+      __syncthreads();
+      // 3. rows still pending subtract (factor segment) * x_q; the block's own
+      // rows take their solution
 #pragma unroll
-        for (int c = 0; c < LG; ++c) {
-          cx<P> tv = {P(0), P(0)};
-          if (lane < nr && c < nc) {
-            cx<P> rhs;
-            if (pass == 0) {
-              const int pr = rat[row];
-              const c128 bv = refine ? R[D.offY + (long long)pr * D.N * L + (long long)j * L + c0 + c]
-                                     : D.V[(long long)(c0 + c) * n + pr];
-              rhs = cvt<P>(bv);
-            } else {
-              rhs = W[(long long)row * L + c0 + c];
-            }
-            tv = rhs - (acc[c] + red[0][lane][c] + red[1][lane][c] + red[2][lane][c]);
+      for (int i = 0; i < RPT; ++i) {
+        const int r = tid + i * kTrsvThreads;
+        if (r >= n) continue;
+        if (r >= R0 && r < R0 + nr) {
+#pragma unroll
+          for (int c = 0; c < LG; ++c) acc[i][c] = Xs[r - R0][c];
+          continue;
+        }
+        const bool pending = pass == 0 ? r >= R0 + nr : r < R0;
+        if (!pending) continue;
+        const cx<P>* __restrict__ seg = T + rowoff[i] + R0;
+        if (nr == B) {  // full block: whole 64-wide segment, vector loads
+          for (int k0 = 0; k0 < B; k0 += 16) {
+            cx<P> lv[16];
+            load_seg16(seg + k0, lv);
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+#pragma unroll
+              for (int c = 0; c < LG; ++c) acc[i][c] = fms(acc[i][c], lv[u], Xs[k0 + u][c]);
           }
-          red[0][lane][c] = tv;
+        } else {  // ragged last block
+          for (int k = 0; k < nr; ++k) {
+            const cx<P> lv = seg[k];
+#pragma unroll
+            for (int c = 0; c < LG; ++c) acc[i][c] = fms(acc[i][c], lv, Xs[k][c]);
+          }
         }
       }
-      __syncthreads();
-      // x_q = Dinv_q t, rows over lanes, columns over waves
-      const cx<P>* __restrict__ inv = Di + ((long long)q * 2 + pass) * kSolveBlk * kSolveBlk + lane * kSolveBlk;
+      // (the next block's barrier after step 1 orders Xs reuse)
+    }
+    __syncthreads();
+  }
+  // acc now holds x for the owned rows: store to Y (FP64) and take maxima
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = tid + i * kTrsvThreads;
+    if (r < n) {
+      c128* y = Y + D.offY + (long long)r * D.N * L + (long long)j * L + c0;
 #pragma unroll
       for (int c = 0; c < LG; ++c) {
-        if ((c & 3) == wave && c < nc && lane < nr) {
-          cx<P> x = {P(0), P(0)};
-          for (int k = 0; k < nr; ++k) x = x + inv[k] * red[0][k][c];
-          W[(long long)row * L + c0 + c] = x;
-          if (pass == 1) {
-            c128* y = Y + D.offY + (long long)row * D.N * L + (long long)j * L + c0 + c;
-            c128 nv = {double(x.re), double(x.im)};
-            if (refine) nv = *y + nv;
-            *y = nv;
-            ymax[c] = fmax(ymax[c], sqrt(norm2(nv)));
-          }
+        if (c < nc) {
+          c128 nv = {double(acc[i][c].re), double(acc[i][c].im)};
+          if (refine) nv = y[c] + nv;
+          y[c] = nv;
+          ymax[c] = fmax(ymax[c], sqrt(norm2(nv)));
         }
       }
-      __syncthreads();
     }
   }
-  // column maxima of the new Y
+  const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
   for (int c = 0; c < LG; ++c) {
     double m = ymax[c];
@@ -194,10 +262,10 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
     if (lane == 0) cmax[wave][c] = m;
   }
   __syncthreads();
-  if (threadIdx.x < nc) {
-    const int c = threadIdx.x;
-    const double m = fmax(fmax(cmax[0][c], cmax[1][c]), fmax(cmax[2][c], cmax[3][c]));
-    atomicMax(&ir.ynorm[(long long)g * kNormStride + c0 + c], (unsigned long long)__double_as_longlong(m));
+  if (tid < nc) {
+    double m = 0.0;
+    for (int w = 0; w < kTrsvThreads / 64; ++w) m = fmax(m, cmax[w][tid]);
+    atomicMax(&ir.ynorm[(long long)g * kNormStride + c0 + tid], (unsigned long long)__double_as_longlong(m));
   }
 }
 
@@ -212,22 +280,33 @@ hipError_t diag_inv_run(const SolvePlan& sp, const int* d_prefix, const MatDesc*
   return hipGetLastError();
 }
 
+template <typename P, int LG>
+static void launch_trsv(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md, const NodeArrays& na,
+                        const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off, const c128* R,
+                        c128* Y, int rf, const int* conv, IrState ir, hipStream_t st) {
+  const dim3 grid(xcd_grid(sp.nmat * sp.groups)), blk(kTrsvThreads);
+  switch (sp.rpt) {
+    case 1: hipLaunchKernelGGL((k_trsv<P, LG, 1>), grid, blk, 0, st, md, sp.nmat, sp.groups, pd, na, T, rows, Dinv,
+                               dinv_off, R, Y, rf, conv, ir); break;
+    case 2: hipLaunchKernelGGL((k_trsv<P, LG, 2>), grid, blk, 0, st, md, sp.nmat, sp.groups, pd, na, T, rows, Dinv,
+                               dinv_off, R, Y, rf, conv, ir); break;
+    case 4: hipLaunchKernelGGL((k_trsv<P, LG, 4>), grid, blk, 0, st, md, sp.nmat, sp.groups, pd, na, T, rows, Dinv,
+                               dinv_off, R, Y, rf, conv, ir); break;
+    default: hipLaunchKernelGGL((k_trsv<P, LG, 8>), grid, blk, 0, st, md, sp.nmat, sp.groups, pd, na, T, rows, Dinv,
+                                dinv_off, R, Y, rf, conv, ir); break;
+  }
+}
+
 template <typename P>
 hipError_t solve_run(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md, const NodeArrays& na,
-                     const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off, cx<P>* Wk,
+                     const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off, cx<P>* /*Wk*/,
                      const c128* R, c128* Y, bool refine, const int* conv, IrState ir, hipStream_t st) {
   if (sp.nmat == 0) return hipSuccess;
-  const dim3 grid(sp.nmat * sp.groups), blk(kTrsvThreads);
   const int rf = refine ? 1 : 0;
   switch (sp.lg) {
-    case 2: hipLaunchKernelGGL((k_trsv<P, 2>), grid, blk, 0, st, md, sp.nmat, sp.groups, pd, na, T, rows, Dinv,
-                               dinv_off, Wk, R, Y, rf, conv, ir); break;
-    case 4: hipLaunchKernelGGL((k_trsv<P, 4>), grid, blk, 0, st, md, sp.nmat, sp.groups, pd, na, T, rows, Dinv,
-                               dinv_off, Wk, R, Y, rf, conv, ir); break;
-    case 8: hipLaunchKernelGGL((k_trsv<P, 8>), grid, blk, 0, st, md, sp.nmat, sp.groups, pd, na, T, rows, Dinv,
-                               dinv_off, Wk, R, Y, rf, conv, ir); break;
-    default: hipLaunchKernelGGL((k_trsv<P, 16>), grid, blk, 0, st, md, sp.nmat, sp.groups, pd, na, T, rows, Dinv,
-                                dinv_off, Wk, R, Y, rf, conv, ir); break;
+    case 4: launch_trsv<P, 4>(sp, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
+    case 8: launch_trsv<P, 8>(sp, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
+    default: launch_trsv<P, 16>(sp, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
   }
   return hipGetLastError();
 }
@@ -246,15 +325,22 @@ template hipError_t solve_run<double>(const SolvePlan&, const ProbDesc*, const M
 // Column-group size: enough groups to occupy the device when there are few
 // matrices, bounded by L (the group is an unrolled register tile).
 static int pick_lg(int nmat, int L) {
+  // Each column group re-reads the node's factor, so prefer one group per
+  // node; split only when there are too few nodes to occupy the device.
   int lg = 16;
-  while (lg > 2 && (lg >= 2 * L || (long long)nmat * ceil_div(L, lg) < 512)) lg >>= 1;
+  while (lg > 4 && lg >= 2 * L) lg >>= 1;
+  while (lg > 4 && (long long)nmat * ceil_div(L, lg) < 256) lg >>= 1;
   return lg;
 }
 
 void SolvePlan_build(SolvePlan& sp, std::vector<int>& buf, const std::vector<MatDesc>& sorted, int L,
                      std::vector<long long>& dinv_off, long long& dinv_elems) {
   sp.nmat = (int)sorted.size();
+  const int nmax = sorted.empty() ? 0 : sorted[0].n;
+  sp.rpt = nmax <= 512 ? 1 : nmax <= 1024 ? 2 : nmax <= 2048 ? 4 : 8;
   sp.lg = pick_lg(sp.nmat, L);
+  // accumulators live in registers: at most 32 complex values per thread
+  while (sp.lg > 4 && sp.rpt * sp.lg > 32) sp.lg >>= 1;
   sp.groups = ceil_div(L, sp.lg);
   std::vector<int> cnt;
   dinv_off.clear();
