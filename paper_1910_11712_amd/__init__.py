@@ -13,7 +13,7 @@ from .binding import (NepError, nep_split_create, nep_split_destroy, nep_ciss_mo
 
 __all__ = ["NepError", "SplitOperator", "binding", "nep_split_create", "nep_split_destroy",
            "nep_ciss_moments", "nep_ciss_wait", "nep_extract", "nep_backward_error", "nep_fn_eval",
-           "device_probes", "moments_to_numpy"]
+           "device_probes", "moments_to_numpy", "Server"]
 
 
 def device_probes(V, device="cuda"):
@@ -79,3 +79,44 @@ class SplitOperator:
 
     def fn_eval(self, z):
         return nep_fn_eval(self.h, self.ell, z)
+
+
+class Server:
+    """Query server over the C ABI: submit (operator, contour, probes) and
+    collect eigenvalues inside the contour; queries sharing (N, L, K,
+    precision) are batched and run on several streams at once."""
+
+    def __init__(self, hbm_budget, max_inflight=64, nstreams=4):
+        self.s = binding.nep_server_create(hbm_budget, max_inflight, nstreams)
+        self._out = {}
+
+    def submit(self, op, contour, V, N, L, K, prec="mixed", max_eigs=64, want_X=False, rank_tol=0.0):
+        o = binding.opts_struct(N, L, K, prec)
+        t, out = binding.nep_server_submit(self.s, op.h, contour, o, V, max_eigs, rank_tol, want_X)
+        self._out[t] = out
+        return t
+
+    def poll(self, ticket):
+        r = binding.nep_server_poll(self.s, ticket, self._out[ticket])
+        if r is not None:
+            del self._out[ticket]
+        return r
+
+    def wait(self, ticket):
+        r = binding.nep_server_wait(self.s, ticket, self._out[ticket])
+        del self._out[ticket]
+        return r
+
+    def clock(self):
+        return binding.nep_server_clock(self.s)
+
+    def close(self):
+        if self.s is not None and self.s.value:
+            binding.nep_server_destroy(self.s)
+        self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

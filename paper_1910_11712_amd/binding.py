@@ -19,6 +19,7 @@ NEP_OK = 0
 ERRORS = {-1: "NEP_ERR_ARG", -2: "NEP_ERR_OOM", -3: "NEP_ERR_SINGULAR",
           -4: "NEP_ERR_NOT_HOLOMORPHIC", -5: "NEP_ERR_REFINE", -6: "NEP_ERR_RANK",
           -7: "NEP_ERR_DEVICE", -8: "NEP_ERR_BUSY"}
+globals().update({v: k for k, v in ERRORS.items()})  # NEP_ERR_ARG = -1, ...
 FN_TYPES = {"rational": 0, "exp": 1, "log": 2, "sqrt": 3, "invsqrt": 4, "phi": 5, "combine": 6}
 PREC = {"fp64": 0, "mixed": 1}
 
@@ -115,9 +116,6 @@ def lib():
                                              C.POINTER(vp), C.POINTER(vp), C.POINTER(nep_ciss_stats)]
         L.nep_prof_enable.argtypes = [ip]
         L.nep_prof_read.argtypes = [ip, C.POINTER(ip), C.POINTER(C.c_double), C.POINTER(C.c_double)]
-        if not hasattr(L, "nep_server_create"):
-            _lib = L
-            return _lib
         L.nep_server_create.argtypes = [C.POINTER(nep_server_opts), C.POINTER(vp)]
         L.nep_server_submit.argtypes = [vp, vp, C.POINTER(nep_contour), C.POINTER(nep_ciss_opts),
                                         C.POINTER(nep_extract_opts), vp, C.POINTER(C.c_double),
@@ -304,3 +302,68 @@ def nep_prof_read(kind):
     n, ms, fl = C.c_int(0), C.c_double(0), C.c_double(0)
     check(lib().nep_prof_read(int(kind), C.byref(n), C.byref(ms), C.byref(fl)))
     return n.value, ms.value, fl.value
+
+
+# --------------------------------------------------------------------------
+# Serving
+
+def nep_server_create(hbm_budget, max_inflight=64, nstreams=4):
+    o = nep_server_opts()
+    o.hbm_budget, o.max_inflight, o.nstreams = int(hbm_budget), int(max_inflight), int(nstreams)
+    s = C.c_void_p()
+    check(lib().nep_server_create(C.byref(o), C.byref(s)))
+    return s
+
+
+def nep_server_submit(s, h, contour, opts, V, max_eigs=64, rank_tol=0.0, want_X=False):
+    """Queues a query.  V: host complex (n, L).  Returns (ticket, out) where
+    out holds the host result arrays the server fills; keep it until the
+    query is collected."""
+    e = nep_extract_opts()
+    e.rank_tol, e.max_eigs = float(rank_tol), int(max_eigs)
+    Vf = np.asfortranarray(np.asarray(V, dtype=np.complex128))
+    n = Vf.shape[0]
+    out = {"V": Vf, "lam": np.zeros(2 * max_eigs), "eta": np.zeros(max_eigs),
+           "inside": np.zeros(max_eigs, dtype=np.int32),
+           "X": np.zeros((n, max_eigs), dtype=np.complex128, order="F") if want_X else None,
+           "opts": opts, "eopts": e, "contour": contour_struct(contour)}
+    t = C.c_longlong(0)
+    xp = C.c_void_p(out["X"].ctypes.data) if want_X else None
+    check(lib().nep_server_submit(s, h, C.byref(out["contour"]), C.byref(opts), C.byref(e),
+                                  C.c_void_p(Vf.ctypes.data), out["lam"].ctypes.data_as(C.POINTER(C.c_double)),
+                                  out["eta"].ctypes.data_as(C.POINTER(C.c_double)),
+                                  out["inside"].ctypes.data_as(C.POINTER(C.c_int)), xp, C.byref(t)))
+    return t.value, out
+
+
+def _query_result(info, out):
+    k = info.m
+    lam = out["lam"]
+    r = {"status": info.status, "m": k, "n_inside": info.n_inside,
+         "t_submit": info.t_submit, "t_start": info.t_start, "t_done": info.t_done,
+         "lam": lam[0:2 * k:2] + 1j * lam[1:2 * k:2], "eta": out["eta"][:k].copy(),
+         "inside": out["inside"][:k].astype(bool)}
+    if out["X"] is not None:
+        r["X"] = out["X"][:, :k].copy()
+    return r
+
+
+def nep_server_poll(s, ticket, out):
+    done = C.c_int(0)
+    info = nep_query_info()
+    check(lib().nep_server_poll(s, int(ticket), C.byref(done), C.byref(info)))
+    return _query_result(info, out) if done.value else None
+
+
+def nep_server_wait(s, ticket, out):
+    info = nep_query_info()
+    check(lib().nep_server_wait(s, int(ticket), C.byref(info)))
+    return _query_result(info, out)
+
+
+def nep_server_clock(s):
+    return lib().nep_server_clock(s)
+
+
+def nep_server_destroy(s):
+    check(lib().nep_server_destroy(C.byref(s)))

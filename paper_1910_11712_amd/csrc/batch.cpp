@@ -79,7 +79,7 @@ nep_status nep_batch_run(nep_batch b, nep_ciss_stats* st) {
   }
   if (!st) return NEP_OK;
   RunResult rr;
-  nep_status s = B.plan->finish(B.stream, rr, false);
+  nep_status s = B.plan->finish(B.stream, rr, true);
   for (int p = 0; p < B.plan->nprob && p < (int)rr.stats.size(); ++p) st[p] = rr.stats[p];
   return s;
 }

@@ -51,6 +51,7 @@ struct NodeArrays {
   c128* mcoef;    // w_g zeta_g^p at [g*kMaxMoments + p]
   int* prob;      // problem of node g
   int* jnode;     // node index within the problem
+  int* bad;       // 1 if some f_i is not holomorphic at z_g
 };
 
 // Per-node refinement state.
@@ -100,7 +101,7 @@ hipError_t diag_inv_run(const SolvePlan& sp, const int* d_prefix, const MatDesc*
                         const int* rows, cx<P>* Dinv, const long long* dinv_off, const int* skip, hipStream_t st);
 template <typename P>
 hipError_t solve_run(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md, const NodeArrays& na,
-                     const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off, cx<P>* Wk,
+                     const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off,
                      const c128* R, c128* Y, bool refine, const int* conv, IrState ir, hipStream_t st);
 void SolvePlan_build(SolvePlan& sp, std::vector<int>& buf, const std::vector<MatDesc>& sorted, int L,
                      std::vector<long long>& dinv_off, long long& dinv_elems);

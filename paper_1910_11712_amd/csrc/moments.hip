@@ -43,6 +43,7 @@ __global__ void k_coef(const ProbDesc* __restrict__ pd, NodeArrays na, int nnode
     na.mcoef[g * kMaxMoments + q] = w * zp;
     zp = zp * zeta;
   }
+  na.bad[g] = bad ? 1 : 0;
   if (bad) {
     atomicAdd(&ir.counters[1], 1);
     atomicMin(&ir.counters[3], g);

@@ -9,9 +9,128 @@
 
 namespace nep {
 
+// --------------------------------------------------------------------------
+static thread_local Arena* tls_arena = nullptr;
+
+ArenaScope::ArenaScope(Arena* a) : prev_(tls_arena) { tls_arena = a; }
+ArenaScope::~ArenaScope() { tls_arena = prev_; }
+
+Arena::~Arena() {
+  if (base_) (void)hipFree(base_);
+}
+
+nep_status Arena::init(size_t bytes) {
+  bytes = (bytes + 255) / 256 * 256;
+  hipError_t e = hipMalloc((void**)&base_, bytes);
+  if (e != hipSuccess) {
+    base_ = nullptr;
+    (void)hipGetLastError();
+    set_error("arena allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    return NEP_ERR_OOM;
+  }
+  size_ = bytes;
+  free_.clear();
+  used_.clear();
+  free_[0] = bytes;
+  return NEP_OK;
+}
+
+void* Arena::take(size_t bytes) {
+  bytes = (bytes + 255) / 256 * 256;
+  std::lock_guard<std::mutex> lk(mu_);
+  for (auto it = free_.begin(); it != free_.end(); ++it) {  // first fit
+    if (it->second < bytes) continue;
+    const size_t off = it->first, len = it->second;
+    free_.erase(it);
+    if (len > bytes) free_[off + bytes] = len - bytes;
+    used_[off] = bytes;
+    return base_ + off;
+  }
+  return nullptr;
+}
+
+void Arena::give(void* q) {
+  std::lock_guard<std::mutex> lk(mu_);
+  const size_t off = (size_t)((char*)q - base_);
+  auto u = used_.find(off);
+  if (u == used_.end()) return;
+  size_t start = off, len = u->second;
+  used_.erase(u);
+  auto nx = free_.lower_bound(start);
+  if (nx != free_.end() && nx->first == start + len) {  // merge with the next block
+    len += nx->second;
+    nx = free_.erase(nx);
+  }
+  if (nx != free_.begin()) {  // merge with the previous block
+    auto pv = std::prev(nx);
+    if (pv->first + pv->second == start) {
+      start = pv->first;
+      len += pv->second;
+      free_.erase(pv);
+    }
+  }
+  free_[start] = len;
+}
+
+size_t Arena::in_use() const {
+  std::lock_guard<std::mutex> lk(mu_);
+  size_t t = 0;
+  for (const auto& kv : used_) t += kv.second;
+  return t;
+}
+
+namespace {
+struct PinnedSlab {
+  std::mutex mu;
+  char* base = nullptr;
+  std::vector<int> free_slots;
+  static constexpr int kSlots = 1024, kSlot = 64;
+};
+PinnedSlab& slab() {
+  static PinnedSlab s;
+  return s;
+}
+}  // namespace
+
+void* pinned_take() {
+  PinnedSlab& s = slab();
+  std::lock_guard<std::mutex> lk(s.mu);
+  if (!s.base) {
+    if (hipHostMalloc((void**)&s.base, (size_t)PinnedSlab::kSlots * PinnedSlab::kSlot, hipHostMallocDefault) !=
+        hipSuccess) {
+      s.base = nullptr;
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    for (int i = PinnedSlab::kSlots - 1; i >= 0; --i) s.free_slots.push_back(i);
+  }
+  if (s.free_slots.empty()) return nullptr;
+  const int i = s.free_slots.back();
+  s.free_slots.pop_back();
+  return s.base + (size_t)i * PinnedSlab::kSlot;
+}
+
+void pinned_give(void* p) {
+  PinnedSlab& s = slab();
+  std::lock_guard<std::mutex> lk(s.mu);
+  if (!s.base || p == nullptr) return;
+  s.free_slots.push_back((int)(((char*)p - s.base) / PinnedSlab::kSlot));
+}
+
+// --------------------------------------------------------------------------
 nep_status DevMem::alloc(size_t b) {
   release();
   if (b == 0) return NEP_OK;
+  if (tls_arena) {
+    p = tls_arena->take(b);
+    if (!p) {
+      set_error("arena has no free block of %zu bytes", b);
+      return NEP_ERR_OOM;
+    }
+    arena = tls_arena;
+    bytes = b;
+    return NEP_OK;
+  }
   hipError_t e = hipMalloc(&p, b);
   if (e != hipSuccess) {
     p = nullptr;
@@ -24,9 +143,13 @@ nep_status DevMem::alloc(size_t b) {
 }
 
 void DevMem::release() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (arena) arena->give(p);
+    else (void)hipFree(p);
+  }
   p = nullptr;
   bytes = 0;
+  arena = nullptr;
 }
 
 static int pad_ld(int n) {
@@ -41,7 +164,6 @@ size_t MomentsPlan::estimate_bytes(int n, int N, int L, int prec) {
   const size_t ld = pad_ld(n);
   size_t b = (size_t)N * ld * n * elem_size(prec);        // factors
   b += (size_t)N * n * sizeof(int);                        // row maps
-  b += (size_t)N * n * L * elem_size(prec);                // solve work
   b += (size_t)N * ((n + 63) / 64) * 2 * 64 * 64 * elem_size(prec);  // diagonal-block inverses
   b += (size_t)N * kLuMaxJB * kLuMaxJB * elem_size(prec);            // panel inverses
   b += 2 * (size_t)n * N * L * sizeof(c128);               // Y, R
@@ -170,14 +292,13 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   NEP_TRY(A(dT_, es * (size_t)t_elems_));
   NEP_TRY(A(drows_, sizeof(int) * (size_t)rows_total_));
   NEP_TRY(A(dinfo_, sizeof(int) * (size_t)nnodes));
-  NEP_TRY(A(dWk_, es * (size_t)w_elems_));
   NEP_TRY(A(ddinv_, es * (size_t)dinv_elems_));
   NEP_TRY(A(dlinv_, es * (size_t)sorted_.size() * kLuMaxJB * kLuMaxJB));
   NEP_TRY(A(ddinv_off_, sizeof(long long) * dinv_off_.size()));
   NEP_TRY(A(dY_, sizeof(c128) * (size_t)y_elems_));
   NEP_TRY(A(dR_, sizeof(c128) * (size_t)y_elems_));
   const size_t G = nnodes;
-  const size_t node_bytes = G * (3 + kMaxTerms + kMaxMoments) * sizeof(c128) + G * sizeof(double) + 2 * G * sizeof(int);
+  const size_t node_bytes = G * (3 + kMaxTerms + kMaxMoments) * sizeof(c128) + G * sizeof(double) + 3 * G * sizeof(int);
   NEP_TRY(A(dnode_, node_bytes));
   const size_t ir_bytes = 2 * G * kNormStride * 8 + (size_t)nprob * 64 * 8 + G * 8 + 3 * G * 4 + 8 * 4;
   NEP_TRY(A(dir_, ir_bytes));
@@ -191,7 +312,8 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
     na_.mcoef = reinterpret_cast<c128*>(q); q += G * kMaxMoments * sizeof(c128);
     na_.fnorm = reinterpret_cast<double*>(q); q += G * sizeof(double);
     na_.prob = reinterpret_cast<int*>(q); q += G * sizeof(int);
-    na_.jnode = reinterpret_cast<int*>(q);
+    na_.jnode = reinterpret_cast<int*>(q); q += G * sizeof(int);
+    na_.bad = reinterpret_cast<int*>(q);
     char* r = dir_.as<char>();
     ir_.rnorm = reinterpret_cast<unsigned long long*>(r); r += G * kNormStride * 8;
     ir_.ynorm = reinterpret_cast<unsigned long long*>(r); r += G * kNormStride * 8;
@@ -202,7 +324,10 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
     ir_.sweeps = reinterpret_cast<int*>(r); r += G * 4;
     ir_.counters = reinterpret_cast<int*>(r);
   }
-  if (!hcounter_) NEP_HIP(hipHostMalloc((void**)&hcounter_, 64, hipHostMallocDefault));
+  if (!hcounter_) {
+    hcounter_ = static_cast<int*>(pinned_take());
+    NEP_CHECK(hcounter_ != nullptr, NEP_ERR_OOM, "no pinned read-back slot left");
+  }
 
   NEP_HIP(hipMemcpy(dmd_.p, sorted_.data(), sizeof(MatDesc) * sorted_.size(), hipMemcpyHostToDevice));
   NEP_HIP(hipMemcpy(dprefix_.p, hprefix_.data(), sizeof(int) * hprefix_.size(), hipMemcpyHostToDevice));
@@ -213,9 +338,9 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
                       hipMemcpyHostToDevice));
   NEP_HIP(hipMemcpy(ddinv_off_.p, dinv_off_.data(), sizeof(long long) * dinv_off_.size(), hipMemcpyHostToDevice));
   NEP_HIP(hipMemcpy(na_.prob, hprob.data(), sizeof(int) * G, hipMemcpyHostToDevice));
+  na_prob_host_ = hprob;
   NEP_HIP(hipMemcpy(na_.jnode, hj.data(), sizeof(int) * G, hipMemcpyHostToDevice));
   dT64_.release();
-  dWk64_.release();
   ddinv64_.release();
   dlinv64_.release();
   return upload_problems(probs);
@@ -227,7 +352,6 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
   const MatDesc* md = dmd_.as<MatDesc>();
   const int* pre = dprefix_.as<int>();
   cx<P>* T = dT_.as<cx<P>>();
-  cx<P>* Wk = dWk_.as<cx<P>>();
   c128* Y = dY_.as<c128>();
   c128* R = dR_.as<c128>();
   int* rows = drows_.as<int>();
@@ -240,7 +364,7 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
   cx<P>* Dinv = ddinv_.as<cx<P>>();
   const long long* doff = ddinv_off_.as<long long>();
   NEP_HIP(diag_inv_run<P>(sp_, pre, md, T, rows, Dinv, doff, nullptr, st));
-  NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, Wk, nullptr, Y, false, nullptr, ir_, st));
+  NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, nullptr, Y, false, nullptr, ir_, st));
   sweeps_run_ = 0;
   if (opt.max_refine > 0) {
     for (int s = 0; s <= opt.max_refine; ++s) {
@@ -253,7 +377,7 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
         if (hcounter_[0] == 0) break;
       }
       if (s == opt.max_refine) break;
-      NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, Wk, R, Y, true, ir_.conv, ir_, st));
+      NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, R, Y, true, ir_.conv, ir_, st));
     }
     if (eager && hcounter_[0] > 0 && opt.fallback && sizeof(P) == 4) NEP_TRY(run_fallback<double>(st));
   }
@@ -268,7 +392,6 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
   static_assert(sizeof(P) == 8, "fallback runs in FP64");
   if (!dT64_.p) {
     NEP_TRY(dT64_.alloc(sizeof(c128) * (size_t)t_elems_));
-    NEP_TRY(dWk64_.alloc(sizeof(c128) * (size_t)w_elems_));
     NEP_TRY(ddinv64_.alloc(sizeof(c128) * (size_t)dinv_elems_));
     NEP_TRY(dlinv64_.alloc(sizeof(c128) * (size_t)sorted_.size() * kLuMaxJB * kLuMaxJB));
   }
@@ -276,7 +399,6 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
   const MatDesc* md = dmd_.as<MatDesc>();
   const int* pre = dprefix_.as<int>();
   c128* T = dT64_.as<c128>();
-  c128* Wk = dWk64_.as<c128>();
   const int* skip = ir_.conv;
   {
     std::vector<int> conv(nnodes);
@@ -291,7 +413,7 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
   c128* Dinv = ddinv64_.as<c128>();
   const long long* doff = ddinv_off_.as<long long>();
   NEP_HIP(diag_inv_run<double>(sp_, pre, md, T, drows_.as<int>(), Dinv, doff, skip, st));
-  NEP_HIP(solve_run<double>(sp_, pd, md, na_, T, drows_.as<int>(), Dinv, doff, Wk, nullptr, dY_.as<c128>(), false,
+  NEP_HIP(solve_run<double>(sp_, pd, md, na_, T, drows_.as<int>(), Dinv, doff, nullptr, dY_.as<c128>(), false,
                             skip, ir_, st));
   // check the residual of the re-solved nodes once
   NEP_HIP(resid_run(pd, pre, pt_.resid, na_, dY_.as<c128>(), dR_.as<c128>(), ir_, nnodes, st));
@@ -306,36 +428,51 @@ nep_status MomentsPlan::enqueue(hipStream_t st, bool eager) {
   return enqueue_t<float>(st, eager);
 }
 
-nep_status MomentsPlan::finish(hipStream_t st, RunResult& out, bool /*allow_fallback*/) {
-  NEP_HIP(hipStreamSynchronize(st));
+nep_status MomentsPlan::finish(hipStream_t st, RunResult& out, bool allow_fallback) {
   const int G = nnodes;
-  std::vector<int> info(G), conv(G), stalled(G), sweeps(G), counters(4);
+  std::vector<int> info(G), conv(G), sweeps(G), bad(G), counters(4);
   std::vector<double> rho(G);
-  NEP_HIP(hipMemcpy(info.data(), dinfo_.p, sizeof(int) * G, hipMemcpyDeviceToHost));
-  NEP_HIP(hipMemcpy(conv.data(), ir_.conv, sizeof(int) * G, hipMemcpyDeviceToHost));
-  NEP_HIP(hipMemcpy(stalled.data(), ir_.stalled, sizeof(int) * G, hipMemcpyDeviceToHost));
-  NEP_HIP(hipMemcpy(sweeps.data(), ir_.sweeps, sizeof(int) * G, hipMemcpyDeviceToHost));
-  NEP_HIP(hipMemcpy(rho.data(), ir_.rho, sizeof(double) * G, hipMemcpyDeviceToHost));
-  NEP_HIP(hipMemcpy(counters.data(), ir_.counters, sizeof(int) * 4, hipMemcpyDeviceToHost));
+  auto read_back = [&]() -> nep_status {
+    NEP_HIP(hipMemcpyAsync(info.data(), dinfo_.p, sizeof(int) * G, hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipMemcpyAsync(conv.data(), ir_.conv, sizeof(int) * G, hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipMemcpyAsync(sweeps.data(), ir_.sweeps, sizeof(int) * G, hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipMemcpyAsync(bad.data(), na_.bad, sizeof(int) * G, hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipMemcpyAsync(rho.data(), ir_.rho, sizeof(double) * G, hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipMemcpyAsync(counters.data(), ir_.counters, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipStreamSynchronize(st));
+    return NEP_OK;
+  };
+  NEP_TRY(read_back());
+  const bool refined = opt.max_refine > 0;
+  const bool mixed = opt.prec == NEP_PREC_C32_IR64;
+  if (allow_fallback && refined && mixed && opt.fallback && !fallback_pending_ && counters[1] == 0) {
+    // a fixed-sweep run left nodes unconverged: re-solve them in FP64 and
+    // recompute the moments (the eager path does this inside enqueue)
+    bool any = false;
+    for (int g = 0; g < G; ++g) any |= (!conv[g] && info[g] >= hpd_[na_prob_host_[g]].n);
+    // (if the FP64 workspace cannot be allocated the nodes stay unconverged
+    // and their problems report NEP_ERR_REFINE)
+    if (any && run_fallback<double>(st) == NEP_OK) {
+      NEP_HIP(launch_moments(dpd_.as<ProbDesc>(), dprefix_.as<int>(), pt_.moments, na_, dY_.as<c128>(), st));
+      NEP_TRY(read_back());
+    }
+  }
   out.stats.assign(nprob, nep_ciss_stats{});
+  out.pstatus.assign(nprob, NEP_OK);
   out.status = NEP_OK;
-  std::vector<int> hprob(G);
-  for (int p = 0; p < nprob; ++p)
-    for (int j = 0; j < opt.N; ++j) hprob[hpd_[p].node0 + j] = p;
   for (int p = 0; p < nprob; ++p) {
     nep_ciss_stats& s = out.stats[p];
     s.N = opt.N;
     s.singular_node = -1;
     s.bad_node = -1;
-    s.max_rel_residual = opt.max_refine > 0 ? 0.0 : -1.0;
+    s.max_rel_residual = refined ? 0.0 : -1.0;
+    if (fallback_pending_) s.n_fallback = fallback_count_[p];
   }
-  const bool refined = opt.max_refine > 0;
-  if (fallback_pending_)
-    for (int p = 0; p < nprob; ++p) out.stats[p].n_fallback = fallback_count_[p];
   for (int g = 0; g < G; ++g) {
-    const int p = hprob[g];
+    const int p = na_prob_host_[g];
     nep_ciss_stats& s = out.stats[p];
     const int j = g - hpd_[p].node0;
+    if (bad[g] && s.bad_node < 0) s.bad_node = j;
     if (info[g] < hpd_[p].n && s.singular_node < 0) s.singular_node = j;
     if (refined) {
       s.refine_sweeps = std::max(s.refine_sweeps, std::min(sweeps[g] - 1, opt.max_refine));
@@ -343,29 +480,36 @@ nep_status MomentsPlan::finish(hipStream_t st, RunResult& out, bool /*allow_fall
       if (std::isfinite(rho[g])) s.max_rel_residual = std::max(s.max_rel_residual, rho[g]);
     }
   }
-  if (counters[1] > 0) {
-    const int g = counters[3];
-    const int p = (g >= 0 && g < G) ? hprob[g] : 0;
-    out.stats[p].bad_node = g - hpd_[p].node0;
-    set_error("quadrature node %d of problem %d lies on a pole or branch cut of some f_i", g - hpd_[p].node0, p);
-    out.status = NEP_ERR_NOT_HOLOMORPHIC;
-    return out.status;
-  }
+  // per-problem status, in order of precedence
   for (int p = 0; p < nprob; ++p) {
-    if (out.stats[p].singular_node >= 0) {
-      set_error("T(z_j) has an exact zero pivot at node %d of problem %d", out.stats[p].singular_node, p);
-      out.status = NEP_ERR_SINGULAR;
-      return out.status;
+    const nep_ciss_stats& s = out.stats[p];
+    nep_status ps = NEP_OK;
+    if (s.bad_node >= 0) {
+      set_error("quadrature node %d of problem %d lies on a pole or branch cut of some f_i", s.bad_node, p);
+      ps = NEP_ERR_NOT_HOLOMORPHIC;
+    } else if (s.singular_node >= 0) {
+      set_error("T(z_j) has an exact zero pivot at node %d of problem %d", s.singular_node, p);
+      ps = NEP_ERR_SINGULAR;
+    } else if (s.n_unconverged > 0 && refined && mixed) {
+      set_error("refinement did not reach the tolerance at %d node(s) of problem %d", s.n_unconverged, p);
+      ps = NEP_ERR_REFINE;
     }
+    out.pstatus[p] = ps;
   }
-  for (int p = 0; p < nprob; ++p) {
-    if (out.stats[p].n_unconverged > 0 && refined && opt.prec == NEP_PREC_C32_IR64) {
-      set_error("refinement did not reach the tolerance at %d node(s) of problem %d", out.stats[p].n_unconverged,
-                p);
-      out.status = NEP_ERR_REFINE;
-      return out.status;
-    }
-  }
+  // the call's status: the most severe kind over problems, message of its first
+  for (nep_status kind : {NEP_ERR_NOT_HOLOMORPHIC, NEP_ERR_SINGULAR, NEP_ERR_REFINE})
+    for (int p = 0; p < nprob; ++p)
+      if (out.pstatus[p] == kind) {
+        const nep_ciss_stats& s = out.stats[p];
+        if (kind == NEP_ERR_NOT_HOLOMORPHIC)
+          set_error("quadrature node %d of problem %d lies on a pole or branch cut of some f_i", s.bad_node, p);
+        else if (kind == NEP_ERR_SINGULAR)
+          set_error("T(z_j) has an exact zero pivot at node %d of problem %d", s.singular_node, p);
+        else
+          set_error("refinement did not reach the tolerance at %d node(s) of problem %d", s.n_unconverged, p);
+        out.status = kind;
+        return out.status;
+      }
   return NEP_OK;
 }
 

@@ -2,17 +2,59 @@
 // launch tables, buffers, and the launch sequence (eager or captured).
 #pragma once
 
+#include <map>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "engine.hpp"
 
 namespace nep {
 
+// A device memory arena: one allocation carved into 256-byte aligned blocks.
+// Returning a block never synchronizes the device (hipFree does), so a
+// server can recycle workspaces while other streams run.
+class Arena {
+ public:
+  Arena() = default;
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+  ~Arena();
+  nep_status init(size_t bytes);
+  void* take(size_t bytes);  // nullptr if no free block is large enough
+  void give(void* p);
+  size_t capacity() const { return size_; }
+  size_t in_use() const;
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0;
+  std::map<size_t, size_t> free_;  // offset -> length, coalesced
+  std::map<size_t, size_t> used_;  // offset -> length
+  mutable std::mutex mu_;
+};
+
+// While an ArenaScope is alive, DevMem allocations made on this thread come
+// from the arena instead of hipMalloc.
+class ArenaScope {
+ public:
+  explicit ArenaScope(Arena* a);
+  ~ArenaScope();
+
+ private:
+  Arena* prev_;
+};
+
+// Small pinned host blocks (64 bytes) from one process-wide pinned slab, so
+// plans do not pair hipHostMalloc/hipHostFree per build.
+void* pinned_take();
+void pinned_give(void* p);
+
 // Device memory block owned by a plan or a handle.
 struct DevMem {
   void* p = nullptr;
   size_t bytes = 0;
+  Arena* arena = nullptr;
   DevMem() = default;
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
@@ -52,8 +94,9 @@ struct PlanOptions {
 };
 
 struct RunResult {
-  nep_status status = NEP_OK;
-  std::vector<nep_ciss_stats> stats;  // per problem
+  nep_status status = NEP_OK;           // first failing problem's status
+  std::vector<nep_ciss_stats> stats;    // per problem
+  std::vector<nep_status> pstatus;      // per problem
 };
 
 class MomentsPlan {
@@ -62,7 +105,7 @@ class MomentsPlan {
   MomentsPlan(const MomentsPlan&) = delete;
   MomentsPlan& operator=(const MomentsPlan&) = delete;
   ~MomentsPlan() {
-    if (hcounter_) (void)hipHostFree(hcounter_);
+    if (hcounter_) pinned_give(hcounter_);
   }
   // Builds layout, tables and buffers.  Problems may differ in n (ragged).
   nep_status build(const std::vector<PlanProblem>& probs, const PlanOptions& o);
@@ -70,8 +113,10 @@ class MomentsPlan {
   // refinement loop early (one small read-back per sweep); eager=false runs a
   // fixed number of sweeps with device-side skipping (graph capture safe).
   nep_status enqueue(hipStream_t st, bool eager);
-  // Waits, reads back device status, runs the FP64 fallback for nodes whose
-  // refinement stalled (if enabled), and fills per-problem stats.
+  // Waits, reads back device status and fills per-problem stats.  With
+  // allow_fallback, nodes that a fixed-sweep (non-eager) run left
+  // unconverged are re-solved in FP64 and the moments recomputed (if the
+  // options enable the fallback).
   nep_status finish(hipStream_t st, RunResult& out, bool allow_fallback);
   // Device buffers shared with extraction and the server.
   const c128* Y() const { return dY_.as<c128>(); }
@@ -99,7 +144,7 @@ class MomentsPlan {
   ProblemTables pt_;
   std::vector<int> hprefix_;
   DevMem dpd_, dmd_, dprefix_, dlu_prefix_, dlu64_prefix_;
-  DevMem dT_, drows_, dinfo_, dWk_, dY_, dR_, dnode_, dir_, dT64_, dWk64_;
+  DevMem dT_, drows_, dinfo_, dY_, dR_, dnode_, dir_, dT64_;
   DevMem ddinv_, ddinv_off_, ddinv64_, dlinv_, dlinv64_;
   std::vector<long long> dinv_off_;
   long long dinv_elems_ = 0;
@@ -112,6 +157,7 @@ class MomentsPlan {
   int sweeps_run_ = 0;
   bool fallback_pending_ = false;
   std::vector<int> fallback_count_;  // per problem, nodes re-solved in FP64
+  std::vector<int> na_prob_host_;    // problem of each node (host copy)
 };
 
 nep_status configure_kernels();

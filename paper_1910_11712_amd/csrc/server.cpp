@@ -1,0 +1,430 @@
+// Serving of "eigenvalues of this operator inside this contour" queries.
+//
+// Queries are queued by nep_server_submit and served by one host thread that
+// owns nstreams device streams ("slots").  Whenever a slot is free, the
+// thread takes the oldest queued query and every other queued query that
+// shares its (N, L, K, precision, refinement) options, as far as the HBM
+// budget and the in-flight limit allow, and runs their moments as one ragged
+// batch (one plan over every (query, node) pair) on that slot's stream.
+// New arrivals join the next free slot while earlier batches still run:
+// continuous batching.  When a slot's batch completes, the thread reads the
+// per-query status, runs the extraction of each query and copies the results
+// to the caller's host arrays.  Workspaces come from one device arena of the
+// budget's size, so recycling them never synchronizes the device.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "handle.hpp"
+
+namespace nep {
+
+namespace {
+
+struct Query {
+  long long ticket = 0;
+  nep_split h = nullptr;
+  nep_contour g{};
+  nep_ciss_opts o{};
+  nep_extract_opts e{};
+  PlanOptions po;
+  int n = 0;
+  std::vector<c128> V;  // host copy of the probes, freed at dispatch
+  double* lambda = nullptr;
+  double* eta = nullptr;
+  int* inside = nullptr;
+  void* X = nullptr;
+  size_t bytes = 0;
+  nep_query_info info{};
+  bool done = false;
+};
+using QueryPtr = std::shared_ptr<Query>;
+
+struct QueryBuffers {
+  DevMem V, S, X;
+};
+
+struct Slot {
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  std::unique_ptr<MomentsPlan> plan;
+  std::vector<QueryPtr> q;
+  std::vector<std::unique_ptr<QueryBuffers>> buf;
+  size_t bytes = 0;
+  bool busy = false;
+};
+
+bool same_batch(const Query& a, const Query& b) {
+  return a.po.N == b.po.N && a.po.L == b.po.L && a.po.K == b.po.K && a.po.prec == b.po.prec &&
+         a.po.max_refine == b.po.max_refine && a.po.fallback == b.po.fallback && a.po.tol == b.po.tol;
+}
+
+}  // namespace
+
+class Server {
+ public:
+  ~Server();
+  nep_status init(const nep_server_opts* o);
+  nep_status submit(nep_split h, const nep_contour* g, const nep_ciss_opts* o, const nep_extract_opts* e,
+                    const void* V, double* lambda, double* eta, int* inside, void* X, long long* ticket);
+  nep_status poll(long long ticket, int* done, nep_query_info* info, bool block);
+  double clock() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
+  }
+  void shutdown();
+
+ private:
+  void loop();
+  bool dispatch(Slot& s);                // true if a batch was started
+  void complete(Slot& s);                // the slot's batch has finished
+  void fail(std::vector<QueryPtr>& qs, nep_status st);
+  static size_t query_bytes(const Query& q);
+
+  Arena arena_;
+  int device_ = 0;
+  size_t budget_ = 0, inflight_bytes_ = 0;
+  int max_inflight_ = 1, inflight_ = 0, batch_cap_ = 1;
+  std::vector<Slot> slots_;
+  std::mutex mu_;
+  std::condition_variable cv_work_, cv_done_;
+  std::deque<QueryPtr> queue_;
+  std::unordered_map<long long, QueryPtr> tickets_;
+  long long next_ticket_ = 1;
+  bool stop_ = false, started_ = false;
+  bool arena_full_ = false;  // a dispatch found no room; wait for a completion
+  std::chrono::steady_clock::time_point t0_ = std::chrono::steady_clock::now();
+  std::thread th_;
+};
+
+Server::~Server() { shutdown(); }
+
+size_t Server::query_bytes(const Query& q) {
+  const size_t c = sizeof(c128);
+  size_t b = MomentsPlan::estimate_bytes(q.n, q.po.N, q.po.L, q.po.prec);
+  b += (size_t)q.n * q.po.L * c * (1 + 2 * q.po.K);  // V and S
+  b += (size_t)q.n * q.e.max_eigs * c;               // X
+  return b + (1u << 20);                              // tables, alignment
+}
+
+nep_status Server::init(const nep_server_opts* o) {
+  NEP_CHECK(o != nullptr, NEP_ERR_ARG, "null server options");
+  NEP_CHECK(o->hbm_budget > 0, NEP_ERR_ARG, "hbm_budget must be positive");
+  NEP_CHECK(o->max_inflight >= 1, NEP_ERR_ARG, "max_inflight must be >= 1");
+  NEP_CHECK(o->nstreams >= 1 && o->nstreams <= 16, NEP_ERR_ARG, "nstreams must be in 1..16");
+  NEP_TRY(configure_kernels());
+  NEP_HIP(hipGetDevice(&device_));
+  budget_ = (size_t)o->hbm_budget;
+  max_inflight_ = o->max_inflight;
+  batch_cap_ = std::max(1, (max_inflight_ + o->nstreams - 1) / o->nstreams);
+  NEP_TRY(arena_.init(budget_));
+  slots_.resize(o->nstreams);
+  for (auto& s : slots_) {
+    NEP_HIP(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
+    NEP_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+  }
+  th_ = std::thread([this] { loop(); });
+  started_ = true;
+  return NEP_OK;
+}
+
+nep_status Server::submit(nep_split h, const nep_contour* g, const nep_ciss_opts* o, const nep_extract_opts* e,
+                          const void* V, double* lambda, double* eta, int* inside, void* X, long long* ticket) {
+  NEP_CHECK(h != nullptr && ticket != nullptr, NEP_ERR_ARG, "null handle or ticket");
+  NEP_CHECK(V != nullptr && lambda != nullptr && eta != nullptr && inside != nullptr, NEP_ERR_ARG,
+            "null probe or result array");
+  NEP_CHECK(e != nullptr && e->max_eigs >= 1, NEP_ERR_ARG, "extract options need max_eigs >= 1");
+  NEP_TRY(check_contour(g));
+  auto q = std::make_shared<Query>();
+  NEP_TRY(check_opts(o, q->po));
+  q->h = h;
+  q->g = *g;
+  q->o = *o;
+  q->e = *e;
+  q->n = h->impl.op.n;
+  q->lambda = lambda;
+  q->eta = eta;
+  q->inside = inside;
+  q->X = X;
+  q->bytes = query_bytes(*q);
+  NEP_CHECK(q->bytes <= budget_, NEP_ERR_BUSY, "query needs %zu bytes, more than the server's HBM budget %zu",
+            q->bytes, budget_);
+  const size_t cnt = (size_t)q->n * q->po.L;
+  q->V.assign(static_cast<const c128*>(V), static_cast<const c128*>(V) + cnt);
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    NEP_CHECK(!stop_, NEP_ERR_ARG, "server is shutting down");
+    q->ticket = next_ticket_++;
+    q->info.status = NEP_OK;
+    q->info.t_submit = clock();
+    tickets_[q->ticket] = q;
+    queue_.push_back(q);
+    *ticket = q->ticket;
+  }
+  cv_work_.notify_one();
+  return NEP_OK;
+}
+
+nep_status Server::poll(long long ticket, int* done, nep_query_info* info, bool block) {
+  std::unique_lock<std::mutex> lk(mu_);
+  auto it = tickets_.find(ticket);
+  NEP_CHECK(it != tickets_.end(), NEP_ERR_ARG, "unknown or already collected ticket %lld", ticket);
+  QueryPtr q = it->second;
+  if (block) cv_done_.wait(lk, [&] { return q->done; });
+  if (done) *done = q->done ? 1 : 0;
+  if (q->done) {
+    if (info) *info = q->info;
+    tickets_.erase(it);  // collected
+  }
+  return NEP_OK;
+}
+
+void Server::shutdown() {
+  if (started_) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_work_.notify_all();
+    th_.join();
+    started_ = false;
+  }
+  for (auto& s : slots_) {
+    if (s.ev) (void)hipEventDestroy(s.ev);
+    if (s.st) (void)hipStreamDestroy(s.st);
+    s.ev = nullptr;
+    s.st = nullptr;
+  }
+}
+
+void Server::fail(std::vector<QueryPtr>& qs, nep_status st) {
+  std::lock_guard<std::mutex> lk(mu_);
+  for (auto& q : qs) {
+    q->info.status = st;
+    q->info.t_done = clock();
+    q->done = true;
+    inflight_--;
+    inflight_bytes_ -= q->bytes;
+  }
+  cv_done_.notify_all();
+}
+
+bool Server::dispatch(Slot& s) {
+  std::vector<QueryPtr> batch;
+  size_t bytes = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (queue_.empty() || arena_full_) return false;
+    const QueryPtr head = queue_.front();
+    for (auto it = queue_.begin(); it != queue_.end() && (int)batch.size() < batch_cap_;) {
+      const Query& q = **it;
+      const bool fits = inflight_ + (int)batch.size() < max_inflight_ && inflight_bytes_ + bytes + q.bytes <= budget_;
+      if (batch.empty() && !fits) break;  // the oldest query waits for room: it is never overtaken
+      if (!fits || !same_batch(q, *head)) {
+        ++it;
+        continue;
+      }
+      bytes += q.bytes;
+      batch.push_back(*it);
+      it = queue_.erase(it);
+    }
+    if (batch.empty()) return false;
+    inflight_ += (int)batch.size();
+    inflight_bytes_ += bytes;
+    const double t = clock();
+    for (auto& q : batch) q->info.t_start = t;
+  }
+  // workspaces and the plan come from the arena
+  ArenaScope scope(&arena_);
+  s.buf.clear();
+  std::vector<PlanProblem> probs;
+  nep_status st = NEP_OK;
+  for (auto& q : batch) {
+    auto b = std::make_unique<QueryBuffers>();
+    const size_t c = sizeof(c128), nl = (size_t)q->n * q->po.L;
+    st = b->V.alloc(nl * c);
+    if (st == NEP_OK) st = b->S.alloc(nl * 2 * q->po.K * c);
+    if (st == NEP_OK) st = b->X.alloc((size_t)q->n * q->e.max_eigs * c);
+    if (st != NEP_OK) break;
+    if (hipMemcpyAsync(b->V.p, q->V.data(), nl * c, hipMemcpyHostToDevice, s.st) != hipSuccess) {
+      (void)hipGetLastError();
+      st = NEP_ERR_DEVICE;
+      break;
+    }
+    probs.push_back(PlanProblem{&q->h->impl.op, q->g, b->V.as<c128>(), b->S.as<c128>()});
+    s.buf.push_back(std::move(b));
+  }
+  if (st == NEP_OK) {
+    s.plan = std::make_unique<MomentsPlan>();
+    st = s.plan->build(probs, batch.front()->po);
+  }
+  if (st == NEP_OK) st = s.plan->enqueue(s.st, false);
+  if (st == NEP_OK && hipEventRecord(s.ev, s.st) != hipSuccess) st = NEP_ERR_DEVICE;
+  if (st == NEP_ERR_OOM) {
+    // the arena is fragmented or the estimate was short: requeue in order
+    (void)hipStreamSynchronize(s.st);
+    s.plan.reset();
+    s.buf.clear();
+    bool others_busy = false;
+    for (auto& o : slots_) others_busy |= o.busy;
+    if (others_busy) {
+      std::lock_guard<std::mutex> lk(mu_);
+      for (auto it = batch.rbegin(); it != batch.rend(); ++it) queue_.push_front(*it);
+      inflight_ -= (int)batch.size();
+      inflight_bytes_ -= bytes;
+      arena_full_ = true;
+      return false;
+    }
+  }
+  if (st != NEP_OK) {
+    (void)hipStreamSynchronize(s.st);
+    s.plan.reset();
+    s.buf.clear();
+    fail(batch, st);
+    return true;
+  }
+  for (auto& q : batch) std::vector<c128>().swap(q->V);  // the device holds the probes now
+  s.q = std::move(batch);
+  s.bytes = bytes;
+  s.busy = true;
+  return true;
+}
+
+void Server::complete(Slot& s) {
+  ArenaScope scope(&arena_);  // a fallback re-solve allocates from the arena
+  RunResult rr;
+  (void)s.plan->finish(s.st, rr, true);
+  for (size_t k = 0; k < s.q.size(); ++k) {
+    Query& q = *s.q[k];
+    nep_status st = k < rr.pstatus.size() ? rr.pstatus[k] : NEP_ERR_DEVICE;
+    int m = 0, nin = 0;
+    if (st == NEP_OK) {
+      nep_ciss_opts o = q.o;
+      o.stream = s.st;
+      ArenaScope off(nullptr);  // extraction workspaces belong to the handle
+      st = nep_extract(q.h, &q.g, &o, s.buf[k]->S.p, &q.e, &m, q.lambda, s.buf[k]->X.p, q.eta, q.inside, nullptr);
+      if (st == NEP_OK && q.X != nullptr && m > 0) {
+        if (hipMemcpyAsync(q.X, s.buf[k]->X.p, sizeof(c128) * (size_t)q.n * m, hipMemcpyDeviceToHost, s.st) !=
+                hipSuccess ||
+            hipStreamSynchronize(s.st) != hipSuccess) {
+          (void)hipGetLastError();
+          st = NEP_ERR_DEVICE;
+        }
+      }
+      if (st == NEP_OK)
+        for (int i = 0; i < m; ++i) nin += q.inside[i] ? 1 : 0;
+    }
+    q.info.status = st;
+    q.info.m = m;
+    q.info.n_inside = nin;
+  }
+  s.plan.reset();
+  s.buf.clear();
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    const double t = clock();
+    for (auto& q : s.q) {
+      q->info.t_done = t;
+      q->done = true;
+    }
+    inflight_ -= (int)s.q.size();
+    inflight_bytes_ -= s.bytes;
+    arena_full_ = false;
+  }
+  cv_done_.notify_all();
+  s.q.clear();
+  s.bytes = 0;
+  s.busy = false;
+}
+
+void Server::loop() {
+  (void)hipSetDevice(device_);
+  for (;;) {
+    bool progress = false;
+    for (auto& s : slots_) {
+      if (s.busy) {
+        const hipError_t e = hipEventQuery(s.ev);
+        if (e == hipSuccess) {
+          complete(s);
+          progress = true;
+        } else if (e != hipErrorNotReady) {
+          (void)hipGetLastError();
+          std::vector<QueryPtr> qs = std::move(s.q);
+          s.plan.reset();
+          s.buf.clear();
+          s.busy = false;
+          s.bytes = 0;
+          fail(qs, NEP_ERR_DEVICE);
+          progress = true;
+        }
+      }
+      if (!s.busy && dispatch(s)) progress = true;
+    }
+    if (progress) continue;
+    std::unique_lock<std::mutex> lk(mu_);
+    bool busy = false;
+    for (auto& s : slots_) busy |= s.busy;
+    if (stop_ && queue_.empty() && !busy) break;
+    if (busy)
+      cv_work_.wait_for(lk, std::chrono::microseconds(100));
+    else if (queue_.empty() || arena_full_)
+      cv_work_.wait(lk, [&] { return stop_ || (!queue_.empty() && !arena_full_); });
+    if (!busy && arena_full_) arena_full_ = false;  // nothing left to wait for
+  }
+}
+
+}  // namespace nep
+
+struct nep_server_s {
+  nep::Server impl;
+};
+
+using namespace nep;
+
+extern "C" {
+
+nep_status nep_server_create(const nep_server_opts* o, nep_server* out) {
+  NEP_CHECK(out != nullptr, NEP_ERR_ARG, "null output");
+  *out = nullptr;
+  auto s = std::make_unique<nep_server_s>();
+  NEP_TRY(s->impl.init(o));
+  *out = s.release();
+  return NEP_OK;
+}
+
+nep_status nep_server_submit(nep_server s, nep_split h, const nep_contour* g, const nep_ciss_opts* o,
+                             const nep_extract_opts* e, const void* V, double* lambda, double* eta, int* inside,
+                             void* X, long long* ticket) {
+  NEP_CHECK(s != nullptr, NEP_ERR_ARG, "null server");
+  return s->impl.submit(h, g, o, e, V, lambda, eta, inside, X, ticket);
+}
+
+nep_status nep_server_poll(nep_server s, long long ticket, int* done, nep_query_info* info) {
+  NEP_CHECK(s != nullptr && done != nullptr, NEP_ERR_ARG, "null server or output");
+  return s->impl.poll(ticket, done, info, false);
+}
+
+nep_status nep_server_wait(nep_server s, long long ticket, nep_query_info* info) {
+  NEP_CHECK(s != nullptr, NEP_ERR_ARG, "null server");
+  int done = 0;
+  return s->impl.poll(ticket, &done, info, true);
+}
+
+double nep_server_clock(nep_server s) { return s ? s->impl.clock() : 0.0; }
+
+nep_status nep_server_destroy(nep_server* s) {
+  NEP_CHECK(s != nullptr, NEP_ERR_ARG, "null server pointer");
+  if (*s) {
+    (*s)->impl.shutdown();
+    delete *s;
+  }
+  *s = nullptr;
+  return NEP_OK;
+}
+
+}  // extern "C"

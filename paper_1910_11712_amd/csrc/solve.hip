@@ -299,7 +299,7 @@ static void launch_trsv(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* 
 
 template <typename P>
 hipError_t solve_run(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md, const NodeArrays& na,
-                     const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off, cx<P>* /*Wk*/,
+                     const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off,
                      const c128* R, c128* Y, bool refine, const int* conv, IrState ir, hipStream_t st) {
   if (sp.nmat == 0) return hipSuccess;
   const int rf = refine ? 1 : 0;
@@ -316,10 +316,10 @@ template hipError_t diag_inv_run<float>(const SolvePlan&, const int*, const MatD
 template hipError_t diag_inv_run<double>(const SolvePlan&, const int*, const MatDesc*, const c128*, const int*,
                                          c128*, const long long*, const int*, hipStream_t);
 template hipError_t solve_run<float>(const SolvePlan&, const ProbDesc*, const MatDesc*, const NodeArrays&, const c64*,
-                                     const int*, const c64*, const long long*, c64*, const c128*, c128*, bool,
+                                     const int*, const c64*, const long long*, const c128*, c128*, bool,
                                      const int*, IrState, hipStream_t);
 template hipError_t solve_run<double>(const SolvePlan&, const ProbDesc*, const MatDesc*, const NodeArrays&,
-                                      const c128*, const int*, const c128*, const long long*, c128*, const c128*,
+                                      const c128*, const int*, const c128*, const long long*, const c128*,
                                       c128*, bool, const int*, IrState, hipStream_t);
 
 // Column-group size: enough groups to occupy the device when there are few

@@ -1,0 +1,131 @@
+"""Serving path (continuous batching over several streams) through the C ABI.
+
+A query's result must not depend on what else is in flight: every query run
+in a mix equals the same query run alone (moments + extraction on its own
+handle), bit for bit, and matches the oracle's eigenvalues inside the
+contour."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from workloads import Contour, Problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def nep():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1910_11712_amd as P
+    P.binding.lib()
+    return P
+
+
+def _alone(P, op, con, V, N, L, K, prec, max_eigs):
+    Vd = P.device_probes(V)
+    S, st = op.moments(con, Vd, N, L, K, prec=prec)
+    X = torch.zeros((max_eigs, op.n), dtype=torch.complex128, device="cuda")
+    return op.extract(con, S, N, L, K, prec=prec, max_eigs=max_eigs, X=X)
+
+
+def _mix_cases():
+    """Rational problems of several sizes and two option groups, plus a
+    delay problem: (problem, contour, N, L, K, V)."""
+    cases = []
+    for i, (n, sig, s) in enumerate([(200, 1.0, 1.0), (150, 1.5, 0.8), (260, 0.7, 1.3), (96, 1.0, 1.0)]):
+        p = wl.loaded_string(n, sigma=sig, a_scale=s)
+        N = 32 if i % 2 == 0 else 64
+        cases.append((p, Contour.circle(100.0 * s, 90.0 * s), N, 8, 2, wl.probes(n, 8, 10 + i)))
+    d = wl.delay_problem(120, tau=1.0, seed=7)
+    cases.append((d, Contour.circle(-1.0, 0.4), 32, 8, 4, wl.probes(120, 8, 20)))
+    return cases
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_server_mix_equals_alone(nep, prec):
+    cases = _mix_cases()
+    ops = [nep.SplitOperator.from_problem(c[0]) for c in cases]
+    max_eigs = 32
+    alone = [_alone(nep, op, c[1], c[5], c[2], c[3], c[4], prec, max_eigs) for op, c in zip(ops, cases)]
+    srv = nep.Server(hbm_budget=1 << 30, max_inflight=16, nstreams=3)
+    try:
+        tickets = []
+        for rep in range(2):  # every case twice, interleaved
+            for op, c in zip(ops, cases):
+                tickets.append(srv.submit(op, c[1], c[5], c[2], c[3], c[4], prec=prec, max_eigs=max_eigs,
+                                          want_X=True))
+        results = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    for k, r in enumerate(results):
+        a = alone[k % len(cases)]
+        assert r["status"] == 0, (k, r["status"])
+        assert r["m"] == a["m"]
+        assert np.array_equal(r["lam"], a["lam"]), k
+        assert np.array_equal(r["eta"], a["eta"]), k
+        assert np.array_equal(r["inside"], a["inside"]), k
+        assert np.array_equal(r["X"], a["X"]), k
+        assert r["t_submit"] <= r["t_start"] <= r["t_done"]
+    # the first case is the rational n=200 problem: its inside eigenvalues
+    # match the oracle
+    p, con, N, L, K, V = cases[0]
+    So = oracle.ciss_moments(p, con, N, K, V)
+    ro = oracle.extract(p, con, So, K)
+    ref = np.sort_complex(ro["lam"][ro["inside"]])
+    got = np.sort_complex(results[0]["lam"][results[0]["inside"]])
+    assert len(ref) == len(got) == 3
+    assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-10
+    assert np.all(results[0]["eta"][results[0]["inside"]] <= 1e-10)
+
+
+def test_server_query_errors_are_isolated(nep):
+    """A query whose contour crosses a branch cut fails alone; the queries
+    batched with it succeed."""
+    good = wl.config0()
+    f = wl.fn_combine(wl.COMB_COMPOSE, wl.fn_rational([-1.0]), wl.fn_sqrt())  # sqrt(-1): on the cut everywhere
+    bad = Problem("cut", [np.eye(8), np.eye(8)], [wl.fn_rational([1.0]), f])
+    op_g = nep.SplitOperator.from_problem(good["problem"])
+    op_b = nep.SplitOperator.from_problem(bad)
+    srv = nep.Server(hbm_budget=1 << 30, max_inflight=8, nstreams=1)
+    try:
+        t1 = srv.submit(op_g, good["contour"], good["V"], 32, 8, 2)
+        t2 = srv.submit(op_b, Contour.circle(0.0, 1.0), wl.probes(8, 8, 0), 32, 8, 2)
+        t3 = srv.submit(op_g, good["contour"], good["V"], 32, 8, 2)
+        r1, r2, r3 = srv.wait(t1), srv.wait(t2), srv.wait(t3)
+    finally:
+        srv.close()
+    assert r1["status"] == 0 and r3["status"] == 0
+    assert nep.binding.ERRORS[r2["status"]] == "NEP_ERR_NOT_HOLOMORPHIC"
+    assert np.array_equal(r1["lam"], r3["lam"])
+
+
+def test_server_budget(nep):
+    """A query larger than the whole budget is refused at submit; a budget
+    that holds one query at a time still serves every query."""
+    cfg = wl.config0()
+    op = nep.SplitOperator.from_problem(cfg["problem"])
+    srv = nep.Server(hbm_budget=4 << 20, max_inflight=4, nstreams=2)
+    try:
+        with pytest.raises(nep.NepError) as ei:
+            srv.submit(op, cfg["contour"], cfg["V"], 32, 8, 2)
+        assert ei.value.name == "NEP_ERR_BUSY"
+    finally:
+        srv.close()
+    one = 40 << 20  # holds one n=200 query (about 33 MB) but not two
+    srv = nep.Server(hbm_budget=one, max_inflight=4, nstreams=2)
+    try:
+        ts = [srv.submit(op, cfg["contour"], cfg["V"], 32, 8, 2) for _ in range(4)]
+        rs = [srv.wait(t) for t in ts]
+    finally:
+        srv.close()
+    for r in rs:
+        assert r["status"] == 0
+        assert np.array_equal(r["lam"], rs[0]["lam"])
+    # served one after another: no two queries overlap in time
+    spans = sorted((r["t_start"], r["t_done"]) for r in rs)
+    for a, b in zip(spans, spans[1:]):
+        assert b[0] >= a[1]
