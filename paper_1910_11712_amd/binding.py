@@ -367,3 +367,35 @@ def nep_server_clock(s):
 
 def nep_server_destroy(s):
     check(lib().nep_server_destroy(C.byref(s)))
+
+
+# --------------------------------------------------------------------------
+# Batched moments
+
+def nep_batch_create(handles, contours, opts, Vs, Ss, use_graph=True, stream=None):
+    """handles: list of nep_split; contours: list; Vs/Ss: device tensors
+    (L, n) and (2K, L, n) complex128.  Returns the batch handle."""
+    n = len(handles)
+    harr = (C.c_void_p * n)(*[h.value for h in handles])
+    garr = (nep_contour * n)(*[contour_struct(c) for c in contours])
+    varr = (C.c_void_p * n)(*[v.data_ptr() for v in Vs])
+    sarr = (C.c_void_p * n)(*[s.data_ptr() for s in Ss])
+    b = C.c_void_p()
+    check(lib().nep_batch_create(n, harr, garr, C.byref(opts), varr, sarr, 1 if use_graph else 0,
+                                 _stream_ptr(stream), C.byref(b)))
+    return b
+
+
+def nep_batch_run(b, nprob=None):
+    """Runs the plan; with nprob the call is synchronous and returns the
+    per-problem stats."""
+    if nprob is None:
+        check(lib().nep_batch_run(b, None))
+        return None
+    st = (nep_ciss_stats * nprob)()
+    check(lib().nep_batch_run(b, st))
+    return [s.as_dict() for s in st]
+
+
+def nep_batch_destroy(b):
+    check(lib().nep_batch_destroy(C.byref(b)))

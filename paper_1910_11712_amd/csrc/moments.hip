@@ -135,7 +135,12 @@ template hipError_t launch_assemble<double>(const ProbDesc*, const int*, const T
 // Y: row-major n x (N*L) per problem; S: column-major n x L per moment p.
 // ---------------------------------------------------------------------------
 constexpr int kMomThreads = 256;
+constexpr int kMomQ = 8;  // moments per thread
 
+// One thread per (row r, probe column c, group of kMomQ moments); the sum
+// over nodes runs in ascending j for every moment.  Lanes of a wave cover
+// consecutive (c, r) pairs of one moment group, so Y loads are contiguous
+// per row and the coefficients w_j zeta_j^p are wave-uniform.
 __global__ __launch_bounds__(kMomThreads) void k_moments(const ProbDesc* __restrict__ pd,
                                                          const int* __restrict__ prefix, int cnt, int total,
                                                          NodeArrays na, const c128* __restrict__ Y) {
@@ -143,24 +148,30 @@ __global__ __launch_bounds__(kMomThreads) void k_moments(const ProbDesc* __restr
   if (v < 0) return;
   const int p = find_slot(prefix, cnt, v);
   const ProbDesc& D = pd[p];
-  const int e = (v - prefix[p]) * kMomThreads + threadIdx.x;
-  const int n = D.n, L = D.L, NL = D.N * D.L;
-  if (e >= n * L) return;
+  const int n = D.n, L = D.L, NL = D.N * D.L, KK = D.KK, N = D.N, node0 = D.node0;
+  const int ngrp = (KK + kMomQ - 1) / kMomQ;
+  const int nl = n * L;
+  const int blocks_per_grp = (nl + kMomThreads - 1) / kMomThreads;
+  const int local = v - prefix[p];
+  const int qg = local / blocks_per_grp;
+  const int e = (local - qg * blocks_per_grp) * kMomThreads + threadIdx.x;
+  if (qg >= ngrp || e >= nl) return;
   const int r = e / L, c = e - r * L;
-  c128 acc[kMaxMoments];
+  const int q0 = qg * kMomQ;
+  c128 acc[kMomQ];
 #pragma unroll
-  for (int q = 0; q < kMaxMoments; ++q) acc[q] = {0.0, 0.0};
+  for (int q = 0; q < kMomQ; ++q) acc[q] = {0.0, 0.0};
   const c128* y = Y + D.offY + (long long)r * NL + c;
-  for (int j = 0; j < D.N; ++j) {
+  const c128* mc0 = na.mcoef + (long long)node0 * kMaxMoments + q0;
+  for (int j = 0; j < N; ++j) {
     const c128 yv = y[j * L];
-    const c128* mc = na.mcoef + (long long)(D.node0 + j) * kMaxMoments;
+    const c128* mc = mc0 + (long long)j * kMaxMoments;
 #pragma unroll
-    for (int q = 0; q < kMaxMoments; ++q)
-      if (q < D.KK) acc[q] = acc[q] + mc[q] * yv;
+    for (int q = 0; q < kMomQ; ++q) acc[q] = cmac(acc[q], mc[q], yv);
   }
 #pragma unroll
-  for (int q = 0; q < kMaxMoments; ++q)
-    if (q < D.KK) D.S[(long long)q * n * L + (long long)c * n + r] = acc[q];
+  for (int q = 0; q < kMomQ; ++q)
+    if (q0 + q < KK) D.S[(long long)(q0 + q) * nl + (long long)c * n + r] = acc[q];
 }
 
 hipError_t launch_moments(const ProbDesc* pd, const int* prefix, const Table& t, const NodeArrays& na,

@@ -270,7 +270,7 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
       const long long n = hpd_[p].n;
       ca.push_back((int)ceil_div_ll(n * n, 256));
       cr.push_back(ceil_div((int)n, 64) * ceil_div(2 * o.N * o.L, 64));
-      cm.push_back(ceil_div((int)n * o.L, 256));
+      cm.push_back(ceil_div((int)n * o.L, 256) * ceil_div(2 * o.K, 8));  // (row, column) blocks x moment groups
     }
     build_prefix(hprefix_, pt_.assemble, ca);
     build_prefix(hprefix_, pt_.resid, cr);
@@ -391,9 +391,23 @@ template <typename P>
 nep_status MomentsPlan::run_fallback(hipStream_t st) {
   static_assert(sizeof(P) == 8, "fallback runs in FP64");
   if (!dT64_.p) {
-    NEP_TRY(dT64_.alloc(sizeof(c128) * (size_t)t_elems_));
-    NEP_TRY(ddinv64_.alloc(sizeof(c128) * (size_t)dinv_elems_));
-    NEP_TRY(dlinv64_.alloc(sizeof(c128) * (size_t)sorted_.size() * kLuMaxJB * kLuMaxJB));
+    auto alloc64 = [&]() -> nep_status {
+      nep_status s = dT64_.alloc(sizeof(c128) * (size_t)t_elems_);
+      if (s == NEP_OK) s = ddinv64_.alloc(sizeof(c128) * (size_t)dinv_elems_);
+      if (s == NEP_OK) s = dlinv64_.alloc(sizeof(c128) * (size_t)sorted_.size() * kLuMaxJB * kLuMaxJB);
+      if (s != NEP_OK) {
+        dT64_.release();
+        ddinv64_.release();
+        dlinv64_.release();
+      }
+      return s;
+    };
+    nep_status s = alloc64();
+    if (s == NEP_ERR_OOM) {  // an arena without room: take the rare re-solve from the device heap
+      ArenaScope heap(nullptr);
+      s = alloc64();
+    }
+    NEP_TRY(s);
   }
   const ProbDesc* pd = dpd_.as<ProbDesc>();
   const MatDesc* md = dmd_.as<MatDesc>();

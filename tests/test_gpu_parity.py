@@ -207,3 +207,42 @@ def test_batch_equals_single_calls(nep, use_graph):
             Sg = nep.moments_to_numpy(Ss[k])
             assert np.array_equal(Sg, singles[k]), (rep, k, np.abs(Sg - singles[k]).max())
     B.check(B.lib().nep_batch_destroy(C.byref(bh)))
+
+
+def test_config3_full_batch_graph_sampled(nep):
+    """The 256-problem ragged batch at full size, replayed from a HIP graph
+    exactly as the benchmark runs it; every problem converges, and sampled
+    problems (smallest, largest and a middle n) match the oracle's moments."""
+    cfg = wl.config3()
+    con, N, L, K = cfg["contour"], cfg["N"], cfg["L"], cfg["K"]
+    probs = cfg["problems"]
+    ops = [nep.SplitOperator.from_problem(p) for p in probs]
+    Vs = [nep.device_probes(V) for V in cfg["V"]]
+    Ss = [torch.zeros((2 * K, L, p.n), dtype=torch.complex128, device="cuda") for p in probs]
+    B = nep.binding
+    b = B.nep_batch_create([op.h for op in ops], [con] * len(ops), B.opts_struct(N, L, K, "mixed"), Vs, Ss,
+                           use_graph=True)
+    B.nep_batch_run(b)                 # first replay
+    stats = B.nep_batch_run(b, len(ops))   # second replay, synchronous
+    B.nep_batch_destroy(b)
+    assert all(s["n_unconverged"] == 0 and s["singular_node"] < 0 for s in stats)
+    ns = np.array([p.n for p in probs])
+    for k in sorted({int(np.argmin(ns)), int(np.argmax(ns)), int(np.argsort(ns)[len(ns) // 2])}):
+        So = oracle.ciss_moments(probs[k], con, N, K, cfg["V"][k])
+        _check_moments(nep.moments_to_numpy(Ss[k]), So)
+
+
+def test_config2_full_size_backward_error(nep):
+    """The square-root problem at its full size n=4096 (mixed path): every
+    eigenpair returned inside the ellipse has an FP64 backward error, computed
+    by the oracle on the CPU, of at most 1e-10."""
+    cfg = wl.config2()
+    p, con = cfg["problem"], cfg["contour"]
+    op, S, Sg, st = _run_moments(nep, p, con, cfg["N"], cfg["L"], cfg["K"], cfg["V"], "mixed")
+    assert st["n_unconverged"] == 0
+    r = op.extract(con, S, cfg["N"], cfg["L"], cfg["K"], max_eigs=64)
+    ins = r["inside"]
+    assert ins.sum() >= 20
+    eta_cpu = oracle.backward_error(p, r["lam"][ins], r["X"][:, ins])
+    assert np.all(eta_cpu <= 1e-10), eta_cpu
+    assert np.all(r["eta"][ins] <= 1e-10)

@@ -10,12 +10,12 @@ from .fn import (fn_rational, fn_exp, fn_log, fn_sqrt, fn_invsqrt, fn_phi,
                  fn_combine, COMB_ADD, COMB_MUL, COMB_DIV, COMB_COMPOSE)
 from .problems import (Problem, Contour, probes, config0, config1, config2,
                        config3, config4_stream, loaded_string, delay_problem,
-                       sqrt_problem, CONFIGS)
+                       sqrt_problem, build_operator, CONFIGS)
 
 __all__ = [
     "fn_rational", "fn_exp", "fn_log", "fn_sqrt", "fn_invsqrt", "fn_phi",
     "fn_combine", "COMB_ADD", "COMB_MUL", "COMB_DIV", "COMB_COMPOSE",
     "Problem", "Contour", "probes", "config0", "config1", "config2",
     "config3", "config4_stream", "loaded_string", "delay_problem",
-    "sqrt_problem", "CONFIGS",
+    "sqrt_problem", "build_operator", "CONFIGS",
 ]
