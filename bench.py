@@ -67,6 +67,23 @@ def _time_moments(P, op, cfg, Vd, S, prec, steps, warmup, prof=False):
     return max(ms_dev / 1e3, wall) / steps, stats, prof_out
 
 
+def _gemm_traffic():
+    """HBM bytes per launch of the trailing-update GEMM, as recorded from
+    rocprofv3 FETCH_SIZE/WRITE_SIZE counters (copy-calibrated) in profiles/;
+    None if the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "lu_gemm_c64_delay_n1000_pmc.txt")
+    src = os.path.join(ROOT, "paper_1910_11712_amd", "csrc", "lu.hip")
+    try:
+        rec = dict(l.split(":", 1) for l in open(path) if not l.startswith("#") and ":" in l)
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if rec["source_sha256_16"].split()[0] != h:
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def _cpu_baseline(cfg, budget_s=20.0):
     """The oracle (numpy/LAPACK FP64) on a bounded sample of nodes."""
     import oracle
@@ -200,7 +217,18 @@ def main():
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 4, "launches": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a design "
                                    "note (nodes and problems are independent), not a measured path"}))
@@ -226,7 +254,7 @@ def main():
     achieved = flops / (ms / 1e3) / 1e12 if ms > 0 else 0.0
     roof = {"kernel": "k_lu_gemm_c64 (trailing update, v_mfma_f32_32x32x2f32)", "bound": "mfma",
             "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": None,
+            "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": _gemm_traffic(),
             "launches_per_step": launches // max(1, args.steps),
             "avg_launch_ms": round(ms / max(1, launches), 5),
             "flops_per_launch": flops / max(1, launches)}
