@@ -366,9 +366,9 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
   const MatDesc d = md[b];
   if (skip != nullptr && skip[d.node]) return;
   const int n = d.n;
-  const int jb = min(jbmax, n - k0);
-  const int s0 = k0 + jb;          // first trailing row/col
-  const int mt = n - s0;           // trailing size
+  const int jb = min(jbmax, n - k0);  // == jbmax whenever a trailing block exists (a multiple of kG32KC)
+  const int s0 = k0 + jb;             // first trailing row/col
+  const int mt = n - s0;              // trailing size
   const int tiles_n = (mt + kG32TN - 1) / kG32TN;
   const int tm = t / tiles_n, tn = t - tm * tiles_n;
   const int row0 = (MODE == 0 ? s0 : k0) + tm * kG32TM, col0 = s0 + tn * kG32TN;
@@ -376,94 +376,136 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
   c64* __restrict__ T = Tb + d.offT;
   const int ld = d.ld;
   const int* __restrict__ rat = rowb + d.offRow;
-  const c64* __restrict__ Li = MODE == 1 ? Linv + (long long)b * kLuMaxJB * kLuMaxJB : nullptr;
+  const c64* __restrict__ Asrc = MODE == 1 ? Linv + (long long)b * kLuMaxJB * kLuMaxJB : T;
 
   // LDS: A as [k][row] complex (stride kG32TM+2), B as re/im planes [k][col].
   __shared__ float As[2][kG32KC][2 * kG32TM + 4];
   __shared__ float Bs[2][kG32KC][2][kG32TN + 4];
+  // element offsets of the tile's A rows (-1: outside) and of the jb B rows
+  __shared__ int aoff_s[kG32TM];
+  __shared__ int boff_s[kLuMaxJB];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 64, wcn = (wave & 1) * 64;
+  if (tid < kG32TM) {
+    const int gr = row0 + tid;
+    aoff_s[tid] = gr < row_end ? (MODE == 0 ? rat[gr] * ld : (gr - k0) * kLuMaxJB) : -1;
+  }
+  for (int i = tid; i < jb; i += 256) boff_s[i] = rat[k0 + i] * ld;
+  __syncthreads();
 
-  // global -> register staging (each thread: 4 float4 of A, 4 float4 of B)
-  // A tile: 128 rows x 16 k complex = 128 rows x 8 float4; thread -> (row, kp)
-  // B tile: 16 k x 128 cols complex = 16 rows x 64 float4
+  // per-thread staging roles: A (row r = tid/8 + 32q, k-pair kp = tid%8),
+  // B (k row kr = tid/64 + 4q, column pair cp = tid%64)
+  const int kp = tid & 7, cp = tid & 63;
+  int aoff[4];
+  bool aval[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int o = aoff_s[(tid >> 3) + 32 * q];
+    aval[q] = o >= 0;
+    aoff[q] = o >= 0 ? o : 0;
+  }
+  const int gc = col0 + 2 * cp;
+  const int gcl = min(gc, ld - 2);  // clamped: the load stays inside the row
+  const bool bval0 = gc < n, bval1 = gc + 1 < n;
+
+  // Loads go to clamped, always-valid addresses; the zero masks are applied
+  // when the staged values are written to LDS, so the loads stay in flight
+  // across the products of the current chunk.
   float4 ra[4], rb[4];
-  auto load_tile = [&](int kk) {
+  auto load_tile = [&](int kk) {  // kk: chunk offset relative to k0
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int e = tid + q * 256;        // 0..1023
-      const int r = e >> 3, kp = e & 7;   // A: row, k-pair
-      const int gr = row0 + r, gk = kk + 2 * kp;
-      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gr < row_end && gk < k0 + jb) {
-        const c64* src = MODE == 0 ? T + (long long)rat[gr] * ld + gk
-                                   : Li + (long long)(gr - k0) * kLuMaxJB + (gk - k0);
-        if (gk + 1 < k0 + jb) val = *reinterpret_cast<const float4*>(src);
-        else val = make_float4(src->re, src->im, 0.f, 0.f);
-      }
-      ra[q] = val;
-      const int kr = e >> 6, cp = e & 63;  // B: k row, column pair
-      const int gk2 = kk + kr, gc = col0 + 2 * cp;
-      float4 vb = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gk2 < k0 + jb && gc < n) {
-        const c64* src = T + (long long)rat[gk2] * ld + gc;
-        if (gc + 1 < n) vb = *reinterpret_cast<const float4*>(src);
-        else vb = make_float4(src->re, src->im, 0.f, 0.f);
-      }
-      rb[q] = vb;
+      ra[q] = *reinterpret_cast<const float4*>(Asrc + aoff[q] + (MODE == 0 ? k0 : 0) + kk + 2 * kp);
+      rb[q] = *reinterpret_cast<const float4*>(T + boff_s[kk + (tid >> 6) + 4 * q] + gcl);
     }
   };
   auto store_tile = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int e = tid + q * 256;
-      const int r = e >> 3, kp = e & 7;
-      As[buf][2 * kp][2 * r] = ra[q].x;
-      As[buf][2 * kp][2 * r + 1] = ra[q].y;
-      As[buf][2 * kp + 1][2 * r] = ra[q].z;
-      As[buf][2 * kp + 1][2 * r + 1] = ra[q].w;
-      const int kr = e >> 6, cp = e & 63;
-      Bs[buf][kr][0][2 * cp] = rb[q].x;
-      Bs[buf][kr][1][2 * cp] = rb[q].y;
-      Bs[buf][kr][0][2 * cp + 1] = rb[q].z;
-      Bs[buf][kr][1][2 * cp + 1] = rb[q].w;
+      const int r = (tid >> 3) + 32 * q;
+      const bool va = aval[q];
+      As[buf][2 * kp][2 * r] = va ? ra[q].x : 0.f;
+      As[buf][2 * kp][2 * r + 1] = va ? ra[q].y : 0.f;
+      As[buf][2 * kp + 1][2 * r] = va ? ra[q].z : 0.f;
+      As[buf][2 * kp + 1][2 * r + 1] = va ? ra[q].w : 0.f;
+      const int kr = (tid >> 6) + 4 * q;
+      Bs[buf][kr][0][2 * cp] = bval0 ? rb[q].x : 0.f;
+      Bs[buf][kr][1][2 * cp] = bval0 ? rb[q].y : 0.f;
+      Bs[buf][kr][0][2 * cp + 1] = bval1 ? rb[q].z : 0.f;
+      Bs[buf][kr][1][2 * cp + 1] = bval1 ? rb[q].w : 0.f;
     }
   };
 
+  // Accumulators.  acc reg r of block (i, j) holds real row 8(r/4) + 4(l/32)
+  // + r%4 of the 32-row block, i.e. complex row 4(r/4) + 2(l/32) + (r%4)/2
+  // (component r%2), and complex column l%32.  MODE 0 starts from C and
+  // accumulates -L21 U12, so the epilogue only stores; MODE 1 starts from 0.
   floatx16 acc[4][2];
+  if (MODE == 0) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j) {
+        const int gcol = col0 + wcn + j * 32 + (lane & 31);
+        const int gcl2 = min(gcol, ld - 1);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+        for (int r = 0; r < 16; r += 2) {
+          const int lr = wr + i * 16 + 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
+          const int o = aoff_s[lr];
+          const c64 cv = T[(o >= 0 ? o : 0) + gcl2];
+          const bool ok = o >= 0 && gcol < n;
+          acc[i][j][r] = ok ? cv.re : 0.f;
+          acc[i][j][r + 1] = ok ? cv.im : 0.f;
+        }
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  }
 
   // operand lane roles: A row (l%32)/2 with component t=l%2; k-half u=l/32
   const int at = lane & 1, au = lane >> 5, arow = (lane & 31) >> 1;
   const int acomp = at ^ au;                      // 0: re, 1: im
-  const float asign = (at == 0 && au == 1) ? -1.f : 1.f;
+  const float asign = ((at == 0 && au == 1) ? -1.f : 1.f) * (MODE == 0 ? -1.f : 1.f);
   const int bcol = lane & 31, bu = lane >> 5;
 
-  const int nk = (jb + kG32KC - 1) / kG32KC;
-  load_tile(k0);
+  const int nk = jb / kG32KC;
+  load_tile(0);
   store_tile(0);
   __syncthreads();
   for (int kc = 0; kc < nk; ++kc) {
     const int buf = kc & 1;
-    if (kc + 1 < nk) load_tile(k0 + (kc + 1) * kG32KC);
+    if (kc + 1 < nk) load_tile((kc + 1) * kG32KC);
+    // operands of step k+1 are read while the products of step k issue
+    float af[2][4], bf[2][2];
+    auto frag = [&](int k, float (&a)[4], float (&bb)[2]) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = asign * As[buf][k][2 * (wr + i * 16 + arow) + acomp];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bb[j] = Bs[buf][k][bu][wcn + j * 32 + bcol];
+    };
+    frag(0, af[0], bf[0]);
+    __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
 #pragma unroll
     for (int k = 0; k < kG32KC; ++k) {
-      float af[4], bf[2];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) af[i] = asign * As[buf][k][2 * (wr + i * 16 + arow) + acomp];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) bf[j] = Bs[buf][k][bu][wcn + j * 32 + bcol];
+      if (k + 1 < kG32KC) frag(k + 1, af[(k + 1) & 1], bf[(k + 1) & 1]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[k & 1][i], bf[k & 1][j], acc[i][j], 0, 0, 0);
+      // issue order: the next step's LDS reads, then this step's products
+      if (k + 1 < kG32KC) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);  // DS reads
+        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // sign multiplies
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);    // MFMA
     }
     if (kc + 1 < nk) {
       store_tile(buf ^ 1);
@@ -471,27 +513,18 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
     }
   }
 
-  // epilogue: C -= acc.  acc reg r: real row 8(r/4) + 4(l/32) + r%4, col l%32
+  // epilogue: store the block (C - L21 U12 in MODE 0, U12 in MODE 1)
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int gc = col0 + wcn + j * 32 + (lane & 31);
+      const int gcol = col0 + wcn + j * 32 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; r += 2) {
-        const int crow = 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
-        const int gr = row0 + wr + i * 16 + crow;
-        if (gr < row_end && gc < n) {
-          c64* p = T + (long long)rat[gr] * ld + gc;
-          if (MODE == 0) {
-            c64 cv = *p;
-            cv.re -= acc[i][j][r];
-            cv.im -= acc[i][j][r + 1];
-            *p = cv;
-          } else {
-            *p = c64{acc[i][j][r], acc[i][j][r + 1]};
-          }
-        }
+        const int lr = wr + i * 16 + 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
+        const int gr = row0 + lr;
+        if (gr < row_end && gcol < n)
+          T[(MODE == 0 ? aoff_s[lr] : rat[gr] * ld) + gcol] = c64{acc[i][j][r], acc[i][j][r + 1]};
       }
     }
 }
@@ -511,7 +544,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
   const MatDesc d = md[b];
   if (skip != nullptr && skip[d.node]) return;
   const int n = d.n;
-  const int jb = min(jbmax, n - k0);
+  const int jb = min(jbmax, n - k0);  // == jbmax whenever a trailing block exists (a multiple of kG64KC)
   const int s0 = k0 + jb;
   const int mt = n - s0;
   const int tiles_n = (mt + kG64TN - 1) / kG64TN;
@@ -521,79 +554,103 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
   c128* __restrict__ T = Tb + d.offT;
   const int ld = d.ld;
   const int* __restrict__ rat = rowb + d.offRow;
-  const c128* __restrict__ Li = MODE == 1 ? Linv + (long long)b * kLuMaxJB * kLuMaxJB : nullptr;
+  const c128* __restrict__ Asrc = MODE == 1 ? Linv + (long long)b * kLuMaxJB * kLuMaxJB : T;
 
   __shared__ double As[2][kG64KC][2 * kG64TM + 2];
   __shared__ double Bs[2][kG64KC][2][kG64TN + 2];
+  __shared__ int aoff_s[kG64TM];
+  __shared__ int boff_s[kLuMaxJB];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 64, wcn = (wave & 1) * 32;
+  if (tid < kG64TM) {
+    const int gr = row0 + tid;
+    aoff_s[tid] = gr < row_end ? (MODE == 0 ? rat[gr] * ld : (gr - k0) * kLuMaxJB) : -1;
+  }
+  for (int i = tid; i < jb; i += 256) boff_s[i] = rat[k0 + i] * ld;
+  __syncthreads();
 
-  // A tile: 128 rows x 8 k complex (16 B each) -> 1024 elements, 4 per thread
-  // B tile: 8 k x 64 cols complex -> 512 elements, 2 per thread
+  // staging roles: A (row tid/8 + 32q, k tid%8), B (k row tid/64 + 4q, column tid%64)
+  const int kq8 = tid & 7, cb = tid & 63;
+  int aoff[4];
+  bool aval[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int o = aoff_s[(tid >> 3) + 32 * q];
+    aval[q] = o >= 0;
+    aoff[q] = o >= 0 ? o : 0;
+  }
+  const int gcb = col0 + cb;
+  const bool bval = gcb < n;
+  const int gcbl = min(gcb, ld - 1);
+
   double2 ra[4], rb[2];
-  auto load_tile = [&](int kk) {
+  auto load_tile = [&](int kk) {  // kk: chunk offset relative to k0
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + q * 256;
-      const int r = e >> 3, kq = e & 7;
-      const int gr = row0 + r, gk = kk + kq;
-      double2 val = make_double2(0.0, 0.0);
-      if (gr < row_end && gk < k0 + jb)
-        val = *reinterpret_cast<const double2*>(MODE == 0 ? T + (long long)rat[gr] * ld + gk
-                                                          : Li + (long long)(gr - k0) * kLuMaxJB + (gk - k0));
-      ra[q] = val;
-    }
+    for (int q = 0; q < 4; ++q)
+      ra[q] = *reinterpret_cast<const double2*>(Asrc + aoff[q] + (MODE == 0 ? k0 : 0) + kk + kq8);
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int e = tid + q * 256;
-      const int kr = e >> 6, c = e & 63;
-      const int gk = kk + kr, gc = col0 + c;
-      double2 val = make_double2(0.0, 0.0);
-      if (gk < k0 + jb && gc < n) val = *reinterpret_cast<const double2*>(T + (long long)rat[gk] * ld + gc);
-      rb[q] = val;
-    }
+    for (int q = 0; q < 2; ++q)
+      rb[q] = *reinterpret_cast<const double2*>(T + boff_s[kk + (tid >> 6) + 4 * q] + gcbl);
   };
   auto store_tile = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int e = tid + q * 256;
-      const int r = e >> 3, kq = e & 7;
-      As[buf][kq][2 * r] = ra[q].x;
-      As[buf][kq][2 * r + 1] = ra[q].y;
+      const int r = (tid >> 3) + 32 * q;
+      As[buf][kq8][2 * r] = aval[q] ? ra[q].x : 0.0;
+      As[buf][kq8][2 * r + 1] = aval[q] ? ra[q].y : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const int e = tid + q * 256;
-      const int kr = e >> 6, c = e & 63;
-      Bs[buf][kr][0][c] = rb[q].x;
-      Bs[buf][kr][1][c] = rb[q].y;
+      const int kr = (tid >> 6) + 4 * q;
+      Bs[buf][kr][0][cb] = bval ? rb[q].x : 0.0;
+      Bs[buf][kr][1][cb] = bval ? rb[q].y : 0.0;
     }
   };
 
+  // acc reg r of lane l: real row l/16 + 4r -> complex row (l/16)/2 + 2r,
+  // component (l/16)%2; col l%16.  MODE 0 starts from C and accumulates
+  // -L21 U12; MODE 1 starts from 0.
+  const int tcomp = (lane >> 4) & 1, rbase = (lane >> 4) >> 1;
   doublex4 acc[8][2];
+  if (MODE == 0) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j) {
+        const int gc = col0 + wcn + j * 16 + (lane & 15);
+        const int gcl = min(gc, ld - 1);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+        for (int r = 0; r < 4; ++r) {
+          const int o = aoff_s[wr + i * 8 + rbase + 2 * r];
+          const double cv = reinterpret_cast<const double*>(T + (o >= 0 ? o : 0) + gcl)[tcomp];
+          acc[i][j][r] = (o >= 0 && gc < n) ? cv : 0.0;
+        }
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+  }
 
   // f64 16x16x4 operand roles: A real row l%16 -> complex row (l%16)/2, t=l%2;
   // real k l/16 -> complex k (l/16)/2 within the pair, u=(l/16)%2.
   const int at = lane & 1, arow = (lane & 15) >> 1;
   const int kq = lane >> 4, ak = kq >> 1, au = kq & 1;
   const int acomp = at ^ au;
-  const double asign = (at == 0 && au == 1) ? -1.0 : 1.0;
+  const double asign = ((at == 0 && au == 1) ? -1.0 : 1.0) * (MODE == 0 ? -1.0 : 1.0);
   const int bcol = lane & 15;
 
-  const int nk = (jb + kG64KC - 1) / kG64KC;
-  load_tile(k0);
+  const int nk = jb / kG64KC;
+  load_tile(0);
   store_tile(0);
   __syncthreads();
   for (int kc = 0; kc < nk; ++kc) {
     const int buf = kc & 1;
-    if (kc + 1 < nk) load_tile(k0 + (kc + 1) * kG64KC);
+    if (kc + 1 < nk) load_tile((kc + 1) * kG64KC);
 #pragma unroll
     for (int k2 = 0; k2 < kG64KC; k2 += 2) {
       double af[8], bf[2];
@@ -612,9 +669,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
       __syncthreads();
     }
   }
-  // epilogue: acc reg r of lane l: real row l/16 + 4r -> complex row (l/16)/2 + 2r,
-  // component (l/16)%2; col l%16.
-  const int tcomp = (lane >> 4) & 1, rbase = (lane >> 4) >> 1;
+  // epilogue: store-only
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
@@ -622,12 +677,10 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
       const int gc = col0 + wcn + j * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gr = row0 + wr + i * 8 + rbase + 2 * r;
-        if (gr < row_end && gc < n) {
-          double* p = reinterpret_cast<double*>(T + (long long)rat[gr] * ld + gc) + tcomp;
-          if (MODE == 0) *p -= acc[i][j][r];
-          else *p = acc[i][j][r];
-        }
+        const int lr = wr + i * 8 + rbase + 2 * r;
+        const int gr = row0 + lr;
+        if (gr < row_end && gc < n)
+          reinterpret_cast<double*>(T + (MODE == 0 ? aoff_s[lr] : rat[gr] * ld) + gc)[tcomp] = acc[i][j][r];
       }
     }
 }
