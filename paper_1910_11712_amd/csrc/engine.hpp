@@ -76,7 +76,6 @@ struct SolvePlan {
   int lg = 4;       // right-hand columns per group
   int groups = 1;   // column groups per matrix
   int rpt = 1;      // rows per thread of the solve kernel (n <= 512 * rpt)
-  Table diag;       // diagonal-block inversions: 2 * nblk per matrix
 };
 
 struct ProblemTables {
@@ -96,9 +95,6 @@ hipError_t launch_moments(const ProbDesc* pd, const int* prefix, const Table& t,
                           const c128* Y, hipStream_t st);
 hipError_t launch_vnorm(const ProbDesc* pd, int nprob, IrState ir, hipStream_t st);
 
-template <typename P>
-hipError_t diag_inv_run(const SolvePlan& sp, const int* d_prefix, const MatDesc* md, const cx<P>* T,
-                        const int* rows, cx<P>* Dinv, const long long* dinv_off, const int* skip, hipStream_t st);
 template <typename P>
 hipError_t solve_run(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md, const NodeArrays& na,
                      const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off,

@@ -15,8 +15,9 @@
 //                of W columns live in registers (one logical row per thread and
 //                slot), pivots are found by a wave shuffle + LDS reduction,
 //                modulus |Re|+|Im|, ties to the lowest row.
-//                The panel group also inverts its unit lower diagonal block
-//                L11 (FP64, stored in the factor precision).
+//   k_lu_inv_l : inverse of the unit lower block L11 (recursive doubling in
+//                LDS), used for U12 and, block by block, by the solves.
+//   k_lu_inv_u : inverses of the 64 x 64 diagonal blocks of U11 (FP64).
 //   k_lu_gemm<1>: U12 = L11^{-1} A12 on the matrix cores (block-row solve).
 //   k_lu_gemm<0>: A22 -= L21 U12 on the matrix cores.  Complex products use the
 //                real 2x2 embedding [ar -ai; ai ar] built in the operand
@@ -305,43 +306,238 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
 //   X[i][c] = -(L[i][c] + sum_{c<j<i} L[i][j] X[j][c]),
 // two lanes per column (alternate j), one barrier per row.
 // ---------------------------------------------------------------------------
+// Inverses of the panel's diagonal blocks.
+//
+// tri_inv_lds inverts, in place, an m x m triangular block held in LDS (row
+// stride lx, m = 64 or 128) with 256 threads: the 8 x 8 diagonal blocks by
+// substitution (one thread per column), then neighbouring blocks are merged
+// with sizes 8 -> 16 -> ... -> m.  For lower [A 0; B C] the inverse's
+// off-diagonal block is -C^{-1} B A^{-1}; for upper [A B; 0 C] it is
+// -A^{-1} B C^{-1}; both are formed as two products against the already
+// inverted diagonal blocks.  The opposite triangle holds zeros; the diagonal
+// holds 1 (unit lower) or u_ii (upper).
+// ---------------------------------------------------------------------------
+template <typename S>
+__device__ __forceinline__ cx<S> cdiv_s(cx<S> a, cx<S> b) {
+  const c128 q = cdiv(c128{double(a.re), double(a.im)}, c128{double(b.re), double(b.im)});
+  return cx<S>{S(q.re), S(q.im)};
+}
+
+template <typename S, bool UPPER>
+__device__ void tri_inv_lds(cx<S>* X, int lx, int m) {
+  const int tid = threadIdx.x;
+  const cx<S> zero = {S(0), S(0)};
+  {  // 8 x 8 diagonal blocks: thread (block, column c)
+    cx<S> col[8];
+    const int o = (tid >> 3) * 8, c = tid & 7;
+    const bool act = tid < m;
+    if (act) {
+      if (!UPPER) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) col[i] = i == c ? cx<S>{S(1), S(0)} : zero;
+#pragma unroll
+        for (int i = 1; i < 8; ++i) {
+          cx<S> sum = zero;
+#pragma unroll
+          for (int k = 0; k < i; ++k) sum = cmac(sum, X[(o + i) * lx + o + k], col[k]);
+          if (i > c) col[i] = -sum;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) col[i] = zero;
+#pragma unroll
+        for (int i = 7; i >= 0; --i) {
+          cx<S> sum = zero;
+#pragma unroll
+          for (int k = i + 1; k < 8; ++k) sum = cmac(sum, X[(o + i) * lx + o + k], col[k]);
+          const cx<S> rhs = i == c ? cx<S>{S(1) - sum.re, -sum.im} : -sum;
+          const cx<S> x = cdiv_s(rhs, X[(o + i) * lx + o + i]);
+          if (i <= c) col[i] = x;
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (UPPER ? i <= c : i >= c) X[(o + i) * lx + o + c] = col[i];
+    }
+    __syncthreads();
+  }
+  // merges: thread groups of 4 consecutive columns of one row of the
+  // off-diagonal block; at most m*s/8 / 256 = 4 groups per thread
+  for (int s = 8; s < m; s <<= 1) {
+    const int gpb = s * (s >> 2);            // groups per block pair
+    const int ng = (m / (2 * s)) * gpb;
+    cx<S> acc[4][4];
+    // step 1: T = B A^{-1} (lower) or T = B C^{-1} (upper)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int g = tid + 256 * q;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[q][j] = zero;
+      if (g < ng) {
+        const int pr = g / gpb, rem = g - pr * gpb;
+        const int r = rem / (s >> 2), c0 = (rem - r * (s >> 2)) * 4;
+        const int a0 = pr * 2 * s, a1 = a0 + s;
+        if (!UPPER) {
+          for (int k = c0; k < s; ++k) {
+            const cx<S> bv = X[(a1 + r) * lx + a0 + k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[q][j] = cmac(acc[q][j], bv, X[(a0 + k) * lx + a0 + c0 + j]);
+          }
+        } else {
+          for (int k = 0; k < c0 + 4; ++k) {
+            const cx<S> bv = X[(a0 + r) * lx + a1 + k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[q][j] = cmac(acc[q][j], bv, X[(a1 + k) * lx + a1 + c0 + j]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int g = tid + 256 * q;
+      if (g < ng) {
+        const int pr = g / gpb, rem = g - pr * gpb;
+        const int r = rem / (s >> 2), c0 = (rem - r * (s >> 2)) * 4;
+        const int a0 = pr * 2 * s, a1 = a0 + s;
+        cx<S>* dst = UPPER ? X + (a0 + r) * lx + a1 + c0 : X + (a1 + r) * lx + a0 + c0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dst[j] = acc[q][j];
+      }
+    }
+    __syncthreads();
+    // step 2: -C^{-1} T (lower) or -A^{-1} T (upper)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int g = tid + 256 * q;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[q][j] = zero;
+      if (g < ng) {
+        const int pr = g / gpb, rem = g - pr * gpb;
+        const int r = rem / (s >> 2), c0 = (rem - r * (s >> 2)) * 4;
+        const int a0 = pr * 2 * s, a1 = a0 + s;
+        if (!UPPER) {
+          for (int k = 0; k <= r; ++k) {
+            const cx<S> cv = X[(a1 + r) * lx + a1 + k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[q][j] = cmac(acc[q][j], cv, X[(a1 + k) * lx + a0 + c0 + j]);
+          }
+        } else {
+          for (int k = r; k < s; ++k) {
+            const cx<S> av = X[(a0 + r) * lx + a0 + k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[q][j] = cmac(acc[q][j], av, X[(a0 + k) * lx + a1 + c0 + j]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int g = tid + 256 * q;
+      if (g < ng) {
+        const int pr = g / gpb, rem = g - pr * gpb;
+        const int r = rem / (s >> 2), c0 = (rem - r * (s >> 2)) * 4;
+        const int a0 = pr * 2 * s, a1 = a0 + s;
+        cx<S>* dst = UPPER ? X + (a0 + r) * lx + a1 + c0 : X + (a1 + r) * lx + a0 + c0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dst[j] = -acc[q][j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// L part: inverse of the unit lower panel block L11 (jb x jb), in the factor
+// precision.  Writes inv(L11) (when trailing columns follow, for the U12
+// product) and its 64 x 64 diagonal blocks, which are the inverses the
+// triangular solves use (Dinv layout per matrix: [blk][0: L, 1: U][64][64],
+// row-major, identity-padded).
 template <typename P>
-__global__ __launch_bounds__(256) void k_l11_inv(const MatDesc* __restrict__ md, int k0, int jbmax,
-                                                 const cx<P>* __restrict__ Tb, const int* __restrict__ rowb,
-                                                 cx<P>* __restrict__ Linv, const int* __restrict__ skip) {
-  const MatDesc d = md[blockIdx.x];
+__global__ __launch_bounds__(256) void k_lu_inv_l(const MatDesc* __restrict__ md, int k0, int jbmax,
+                                                  const cx<P>* __restrict__ Tb, const int* __restrict__ rowb,
+                                                  cx<P>* __restrict__ Linv, cx<P>* __restrict__ Dinv,
+                                                  const long long* __restrict__ dinv_off,
+                                                  const int* __restrict__ skip) {
+  const int b = blockIdx.x;
+  const MatDesc d = md[b];
   const int n = d.n;
   if (k0 >= n) return;
   if (skip != nullptr && skip[d.node]) return;
   const int jb = min(jbmax, n - k0);
-  if (n - k0 - jb <= 0) return;  // no trailing columns: inverse not needed
+  const int m = jb > kSolveBlkLu ? 2 * kSolveBlkLu : kSolveBlkLu;
+  const int lx = m + 1;
   const cx<P>* __restrict__ T = Tb + d.offT;
   const int ld = d.ld;
   const int* __restrict__ rat = rowb + d.offRow + k0;
   extern __shared__ unsigned char smem_raw[];
-  cx<P>* X = reinterpret_cast<cx<P>*>(smem_raw);  // jb x (jb+1)
-  const int lx = jb + 1;
-  for (int e = threadIdx.x; e < jb * jb; e += 256) {
-    const int i = e / jb, k = e - i * jb;
-    X[i * lx + k] = k < i ? T[(long long)rat[i] * ld + k0 + k] : cx<P>{P(0), P(0)};
+  cx<P>* X = reinterpret_cast<cx<P>*>(smem_raw);  // m x (m+1)
+  for (int e = threadIdx.x; e < m * m; e += 256) {
+    const int i = e / m, k = e - i * m;
+    cx<P> v = {P(i == k ? 1 : 0), P(0)};
+    if (i < jb && k < i) v = T[(long long)rat[i] * ld + k0 + k];
+    X[i * lx + k] = v;
   }
   __syncthreads();
-  const int c = threadIdx.x >> 1, h = threadIdx.x & 1;
-  for (int i = 1; i < jb; ++i) {
-    cx<P> s = {P(0), P(0)};
-    if (c < i) {
-      for (int jj = c + 1 + h; jj < i; jj += 2) s = cmac(s, X[i * lx + jj], X[jj * lx + c]);
+  tri_inv_lds<P, false>(X, lx, m);
+  if (n - k0 - jb > 0) {
+    cx<P>* __restrict__ Li = Linv + (long long)b * kLuMaxJB * kLuMaxJB;
+    for (int e = threadIdx.x; e < jb * jb; e += 256) {
+      const int i = e / jb, k = e - i * jb;
+      Li[(long long)i * kLuMaxJB + k] = X[i * lx + k];
     }
-    s.re += __shfl_xor(s.re, 1, 64);
-    s.im += __shfl_xor(s.im, 1, 64);
-    __syncthreads();  // every lane has read row i
-    if (c < i && h == 0) X[i * lx + c] = -(X[i * lx + c] + s);
-    __syncthreads();
   }
-  cx<P>* __restrict__ Li = Linv + (long long)blockIdx.x * kLuMaxJB * kLuMaxJB;
-  for (int e = threadIdx.x; e < jb * jb; e += 256) {
-    const int i = e / jb, k = e - i * jb;
-    Li[(long long)i * kLuMaxJB + k] = k < i ? X[i * lx + k] : (k == i ? cx<P>{P(1), P(0)} : cx<P>{P(0), P(0)});
+  const int kb = k0 / kSolveBlkLu;
+  for (int q = 0; q * kSolveBlkLu < jb; ++q) {
+    cx<P>* __restrict__ out = Dinv + dinv_off[b] + ((long long)(kb + q) * 2 + 0) * kSolveBlkLu * kSolveBlkLu;
+    for (int e = threadIdx.x; e < kSolveBlkLu * kSolveBlkLu; e += 256) {
+      const int i = e / kSolveBlkLu, k = e - i * kSolveBlkLu;
+      out[e] = X[(q * kSolveBlkLu + i) * lx + q * kSolveBlkLu + k];
+    }
+  }
+}
+
+// U part: inverses of the 64 x 64 diagonal blocks of U11, in FP64, stored in
+// the factor precision.  One group per (matrix, 64-row block of the panel).
+template <typename P>
+__global__ __launch_bounds__(256) void k_lu_inv_u(const MatDesc* __restrict__ md, int k0, int jbmax,
+                                                  const cx<P>* __restrict__ Tb, const int* __restrict__ rowb,
+                                                  cx<P>* __restrict__ Dinv, const long long* __restrict__ dinv_off,
+                                                  const int* __restrict__ skip) {
+  constexpr int B = kSolveBlkLu;
+  const int nbp = jbmax / B;
+  const int b = blockIdx.x / nbp, q = blockIdx.x - b * nbp;
+  const MatDesc d = md[b];
+  const int n = d.n;
+  if (k0 >= n) return;
+  if (skip != nullptr && skip[d.node]) return;
+  const int R0 = k0 + q * B;
+  const int jb = min(jbmax, n - k0);
+  if (q * B >= jb) return;
+  const int nr = min(B, n - R0);
+  const cx<P>* __restrict__ T = Tb + d.offT;
+  const int ld = d.ld;
+  const int* __restrict__ rat = rowb + d.offRow + R0;
+  __shared__ c128 X[B * (B + 1)];
+  for (int e = threadIdx.x; e < B * B; e += 256) {
+    const int i = e / B, k = e - i * B;
+    c128 v = {i == k ? 1.0 : 0.0, 0.0};
+    if (i < nr && k < nr && k >= i) {
+      const cx<P> t = T[(long long)rat[i] * ld + R0 + k];
+      v = c128{double(t.re), double(t.im)};
+    }
+    X[i * (B + 1) + k] = v;
+  }
+  __syncthreads();
+  tri_inv_lds<double, true>(X, B + 1, B);
+  cx<P>* __restrict__ out = Dinv + dinv_off[b] + ((long long)(R0 / B) * 2 + 1) * B * B;
+  for (int e = threadIdx.x; e < B * B; e += 256) {
+    const int i = e / B, k = e - i * B;
+    const c128 v = X[i * (B + 1) + k];
+    out[e] = cx<P>{P(v.re), P(v.im)};
   }
 }
 
@@ -751,9 +947,16 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
 static KernelProf g_prof;
 KernelProf& kernel_prof() { return g_prof; }
 
+// dynamic LDS of k_lu_inv_l: the panel block padded to 64 or 128, row stride +1
+template <typename P>
+static size_t inv_l_lds(int jb) {
+  const int m = jb > kSolveBlkLu ? 2 * kSolveBlkLu : kSolveBlkLu;
+  return (size_t)m * (m + 1) * sizeof(cx<P>);
+}
+
 template <typename P>
 hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* info,
-                  const int* skip, cx<P>* Linv, hipStream_t st) {
+                  const int* skip, cx<P>* Linv, cx<P>* Dinv, const long long* dinv_off, hipStream_t st) {
   hipError_t e;
   hipLaunchKernelGGL(k_lu_init, dim3(plan.nmat), dim3(256), 0, st, d_md, plan.nmat, rows, info);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -762,10 +965,13 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
     const bool more = s.tot_trsm > 0;
     if ((e = launch_panel<P, W>(s.rpt, s.nact, d_md, s.k0, plan.jb, T, rows, info, skip, st)) != hipSuccess)
       return e;
-    if (!more) continue;
-    hipLaunchKernelGGL(k_l11_inv<P>, dim3(s.nact), dim3(256), (size_t)plan.jb * (plan.jb + 1) * sizeof(cx<P>), st,
-                       d_md, s.k0, plan.jb, T, rows, Linv, skip);
+    hipLaunchKernelGGL(k_lu_inv_u<P>, dim3(s.nact * (plan.jb / kSolveBlkLu)), dim3(256), 0, st, d_md, s.k0, plan.jb,
+                       T, rows, Dinv, dinv_off, skip);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lu_inv_l<P>, dim3(s.nact), dim3(256), inv_l_lds<P>(plan.jb), st, d_md, s.k0, plan.jb, T,
+                       rows, Linv, Dinv, dinv_off, skip);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!more) continue;
     if constexpr (sizeof(P) == 4)
       hipLaunchKernelGGL(k_lu_gemm_c64<1>, dim3(xcd_grid(s.tot_trsm)), dim3(256), 0, st, d_md, d_prefix + s.off_trsm,
                          s.nact, s.tot_trsm, s.k0, plan.jb, T, rows, skip, Linv);
@@ -802,16 +1008,16 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
 }
 
 hipError_t lu_configure() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_l11_inv<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)(kLuMaxJB * (kLuMaxJB + 1) * sizeof(c64)));
+  hipError_t e = hipFuncSetAttribute((const void*)k_lu_inv_l<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)inv_l_lds<float>(lu_jb(NEP_PREC_C32_IR64)));
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_l11_inv<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)(64 * 65 * sizeof(c128)));
+  return hipFuncSetAttribute((const void*)k_lu_inv_l<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)inv_l_lds<double>(lu_jb(NEP_PREC_FP64)));
 }
 
 template hipError_t lu_run<float>(const LuPlan&, const MatDesc*, const int*, c64*, int*, int*, const int*, c64*,
-                                  hipStream_t);
+                                  c64*, const long long*, hipStream_t);
 template hipError_t lu_run<double>(const LuPlan&, const MatDesc*, const int*, c128*, int*, int*, const int*, c128*,
-                                   hipStream_t);
+                                   c128*, const long long*, hipStream_t);
 
 }  // namespace nep

@@ -8,6 +8,7 @@
 namespace nep {
 
 constexpr int kLuMaxJB = 128;
+constexpr int kSolveBlkLu = 64;  // diagonal-block size of the stored inverses (the solve's block)
 
 // Launch plan of a (possibly ragged) batch: matrices sorted by n, descending.
 struct LuPlan {
@@ -40,8 +41,10 @@ int lu_jb(int prec);
 hipError_t lu_configure();
 
 // Linv: workspace of nact * kLuMaxJB^2 elements (inverses of the L11 blocks).
+// Dinv/dinv_off: per matrix, the inverses of the 64 x 64 diagonal blocks of L
+// and U ([blk][0: L, 1: U][64][64]), written as the panels complete.
 template <typename P>
 hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* info,
-                  const int* skip, cx<P>* Linv, hipStream_t st);
+                  const int* skip, cx<P>* Linv, cx<P>* Dinv, const long long* dinv_off, hipStream_t st);
 
 }  // namespace nep

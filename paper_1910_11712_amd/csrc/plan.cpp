@@ -9,6 +9,8 @@
 
 namespace nep {
 
+static_assert(kSolveBlk == kSolveBlkLu, "the LU writes the solve's diagonal-block inverses");
+
 // --------------------------------------------------------------------------
 static thread_local Arena* tls_arena = nullptr;
 
@@ -360,10 +362,9 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
   NEP_HIP(launch_vnorm(pd, nprob, ir_, st));
   NEP_HIP(launch_coef(pd, na_, nnodes, ir_, st));
   NEP_HIP(launch_assemble<P>(pd, pre, pt_.assemble, na_, T, nullptr, st));
-  NEP_HIP(lu_run<P>(lu_, md, dlu_prefix_.as<int>(), T, rows, info, nullptr, dlinv_.as<cx<P>>(), st));
   cx<P>* Dinv = ddinv_.as<cx<P>>();
   const long long* doff = ddinv_off_.as<long long>();
-  NEP_HIP(diag_inv_run<P>(sp_, pre, md, T, rows, Dinv, doff, nullptr, st));
+  NEP_HIP(lu_run<P>(lu_, md, dlu_prefix_.as<int>(), T, rows, info, nullptr, dlinv_.as<cx<P>>(), Dinv, doff, st));
   NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, nullptr, Y, false, nullptr, ir_, st));
   sweeps_run_ = 0;
   if (opt.max_refine > 0) {
@@ -422,11 +423,10 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
       for (int j = 0; j < opt.N; ++j) fallback_count_[p] += conv[hpd_[p].node0 + j] ? 0 : 1;
   }
   NEP_HIP(launch_assemble<double>(pd, pre, pt_.assemble, na_, T, skip, st));
-  NEP_HIP(lu_run<double>(lu64_, md, dlu64_prefix_.as<int>(), T, drows_.as<int>(), dinfo_.as<int>(), skip,
-                         dlinv64_.as<c128>(), st));
   c128* Dinv = ddinv64_.as<c128>();
   const long long* doff = ddinv_off_.as<long long>();
-  NEP_HIP(diag_inv_run<double>(sp_, pre, md, T, drows_.as<int>(), Dinv, doff, skip, st));
+  NEP_HIP(lu_run<double>(lu64_, md, dlu64_prefix_.as<int>(), T, drows_.as<int>(), dinfo_.as<int>(), skip,
+                         dlinv64_.as<c128>(), Dinv, doff, st));
   NEP_HIP(solve_run<double>(sp_, pd, md, na_, T, drows_.as<int>(), Dinv, doff, nullptr, dY_.as<c128>(), false,
                             skip, ir_, st));
   // check the residual of the re-solved nodes once

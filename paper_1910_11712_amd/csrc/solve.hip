@@ -2,93 +2,19 @@
 // with P T = L U (P through the row map), B the probe block V or a
 // refinement residual R.
 //
-//   k_diag_inv : after each factorization, the 64 x 64 diagonal blocks of L
-//                (unit lower) and U are inverted once, in FP64, and stored in
-//                the factor precision.  One group per block; one wave per
-//                column of the inverse with the rows spread over the lanes.
-//   k_trsv     : one launch per solve.  A group owns one node and a group of
-//                Lg right-hand columns and runs forward then backward
-//                substitution over 64-row blocks: each block first gathers the
-//                products of the finished part (the four waves split the
-//                inner dimension, then reduce through LDS), then multiplies by
-//                the stored inverse of its diagonal block.  The right-hand
-//                side is gathered through the row map on the fly; the result
-//                is stored to (or, for a correction, added to) Y in FP64,
-//                together with the column maxima of |Y| for the refinement test.
+// The LU writes, as its panels complete, the inverses of the 64 x 64 diagonal
+// blocks of L (unit lower) and U.  k_trsv runs one launch per solve: a group
+// owns one node and a group of Lg right-hand columns and runs forward then
+// backward substitution over 64-row blocks (right-looking, accumulators in
+// registers; see the kernel).  The right-hand side is gathered through the
+// row map; the result is stored to (or, for a correction, added to) Y in
+// FP64, with the column maxima of |Y| for the refinement test.
 #include "engine.hpp"
 
 namespace nep {
 
 constexpr int kTrsvThreads = 512;
-constexpr int kInvBlk = kSolveBlk;  // 64
 
-// ---------------------------------------------------------------------------
-// Diagonal-block inverses.  Dinv layout per matrix: [blk][which][64][64]
-// (which 0: L^{-1}, 1: U^{-1}), row-major, padded with the identity.
-// ---------------------------------------------------------------------------
-template <typename P>
-__global__ __launch_bounds__(256) void k_diag_inv(const MatDesc* __restrict__ md, const int* __restrict__ prefix,
-                                                  int cnt, int total, const cx<P>* __restrict__ Tb,
-                                                  const int* __restrict__ rows, cx<P>* __restrict__ Dinv,
-                                                  const long long* __restrict__ dinv_off,
-                                                  const int* __restrict__ skip) {
-  const int v = xcd_remap(blockIdx.x, gridDim.x, total);
-  if (v < 0) return;
-  const int b = find_slot(prefix, cnt, v);
-  const int t = v - prefix[b];
-  const MatDesc d = md[b];
-  if (skip != nullptr && skip[d.node]) return;
-  const int blk = t >> 1, which = t & 1;
-  const int n = d.n, ld = d.ld;
-  const int R0 = blk * kInvBlk, nr = min(kInvBlk, n - R0);
-  const cx<P>* __restrict__ T = Tb + d.offT;
-  const int* __restrict__ rat = rows + d.offRow;
-  __shared__ c128 A[kInvBlk][kInvBlk + 1];
-  for (int e = threadIdx.x; e < kInvBlk * kInvBlk; e += 256) {
-    const int i = e / kInvBlk, k = e - i * kInvBlk;
-    c128 val = {0.0, 0.0};
-    if (i < nr && k < nr) {
-      const bool keep = which == 0 ? (k < i) : (k >= i);
-      if (keep) {
-        const cx<P> x = T[(long long)rat[R0 + i] * ld + R0 + k];
-        val = c128{double(x.re), double(x.im)};
-      }
-    } else if (which == 1 && i == k) {
-      val = c128{1.0, 0.0};  // identity padding of U
-    }
-    A[i][k] = val;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  cx<P>* __restrict__ out = Dinv + dinv_off[b] + ((long long)blk * 2 + which) * kInvBlk * kInvBlk;
-  for (int c = wave; c < kInvBlk; c += 4) {
-    c128 x = {lane == c ? 1.0 : 0.0, 0.0};
-    if (which == 0) {
-      for (int s = c; s < kInvBlk; ++s) {
-        c128 xs;
-        xs.re = __shfl(x.re, s, 64);
-        xs.im = __shfl(x.im, s, 64);
-        if (lane > s) x = fms(x, A[lane][s], xs);
-      }
-    } else {
-      for (int s = c; s >= 0; --s) {
-        if (lane == s) x = cdiv(x, A[s][s]);
-        c128 xs;
-        xs.re = __shfl(x.re, s, 64);
-        xs.im = __shfl(x.im, s, 64);
-        if (lane < s) x = fms(x, A[lane][s], xs);
-      }
-    }
-    out[lane * kInvBlk + c] = cx<P>{P(x.re), P(x.im)};
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Fused forward + backward substitution.
-// The finished part of each 64-row block is streamed through LDS in chunks
-// of SCH columns (coalesced loads, double-buffered so the next chunk is in
-// flight while the current one is multiplied); thread (row, quarter) keeps
-// LG/4 right-hand columns.
 // ---------------------------------------------------------------------------
 // Right-looking substitution with the accumulators in registers: thread t
 // owns the logical rows t, t+512, ...  For each 64-row block (in order for
@@ -270,15 +196,6 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
 }
 
 // ---------------------------------------------------------------------------
-template <typename P>
-hipError_t diag_inv_run(const SolvePlan& sp, const int* d_prefix, const MatDesc* md, const cx<P>* T,
-                        const int* rows, cx<P>* Dinv, const long long* dinv_off, const int* skip, hipStream_t st) {
-  const Table& t = sp.diag;
-  if (t.total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_diag_inv<P>, dim3(xcd_grid(t.total)), dim3(256), 0, st, md, d_prefix + t.off, t.cnt, t.total,
-                     T, rows, Dinv, dinv_off, skip);
-  return hipGetLastError();
-}
 
 template <typename P, int LG>
 static void launch_trsv(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md, const NodeArrays& na,
@@ -311,10 +228,6 @@ hipError_t solve_run(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md,
   return hipGetLastError();
 }
 
-template hipError_t diag_inv_run<float>(const SolvePlan&, const int*, const MatDesc*, const c64*, const int*, c64*,
-                                        const long long*, const int*, hipStream_t);
-template hipError_t diag_inv_run<double>(const SolvePlan&, const int*, const MatDesc*, const c128*, const int*,
-                                         c128*, const long long*, const int*, hipStream_t);
 template hipError_t solve_run<float>(const SolvePlan&, const ProbDesc*, const MatDesc*, const NodeArrays&, const c64*,
                                      const int*, const c64*, const long long*, const c128*, c128*, bool,
                                      const int*, IrState, hipStream_t);
@@ -333,7 +246,7 @@ static int pick_lg(int nmat, int L) {
   return lg;
 }
 
-void SolvePlan_build(SolvePlan& sp, std::vector<int>& buf, const std::vector<MatDesc>& sorted, int L,
+void SolvePlan_build(SolvePlan& sp, std::vector<int>& /*buf*/, const std::vector<MatDesc>& sorted, int L,
                      std::vector<long long>& dinv_off, long long& dinv_elems) {
   sp.nmat = (int)sorted.size();
   const int nmax = sorted.empty() ? 0 : sorted[0].n;
@@ -342,17 +255,14 @@ void SolvePlan_build(SolvePlan& sp, std::vector<int>& buf, const std::vector<Mat
   // accumulators live in registers: at most 32 complex values per thread
   while (sp.lg > 4 && sp.rpt * sp.lg > 32) sp.lg >>= 1;
   sp.groups = ceil_div(L, sp.lg);
-  std::vector<int> cnt;
   dinv_off.clear();
   long long off = 0;
   for (const auto& m : sorted) {
     const int nb = ceil_div(m.n, kSolveBlk);
-    cnt.push_back(2 * nb);
     dinv_off.push_back(off);
     off += (long long)nb * 2 * kSolveBlk * kSolveBlk;
   }
   dinv_elems = off;
-  build_prefix(buf, sp.diag, cnt);
 }
 
 hipError_t solve_configure() { return hipSuccess; }
