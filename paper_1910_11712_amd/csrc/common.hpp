@@ -49,6 +49,13 @@ template <typename P>
 __host__ __device__ __forceinline__ cx<P> cmac(cx<P> acc, cx<P> a, cx<P> b) {
   return {pfma(a.re, b.re, pfma(-a.im, b.im, acc.re)), pfma(a.re, b.im, pfma(a.im, b.re, acc.im))};
 }
+// c ? a : b on values, component by component.  (A conditional between two
+// complex lvalues would select their addresses, which keeps register arrays
+// from being promoted to registers.)
+template <typename P>
+__host__ __device__ __forceinline__ cx<P> csel(bool c, cx<P> a, cx<P> b) {
+  return {c ? a.re : b.re, c ? a.im : b.im};
+}
 template <typename P>
 __host__ __device__ __forceinline__ P abs1(cx<P> a) {  // |Re| + |Im|
   return (a.re < 0 ? -a.re : a.re) + (a.im < 0 ? -a.im : a.im);

@@ -56,6 +56,42 @@ __global__ void k_lu_init(const MatDesc* __restrict__ md, int nmat, int* __restr
 template <typename P>
 __device__ __forceinline__ P shfl_xor_p(P v, int m) { return __shfl_xor(v, m, 64); }
 
+// Pivot key of a candidate: the bits of its modulus (non-negative FP32, so
+// they order like the values) above the complement of its row, so the
+// largest key has the largest modulus and, among equal moduli, the lowest row.
+__device__ __forceinline__ unsigned long long pivot_key(float v, int row) {
+  return ((unsigned long long)__float_as_uint(v) << 32) | (0xffffffffu - (unsigned)row);
+}
+__device__ __forceinline__ int key_row(unsigned long long k) { return (int)(0xffffffffu - (unsigned)k); }
+
+// Maximum of a 64-bit key over the wave with DPP row operations (quad
+// swaps, half-row and row mirrors, then the row broadcasts that carry rows
+// 0-2 into row 3); lane 63 holds the result, which is returned uniform.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
+  int hi = (int)(k >> 32), lo = (int)(unsigned)k;
+  auto step = [&](int oh, int ol) {
+    const unsigned uh = (unsigned)oh, ul = (unsigned)ol, ch = (unsigned)hi, cl = (unsigned)lo;
+    const bool t = uh > ch || (uh == ch && ul > cl);
+    hi = t ? oh : hi;
+    lo = t ? ol : lo;
+  };
+  step(__builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false),   // quad_perm [1,0,3,2]
+       __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false));
+  step(__builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false),   // quad_perm [2,3,0,1]
+       __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false));
+  step(__builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false),  // row_half_mirror
+       __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false));
+  step(__builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false),  // row_mirror
+       __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false));
+  step(__builtin_amdgcn_update_dpp(0, hi, 0x142, 0xA, 0xF, false),  // row_bcast15 -> rows 1, 3
+       __builtin_amdgcn_update_dpp(0, lo, 0x142, 0xA, 0xF, false));
+  step(__builtin_amdgcn_update_dpp(0, hi, 0x143, 0xC, 0xF, false),  // row_bcast31 -> rows 2, 3
+       __builtin_amdgcn_update_dpp(0, lo, 0x143, 0xC, 0xF, false));
+  const unsigned h = (unsigned)__builtin_amdgcn_readlane(hi, 63);
+  const unsigned l = (unsigned)__builtin_amdgcn_readlane(lo, 63);
+  return ((unsigned long long)h << 32) | l;
+}
+
 template <typename P, int W, int RPT>
 __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __restrict__ md, int k0, int jbmax,
                                                            cx<P>* __restrict__ Tb, int* __restrict__ rowb,
@@ -73,11 +109,12 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
   __shared__ int rat[kMaxPanelRows];
   __shared__ P redv[2][kPanelThreads / 64];
   __shared__ int redi[2][kPanelThreads / 64];
+  __shared__ unsigned long long redk[2][kPanelThreads / 64];
   __shared__ cx<P> xbuf[2][2][W];
   __shared__ cx<P> wrow[2][kPanelThreads / 64][W];
   __shared__ cx<P> Ltop[W][W];
   __shared__ cx<P> Utop[W][kLuMaxJB];
-  __shared__ cx<P> Lc[kPanelThreads][W];
+  __shared__ cx<P> Lc[kPanelThreads][W + 1];  // +1: rows in distinct banks
   __shared__ int zero_pivot;
 
   const int tid = threadIdx.x;
@@ -108,81 +145,113 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
     for (int w = 0; w < W; ++w) {
       if (w < wc) {
         const int c = c0 + w;
-        // ---- pivot search: max |Re|+|Im| over logical rows >= c, lowest row on ties
+        // ---- pivot search: max |Re|+|Im| over logical rows >= c, lowest row on
+        // ties.  Each thread also keeps a copy of its best row, so publishing
+        // the winner needs no indexing of the leaf by a run-time slot.
         P bv = P(-1);
         int bi = INT_MAX;
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-          const int r = c0 + tid + i * kPanelThreads;
-          const P v = (r >= c && r < n) ? abs1(a[i][w]) : P(-1);
-          const bool take = v > bv;
-          bv = take ? v : bv;
-          bi = take ? r : bi;
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-          const P ov = shfl_xor_p(bv, off);
-          const int oi = __shfl_xor(bi, off, 64);
-          const bool take = ov > bv || (ov == bv && oi < bi);
-          bv = take ? ov : bv;
-          bi = take ? oi : bi;
-        }
-        // one barrier per column: every wave publishes its candidate value,
-        // index and row; the owner of row c publishes row c
-        const int oc = (c - c0) % kPanelThreads, ic = (c - c0) / kPanelThreads;
-        if (lane == 0) { redv[par][wave] = bv; redi[par][wave] = bi; }
-        if (bi != INT_MAX && tid == (bi - c0) % kPanelThreads) {
-          const int ib = (bi - c0) / kPanelThreads;
-#pragma unroll
-          for (int i = 0; i < RPT; ++i)
-            if (i == ib) {
-#pragma unroll
-              for (int v = 0; v < W; ++v) wrow[par][wave][v] = a[i][v];
-            }
-        }
-        if (tid == oc) {
-#pragma unroll
-          for (int i = 0; i < RPT; ++i)
-            if (i == ic) {
-#pragma unroll
-              for (int v = 0; v < W; ++v) xbuf[par][1][v] = a[i][v];
-            }
-        }
-        __syncthreads();
-        bv = redv[par][0];
-        bi = redi[par][0];
         int wq = 0;
+        cx<P> brow[W];
 #pragma unroll
-        for (int q = 1; q < kPanelThreads / 64; ++q) {
-          const P ov = redv[par][q];
-          const int oi = redi[par][q];
-          const bool take = ov > bv || (ov == bv && oi < bi);
-          bv = take ? ov : bv;
-          bi = take ? oi : bi;
-          wq = take ? q : wq;
+        for (int v = 0; v < W; ++v) brow[v] = a[0][v];
+        if constexpr (sizeof(P) == 4) {
+          // complex FP32: one 64-bit key per candidate, (bits of |.|, ~row);
+          // the largest key is the pivot.  Wave maximum by DPP (no LDS
+          // permutes), one key per wave through LDS.
+          unsigned long long key = 0;
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) {
+            const int r = c0 + tid + i * kPanelThreads;
+            const unsigned long long ki =
+                (r >= c && r < n) ? pivot_key(abs1(a[i][w]), r) : 0ull;
+            const bool take = ki > key;
+            key = take ? ki : key;
+            if (i > 0) {
+#pragma unroll
+              for (int u = 0; u < W; ++u) brow[u] = csel(take, a[i][u], brow[u]);
+            }
+          }
+          const unsigned long long wkey = wave_max_u64(key);
+          const int wrow_r = key_row(wkey);
+          if (lane == 0) redk[par][wave] = wkey;
+          if (wkey != 0ull && tid == (wrow_r - c0) % kPanelThreads) {
+#pragma unroll
+            for (int v = 0; v < W; ++v) wrow[par][wave][v] = brow[v];
+          }
+          if (tid == w) {
+#pragma unroll
+            for (int v = 0; v < W; ++v) xbuf[par][1][v] = a[0][v];
+          }
+          __syncthreads();
+          unsigned long long best = redk[par][0];
+#pragma unroll
+          for (int q = 1; q < kPanelThreads / 64; ++q) {
+            const unsigned long long o = redk[par][q];
+            const bool take = o > best;
+            best = take ? o : best;
+            wq = take ? q : wq;
+          }
+          bi = key_row(best);
+          bv = __uint_as_float((unsigned)(best >> 32));
+        } else {
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) {
+            const int r = c0 + tid + i * kPanelThreads;
+            const P v = (r >= c && r < n) ? abs1(a[i][w]) : P(-1);
+            const bool take = v > bv;
+            bv = take ? v : bv;
+            bi = take ? r : bi;
+            if (i > 0) {
+#pragma unroll
+              for (int u = 0; u < W; ++u) brow[u] = csel(take, a[i][u], brow[u]);
+            }
+          }
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1) {
+            const P ov = shfl_xor_p(bv, off);
+            const int oi = __shfl_xor(bi, off, 64);
+            const bool take = ov > bv || (ov == bv && oi < bi);
+            bv = take ? ov : bv;
+            bi = take ? oi : bi;
+          }
+          // one barrier per column: every wave publishes its candidate value,
+          // index and row; the owner of row c (thread c - c0, slot 0)
+          // publishes row c
+          if (lane == 0) { redv[par][wave] = bv; redi[par][wave] = bi; }
+          if (bi != INT_MAX && tid == (bi - c0) % kPanelThreads) {
+#pragma unroll
+            for (int v = 0; v < W; ++v) wrow[par][wave][v] = brow[v];
+          }
+          if (tid == w) {
+#pragma unroll
+            for (int v = 0; v < W; ++v) xbuf[par][1][v] = a[0][v];
+          }
+          __syncthreads();
+          bv = redv[par][0];
+          bi = redi[par][0];
+#pragma unroll
+          for (int q = 1; q < kPanelThreads / 64; ++q) {
+            const P ov = redv[par][q];
+            const int oi = redi[par][q];
+            const bool take = ov > bv || (ov == bv && oi < bi);
+            bv = take ? ov : bv;
+            bi = take ? oi : bi;
+            wq = take ? q : wq;
+          }
         }
         const int p = bi;
-        const int op = (p - c0) % kPanelThreads, ip = (p - c0) / kPanelThreads;
-        cx<P> prow[W];
-#pragma unroll
-        for (int v = 0; v < W; ++v) prow[v] = wrow[par][wq][v];
+        const cx<P>* prow = wrow[par][wq];  // pivot row (LDS, read where used)
         // ---- exchange logical rows c and p (registers only; row_at records it)
-        if (p != c) {
-          if (tid == oc) {
+        if (p != c) {  // uniform
+          if (tid == w) {
 #pragma unroll
-            for (int i = 0; i < RPT; ++i)
-              if (i == ic) {
-#pragma unroll
-                for (int v = 0; v < W; ++v) a[i][v] = prow[v];
-              }
+            for (int v = 0; v < W; ++v) a[0][v] = prow[v];
           }
-          if (tid == op) {
 #pragma unroll
-            for (int i = 0; i < RPT; ++i)
-              if (i == ip) {
+          for (int i = 0; i < RPT; ++i) {
+            const bool mine = c0 + tid + i * kPanelThreads == p;
 #pragma unroll
-                for (int v = 0; v < W; ++v) a[i][v] = xbuf[par][1][v];
-              }
+            for (int v = 0; v < W; ++v) a[i][v] = csel(mine, xbuf[par][1][v], a[i][v]);
           }
         }
         if (tid == 0) {
@@ -198,8 +267,8 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
           const int r = c0 + tid + i * kPanelThreads;
           const bool below = r > c && r < n;
           const cx<P> l = a[i][w] * inv;
-          const cx<P> lm = below ? l : cx<P>{P(0), P(0)};
-          a[i][w] = below ? l : a[i][w];
+          const cx<P> lm = csel(below, l, cx<P>{P(0), P(0)});
+          a[i][w] = csel(below, l, a[i][w]);
 #pragma unroll
           for (int v = w + 1; v < W; ++v) a[i][v] = fms(a[i][v], lm, prow[v]);
         }
@@ -229,7 +298,9 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
         for (int w = 0; w < W; ++w) Ltop[tid][w] = a[0][w];
       }
       __syncthreads();
-      for (int j = tid; j < nr; j += kPanelThreads) {
+      static_assert(kLuMaxJB <= kPanelThreads, "one thread per right-hand column of the panel");
+      if (tid < nr) {  // nr < jb <= kLuMaxJB: one column per thread
+        const int j = tid;
         cx<P> x[W];
 #pragma unroll
         for (int w = 0; w < W; ++w)
@@ -246,52 +317,143 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
       }
       __syncthreads();
       // rows >= rc0: A[r][right] -= L[r][leaf] U[leaf][right], 512 rows at a
-      // time; the leaf values go through LDS so that each wave updates whole
-      // contiguous row segments (lanes along the columns).
+      // time, the chunk's L through LDS.
+      if constexpr (sizeof(P) == 4) {
+        // Complex FP32: on the matrix cores.  A wave takes 16 x 32 complex
+        // blocks of the right part; C is loaded into the accumulators, the
+        // leaf's W complex k run as W v_mfma_f32_32x32x2f32 on the real 2x2
+        // embedding (A operand negated, so the sum is C - L U), and the block
+        // is stored back.
+        constexpr int RB = 16, CB = 32;
+        const int ncb = (nr + CB - 1) / CB;
+        const int at = lane & 1, au = lane >> 5, arow = (lane & 31) >> 1;
+        const int acomp = at ^ au;
+        const float asign = (at == 0 && au == 1) ? 1.f : -1.f;
+        const int gcol = rc0 + (lane & 31);
+        for (int i = 0; i < RPT; ++i) {
+          const int rbase = c0 + i * kPanelThreads;
+          if (rbase >= n) continue;  // uniform
+          {
+            // the chunk's L rows, read back from the leaf this thread wrote
+            const int r = rbase + tid;
+            const bool live = r >= rc0 && r < n;
+            const cx<P>* src = T + (long long)rat[(live ? r : rc0) - k0] * ld + c0;
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int rbase = c0 + i * kPanelThreads;
-        if (rbase >= n) break;
-#pragma unroll
-        for (int w = 0; w < W; ++w) Lc[tid][w] = a[i][w];
-        __syncthreads();
-        const int rlo = max(rbase, rc0), rhi = min(n, rbase + kPanelThreads);
-        // each wave takes kRows rows at a time so that their loads are in
-        // flight together; full leaves and full row batches run branch-free
-        constexpr int kRows = 8;
-        for (int r0 = rlo + wave * kRows; r0 < rhi; r0 += (kPanelThreads / 64) * kRows) {
-          const int nrow = min(kRows, rhi - r0);
-          for (int j = lane; j < nr; j += 64) {
-            long long off[kRows];
-            cx<P> acc[kRows];
-#pragma unroll
-            for (int u = 0; u < kRows; ++u) {
-              const int r = r0 + min(u, nrow - 1);
-              off[u] = (long long)rat[r - k0] * ld + rc0 + j;
+            for (int w = 0; w < W; ++w) {
+              const cx<P> v = src[w < wc ? w : 0];
+              Lc[tid][w] = (live && w < wc) ? v : cx<P>{P(0), P(0)};
             }
-#pragma unroll
-            for (int u = 0; u < kRows; ++u) acc[u] = T[off[u]];
-            if (wc == W) {
-#pragma unroll
-              for (int u = 0; u < kRows; ++u) {
-                const int lr = r0 + min(u, nrow - 1) - rbase;
-#pragma unroll
-                for (int w = 0; w < W; ++w) acc[u] = fms(acc[u], Lc[lr][w], Utop[w][j]);
-              }
-            } else {
-#pragma unroll
-              for (int u = 0; u < kRows; ++u) {
-                const int lr = r0 + min(u, nrow - 1) - rbase;
-                for (int w = 0; w < wc; ++w) acc[u] = fms(acc[u], Lc[lr][w], Utop[w][j]);
-              }
-            }
-            // duplicated tail rows compute identical values, so storing them
-            // twice is harmless
-#pragma unroll
-            for (int u = kRows - 1; u >= 0; --u) T[off[u]] = acc[u];
           }
+          __syncthreads();
+          const int rb_lo = max(0, rc0 - rbase) / RB;
+          const int rb_hi = (min(kPanelThreads, n - rbase) + RB - 1) / RB;
+          // a wave takes a 16-row block across every column block (<= 4): all
+          // its C loads are issued before the products
+          for (int rb = rb_lo + wave; rb < rb_hi; rb += kPanelThreads / 64) {
+            floatx16 acc[kLuMaxJB / CB];
+            int roff[8];
+            bool rok[8];
+#pragma unroll
+            for (int e = 0; e < 16; e += 2) {
+              const int r = rbase + RB * rb + 4 * (e >> 2) + 2 * (lane >> 5) + ((e & 3) >> 1);
+              rok[e >> 1] = r >= rc0 && r < n;
+              roff[e >> 1] = rat[(rok[e >> 1] ? r : rc0) - k0] * ld;
+            }
+#pragma unroll
+            for (int cb = 0; cb < kLuMaxJB / CB; ++cb) {
+              if (cb < ncb) {  // uniform
+                const int col = gcol + CB * cb;
+                const bool cok = col < k0 + jb;
+                const int cc = cok ? col : rc0;
+#pragma unroll
+                for (int e = 0; e < 16; e += 2) {
+                  const cx<P> cv = T[roff[e >> 1] + cc];
+                  const bool ok = cok && rok[e >> 1];
+                  acc[cb][e] = ok ? cv.re : 0.f;
+                  acc[cb][e + 1] = ok ? cv.im : 0.f;
+                }
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+              const cx<P> lv = Lc[RB * rb + arow][k];
+              const float av = asign * (acomp ? lv.im : lv.re);
+#pragma unroll
+              for (int cb = 0; cb < kLuMaxJB / CB; ++cb) {
+                if (cb < ncb) {
+                  const cx<P> uv = Utop[k][CB * cb + (lane & 31)];
+                  const float bv = au ? uv.im : uv.re;
+                  acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[cb], 0, 0, 0);
+                }
+              }
+            }
+#pragma unroll
+            for (int cb = 0; cb < kLuMaxJB / CB; ++cb) {
+              if (cb < ncb) {
+                const int col = gcol + CB * cb;
+                if (col < k0 + jb) {
+#pragma unroll
+                  for (int e = 0; e < 16; e += 2)
+                    if (rok[e >> 1]) T[roff[e >> 1] + col] = cx<P>{acc[cb][e], acc[cb][e + 1]};
+                }
+              }
+            }
+          }
+          __syncthreads();
         }
-        __syncthreads();
+      } else {
+        for (int i = 0; i < RPT; ++i) {
+          const int rbase = c0 + i * kPanelThreads;
+          if (rbase >= n) continue;  // uniform
+          {
+            const int r = rbase + tid;
+            const bool live = r < n;
+            const cx<P>* src = T + (long long)rat[(live ? r : c0) - k0] * ld + c0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+              const cx<P> v = src[w < wc ? w : 0];
+              Lc[tid][w] = (live && w < wc) ? v : cx<P>{P(0), P(0)};
+            }
+          }
+          __syncthreads();
+          const int rlo = max(rbase, rc0), rhi = min(n, rbase + kPanelThreads);
+          // each wave takes kRows rows at a time so that their loads are in
+          // flight together; full leaves and full row batches run branch-free
+          constexpr int kRows = 8;
+          for (int r0 = rlo + wave * kRows; r0 < rhi; r0 += (kPanelThreads / 64) * kRows) {
+            const int nrow = min(kRows, rhi - r0);
+            for (int j = lane; j < nr; j += 64) {
+              long long off[kRows];
+              cx<P> acc[kRows];
+#pragma unroll
+              for (int u = 0; u < kRows; ++u) {
+                const int r = r0 + min(u, nrow - 1);
+                off[u] = (long long)rat[r - k0] * ld + rc0 + j;
+              }
+#pragma unroll
+              for (int u = 0; u < kRows; ++u) acc[u] = T[off[u]];
+              if (wc == W) {
+#pragma unroll
+                for (int u = 0; u < kRows; ++u) {
+                  const int lr = r0 + min(u, nrow - 1) - rbase;
+#pragma unroll
+                  for (int w = 0; w < W; ++w) acc[u] = fms(acc[u], Lc[lr][w], Utop[w][j]);
+                }
+              } else {
+#pragma unroll
+                for (int u = 0; u < kRows; ++u) {
+                  const int lr = r0 + min(u, nrow - 1) - rbase;
+                  for (int w = 0; w < wc; ++w) acc[u] = fms(acc[u], Lc[lr][w], Utop[w][j]);
+                }
+              }
+              // duplicated tail rows compute identical values, so storing them
+              // twice is harmless
+#pragma unroll
+              for (int u = kRows - 1; u >= 0; --u) T[off[u]] = acc[u];
+            }
+          }
+          __syncthreads();
+        }
       }
     }
   }
@@ -299,12 +461,6 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
   if (tid == 0 && zero_pivot < n) atomicMin(&info[d.node], zero_pivot);
 }
 
-// ---------------------------------------------------------------------------
-// Inverse of the unit lower diagonal block L11 of the current panel, for the
-// block-row solve U12 = L11^{-1} A12 on the matrix cores.  L11 is held in
-// LDS and inverted in place row by row: for i > c,
-//   X[i][c] = -(L[i][c] + sum_{c<j<i} L[i][j] X[j][c]),
-// two lanes per column (alternate j), one barrier per row.
 // ---------------------------------------------------------------------------
 // Inverses of the panel's diagonal blocks.
 //
@@ -554,7 +710,8 @@ template <int MODE>
 __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restrict__ md, const int* __restrict__ prefix,
                                                      int nact, int total, int k0, int jbmax, c64* __restrict__ Tb,
                                                      const int* __restrict__ rowb, const int* __restrict__ skip,
-                                                     const c64* __restrict__ Linv) {
+                                                     const c64* __restrict__ Linv, const int* __restrict__ rowa,
+                                                     int tn0, int ntn) {
   const int v = xcd_remap(blockIdx.x, gridDim.x, total);
   if (v < 0) return;
   const int b = find_slot(prefix, nact, v);
@@ -565,13 +722,15 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
   const int jb = min(jbmax, n - k0);  // == jbmax whenever a trailing block exists (a multiple of kG32KC)
   const int s0 = k0 + jb;             // first trailing row/col
   const int mt = n - s0;              // trailing size
-  const int tiles_n = (mt + kG32TN - 1) / kG32TN;
-  const int tm = t / tiles_n, tn = t - tm * tiles_n;
+  // tile columns tn0 .. tn0 + ntn - 1 of the trailing columns (clipped)
+  const int tiles_n = min(ntn, (mt + kG32TN - 1) / kG32TN - tn0);
+  const int tm = t / tiles_n, tn = tn0 + (t - tm * tiles_n);
   const int row0 = (MODE == 0 ? s0 : k0) + tm * kG32TM, col0 = s0 + tn * kG32TN;
   const int row_end = MODE == 0 ? n : k0 + jb;
   c64* __restrict__ T = Tb + d.offT;
   const int ld = d.ld;
-  const int* __restrict__ rat = rowb + d.offRow;
+  const int* __restrict__ rat = rowb + d.offRow;    // B rows (and U12 rows in MODE 1)
+  const int* __restrict__ rata = rowa + d.offRow;   // A and C rows of the trailing update
   const c64* __restrict__ Asrc = MODE == 1 ? Linv + (long long)b * kLuMaxJB * kLuMaxJB : T;
 
   // LDS: A as [k][row] complex (stride kG32TM+2), B as re/im planes [k][col].
@@ -585,7 +744,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
   const int wr = (wave >> 1) * 64, wcn = (wave & 1) * 64;
   if (tid < kG32TM) {
     const int gr = row0 + tid;
-    aoff_s[tid] = gr < row_end ? (MODE == 0 ? rat[gr] * ld : (gr - k0) * kLuMaxJB) : -1;
+    aoff_s[tid] = gr < row_end ? (MODE == 0 ? rata[gr] * ld : (gr - k0) * kLuMaxJB) : -1;
   }
   for (int i = tid; i < jb; i += 256) boff_s[i] = rat[k0 + i] * ld;
   __syncthreads();
@@ -732,7 +891,8 @@ template <int MODE>
 __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restrict__ md, const int* __restrict__ prefix,
                                                       int nact, int total, int k0, int jbmax, c128* __restrict__ Tb,
                                                       const int* __restrict__ rowb, const int* __restrict__ skip,
-                                                      const c128* __restrict__ Linv) {
+                                                      const c128* __restrict__ Linv, const int* __restrict__ rowa,
+                                                      int tn0, int ntn) {
   const int v = xcd_remap(blockIdx.x, gridDim.x, total);
   if (v < 0) return;
   const int b = find_slot(prefix, nact, v);
@@ -743,13 +903,14 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
   const int jb = min(jbmax, n - k0);  // == jbmax whenever a trailing block exists (a multiple of kG64KC)
   const int s0 = k0 + jb;
   const int mt = n - s0;
-  const int tiles_n = (mt + kG64TN - 1) / kG64TN;
-  const int tm = t / tiles_n, tn = t - tm * tiles_n;
+  const int tiles_n = min(ntn, (mt + kG64TN - 1) / kG64TN - tn0);
+  const int tm = t / tiles_n, tn = tn0 + (t - tm * tiles_n);
   const int row0 = (MODE == 0 ? s0 : k0) + tm * kG64TM, col0 = s0 + tn * kG64TN;
   const int row_end = MODE == 0 ? n : k0 + jb;
   c128* __restrict__ T = Tb + d.offT;
   const int ld = d.ld;
-  const int* __restrict__ rat = rowb + d.offRow;
+  const int* __restrict__ rat = rowb + d.offRow;    // B rows (and U12 rows in MODE 1)
+  const int* __restrict__ rata = rowa + d.offRow;   // A and C rows of the trailing update
   const c128* __restrict__ Asrc = MODE == 1 ? Linv + (long long)b * kLuMaxJB * kLuMaxJB : T;
 
   __shared__ double As[2][kG64KC][2 * kG64TM + 2];
@@ -761,7 +922,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
   const int wr = (wave >> 1) * 64, wcn = (wave & 1) * 32;
   if (tid < kG64TM) {
     const int gr = row0 + tid;
-    aoff_s[tid] = gr < row_end ? (MODE == 0 ? rat[gr] * ld : (gr - k0) * kLuMaxJB) : -1;
+    aoff_s[tid] = gr < row_end ? (MODE == 0 ? rata[gr] * ld : (gr - k0) * kLuMaxJB) : -1;
   }
   for (int i = tid; i < jb; i += 256) boff_s[i] = rat[k0 + i] * ld;
   __syncthreads();
@@ -884,20 +1045,25 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-template <typename P, int W>
+// Leaf width: complex FP32 panels of one row per thread take 16-column
+// leaves (half the passes over the panel's right part); otherwise 8 (c64) or
+// 4 (c128), which keeps the unrolled leaf in registers.
+template <typename P>
 static hipError_t launch_panel(int rpt, int nact, const MatDesc* md, int k0, int jb, cx<P>* T, int* rows, int* info,
                                const int* skip, hipStream_t st) {
   dim3 g(nact), blk(kPanelThreads);
+  constexpr bool f32 = sizeof(P) == 4;
+  constexpr int Wn = f32 ? 16 : 4, Ww = f32 ? 8 : 4;
   switch (rpt) {
-    case 1: hipLaunchKernelGGL((k_lu_panel<P, W, 1>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
-    case 2: hipLaunchKernelGGL((k_lu_panel<P, W, 2>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
-    case 4: hipLaunchKernelGGL((k_lu_panel<P, W, 4>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
-    default: hipLaunchKernelGGL((k_lu_panel<P, W, 8>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    case 1: hipLaunchKernelGGL((k_lu_panel<P, Wn, 1>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    case 2: hipLaunchKernelGGL((k_lu_panel<P, Ww, 2>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    case 4: hipLaunchKernelGGL((k_lu_panel<P, Ww, 4>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    default: hipLaunchKernelGGL((k_lu_panel<P, Ww, 8>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
   }
   return hipGetLastError();
 }
 
-int lu_jb(int prec) { return prec == NEP_PREC_FP64 ? 64 : 128; }
+int lu_jb(int prec) { return prec == NEP_PREC_FP64 ? 64 : 64; }
 
 void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
   prec = prec_;
@@ -916,27 +1082,27 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
     s.nact = nact;
     int rmax = sorted[0].n - k0;
     s.rpt = rmax <= 512 ? 1 : rmax <= 1024 ? 2 : rmax <= 2048 ? 4 : 8;
-    // trsm and gemm tile prefixes
-    s.off_trsm = (int)prefix.size();
-    int acc = 0;
-    prefix.push_back(0);
-    const int TNs = prec == NEP_PREC_FP64 ? kG64TN : kG32TN;
-    for (int b = 0; b < nact; ++b) {
-      const int n = sorted[b].n, jbb = std::min(jb, n - k0), mt = n - k0 - jbb;
-      acc += mt > 0 ? ceil_div(mt, TNs) : 0;
-      prefix.push_back(acc);
+    // tile prefixes of the block-row product (U12) and of the trailing
+    // update, each in two parts: part 0 = the first tile column (it holds
+    // the next panel), part 1 = the remaining tile columns
+    const int TM = prec == NEP_PREC_FP64 ? kG64TM : kG32TM, TN = prec == NEP_PREC_FP64 ? kG64TN : kG32TN;
+    for (int part = 0; part < 2; ++part) {
+      for (int kind = 0; kind < 2; ++kind) {  // 0: U12 product, 1: trailing update
+        int& off = kind == 0 ? s.off_trsm[part] : s.off_gemm[part];
+        int& tot = kind == 0 ? s.tot_trsm[part] : s.tot_gemm[part];
+        off = (int)prefix.size();
+        int acc = 0;
+        prefix.push_back(0);
+        for (int b = 0; b < nact; ++b) {
+          const int n = sorted[b].n, jbb = std::min(jb, n - k0), mt = n - k0 - jbb;
+          const int tn_all = mt > 0 ? ceil_div(mt, TN) : 0;
+          const int ntn = part == 0 ? std::min(1, tn_all) : std::max(0, tn_all - 1);
+          acc += kind == 0 ? ntn : (mt > 0 ? ceil_div(mt, TM) : 0) * ntn;
+          prefix.push_back(acc);
+        }
+        tot = acc;
+      }
     }
-    s.tot_trsm = acc;
-    s.off_gemm = (int)prefix.size();
-    acc = 0;
-    prefix.push_back(0);
-    for (int b = 0; b < nact; ++b) {
-      const int n = sorted[b].n, jbb = std::min(jb, n - k0), mt = n - k0 - jbb;
-      const int TM = prec == NEP_PREC_FP64 ? kG64TM : kG32TM, TN = prec == NEP_PREC_FP64 ? kG64TN : kG32TN;
-      acc += mt > 0 ? ceil_div(mt, TM) * ceil_div(mt, TN) : 0;
-      prefix.push_back(acc);
-    }
-    s.tot_gemm = acc;
     steps.push_back(s);
   }
 }
@@ -954,55 +1120,137 @@ static size_t inv_l_lds(int jb) {
   return (size_t)m * (m + 1) * sizeof(cx<P>);
 }
 
+__global__ void k_copy_int(const int* __restrict__ src, int* __restrict__ dst, int cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) dst[i] = src[i];
+}
+
+// Panel of a step and the inverses of its diagonal blocks.  The U inverses
+// are needed only by the solves: with a side stream they run there, off the
+// factorization's critical path (the side stream is joined at the end).
 template <typename P>
-hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* info,
-                  const int* skip, cx<P>* Linv, cx<P>* Dinv, const long long* dinv_off, hipStream_t st) {
+static hipError_t lu_panel_step(const LuPlan& plan, const LuPlan::Step& s, const MatDesc* d_md, cx<P>* T, int* rows,
+                                int* info, const int* skip, cx<P>* Linv, cx<P>* Dinv, const long long* dinv_off,
+                                hipStream_t st, hipStream_t side, hipEvent_t ev_side) {
+  hipError_t e;
+  if ((e = launch_panel<P>(s.rpt, s.nact, d_md, s.k0, plan.jb, T, rows, info, skip, st)) != hipSuccess) return e;
+  hipStream_t su = st;
+  if (side != nullptr) {
+    if ((e = hipEventRecord(ev_side, st)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(side, ev_side, 0)) != hipSuccess) return e;
+    su = side;
+  }
+  hipLaunchKernelGGL(k_lu_inv_u<P>, dim3(s.nact * (plan.jb / kSolveBlkLu)), dim3(256), 0, su, d_md, s.k0, plan.jb, T,
+                     rows, Dinv, dinv_off, skip);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lu_inv_l<P>, dim3(s.nact), dim3(256), inv_l_lds<P>(plan.jb), st, d_md, s.k0, plan.jb, T,
+                     rows, Linv, Dinv, dinv_off, skip);
+  return hipGetLastError();
+}
+
+// U12 product and trailing update of one part of a step's tile columns.
+template <typename P>
+static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int part, const MatDesc* d_md,
+                                 const int* d_prefix, cx<P>* T, const int* rows, const int* rows_ac, const int* skip,
+                                 const cx<P>* Linv, hipStream_t st) {
+  const int tn0 = part == 0 ? 0 : 1, ntn = part == 0 ? 1 : INT_MAX;
+  if (s.tot_trsm[part] > 0) {
+    if constexpr (sizeof(P) == 4)
+      hipLaunchKernelGGL(k_lu_gemm_c64<1>, dim3(xcd_grid(s.tot_trsm[part])), dim3(256), 0, st, d_md,
+                         d_prefix + s.off_trsm[part], s.nact, s.tot_trsm[part], s.k0, plan.jb, T, rows, skip, Linv,
+                         rows, tn0, ntn);
+    else
+      hipLaunchKernelGGL(k_lu_gemm_c128<1>, dim3(xcd_grid(s.tot_trsm[part])), dim3(256), 0, st, d_md,
+                         d_prefix + s.off_trsm[part], s.nact, s.tot_trsm[part], s.k0, plan.jb, T, rows, skip, Linv,
+                         rows, tn0, ntn);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (s.tot_gemm[part] > 0) {
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (g_prof.on) {
+      (void)hipEventCreate(&ev0);
+      (void)hipEventCreate(&ev1);
+      (void)hipEventRecord(ev0, st);
+    }
+    if constexpr (sizeof(P) == 4)
+      hipLaunchKernelGGL(k_lu_gemm_c64<0>, dim3(xcd_grid(s.tot_gemm[part])), dim3(256), 0, st, d_md,
+                         d_prefix + s.off_gemm[part], s.nact, s.tot_gemm[part], s.k0, plan.jb, T, rows, skip, Linv,
+                         rows_ac, tn0, ntn);
+    else
+      hipLaunchKernelGGL(k_lu_gemm_c128<0>, dim3(xcd_grid(s.tot_gemm[part])), dim3(256), 0, st, d_md,
+                         d_prefix + s.off_gemm[part], s.nact, s.tot_gemm[part], s.k0, plan.jb, T, rows, skip, Linv,
+                         rows_ac, tn0, ntn);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (g_prof.on) {
+      (void)hipEventRecord(ev1, st);
+      const int TN = sizeof(P) == 4 ? kG32TN : kG64TN;
+      double flops = 0.0;  // 8 real flops per complex multiply-add of the update
+      for (int b = 0; b < s.nact; ++b) {
+        const int n = plan.nvec[b], jbb = std::min(plan.jb, n - s.k0), mt = n - s.k0 - jbb;
+        if (mt <= 0) continue;
+        const int c_lo = part == 0 ? 0 : std::min(mt, TN), c_hi = part == 0 ? std::min(mt, TN) : mt;
+        flops += 8.0 * mt * (double)(c_hi - c_lo) * jbb;
+      }
+      g_prof.add(sizeof(P) == 4 ? 0 : 1, ev0, ev1, flops);
+    }
+  }
+  return hipSuccess;
+}
+
+// Look-ahead schedule.  After the part of step k's update that holds the
+// next panel, the next panel (and its inverses) runs on the auxiliary stream
+// while the rest of step k's update runs on st; st waits for the panel before
+// step k+1.  The next panel permutes its rows (through the row map) while the
+// rest of the update runs, so that update addresses its A and C rows through
+// a copy of the row map taken before the fork: the rows it touches form the
+// same set under either order, and the panel writes only its own columns.
+template <typename P>
+hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* rows_snap,
+                  int rows_total, int* info, const int* skip, cx<P>* Linv, cx<P>* Dinv, const long long* dinv_off,
+                  hipStream_t st, const LuStreams& ls) {
+  hipStream_t aux = ls.aux, side = ls.side;
+  hipEvent_t ev_fork = ls.ev_fork, ev_join = ls.ev_join;
   hipError_t e;
   hipLaunchKernelGGL(k_lu_init, dim3(plan.nmat), dim3(256), 0, st, d_md, plan.nmat, rows, info);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  constexpr int W = sizeof(P) == 4 ? 8 : 4;
-  for (const auto& s : plan.steps) {
-    const bool more = s.tot_trsm > 0;
-    if ((e = launch_panel<P, W>(s.rpt, s.nact, d_md, s.k0, plan.jb, T, rows, info, skip, st)) != hipSuccess)
-      return e;
-    hipLaunchKernelGGL(k_lu_inv_u<P>, dim3(s.nact * (plan.jb / kSolveBlkLu)), dim3(256), 0, st, d_md, s.k0, plan.jb,
-                       T, rows, Dinv, dinv_off, skip);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lu_inv_l<P>, dim3(s.nact), dim3(256), inv_l_lds<P>(plan.jb), st, d_md, s.k0, plan.jb, T,
-                       rows, Linv, Dinv, dinv_off, skip);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (!more) continue;
-    if constexpr (sizeof(P) == 4)
-      hipLaunchKernelGGL(k_lu_gemm_c64<1>, dim3(xcd_grid(s.tot_trsm)), dim3(256), 0, st, d_md, d_prefix + s.off_trsm,
-                         s.nact, s.tot_trsm, s.k0, plan.jb, T, rows, skip, Linv);
-    else
-      hipLaunchKernelGGL(k_lu_gemm_c128<1>, dim3(xcd_grid(s.tot_trsm)), dim3(256), 0, st, d_md,
-                         d_prefix + s.off_trsm, s.nact, s.tot_trsm, s.k0, plan.jb, T, rows, skip, Linv);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (s.tot_gemm > 0) {
-      hipEvent_t ev0 = nullptr, ev1 = nullptr;
-      if (g_prof.on) {
-        (void)hipEventCreate(&ev0);
-        (void)hipEventCreate(&ev1);
-        (void)hipEventRecord(ev0, st);
-      }
-      if constexpr (sizeof(P) == 4)
-        hipLaunchKernelGGL(k_lu_gemm_c64<0>, dim3(xcd_grid(s.tot_gemm)), dim3(256), 0, st, d_md,
-                           d_prefix + s.off_gemm, s.nact, s.tot_gemm, s.k0, plan.jb, T, rows, skip, Linv);
-      else
-        hipLaunchKernelGGL(k_lu_gemm_c128<0>, dim3(xcd_grid(s.tot_gemm)), dim3(256), 0, st, d_md,
-                           d_prefix + s.off_gemm, s.nact, s.tot_gemm, s.k0, plan.jb, T, rows, skip, Linv);
+  const int nsteps = (int)plan.steps.size();
+  if (nsteps == 0) return hipSuccess;
+  const bool lookahead = aux != nullptr && rows_snap != nullptr;
+  if ((e = lu_panel_step<P>(plan, plan.steps[0], d_md, T, rows, info, skip, Linv, Dinv, dinv_off, st, side, ls.ev_side[0])) != hipSuccess)
+    return e;
+  for (int k = 0; k < nsteps; ++k) {
+    const auto& s = plan.steps[k];
+    const bool has_next = k + 1 < nsteps;
+    if ((e = lu_update_part<P>(plan, s, 0, d_md, d_prefix, T, rows, rows, skip, Linv, st)) != hipSuccess) return e;
+    const bool overlap = lookahead && has_next && s.tot_gemm[1] > 0;
+    if (overlap) {
+      hipLaunchKernelGGL(k_copy_int, dim3(ceil_div(rows_total, 256)), dim3(256), 0, st, rows, rows_snap, rows_total);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      if (g_prof.on) {
-        (void)hipEventRecord(ev1, st);
-        double flops = 0.0;  // 8 real flops per complex multiply-add of the update
-        for (int b = 0; b < s.nact; ++b) {
-          const int n = plan.nvec[b], jbb = std::min(plan.jb, n - s.k0), mt = n - s.k0 - jbb;
-          if (mt > 0) flops += 8.0 * mt * (double)mt * jbb;
-        }
-        g_prof.add(sizeof(P) == 4 ? 0 : 1, ev0, ev1, flops);
+      if ((e = hipEventRecord(ev_fork, st)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(aux, ev_fork, 0)) != hipSuccess) return e;
+      if ((e = lu_panel_step<P>(plan, plan.steps[k + 1], d_md, T, rows, info, skip, Linv, Dinv, dinv_off, aux, side,
+                                  ls.ev_side[(k + 1) & 1])) !=
+          hipSuccess)
+        return e;
+      if ((e = hipEventRecord(ev_join, aux)) != hipSuccess) return e;
+    }
+    if ((e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, rows, overlap ? rows_snap : rows, skip, Linv, st)) !=
+        hipSuccess)
+      return e;
+    if (has_next) {
+      if (overlap) {
+        if ((e = hipStreamWaitEvent(st, ev_join, 0)) != hipSuccess) return e;
+      } else if ((e = lu_panel_step<P>(plan, plan.steps[k + 1], d_md, T, rows, info, skip, Linv, Dinv, dinv_off,
+                                       st, side, ls.ev_side[(k + 1) & 1])) != hipSuccess) {
+        return e;
       }
     }
+  }
+  if (side != nullptr) {  // join the U inverses
+    if ((e = hipEventRecord(ls.ev_side_done, side)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(st, ls.ev_side_done, 0)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -1015,9 +1263,9 @@ hipError_t lu_configure() {
                              (int)inv_l_lds<double>(lu_jb(NEP_PREC_FP64)));
 }
 
-template hipError_t lu_run<float>(const LuPlan&, const MatDesc*, const int*, c64*, int*, int*, const int*, c64*,
-                                  c64*, const long long*, hipStream_t);
-template hipError_t lu_run<double>(const LuPlan&, const MatDesc*, const int*, c128*, int*, int*, const int*, c128*,
-                                   c128*, const long long*, hipStream_t);
+template hipError_t lu_run<float>(const LuPlan&, const MatDesc*, const int*, c64*, int*, int*, int, int*, const int*,
+                                  c64*, c64*, const long long*, hipStream_t, const LuStreams&);
+template hipError_t lu_run<double>(const LuPlan&, const MatDesc*, const int*, c128*, int*, int*, int, int*, const int*,
+                                   c128*, c128*, const long long*, hipStream_t, const LuStreams&);
 
 }  // namespace nep

@@ -14,8 +14,10 @@ constexpr int kSolveBlkLu = 64;  // diagonal-block size of the stored inverses (
 struct LuPlan {
   struct Step {
     int k0, nact, rpt;
-    int off_trsm, tot_trsm;
-    int off_gemm, tot_gemm;
+    // tiles of the U12 product and of the trailing update; part 0 is the
+    // first tile column (it holds the next panel), part 1 the rest
+    int off_trsm[2], tot_trsm[2];
+    int off_gemm[2], tot_gemm[2];
   };
   int jb = 128, prec = NEP_PREC_C32_IR64, nmat = 0, nmax = 0;
   std::vector<Step> steps;
@@ -43,8 +45,19 @@ hipError_t lu_configure();
 // Linv: workspace of nact * kLuMaxJB^2 elements (inverses of the L11 blocks).
 // Dinv/dinv_off: per matrix, the inverses of the 64 x 64 diagonal blocks of L
 // and U ([blk][0: L, 1: U][64][64]), written as the panels complete.
+// Streams and events of the look-ahead schedule: the next panel runs on aux
+// while the rest of the trailing update runs on the caller's stream, and the
+// inverses of the U blocks run on side.  nullptr streams: no overlap.  All
+// streams keep the default priority.
+struct LuStreams {
+  hipStream_t aux = nullptr, side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_side[2] = {nullptr, nullptr}, ev_side_done = nullptr;
+};
+
+// rows_snap: rows_total ints (a copy of the row maps for the overlapped update).
 template <typename P>
-hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* info,
-                  const int* skip, cx<P>* Linv, cx<P>* Dinv, const long long* dinv_off, hipStream_t st);
+hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* rows_snap,
+                  int rows_total, int* info, const int* skip, cx<P>* Linv, cx<P>* Dinv, const long long* dinv_off,
+                  hipStream_t st, const LuStreams& ls);
 
 }  // namespace nep

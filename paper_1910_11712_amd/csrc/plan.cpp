@@ -293,6 +293,13 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   if (mixed && o.fallback) NEP_TRY(A(dlu64_prefix_, sizeof(int) * std::max<size_t>(1, lu64_.prefix.size())));
   NEP_TRY(A(dT_, es * (size_t)t_elems_));
   NEP_TRY(A(drows_, sizeof(int) * (size_t)rows_total_));
+  NEP_TRY(A(drows_snap_, sizeof(int) * (size_t)rows_total_));
+  if (!ls_.aux) {
+    NEP_HIP(hipStreamCreateWithFlags(&ls_.aux, hipStreamNonBlocking));
+    NEP_HIP(hipStreamCreateWithFlags(&ls_.side, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&ls_.ev_fork, &ls_.ev_join, &ls_.ev_side[0], &ls_.ev_side[1], &ls_.ev_side_done})
+      NEP_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  }
   NEP_TRY(A(dinfo_, sizeof(int) * (size_t)nnodes));
   NEP_TRY(A(ddinv_, es * (size_t)dinv_elems_));
   NEP_TRY(A(dlinv_, es * (size_t)sorted_.size() * kLuMaxJB * kLuMaxJB));
@@ -364,7 +371,8 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
   NEP_HIP(launch_assemble<P>(pd, pre, pt_.assemble, na_, T, nullptr, st));
   cx<P>* Dinv = ddinv_.as<cx<P>>();
   const long long* doff = ddinv_off_.as<long long>();
-  NEP_HIP(lu_run<P>(lu_, md, dlu_prefix_.as<int>(), T, rows, info, nullptr, dlinv_.as<cx<P>>(), Dinv, doff, st));
+  NEP_HIP(lu_run<P>(lu_, md, dlu_prefix_.as<int>(), T, rows, drows_snap_.as<int>(), rows_total_, info, nullptr,
+                    dlinv_.as<cx<P>>(), Dinv, doff, st, ls_));
   NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, nullptr, Y, false, nullptr, ir_, st));
   sweeps_run_ = 0;
   if (opt.max_refine > 0) {
@@ -425,8 +433,8 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
   NEP_HIP(launch_assemble<double>(pd, pre, pt_.assemble, na_, T, skip, st));
   c128* Dinv = ddinv64_.as<c128>();
   const long long* doff = ddinv_off_.as<long long>();
-  NEP_HIP(lu_run<double>(lu64_, md, dlu64_prefix_.as<int>(), T, drows_.as<int>(), dinfo_.as<int>(), skip,
-                         dlinv64_.as<c128>(), Dinv, doff, st));
+  NEP_HIP(lu_run<double>(lu64_, md, dlu64_prefix_.as<int>(), T, drows_.as<int>(), drows_snap_.as<int>(), rows_total_,
+                         dinfo_.as<int>(), skip, dlinv64_.as<c128>(), Dinv, doff, st, ls_));
   NEP_HIP(solve_run<double>(sp_, pd, md, na_, T, drows_.as<int>(), Dinv, doff, nullptr, dY_.as<c128>(), false,
                             skip, ir_, st));
   // check the residual of the re-solved nodes once

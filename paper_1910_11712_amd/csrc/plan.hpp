@@ -106,6 +106,10 @@ class MomentsPlan {
   MomentsPlan& operator=(const MomentsPlan&) = delete;
   ~MomentsPlan() {
     if (hcounter_) pinned_give(hcounter_);
+    for (hipEvent_t e : {ls_.ev_fork, ls_.ev_join, ls_.ev_side[0], ls_.ev_side[1], ls_.ev_side_done})
+      if (e) (void)hipEventDestroy(e);
+    if (ls_.aux) (void)hipStreamDestroy(ls_.aux);
+    if (ls_.side) (void)hipStreamDestroy(ls_.side);
   }
   // Builds layout, tables and buffers.  Problems may differ in n (ragged).
   nep_status build(const std::vector<PlanProblem>& probs, const PlanOptions& o);
@@ -144,13 +148,14 @@ class MomentsPlan {
   ProblemTables pt_;
   std::vector<int> hprefix_;
   DevMem dpd_, dmd_, dprefix_, dlu_prefix_, dlu64_prefix_;
-  DevMem dT_, drows_, dinfo_, dY_, dR_, dnode_, dir_, dT64_;
+  DevMem dT_, drows_, drows_snap_, dinfo_, dY_, dR_, dnode_, dir_, dT64_;
   DevMem ddinv_, ddinv_off_, ddinv64_, dlinv_, dlinv64_;
   std::vector<long long> dinv_off_;
   long long dinv_elems_ = 0;
   NodeArrays na_{};
   IrState ir_{};
   int* hcounter_ = nullptr;  // pinned host read-back
+  LuStreams ls_;  // look-ahead LU streams (default priority) and events
   size_t total_bytes_ = 0;
   long long t_elems_ = 0, w_elems_ = 0, y_elems_ = 0;
   int rows_total_ = 0;
