@@ -71,6 +71,19 @@ __host__ __device__ __forceinline__ cx<P> recip(cx<P> a) {
   if (d == 0.0) return {P(0), P(0)};
   return {P(ar / d), P(-ai / d)};
 }
+// 1/a in FP32: a is scaled by a power of two to |a| ~ 1 (exact), the
+// hardware reciprocal of |a|^2 is refined by one Newton step (about one
+// ulp), and 1/a = conj(a)/|a|^2 is scaled back.  Zero maps to zero.
+__device__ __forceinline__ c64 recip_f32(c64 a) {
+  const float m = fmaxf(fabsf(a.re), fabsf(a.im));
+  if (m == 0.f) return {0.f, 0.f};
+  const int e = __builtin_amdgcn_frexp_expf(m);
+  const float xr = ldexpf(a.re, -e), xi = ldexpf(a.im, -e);
+  const float d = xr * xr + xi * xi;
+  float r = __builtin_amdgcn_rcpf(d);
+  r = r * (2.f - d * r);
+  return {ldexpf(xr * r, -e), ldexpf(-xi * r, -e)};
+}
 // a / b in double precision.
 __host__ __device__ __forceinline__ c128 cdiv(c128 a, c128 b) {
   // Smith's scaling to avoid overflow

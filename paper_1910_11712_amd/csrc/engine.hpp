@@ -99,7 +99,7 @@ template <typename P>
 hipError_t solve_run(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md, const NodeArrays& na,
                      const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off,
                      const c128* R, c128* Y, bool refine, const int* conv, IrState ir, hipStream_t st);
-void SolvePlan_build(SolvePlan& sp, std::vector<int>& buf, const std::vector<MatDesc>& sorted, int L,
+void SolvePlan_build(SolvePlan& sp, std::vector<int>& buf, const std::vector<MatDesc>& sorted, int L, int prec,
                      std::vector<long long>& dinv_off, long long& dinv_elems);
 hipError_t solve_configure();
 

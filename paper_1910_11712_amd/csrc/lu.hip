@@ -92,6 +92,198 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k)
   return ((unsigned long long)h << 32) | l;
 }
 
+// Panel columns right of a finished leaf (columns c0+wc .. k0+jb-1): the
+// leaf's top rows become rows of U by a unit lower solve with the leaf's top
+// block, then every row below takes the rank-wc update.  top: this thread's
+// leaf row when tid < wc (the leaf's top rows).
+template <typename P, int W, int RPT>
+__device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const int* rat, int ld, int n, int k0,
+                                                   int jb, int c0, int wc, const cx<P> (&top)[W],
+                                                   cx<P> (&Ltop)[W][W], cx<P> (&Utop)[W][kLuMaxJB],
+                                                   cx<P> (&Lc)[kPanelThreads][W + 1]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // ---- update the panel columns right of the leaf
+  const int rc0 = c0 + wc;
+  const int nr = k0 + jb - rc0;
+  if (nr > 0) {
+    if (tid < wc) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) Ltop[tid][w] = top[w];
+    }
+    __syncthreads();
+    static_assert(kLuMaxJB <= kPanelThreads, "one thread per right-hand column of the panel");
+    if (tid < nr) {  // nr < jb <= kLuMaxJB: one column per thread
+      const int j = tid;
+      cx<P> x[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        if (w < wc) x[w] = T[(long long)rat[c0 + w - k0] * ld + rc0 + j];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        if (w < wc) {
+#pragma unroll
+          for (int v = 0; v < w; ++v) x[w] = fms(x[w], Ltop[w][v], x[v]);
+          T[(long long)rat[c0 + w - k0] * ld + rc0 + j] = x[w];
+          Utop[w][j] = x[w];
+        }
+      }
+    }
+    __syncthreads();
+    // rows >= rc0: A[r][right] -= L[r][leaf] U[leaf][right], 512 rows at a
+    // time, the chunk's L through LDS.
+    if constexpr (sizeof(P) == 4) {
+      // Complex FP32: on the matrix cores.  A wave takes 16 x 32 complex
+      // blocks of the right part; C is loaded into the accumulators, the
+      // leaf's W complex k run as W v_mfma_f32_32x32x2f32 on the real 2x2
+      // embedding (A operand negated, so the sum is C - L U), and the block
+      // is stored back.
+      constexpr int RB = 16, CB = 32;
+      const int ncb = (nr + CB - 1) / CB;
+      const int at = lane & 1, au = lane >> 5, arow = (lane & 31) >> 1;
+      const int acomp = at ^ au;
+      const float asign = (at == 0 && au == 1) ? 1.f : -1.f;
+      const int gcol = rc0 + (lane & 31);
+      for (int i = 0; i < RPT; ++i) {
+        const int rbase = c0 + i * kPanelThreads;
+        if (rbase >= n) continue;  // uniform
+        {
+          // the chunk's L rows, read back from the leaf this thread wrote
+          const int r = rbase + tid;
+          const bool live = r >= rc0 && r < n;
+          const cx<P>* src = T + (long long)rat[(live ? r : rc0) - k0] * ld + c0;
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            const cx<P> v = src[w < wc ? w : 0];
+            Lc[tid][w] = (live && w < wc) ? v : cx<P>{P(0), P(0)};
+          }
+        }
+        __syncthreads();
+        const int rb_lo = max(0, rc0 - rbase) / RB;
+        const int rb_hi = (min(kPanelThreads, n - rbase) + RB - 1) / RB;
+        // a wave takes two consecutive 16-row blocks and two 32-column blocks
+        // per pass: all the pass's C loads are in flight before the products
+        constexpr int NRB = 2, NCB = 2;
+        for (int cb0 = 0; cb0 < ncb; cb0 += NCB) {
+          for (int rb0 = rb_lo + wave * NRB; rb0 < rb_hi; rb0 += (kPanelThreads / 64) * NRB) {
+            floatx16 acc[NRB][NCB];
+            int roff[NRB][8];
+            bool rok[NRB][8];
+            int rbq[NRB];
+#pragma unroll
+            for (int q = 0; q < NRB; ++q) {
+              const bool vq = rb0 + q < rb_hi;  // uniform
+              rbq[q] = vq ? rb0 + q : rb0;
+#pragma unroll
+              for (int e = 0; e < 16; e += 2) {
+                const int r = rbase + RB * (rb0 + q) + 4 * (e >> 2) + 2 * (lane >> 5) + ((e & 3) >> 1);
+                rok[q][e >> 1] = vq && r >= rc0 && r < n;
+                roff[q][e >> 1] = rat[(rok[q][e >> 1] ? r : rc0) - k0] * ld;
+              }
+            }
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) {
+              const int col = gcol + CB * (cb0 + c);
+              const bool cok = cb0 + c < ncb && col < k0 + jb;
+              const int cc = cok ? col : rc0;
+#pragma unroll
+              for (int q = 0; q < NRB; ++q)
+#pragma unroll
+                for (int e = 0; e < 16; e += 2) {
+                  const cx<P> cv = T[roff[q][e >> 1] + cc];
+                  const bool ok = cok && rok[q][e >> 1];
+                  acc[q][c][e] = ok ? cv.re : 0.f;
+                  acc[q][c][e + 1] = ok ? cv.im : 0.f;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+              float bv[NCB];
+#pragma unroll
+              for (int c = 0; c < NCB; ++c) {
+                const cx<P> uv = Utop[k][min(CB * (cb0 + c), kLuMaxJB - CB) + (lane & 31)];
+                bv[c] = au ? uv.im : uv.re;
+              }
+#pragma unroll
+              for (int q = 0; q < NRB; ++q) {
+                const cx<P> lv = Lc[RB * rbq[q] + arow][k];
+                const float av = asign * (acomp ? lv.im : lv.re);
+#pragma unroll
+                for (int c = 0; c < NCB; ++c)
+                  acc[q][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[c], acc[q][c], 0, 0, 0);
+              }
+            }
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) {
+              const int col = gcol + CB * (cb0 + c);
+              if (cb0 + c < ncb && col < k0 + jb) {
+#pragma unroll
+                for (int q = 0; q < NRB; ++q)
+#pragma unroll
+                  for (int e = 0; e < 16; e += 2)
+                    if (rok[q][e >> 1]) T[roff[q][e >> 1] + col] = cx<P>{acc[q][c][e], acc[q][c][e + 1]};
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+    } else {
+      for (int i = 0; i < RPT; ++i) {
+        const int rbase = c0 + i * kPanelThreads;
+        if (rbase >= n) continue;  // uniform
+        {
+          const int r = rbase + tid;
+          const bool live = r < n;
+          const cx<P>* src = T + (long long)rat[(live ? r : c0) - k0] * ld + c0;
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            const cx<P> v = src[w < wc ? w : 0];
+            Lc[tid][w] = (live && w < wc) ? v : cx<P>{P(0), P(0)};
+          }
+        }
+        __syncthreads();
+        const int rlo = max(rbase, rc0), rhi = min(n, rbase + kPanelThreads);
+        // each wave takes kRows rows at a time so that their loads are in
+        // flight together; full leaves and full row batches run branch-free
+        constexpr int kRows = 8;
+        for (int r0 = rlo + wave * kRows; r0 < rhi; r0 += (kPanelThreads / 64) * kRows) {
+          const int nrow = min(kRows, rhi - r0);
+          for (int j = lane; j < nr; j += 64) {
+            long long off[kRows];
+            cx<P> acc[kRows];
+#pragma unroll
+            for (int u = 0; u < kRows; ++u) {
+              const int r = r0 + min(u, nrow - 1);
+              off[u] = (long long)rat[r - k0] * ld + rc0 + j;
+            }
+#pragma unroll
+            for (int u = 0; u < kRows; ++u) acc[u] = T[off[u]];
+            if (wc == W) {
+#pragma unroll
+              for (int u = 0; u < kRows; ++u) {
+                const int lr = r0 + min(u, nrow - 1) - rbase;
+#pragma unroll
+                for (int w = 0; w < W; ++w) acc[u] = fms(acc[u], Lc[lr][w], Utop[w][j]);
+              }
+            } else {
+#pragma unroll
+              for (int u = 0; u < kRows; ++u) {
+                const int lr = r0 + min(u, nrow - 1) - rbase;
+                for (int w = 0; w < wc; ++w) acc[u] = fms(acc[u], Lc[lr][w], Utop[w][j]);
+              }
+            }
+            // duplicated tail rows compute identical values, so storing them
+            // twice is harmless
+#pragma unroll
+            for (int u = kRows - 1; u >= 0; --u) T[off[u]] = acc[u];
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
 template <typename P, int W, int RPT>
 __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __restrict__ md, int k0, int jbmax,
                                                            cx<P>* __restrict__ Tb, int* __restrict__ rowb,
@@ -261,7 +453,9 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
           if (bv == P(0) && zero_pivot == n) zero_pivot = c;
         }
         // ---- scale the column and update the rest of the leaf (selects, no branches)
-        const cx<P> inv = recip(prow[w]);
+        cx<P> inv;
+        if constexpr (sizeof(P) == 4) inv = recip_f32(prow[w]);
+        else inv = recip(prow[w]);
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
           const int r = c0 + tid + i * kPanelThreads;
@@ -289,173 +483,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
       }
     }
 
-    // ---- update the panel columns right of the leaf
-    const int rc0 = c0 + wc;
-    const int nr = k0 + jb - rc0;
-    if (nr > 0) {
-      if (tid < wc) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) Ltop[tid][w] = a[0][w];
-      }
-      __syncthreads();
-      static_assert(kLuMaxJB <= kPanelThreads, "one thread per right-hand column of the panel");
-      if (tid < nr) {  // nr < jb <= kLuMaxJB: one column per thread
-        const int j = tid;
-        cx<P> x[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w)
-          if (w < wc) x[w] = T[(long long)rat[c0 + w - k0] * ld + rc0 + j];
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          if (w < wc) {
-#pragma unroll
-            for (int v = 0; v < w; ++v) x[w] = fms(x[w], Ltop[w][v], x[v]);
-            T[(long long)rat[c0 + w - k0] * ld + rc0 + j] = x[w];
-            Utop[w][j] = x[w];
-          }
-        }
-      }
-      __syncthreads();
-      // rows >= rc0: A[r][right] -= L[r][leaf] U[leaf][right], 512 rows at a
-      // time, the chunk's L through LDS.
-      if constexpr (sizeof(P) == 4) {
-        // Complex FP32: on the matrix cores.  A wave takes 16 x 32 complex
-        // blocks of the right part; C is loaded into the accumulators, the
-        // leaf's W complex k run as W v_mfma_f32_32x32x2f32 on the real 2x2
-        // embedding (A operand negated, so the sum is C - L U), and the block
-        // is stored back.
-        constexpr int RB = 16, CB = 32;
-        const int ncb = (nr + CB - 1) / CB;
-        const int at = lane & 1, au = lane >> 5, arow = (lane & 31) >> 1;
-        const int acomp = at ^ au;
-        const float asign = (at == 0 && au == 1) ? 1.f : -1.f;
-        const int gcol = rc0 + (lane & 31);
-        for (int i = 0; i < RPT; ++i) {
-          const int rbase = c0 + i * kPanelThreads;
-          if (rbase >= n) continue;  // uniform
-          {
-            // the chunk's L rows, read back from the leaf this thread wrote
-            const int r = rbase + tid;
-            const bool live = r >= rc0 && r < n;
-            const cx<P>* src = T + (long long)rat[(live ? r : rc0) - k0] * ld + c0;
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-              const cx<P> v = src[w < wc ? w : 0];
-              Lc[tid][w] = (live && w < wc) ? v : cx<P>{P(0), P(0)};
-            }
-          }
-          __syncthreads();
-          const int rb_lo = max(0, rc0 - rbase) / RB;
-          const int rb_hi = (min(kPanelThreads, n - rbase) + RB - 1) / RB;
-          // a wave takes a 16-row block across every column block (<= 4): all
-          // its C loads are issued before the products
-          for (int rb = rb_lo + wave; rb < rb_hi; rb += kPanelThreads / 64) {
-            floatx16 acc[kLuMaxJB / CB];
-            int roff[8];
-            bool rok[8];
-#pragma unroll
-            for (int e = 0; e < 16; e += 2) {
-              const int r = rbase + RB * rb + 4 * (e >> 2) + 2 * (lane >> 5) + ((e & 3) >> 1);
-              rok[e >> 1] = r >= rc0 && r < n;
-              roff[e >> 1] = rat[(rok[e >> 1] ? r : rc0) - k0] * ld;
-            }
-#pragma unroll
-            for (int cb = 0; cb < kLuMaxJB / CB; ++cb) {
-              if (cb < ncb) {  // uniform
-                const int col = gcol + CB * cb;
-                const bool cok = col < k0 + jb;
-                const int cc = cok ? col : rc0;
-#pragma unroll
-                for (int e = 0; e < 16; e += 2) {
-                  const cx<P> cv = T[roff[e >> 1] + cc];
-                  const bool ok = cok && rok[e >> 1];
-                  acc[cb][e] = ok ? cv.re : 0.f;
-                  acc[cb][e + 1] = ok ? cv.im : 0.f;
-                }
-              }
-            }
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-              const cx<P> lv = Lc[RB * rb + arow][k];
-              const float av = asign * (acomp ? lv.im : lv.re);
-#pragma unroll
-              for (int cb = 0; cb < kLuMaxJB / CB; ++cb) {
-                if (cb < ncb) {
-                  const cx<P> uv = Utop[k][CB * cb + (lane & 31)];
-                  const float bv = au ? uv.im : uv.re;
-                  acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[cb], 0, 0, 0);
-                }
-              }
-            }
-#pragma unroll
-            for (int cb = 0; cb < kLuMaxJB / CB; ++cb) {
-              if (cb < ncb) {
-                const int col = gcol + CB * cb;
-                if (col < k0 + jb) {
-#pragma unroll
-                  for (int e = 0; e < 16; e += 2)
-                    if (rok[e >> 1]) T[roff[e >> 1] + col] = cx<P>{acc[cb][e], acc[cb][e + 1]};
-                }
-              }
-            }
-          }
-          __syncthreads();
-        }
-      } else {
-        for (int i = 0; i < RPT; ++i) {
-          const int rbase = c0 + i * kPanelThreads;
-          if (rbase >= n) continue;  // uniform
-          {
-            const int r = rbase + tid;
-            const bool live = r < n;
-            const cx<P>* src = T + (long long)rat[(live ? r : c0) - k0] * ld + c0;
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-              const cx<P> v = src[w < wc ? w : 0];
-              Lc[tid][w] = (live && w < wc) ? v : cx<P>{P(0), P(0)};
-            }
-          }
-          __syncthreads();
-          const int rlo = max(rbase, rc0), rhi = min(n, rbase + kPanelThreads);
-          // each wave takes kRows rows at a time so that their loads are in
-          // flight together; full leaves and full row batches run branch-free
-          constexpr int kRows = 8;
-          for (int r0 = rlo + wave * kRows; r0 < rhi; r0 += (kPanelThreads / 64) * kRows) {
-            const int nrow = min(kRows, rhi - r0);
-            for (int j = lane; j < nr; j += 64) {
-              long long off[kRows];
-              cx<P> acc[kRows];
-#pragma unroll
-              for (int u = 0; u < kRows; ++u) {
-                const int r = r0 + min(u, nrow - 1);
-                off[u] = (long long)rat[r - k0] * ld + rc0 + j;
-              }
-#pragma unroll
-              for (int u = 0; u < kRows; ++u) acc[u] = T[off[u]];
-              if (wc == W) {
-#pragma unroll
-                for (int u = 0; u < kRows; ++u) {
-                  const int lr = r0 + min(u, nrow - 1) - rbase;
-#pragma unroll
-                  for (int w = 0; w < W; ++w) acc[u] = fms(acc[u], Lc[lr][w], Utop[w][j]);
-                }
-              } else {
-#pragma unroll
-                for (int u = 0; u < kRows; ++u) {
-                  const int lr = r0 + min(u, nrow - 1) - rbase;
-                  for (int w = 0; w < wc; ++w) acc[u] = fms(acc[u], Lc[lr][w], Utop[w][j]);
-                }
-              }
-              // duplicated tail rows compute identical values, so storing them
-              // twice is harmless
-#pragma unroll
-              for (int u = kRows - 1; u >= 0; --u) T[off[u]] = acc[u];
-            }
-          }
-          __syncthreads();
-        }
-      }
-    }
+    panel_right_update<P, W, RPT>(T, rat, ld, n, k0, jb, c0, wc, a[0], Ltop, Utop, Lc);
   }
   for (int r = tid; r < m; r += kPanelThreads) rowg[k0 + r] = rat[r];
   if (tid == 0 && zero_pivot < n) atomicMin(&info[d.node], zero_pivot);
@@ -1063,7 +1091,7 @@ static hipError_t launch_panel(int rpt, int nact, const MatDesc* md, int k0, int
   return hipGetLastError();
 }
 
-int lu_jb(int prec) { return prec == NEP_PREC_FP64 ? 64 : 64; }
+int lu_jb(int /*prec*/) { return 64; }  // panel width (both precisions)
 
 void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
   prec = prec_;

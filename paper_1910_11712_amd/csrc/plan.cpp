@@ -265,7 +265,7 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   if (mixed && o.fallback) lu64_.build(sorted_, NEP_PREC_FP64);
 
   hprefix_.clear();
-  SolvePlan_build(sp_, hprefix_, sorted_, o.L, dinv_off_, dinv_elems_);
+  SolvePlan_build(sp_, hprefix_, sorted_, o.L, o.prec, dinv_off_, dinv_elems_);
   {
     std::vector<int> ca, cr, cm;
     for (int p = 0; p < nprob; ++p) {

@@ -47,6 +47,18 @@ __device__ __forceinline__ void load_seg16(const c128* __restrict__ s, c128 (&v)
   }
 }
 
+template <int Q, typename P>
+__device__ __forceinline__ void load_seg(const cx<P>* __restrict__ s, cx<P> (&v)[Q]) {
+  static_assert(Q % 16 == 0, "segments of 16 elements");
+#pragma unroll
+  for (int k = 0; k < Q; k += 16) {
+    cx<P> t[16];
+    load_seg16(s + k, t);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[k + u] = t[u];
+  }
+}
+
 template <typename P, int LG, int RPT>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict__ md, int nmat, int groups,
                                                       const ProbDesc* __restrict__ pd, NodeArrays na,
@@ -56,6 +68,15 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
                                                       const c128* __restrict__ R, c128* __restrict__ Y, int refine,
                                                       const int* __restrict__ conv, IrState ir) {
   constexpr int B = kSolveBlk;  // 64
+  // register budget (32-bit words per thread) of the prefetched segment
+  // columns (PF per row) and of the rows whose 16-column chunks load together
+  // (GR): accumulators + prefetch + one chunk per grouped row stay within it
+  constexpr int FW = 2 * (int)(sizeof(P) / 4);  // words per complex
+  constexpr int kBudget = sizeof(P) == 8 ? 112 : 176;
+  constexpr int PF = RPT * FW * (32 + 16 + LG) <= kBudget   ? 32
+                     : RPT * FW * (16 + 16 + LG) <= kBudget ? 16
+                                                            : 0;
+  constexpr int GR = RPT * FW * (PF + 16 + LG) <= kBudget ? RPT : 1;
   // the column groups of one matrix run on one XCD and share its L2
   const int v = xcd_remap(blockIdx.x, gridDim.x, nmat * groups);
   if (v < 0) return;
@@ -80,12 +101,16 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
   __shared__ cx<P> Xs[B][LG];      // block solution
   __shared__ double cmax[kTrsvThreads / 64][LG];
 
+  // rows of this thread: slot i holds row i*T + tid (i even) or
+  // (i+1)*T - 1 - tid (i odd), so every thread has rows from both ends and
+  // the pending rows of a block are spread evenly over the waves
+  auto row_of = [&](int i) { return (i & 1) ? (i + 1) * kTrsvThreads - 1 - tid : i * kTrsvThreads + tid; };
   // right-hand side P b gathered into the owners' accumulators
   cx<P> acc[RPT][LG];
   long long rowoff[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    const int r = tid + i * kTrsvThreads;
+    const int r = row_of(i);
     const int pr = r < n ? rat[r] : 0;
     rowoff[i] = (long long)pr * ld;
 #pragma unroll
@@ -100,23 +125,46 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
 #pragma unroll
   for (int c = 0; c < LG; ++c) ymax[c] = 0.0;
 
+  constexpr int DPT = B * B / kTrsvThreads;  // inverse elements per thread
+  static_assert(DPT * kTrsvThreads == B * B, "inverse staging");
+  cx<P> dreg[DPT];
+#pragma unroll
+  for (int u = 0; u < DPT; ++u) {  // block 0 of L
+    const cx<P>* src = Di + tid + u * kTrsvThreads;
+    dreg[u] = cx<P>{src->re, src->im};
+  }
   for (int pass = 0; pass < 2; ++pass) {  // 0: L y = P b, 1: U x = y
     for (int qq = 0; qq < nblk; ++qq) {
       const int q = pass == 0 ? qq : nblk - 1 - qq;
       const int R0 = q * B, nr = min(B, n - R0);
+      // 0. the factor segments of the pending rows do not depend on this
+      // block's solution: the first PF columns are loaded now and arrive
+      // while the block is solved
+      cx<P> pre[RPT][PF > 0 ? PF : 1];
+      if constexpr (PF > 0) {
+        if (nr == B) {
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) {
+            const int r = row_of(i);
+            if (r < n && (pass == 0 ? r >= R0 + B : r < R0)) load_seg<PF>(T + rowoff[i] + R0, pre[i]);
+          }
+        }
+      }
       // 1. publish the block's pending sums; stage the inverse
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        const int r = tid + i * kTrsvThreads;
+        const int r = row_of(i);
         if (r >= R0 && r < R0 + B) {
 #pragma unroll
           for (int c = 0; c < LG; ++c) Ts[r - R0][c] = r < n ? acc[i][c] : cx<P>{P(0), P(0)};
         }
       }
-      const cx<P>* __restrict__ inv = Di + ((long long)q * 2 + pass) * B * B;
-      for (int e = tid; e < B * B; e += kTrsvThreads) {
-        const int i = e / B, k = e - i * B;
-        Ds[i][k] = k < nr ? inv[e] : cx<P>{P(0), P(0)};
+      // the block's inverse arrived in registers during the previous block
+      // (identity-padded past nr, so no masking is needed)
+#pragma unroll
+      for (int u = 0; u < DPT; ++u) {
+        const int e = tid + u * kTrsvThreads;
+        Ds[e / B][e % B] = cx<P>{dreg[u].re, dreg[u].im};
       }
       __syncthreads();
       // 2. x_q = Dinv_q t
@@ -128,11 +176,26 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
         Xs[i][c] = x;
       }
       __syncthreads();
+      // prefetch the next block's inverse (forward order in pass 0, then
+      // backward in pass 1)
+      {
+        const bool last = pass == 1 && qq + 1 == nblk;
+        const int nq = pass == 0 ? (qq + 1 < nblk ? q + 1 : nblk - 1) : q - 1;
+        const int npass = (pass == 0 && qq + 1 == nblk) ? 1 : pass;
+        if (!last) {
+          const cx<P>* __restrict__ nx = Di + ((long long)nq * 2 + npass) * B * B;
+#pragma unroll
+          for (int u = 0; u < DPT; ++u) {
+            const cx<P>* src = nx + tid + u * kTrsvThreads;
+            dreg[u] = cx<P>{src->re, src->im};
+          }
+        }
+      }
       // 3. rows still pending subtract (factor segment) * x_q; the block's own
       // rows take their solution
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        const int r = tid + i * kTrsvThreads;
+        const int r = row_of(i);
         if (r >= n) continue;
         if (r >= R0 && r < R0 + nr) {
 #pragma unroll
@@ -142,20 +205,42 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
         const bool pending = pass == 0 ? r >= R0 + nr : r < R0;
         if (!pending) continue;
         const cx<P>* __restrict__ seg = T + rowoff[i] + R0;
-        if (nr == B) {  // full block: whole 64-wide segment, vector loads
-          for (int k0 = 0; k0 < B; k0 += 16) {
-            cx<P> lv[16];
-            load_seg16(seg + k0, lv);
+        if (nr == B) {  // full block: prefetched part first
 #pragma unroll
-            for (int u = 0; u < 16; ++u)
+          for (int u = 0; u < PF; ++u)
 #pragma unroll
-              for (int c = 0; c < LG; ++c) acc[i][c] = fms(acc[i][c], lv[u], Xs[k0 + u][c]);
-          }
+            for (int c = 0; c < LG; ++c) acc[i][c] = fms(acc[i][c], pre[i][u], Xs[u][c]);
         } else {  // ragged last block
           for (int k = 0; k < nr; ++k) {
             const cx<P> lv = seg[k];
 #pragma unroll
             for (int c = 0; c < LG; ++c) acc[i][c] = fms(acc[i][c], lv, Xs[k][c]);
+          }
+        }
+      }
+      // rest of the full-block segments, 16 columns at a time, every row's
+      // loads issued together
+      if (nr == B) {
+#pragma unroll
+        for (int i0 = 0; i0 < RPT; i0 += GR) {
+          for (int k0 = PF; k0 < B; k0 += 16) {
+            cx<P> lv[GR][16];
+#pragma unroll
+            for (int g = 0; g < GR; ++g) {
+              const int r = row_of(i0 + g);
+              if (r < n && (pass == 0 ? r >= R0 + B : r < R0)) load_seg16(T + rowoff[i0 + g] + R0 + k0, lv[g]);
+            }
+#pragma unroll
+            for (int g = 0; g < GR; ++g) {
+              const int r = row_of(i0 + g);
+              const bool pending = r < n && (pass == 0 ? r >= R0 + B : r < R0);
+              if (pending) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+#pragma unroll
+                  for (int c = 0; c < LG; ++c) acc[i0 + g][c] = fms(acc[i0 + g][c], lv[g][u], Xs[k0 + u][c]);
+              }
+            }
           }
         }
       }
@@ -166,7 +251,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
   // acc now holds x for the owned rows: store to Y (FP64) and take maxima
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    const int r = tid + i * kTrsvThreads;
+    const int r = row_of(i);
     if (r < n) {
       c128* y = Y + D.offY + (long long)r * D.N * L + (long long)j * L + c0;
 #pragma unroll
@@ -238,22 +323,25 @@ template hipError_t solve_run<double>(const SolvePlan&, const ProbDesc*, const M
 // Column-group size: enough groups to occupy the device when there are few
 // matrices, bounded by L (the group is an unrolled register tile).
 static int pick_lg(int nmat, int L) {
-  // Each column group re-reads the node's factor, so prefer one group per
-  // node; split only when there are too few nodes to occupy the device.
+  // Each column group re-reads the node's factor (from the XCD's L2), so
+  // prefer few groups per node; split only when there are too few nodes to
+  // occupy the device.
   int lg = 16;
   while (lg > 4 && lg >= 2 * L) lg >>= 1;
   while (lg > 4 && (long long)nmat * ceil_div(L, lg) < 256) lg >>= 1;
   return lg;
 }
 
-void SolvePlan_build(SolvePlan& sp, std::vector<int>& /*buf*/, const std::vector<MatDesc>& sorted, int L,
+void SolvePlan_build(SolvePlan& sp, std::vector<int>& /*buf*/, const std::vector<MatDesc>& sorted, int L, int prec,
                      std::vector<long long>& dinv_off, long long& dinv_elems) {
   sp.nmat = (int)sorted.size();
   const int nmax = sorted.empty() ? 0 : sorted[0].n;
   sp.rpt = nmax <= 512 ? 1 : nmax <= 1024 ? 2 : nmax <= 2048 ? 4 : 8;
   sp.lg = pick_lg(sp.nmat, L);
-  // accumulators live in registers: at most 32 complex values per thread
-  while (sp.lg > 4 && sp.rpt * sp.lg > 32) sp.lg >>= 1;
+  // accumulators live in registers: at most 32 complex FP32 (8 complex FP64)
+  // values per thread
+  const int cap = prec == NEP_PREC_FP64 ? 8 : 32;
+  while (sp.lg > 4 && sp.rpt * sp.lg > cap) sp.lg >>= 1;
   sp.groups = ceil_div(L, sp.lg);
   dinv_off.clear();
   long long off = 0;

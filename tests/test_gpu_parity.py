@@ -78,7 +78,10 @@ def test_config0_moments(nep, prec):
     print(prec, st)
     _check_moments(Sg, So)
     if prec == "mixed":
-        assert st["n_unconverged"] == 0
+        # the complex-FP32 factorization alone must carry the refinement: no
+        # FP64 fallback, few sweeps
+        assert st["n_unconverged"] == 0 and st["n_fallback"] == 0
+        assert st["refine_sweeps"] <= 3
         assert st["max_rel_residual"] <= 1e-14
 
 
@@ -98,6 +101,8 @@ def test_ragged_sizes_complex_terms(nep, n):
     for prec in ("mixed", "fp64"):
         _, _, Sg, st = _run_moments(nep, prob, con, N, L, K, V, prec)
         _check_moments(Sg, So, 1e-10 if prec == "fp64" else 1e-9)
+        if prec == "mixed":
+            assert st["n_fallback"] == 0 and st["refine_sweeps"] <= 3, st
 
 
 def test_config0_extract(nep):
@@ -126,6 +131,8 @@ def test_config1_full_size_moments(nep):
         _, _, Sg, st = _run_moments(nep, p, con, cfg["N"], cfg["L"], cfg["K"], cfg["V"], prec)
         print(prec, st)
         _check_moments(Sg, So)
+        if prec == "mixed":
+            assert st["n_fallback"] == 0 and st["refine_sweeps"] <= 3, st
 
 
 def test_config2_reduced_extract(nep):
