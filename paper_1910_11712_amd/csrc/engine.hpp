@@ -80,7 +80,8 @@ struct SolvePlan {
 
 struct ProblemTables {
   Table assemble;  // element tiles per problem
-  Table resid;     // residual GEMM tiles per problem
+  Table resid;       // residual GEMM tiles per problem with complex terms (64 x 64)
+  Table resid_real;  // residual GEMM tiles per problem with real terms only (128 x 64)
   Table moments;   // n*L tiles per problem
 };
 
@@ -103,8 +104,8 @@ void SolvePlan_build(SolvePlan& sp, std::vector<int>& buf, const std::vector<Mat
                      std::vector<long long>& dinv_off, long long& dinv_elems);
 hipError_t solve_configure();
 
-hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const NodeArrays& na, const c128* Y,
-                     c128* R, IrState ir, int nnodes, hipStream_t st);
+hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const Table& tr, const NodeArrays& na,
+                     const c128* Y, c128* R, IrState ir, int nnodes, hipStream_t st);
 hipError_t ir_control(const ProbDesc* pd, const NodeArrays& na, IrState ir, int nnodes, int sweep, double tol,
                       hipStream_t st);
 hipError_t ir_reset(IrState ir, int nnodes, hipStream_t st);

@@ -177,7 +177,8 @@ bool MomentsPlan::matches(const std::vector<PlanProblem>& probs, const PlanOptio
   if ((int)probs.size() != nprob) return false;
   if (o.N != opt.N || o.L != opt.L || o.K != opt.K || o.prec != opt.prec) return false;
   for (int p = 0; p < nprob; ++p)
-    if (probs[p].op->n != hpd_[p].n || probs[p].op->ell != hpd_[p].ell) return false;
+    if (probs[p].op->n != hpd_[p].n || probs[p].op->ell != hpd_[p].ell || probs[p].op->a_cplx != hpd_[p].a_cplx)
+      return false;
   return true;
 }
 
@@ -267,15 +268,18 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   hprefix_.clear();
   SolvePlan_build(sp_, hprefix_, sorted_, o.L, o.prec, dinv_off_, dinv_elems_);
   {
-    std::vector<int> ca, cr, cm;
+    std::vector<int> ca, cr, crr, cm;
     for (int p = 0; p < nprob; ++p) {
       const long long n = hpd_[p].n;
+      const bool cplx = probs[p].op->a_cplx != 0;
       ca.push_back((int)ceil_div_ll(n * n, 256));
-      cr.push_back(ceil_div((int)n, 64) * ceil_div(2 * o.N * o.L, 64));
+      cr.push_back(cplx ? ceil_div((int)n, 64) * ceil_div(2 * o.N * o.L, 64) : 0);
+      crr.push_back(cplx ? 0 : ceil_div((int)n, 128) * ceil_div(2 * o.N * o.L, 64));
       cm.push_back(ceil_div((int)n * o.L, 256) * ceil_div(2 * o.K, 8));  // (row, column) blocks x moment groups
     }
     build_prefix(hprefix_, pt_.assemble, ca);
     build_prefix(hprefix_, pt_.resid, cr);
+    build_prefix(hprefix_, pt_.resid_real, crr);
     build_prefix(hprefix_, pt_.moments, cm);
   }
 
@@ -377,7 +381,7 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
   sweeps_run_ = 0;
   if (opt.max_refine > 0) {
     for (int s = 0; s <= opt.max_refine; ++s) {
-      NEP_HIP(resid_run(pd, pre, pt_.resid, na_, Y, R, ir_, nnodes, st));
+      NEP_HIP(resid_run(pd, pre, pt_.resid, pt_.resid_real, na_, Y, R, ir_, nnodes, st));
       NEP_HIP(ir_control(pd, na_, ir_, nnodes, s, opt.tol, st));
       sweeps_run_ = s;
       if (eager) {
@@ -438,7 +442,7 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
   NEP_HIP(solve_run<double>(sp_, pd, md, na_, T, drows_.as<int>(), Dinv, doff, nullptr, dY_.as<c128>(), false,
                             skip, ir_, st));
   // check the residual of the re-solved nodes once
-  NEP_HIP(resid_run(pd, pre, pt_.resid, na_, dY_.as<c128>(), dR_.as<c128>(), ir_, nnodes, st));
+  NEP_HIP(resid_run(pd, pre, pt_.resid, pt_.resid_real, na_, dY_.as<c128>(), dR_.as<c128>(), ir_, nnodes, st));
   NEP_HIP(ir_control(pd, na_, ir_, nnodes, opt.max_refine + 1, opt.tol, st));
   fallback_pending_ = true;
   return NEP_OK;

@@ -160,16 +160,168 @@ __global__ __launch_bounds__(256) void k_resid(const ProbDesc* __restrict__ pd, 
   }
 }
 
-hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const NodeArrays& na, const c128* Y,
-                     c128* R, IrState ir, int /*nnodes*/, hipStream_t st) {
-  if (t.total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_resid<false>, dim3(xcd_grid(t.total)), dim3(256), 0, st, pd, prefix + t.off, t.cnt, t.total,
-                     na, Y, R, ir);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_resid<true>, dim3(xcd_grid(t.total)), dim3(256), 0, st, pd, prefix + t.off, t.cnt, t.total,
-                     na, Y, R, ir);
-  return hipGetLastError();
+// ---------------------------------------------------------------------------
+// Real A_i (every term real): 128 x 64 tiles (128 rows, 32 complex columns)
+// per group of 4 waves, each wave 64 x 32 as 4 x 2 blocks of
+// v_mfma_f64_16x16x4f64.  The next stage's A and f_i(z_j) Y tiles are loaded
+// into registers while the current stage runs from LDS (double-buffered).
+// ---------------------------------------------------------------------------
+constexpr int kR2TM = 128, kR2TQ = 64, kR2KC = 16;
+
+__global__ __launch_bounds__(256, 2) void k_resid_real(const ProbDesc* __restrict__ pd, const int* __restrict__ prefix,
+                                                       int cnt, int total, NodeArrays na, const c128* __restrict__ Y,
+                                                       c128* __restrict__ R, IrState ir) {
+  const int v = xcd_remap(blockIdx.x, gridDim.x, total);
+  if (v < 0) return;
+  const int p = find_slot(prefix, cnt, v);
+  const ProbDesc& D = pd[p];
+  const int t = v - prefix[p];
+  const int n = D.n, L = D.L, NL = D.N * D.L, Q = 2 * NL;
+  const int tiles_q = (Q + kR2TQ - 1) / kR2TQ;
+  const int tm = t / tiles_q, tq = t - tm * tiles_q;
+  const int row0 = tm * kR2TM, q0 = tq * kR2TQ;
+  {
+    const int cc0 = q0 / 2, cc1 = min(NL, cc0 + kR2TQ / 2) - 1;
+    bool any = false;
+    for (int j = cc0 / L; j <= cc1 / L; ++j) any |= (ir.conv[D.node0 + j] == 0);
+    if (!any) return;
+  }
+  __shared__ double As[2][kR2KC][kR2TM + 1];
+  __shared__ double Bs[2][kR2KC][kR2TQ + 2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 64, wq = (wave & 1) * 32;
+  const c128* __restrict__ Yp = Y + D.offY;
+
+  // staging roles: A (row tid/8 + 32u, k pair tid%8), B (k row tid/32 + 8u, complex column tid%32)
+  const int akp = tid & 7, bcl = tid & 31;
+  const int bcc = q0 / 2 + bcl;
+  const bool bcol_ok = bcc < NL;
+  const int bnode = bcol_ok ? bcc / L : 0;
+
+  doublex4 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+
+  for (int term = 0; term < D.ell; ++term) {
+    if (D.a_is_diag[term]) continue;  // applied in the epilogue
+    const double* __restrict__ A = reinterpret_cast<const double*>(D.A[term]);
+    const c128 f = bcol_ok ? na.fz[(long long)(D.node0 + bnode) * kMaxTerms + term] : c128{0.0, 0.0};
+    double ra[4][2];
+    c128 rb[2];
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int gr = row0 + (tid >> 3) + 32 * u, gk = k0 + 2 * akp;
+        const double* src = A + (long long)min(gr, n - 1) * n;
+        const double a0 = src[min(gk, n - 1)], a1 = src[min(gk + 1, n - 1)];
+        ra[u][0] = (gr < n && gk < n) ? a0 : 0.0;
+        ra[u][1] = (gr < n && gk + 1 < n) ? a1 : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int s = k0 + (tid >> 5) + 8 * u;
+        const c128 y = Yp[(long long)min(s, n - 1) * NL + (bcol_ok ? bcc : 0)];
+        rb[u] = (s < n && bcol_ok) ? f * y : c128{0.0, 0.0};
+      }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = (tid >> 3) + 32 * u;
+        As[buf][2 * akp][r] = ra[u][0];
+        As[buf][2 * akp + 1][r] = ra[u][1];
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = (tid >> 5) + 8 * u;
+        Bs[buf][k][2 * bcl] = rb[u].re;
+        Bs[buf][k][2 * bcl + 1] = rb[u].im;
+      }
+    };
+    const int nk = (n + kR2KC - 1) / kR2KC;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int ks = 0; ks < nk; ++ks) {
+      const int buf = ks & 1;
+      if (ks + 1 < nk) load((ks + 1) * kR2KC);
+#pragma unroll
+      for (int kk = 0; kk < kR2KC; kk += 4) {
+        double af[4], bf[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) af[i] = As[buf][kk + (lane >> 4)][wr + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bf[j] = Bs[buf][kk + (lane >> 4)][wq + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+      }
+      if (ks + 1 < nk) {
+        store(buf ^ 1);
+        __syncthreads();
+      }
+    }
+    __syncthreads();  // the next term restages buffer 0
+  }
+  // epilogue: lane l, reg r -> row (l/16) + 4r, real column l%16 of the block
+  const double* __restrict__ Yd = reinterpret_cast<const double*>(Yp);
+  double* __restrict__ Rd = reinterpret_cast<double*>(R + D.offY);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int q = q0 + wq + j * 16 + (lane & 15);
+    const int cc = q >> 1, tcomp = q & 1;
+    const int node = cc / L, c = cc - node * L;
+    double cm = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + wr + i * 16 + (lane >> 4) + 4 * r;
+        double val = 0.0;
+        if (gr < n && q < Q) {
+          const c128 vv = D.V[(long long)c * n + gr];
+          double s = acc[i][j][r];
+          for (int term = 0; term < D.ell; ++term) {
+            if (!D.a_is_diag[term]) continue;
+            const c128 y = {Yd[2 * ((long long)gr * NL + cc)], Yd[2 * ((long long)gr * NL + cc) + 1]};
+            const c128 fz = na.fz[(long long)(D.node0 + node) * kMaxTerms + term];
+            const c128 dy = (fz * D.Adiag[term][gr]) * y;
+            s += tcomp ? dy.im : dy.re;
+          }
+          val = (tcomp ? vv.im : vv.re) - s;
+          Rd[(long long)gr * Q + q] = val;
+        }
+        const double other = __shfl_xor(val, 1, 64);
+        cm = fmax(cm, sqrt(val * val + other * other));
+      }
+    cm = fmax(cm, __shfl_xor(cm, 16, 64));
+    cm = fmax(cm, __shfl_xor(cm, 32, 64));
+    if (lane < 16 && tcomp == 0 && q < Q)
+      atomicMax(&ir.rnorm[(long long)(D.node0 + node) * kNormStride + c], (unsigned long long)__double_as_longlong(cm));
+  }
+}
+
+// t: tiles of the complex-term kernel (64 x 64); tr: tiles of the real-term
+// kernel (128 x 64).  A problem counts in exactly one of them.
+hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const Table& tr, const NodeArrays& na,
+                     const c128* Y, c128* R, IrState ir, int /*nnodes*/, hipStream_t st) {
+  if (tr.total > 0) {
+    hipLaunchKernelGGL(k_resid_real, dim3(xcd_grid(tr.total)), dim3(256), 0, st, pd, prefix + tr.off, tr.cnt,
+                       tr.total, na, Y, R, ir);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (t.total > 0) {
+    hipLaunchKernelGGL(k_resid<true>, dim3(xcd_grid(t.total)), dim3(256), 0, st, pd, prefix + t.off, t.cnt, t.total,
+                       na, Y, R, ir);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
