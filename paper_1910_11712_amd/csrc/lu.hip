@@ -1108,6 +1108,8 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
     int nact = 0;
     while (nact < nmat && sorted[nact].n > k0) ++nact;
     s.nact = nact;
+    s.nwide = 0;
+    while (s.nwide < nact && sorted[s.nwide].n - k0 > kPanelThreads) ++s.nwide;
     int rmax = sorted[0].n - k0;
     s.rpt = rmax <= 512 ? 1 : rmax <= 1024 ? 2 : rmax <= 2048 ? 4 : 8;
     // tile prefixes of the block-row product (U12) and of the trailing
@@ -1161,7 +1163,11 @@ static hipError_t lu_panel_step(const LuPlan& plan, const LuPlan::Step& s, const
                                 int* info, const int* skip, cx<P>* Linv, cx<P>* Dinv, const long long* dinv_off,
                                 hipStream_t st, hipStream_t side, hipEvent_t ev_side) {
   hipError_t e;
-  if ((e = launch_panel<P>(s.rpt, s.nact, d_md, s.k0, plan.jb, T, rows, info, skip, st)) != hipSuccess) return e;
+  if (s.nwide > 0 && (e = launch_panel<P>(s.rpt, s.nwide, d_md, s.k0, plan.jb, T, rows, info, skip, st)) != hipSuccess)
+    return e;
+  if (s.nwide < s.nact &&
+      (e = launch_panel<P>(1, s.nact - s.nwide, d_md + s.nwide, s.k0, plan.jb, T, rows, info, skip, st)) != hipSuccess)
+    return e;
   hipStream_t su = st;
   if (side != nullptr) {
     if ((e = hipEventRecord(ev_side, st)) != hipSuccess) return e;
@@ -1234,6 +1240,9 @@ static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int 
 // rest of the update runs, so that update addresses its A and C rows through
 // a copy of the row map taken before the fork: the rows it touches form the
 // same set under either order, and the panel writes only its own columns.
+// The L11 inverses are kept in two halves of Linv by step parity: the next
+// panel's inverse is written while the rest of step k's U12 product still
+// reads step k's.
 template <typename P>
 hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* rows_snap,
                   int rows_total, int* info, const int* skip, cx<P>* Linv, cx<P>* Dinv, const long long* dinv_off,
@@ -1246,31 +1255,33 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
   const int nsteps = (int)plan.steps.size();
   if (nsteps == 0) return hipSuccess;
   const bool lookahead = aux != nullptr && rows_snap != nullptr;
-  if ((e = lu_panel_step<P>(plan, plan.steps[0], d_md, T, rows, info, skip, Linv, Dinv, dinv_off, st, side, ls.ev_side[0])) != hipSuccess)
+  const long long half = (long long)plan.nmat * kLuMaxJB * kLuMaxJB;
+  auto linv = [&](int k) { return Linv + (k & 1) * half; };
+  if ((e = lu_panel_step<P>(plan, plan.steps[0], d_md, T, rows, info, skip, linv(0), Dinv, dinv_off, st, side,
+                            ls.ev_side[0])) != hipSuccess)
     return e;
   for (int k = 0; k < nsteps; ++k) {
     const auto& s = plan.steps[k];
     const bool has_next = k + 1 < nsteps;
-    if ((e = lu_update_part<P>(plan, s, 0, d_md, d_prefix, T, rows, rows, skip, Linv, st)) != hipSuccess) return e;
+    if ((e = lu_update_part<P>(plan, s, 0, d_md, d_prefix, T, rows, rows, skip, linv(k), st)) != hipSuccess) return e;
     const bool overlap = lookahead && has_next && s.tot_gemm[1] > 0;
     if (overlap) {
       hipLaunchKernelGGL(k_copy_int, dim3(ceil_div(rows_total, 256)), dim3(256), 0, st, rows, rows_snap, rows_total);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       if ((e = hipEventRecord(ev_fork, st)) != hipSuccess) return e;
       if ((e = hipStreamWaitEvent(aux, ev_fork, 0)) != hipSuccess) return e;
-      if ((e = lu_panel_step<P>(plan, plan.steps[k + 1], d_md, T, rows, info, skip, Linv, Dinv, dinv_off, aux, side,
-                                  ls.ev_side[(k + 1) & 1])) !=
-          hipSuccess)
+      if ((e = lu_panel_step<P>(plan, plan.steps[k + 1], d_md, T, rows, info, skip, linv(k + 1), Dinv, dinv_off,
+                                aux, side, ls.ev_side[(k + 1) & 1])) != hipSuccess)
         return e;
       if ((e = hipEventRecord(ev_join, aux)) != hipSuccess) return e;
     }
-    if ((e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, rows, overlap ? rows_snap : rows, skip, Linv, st)) !=
+    if ((e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, rows, overlap ? rows_snap : rows, skip, linv(k), st)) !=
         hipSuccess)
       return e;
     if (has_next) {
       if (overlap) {
         if ((e = hipStreamWaitEvent(st, ev_join, 0)) != hipSuccess) return e;
-      } else if ((e = lu_panel_step<P>(plan, plan.steps[k + 1], d_md, T, rows, info, skip, Linv, Dinv, dinv_off,
+      } else if ((e = lu_panel_step<P>(plan, plan.steps[k + 1], d_md, T, rows, info, skip, linv(k + 1), Dinv, dinv_off,
                                        st, side, ls.ev_side[(k + 1) & 1])) != hipSuccess) {
         return e;
       }

@@ -14,6 +14,10 @@ constexpr int kSolveBlkLu = 64;  // diagonal-block size of the stored inverses (
 struct LuPlan {
   struct Step {
     int k0, nact, rpt;
+    // matrices [0, nwide) have more than one panel row per thread; the rest
+    // take the single-row panel, so the leaf width (and with it the rounding)
+    // of a matrix's panel depends on that matrix alone, not on its batch
+    int nwide;
     // tiles of the U12 product and of the trailing update; part 0 is the
     // first tile column (it holds the next panel), part 1 the rest
     int off_trsm[2], tot_trsm[2];
@@ -42,7 +46,8 @@ KernelProf& kernel_prof();
 int lu_jb(int prec);
 hipError_t lu_configure();
 
-// Linv: workspace of nact * kLuMaxJB^2 elements (inverses of the L11 blocks).
+// Linv: workspace of 2 * nmat * kLuMaxJB^2 elements (inverses of the L11 blocks,
+// one half per step parity).
 // Dinv/dinv_off: per matrix, the inverses of the 64 x 64 diagonal blocks of L
 // and U ([blk][0: L, 1: U][64][64]), written as the panels complete.
 // Streams and events of the look-ahead schedule: the next panel runs on aux

