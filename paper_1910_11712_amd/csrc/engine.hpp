@@ -13,6 +13,7 @@ namespace nep {
 constexpr int kMaxTerms = 16;
 constexpr int kMaxMoments = 32;  // 2K
 constexpr int kSolveBlk = 64;    // triangular-solve block rows
+constexpr int kFallbackSweeps = 2;  // FP64 refinement sweeps after an FP64 re-solve
 constexpr int kNormStride = 64;  // per-node stride of the column-norm arrays (L <= 64)
 
 // Per-problem descriptor (device resident).

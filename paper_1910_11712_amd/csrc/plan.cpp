@@ -399,7 +399,10 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
 }
 
 // FP64 re-solve of the nodes whose refinement did not converge: assemble in
-// complex FP64, factor on the FP64 matrix cores, solve, overwrite Y.
+// complex FP64, factor on the FP64 matrix cores, solve, overwrite Y, then
+// refine with the FP64 factor (fixed-precision refinement: a backward-stable
+// LU's solution can sit above a tolerance near unit roundoff on large,
+// ill-conditioned nodes; one or two sweeps bring it to that level).
 template <typename P>
 nep_status MomentsPlan::run_fallback(hipStream_t st) {
   static_assert(sizeof(P) == 8, "fallback runs in FP64");
@@ -441,9 +444,16 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
                          dinfo_.as<int>(), skip, dlinv64_.as<c128>(), Dinv, doff, st, ls_));
   NEP_HIP(solve_run<double>(sp_, pd, md, na_, T, drows_.as<int>(), Dinv, doff, nullptr, dY_.as<c128>(), false,
                             skip, ir_, st));
-  // check the residual of the re-solved nodes once
-  NEP_HIP(resid_run(pd, pre, pt_.resid, pt_.resid_real, na_, dY_.as<c128>(), dR_.as<c128>(), ir_, nnodes, st));
-  NEP_HIP(ir_control(pd, na_, ir_, nnodes, opt.max_refine + 1, opt.tol, st));
+  for (int s = 0;; ++s) {
+    NEP_HIP(resid_run(pd, pre, pt_.resid, pt_.resid_real, na_, dY_.as<c128>(), dR_.as<c128>(), ir_, nnodes, st));
+    NEP_HIP(ir_control(pd, na_, ir_, nnodes, opt.max_refine + 1 + s, opt.tol, st));
+    if (s == kFallbackSweeps) break;
+    NEP_HIP(hipMemcpyAsync(hcounter_, ir_.counters, sizeof(int), hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipStreamSynchronize(st));
+    if (hcounter_[0] == 0) break;
+    NEP_HIP(solve_run<double>(sp_, pd, md, na_, T, drows_.as<int>(), Dinv, doff, dR_.as<c128>(), dY_.as<c128>(),
+                              true, ir_.conv, ir_, st));
+  }
   fallback_pending_ = true;
   return NEP_OK;
 }

@@ -309,3 +309,38 @@ def test_ragged_batch_large_sizes(nep, prec):
         assert np.array_equal(Sg, singles[k]), (k, sizes[k], np.abs(Sg - singles[k]).max(), stats[k])
     So = oracle.ciss_moments(probs[1], con, N, K, Vs[1])
     _check_moments(nep.moments_to_numpy(Ss[1]), So, 1e-10 if prec == "fp64" else 1e-9)
+
+
+def test_mixed_fallback_refined_on_ill_conditioned_nodes(nep):
+    """Loaded string n=1912 (sigma 1.413, A scale 1.557) with the serving
+    contour around its third eigenvalue: FP32-factor refinement stalls at
+    some nodes (kappa(T(z)) ~ 1e6), those nodes are re-solved in FP64 and
+    refined with the FP64 factor to the tolerance; the eigenvalue inside
+    matches the oracle."""
+    from workloads.problems import _string_pencil_value
+    n, sig, s = 1912, 1.4132774252668214, 1.5572971183471138
+    prob = wl.loaded_string(n, sigma=sig, a_scale=s)
+    lam = [_string_pencil_value(n, j, s) for j in (2, 3, 4)]
+    con = Contour.circle(lam[1], 0.5 * min(lam[1] - lam[0], lam[2] - lam[1]))
+    N, L, K = 32, 8, 2
+    V = wl.probes(n, L, 330947230)
+    op, S, Sg, st = _run_moments(nep, prob, con, N, L, K, V, "mixed")
+    print(st)
+    assert st["n_fallback"] >= 1 and st["n_unconverged"] == 0, st
+    assert 0.0 < st["max_rel_residual"] <= 1e-14, st
+    So = oracle.ciss_moments(prob, con, N, K, V)
+    # S_1 cancels by ~1e6 here and kappa ~ 1e6 magnifies any backward-stable
+    # solver's error, so the moments are held to the plain FP64 path's own
+    # distance from the oracle rather than to a fixed 1e-10
+    _, _, S64, _ = _run_moments(nep, prob, con, N, L, K, V, "fp64")
+    for p in range(2 * K):
+        e_mixed, e_64 = _rel_fro(Sg[p], So[p]), _rel_fro(S64[p], So[p])
+        print(p, e_mixed, e_64)
+        assert e_mixed <= 10.0 * max(e_64, 1e-12), (p, e_mixed, e_64)
+    ro = oracle.extract(prob, con, So, K)
+    r = op.extract(con, S, N, L, K, prec="mixed", max_eigs=16)
+    ref = np.sort_complex(ro["lam"][ro["inside"]])
+    got = np.sort_complex(r["lam"][r["inside"]])
+    assert len(ref) == len(got) == 1
+    assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-10
+    assert np.all(r["eta"][r["inside"]] <= 1e-10)
