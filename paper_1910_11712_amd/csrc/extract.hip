@@ -354,8 +354,8 @@ static nep_status extract(Split& h, const nep_contour* g, const nep_ciss_opts* o
   while (m < KL && sv[m] > tol) ++m;
   *m_out = m;
   NEP_CHECK(m > 0, NEP_ERR_RANK, "all moments vanish: no eigenvalue inside the contour is visible");
-  NEP_CHECK(m < KL, NEP_ERR_RANK, "moment rank %d == K*L: the contour holds more eigenvalues than K*L=%d can "
-            "resolve; increase L or K", m, KL);
+  NEP_CHECK(m < KL, NEP_ERR_RANK, "moment rank %d == K*L: more eigenvalues inside or near the contour pass the "
+            "rank threshold than K*L=%d can resolve; increase L or K (or N)", m, KL);
   NEP_CHECK(m <= e->max_eigs, NEP_ERR_ARG, "rank %d exceeds max_eigs %d", m, e->max_eigs);
   // V0 = Q [Ur0; 0]
   NEP_TRY(grow(w.V0, sizeof(c128) * M * m));
