@@ -56,40 +56,50 @@ __global__ void k_lu_init(const MatDesc* __restrict__ md, int nmat, int* __restr
 template <typename P>
 __device__ __forceinline__ P shfl_xor_p(P v, int m) { return __shfl_xor(v, m, 64); }
 
-// Pivot key of a candidate: the bits of its modulus (non-negative FP32, so
-// they order like the values) above the complement of its row, so the
-// largest key has the largest modulus and, among equal moduli, the lowest row.
-__device__ __forceinline__ unsigned long long pivot_key(float v, int row) {
-  return ((unsigned long long)__float_as_uint(v) << 32) | (0xffffffffu - (unsigned)row);
-}
-__device__ __forceinline__ int key_row(unsigned long long k) { return (int)(0xffffffffu - (unsigned)k); }
+// Component-wise read / write of a complex element: whole-struct copies of
+// the register-resident leaf are lowered as 64-bit moves, which keeps the
+// leaf array out of registers.
+template <typename P>
+__device__ __forceinline__ cx<P> cget(const cx<P>& x) { return cx<P>{x.re, x.im}; }
+template <typename P>
+__device__ __forceinline__ void cput(cx<P>& d, const cx<P> v) { d.re = v.re; d.im = v.im; }
 
-// Maximum of a 64-bit key over the wave with DPP row operations (quad
-// swaps, half-row and row mirrors, then the row broadcasts that carry rows
-// 0-2 into row 3); lane 63 holds the result, which is returned uniform.
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
-  int hi = (int)(k >> 32), lo = (int)(unsigned)k;
-  auto step = [&](int oh, int ol) {
-    const unsigned uh = (unsigned)oh, ul = (unsigned)ol, ch = (unsigned)hi, cl = (unsigned)lo;
-    const bool t = uh > ch || (uh == ch && ul > cl);
-    hi = t ? oh : hi;
-    lo = t ? ol : lo;
-  };
-  step(__builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false),   // quad_perm [1,0,3,2]
-       __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false));
-  step(__builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false),   // quad_perm [2,3,0,1]
-       __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false));
-  step(__builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false),  // row_half_mirror
-       __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false));
-  step(__builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false),  // row_mirror
-       __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false));
-  step(__builtin_amdgcn_update_dpp(0, hi, 0x142, 0xA, 0xF, false),  // row_bcast15 -> rows 1, 3
-       __builtin_amdgcn_update_dpp(0, lo, 0x142, 0xA, 0xF, false));
-  step(__builtin_amdgcn_update_dpp(0, hi, 0x143, 0xC, 0xF, false),  // row_bcast31 -> rows 2, 3
-       __builtin_amdgcn_update_dpp(0, lo, 0x143, 0xC, 0xF, false));
-  const unsigned h = (unsigned)__builtin_amdgcn_readlane(hi, 63);
-  const unsigned l = (unsigned)__builtin_amdgcn_readlane(lo, 63);
-  return ((unsigned long long)h << 32) | l;
+// Pivot key of a candidate: the bits of its modulus |Re|+|Im| (non-negative,
+// so the bits order like the values) plus one, 0 for "no candidate".  FP32
+// keys are exact; FP64 keys keep the high word of the double (sign, exponent
+// and 20 mantissa bits), so moduli within 2^-20 of each other tie.  Ties go to
+// the lowest row, which keeps the choice deterministic.
+__device__ __forceinline__ unsigned pivot_key(float v) { return __float_as_uint(v) + 1u; }
+__device__ __forceinline__ unsigned pivot_key(double v) {
+  return (unsigned)((unsigned long long)__double_as_longlong(v) >> 32) + 1u;
+}
+
+// Maximum / minimum of a 32-bit value over the wave with DPP row operations
+// (quad swaps, half-row and row mirrors, then the row broadcasts that carry
+// rows 0-2 into row 3); lane 63 holds the result, returned uniform.  Lanes a
+// broadcast does not reach keep their value (the "old" operand is the
+// operation's identity).
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  int x = (int)v;
+  auto mx = [](int a, int b) { return (int)max((unsigned)a, (unsigned)b); };
+  x = mx(x, __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  x = mx(x, __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  x = mx(x, __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  x = mx(x, __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false));  // row_mirror
+  x = mx(x, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false));  // row_bcast15 -> rows 1, 3
+  x = mx(x, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false));  // row_bcast31 -> rows 2, 3
+  return (unsigned)__builtin_amdgcn_readlane(x, 63);
+}
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
+  int x = (int)v;
+  auto mn = [](int a, int b) { return (int)min((unsigned)a, (unsigned)b); };
+  x = mn(x, __builtin_amdgcn_update_dpp(-1, x, 0xB1, 0xF, 0xF, false));
+  x = mn(x, __builtin_amdgcn_update_dpp(-1, x, 0x4E, 0xF, 0xF, false));
+  x = mn(x, __builtin_amdgcn_update_dpp(-1, x, 0x141, 0xF, 0xF, false));
+  x = mn(x, __builtin_amdgcn_update_dpp(-1, x, 0x140, 0xF, 0xF, false));
+  x = mn(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xA, 0xF, false));
+  x = mn(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xC, 0xF, false));
+  return (unsigned)__builtin_amdgcn_readlane(x, 63);
 }
 
 // Panel columns right of a finished leaf (columns c0+wc .. k0+jb-1): the
@@ -108,7 +118,7 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
   if (nr > 0) {
     if (tid < wc) {
 #pragma unroll
-      for (int w = 0; w < W; ++w) Ltop[tid][w] = top[w];
+      for (int w = 0; w < W; ++w) cput(Ltop[tid][w], cget(top[w]));
     }
     __syncthreads();
     static_assert(kLuMaxJB <= kPanelThreads, "one thread per right-hand column of the panel");
@@ -122,7 +132,8 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
       for (int w = 0; w < W; ++w) {
         if (w < wc) {
 #pragma unroll
-          for (int v = 0; v < w; ++v) x[w] = fms(x[w], Ltop[w][v], x[v]);
+          for (int v = 0; v < W; ++v)
+            if (v < w) x[w] = fms(x[w], Ltop[w][v], x[v]);
           T[(long long)rat[c0 + w - k0] * ld + rc0 + j] = x[w];
           Utop[w][j] = x[w];
         }
@@ -299,37 +310,45 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
   int* __restrict__ rowg = rowb + d.offRow;
 
   __shared__ int rat[kMaxPanelRows];
-  __shared__ P redv[2][kPanelThreads / 64];
-  __shared__ int redi[2][kPanelThreads / 64];
-  __shared__ unsigned long long redk[2][kPanelThreads / 64];
-  __shared__ cx<P> xbuf[2][2][W];
-  __shared__ cx<P> wrow[2][kPanelThreads / 64][W];
+  __shared__ __align__(16) uint2 redk[2][kPanelThreads / 64];  // per wave: (key, row) of its candidate
+  __shared__ cx<P> xbuf[2][W];                    // row c, for the pivot row's owner
+  __shared__ int xph[2];
+  __shared__ cx<P> wrow[2][kPanelThreads / 64][W];  // per wave: its candidate row
+  __shared__ int wph[2][kPanelThreads / 64];
   __shared__ cx<P> Ltop[W][W];
   __shared__ cx<P> Utop[W][kLuMaxJB];
   __shared__ cx<P> Lc[kPanelThreads][W + 1];  // +1: rows in distinct banks
-  __shared__ int zero_pivot;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int m = n - k0;
   for (int r = tid; r < m; r += kPanelThreads) rat[r] = rowg[k0 + r];
-  if (tid == 0) zero_pivot = n;
   __syncthreads();
 
+  int zp = n;  // first zero pivot (uniform)
   int par = 0;
   for (int c0 = k0; c0 < k0 + jb; c0 += W) {
     const int wc = min(W, k0 + jb - c0);
+    // the leaf: logical rows c0 + tid + i*512 with their physical rows ph;
+    // row exchanges move data and physical row together, and the row map is
+    // written once at the end of the leaf
     cx<P> a[RPT][W];
+    int ph[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = c0 + tid + i * kPanelThreads;
 #pragma unroll
       for (int w = 0; w < W; ++w) a[i][w] = cx<P>{P(0), P(0)};
+      ph[i] = 0;
       if (r < n) {
-        const cx<P>* src = T + (long long)rat[r - k0] * ld + c0;
+        ph[i] = rat[r - k0];
+        const cx<P>* src = T + (long long)ph[i] * ld + c0;
 #pragma unroll
         for (int w = 0; w < W; ++w)
-          if (w < wc) a[i][w] = src[w];
+          if (w < wc) {
+            a[i][w].re = src[w].re;
+            a[i][w].im = src[w].im;
+          }
       }
     }
 
@@ -337,156 +356,118 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
     for (int w = 0; w < W; ++w) {
       if (w < wc) {
         const int c = c0 + w;
-        // ---- pivot search: max |Re|+|Im| over logical rows >= c, lowest row on
-        // ties.  Each thread also keeps a copy of its best row, so publishing
-        // the winner needs no indexing of the leaf by a run-time slot.
-        P bv = P(-1);
-        int bi = INT_MAX;
-        int wq = 0;
-        cx<P> brow[W];
+        // ---- pivot search: largest key over logical rows >= c, lowest row on ties
+        unsigned key = 0u;
+        int row = INT_MAX;
 #pragma unroll
-        for (int v = 0; v < W; ++v) brow[v] = a[0][v];
-        if constexpr (sizeof(P) == 4) {
-          // complex FP32: one 64-bit key per candidate, (bits of |.|, ~row);
-          // the largest key is the pivot.  Wave maximum by DPP (no LDS
-          // permutes), one key per wave through LDS.
-          unsigned long long key = 0;
+        for (int i = 0; i < RPT; ++i) {
+          const int r = c0 + tid + i * kPanelThreads;
+          const unsigned ki = (r >= c && r < n) ? pivot_key(abs1(cget(a[i][w]))) : 0u;
+          const bool take = ki > key;  // rows ascend with i: ties keep the lower
+          key = take ? ki : key;
+          row = take ? r : row;
+        }
+        // wave: the largest key, then the lowest row holding it; the lane that
+        // holds it publishes the row (a branch taken by that lane alone)
+        const unsigned wkey = wave_max_u32(key);
+        const unsigned wr = wave_min_u32(key == wkey ? (unsigned)row : 0xffffffffu);
+        if (lane == 0) redk[par][wave] = make_uint2(wkey, wr);
 #pragma unroll
-          for (int i = 0; i < RPT; ++i) {
-            const int r = c0 + tid + i * kPanelThreads;
-            const unsigned long long ki =
-                (r >= c && r < n) ? pivot_key(abs1(a[i][w]), r) : 0ull;
-            const bool take = ki > key;
-            key = take ? ki : key;
-            if (i > 0) {
+        for (int i = 0; i < RPT; ++i) {
+          if (wkey != 0u && c0 + tid + i * kPanelThreads == (int)wr) {
 #pragma unroll
-              for (int u = 0; u < W; ++u) brow[u] = csel(take, a[i][u], brow[u]);
+            for (int v = 0; v < W; ++v) {  // component copies keep a[][] in registers
+              wrow[par][wave][v].re = a[i][v].re;
+              wrow[par][wave][v].im = a[i][v].im;
             }
-          }
-          const unsigned long long wkey = wave_max_u64(key);
-          const int wrow_r = key_row(wkey);
-          if (lane == 0) redk[par][wave] = wkey;
-          if (wkey != 0ull && tid == (wrow_r - c0) % kPanelThreads) {
-#pragma unroll
-            for (int v = 0; v < W; ++v) wrow[par][wave][v] = brow[v];
-          }
-          if (tid == w) {
-#pragma unroll
-            for (int v = 0; v < W; ++v) xbuf[par][1][v] = a[0][v];
-          }
-          __syncthreads();
-          unsigned long long best = redk[par][0];
-#pragma unroll
-          for (int q = 1; q < kPanelThreads / 64; ++q) {
-            const unsigned long long o = redk[par][q];
-            const bool take = o > best;
-            best = take ? o : best;
-            wq = take ? q : wq;
-          }
-          bi = key_row(best);
-          bv = __uint_as_float((unsigned)(best >> 32));
-        } else {
-#pragma unroll
-          for (int i = 0; i < RPT; ++i) {
-            const int r = c0 + tid + i * kPanelThreads;
-            const P v = (r >= c && r < n) ? abs1(a[i][w]) : P(-1);
-            const bool take = v > bv;
-            bv = take ? v : bv;
-            bi = take ? r : bi;
-            if (i > 0) {
-#pragma unroll
-              for (int u = 0; u < W; ++u) brow[u] = csel(take, a[i][u], brow[u]);
-            }
-          }
-#pragma unroll
-          for (int off = 32; off >= 1; off >>= 1) {
-            const P ov = shfl_xor_p(bv, off);
-            const int oi = __shfl_xor(bi, off, 64);
-            const bool take = ov > bv || (ov == bv && oi < bi);
-            bv = take ? ov : bv;
-            bi = take ? oi : bi;
-          }
-          // one barrier per column: every wave publishes its candidate value,
-          // index and row; the owner of row c (thread c - c0, slot 0)
-          // publishes row c
-          if (lane == 0) { redv[par][wave] = bv; redi[par][wave] = bi; }
-          if (bi != INT_MAX && tid == (bi - c0) % kPanelThreads) {
-#pragma unroll
-            for (int v = 0; v < W; ++v) wrow[par][wave][v] = brow[v];
-          }
-          if (tid == w) {
-#pragma unroll
-            for (int v = 0; v < W; ++v) xbuf[par][1][v] = a[0][v];
-          }
-          __syncthreads();
-          bv = redv[par][0];
-          bi = redi[par][0];
-#pragma unroll
-          for (int q = 1; q < kPanelThreads / 64; ++q) {
-            const P ov = redv[par][q];
-            const int oi = redi[par][q];
-            const bool take = ov > bv || (ov == bv && oi < bi);
-            bv = take ? ov : bv;
-            bi = take ? oi : bi;
-            wq = take ? q : wq;
+            wph[par][wave] = ph[i];
           }
         }
-        const int p = bi;
+        if (tid == w) {  // the owner of row c (slot 0) publishes it
+#pragma unroll
+          for (int v = 0; v < W; ++v) {
+            xbuf[par][v].re = a[0][v].re;
+            xbuf[par][v].im = a[0][v].im;
+          }
+          xph[par] = ph[0];
+        }
+        __syncthreads();
+        uint2 best = redk[par][0];
+        int wq = 0;
+#pragma unroll
+        for (int q = 1; q < kPanelThreads / 64; ++q) {
+          const uint2 o = redk[par][q];
+          const bool take = o.x > best.x || (o.x == best.x && o.y < best.y);
+          best = take ? o : best;
+          wq = take ? q : wq;
+        }
+        const int p = (int)best.y;
         const cx<P>* prow = wrow[par][wq];  // pivot row (LDS, read where used)
-        // ---- exchange logical rows c and p (registers only; row_at records it)
+        // ---- exchange logical rows c and p (registers only)
         if (p != c) {  // uniform
           if (tid == w) {
 #pragma unroll
-            for (int v = 0; v < W; ++v) a[0][v] = prow[v];
+            for (int v = 0; v < W; ++v) {
+              a[0][v].re = prow[v].re;
+              a[0][v].im = prow[v].im;
+            }
+            ph[0] = wph[par][wq];
           }
 #pragma unroll
           for (int i = 0; i < RPT; ++i) {
-            const bool mine = c0 + tid + i * kPanelThreads == p;
+            if (c0 + tid + i * kPanelThreads == p) {  // the pivot row's owner takes row c
 #pragma unroll
-            for (int v = 0; v < W; ++v) a[i][v] = csel(mine, xbuf[par][1][v], a[i][v]);
+              for (int v = 0; v < W; ++v) {
+                a[i][v].re = xbuf[par][v].re;
+                a[i][v].im = xbuf[par][v].im;
+              }
+              ph[i] = xph[par];
+            }
           }
         }
-        if (tid == 0) {
-          const int t = rat[c - k0];
-          rat[c - k0] = rat[p - k0];
-          rat[p - k0] = t;
-          if (bv == P(0) && zero_pivot == n) zero_pivot = c;
-        }
         // ---- scale the column and update the rest of the leaf (selects, no branches)
+        const cx<P> pv = prow[w];
+        if (pv.re == P(0) && pv.im == P(0) && zp == n) zp = c;
         cx<P> inv;
-        if constexpr (sizeof(P) == 4) inv = recip_f32(prow[w]);
-        else inv = recip(prow[w]);
+        if constexpr (sizeof(P) == 4) inv = recip_f32(pv);
+        else inv = recip(pv);
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
           const int r = c0 + tid + i * kPanelThreads;
           const bool below = r > c && r < n;
-          const cx<P> l = a[i][w] * inv;
+          const cx<P> l = cget(a[i][w]) * inv;
           const cx<P> lm = csel(below, l, cx<P>{P(0), P(0)});
-          a[i][w] = csel(below, l, a[i][w]);
+          cput(a[i][w], csel(below, l, cget(a[i][w])));
 #pragma unroll
-          for (int v = w + 1; v < W; ++v) a[i][v] = fms(a[i][v], lm, prow[v]);
+          for (int v = 0; v < W; ++v)  // constant trip count: unrolled before w is
+            if (v > w) cput(a[i][v], fms(cget(a[i][v]), lm, cget(prow[v])));
         }
         par ^= 1;
       }
     }
-    __syncthreads();  // row_at swaps visible
 
-    // ---- write the leaf back
+    // ---- write the leaf back and record its row exchanges in the row map
+    // (visible to the right update after its first barrier)
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = c0 + tid + i * kPanelThreads;
       if (r < n) {
-        cx<P>* dst = T + (long long)rat[r - k0] * ld + c0;
+        cx<P>* dst = T + (long long)ph[i] * ld + c0;
 #pragma unroll
         for (int w = 0; w < W; ++w)
-          if (w < wc) dst[w] = a[i][w];
+          if (w < wc) {
+            dst[w].re = a[i][w].re;
+            dst[w].im = a[i][w].im;
+          }
+        rat[r - k0] = ph[i];
       }
     }
 
     panel_right_update<P, W, RPT>(T, rat, ld, n, k0, jb, c0, wc, a[0], Ltop, Utop, Lc);
   }
+  __syncthreads();
   for (int r = tid; r < m; r += kPanelThreads) rowg[k0 + r] = rat[r];
-  if (tid == 0 && zero_pivot < n) atomicMin(&info[d.node], zero_pivot);
+  if (tid == 0 && zp < n) atomicMin(&info[d.node], zp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1080,13 +1061,14 @@ template <typename P>
 static hipError_t launch_panel(int rpt, int nact, const MatDesc* md, int k0, int jb, cx<P>* T, int* rows, int* info,
                                const int* skip, hipStream_t st) {
   dim3 g(nact), blk(kPanelThreads);
+  // leaf width: as wide as the registers allow (RPT rows x W complex per thread)
   constexpr bool f32 = sizeof(P) == 4;
-  constexpr int Wn = f32 ? 16 : 4, Ww = f32 ? 8 : 4;
+  constexpr int W1 = f32 ? 16 : 8, W8 = f32 ? 8 : 4;
   switch (rpt) {
-    case 1: hipLaunchKernelGGL((k_lu_panel<P, Wn, 1>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
-    case 2: hipLaunchKernelGGL((k_lu_panel<P, Ww, 2>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
-    case 4: hipLaunchKernelGGL((k_lu_panel<P, Ww, 4>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
-    default: hipLaunchKernelGGL((k_lu_panel<P, Ww, 8>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    case 1: hipLaunchKernelGGL((k_lu_panel<P, W1, 1>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    case 2: hipLaunchKernelGGL((k_lu_panel<P, W1, 2>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    case 4: hipLaunchKernelGGL((k_lu_panel<P, W1, 4>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    default: hipLaunchKernelGGL((k_lu_panel<P, W8, 8>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
   }
   return hipGetLastError();
 }
