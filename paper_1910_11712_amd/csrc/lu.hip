@@ -13,10 +13,10 @@
 // Right-looking blocked algorithm, one step per panel of jb columns:
 //   k_lu_panel : one work-group per matrix factors the n-k0 by jb panel; leaves
 //                of W columns live in registers (one logical row per thread and
-//                slot), pivots are found by a wave shuffle + LDS reduction,
-//                modulus |Re|+|Im|, ties to the lowest row.
-//   k_lu_inv_l : inverse of the unit lower block L11 (recursive doubling in
-//                LDS), used for U12 and, block by block, by the solves.
+//                slot), pivots are found by DPP wave reductions + LDS, modulus
+//                |Re|+|Im|, ties to the lowest row.  At its end the group
+//                inverts the unit lower block L11 (recursive doubling in LDS),
+//                used for U12 and, block by block, by the solves.
 //   k_lu_inv_u : inverses of the 64 x 64 diagonal blocks of U11 (FP64).
 //   k_lu_gemm<1>: U12 = L11^{-1} A12 on the matrix cores (block-row solve).
 //   k_lu_gemm<0>: A22 -= L21 U12 on the matrix cores.  Complex products use the
@@ -48,6 +48,153 @@ __global__ void k_lu_init(const MatDesc* __restrict__ md, int nmat, int* __restr
   const MatDesc d = md[b];
   for (int r = threadIdx.x; r < d.n; r += blockDim.x) rowb[d.offRow + r] = r;
   if (threadIdx.x == 0) info[d.node] = d.n;
+}
+
+// ---------------------------------------------------------------------------
+// Inverses of the panel's diagonal blocks.
+//
+// tri_inv_lds inverts, in place, an m x m triangular block held in LDS (row
+// stride lx, m = 64 or 128) with NT threads: the 8 x 8 diagonal blocks by
+// substitution (one thread per column), then neighbouring blocks are merged
+// with sizes 8 -> 16 -> ... -> m.  For lower [A 0; B C] the inverse's
+// off-diagonal block is -C^{-1} B A^{-1}; for upper [A B; 0 C] it is
+// -A^{-1} B C^{-1}; both are formed as two products against the already
+// inverted diagonal blocks.  The opposite triangle holds zeros; the diagonal
+// holds 1 (unit lower) or u_ii (upper).
+// ---------------------------------------------------------------------------
+template <typename S>
+__device__ __forceinline__ cx<S> cdiv_s(cx<S> a, cx<S> b) {
+  const c128 q = cdiv(c128{double(a.re), double(a.im)}, c128{double(b.re), double(b.im)});
+  return cx<S>{S(q.re), S(q.im)};
+}
+
+template <typename S, bool UPPER, int NT = 256>
+__device__ void tri_inv_lds(cx<S>* X, int lx, int m) {
+  constexpr int NQ = 1024 / NT;  // groups per thread
+  const int tid = threadIdx.x;
+  const cx<S> zero = {S(0), S(0)};
+  {  // 8 x 8 diagonal blocks: thread (block, column c)
+    cx<S> col[8];
+    const int o = (tid >> 3) * 8, c = tid & 7;
+    const bool act = tid < m;
+    if (act) {
+      if (!UPPER) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) col[i] = i == c ? cx<S>{S(1), S(0)} : zero;
+#pragma unroll
+        for (int i = 1; i < 8; ++i) {
+          cx<S> sum = zero;
+#pragma unroll
+          for (int k = 0; k < i; ++k) sum = cmac(sum, X[(o + i) * lx + o + k], col[k]);
+          if (i > c) col[i] = -sum;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) col[i] = zero;
+#pragma unroll
+        for (int i = 7; i >= 0; --i) {
+          cx<S> sum = zero;
+#pragma unroll
+          for (int k = i + 1; k < 8; ++k) sum = cmac(sum, X[(o + i) * lx + o + k], col[k]);
+          const cx<S> rhs = i == c ? cx<S>{S(1) - sum.re, -sum.im} : -sum;
+          const cx<S> x = cdiv_s(rhs, X[(o + i) * lx + o + i]);
+          if (i <= c) col[i] = x;
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (UPPER ? i <= c : i >= c) X[(o + i) * lx + o + c] = col[i];
+    }
+    __syncthreads();
+  }
+  // merges: thread groups of 4 consecutive columns of one row of the
+  // off-diagonal block; at most m*s/8 / NT groups per thread
+  for (int s = 8; s < m; s <<= 1) {
+    const int gpb = s * (s >> 2);            // groups per block pair
+    const int ng = (m / (2 * s)) * gpb;
+    cx<S> acc[NQ][4];
+    // step 1: T = B A^{-1} (lower) or T = B C^{-1} (upper)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int g = tid + NT * q;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[q][j] = zero;
+      if (g < ng) {
+        const int pr = g / gpb, rem = g - pr * gpb;
+        const int r = rem / (s >> 2), c0 = (rem - r * (s >> 2)) * 4;
+        const int a0 = pr * 2 * s, a1 = a0 + s;
+        if (!UPPER) {
+          for (int k = c0; k < s; ++k) {
+            const cx<S> bv = X[(a1 + r) * lx + a0 + k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[q][j] = cmac(acc[q][j], bv, X[(a0 + k) * lx + a0 + c0 + j]);
+          }
+        } else {
+          for (int k = 0; k < c0 + 4; ++k) {
+            const cx<S> bv = X[(a0 + r) * lx + a1 + k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[q][j] = cmac(acc[q][j], bv, X[(a1 + k) * lx + a1 + c0 + j]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int g = tid + NT * q;
+      if (g < ng) {
+        const int pr = g / gpb, rem = g - pr * gpb;
+        const int r = rem / (s >> 2), c0 = (rem - r * (s >> 2)) * 4;
+        const int a0 = pr * 2 * s, a1 = a0 + s;
+        cx<S>* dst = UPPER ? X + (a0 + r) * lx + a1 + c0 : X + (a1 + r) * lx + a0 + c0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dst[j] = acc[q][j];
+      }
+    }
+    __syncthreads();
+    // step 2: -C^{-1} T (lower) or -A^{-1} T (upper)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int g = tid + NT * q;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[q][j] = zero;
+      if (g < ng) {
+        const int pr = g / gpb, rem = g - pr * gpb;
+        const int r = rem / (s >> 2), c0 = (rem - r * (s >> 2)) * 4;
+        const int a0 = pr * 2 * s, a1 = a0 + s;
+        if (!UPPER) {
+          for (int k = 0; k <= r; ++k) {
+            const cx<S> cv = X[(a1 + r) * lx + a1 + k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[q][j] = cmac(acc[q][j], cv, X[(a1 + k) * lx + a0 + c0 + j]);
+          }
+        } else {
+          for (int k = r; k < s; ++k) {
+            const cx<S> av = X[(a0 + r) * lx + a0 + k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[q][j] = cmac(acc[q][j], av, X[(a0 + k) * lx + a1 + c0 + j]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int g = tid + NT * q;
+      if (g < ng) {
+        const int pr = g / gpb, rem = g - pr * gpb;
+        const int r = rem / (s >> 2), c0 = (rem - r * (s >> 2)) * 4;
+        const int a0 = pr * 2 * s, a1 = a0 + s;
+        cx<S>* dst = UPPER ? X + (a0 + r) * lx + a1 + c0 : X + (a1 + r) * lx + a0 + c0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dst[j] = -acc[q][j];
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -297,17 +444,21 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
 
 template <typename P, int W, int RPT>
 __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __restrict__ md, int k0, int jbmax,
-                                                           cx<P>* __restrict__ Tb, int* __restrict__ rowb,
-                                                           int* __restrict__ info,
-                                                           const int* __restrict__ skip) {
-  const MatDesc d = md[blockIdx.x];
+                                                           cx<P>* __restrict__ Tb, const int* __restrict__ rsrc,
+                                                           int* __restrict__ rdst, int* __restrict__ info,
+                                                           const int* __restrict__ skip, cx<P>* __restrict__ Linv,
+                                                           cx<P>* __restrict__ Dinv,
+                                                           const long long* __restrict__ dinv_off) {
+  const int b = blockIdx.x;
+  const MatDesc d = md[b];
   const int n = d.n;
   if (k0 >= n) return;
   if (skip != nullptr && skip[d.node]) return;
-  const int jb = min(jbmax, n - k0);
+  const int jb = min(jbmax, n - k0);  // jbmax <= kSolveBlkLu
   cx<P>* __restrict__ T = Tb + d.offT;
   const int ld = d.ld;
-  int* __restrict__ rowg = rowb + d.offRow;
+  const int* __restrict__ rowg = rsrc + d.offRow;
+  int* __restrict__ rowo = rdst + d.offRow;
 
   __shared__ int rat[kMaxPanelRows];
   __shared__ __align__(16) uint2 redk[2][kPanelThreads / 64];  // per wave: (key, row) of its candidate
@@ -317,12 +468,18 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
   __shared__ int wph[2][kPanelThreads / 64];
   __shared__ cx<P> Ltop[W][W];
   __shared__ cx<P> Utop[W][kLuMaxJB];
-  __shared__ cx<P> Lc[kPanelThreads][W + 1];  // +1: rows in distinct banks
+  // the right update's L rows (+1: rows in distinct banks), and afterwards
+  // the panel's diagonal block for its inverse
+  constexpr int kLcBytes = kPanelThreads * (W + 1) * (int)sizeof(cx<P>);
+  constexpr int kXBytes = kSolveBlkLu * (kSolveBlkLu + 1) * (int)sizeof(cx<P>);
+  __shared__ __align__(16) unsigned char pool[kLcBytes > kXBytes ? kLcBytes : kXBytes];
+  auto& Lc = *reinterpret_cast<cx<P>(*)[kPanelThreads][W + 1]>(pool);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int m = n - k0;
   for (int r = tid; r < m; r += kPanelThreads) rat[r] = rowg[k0 + r];
+  for (int r = tid; r < k0; r += kPanelThreads) rowo[r] = rowg[r];  // rows above the panel: unchanged
   __syncthreads();
 
   int zp = n;  // first zero pivot (uniform)
@@ -466,202 +623,33 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
     panel_right_update<P, W, RPT>(T, rat, ld, n, k0, jb, c0, wc, a[0], Ltop, Utop, Lc);
   }
   __syncthreads();
-  for (int r = tid; r < m; r += kPanelThreads) rowg[k0 + r] = rat[r];
+  for (int r = tid; r < m; r += kPanelThreads) rowo[k0 + r] = rat[r];
   if (tid == 0 && zp < n) atomicMin(&info[d.node], zp);
-}
 
-// ---------------------------------------------------------------------------
-// Inverses of the panel's diagonal blocks.
-//
-// tri_inv_lds inverts, in place, an m x m triangular block held in LDS (row
-// stride lx, m = 64 or 128) with 256 threads: the 8 x 8 diagonal blocks by
-// substitution (one thread per column), then neighbouring blocks are merged
-// with sizes 8 -> 16 -> ... -> m.  For lower [A 0; B C] the inverse's
-// off-diagonal block is -C^{-1} B A^{-1}; for upper [A B; 0 C] it is
-// -A^{-1} B C^{-1}; both are formed as two products against the already
-// inverted diagonal blocks.  The opposite triangle holds zeros; the diagonal
-// holds 1 (unit lower) or u_ii (upper).
-// ---------------------------------------------------------------------------
-template <typename S>
-__device__ __forceinline__ cx<S> cdiv_s(cx<S> a, cx<S> b) {
-  const c128 q = cdiv(c128{double(a.re), double(a.im)}, c128{double(b.re), double(b.im)});
-  return cx<S>{S(q.re), S(q.im)};
-}
-
-template <typename S, bool UPPER>
-__device__ void tri_inv_lds(cx<S>* X, int lx, int m) {
-  const int tid = threadIdx.x;
-  const cx<S> zero = {S(0), S(0)};
-  {  // 8 x 8 diagonal blocks: thread (block, column c)
-    cx<S> col[8];
-    const int o = (tid >> 3) * 8, c = tid & 7;
-    const bool act = tid < m;
-    if (act) {
-      if (!UPPER) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) col[i] = i == c ? cx<S>{S(1), S(0)} : zero;
-#pragma unroll
-        for (int i = 1; i < 8; ++i) {
-          cx<S> sum = zero;
-#pragma unroll
-          for (int k = 0; k < i; ++k) sum = cmac(sum, X[(o + i) * lx + o + k], col[k]);
-          if (i > c) col[i] = -sum;
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) col[i] = zero;
-#pragma unroll
-        for (int i = 7; i >= 0; --i) {
-          cx<S> sum = zero;
-#pragma unroll
-          for (int k = i + 1; k < 8; ++k) sum = cmac(sum, X[(o + i) * lx + o + k], col[k]);
-          const cx<S> rhs = i == c ? cx<S>{S(1) - sum.re, -sum.im} : -sum;
-          const cx<S> x = cdiv_s(rhs, X[(o + i) * lx + o + i]);
-          if (i <= c) col[i] = x;
-        }
+  // ---- inverse of the unit lower block L11 (recursive doubling in LDS):
+  // inv(L11) for the U12 product when trailing columns follow, and the 64 x 64
+  // diagonal-block inverse of L that the triangular solves use (Dinv layout
+  // per matrix: [blk][0: L, 1: U][64][64], row-major, identity-padded)
+  {
+    constexpr int B = kSolveBlkLu, lx = B + 1;
+    cx<P>* X = reinterpret_cast<cx<P>*>(pool);
+    for (int e = tid; e < B * B; e += kPanelThreads) {
+      const int i = e / B, k = e - i * B;
+      cx<P> v = {P(i == k ? 1 : 0), P(0)};
+      if (i < jb && k < i) v = cget(T[(long long)rat[i] * ld + k0 + k]);
+      cput(X[i * lx + k], v);
+    }
+    __syncthreads();
+    tri_inv_lds<P, false, kPanelThreads>(X, lx, B);
+    if (n - k0 - jb > 0) {
+      cx<P>* __restrict__ Li = Linv + (long long)b * kLuMaxJB * kLuMaxJB;
+      for (int e = tid; e < jb * jb; e += kPanelThreads) {
+        const int i = e / jb, k = e - i * jb;
+        cput(Li[(long long)i * kLuMaxJB + k], cget(X[i * lx + k]));
       }
     }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (UPPER ? i <= c : i >= c) X[(o + i) * lx + o + c] = col[i];
-    }
-    __syncthreads();
-  }
-  // merges: thread groups of 4 consecutive columns of one row of the
-  // off-diagonal block; at most m*s/8 / 256 = 4 groups per thread
-  for (int s = 8; s < m; s <<= 1) {
-    const int gpb = s * (s >> 2);            // groups per block pair
-    const int ng = (m / (2 * s)) * gpb;
-    cx<S> acc[4][4];
-    // step 1: T = B A^{-1} (lower) or T = B C^{-1} (upper)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int g = tid + 256 * q;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[q][j] = zero;
-      if (g < ng) {
-        const int pr = g / gpb, rem = g - pr * gpb;
-        const int r = rem / (s >> 2), c0 = (rem - r * (s >> 2)) * 4;
-        const int a0 = pr * 2 * s, a1 = a0 + s;
-        if (!UPPER) {
-          for (int k = c0; k < s; ++k) {
-            const cx<S> bv = X[(a1 + r) * lx + a0 + k];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[q][j] = cmac(acc[q][j], bv, X[(a0 + k) * lx + a0 + c0 + j]);
-          }
-        } else {
-          for (int k = 0; k < c0 + 4; ++k) {
-            const cx<S> bv = X[(a0 + r) * lx + a1 + k];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[q][j] = cmac(acc[q][j], bv, X[(a1 + k) * lx + a1 + c0 + j]);
-          }
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int g = tid + 256 * q;
-      if (g < ng) {
-        const int pr = g / gpb, rem = g - pr * gpb;
-        const int r = rem / (s >> 2), c0 = (rem - r * (s >> 2)) * 4;
-        const int a0 = pr * 2 * s, a1 = a0 + s;
-        cx<S>* dst = UPPER ? X + (a0 + r) * lx + a1 + c0 : X + (a1 + r) * lx + a0 + c0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) dst[j] = acc[q][j];
-      }
-    }
-    __syncthreads();
-    // step 2: -C^{-1} T (lower) or -A^{-1} T (upper)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int g = tid + 256 * q;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[q][j] = zero;
-      if (g < ng) {
-        const int pr = g / gpb, rem = g - pr * gpb;
-        const int r = rem / (s >> 2), c0 = (rem - r * (s >> 2)) * 4;
-        const int a0 = pr * 2 * s, a1 = a0 + s;
-        if (!UPPER) {
-          for (int k = 0; k <= r; ++k) {
-            const cx<S> cv = X[(a1 + r) * lx + a1 + k];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[q][j] = cmac(acc[q][j], cv, X[(a1 + k) * lx + a0 + c0 + j]);
-          }
-        } else {
-          for (int k = r; k < s; ++k) {
-            const cx<S> av = X[(a0 + r) * lx + a0 + k];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[q][j] = cmac(acc[q][j], av, X[(a0 + k) * lx + a1 + c0 + j]);
-          }
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int g = tid + 256 * q;
-      if (g < ng) {
-        const int pr = g / gpb, rem = g - pr * gpb;
-        const int r = rem / (s >> 2), c0 = (rem - r * (s >> 2)) * 4;
-        const int a0 = pr * 2 * s, a1 = a0 + s;
-        cx<S>* dst = UPPER ? X + (a0 + r) * lx + a1 + c0 : X + (a1 + r) * lx + a0 + c0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) dst[j] = -acc[q][j];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// L part: inverse of the unit lower panel block L11 (jb x jb), in the factor
-// precision.  Writes inv(L11) (when trailing columns follow, for the U12
-// product) and its 64 x 64 diagonal blocks, which are the inverses the
-// triangular solves use (Dinv layout per matrix: [blk][0: L, 1: U][64][64],
-// row-major, identity-padded).
-template <typename P>
-__global__ __launch_bounds__(256) void k_lu_inv_l(const MatDesc* __restrict__ md, int k0, int jbmax,
-                                                  const cx<P>* __restrict__ Tb, const int* __restrict__ rowb,
-                                                  cx<P>* __restrict__ Linv, cx<P>* __restrict__ Dinv,
-                                                  const long long* __restrict__ dinv_off,
-                                                  const int* __restrict__ skip) {
-  const int b = blockIdx.x;
-  const MatDesc d = md[b];
-  const int n = d.n;
-  if (k0 >= n) return;
-  if (skip != nullptr && skip[d.node]) return;
-  const int jb = min(jbmax, n - k0);
-  const int m = jb > kSolveBlkLu ? 2 * kSolveBlkLu : kSolveBlkLu;
-  const int lx = m + 1;
-  const cx<P>* __restrict__ T = Tb + d.offT;
-  const int ld = d.ld;
-  const int* __restrict__ rat = rowb + d.offRow + k0;
-  extern __shared__ unsigned char smem_raw[];
-  cx<P>* X = reinterpret_cast<cx<P>*>(smem_raw);  // m x (m+1)
-  for (int e = threadIdx.x; e < m * m; e += 256) {
-    const int i = e / m, k = e - i * m;
-    cx<P> v = {P(i == k ? 1 : 0), P(0)};
-    if (i < jb && k < i) v = T[(long long)rat[i] * ld + k0 + k];
-    X[i * lx + k] = v;
-  }
-  __syncthreads();
-  tri_inv_lds<P, false>(X, lx, m);
-  if (n - k0 - jb > 0) {
-    cx<P>* __restrict__ Li = Linv + (long long)b * kLuMaxJB * kLuMaxJB;
-    for (int e = threadIdx.x; e < jb * jb; e += 256) {
-      const int i = e / jb, k = e - i * jb;
-      Li[(long long)i * kLuMaxJB + k] = X[i * lx + k];
-    }
-  }
-  const int kb = k0 / kSolveBlkLu;
-  for (int q = 0; q * kSolveBlkLu < jb; ++q) {
-    cx<P>* __restrict__ out = Dinv + dinv_off[b] + ((long long)(kb + q) * 2 + 0) * kSolveBlkLu * kSolveBlkLu;
-    for (int e = threadIdx.x; e < kSolveBlkLu * kSolveBlkLu; e += 256) {
-      const int i = e / kSolveBlkLu, k = e - i * kSolveBlkLu;
-      out[e] = X[(q * kSolveBlkLu + i) * lx + q * kSolveBlkLu + k];
-    }
+    cx<P>* __restrict__ out = Dinv + dinv_off[b] + ((long long)(k0 / B) * 2 + 0) * B * B;
+    for (int e = tid; e < B * B; e += kPanelThreads) cput(out[e], cget(X[(e / B) * lx + (e % B)]));
   }
 }
 
@@ -1058,18 +1046,23 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
 // leaves (half the passes over the panel's right part); otherwise 8 (c64) or
 // 4 (c128), which keeps the unrolled leaf in registers.
 template <typename P>
-static hipError_t launch_panel(int rpt, int nact, const MatDesc* md, int k0, int jb, cx<P>* T, int* rows, int* info,
-                               const int* skip, hipStream_t st) {
+static hipError_t launch_panel(int rpt, int nact, const MatDesc* md, int k0, int jb, cx<P>* T, const int* rsrc,
+                               int* rdst, int* info, const int* skip, cx<P>* Linv, cx<P>* Dinv,
+                               const long long* dinv_off, hipStream_t st) {
   dim3 g(nact), blk(kPanelThreads);
   // leaf width: as wide as the registers allow (RPT rows x W complex per thread)
   constexpr bool f32 = sizeof(P) == 4;
   constexpr int W1 = f32 ? 16 : 8, W8 = f32 ? 8 : 4;
+#define NEP_PANEL(W, R)                                                                                    \
+  hipLaunchKernelGGL((k_lu_panel<P, W, R>), g, blk, 0, st, md, k0, jb, T, rsrc, rdst, info, skip, Linv, Dinv, \
+                     dinv_off)
   switch (rpt) {
-    case 1: hipLaunchKernelGGL((k_lu_panel<P, W1, 1>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
-    case 2: hipLaunchKernelGGL((k_lu_panel<P, W1, 2>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
-    case 4: hipLaunchKernelGGL((k_lu_panel<P, W1, 4>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
-    default: hipLaunchKernelGGL((k_lu_panel<P, W8, 8>), g, blk, 0, st, md, k0, jb, T, rows, info, skip); break;
+    case 1: NEP_PANEL(W1, 1); break;
+    case 2: NEP_PANEL(W1, 2); break;
+    case 4: NEP_PANEL(W1, 4); break;
+    default: NEP_PANEL(W8, 8); break;
   }
+#undef NEP_PANEL
   return hipGetLastError();
 }
 
@@ -1125,30 +1118,34 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
 static KernelProf g_prof;
 KernelProf& kernel_prof() { return g_prof; }
 
-// dynamic LDS of k_lu_inv_l: the panel block padded to 64 or 128, row stride +1
-template <typename P>
-static size_t inv_l_lds(int jb) {
-  const int m = jb > kSolveBlkLu ? 2 * kSolveBlkLu : kSolveBlkLu;
-  return (size_t)m * (m + 1) * sizeof(cx<P>);
+// Final row maps: a matrix's map is in the buffer its own last panel wrote
+// (matrices leave the schedule when their panels end); copy it to rows
+// where that is the second buffer.
+__global__ void k_lu_map_final(const MatDesc* __restrict__ md, int jb, const int* __restrict__ alt,
+                               int* __restrict__ rows, const int* __restrict__ skip) {
+  const MatDesc d = md[blockIdx.x];
+  if (skip != nullptr && skip[d.node]) return;
+  if ((((d.n + jb - 1) / jb) & 1) == 0) return;  // an even number of panels ends in rows
+  for (int r = threadIdx.x; r < d.n; r += blockDim.x) rows[d.offRow + r] = alt[d.offRow + r];
 }
 
-__global__ void k_copy_int(const int* __restrict__ src, int* __restrict__ dst, int cnt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) dst[i] = src[i];
-}
-
-// Panel of a step and the inverses of its diagonal blocks.  The U inverses
-// are needed only by the solves: with a side stream they run there, off the
-// factorization's critical path (the side stream is joined at the end).
+// Panel of a step (which also inverts its L11 block) and the inverses of its
+// U diagonal blocks.  The U inverses are needed only by the solves: with a
+// side stream they run there, off the factorization's critical path (the
+// side stream is joined at the end).  The panel reads the row map from rsrc
+// and writes the updated map to rdst.
 template <typename P>
-static hipError_t lu_panel_step(const LuPlan& plan, const LuPlan::Step& s, const MatDesc* d_md, cx<P>* T, int* rows,
-                                int* info, const int* skip, cx<P>* Linv, cx<P>* Dinv, const long long* dinv_off,
-                                hipStream_t st, hipStream_t side, hipEvent_t ev_side) {
+static hipError_t lu_panel_step(const LuPlan& plan, const LuPlan::Step& s, const MatDesc* d_md, cx<P>* T,
+                                const int* rsrc, int* rdst, int* info, const int* skip, cx<P>* Linv, cx<P>* Dinv,
+                                const long long* dinv_off, hipStream_t st, hipStream_t side, hipEvent_t ev_side) {
   hipError_t e;
-  if (s.nwide > 0 && (e = launch_panel<P>(s.rpt, s.nwide, d_md, s.k0, plan.jb, T, rows, info, skip, st)) != hipSuccess)
+  if (s.nwide > 0 && (e = launch_panel<P>(s.rpt, s.nwide, d_md, s.k0, plan.jb, T, rsrc, rdst, info, skip, Linv, Dinv,
+                                          dinv_off, st)) != hipSuccess)
     return e;
   if (s.nwide < s.nact &&
-      (e = launch_panel<P>(1, s.nact - s.nwide, d_md + s.nwide, s.k0, plan.jb, T, rows, info, skip, st)) != hipSuccess)
+      (e = launch_panel<P>(1, s.nact - s.nwide, d_md + s.nwide, s.k0, plan.jb, T, rsrc, rdst, info, skip,
+                           Linv + (long long)s.nwide * kLuMaxJB * kLuMaxJB, Dinv, dinv_off + s.nwide, st)) !=
+          hipSuccess)
     return e;
   hipStream_t su = st;
   if (side != nullptr) {
@@ -1157,10 +1154,7 @@ static hipError_t lu_panel_step(const LuPlan& plan, const LuPlan::Step& s, const
     su = side;
   }
   hipLaunchKernelGGL(k_lu_inv_u<P>, dim3(s.nact * (plan.jb / kSolveBlkLu)), dim3(256), 0, su, d_md, s.k0, plan.jb, T,
-                     rows, Dinv, dinv_off, skip);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lu_inv_l<P>, dim3(s.nact), dim3(256), inv_l_lds<P>(plan.jb), st, d_md, s.k0, plan.jb, T,
-                     rows, Linv, Dinv, dinv_off, skip);
+                     rdst, Dinv, dinv_off, skip);
   return hipGetLastError();
 }
 
@@ -1216,19 +1210,24 @@ static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int 
 }
 
 // Look-ahead schedule.  After the part of step k's update that holds the
-// next panel, the next panel (and its inverses) runs on the auxiliary stream
-// while the rest of step k's update runs on st; st waits for the panel before
-// step k+1.  The next panel permutes its rows (through the row map) while the
-// rest of the update runs, so that update addresses its A and C rows through
-// a copy of the row map taken before the fork: the rows it touches form the
-// same set under either order, and the panel writes only its own columns.
-// The L11 inverses are kept in two halves of Linv by step parity: the next
+// next panel, the rest of step k's update forks to the auxiliary stream and
+// the next panel runs on st right away (the panels and the first tile
+// columns form the factorization's critical path, so they stay on one
+// stream); st joins the auxiliary stream before step k+1's update.
+// Row maps alternate between two buffers: step k's kernels use map k, and
+// panel k+1 reads map k and writes map k+1 into the other buffer, so the rest
+// of step k's update keeps addressing its rows through map k while the next
+// panel permutes rows (the rows that update touches form the same set under
+// either map, and the panel writes only its own columns).  The L11 inverses
+// are kept in two halves of Linv by step parity for the same reason: the next
 // panel's inverse is written while the rest of step k's U12 product still
-// reads step k's.
+// reads step k's.  Without a second buffer (rows_alt null) or an auxiliary
+// stream the steps run in order on st with one map.
 template <typename P>
-hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* rows_snap,
+hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* rows_alt,
                   int rows_total, int* info, const int* skip, cx<P>* Linv, cx<P>* Dinv, const long long* dinv_off,
                   hipStream_t st, const LuStreams& ls) {
+  (void)rows_total;
   hipStream_t aux = ls.aux, side = ls.side;
   hipEvent_t ev_fork = ls.ev_fork, ev_join = ls.ev_join;
   hipError_t e;
@@ -1236,53 +1235,54 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int nsteps = (int)plan.steps.size();
   if (nsteps == 0) return hipSuccess;
-  const bool lookahead = aux != nullptr && rows_snap != nullptr;
+  if (plan.jb > kSolveBlkLu) return hipErrorInvalidValue;  // the panel inverts one 64 x 64 block
+  const bool lookahead = aux != nullptr && rows_alt != nullptr;
+  int* const R[2] = {rows, lookahead ? rows_alt : rows};
+  auto map = [&](int k) { return R[(k + 1) & 1]; };  // map of step k (map -1: the initial one)
   const long long half = (long long)plan.nmat * kLuMaxJB * kLuMaxJB;
   auto linv = [&](int k) { return Linv + (k & 1) * half; };
-  if ((e = lu_panel_step<P>(plan, plan.steps[0], d_md, T, rows, info, skip, linv(0), Dinv, dinv_off, st, side,
-                            ls.ev_side[0])) != hipSuccess)
+  if ((e = lu_panel_step<P>(plan, plan.steps[0], d_md, T, map(-1), map(0), info, skip, linv(0), Dinv, dinv_off, st,
+                            side, ls.ev_side[0])) != hipSuccess)
     return e;
+  bool joined = true;  // st has waited for the last work forked to aux
   for (int k = 0; k < nsteps; ++k) {
     const auto& s = plan.steps[k];
     const bool has_next = k + 1 < nsteps;
-    if ((e = lu_update_part<P>(plan, s, 0, d_md, d_prefix, T, rows, rows, skip, linv(k), st)) != hipSuccess) return e;
-    const bool overlap = lookahead && has_next && s.tot_gemm[1] > 0;
+    if ((e = lu_update_part<P>(plan, s, 0, d_md, d_prefix, T, map(k), map(k), skip, linv(k), st)) != hipSuccess)
+      return e;
+    const bool overlap = lookahead && has_next && (s.tot_gemm[1] > 0 || s.tot_trsm[1] > 0);
     if (overlap) {
-      hipLaunchKernelGGL(k_copy_int, dim3(ceil_div(rows_total, 256)), dim3(256), 0, st, rows, rows_snap, rows_total);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
       if ((e = hipEventRecord(ev_fork, st)) != hipSuccess) return e;
       if ((e = hipStreamWaitEvent(aux, ev_fork, 0)) != hipSuccess) return e;
-      if ((e = lu_panel_step<P>(plan, plan.steps[k + 1], d_md, T, rows, info, skip, linv(k + 1), Dinv, dinv_off,
-                                aux, side, ls.ev_side[(k + 1) & 1])) != hipSuccess)
+      if ((e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, map(k), map(k), skip, linv(k), aux)) != hipSuccess)
         return e;
       if ((e = hipEventRecord(ev_join, aux)) != hipSuccess) return e;
-    }
-    if ((e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, rows, overlap ? rows_snap : rows, skip, linv(k), st)) !=
-        hipSuccess)
+      joined = false;
+    } else if ((e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, map(k), map(k), skip, linv(k), st)) !=
+               hipSuccess) {
       return e;
-    if (has_next) {
-      if (overlap) {
-        if ((e = hipStreamWaitEvent(st, ev_join, 0)) != hipSuccess) return e;
-      } else if ((e = lu_panel_step<P>(plan, plan.steps[k + 1], d_md, T, rows, info, skip, linv(k + 1), Dinv, dinv_off,
-                                       st, side, ls.ev_side[(k + 1) & 1])) != hipSuccess) {
-        return e;
-      }
+    }
+    if (has_next && (e = lu_panel_step<P>(plan, plan.steps[k + 1], d_md, T, map(k), map(k + 1), info, skip,
+                                          linv(k + 1), Dinv, dinv_off, st, side, ls.ev_side[(k + 1) & 1])) !=
+                        hipSuccess)
+      return e;
+    if (!joined) {
+      if ((e = hipStreamWaitEvent(st, ev_join, 0)) != hipSuccess) return e;
+      joined = true;
     }
   }
   if (side != nullptr) {  // join the U inverses
     if ((e = hipEventRecord(ls.ev_side_done, side)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(st, ls.ev_side_done, 0)) != hipSuccess) return e;
   }
+  if (lookahead) {  // the final maps go to rows
+    hipLaunchKernelGGL(k_lu_map_final, dim3(plan.nmat), dim3(256), 0, st, d_md, plan.jb, rows_alt, rows, skip);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
-hipError_t lu_configure() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_lu_inv_l<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)inv_l_lds<float>(lu_jb(NEP_PREC_C32_IR64)));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_lu_inv_l<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)inv_l_lds<double>(lu_jb(NEP_PREC_FP64)));
-}
+hipError_t lu_configure() { return hipSuccess; }
 
 template hipError_t lu_run<float>(const LuPlan&, const MatDesc*, const int*, c64*, int*, int*, int, int*, const int*,
                                   c64*, c64*, const long long*, hipStream_t, const LuStreams&);
