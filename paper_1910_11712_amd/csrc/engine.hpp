@@ -107,6 +107,9 @@ hipError_t solve_configure();
 
 hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const Table& tr, const NodeArrays& na,
                      const c128* Y, c128* R, IrState ir, int nnodes, hipStream_t st);
+// status read-back block (see k_gather_status) and its size
+size_t status_bytes(int G);
+hipError_t gather_status(IrState ir, const int* info, const int* bad, int G, void* out, hipStream_t st);
 hipError_t ir_control(const ProbDesc* pd, const NodeArrays& na, IrState ir, int nnodes, int sweep, double tol,
                       hipStream_t st);
 hipError_t ir_reset(IrState ir, int nnodes, hipStream_t st);

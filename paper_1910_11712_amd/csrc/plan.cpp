@@ -315,6 +315,16 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   NEP_TRY(A(dnode_, node_bytes));
   const size_t ir_bytes = 2 * G * kNormStride * 8 + (size_t)nprob * 64 * 8 + G * 8 + 3 * G * 4 + 8 * 4;
   NEP_TRY(A(dir_, ir_bytes));
+  NEP_TRY(A(dstat_, status_bytes((int)G)));
+  if (hstat_ && hstat_bytes_ < status_bytes((int)G)) {
+    (void)hipHostFree(hstat_);
+    hstat_ = nullptr;
+  }
+  if (!hstat_) {
+    hstat_bytes_ = status_bytes((int)G);
+    NEP_HIP(hipHostMalloc((void**)&hstat_, hstat_bytes_, hipHostMallocDefault));
+  }
+  if (!ev_counter_) NEP_HIP(hipEventCreateWithFlags(&ev_counter_, hipEventDisableTiming));
 
   {
     char* q = dnode_.as<char>();
@@ -380,17 +390,24 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
   NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, nullptr, Y, false, nullptr, ir_, st));
   sweeps_run_ = 0;
   if (opt.max_refine > 0) {
+    // The correction solve of each sweep is queued before the host reads the
+    // sweep's convergence count, so the device never waits for that round
+    // trip; nodes already converged skip the solve, which makes it a no-op
+    // when the count turns out to be zero.
     for (int s = 0; s <= opt.max_refine; ++s) {
       NEP_HIP(resid_run(pd, pre, pt_.resid, pt_.resid_real, na_, Y, R, ir_, nnodes, st));
       NEP_HIP(ir_control(pd, na_, ir_, nnodes, s, opt.tol, st));
       sweeps_run_ = s;
       if (eager) {
         NEP_HIP(hipMemcpyAsync(hcounter_, ir_.counters, sizeof(int), hipMemcpyDeviceToHost, st));
-        NEP_HIP(hipStreamSynchronize(st));
+        NEP_HIP(hipEventRecord(ev_counter_, st));
+      }
+      if (s < opt.max_refine)
+        NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, R, Y, true, ir_.conv, ir_, st));
+      if (eager) {
+        NEP_HIP(hipEventSynchronize(ev_counter_));
         if (hcounter_[0] == 0) break;
       }
-      if (s == opt.max_refine) break;
-      NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, R, Y, true, ir_.conv, ir_, st));
     }
     if (eager && hcounter_[0] > 0 && opt.fallback && sizeof(P) == 4) NEP_TRY(run_fallback<double>(st));
   }
@@ -468,14 +485,17 @@ nep_status MomentsPlan::finish(hipStream_t st, RunResult& out, bool allow_fallba
   const int G = nnodes;
   std::vector<int> info(G), conv(G), sweeps(G), bad(G), counters(4);
   std::vector<double> rho(G);
-  auto read_back = [&]() -> nep_status {
-    NEP_HIP(hipMemcpyAsync(info.data(), dinfo_.p, sizeof(int) * G, hipMemcpyDeviceToHost, st));
-    NEP_HIP(hipMemcpyAsync(conv.data(), ir_.conv, sizeof(int) * G, hipMemcpyDeviceToHost, st));
-    NEP_HIP(hipMemcpyAsync(sweeps.data(), ir_.sweeps, sizeof(int) * G, hipMemcpyDeviceToHost, st));
-    NEP_HIP(hipMemcpyAsync(bad.data(), na_.bad, sizeof(int) * G, hipMemcpyDeviceToHost, st));
-    NEP_HIP(hipMemcpyAsync(rho.data(), ir_.rho, sizeof(double) * G, hipMemcpyDeviceToHost, st));
-    NEP_HIP(hipMemcpyAsync(counters.data(), ir_.counters, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+  auto read_back = [&]() -> nep_status {  // one gathered block, one copy
+    NEP_HIP(gather_status(ir_, dinfo_.as<int>(), na_.bad, G, dstat_.p, st));
+    NEP_HIP(hipMemcpyAsync(hstat_, dstat_.p, status_bytes(G), hipMemcpyDeviceToHost, st));
     NEP_HIP(hipStreamSynchronize(st));
+    const int* iv = reinterpret_cast<const int*>(hstat_ + (size_t)G * sizeof(double));
+    std::memcpy(rho.data(), hstat_, sizeof(double) * G);
+    std::memcpy(info.data(), iv, sizeof(int) * G);
+    std::memcpy(conv.data(), iv + G, sizeof(int) * G);
+    std::memcpy(sweeps.data(), iv + 2 * G, sizeof(int) * G);
+    std::memcpy(bad.data(), iv + 3 * G, sizeof(int) * G);
+    std::memcpy(counters.data(), iv + 4 * G, sizeof(int) * 4);
     return NEP_OK;
   };
   NEP_TRY(read_back());

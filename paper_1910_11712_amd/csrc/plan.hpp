@@ -106,6 +106,8 @@ class MomentsPlan {
   MomentsPlan& operator=(const MomentsPlan&) = delete;
   ~MomentsPlan() {
     if (hcounter_) pinned_give(hcounter_);
+    if (hstat_) (void)hipHostFree(hstat_);
+    if (ev_counter_) (void)hipEventDestroy(ev_counter_);
     for (hipEvent_t e : {ls_.ev_fork, ls_.ev_join, ls_.ev_side[0], ls_.ev_side[1], ls_.ev_side_done})
       if (e) (void)hipEventDestroy(e);
     if (ls_.aux) (void)hipStreamDestroy(ls_.aux);
@@ -155,6 +157,10 @@ class MomentsPlan {
   NodeArrays na_{};
   IrState ir_{};
   int* hcounter_ = nullptr;  // pinned host read-back
+  hipEvent_t ev_counter_ = nullptr;  // marks the counter read-back of a sweep
+  DevMem dstat_;                     // status block gathered for finish()
+  char* hstat_ = nullptr;            // its pinned host copy
+  size_t hstat_bytes_ = 0;
   LuStreams ls_;  // look-ahead LU streams (default priority) and events
   size_t total_bytes_ = 0;
   long long t_elems_ = 0, w_elems_ = 0, y_elems_ = 0;

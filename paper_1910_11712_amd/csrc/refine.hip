@@ -386,6 +386,32 @@ hipError_t ir_control(const ProbDesc* pd, const NodeArrays& na, IrState ir, int 
   return hipGetLastError();
 }
 
+// Per-node status for the host in one block (one copy instead of one per
+// array): rho[G] (double), then info, conv, sweeps, bad (int each), then the
+// four counters.
+__global__ void k_gather_status(IrState ir, const int* __restrict__ info, const int* __restrict__ bad, int G,
+                                char* __restrict__ out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  double* rho = reinterpret_cast<double*>(out);
+  int* iv = reinterpret_cast<int*>(out + (size_t)G * sizeof(double));
+  if (g < G) {
+    rho[g] = ir.rho[g];
+    iv[g] = info[g];
+    iv[G + g] = ir.conv[g];
+    iv[2 * G + g] = ir.sweeps[g];
+    iv[3 * G + g] = bad[g];
+  }
+  if (g < 4) iv[4 * G + g] = ir.counters[g];
+}
+
+size_t status_bytes(int G) { return (size_t)G * (sizeof(double) + 4 * sizeof(int)) + 4 * sizeof(int); }
+
+hipError_t gather_status(IrState ir, const int* info, const int* bad, int G, void* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_status, dim3(ceil_div(std::max(G, 4), 256)), dim3(256), 0, st, ir, info, bad, G,
+                     static_cast<char*>(out));
+  return hipGetLastError();
+}
+
 hipError_t ir_reset(IrState ir, int nnodes, hipStream_t st) {
   hipLaunchKernelGGL(k_ir_reset, dim3(ceil_div(std::max(nnodes * kNormStride, 1), 256)), dim3(256), 0, st, ir, nnodes);
   return hipGetLastError();
