@@ -708,7 +708,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
                                                      int nact, int total, int k0, int jbmax, c64* __restrict__ Tb,
                                                      const int* __restrict__ rowb, const int* __restrict__ skip,
                                                      const c64* __restrict__ Linv, const int* __restrict__ rowa,
-                                                     int tn0, int ntn) {
+                                                     int coff, int ntn) {
   const int v = xcd_remap(blockIdx.x, gridDim.x, total);
   if (v < 0) return;
   const int b = find_slot(prefix, nact, v);
@@ -719,10 +719,10 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
   const int jb = min(jbmax, n - k0);  // == jbmax whenever a trailing block exists (a multiple of kG32KC)
   const int s0 = k0 + jb;             // first trailing row/col
   const int mt = n - s0;              // trailing size
-  // tile columns tn0 .. tn0 + ntn - 1 of the trailing columns (clipped)
-  const int tiles_n = min(ntn, (mt + kG32TN - 1) / kG32TN - tn0);
-  const int tm = t / tiles_n, tn = tn0 + (t - tm * tiles_n);
-  const int row0 = (MODE == 0 ? s0 : k0) + tm * kG32TM, col0 = s0 + tn * kG32TN;
+  // tile columns 0 .. ntn - 1 of the trailing columns from coff on (clipped)
+  const int tiles_n = min(ntn, (mt - coff + kG32TN - 1) / kG32TN);
+  const int tm = t / tiles_n, tn = t - tm * tiles_n;
+  const int row0 = (MODE == 0 ? s0 : k0) + tm * kG32TM, col0 = s0 + coff + tn * kG32TN;
   const int row_end = MODE == 0 ? n : k0 + jb;
   c64* __restrict__ T = Tb + d.offT;
   const int ld = d.ld;
@@ -881,6 +881,187 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
     }
 }
 
+// Part 0 of a step, complex FP32: the first kP0TN trailing columns, which
+// hold the next panel.  Every group first forms U12 = inv(L11) A12 for those
+// columns on the matrix cores (inv(L11) and A12 staged in LDS; the group of
+// the first row tile also stores U12), then applies C -= L21 U12 to its
+// 128 x 64 block with U12 kept in LDS.  One launch instead of a block-row
+// product followed by an update, on the factorization's critical path.
+// Grid: the row tiles of all active matrices (prefix table).  Operand lane
+// roles and the accumulator layout are those of k_lu_gemm_c64.
+constexpr int kP0TM = 128, kP0TN = kPart0Cols, kP0KC = 16;
+
+__global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restrict__ md,
+                                                      const int* __restrict__ prefix, int nact, int total, int k0,
+                                                      int jbmax, c64* __restrict__ Tb, const int* __restrict__ rowb,
+                                                      const int* __restrict__ skip, const c64* __restrict__ Linv) {
+  const int v = xcd_remap(blockIdx.x, gridDim.x, total);
+  if (v < 0) return;
+  const int b = find_slot(prefix, nact, v);
+  const int tm = v - prefix[b];
+  const MatDesc d = md[b];
+  if (skip != nullptr && skip[d.node]) return;
+  const int n = d.n;
+  const int s0 = k0 + jbmax;   // a trailing block exists, so the panel was jbmax (= 64) wide
+  const int mt = n - s0;
+  const int ncol = min(kP0TN, mt);
+  c64* __restrict__ T = Tb + d.offT;
+  const int ld = d.ld;
+  const int* __restrict__ rat = rowb + d.offRow;
+  const c64* __restrict__ Li = Linv + (long long)b * kLuMaxJB * kLuMaxJB;
+
+  constexpr int K = kSolveBlkLu;          // 64 = jbmax
+  constexpr int SA = 2 * K + 4;           // phase 1: inv(L11) as [k][2 row + comp]
+  constexpr int SC = 2 * kP0TM + 4;       // phase 2: L21 chunks as [buf][k][2 row + comp]
+  constexpr int kSa = K * SA > 2 * kP0KC * SC ? K * SA : 2 * kP0KC * SC;
+  __shared__ float Sa[kSa];
+  __shared__ float Sb[K][2][kP0TN + 4];   // A12, then U12: re/im planes [k][col]
+  __shared__ int aoff_s[kP0TM];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int at = lane & 1, au = lane >> 5, arow = (lane & 31) >> 1;
+  const int acomp = at ^ au;
+  const float asign = (at == 0 && au == 1) ? -1.f : 1.f;
+  const int bcol = lane & 31, bu = lane >> 5;
+
+  // ---- stage inv(L11) (64 x 64, row-major, stride kLuMaxJB) and A12 (the
+  // panel's rows, columns s0 .. s0+63; zero beyond the matrix)
+  for (int e = tid; e < K * K / 2; e += 256) {
+    const int r = e / (K / 2), kp = e - r * (K / 2);
+    const float4 x = *reinterpret_cast<const float4*>(Li + (long long)r * kLuMaxJB + 2 * kp);
+    Sa[(2 * kp) * SA + 2 * r] = x.x;
+    Sa[(2 * kp) * SA + 2 * r + 1] = x.y;
+    Sa[(2 * kp + 1) * SA + 2 * r] = x.z;
+    Sa[(2 * kp + 1) * SA + 2 * r + 1] = x.w;
+  }
+  for (int e = tid; e < K * kP0TN / 2; e += 256) {
+    const int k = e / (kP0TN / 2), cp = e - k * (kP0TN / 2);
+    const int gc = s0 + 2 * cp;
+    const float4 x = *reinterpret_cast<const float4*>(T + (long long)rat[k0 + k] * ld + min(gc, ld - 2));
+    const bool v0 = 2 * cp < ncol, v1 = 2 * cp + 1 < ncol;
+    Sb[k][0][2 * cp] = v0 ? x.x : 0.f;
+    Sb[k][1][2 * cp] = v0 ? x.y : 0.f;
+    Sb[k][0][2 * cp + 1] = v1 ? x.z : 0.f;
+    Sb[k][1][2 * cp + 1] = v1 ? x.w : 0.f;
+  }
+  if (tid < kP0TM) {
+    const int gr = s0 + tm * kP0TM + tid;
+    aoff_s[tid] = gr < n ? rat[gr] * ld : -1;
+  }
+  __syncthreads();
+
+  // ---- U12 rows 16 w .. 16 w + 15 on wave w (inv(L11) is lower triangular:
+  // k runs to the block's last row)
+  floatx16 u[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) u[j][r] = 0.f;
+  const int kend = 16 * wave + 16;
+  for (int k = 0; k < kend; ++k) {
+    const float a = asign * Sa[k * SA + 2 * (16 * wave + arow) + acomp];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      u[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, Sb[k][bu][j * 32 + bcol], u[j], 0, 0, 0);
+  }
+  __syncthreads();  // every wave is done with A12 and inv(L11)
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int col = j * 32 + (lane & 31);
+#pragma unroll
+    for (int r = 0; r < 16; r += 2) {
+      const int k = 16 * wave + 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
+      Sb[k][0][col] = u[j][r];
+      Sb[k][1][col] = u[j][r + 1];
+      if (tm == 0 && col < ncol) T[(long long)rat[k0 + k] * ld + s0 + col] = c64{u[j][r], u[j][r + 1]};
+    }
+  }
+
+  // ---- C -= L21 U12: wave w takes rows 32 w .. 32 w + 31 (two 16-row
+  // blocks) and both 32-column blocks; C is loaded into the accumulators
+  const int kp = tid & 7;
+  int aoff[4];
+  bool aval[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int o = aoff_s[(tid >> 3) + 32 * q];
+    aval[q] = o >= 0;
+    aoff[q] = o >= 0 ? o : 0;
+  }
+  float4 ra[4];
+  auto load_chunk = [&](int kk) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ra[q] = *reinterpret_cast<const float4*>(T + aoff[q] + k0 + kk + 2 * kp);
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = (tid >> 3) + 32 * q;
+      float* base = Sa + (buf * kP0KC) * SC;
+      base[(2 * kp) * SC + 2 * r] = aval[q] ? ra[q].x : 0.f;
+      base[(2 * kp) * SC + 2 * r + 1] = aval[q] ? ra[q].y : 0.f;
+      base[(2 * kp + 1) * SC + 2 * r] = aval[q] ? ra[q].z : 0.f;
+      base[(2 * kp + 1) * SC + 2 * r + 1] = aval[q] ? ra[q].w : 0.f;
+    }
+  };
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int gcol = s0 + j * 32 + (lane & 31);
+      const int gcl = min(gcol, ld - 1);
+#pragma unroll
+      for (int r = 0; r < 16; r += 2) {
+        const int lr = 32 * wave + 16 * i + 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
+        const int o = aoff_s[lr];
+        const c64 cv = T[(o >= 0 ? o : 0) + gcl];
+        const bool ok = o >= 0 && j * 32 + (lane & 31) < ncol;
+        acc[i][j][r] = ok ? cv.re : 0.f;
+        acc[i][j][r + 1] = ok ? cv.im : 0.f;
+      }
+    }
+  load_chunk(0);
+  __syncthreads();  // U12 in Sb; Sa free for the L21 chunks
+  store_chunk(0);
+  __syncthreads();
+  constexpr int nk = K / kP0KC;
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) load_chunk((kc + 1) * kP0KC);
+    const float* base = Sa + (buf * kP0KC) * SC;
+#pragma unroll
+    for (int k = 0; k < kP0KC; ++k) {
+      float a[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = -asign * base[k * SC + 2 * (32 * wave + 16 * i + arow) + acomp];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const float bb = Sb[kc * kP0KC + k][bu][j * 32 + bcol];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], bb, acc[i][j], 0, 0, 0);
+      }
+    }
+    if (kc + 1 < nk) {
+      store_chunk(buf ^ 1);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = j * 32 + (lane & 31);
+      if (col >= ncol) continue;
+#pragma unroll
+      for (int r = 0; r < 16; r += 2) {
+        const int lr = 32 * wave + 16 * i + 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
+        const int o = aoff_s[lr];
+        if (o >= 0) T[o + s0 + col] = c64{acc[i][j][r], acc[i][j][r + 1]};
+      }
+    }
+}
+
 // c128 variant: 256 threads = 4 waves (2 x 2), each wave 64 x 32 complex.
 constexpr int kG64TM = 128, kG64TN = 64, kG64KC = 8;
 
@@ -889,7 +1070,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
                                                       int nact, int total, int k0, int jbmax, c128* __restrict__ Tb,
                                                       const int* __restrict__ rowb, const int* __restrict__ skip,
                                                       const c128* __restrict__ Linv, const int* __restrict__ rowa,
-                                                      int tn0, int ntn) {
+                                                      int coff, int ntn) {
   const int v = xcd_remap(blockIdx.x, gridDim.x, total);
   if (v < 0) return;
   const int b = find_slot(prefix, nact, v);
@@ -900,9 +1081,9 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
   const int jb = min(jbmax, n - k0);  // == jbmax whenever a trailing block exists (a multiple of kG64KC)
   const int s0 = k0 + jb;
   const int mt = n - s0;
-  const int tiles_n = min(ntn, (mt + kG64TN - 1) / kG64TN - tn0);
-  const int tm = t / tiles_n, tn = tn0 + (t - tm * tiles_n);
-  const int row0 = (MODE == 0 ? s0 : k0) + tm * kG64TM, col0 = s0 + tn * kG64TN;
+  const int tiles_n = min(ntn, (mt - coff + kG64TN - 1) / kG64TN);
+  const int tm = t / tiles_n, tn = t - tm * tiles_n;
+  const int row0 = (MODE == 0 ? s0 : k0) + tm * kG64TM, col0 = s0 + coff + tn * kG64TN;
   const int row_end = MODE == 0 ? n : k0 + jb;
   c128* __restrict__ T = Tb + d.offT;
   const int ld = d.ld;
@@ -1088,10 +1269,13 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
     int rmax = sorted[0].n - k0;
     s.rpt = rmax <= 512 ? 1 : rmax <= 1024 ? 2 : rmax <= 2048 ? 4 : 8;
     // tile prefixes of the block-row product (U12) and of the trailing
-    // update, each in two parts: part 0 = the first tile column (it holds
-    // the next panel), part 1 = the remaining tile columns
-    const int TM = prec == NEP_PREC_FP64 ? kG64TM : kG32TM, TN = prec == NEP_PREC_FP64 ? kG64TN : kG32TN;
+    // update, each in two parts: part 0 = the first kPart0Cols trailing
+    // columns (they hold the next panel), part 1 = the rest.  Complex FP32
+    // runs part 0 as one fused kernel (128-row tiles, U12 formed in each).
+    const bool f32 = prec != NEP_PREC_FP64;
+    const int TM = f32 ? kG32TM : kG64TM;
     for (int part = 0; part < 2; ++part) {
+      const int TN = part == 0 ? kPart0Cols : (f32 ? kG32TN : kG64TN);
       for (int kind = 0; kind < 2; ++kind) {  // 0: U12 product, 1: trailing update
         int& off = kind == 0 ? s.off_trsm[part] : s.off_gemm[part];
         int& tot = kind == 0 ? s.tot_trsm[part] : s.tot_gemm[part];
@@ -1100,9 +1284,10 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
         prefix.push_back(0);
         for (int b = 0; b < nact; ++b) {
           const int n = sorted[b].n, jbb = std::min(jb, n - k0), mt = n - k0 - jbb;
-          const int tn_all = mt > 0 ? ceil_div(mt, TN) : 0;
-          const int ntn = part == 0 ? std::min(1, tn_all) : std::max(0, tn_all - 1);
-          acc += kind == 0 ? ntn : (mt > 0 ? ceil_div(mt, TM) : 0) * ntn;
+          const int ncols = part == 0 ? std::min(mt, kPart0Cols) : std::max(0, mt - kPart0Cols);
+          const int ntn = ncols > 0 ? ceil_div(ncols, TN) : 0;
+          if (kind == 0) acc += (f32 && part == 0) ? 0 : ntn;
+          else acc += (mt > 0 ? ceil_div(mt, TM) : 0) * ntn;
           prefix.push_back(acc);
         }
         tot = acc;
@@ -1163,16 +1348,26 @@ template <typename P>
 static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int part, const MatDesc* d_md,
                                  const int* d_prefix, cx<P>* T, const int* rows, const int* rows_ac, const int* skip,
                                  const cx<P>* Linv, hipStream_t st) {
-  const int tn0 = part == 0 ? 0 : 1, ntn = part == 0 ? 1 : INT_MAX;
+  const int coff = part == 0 ? 0 : kPart0Cols, ntn = part == 0 ? 1 : INT_MAX;
+  if constexpr (sizeof(P) == 4) {
+    if (part == 0) {  // fused U12 product and update of the first columns
+      if (s.tot_gemm[0] > 0) {
+        hipLaunchKernelGGL(k_lu_part0_c64, dim3(xcd_grid(s.tot_gemm[0])), dim3(256), 0, st, d_md,
+                           d_prefix + s.off_gemm[0], s.nact, s.tot_gemm[0], s.k0, plan.jb, T, rows, skip, Linv);
+        return hipGetLastError();
+      }
+      return hipSuccess;
+    }
+  }
   if (s.tot_trsm[part] > 0) {
     if constexpr (sizeof(P) == 4)
       hipLaunchKernelGGL(k_lu_gemm_c64<1>, dim3(xcd_grid(s.tot_trsm[part])), dim3(256), 0, st, d_md,
                          d_prefix + s.off_trsm[part], s.nact, s.tot_trsm[part], s.k0, plan.jb, T, rows, skip, Linv,
-                         rows, tn0, ntn);
+                         rows, coff, ntn);
     else
       hipLaunchKernelGGL(k_lu_gemm_c128<1>, dim3(xcd_grid(s.tot_trsm[part])), dim3(256), 0, st, d_md,
                          d_prefix + s.off_trsm[part], s.nact, s.tot_trsm[part], s.k0, plan.jb, T, rows, skip, Linv,
-                         rows, tn0, ntn);
+                         rows, coff, ntn);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1186,21 +1381,20 @@ static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int 
     if constexpr (sizeof(P) == 4)
       hipLaunchKernelGGL(k_lu_gemm_c64<0>, dim3(xcd_grid(s.tot_gemm[part])), dim3(256), 0, st, d_md,
                          d_prefix + s.off_gemm[part], s.nact, s.tot_gemm[part], s.k0, plan.jb, T, rows, skip, Linv,
-                         rows_ac, tn0, ntn);
+                         rows_ac, coff, ntn);
     else
       hipLaunchKernelGGL(k_lu_gemm_c128<0>, dim3(xcd_grid(s.tot_gemm[part])), dim3(256), 0, st, d_md,
                          d_prefix + s.off_gemm[part], s.nact, s.tot_gemm[part], s.k0, plan.jb, T, rows, skip, Linv,
-                         rows_ac, tn0, ntn);
+                         rows_ac, coff, ntn);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (g_prof.on) {
       (void)hipEventRecord(ev1, st);
-      const int TN = sizeof(P) == 4 ? kG32TN : kG64TN;
       double flops = 0.0;  // 8 real flops per complex multiply-add of the update
       for (int b = 0; b < s.nact; ++b) {
         const int n = plan.nvec[b], jbb = std::min(plan.jb, n - s.k0), mt = n - s.k0 - jbb;
         if (mt <= 0) continue;
-        const int c_lo = part == 0 ? 0 : std::min(mt, TN), c_hi = part == 0 ? std::min(mt, TN) : mt;
+        const int c_lo = part == 0 ? 0 : std::min(mt, kPart0Cols), c_hi = part == 0 ? std::min(mt, kPart0Cols) : mt;
         flops += 8.0 * mt * (double)(c_hi - c_lo) * jbb;
       }
       g_prof.add(sizeof(P) == 4 ? 0 : 1, ev0, ev1, flops);

@@ -9,6 +9,7 @@ namespace nep {
 
 constexpr int kLuMaxJB = 128;
 constexpr int kSolveBlkLu = 64;  // diagonal-block size of the stored inverses (the solve's block)
+constexpr int kPart0Cols = 64;   // trailing columns updated first in each step (the next panel)
 
 // Launch plan of a (possibly ragged) batch: matrices sorted by n, descending.
 struct LuPlan {
