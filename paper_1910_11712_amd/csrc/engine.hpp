@@ -13,6 +13,7 @@ namespace nep {
 constexpr int kMaxTerms = 16;
 constexpr int kMaxMoments = 32;  // 2K
 constexpr int kSolveBlk = 64;    // triangular-solve block rows
+constexpr int kResidRealTM = 64, kResidRealTQ = 64;  // real-term residual tile: rows x real columns
 constexpr int kFallbackSweeps = 2;  // FP64 refinement sweeps after an FP64 re-solve
 constexpr int kNormStride = 64;  // per-node stride of the column-norm arrays (L <= 64)
 
@@ -82,7 +83,7 @@ struct SolvePlan {
 struct ProblemTables {
   Table assemble;  // element tiles per problem
   Table resid;       // residual GEMM tiles per problem with complex terms (64 x 64)
-  Table resid_real;  // residual GEMM tiles per problem with real terms only (128 x 64)
+  Table resid_real;  // residual GEMM tiles per problem with real terms only (kResidRealTM x kResidRealTQ)
   Table moments;   // n*L tiles per problem
 };
 

@@ -274,7 +274,7 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
       const bool cplx = probs[p].op->a_cplx != 0;
       ca.push_back((int)ceil_div_ll(n * n, 256));
       cr.push_back(cplx ? ceil_div((int)n, 64) * ceil_div(2 * o.N * o.L, 64) : 0);
-      crr.push_back(cplx ? 0 : ceil_div((int)n, 128) * ceil_div(2 * o.N * o.L, 64));
+      crr.push_back(cplx ? 0 : ceil_div((int)n, kResidRealTM) * ceil_div(2 * o.N * o.L, kResidRealTQ));
       cm.push_back(ceil_div((int)n * o.L, 256) * ceil_div(2 * o.K, 8));  // (row, column) blocks x moment groups
     }
     build_prefix(hprefix_, pt_.assemble, ca);

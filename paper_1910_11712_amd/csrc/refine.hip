@@ -161,48 +161,59 @@ __global__ __launch_bounds__(256) void k_resid(const ProbDesc* __restrict__ pd, 
 }
 
 // ---------------------------------------------------------------------------
-// Real A_i (every term real): 128 x 64 tiles (128 rows, 32 complex columns)
-// per group of 4 waves, each wave 64 x 32 as 4 x 2 blocks of
+// Real A_i (every term real): tiles of TM rows x TQ real columns per group of
+// WR x WQ waves, each wave (TM/WR) x (TQ/WQ) as blocks of
 // v_mfma_f64_16x16x4f64.  The next stage's A and f_i(z_j) Y tiles are loaded
 // into registers while the current stage runs from LDS (double-buffered).
 // ---------------------------------------------------------------------------
-constexpr int kR2TM = 128, kR2TQ = 64, kR2KC = 16;
+constexpr int kR2KC = 32;
 
-__global__ __launch_bounds__(256, 2) void k_resid_real(const ProbDesc* __restrict__ pd, const int* __restrict__ prefix,
-                                                       int cnt, int total, NodeArrays na, const c128* __restrict__ Y,
-                                                       c128* __restrict__ R, IrState ir) {
+template <int TM, int TQ, int WR, int WQ>
+__global__ __launch_bounds__(64 * WR * WQ) void k_resid_real(const ProbDesc* __restrict__ pd,
+                                                              const int* __restrict__ prefix, int cnt, int total,
+                                                              NodeArrays na, const c128* __restrict__ Y,
+                                                              c128* __restrict__ R, IrState ir) {
+  constexpr int NT = 64 * WR * WQ;
+  constexpr int MI = TM / WR / 16, MJ = TQ / WQ / 16;  // 16 x 16 blocks per wave
+  constexpr int AU = TM * kR2KC / 2 / NT;              // A k-pairs staged per thread
+  constexpr int BU = kR2KC * (TQ / 2) / NT;            // B complex entries staged per thread
+  static_assert(MI >= 1 && MJ >= 1 && AU >= 1 && BU >= 1, "tile shape");
+  static_assert(AU * 2 * NT == TM * kR2KC && BU * NT == kR2KC * (TQ / 2), "staging");
   const int v = xcd_remap(blockIdx.x, gridDim.x, total);
   if (v < 0) return;
   const int p = find_slot(prefix, cnt, v);
   const ProbDesc& D = pd[p];
   const int t = v - prefix[p];
   const int n = D.n, L = D.L, NL = D.N * D.L, Q = 2 * NL;
-  const int tiles_q = (Q + kR2TQ - 1) / kR2TQ;
+  const int tiles_q = (Q + TQ - 1) / TQ;
   const int tm = t / tiles_q, tq = t - tm * tiles_q;
-  const int row0 = tm * kR2TM, q0 = tq * kR2TQ;
+  const int row0 = tm * TM, q0 = tq * TQ;
   {
-    const int cc0 = q0 / 2, cc1 = min(NL, cc0 + kR2TQ / 2) - 1;
+    const int cc0 = q0 / 2, cc1 = min(NL, cc0 + TQ / 2) - 1;
     bool any = false;
     for (int j = cc0 / L; j <= cc1 / L; ++j) any |= (ir.conv[D.node0 + j] == 0);
     if (!any) return;
   }
-  __shared__ double As[2][kR2KC][kR2TM + 1];
-  __shared__ double Bs[2][kR2KC][kR2TQ + 2];
+  __shared__ double As[2][kR2KC][TM + 1];
+  __shared__ double Bs[2][kR2KC][TQ + 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave >> 1) * 64, wq = (wave & 1) * 32;
+  const int wr = (wave / WQ) * (TM / WR), wq = (wave % WQ) * (TQ / WQ);
   const c128* __restrict__ Yp = Y + D.offY;
 
-  // staging roles: A (row tid/8 + 32u, k pair tid%8), B (k row tid/32 + 8u, complex column tid%32)
-  const int akp = tid & 7, bcl = tid & 31;
+  // staging roles: A element e = tid + NT u is (row e / KP, k pair e % KP);
+  // B element e is (k row e / (TQ/2), complex column e % (TQ/2))
+  constexpr int KP = kR2KC / 2;
+  static_assert(NT % KP == 0 && NT % (TQ / 2) == 0, "staging roles");
+  const int akp = tid % KP, bcl = tid % (TQ / 2);
   const int bcc = q0 / 2 + bcl;
   const bool bcol_ok = bcc < NL;
   const int bnode = bcol_ok ? bcc / L : 0;
 
-  doublex4 acc[4][2];
+  doublex4 acc[MI][MJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < MJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
 
@@ -210,34 +221,34 @@ __global__ __launch_bounds__(256, 2) void k_resid_real(const ProbDesc* __restric
     if (D.a_is_diag[term]) continue;  // applied in the epilogue
     const double* __restrict__ A = reinterpret_cast<const double*>(D.A[term]);
     const c128 f = bcol_ok ? na.fz[(long long)(D.node0 + bnode) * kMaxTerms + term] : c128{0.0, 0.0};
-    double ra[4][2];
-    c128 rb[2];
+    double ra[AU][2];
+    c128 rb[BU];
     auto load = [&](int k0) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int gr = row0 + (tid >> 3) + 32 * u, gk = k0 + 2 * akp;
+      for (int u = 0; u < AU; ++u) {
+        const int gr = row0 + tid / KP + (NT / KP) * u, gk = k0 + 2 * akp;
         const double* src = A + (long long)min(gr, n - 1) * n;
         const double a0 = src[min(gk, n - 1)], a1 = src[min(gk + 1, n - 1)];
         ra[u][0] = (gr < n && gk < n) ? a0 : 0.0;
         ra[u][1] = (gr < n && gk + 1 < n) ? a1 : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int s = k0 + (tid >> 5) + 8 * u;
+      for (int u = 0; u < BU; ++u) {
+        const int s = k0 + tid / (TQ / 2) + (2 * NT / TQ) * u;
         const c128 y = Yp[(long long)min(s, n - 1) * NL + (bcol_ok ? bcc : 0)];
         rb[u] = (s < n && bcol_ok) ? f * y : c128{0.0, 0.0};
       }
     };
     auto store = [&](int buf) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int r = (tid >> 3) + 32 * u;
+      for (int u = 0; u < AU; ++u) {
+        const int r = tid / KP + (NT / KP) * u;
         As[buf][2 * akp][r] = ra[u][0];
         As[buf][2 * akp + 1][r] = ra[u][1];
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int k = (tid >> 5) + 8 * u;
+      for (int u = 0; u < BU; ++u) {
+        const int k = tid / (TQ / 2) + (2 * NT / TQ) * u;
         Bs[buf][k][2 * bcl] = rb[u].re;
         Bs[buf][k][2 * bcl + 1] = rb[u].im;
       }
@@ -251,15 +262,15 @@ __global__ __launch_bounds__(256, 2) void k_resid_real(const ProbDesc* __restric
       if (ks + 1 < nk) load((ks + 1) * kR2KC);
 #pragma unroll
       for (int kk = 0; kk < kR2KC; kk += 4) {
-        double af[4], bf[2];
+        double af[MI], bf[MJ];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) af[i] = As[buf][kk + (lane >> 4)][wr + i * 16 + (lane & 15)];
+        for (int i = 0; i < MI; ++i) af[i] = As[buf][kk + (lane >> 4)][wr + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bf[j] = Bs[buf][kk + (lane >> 4)][wq + j * 16 + (lane & 15)];
+        for (int j = 0; j < MJ; ++j) bf[j] = Bs[buf][kk + (lane >> 4)][wq + j * 16 + (lane & 15)];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < MJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
       }
       if (ks + 1 < nk) {
         store(buf ^ 1);
@@ -272,13 +283,13 @@ __global__ __launch_bounds__(256, 2) void k_resid_real(const ProbDesc* __restric
   const double* __restrict__ Yd = reinterpret_cast<const double*>(Yp);
   double* __restrict__ Rd = reinterpret_cast<double*>(R + D.offY);
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < MJ; ++j) {
     const int q = q0 + wq + j * 16 + (lane & 15);
     const int cc = q >> 1, tcomp = q & 1;
     const int node = cc / L, c = cc - node * L;
     double cm = 0.0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gr = row0 + wr + i * 16 + (lane >> 4) + 4 * r;
@@ -311,7 +322,9 @@ __global__ __launch_bounds__(256, 2) void k_resid_real(const ProbDesc* __restric
 hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const Table& tr, const NodeArrays& na,
                      const c128* Y, c128* R, IrState ir, int /*nnodes*/, hipStream_t st) {
   if (tr.total > 0) {
-    hipLaunchKernelGGL(k_resid_real, dim3(xcd_grid(tr.total)), dim3(256), 0, st, pd, prefix + tr.off, tr.cnt,
+    constexpr int WR = 4, WQ = 2;  // 8 waves of 16 x 32
+    hipLaunchKernelGGL((k_resid_real<kResidRealTM, kResidRealTQ, WR, WQ>), dim3(xcd_grid(tr.total)), dim3(64 * WR * WQ),
+                       0, st, pd, prefix + tr.off, tr.cnt,
                        tr.total, na, Y, R, ir);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
