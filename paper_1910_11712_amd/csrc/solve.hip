@@ -77,6 +77,10 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
                      : RPT * FW * (16 + 16 + LG) <= kBudget ? 16
                                                             : 0;
   constexpr int GR = RPT * FW * (PF + 16 + LG) <= kBudget ? RPT : 1;
+  // full blocks as a pipeline of 16-column chunks in two register buffers
+  // (the prefetched first chunk is one of them): each chunk's loads are in
+  // flight while the previous chunk is applied
+  constexpr bool PIPE = PF == 16 && RPT * FW * (2 * 16 + LG) <= 160;
   // the column groups of one matrix run on one XCD and share its L2
   const int v = xcd_remap(blockIdx.x, gridDim.x, nmat * groups);
   if (v < 0) return;
@@ -205,6 +209,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
         const bool pending = pass == 0 ? r >= R0 + nr : r < R0;
         if (!pending) continue;
         const cx<P>* __restrict__ seg = T + rowoff[i] + R0;
+        if (nr == B && PIPE) continue;  // applied by the pipeline below
         if (nr == B) {  // full block: prefetched part first
 #pragma unroll
           for (int u = 0; u < PF; ++u)
@@ -218,9 +223,57 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
           }
         }
       }
+      if constexpr (PIPE) {
+        if (nr == B) {
+          bool pend[RPT];
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) {
+            const int r = row_of(i);
+            pend[i] = r < n && (pass == 0 ? r >= R0 + B : r < R0);
+          }
+          cx<P> nb[RPT][16];
+          auto issue = [&](cx<P> (&buf)[RPT][PF > 0 ? PF : 1], int k0) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+              if (pend[i]) load_seg16(T + rowoff[i] + R0 + k0, reinterpret_cast<cx<P>(&)[16]>(buf[i]));
+          };
+          auto issue_nb = [&](int k0) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+              if (pend[i]) load_seg16(T + rowoff[i] + R0 + k0, nb[i]);
+          };
+          auto apply_pre = [&](int k0) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+              if (pend[i]) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+#pragma unroll
+                  for (int c = 0; c < LG; ++c) acc[i][c] = fms(acc[i][c], pre[i][u], Xs[k0 + u][c]);
+              }
+          };
+          auto apply_nb = [&](int k0) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+              if (pend[i]) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+#pragma unroll
+                  for (int c = 0; c < LG; ++c) acc[i][c] = fms(acc[i][c], nb[i][u], Xs[k0 + u][c]);
+              }
+          };
+          issue_nb(16);
+          apply_pre(0);
+          issue(pre, 32);
+          apply_nb(16);
+          issue_nb(48);
+          apply_pre(32);
+          apply_nb(48);
+        }
+      }
       // rest of the full-block segments, 16 columns at a time, every row's
       // loads issued together
-      if (nr == B) {
+      if (!PIPE && nr == B) {
 #pragma unroll
         for (int i0 = 0; i0 < RPT; i0 += GR) {
           for (int k0 = PF; k0 < B; k0 += 16) {
