@@ -887,6 +887,9 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
 // the first row tile also stores U12), then applies C -= L21 U12 to its
 // 128 x 64 block with U12 kept in LDS.  One launch instead of a block-row
 // product followed by an update, on the factorization's critical path.
+// U12 replaces A12 in place, so it is stored by the last group of the matrix
+// to have staged A12 (a per-matrix arrival count, reset by that group): every
+// other group has read A12 by then.
 // Grid: the row tiles of all active matrices (prefix table).  Operand lane
 // roles and the accumulator layout are those of k_lu_gemm_c64.
 constexpr int kP0TM = 128, kP0TN = kPart0Cols, kP0KC = 16;
@@ -894,7 +897,8 @@ constexpr int kP0TM = 128, kP0TN = kPart0Cols, kP0KC = 16;
 __global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restrict__ md,
                                                       const int* __restrict__ prefix, int nact, int total, int k0,
                                                       int jbmax, c64* __restrict__ Tb, const int* __restrict__ rowb,
-                                                      const int* __restrict__ skip, const c64* __restrict__ Linv) {
+                                                      const int* __restrict__ skip, const c64* __restrict__ Linv,
+                                                      int* __restrict__ arrivals) {
   const int v = xcd_remap(blockIdx.x, gridDim.x, total);
   if (v < 0) return;
   const int b = find_slot(prefix, nact, v);
@@ -917,6 +921,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restri
   __shared__ float Sa[kSa];
   __shared__ float Sb[K][2][kP0TN + 4];   // A12, then U12: re/im planes [k][col]
   __shared__ int aoff_s[kP0TM];
+  __shared__ int store_u12;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int at = lane & 1, au = lane >> 5, arow = (lane & 31) >> 1;
@@ -948,7 +953,14 @@ __global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restri
     const int gr = s0 + tm * kP0TM + tid;
     aoff_s[tid] = gr < n ? rat[gr] * ld : -1;
   }
-  __syncthreads();
+  __syncthreads();  // A12 is in LDS
+  if (tid == 0) {
+    const int ntiles = (mt + kP0TM - 1) / kP0TM;
+    __threadfence();
+    const int before = atomicAdd(&arrivals[b], 1);
+    store_u12 = before == ntiles - 1;
+    if (store_u12) arrivals[b] = 0;  // every group of this matrix has arrived
+  }
 
   // ---- U12 rows 16 w .. 16 w + 15 on wave w (inv(L11) is lower triangular:
   // k runs to the block's last row)
@@ -973,7 +985,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restri
       const int k = 16 * wave + 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
       Sb[k][0][col] = u[j][r];
       Sb[k][1][col] = u[j][r + 1];
-      if (tm == 0 && col < ncol) T[(long long)rat[k0 + k] * ld + s0 + col] = c64{u[j][r], u[j][r + 1]};
+      if (store_u12 && col < ncol) T[(long long)rat[k0 + k] * ld + s0 + col] = c64{u[j][r], u[j][r + 1]};
     }
   }
 
@@ -1347,13 +1359,14 @@ static hipError_t lu_panel_step(const LuPlan& plan, const LuPlan::Step& s, const
 template <typename P>
 static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int part, const MatDesc* d_md,
                                  const int* d_prefix, cx<P>* T, const int* rows, const int* rows_ac, const int* skip,
-                                 const cx<P>* Linv, hipStream_t st) {
+                                 const cx<P>* Linv, int* arrivals, hipStream_t st) {
   const int coff = part == 0 ? 0 : kPart0Cols, ntn = part == 0 ? 1 : INT_MAX;
   if constexpr (sizeof(P) == 4) {
     if (part == 0) {  // fused U12 product and update of the first columns
       if (s.tot_gemm[0] > 0) {
         hipLaunchKernelGGL(k_lu_part0_c64, dim3(xcd_grid(s.tot_gemm[0])), dim3(256), 0, st, d_md,
-                           d_prefix + s.off_gemm[0], s.nact, s.tot_gemm[0], s.k0, plan.jb, T, rows, skip, Linv);
+                           d_prefix + s.off_gemm[0], s.nact, s.tot_gemm[0], s.k0, plan.jb, T, rows, skip, Linv,
+                           arrivals);
         return hipGetLastError();
       }
       return hipSuccess;
@@ -1420,7 +1433,7 @@ static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int 
 template <typename P>
 hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* rows_alt,
                   int rows_total, int* info, const int* skip, cx<P>* Linv, cx<P>* Dinv, const long long* dinv_off,
-                  hipStream_t st, const LuStreams& ls) {
+                  int* arrivals, hipStream_t st, const LuStreams& ls) {
   (void)rows_total;
   hipStream_t aux = ls.aux, side = ls.side;
   hipEvent_t ev_fork = ls.ev_fork, ev_join = ls.ev_join;
@@ -1442,17 +1455,17 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
   for (int k = 0; k < nsteps; ++k) {
     const auto& s = plan.steps[k];
     const bool has_next = k + 1 < nsteps;
-    if ((e = lu_update_part<P>(plan, s, 0, d_md, d_prefix, T, map(k), map(k), skip, linv(k), st)) != hipSuccess)
+    if ((e = lu_update_part<P>(plan, s, 0, d_md, d_prefix, T, map(k), map(k), skip, linv(k), arrivals, st)) != hipSuccess)
       return e;
     const bool overlap = lookahead && has_next && (s.tot_gemm[1] > 0 || s.tot_trsm[1] > 0);
     if (overlap) {
       if ((e = hipEventRecord(ev_fork, st)) != hipSuccess) return e;
       if ((e = hipStreamWaitEvent(aux, ev_fork, 0)) != hipSuccess) return e;
-      if ((e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, map(k), map(k), skip, linv(k), aux)) != hipSuccess)
+      if ((e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, map(k), map(k), skip, linv(k), arrivals, aux)) != hipSuccess)
         return e;
       if ((e = hipEventRecord(ev_join, aux)) != hipSuccess) return e;
       joined = false;
-    } else if ((e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, map(k), map(k), skip, linv(k), st)) !=
+    } else if ((e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, map(k), map(k), skip, linv(k), arrivals, st)) !=
                hipSuccess) {
       return e;
     }
@@ -1479,8 +1492,8 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
 hipError_t lu_configure() { return hipSuccess; }
 
 template hipError_t lu_run<float>(const LuPlan&, const MatDesc*, const int*, c64*, int*, int*, int, int*, const int*,
-                                  c64*, c64*, const long long*, hipStream_t, const LuStreams&);
+                                  c64*, c64*, const long long*, int*, hipStream_t, const LuStreams&);
 template hipError_t lu_run<double>(const LuPlan&, const MatDesc*, const int*, c128*, int*, int*, int, int*, const int*,
-                                   c128*, c128*, const long long*, hipStream_t, const LuStreams&);
+                                   c128*, c128*, const long long*, int*, hipStream_t, const LuStreams&);
 
 }  // namespace nep

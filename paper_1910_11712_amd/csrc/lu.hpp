@@ -60,11 +60,13 @@ struct LuStreams {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_side[2] = {nullptr, nullptr}, ev_side_done = nullptr;
 };
 
+// arrivals: nmat ints, zero before the first call (left zero by every call):
+// per-matrix arrival counts of the fused first-columns update.
 // rows_alt: rows_total ints, the second row-map buffer of the look-ahead
 // schedule (the final map is always left in rows).
 template <typename P>
 hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, cx<P>* T, int* rows, int* rows_alt,
                   int rows_total, int* info, const int* skip, cx<P>* Linv, cx<P>* Dinv, const long long* dinv_off,
-                  hipStream_t st, const LuStreams& ls);
+                  int* arrivals, hipStream_t st, const LuStreams& ls);
 
 }  // namespace nep

@@ -307,6 +307,8 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   NEP_TRY(A(dinfo_, sizeof(int) * (size_t)nnodes));
   NEP_TRY(A(ddinv_, es * (size_t)dinv_elems_));
   NEP_TRY(A(dlinv_, 2 * es * (size_t)sorted_.size() * kLuMaxJB * kLuMaxJB));
+  NEP_TRY(A(darrive_, sizeof(int) * std::max<size_t>(1, sorted_.size())));
+  NEP_HIP(hipMemset(darrive_.p, 0, sizeof(int) * std::max<size_t>(1, sorted_.size())));
   NEP_TRY(A(ddinv_off_, sizeof(long long) * dinv_off_.size()));
   NEP_TRY(A(dY_, sizeof(c128) * (size_t)y_elems_));
   NEP_TRY(A(dR_, sizeof(c128) * (size_t)y_elems_));
@@ -386,7 +388,7 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
   cx<P>* Dinv = ddinv_.as<cx<P>>();
   const long long* doff = ddinv_off_.as<long long>();
   NEP_HIP(lu_run<P>(lu_, md, dlu_prefix_.as<int>(), T, rows, drows_snap_.as<int>(), rows_total_, info, nullptr,
-                    dlinv_.as<cx<P>>(), Dinv, doff, st, ls_));
+                    dlinv_.as<cx<P>>(), Dinv, doff, darrive_.as<int>(), st, ls_));
   NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, nullptr, Y, false, nullptr, ir_, st));
   sweeps_run_ = 0;
   if (opt.max_refine > 0) {
@@ -458,7 +460,7 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
   c128* Dinv = ddinv64_.as<c128>();
   const long long* doff = ddinv_off_.as<long long>();
   NEP_HIP(lu_run<double>(lu64_, md, dlu64_prefix_.as<int>(), T, drows_.as<int>(), drows_snap_.as<int>(), rows_total_,
-                         dinfo_.as<int>(), skip, dlinv64_.as<c128>(), Dinv, doff, st, ls_));
+                         dinfo_.as<int>(), skip, dlinv64_.as<c128>(), Dinv, doff, darrive_.as<int>(), st, ls_));
   NEP_HIP(solve_run<double>(sp_, pd, md, na_, T, drows_.as<int>(), Dinv, doff, nullptr, dY_.as<c128>(), false,
                             skip, ir_, st));
   for (int s = 0;; ++s) {

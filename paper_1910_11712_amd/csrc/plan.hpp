@@ -151,7 +151,7 @@ class MomentsPlan {
   std::vector<int> hprefix_;
   DevMem dpd_, dmd_, dprefix_, dlu_prefix_, dlu64_prefix_;
   DevMem dT_, drows_, drows_snap_, dinfo_, dY_, dR_, dnode_, dir_, dT64_;
-  DevMem ddinv_, ddinv_off_, ddinv64_, dlinv_, dlinv64_;
+  DevMem ddinv_, ddinv_off_, ddinv64_, dlinv_, dlinv64_, darrive_;
   std::vector<long long> dinv_off_;
   long long dinv_elems_ = 0;
   NodeArrays na_{};
