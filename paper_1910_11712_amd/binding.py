@@ -93,6 +93,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"libnep.so not built ({LIB_PATH}); run paper_1910_11712_amd/build.py")
+        # torch first: its HIP runtime must be the one loaded when libnep.so
+        # resolves libamdhip64 (tensors handed to the library come from torch)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, ip = C.c_void_p, C.c_int
         L.nep_last_error.restype = C.c_char_p

@@ -77,7 +77,9 @@ struct SolvePlan {
   int nmat = 0;     // matrices (sorted order)
   int lg = 4;       // right-hand columns per group
   int groups = 1;   // column groups per matrix
-  int rpt = 1;      // rows per thread of the solve kernel (n <= 512 * rpt)
+  int rpt = 1;      // rows per thread of the 512-thread solve groups (n <= 512 * rpt)
+  int nbig = 0;     // matrices of more than 512 rows (the first nbig in sorted order)
+  int nmid = 0;     // then matrices of 257..512 rows; the rest have at most 256
 };
 
 struct ProblemTables {

@@ -13,7 +13,10 @@
 
 namespace nep {
 
-constexpr int kTrsvThreads = 512;
+// Threads per group: 512 for matrices of more than 512 rows, 256 below
+// (two rows per thread up to 512 rows, one up to 256), so that small matrices
+// of a ragged batch do not leave most of a large group idle.
+constexpr int kTrsvThreads = 512, kTrsvThreadsSmall = 256;
 
 // ---------------------------------------------------------------------------
 // Right-looking substitution with the accumulators in registers: thread t
@@ -59,8 +62,8 @@ __device__ __forceinline__ void load_seg(const cx<P>* __restrict__ s, cx<P> (&v)
   }
 }
 
-template <typename P, int LG, int RPT>
-__global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict__ md, int nmat, int groups,
+template <typename P, int LG, int RPT, int NT>
+__global__ __launch_bounds__(NT) void k_trsv(const MatDesc* __restrict__ md, int nmat, int groups,
                                                       const ProbDesc* __restrict__ pd, NodeArrays na,
                                                       const cx<P>* __restrict__ Tb, const int* __restrict__ rows,
                                                       const cx<P>* __restrict__ Dinv,
@@ -103,12 +106,12 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
   __shared__ cx<P> Ds[B][B + 1];   // diagonal-block inverse
   __shared__ cx<P> Ts[B][LG];      // block right-hand side
   __shared__ cx<P> Xs[B][LG];      // block solution
-  __shared__ double cmax[kTrsvThreads / 64][LG];
+  __shared__ double cmax[NT / 64][LG];
 
   // rows of this thread: slot i holds row i*T + tid (i even) or
   // (i+1)*T - 1 - tid (i odd), so every thread has rows from both ends and
   // the pending rows of a block are spread evenly over the waves
-  auto row_of = [&](int i) { return (i & 1) ? (i + 1) * kTrsvThreads - 1 - tid : i * kTrsvThreads + tid; };
+  auto row_of = [&](int i) { return (i & 1) ? (i + 1) * NT - 1 - tid : i * NT + tid; };
   // right-hand side P b gathered into the owners' accumulators
   cx<P> acc[RPT][LG];
   long long rowoff[RPT];
@@ -129,12 +132,12 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
 #pragma unroll
   for (int c = 0; c < LG; ++c) ymax[c] = 0.0;
 
-  constexpr int DPT = B * B / kTrsvThreads;  // inverse elements per thread
-  static_assert(DPT * kTrsvThreads == B * B, "inverse staging");
+  constexpr int DPT = B * B / NT;  // inverse elements per thread
+  static_assert(DPT * NT == B * B, "inverse staging");
   cx<P> dreg[DPT];
 #pragma unroll
   for (int u = 0; u < DPT; ++u) {  // block 0 of L
-    const cx<P>* src = Di + tid + u * kTrsvThreads;
+    const cx<P>* src = Di + tid + u * NT;
     dreg[u] = cx<P>{src->re, src->im};
   }
   for (int pass = 0; pass < 2; ++pass) {  // 0: L y = P b, 1: U x = y
@@ -167,12 +170,12 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
       // (identity-padded past nr, so no masking is needed)
 #pragma unroll
       for (int u = 0; u < DPT; ++u) {
-        const int e = tid + u * kTrsvThreads;
+        const int e = tid + u * NT;
         Ds[e / B][e % B] = cx<P>{dreg[u].re, dreg[u].im};
       }
       __syncthreads();
       // 2. x_q = Dinv_q t
-      for (int e = tid; e < B * LG; e += kTrsvThreads) {
+      for (int e = tid; e < B * LG; e += NT) {
         const int i = e / LG, c = e - i * LG;
         cx<P> x = {P(0), P(0)};
 #pragma unroll 16
@@ -190,7 +193,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
           const cx<P>* __restrict__ nx = Di + ((long long)nq * 2 + npass) * B * B;
 #pragma unroll
           for (int u = 0; u < DPT; ++u) {
-            const cx<P>* src = nx + tid + u * kTrsvThreads;
+            const cx<P>* src = nx + tid + u * NT;
             dreg[u] = cx<P>{src->re, src->im};
           }
         }
@@ -328,28 +331,40 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(const MatDesc* __restrict
   __syncthreads();
   if (tid < nc) {
     double m = 0.0;
-    for (int w = 0; w < kTrsvThreads / 64; ++w) m = fmax(m, cmax[w][tid]);
+    for (int w = 0; w < NT / 64; ++w) m = fmax(m, cmax[w][tid]);
     atomicMax(&ir.ynorm[(long long)g * kNormStride + c0 + tid], (unsigned long long)__double_as_longlong(m));
   }
 }
 
 // ---------------------------------------------------------------------------
 
+template <typename P, int LG, int RPT, int NT>
+static void launch_trsv_class(const SolvePlan& sp, int b0, int cnt, const ProbDesc* pd, const MatDesc* md,
+                              const NodeArrays& na, const cx<P>* T, const int* rows, const cx<P>* Dinv,
+                              const long long* dinv_off, const c128* R, c128* Y, int rf, const int* conv, IrState ir,
+                              hipStream_t st) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL((k_trsv<P, LG, RPT, NT>), dim3(xcd_grid(cnt * sp.groups)), dim3(NT), 0, st, md + b0, cnt,
+                     sp.groups, pd, na, T, rows, Dinv, dinv_off + b0, R, Y, rf, conv, ir);
+}
+
+// One launch per size class of the (size-sorted) matrices: more than 512
+// rows (512 threads, sp.rpt rows each), 257..512 rows and up to 256 rows
+// (256 threads, two and one rows each).
 template <typename P, int LG>
 static void launch_trsv(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md, const NodeArrays& na,
                         const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off, const c128* R,
                         c128* Y, int rf, const int* conv, IrState ir, hipStream_t st) {
-  const dim3 grid(xcd_grid(sp.nmat * sp.groups)), blk(kTrsvThreads);
+  const int nb = sp.nbig, nm = sp.nmid, ns = sp.nmat - sp.nbig - sp.nmid;
   switch (sp.rpt) {
-    case 1: hipLaunchKernelGGL((k_trsv<P, LG, 1>), grid, blk, 0, st, md, sp.nmat, sp.groups, pd, na, T, rows, Dinv,
-                               dinv_off, R, Y, rf, conv, ir); break;
-    case 2: hipLaunchKernelGGL((k_trsv<P, LG, 2>), grid, blk, 0, st, md, sp.nmat, sp.groups, pd, na, T, rows, Dinv,
-                               dinv_off, R, Y, rf, conv, ir); break;
-    case 4: hipLaunchKernelGGL((k_trsv<P, LG, 4>), grid, blk, 0, st, md, sp.nmat, sp.groups, pd, na, T, rows, Dinv,
-                               dinv_off, R, Y, rf, conv, ir); break;
-    default: hipLaunchKernelGGL((k_trsv<P, LG, 8>), grid, blk, 0, st, md, sp.nmat, sp.groups, pd, na, T, rows, Dinv,
-                                dinv_off, R, Y, rf, conv, ir); break;
+    case 1:
+    case 2: launch_trsv_class<P, LG, 2, kTrsvThreads>(sp, 0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
+    case 4: launch_trsv_class<P, LG, 4, kTrsvThreads>(sp, 0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
+    default: launch_trsv_class<P, LG, 8, kTrsvThreads>(sp, 0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
   }
+  launch_trsv_class<P, LG, 2, kTrsvThreadsSmall>(sp, nb, nm, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st);
+  launch_trsv_class<P, LG, 1, kTrsvThreadsSmall>(sp, nb + nm, ns, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir,
+                                                 st);
 }
 
 template <typename P>
@@ -389,7 +404,12 @@ void SolvePlan_build(SolvePlan& sp, std::vector<int>& /*buf*/, const std::vector
                      std::vector<long long>& dinv_off, long long& dinv_elems) {
   sp.nmat = (int)sorted.size();
   const int nmax = sorted.empty() ? 0 : sorted[0].n;
-  sp.rpt = nmax <= 512 ? 1 : nmax <= 1024 ? 2 : nmax <= 2048 ? 4 : 8;
+  sp.rpt = nmax <= 512 ? 1 : nmax <= 1024 ? 2 : nmax <= 2048 ? 4 : 8;  // rows per thread of the 512-thread class
+  sp.nbig = sp.nmid = 0;
+  for (const auto& m : sorted) {
+    if (m.n > 2 * kTrsvThreadsSmall) ++sp.nbig;
+    else if (m.n > kTrsvThreadsSmall) ++sp.nmid;
+  }
   sp.lg = pick_lg(sp.nmat, L);
   // accumulators live in registers: at most 32 complex FP32 (8 complex FP64)
   // values per thread
