@@ -1076,9 +1076,10 @@ __global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restri
 
 // c128 variant: 256 threads = 4 waves (2 x 2), each wave 64 x 32 complex.
 constexpr int kG64TM = 128, kG64TN = 64, kG64KC = 8;
+constexpr int kG64Waves = 8;  // waves per group of the complex-FP64 GEMM
 
-template <int MODE>
-__global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restrict__ md, const int* __restrict__ prefix,
+template <int MODE, int NW>
+__global__ __launch_bounds__(64 * NW) void k_lu_gemm_c128(const MatDesc* __restrict__ md, const int* __restrict__ prefix,
                                                       int nact, int total, int k0, int jbmax, c128* __restrict__ Tb,
                                                       const int* __restrict__ rowb, const int* __restrict__ skip,
                                                       const c128* __restrict__ Linv, const int* __restrict__ rowa,
@@ -1102,6 +1103,10 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
   const int* __restrict__ rat = rowb + d.offRow;    // B rows (and U12 rows in MODE 1)
   const int* __restrict__ rata = rowa + d.offRow;   // A and C rows of the trailing update
   const c128* __restrict__ Asrc = MODE == 1 ? Linv + (long long)b * kLuMaxJB * kLuMaxJB : T;
+  // NW waves as WR x 2, each (kG64TM / WR) complex rows x 32 complex columns
+  constexpr int NT = 64 * NW, WR = NW / 2, MI = kG64TM / WR / 8;
+  constexpr int AQ = kG64TM * kG64KC / NT, BQ = kG64KC * kG64TN / NT;  // staged complex per thread
+  static_assert(AQ >= 1 && BQ >= 1 && MI >= 1, "tile shape");
 
   __shared__ double As[2][kG64KC][2 * kG64TM + 2];
   __shared__ double Bs[2][kG64KC][2][kG64TN + 2];
@@ -1109,21 +1114,21 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
   __shared__ int boff_s[kLuMaxJB];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave >> 1) * 64, wcn = (wave & 1) * 32;
+  const int wr = (wave >> 1) * (kG64TM / WR), wcn = (wave & 1) * 32;
   if (tid < kG64TM) {
     const int gr = row0 + tid;
     aoff_s[tid] = gr < row_end ? (MODE == 0 ? rata[gr] * ld : (gr - k0) * kLuMaxJB) : -1;
   }
-  for (int i = tid; i < jb; i += 256) boff_s[i] = rat[k0 + i] * ld;
+  for (int i = tid; i < jb; i += NT) boff_s[i] = rat[k0 + i] * ld;
   __syncthreads();
 
-  // staging roles: A (row tid/8 + 32q, k tid%8), B (k row tid/64 + 4q, column tid%64)
+  // staging roles: A (row tid/8 + (NT/8) q, k tid%8), B (k row tid/64 + NW q, column tid%64)
   const int kq8 = tid & 7, cb = tid & 63;
-  int aoff[4];
-  bool aval[4];
+  int aoff[AQ];
+  bool aval[AQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int o = aoff_s[(tid >> 3) + 32 * q];
+  for (int q = 0; q < AQ; ++q) {
+    const int o = aoff_s[(tid >> 3) + (NT / 8) * q];
     aval[q] = o >= 0;
     aoff[q] = o >= 0 ? o : 0;
   }
@@ -1131,25 +1136,25 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
   const bool bval = gcb < n;
   const int gcbl = min(gcb, ld - 1);
 
-  double2 ra[4], rb[2];
+  double2 ra[AQ], rb[BQ];
   auto load_tile = [&](int kk) {  // kk: chunk offset relative to k0
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < AQ; ++q)
       ra[q] = *reinterpret_cast<const double2*>(Asrc + aoff[q] + (MODE == 0 ? k0 : 0) + kk + kq8);
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-      rb[q] = *reinterpret_cast<const double2*>(T + boff_s[kk + (tid >> 6) + 4 * q] + gcbl);
+    for (int q = 0; q < BQ; ++q)
+      rb[q] = *reinterpret_cast<const double2*>(T + boff_s[kk + (tid >> 6) + NW * q] + gcbl);
   };
   auto store_tile = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = (tid >> 3) + 32 * q;
+    for (int q = 0; q < AQ; ++q) {
+      const int r = (tid >> 3) + (NT / 8) * q;
       As[buf][kq8][2 * r] = aval[q] ? ra[q].x : 0.0;
       As[buf][kq8][2 * r + 1] = aval[q] ? ra[q].y : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int kr = (tid >> 6) + 4 * q;
+    for (int q = 0; q < BQ; ++q) {
+      const int kr = (tid >> 6) + NW * q;
       Bs[buf][kr][0][cb] = bval ? rb[q].x : 0.0;
       Bs[buf][kr][1][cb] = bval ? rb[q].y : 0.0;
     }
@@ -1159,10 +1164,10 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
   // component (l/16)%2; col l%16.  MODE 0 starts from C and accumulates
   // -L21 U12; MODE 1 starts from 0.
   const int tcomp = (lane >> 4) & 1, rbase = (lane >> 4) >> 1;
-  doublex4 acc[8][2];
+  doublex4 acc[MI][2];
   if (MODE == 0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int gc = col0 + wcn + j * 16 + (lane & 15);
@@ -1176,7 +1181,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
       }
   } else {
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -1200,13 +1205,13 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
     if (kc + 1 < nk) load_tile((kc + 1) * kG64KC);
 #pragma unroll
     for (int k2 = 0; k2 < kG64KC; k2 += 2) {
-      double af[8], bf[2];
+      double af[MI], bf[2];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) af[i] = asign * As[buf][k2 + ak][2 * (wr + i * 8 + arow) + acomp];
+      for (int i = 0; i < MI; ++i) af[i] = asign * As[buf][k2 + ak][2 * (wr + i * 8 + arow) + acomp];
 #pragma unroll
       for (int j = 0; j < 2; ++j) bf[j] = Bs[buf][k2 + ak][au][wcn + j * 16 + bcol];
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
@@ -1218,7 +1223,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c128(const MatDesc* __restri
   }
   // epilogue: store-only
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int gc = col0 + wcn + j * 16 + (lane & 15);
@@ -1378,7 +1383,7 @@ static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int 
                          d_prefix + s.off_trsm[part], s.nact, s.tot_trsm[part], s.k0, plan.jb, T, rows, skip, Linv,
                          rows, coff, ntn);
     else
-      hipLaunchKernelGGL(k_lu_gemm_c128<1>, dim3(xcd_grid(s.tot_trsm[part])), dim3(256), 0, st, d_md,
+      hipLaunchKernelGGL((k_lu_gemm_c128<1, kG64Waves>), dim3(xcd_grid(s.tot_trsm[part])), dim3(64 * kG64Waves), 0, st, d_md,
                          d_prefix + s.off_trsm[part], s.nact, s.tot_trsm[part], s.k0, plan.jb, T, rows, skip, Linv,
                          rows, coff, ntn);
     hipError_t e = hipGetLastError();
@@ -1396,7 +1401,7 @@ static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int 
                          d_prefix + s.off_gemm[part], s.nact, s.tot_gemm[part], s.k0, plan.jb, T, rows, skip, Linv,
                          rows_ac, coff, ntn);
     else
-      hipLaunchKernelGGL(k_lu_gemm_c128<0>, dim3(xcd_grid(s.tot_gemm[part])), dim3(256), 0, st, d_md,
+      hipLaunchKernelGGL((k_lu_gemm_c128<0, kG64Waves>), dim3(xcd_grid(s.tot_gemm[part])), dim3(64 * kG64Waves), 0, st, d_md,
                          d_prefix + s.off_gemm[part], s.nact, s.tot_gemm[part], s.k0, plan.jb, T, rows, skip, Linv,
                          rows_ac, coff, ntn);
     hipError_t e = hipGetLastError();
