@@ -699,12 +699,13 @@ __global__ __launch_bounds__(256) void k_lu_inv_u(const MatDesc* __restrict__ md
 // ---------------------------------------------------------------------------
 // c64 variant: 256 threads = 4 waves (2 x 2), each wave 64 x 64 complex.
 constexpr int kG32TM = 128, kG32TN = 128, kG32KC = 16;
+constexpr int kG32Waves = 8;  // waves per group of the complex-FP32 GEMM
 
 // MODE 0: trailing update A22 -= L21 U12 (rows/cols >= k0+jb).
 // MODE 1: block-row solve U12 = L11^{-1} A12 with the stored inverse (rows
 //         k0..k0+jb-1, cols >= k0+jb), result stored in place.
-template <int MODE>
-__global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restrict__ md, const int* __restrict__ prefix,
+template <int MODE, int NW>
+__global__ __launch_bounds__(64 * NW) void k_lu_gemm_c64(const MatDesc* __restrict__ md, const int* __restrict__ prefix,
                                                      int nact, int total, int k0, int jbmax, c64* __restrict__ Tb,
                                                      const int* __restrict__ rowb, const int* __restrict__ skip,
                                                      const c64* __restrict__ Linv, const int* __restrict__ rowa,
@@ -729,6 +730,10 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
   const int* __restrict__ rat = rowb + d.offRow;    // B rows (and U12 rows in MODE 1)
   const int* __restrict__ rata = rowa + d.offRow;   // A and C rows of the trailing update
   const c64* __restrict__ Asrc = MODE == 1 ? Linv + (long long)b * kLuMaxJB * kLuMaxJB : T;
+  // NW waves as WR x 2, each (kG32TM / WR) complex rows x 64 complex columns
+  constexpr int NT = 64 * NW, WR = NW / 2, MI = kG32TM / WR / 16;
+  constexpr int AQ = kG32TM * kG32KC / 2 / NT, BQ = kG32KC * kG32TN / 2 / NT;  // staged pairs per thread
+  static_assert(AQ >= 1 && BQ >= 1 && MI >= 1, "tile shape");
 
   // LDS: A as [k][row] complex (stride kG32TM+2), B as re/im planes [k][col].
   __shared__ float As[2][kG32KC][2 * kG32TM + 4];
@@ -738,22 +743,22 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
   __shared__ int boff_s[kLuMaxJB];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave >> 1) * 64, wcn = (wave & 1) * 64;
+  const int wr = (wave >> 1) * (kG32TM / WR), wcn = (wave & 1) * 64;
   if (tid < kG32TM) {
     const int gr = row0 + tid;
     aoff_s[tid] = gr < row_end ? (MODE == 0 ? rata[gr] * ld : (gr - k0) * kLuMaxJB) : -1;
   }
-  for (int i = tid; i < jb; i += 256) boff_s[i] = rat[k0 + i] * ld;
+  for (int i = tid; i < jb; i += NT) boff_s[i] = rat[k0 + i] * ld;
   __syncthreads();
 
-  // per-thread staging roles: A (row r = tid/8 + 32q, k-pair kp = tid%8),
-  // B (k row kr = tid/64 + 4q, column pair cp = tid%64)
+  // per-thread staging roles: A (row r = tid/8 + (NT/8) q, k-pair kp = tid%8),
+  // B (k row kr = tid/64 + NW q, column pair cp = tid%64)
   const int kp = tid & 7, cp = tid & 63;
-  int aoff[4];
-  bool aval[4];
+  int aoff[AQ];
+  bool aval[AQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int o = aoff_s[(tid >> 3) + 32 * q];
+  for (int q = 0; q < AQ; ++q) {
+    const int o = aoff_s[(tid >> 3) + (NT / 8) * q];
     aval[q] = o >= 0;
     aoff[q] = o >= 0 ? o : 0;
   }
@@ -764,24 +769,28 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
   // Loads go to clamped, always-valid addresses; the zero masks are applied
   // when the staged values are written to LDS, so the loads stay in flight
   // across the products of the current chunk.
-  float4 ra[4], rb[4];
+  float4 ra[AQ], rb[BQ];
   auto load_tile = [&](int kk) {  // kk: chunk offset relative to k0
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < AQ; ++q)
       ra[q] = *reinterpret_cast<const float4*>(Asrc + aoff[q] + (MODE == 0 ? k0 : 0) + kk + 2 * kp);
-      rb[q] = *reinterpret_cast<const float4*>(T + boff_s[kk + (tid >> 6) + 4 * q] + gcl);
-    }
+#pragma unroll
+    for (int q = 0; q < BQ; ++q)
+      rb[q] = *reinterpret_cast<const float4*>(T + boff_s[kk + (tid >> 6) + NW * q] + gcl);
   };
   auto store_tile = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = (tid >> 3) + 32 * q;
+    for (int q = 0; q < AQ; ++q) {
+      const int r = (tid >> 3) + (NT / 8) * q;
       const bool va = aval[q];
       As[buf][2 * kp][2 * r] = va ? ra[q].x : 0.f;
       As[buf][2 * kp][2 * r + 1] = va ? ra[q].y : 0.f;
       As[buf][2 * kp + 1][2 * r] = va ? ra[q].z : 0.f;
       As[buf][2 * kp + 1][2 * r + 1] = va ? ra[q].w : 0.f;
-      const int kr = (tid >> 6) + 4 * q;
+    }
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) {
+      const int kr = (tid >> 6) + NW * q;
       Bs[buf][kr][0][2 * cp] = bval0 ? rb[q].x : 0.f;
       Bs[buf][kr][1][2 * cp] = bval0 ? rb[q].y : 0.f;
       Bs[buf][kr][0][2 * cp + 1] = bval1 ? rb[q].z : 0.f;
@@ -793,10 +802,10 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
   // + r%4 of the 32-row block, i.e. complex row 4(r/4) + 2(l/32) + (r%4)/2
   // (component r%2), and complex column l%32.  MODE 0 starts from C and
   // accumulates -L21 U12, so the epilogue only stores; MODE 1 starts from 0.
-  floatx16 acc[4][2];
+  floatx16 acc[MI][2];
   if (MODE == 0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int gcol = col0 + wcn + j * 32 + (lane & 31);
@@ -813,7 +822,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
       }
   } else {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -834,30 +843,30 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
     const int buf = kc & 1;
     if (kc + 1 < nk) load_tile((kc + 1) * kG32KC);
     // operands of step k+1 are read while the products of step k issue
-    float af[2][4], bf[2][2];
-    auto frag = [&](int k, float (&a)[4], float (&bb)[2]) {
+    float af[2][MI], bf[2][2];
+    auto frag = [&](int k, float (&a)[MI], float (&bb)[2]) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = asign * As[buf][k][2 * (wr + i * 16 + arow) + acomp];
+      for (int i = 0; i < MI; ++i) a[i] = asign * As[buf][k][2 * (wr + i * 16 + arow) + acomp];
 #pragma unroll
       for (int j = 0; j < 2; ++j) bb[j] = Bs[buf][k][bu][wcn + j * 32 + bcol];
     };
     frag(0, af[0], bf[0]);
-    __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
-    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, (MI + 2) / 2, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, MI, 0);
 #pragma unroll
     for (int k = 0; k < kG32KC; ++k) {
       if (k + 1 < kG32KC) frag(k + 1, af[(k + 1) & 1], bf[(k + 1) & 1]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[k & 1][i], bf[k & 1][j], acc[i][j], 0, 0, 0);
       // issue order: the next step's LDS reads, then this step's products
       if (k + 1 < kG32KC) {
-        __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);  // DS reads
-        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // sign multiplies
+        __builtin_amdgcn_sched_group_barrier(0x100, (MI + 2) / 2, 0);  // DS reads
+        __builtin_amdgcn_sched_group_barrier(0x002, MI, 0);  // sign multiplies
       }
-      __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);    // MFMA
+      __builtin_amdgcn_sched_group_barrier(0x008, 2 * MI, 0);    // MFMA
     }
     if (kc + 1 < nk) {
       store_tile(buf ^ 1);
@@ -867,7 +876,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_gemm_c64(const MatDesc* __restric
 
   // epilogue: store the block (C - L21 U12 in MODE 0, U12 in MODE 1)
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int gcol = col0 + wcn + j * 32 + (lane & 31);
@@ -1379,7 +1388,7 @@ static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int 
   }
   if (s.tot_trsm[part] > 0) {
     if constexpr (sizeof(P) == 4)
-      hipLaunchKernelGGL(k_lu_gemm_c64<1>, dim3(xcd_grid(s.tot_trsm[part])), dim3(256), 0, st, d_md,
+      hipLaunchKernelGGL((k_lu_gemm_c64<1, kG32Waves>), dim3(xcd_grid(s.tot_trsm[part])), dim3(64 * kG32Waves), 0, st, d_md,
                          d_prefix + s.off_trsm[part], s.nact, s.tot_trsm[part], s.k0, plan.jb, T, rows, skip, Linv,
                          rows, coff, ntn);
     else
@@ -1397,7 +1406,7 @@ static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int 
       (void)hipEventRecord(ev0, st);
     }
     if constexpr (sizeof(P) == 4)
-      hipLaunchKernelGGL(k_lu_gemm_c64<0>, dim3(xcd_grid(s.tot_gemm[part])), dim3(256), 0, st, d_md,
+      hipLaunchKernelGGL((k_lu_gemm_c64<0, kG32Waves>), dim3(xcd_grid(s.tot_gemm[part])), dim3(64 * kG32Waves), 0, st, d_md,
                          d_prefix + s.off_gemm[part], s.nact, s.tot_gemm[part], s.k0, plan.jb, T, rows, skip, Linv,
                          rows_ac, coff, ntn);
     else
