@@ -902,8 +902,10 @@ __global__ __launch_bounds__(64 * NW) void k_lu_gemm_c64(const MatDesc* __restri
 // Grid: the row tiles of all active matrices (prefix table).  Operand lane
 // roles and the accumulator layout are those of k_lu_gemm_c64.
 constexpr int kP0TM = 128, kP0TN = kPart0Cols, kP0KC = 16;
+constexpr int kP0Waves = 8;  // waves per group
 
-__global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restrict__ md,
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_lu_part0_c64(const MatDesc* __restrict__ md,
                                                       const int* __restrict__ prefix, int nact, int total, int k0,
                                                       int jbmax, c64* __restrict__ Tb, const int* __restrict__ rowb,
                                                       const int* __restrict__ skip, const c64* __restrict__ Linv,
@@ -924,6 +926,11 @@ __global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restri
   const c64* __restrict__ Li = Linv + (long long)b * kLuMaxJB * kLuMaxJB;
 
   constexpr int K = kSolveBlkLu;          // 64 = jbmax
+  constexpr int NT = 64 * NW;
+  // U12 (64 x 64): 4 row blocks x 2 column blocks of 16 x 32, CB1 per wave;
+  // update (128 x 64): each wave 128/NW rows (MI3 blocks of 16) x 64 columns
+  constexpr int CB1 = 8 / NW, MI3 = kP0TM / NW / 16, AQ3 = kP0TM * kP0KC / 2 / NT;
+  static_assert(CB1 >= 1 && MI3 >= 1 && AQ3 >= 1, "wave layout");
   constexpr int SA = 2 * K + 4;           // phase 1: inv(L11) as [k][2 row + comp]
   constexpr int SC = 2 * kP0TM + 4;       // phase 2: L21 chunks as [buf][k][2 row + comp]
   constexpr int kSa = K * SA > 2 * kP0KC * SC ? K * SA : 2 * kP0KC * SC;
@@ -940,7 +947,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restri
 
   // ---- stage inv(L11) (64 x 64, row-major, stride kLuMaxJB) and A12 (the
   // panel's rows, columns s0 .. s0+63; zero beyond the matrix)
-  for (int e = tid; e < K * K / 2; e += 256) {
+  for (int e = tid; e < K * K / 2; e += NT) {
     const int r = e / (K / 2), kp = e - r * (K / 2);
     const float4 x = *reinterpret_cast<const float4*>(Li + (long long)r * kLuMaxJB + 2 * kp);
     Sa[(2 * kp) * SA + 2 * r] = x.x;
@@ -948,7 +955,7 @@ __global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restri
     Sa[(2 * kp + 1) * SA + 2 * r] = x.z;
     Sa[(2 * kp + 1) * SA + 2 * r + 1] = x.w;
   }
-  for (int e = tid; e < K * kP0TN / 2; e += 256) {
+  for (int e = tid; e < K * kP0TN / 2; e += NT) {
     const int k = e / (kP0TN / 2), cp = e - k * (kP0TN / 2);
     const int gc = s0 + 2 * cp;
     const float4 x = *reinterpret_cast<const float4*>(T + (long long)rat[k0 + k] * ld + min(gc, ld - 2));
@@ -971,53 +978,56 @@ __global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restri
     if (store_u12) arrivals[b] = 0;  // every group of this matrix has arrived
   }
 
-  // ---- U12 rows 16 w .. 16 w + 15 on wave w (inv(L11) is lower triangular:
-  // k runs to the block's last row)
-  floatx16 u[2];
+  // ---- U12: wave w takes row block rb1 (rows 16 rb1 .. 16 rb1 + 15) and
+  // CB1 column blocks from cb1 on (inv(L11) is lower triangular: k runs to
+  // the block's last row)
+  const int rb1 = wave * CB1 / 2, cb1 = (wave * CB1) % 2;
+  floatx16 u[CB1];
 #pragma unroll
-  for (int j = 0; j < 2; ++j)
+  for (int j = 0; j < CB1; ++j)
 #pragma unroll
     for (int r = 0; r < 16; ++r) u[j][r] = 0.f;
-  const int kend = 16 * wave + 16;
+  const int kend = 16 * rb1 + 16;
   for (int k = 0; k < kend; ++k) {
-    const float a = asign * Sa[k * SA + 2 * (16 * wave + arow) + acomp];
+    const float a = asign * Sa[k * SA + 2 * (16 * rb1 + arow) + acomp];
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      u[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, Sb[k][bu][j * 32 + bcol], u[j], 0, 0, 0);
+    for (int j = 0; j < CB1; ++j)
+      u[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, Sb[k][bu][(cb1 + j) * 32 + bcol], u[j], 0, 0, 0);
   }
   __syncthreads();  // every wave is done with A12 and inv(L11)
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int col = j * 32 + (lane & 31);
+  for (int j = 0; j < CB1; ++j) {
+    const int col = (cb1 + j) * 32 + (lane & 31);
 #pragma unroll
     for (int r = 0; r < 16; r += 2) {
-      const int k = 16 * wave + 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
+      const int k = 16 * rb1 + 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
       Sb[k][0][col] = u[j][r];
       Sb[k][1][col] = u[j][r + 1];
       if (store_u12 && col < ncol) T[(long long)rat[k0 + k] * ld + s0 + col] = c64{u[j][r], u[j][r + 1]};
     }
   }
 
-  // ---- C -= L21 U12: wave w takes rows 32 w .. 32 w + 31 (two 16-row
-  // blocks) and both 32-column blocks; C is loaded into the accumulators
+  // ---- C -= L21 U12: wave w takes rows (128/NW) w .. (MI3 16-row blocks)
+  // and both 32-column blocks; C is loaded into the accumulators
   const int kp = tid & 7;
-  int aoff[4];
-  bool aval[4];
+  const int wr3 = wave * MI3 * 16;
+  int aoff[AQ3];
+  bool aval[AQ3];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int o = aoff_s[(tid >> 3) + 32 * q];
+  for (int q = 0; q < AQ3; ++q) {
+    const int o = aoff_s[(tid >> 3) + (NT / 8) * q];
     aval[q] = o >= 0;
     aoff[q] = o >= 0 ? o : 0;
   }
-  float4 ra[4];
+  float4 ra[AQ3];
   auto load_chunk = [&](int kk) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) ra[q] = *reinterpret_cast<const float4*>(T + aoff[q] + k0 + kk + 2 * kp);
+    for (int q = 0; q < AQ3; ++q) ra[q] = *reinterpret_cast<const float4*>(T + aoff[q] + k0 + kk + 2 * kp);
   };
   auto store_chunk = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = (tid >> 3) + 32 * q;
+    for (int q = 0; q < AQ3; ++q) {
+      const int r = (tid >> 3) + (NT / 8) * q;
       float* base = Sa + (buf * kP0KC) * SC;
       base[(2 * kp) * SC + 2 * r] = aval[q] ? ra[q].x : 0.f;
       base[(2 * kp) * SC + 2 * r + 1] = aval[q] ? ra[q].y : 0.f;
@@ -1025,16 +1035,16 @@ __global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restri
       base[(2 * kp + 1) * SC + 2 * r + 1] = aval[q] ? ra[q].w : 0.f;
     }
   };
-  floatx16 acc[2][2];
+  floatx16 acc[MI3][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI3; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int gcol = s0 + j * 32 + (lane & 31);
       const int gcl = min(gcol, ld - 1);
 #pragma unroll
       for (int r = 0; r < 16; r += 2) {
-        const int lr = 32 * wave + 16 * i + 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
+        const int lr = wr3 + 16 * i + 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
         const int o = aoff_s[lr];
         const c64 cv = T[(o >= 0 ? o : 0) + gcl];
         const bool ok = o >= 0 && j * 32 + (lane & 31) < ncol;
@@ -1053,14 +1063,14 @@ __global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restri
     const float* base = Sa + (buf * kP0KC) * SC;
 #pragma unroll
     for (int k = 0; k < kP0KC; ++k) {
-      float a[2];
+      float a[MI3];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = -asign * base[k * SC + 2 * (32 * wave + 16 * i + arow) + acomp];
+      for (int i = 0; i < MI3; ++i) a[i] = -asign * base[k * SC + 2 * (wr3 + 16 * i + arow) + acomp];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const float bb = Sb[kc * kP0KC + k][bu][j * 32 + bcol];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], bb, acc[i][j], 0, 0, 0);
+        for (int i = 0; i < MI3; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], bb, acc[i][j], 0, 0, 0);
       }
     }
     if (kc + 1 < nk) {
@@ -1069,14 +1079,14 @@ __global__ __launch_bounds__(256, 2) void k_lu_part0_c64(const MatDesc* __restri
     }
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI3; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int col = j * 32 + (lane & 31);
       if (col >= ncol) continue;
 #pragma unroll
       for (int r = 0; r < 16; r += 2) {
-        const int lr = 32 * wave + 16 * i + 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
+        const int lr = wr3 + 16 * i + 4 * (r >> 2) + 2 * (lane >> 5) + ((r & 3) >> 1);
         const int o = aoff_s[lr];
         if (o >= 0) T[o + s0 + col] = c64{acc[i][j][r], acc[i][j][r + 1]};
       }
@@ -1378,7 +1388,7 @@ static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int 
   if constexpr (sizeof(P) == 4) {
     if (part == 0) {  // fused U12 product and update of the first columns
       if (s.tot_gemm[0] > 0) {
-        hipLaunchKernelGGL(k_lu_part0_c64, dim3(xcd_grid(s.tot_gemm[0])), dim3(256), 0, st, d_md,
+        hipLaunchKernelGGL((k_lu_part0_c64<kP0Waves>), dim3(xcd_grid(s.tot_gemm[0])), dim3(64 * kP0Waves), 0, st, d_md,
                            d_prefix + s.off_gemm[0], s.nact, s.tot_gemm[0], s.k0, plan.jb, T, rows, skip, Linv,
                            arrivals);
         return hipGetLastError();
