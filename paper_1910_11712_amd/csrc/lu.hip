@@ -249,13 +249,75 @@ __device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
   return (unsigned)__builtin_amdgcn_readlane(x, 63);
 }
 
-// Panel columns right of a finished leaf (columns c0+wc .. k0+jb-1): the
-// leaf's top rows become rows of U by a unit lower solve with the leaf's top
-// block, then every row below takes the rank-wc update.  top: this thread's
-// leaf row when tid < wc (the leaf's top rows).
+// Leaf rows between the row-major factor and the LDS block S (one chunk of
+// kPanelThreads logical rows from rbase).  A row's W-column segment is 128
+// bytes (64 for the 8-rows-per-thread leaves) split into 16-byte pieces, one
+// per lane, so every load or store instruction of a wave covers whole rows
+// instead of one row per lane.  The segment start is 16-byte aligned (the
+// leading dimension is a multiple of 16 elements and c0 a multiple of W), and
+// a whole segment lies inside the padded row, so loads need no column bound;
+// stores stop at column c0 + wc.
+template <typename P, int W>
+__device__ __forceinline__ void leaf_to_lds(const cx<P>* __restrict__ T, const int* rat, int ld, int k0, int c0,
+                                            int rbase, int nrow, cx<P> (&S)[kPanelThreads][W + 1]) {
+  constexpr int CP = 16 / (int)sizeof(cx<P>);  // elements per piece
+  constexpr int LPR = W / CP;                   // pieces per row
+  constexpr int RPP = kPanelThreads / LPR;      // rows per pass
+  static_assert(W % CP == 0 && kPanelThreads % LPR == 0, "whole pieces per row");
+  const int q = threadIdx.x % LPR, rr = threadIdx.x / LPR;
+#pragma unroll
+  for (int p = 0; p < LPR; ++p) {
+    const int lr = p * RPP + rr;
+    if (lr < nrow) {
+      const cx<P>* src = T + (long long)rat[rbase + lr - k0] * ld + c0 + q * CP;
+      if constexpr (CP == 2) {
+        const float4 t = *reinterpret_cast<const float4*>(src);
+        cput(S[lr][2 * q], cx<P>{t.x, t.y});
+        cput(S[lr][2 * q + 1], cx<P>{t.z, t.w});
+      } else {
+        const double2 t = *reinterpret_cast<const double2*>(src);
+        cput(S[lr][q], cx<P>{t.x, t.y});
+      }
+    }
+  }
+}
+
+template <typename P, int W>
+__device__ __forceinline__ void lds_to_leaf(cx<P>* __restrict__ T, const int* rat, int ld, int k0, int c0, int rbase,
+                                            int nrow, int wc, const cx<P> (&S)[kPanelThreads][W + 1]) {
+  constexpr int CP = 16 / (int)sizeof(cx<P>);
+  constexpr int LPR = W / CP;
+  constexpr int RPP = kPanelThreads / LPR;
+  const int q = threadIdx.x % LPR, rr = threadIdx.x / LPR;
+#pragma unroll
+  for (int p = 0; p < LPR; ++p) {
+    const int lr = p * RPP + rr;
+    if (lr < nrow && q * CP < wc) {
+      cx<P>* dst = T + (long long)rat[rbase + lr - k0] * ld + c0 + q * CP;
+      if constexpr (CP == 2) {
+        const cx<P> x0 = cget(S[lr][2 * q]), x1 = cget(S[lr][2 * q + 1]);
+        if (2 * q + 1 < wc)
+          *reinterpret_cast<float4*>(dst) = make_float4(x0.re, x0.im, x1.re, x1.im);
+        else
+          *reinterpret_cast<float2*>(dst) = make_float2(x0.re, x0.im);  // odd last column
+      } else {
+        const cx<P> x0 = cget(S[lr][q]);
+        *reinterpret_cast<double2*>(dst) = make_double2(x0.re, x0.im);
+      }
+    }
+  }
+}
+
+// The end of a leaf (columns c0 .. c0+wc-1, held in registers as a[i][w] for
+// logical rows c0 + tid + i*kPanelThreads): the leaf's top rows make the
+// panel columns right of it (c0+wc .. k0+jb-1) rows of U by a unit lower
+// solve with the leaf's top block; then, one chunk of kPanelThreads rows at a
+// time, the chunk's leaf rows go to LDS, from there to the factor (coalesced),
+// and, as the L operand, into the rank-wc update of the right columns.  The
+// row map must hold the leaf's physical rows before the call.
 template <typename P, int W, int RPT>
 __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const int* rat, int ld, int n, int k0,
-                                                   int jb, int c0, int wc, const cx<P> (&top)[W],
+                                                   int jb, int c0, int wc, const cx<P> (&a)[RPT][W],
                                                    cx<P> (&Ltop)[W][W], cx<P> (&Utop)[W][kLuMaxJB],
                                                    cx<P> (&Lc)[kPanelThreads][W + 1]) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -265,7 +327,7 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
   if (nr > 0) {
     if (tid < wc) {
 #pragma unroll
-      for (int w = 0; w < W; ++w) cput(Ltop[tid][w], cget(top[w]));
+      for (int w = 0; w < W; ++w) cput(Ltop[tid][w], cget(a[0][w]));
     }
     __syncthreads();
     static_assert(kLuMaxJB <= kPanelThreads, "one thread per right-hand column of the panel");
@@ -286,132 +348,105 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
         }
       }
     }
-    __syncthreads();
-    // rows >= rc0: A[r][right] -= L[r][leaf] U[leaf][right], 512 rows at a
-    // time, the chunk's L through LDS.
-    if constexpr (sizeof(P) == 4) {
-      // Complex FP32: on the matrix cores.  A wave takes 16 x 32 complex
-      // blocks of the right part; C is loaded into the accumulators, the
-      // leaf's W complex k run as W v_mfma_f32_32x32x2f32 on the real 2x2
-      // embedding (A operand negated, so the sum is C - L U), and the block
-      // is stored back.
-      constexpr int RB = 16, CB = 32;
-      const int ncb = (nr + CB - 1) / CB;
-      const int at = lane & 1, au = lane >> 5, arow = (lane & 31) >> 1;
-      const int acomp = at ^ au;
-      const float asign = (at == 0 && au == 1) ? 1.f : -1.f;
-      const int gcol = rc0 + (lane & 31);
-      for (int i = 0; i < RPT; ++i) {
-        const int rbase = c0 + i * kPanelThreads;
-        if (rbase >= n) continue;  // uniform
-        {
-          // the chunk's L rows, read back from the leaf this thread wrote
-          const int r = rbase + tid;
-          const bool live = r >= rc0 && r < n;
-          const cx<P>* src = T + (long long)rat[(live ? r : rc0) - k0] * ld + c0;
+    // (the chunk loop's first barrier orders Utop before its readers)
+  }
+  // rows >= rc0: A[r][right] -= L[r][leaf] U[leaf][right], one chunk of
+  // kPanelThreads rows at a time, the chunk's L rows in LDS
+  for (int i = 0; i < RPT; ++i) {
+    const int rbase = c0 + i * kPanelThreads;
+    if (rbase >= n) break;  // uniform
+    const int nrow = min(kPanelThreads, n - rbase);
+    // this thread's row of chunk i (selects: a[][] stays in registers)
 #pragma unroll
-          for (int w = 0; w < W; ++w) {
-            const cx<P> v = src[w < wc ? w : 0];
-            Lc[tid][w] = (live && w < wc) ? v : cx<P>{P(0), P(0)};
-          }
-        }
-        __syncthreads();
+    for (int w = 0; w < W; ++w) {
+      cx<P> v = cget(a[0][w]);
+#pragma unroll
+      for (int u = 1; u < RPT; ++u) v = csel(i == u, cget(a[u][w]), v);
+      cput(Lc[tid][w], w < wc ? v : cx<P>{P(0), P(0)});
+    }
+    __syncthreads();
+    lds_to_leaf<P, W>(T, rat, ld, k0, c0, rbase, nrow, wc, Lc);
+    if (nr > 0) {
+      if constexpr (sizeof(P) == 4) {
+        // Complex FP32: on the matrix cores.  A wave takes four 16-row blocks
+        // of one 32-column block of the right part; C is loaded into the
+        // accumulators, the leaf's W complex k run as W v_mfma_f32_32x32x2f32
+        // on the real 2x2 embedding (A operand negated, so the sum is C - L U),
+        // and the blocks are stored back.  Rows of a block below rc0 or past n
+        // compute discarded values.
+        // four row blocks per unit; two where the leaf rows held in registers
+        // (RPT * W complex) leave too few for four blocks' accumulators
+        constexpr int RB = 16, CB = 32, NRB = RPT * W > 32 ? 2 : 4;
+        const int ncb = (nr + CB - 1) / CB;
+        const int at = lane & 1, au = lane >> 5, arow = (lane & 31) >> 1;
+        const int acomp = at ^ au;
+        const float asign = (at == 0 && au == 1) ? 1.f : -1.f;
         const int rb_lo = max(0, rc0 - rbase) / RB;
-        const int rb_hi = (min(kPanelThreads, n - rbase) + RB - 1) / RB;
-        // a wave takes two consecutive 16-row blocks and two 32-column blocks
-        // per pass: all the pass's C loads are in flight before the products
-        constexpr int NRB = 2, NCB = 2;
-        for (int cb0 = 0; cb0 < ncb; cb0 += NCB) {
-          for (int rb0 = rb_lo + wave * NRB; rb0 < rb_hi; rb0 += (kPanelThreads / 64) * NRB) {
-            floatx16 acc[NRB][NCB];
-            int roff[NRB][8];
-            bool rok[NRB][8];
-            int rbq[NRB];
+        const int rb_hi = (nrow + RB - 1) / RB;
+        const int nquad = (rb_hi - rb_lo + NRB - 1) / NRB;
+        for (int unit = wave; unit < nquad * ncb; unit += kPanelThreads / 64) {
+          const int cb = unit / nquad, rb0 = rb_lo + NRB * (unit - cb * nquad);
+          const int col = rc0 + CB * cb + (lane & 31);
+          const bool cok = col < k0 + jb;
+          floatx16 acc[NRB];
+          int roff[NRB][8];
+          bool rok[NRB][8];
+          int rbq[NRB];
+#pragma unroll
+          for (int q = 0; q < NRB; ++q) {
+            const bool vq = rb0 + q < rb_hi;  // uniform
+            rbq[q] = vq ? rb0 + q : rb0;
+#pragma unroll
+            for (int e = 0; e < 16; e += 2) {
+              const int r = rbase + RB * (rb0 + q) + 4 * (e >> 2) + 2 * (lane >> 5) + ((e & 3) >> 1);
+              rok[q][e >> 1] = vq && r >= rc0 && r < n;
+              roff[q][e >> 1] = rat[(rok[q][e >> 1] ? r : rc0) - k0] * ld;
+            }
+          }
+          const int cc = cok ? col : rc0;
+#pragma unroll
+          for (int q = 0; q < NRB; ++q)
+#pragma unroll
+            for (int e = 0; e < 16; e += 2) {
+              const cx<P> cv = T[roff[q][e >> 1] + cc];
+              const bool ok = cok && rok[q][e >> 1];
+              acc[q][e] = ok ? cv.re : 0.f;
+              acc[q][e + 1] = ok ? cv.im : 0.f;
+            }
+#pragma unroll
+          for (int k = 0; k < W; ++k) {
+            const cx<P> uv = Utop[k][min(CB * cb, kLuMaxJB - CB) + (lane & 31)];
+            const float bv = au ? uv.im : uv.re;
 #pragma unroll
             for (int q = 0; q < NRB; ++q) {
-              const bool vq = rb0 + q < rb_hi;  // uniform
-              rbq[q] = vq ? rb0 + q : rb0;
-#pragma unroll
-              for (int e = 0; e < 16; e += 2) {
-                const int r = rbase + RB * (rb0 + q) + 4 * (e >> 2) + 2 * (lane >> 5) + ((e & 3) >> 1);
-                rok[q][e >> 1] = vq && r >= rc0 && r < n;
-                roff[q][e >> 1] = rat[(rok[q][e >> 1] ? r : rc0) - k0] * ld;
-              }
-            }
-#pragma unroll
-            for (int c = 0; c < NCB; ++c) {
-              const int col = gcol + CB * (cb0 + c);
-              const bool cok = cb0 + c < ncb && col < k0 + jb;
-              const int cc = cok ? col : rc0;
-#pragma unroll
-              for (int q = 0; q < NRB; ++q)
-#pragma unroll
-                for (int e = 0; e < 16; e += 2) {
-                  const cx<P> cv = T[roff[q][e >> 1] + cc];
-                  const bool ok = cok && rok[q][e >> 1];
-                  acc[q][c][e] = ok ? cv.re : 0.f;
-                  acc[q][c][e + 1] = ok ? cv.im : 0.f;
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-              float bv[NCB];
-#pragma unroll
-              for (int c = 0; c < NCB; ++c) {
-                const cx<P> uv = Utop[k][min(CB * (cb0 + c), kLuMaxJB - CB) + (lane & 31)];
-                bv[c] = au ? uv.im : uv.re;
-              }
-#pragma unroll
-              for (int q = 0; q < NRB; ++q) {
-                const cx<P> lv = Lc[RB * rbq[q] + arow][k];
-                const float av = asign * (acomp ? lv.im : lv.re);
-#pragma unroll
-                for (int c = 0; c < NCB; ++c)
-                  acc[q][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[c], acc[q][c], 0, 0, 0);
-              }
-            }
-#pragma unroll
-            for (int c = 0; c < NCB; ++c) {
-              const int col = gcol + CB * (cb0 + c);
-              if (cb0 + c < ncb && col < k0 + jb) {
-#pragma unroll
-                for (int q = 0; q < NRB; ++q)
-#pragma unroll
-                  for (int e = 0; e < 16; e += 2)
-                    if (rok[q][e >> 1]) T[roff[q][e >> 1] + col] = cx<P>{acc[q][c][e], acc[q][c][e + 1]};
-              }
+              const cx<P> lv = Lc[RB * rbq[q] + arow][k];
+              const float av = asign * (acomp ? lv.im : lv.re);
+              acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[q], 0, 0, 0);
             }
           }
-        }
-        __syncthreads();
-      }
-    } else {
-      for (int i = 0; i < RPT; ++i) {
-        const int rbase = c0 + i * kPanelThreads;
-        if (rbase >= n) continue;  // uniform
-        {
-          const int r = rbase + tid;
-          const bool live = r < n;
-          const cx<P>* src = T + (long long)rat[(live ? r : c0) - k0] * ld + c0;
+          if (cok) {
 #pragma unroll
-          for (int w = 0; w < W; ++w) {
-            const cx<P> v = src[w < wc ? w : 0];
-            Lc[tid][w] = (live && w < wc) ? v : cx<P>{P(0), P(0)};
+            for (int q = 0; q < NRB; ++q)
+#pragma unroll
+              for (int e = 0; e < 16; e += 2)
+                if (rok[q][e >> 1]) T[roff[q][e >> 1] + col] = cx<P>{acc[q][e], acc[q][e + 1]};
           }
         }
-        __syncthreads();
-        const int rlo = max(rbase, rc0), rhi = min(n, rbase + kPanelThreads);
+      } else {
+        const int rlo = max(rbase, rc0), rhi = rbase + nrow;
         // each wave takes kRows rows at a time so that their loads are in
-        // flight together; full leaves and full row batches run branch-free
-        constexpr int kRows = 8;
+        // flight together (fewer where the leaf rows held in registers are
+        // many); full leaves and full row batches run branch-free
+        constexpr int kLeafWords = RPT * W * (int)sizeof(cx<P>) / 4;
+        constexpr int kRows = kLeafWords >= 128 ? 2 : kLeafWords > 64 ? 4 : 8;
         for (int r0 = rlo + wave * kRows; r0 < rhi; r0 += (kPanelThreads / 64) * kRows) {
-          const int nrow = min(kRows, rhi - r0);
+          const int nrw = min(kRows, rhi - r0);
           for (int j = lane; j < nr; j += 64) {
             long long off[kRows];
             cx<P> acc[kRows];
 #pragma unroll
             for (int u = 0; u < kRows; ++u) {
-              const int r = r0 + min(u, nrow - 1);
+              const int r = r0 + min(u, nrw - 1);
               off[u] = (long long)rat[r - k0] * ld + rc0 + j;
             }
 #pragma unroll
@@ -419,14 +454,14 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
             if (wc == W) {
 #pragma unroll
               for (int u = 0; u < kRows; ++u) {
-                const int lr = r0 + min(u, nrow - 1) - rbase;
+                const int lr = r0 + min(u, nrw - 1) - rbase;
 #pragma unroll
                 for (int w = 0; w < W; ++w) acc[u] = fms(acc[u], Lc[lr][w], Utop[w][j]);
               }
             } else {
 #pragma unroll
               for (int u = 0; u < kRows; ++u) {
-                const int lr = r0 + min(u, nrow - 1) - rbase;
+                const int lr = r0 + min(u, nrw - 1) - rbase;
                 for (int w = 0; w < wc; ++w) acc[u] = fms(acc[u], Lc[lr][w], Utop[w][j]);
               }
             }
@@ -436,9 +471,9 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
             for (int u = kRows - 1; u >= 0; --u) T[off[u]] = acc[u];
           }
         }
-        __syncthreads();
       }
     }
+    __syncthreads();
   }
 }
 
@@ -489,23 +524,26 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
     // the leaf: logical rows c0 + tid + i*512 with their physical rows ph;
     // row exchanges move data and physical row together, and the row map is
     // written once at the end of the leaf
+    // (staged through LDS one chunk of kPanelThreads rows at a time so that
+    // the loads are coalesced; columns from wc on are zero)
     cx<P> a[RPT][W];
     int ph[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int r = c0 + tid + i * kPanelThreads;
+      const int rbase = c0 + i * kPanelThreads, r = rbase + tid;
 #pragma unroll
       for (int w = 0; w < W; ++w) a[i][w] = cx<P>{P(0), P(0)};
       ph[i] = 0;
-      if (r < n) {
-        ph[i] = rat[r - k0];
-        const cx<P>* src = T + (long long)ph[i] * ld + c0;
+      if (rbase < n) {  // uniform
+        if (i > 0) __syncthreads();  // the previous chunk has been read
+        leaf_to_lds<P, W>(T, rat, ld, k0, c0, rbase, min(kPanelThreads, n - rbase), Lc);
+        __syncthreads();
+        if (r < n) {
+          ph[i] = rat[r - k0];
 #pragma unroll
-        for (int w = 0; w < W; ++w)
-          if (w < wc) {
-            a[i][w].re = src[w].re;
-            a[i][w].im = src[w].im;
-          }
+          for (int w = 0; w < W; ++w)
+            if (w < wc) cput(a[i][w], cget(Lc[tid][w]));
+        }
       }
     }
 
@@ -603,24 +641,15 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
       }
     }
 
-    // ---- write the leaf back and record its row exchanges in the row map
-    // (visible to the right update after its first barrier)
+    // ---- record the leaf's row exchanges in the row map (visible after the
+    // next barrier), then store the leaf and update the columns right of it
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = c0 + tid + i * kPanelThreads;
-      if (r < n) {
-        cx<P>* dst = T + (long long)ph[i] * ld + c0;
-#pragma unroll
-        for (int w = 0; w < W; ++w)
-          if (w < wc) {
-            dst[w].re = a[i][w].re;
-            dst[w].im = a[i][w].im;
-          }
-        rat[r - k0] = ph[i];
-      }
+      if (r < n) rat[r - k0] = ph[i];
     }
 
-    panel_right_update<P, W, RPT>(T, rat, ld, n, k0, jb, c0, wc, a[0], Ltop, Utop, Lc);
+    panel_right_update<P, W, RPT>(T, rat, ld, n, k0, jb, c0, wc, a, Ltop, Utop, Lc);
   }
   __syncthreads();
   for (int r = tid; r < m; r += kPanelThreads) rowo[k0 + r] = rat[r];
