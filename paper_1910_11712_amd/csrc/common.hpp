@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -57,8 +58,8 @@ __host__ __device__ __forceinline__ cx<P> csel(bool c, cx<P> a, cx<P> b) {
   return {c ? a.re : b.re, c ? a.im : b.im};
 }
 template <typename P>
-__host__ __device__ __forceinline__ P abs1(cx<P> a) {  // |Re| + |Im|
-  return (a.re < 0 ? -a.re : a.re) + (a.im < 0 ? -a.im : a.im);
+__host__ __device__ __forceinline__ P abs1(cx<P> a) {  // |Re| + |Im|, +0 for signed zeros
+  return std::fabs(a.re) + std::fabs(a.im);
 }
 template <typename P>
 __host__ __device__ __forceinline__ P norm2(cx<P> a) { return a.re * a.re + a.im * a.im; }

@@ -496,7 +496,10 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
   int* __restrict__ rowo = rdst + d.offRow;
 
   __shared__ int rat[kMaxPanelRows];
-  __shared__ __align__(16) uint2 redk[2][kPanelThreads / 64];  // per wave: (key, row) of its candidate
+  // the column's best candidate, (key << 32) | ~row, by an LDS atomic max of
+  // every wave's candidate; three slots in rotation, so that a slot is
+  // cleared a column after its last read and a column before its next use
+  __shared__ unsigned long long redm[3];
   __shared__ cx<P> xbuf[2][W];                    // row c, for the pivot row's owner
   __shared__ int xph[2];
   __shared__ cx<P> wrow[2][kPanelThreads / 64][W];  // per wave: its candidate row
@@ -515,10 +518,11 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
   const int m = n - k0;
   for (int r = tid; r < m; r += kPanelThreads) rat[r] = rowg[k0 + r];
   for (int r = tid; r < k0; r += kPanelThreads) rowo[r] = rowg[r];  // rows above the panel: unchanged
+  if (tid < 3) redm[tid] = 0ull;
   __syncthreads();
 
   int zp = n;  // first zero pivot (uniform)
-  int par = 0;
+  int par = 0, slot = 0;
   for (int c0 = k0; c0 < k0 + jb; c0 += W) {
     const int wc = min(W, k0 + jb - c0);
     // the leaf: logical rows c0 + tid + i*512 with their physical rows ph;
@@ -566,7 +570,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
         // holds it publishes the row (a branch taken by that lane alone)
         const unsigned wkey = wave_max_u32(key);
         const unsigned wr = wave_min_u32(key == wkey ? (unsigned)row : 0xffffffffu);
-        if (lane == 0) redk[par][wave] = make_uint2(wkey, wr);
+        if (lane == 0) atomicMax(&redm[slot], ((unsigned long long)wkey << 32) | (0xffffffffu - wr));
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
           if (wkey != 0u && c0 + tid + i * kPanelThreads == (int)wr) {
@@ -587,16 +591,11 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
           xph[par] = ph[0];
         }
         __syncthreads();
-        uint2 best = redk[par][0];
-        int wq = 0;
-#pragma unroll
-        for (int q = 1; q < kPanelThreads / 64; ++q) {
-          const uint2 o = redk[par][q];
-          const bool take = o.x > best.x || (o.x == best.x && o.y < best.y);
-          best = take ? o : best;
-          wq = take ? q : wq;
-        }
-        const int p = (int)best.y;
+        // the previous column's slot has been read by every thread
+        if (tid == 0) redm[slot == 0 ? 2 : slot - 1] = 0ull;
+        const int p = (int)(0xffffffffu - (unsigned)redm[slot]);
+        slot = slot == 2 ? 0 : slot + 1;
+        const int wq = ((p - c0) & (kPanelThreads - 1)) >> 6;  // the wave that owns logical row p
         const cx<P>* prow = wrow[par][wq];  // pivot row (LDS, read where used)
         // ---- exchange logical rows c and p (registers only)
         if (p != c) {  // uniform
