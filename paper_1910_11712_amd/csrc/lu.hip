@@ -1468,11 +1468,14 @@ static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int 
   return hipSuccess;
 }
 
-// Look-ahead schedule.  After the part of step k's update that holds the
-// next panel, the rest of step k's update forks to the auxiliary stream and
-// the next panel runs on st right away (the panels and the first tile
-// columns form the factorization's critical path, so they stay on one
-// stream); st joins the auxiliary stream before step k+1's update.
+// Look-ahead schedule.  Once panel k is done, the rest of step k's update
+// (the tile columns after the first, which hold the next panel) forks to the
+// auxiliary stream, while st updates the first tile columns and runs the next
+// panel (the panels and the first tile columns form the factorization's
+// critical path, so they stay on one stream).  The two parts touch disjoint
+// columns and only read panel k's factors, so the auxiliary stream's updates
+// of consecutive steps follow each other without waiting for st.  st joins
+// the auxiliary stream before step k+1's update.
 // Row maps alternate between two buffers: step k's kernels use map k, and
 // panel k+1 reads map k and writes map k+1 into the other buffer, so the rest
 // of step k's update keeps addressing its rows through map k while the next
@@ -1507,8 +1510,6 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
   for (int k = 0; k < nsteps; ++k) {
     const auto& s = plan.steps[k];
     const bool has_next = k + 1 < nsteps;
-    if ((e = lu_update_part<P>(plan, s, 0, d_md, d_prefix, T, map(k), map(k), skip, linv(k), arrivals, st)) != hipSuccess)
-      return e;
     const bool overlap = lookahead && has_next && (s.tot_gemm[1] > 0 || s.tot_trsm[1] > 0);
     if (overlap) {
       if ((e = hipEventRecord(ev_fork, st)) != hipSuccess) return e;
@@ -1517,10 +1518,12 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
         return e;
       if ((e = hipEventRecord(ev_join, aux)) != hipSuccess) return e;
       joined = false;
-    } else if ((e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, map(k), map(k), skip, linv(k), arrivals, st)) !=
-               hipSuccess) {
-      return e;
     }
+    if ((e = lu_update_part<P>(plan, s, 0, d_md, d_prefix, T, map(k), map(k), skip, linv(k), arrivals, st)) != hipSuccess)
+      return e;
+    if (!overlap &&
+        (e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, map(k), map(k), skip, linv(k), arrivals, st)) != hipSuccess)
+      return e;
     if (has_next && (e = lu_panel_step<P>(plan, plan.steps[k + 1], d_md, T, map(k), map(k + 1), info, skip,
                                           linv(k + 1), Dinv, dinv_off, st, side, ls.ev_side[(k + 1) & 1])) !=
                         hipSuccess)
