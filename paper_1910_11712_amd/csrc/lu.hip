@@ -1468,14 +1468,16 @@ static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int 
   return hipSuccess;
 }
 
-// Look-ahead schedule.  Once panel k is done, the rest of step k's update
-// (the tile columns after the first, which hold the next panel) forks to the
-// auxiliary stream, while st updates the first tile columns and runs the next
-// panel (the panels and the first tile columns form the factorization's
-// critical path, so they stay on one stream).  The two parts touch disjoint
-// columns and only read panel k's factors, so the auxiliary stream's updates
-// of consecutive steps follow each other without waiting for st.  st joins
-// the auxiliary stream before step k+1's update.
+// Look-ahead schedule.  The rest of step k's update (the tile columns after
+// the first, which hold the next panel) forks to the auxiliary stream while
+// st updates the first tile columns and runs the next panel (the panels and
+// the first tile columns form the factorization's critical path, so they stay
+// on one stream); st joins the auxiliary stream before step k+1's update.
+// The two parts touch disjoint columns and only read panel k's factors.  In
+// complex FP32 the fork comes as soon as panel k is done, so the auxiliary
+// stream's updates of consecutive steps follow each other without waiting for
+// st; in complex FP64 it comes after the first columns' update, whose two
+// kernels were slowed more by the overlap than the auxiliary stream gained.
 // Row maps alternate between two buffers: step k's kernels use map k, and
 // panel k+1 reads map k and writes map k+1 into the other buffer, so the rest
 // of step k's update keeps addressing its rows through map k while the next
@@ -1511,16 +1513,21 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
     const auto& s = plan.steps[k];
     const bool has_next = k + 1 < nsteps;
     const bool overlap = lookahead && has_next && (s.tot_gemm[1] > 0 || s.tot_trsm[1] > 0);
-    if (overlap) {
-      if ((e = hipEventRecord(ev_fork, st)) != hipSuccess) return e;
-      if ((e = hipStreamWaitEvent(aux, ev_fork, 0)) != hipSuccess) return e;
-      if ((e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, map(k), map(k), skip, linv(k), arrivals, aux)) != hipSuccess)
-        return e;
-      if ((e = hipEventRecord(ev_join, aux)) != hipSuccess) return e;
+    constexpr bool early = sizeof(P) == 4;  // fork before the first columns' update
+    auto fork = [&]() -> hipError_t {
+      hipError_t r;
+      if ((r = hipEventRecord(ev_fork, st)) != hipSuccess) return r;
+      if ((r = hipStreamWaitEvent(aux, ev_fork, 0)) != hipSuccess) return r;
+      if ((r = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, map(k), map(k), skip, linv(k), arrivals, aux)) !=
+          hipSuccess)
+        return r;
       joined = false;
-    }
+      return hipEventRecord(ev_join, aux);
+    };
+    if (overlap && early && (e = fork()) != hipSuccess) return e;
     if ((e = lu_update_part<P>(plan, s, 0, d_md, d_prefix, T, map(k), map(k), skip, linv(k), arrivals, st)) != hipSuccess)
       return e;
+    if (overlap && !early && (e = fork()) != hipSuccess) return e;
     if (!overlap &&
         (e = lu_update_part<P>(plan, s, 1, d_md, d_prefix, T, map(k), map(k), skip, linv(k), arrivals, st)) != hipSuccess)
       return e;
