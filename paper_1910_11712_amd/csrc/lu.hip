@@ -772,6 +772,10 @@ __global__ __launch_bounds__(64 * NW) void k_lu_gemm_c64(const MatDesc* __restri
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * (kG32TM / WR), wcn = (wave & 1) * 64;
+  // a wave whose rows or columns lie wholly outside the matrix (edge tiles of
+  // the shrinking trailing block, the lower half of the U12 tiles) stages its
+  // share of the operands but issues no products (uniform per wave)
+  const bool wlive = row0 + wr < row_end && col0 + wcn < n;
   if (tid < kG32TM) {
     const int gr = row0 + tid;
     aoff_s[tid] = gr < row_end ? (MODE == 0 ? rata[gr] * ld : (gr - k0) * kLuMaxJB) : -1;
@@ -831,7 +835,7 @@ __global__ __launch_bounds__(64 * NW) void k_lu_gemm_c64(const MatDesc* __restri
   // (component r%2), and complex column l%32.  MODE 0 starts from C and
   // accumulates -L21 U12, so the epilogue only stores; MODE 1 starts from 0.
   floatx16 acc[MI][2];
-  if (MODE == 0) {
+  if (MODE == 0 && wlive) {
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -870,6 +874,7 @@ __global__ __launch_bounds__(64 * NW) void k_lu_gemm_c64(const MatDesc* __restri
   for (int kc = 0; kc < nk; ++kc) {
     const int buf = kc & 1;
     if (kc + 1 < nk) load_tile((kc + 1) * kG32KC);
+    if (wlive) {
     // operands of step k+1 are read while the products of step k issue
     float af[2][MI], bf[2][2];
     auto frag = [&](int k, float (&a)[MI], float (&bb)[2]) {
@@ -896,11 +901,13 @@ __global__ __launch_bounds__(64 * NW) void k_lu_gemm_c64(const MatDesc* __restri
       }
       __builtin_amdgcn_sched_group_barrier(0x008, 2 * MI, 0);    // MFMA
     }
+    }
     if (kc + 1 < nk) {
       store_tile(buf ^ 1);
       __syncthreads();
     }
   }
+  if (!wlive) return;
 
   // epilogue: store the block (C - L21 U12 in MODE 0, U12 in MODE 1)
 #pragma unroll
@@ -1162,6 +1169,8 @@ __global__ __launch_bounds__(64 * NW) void k_lu_gemm_c128(const MatDesc* __restr
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * (kG64TM / WR), wcn = (wave & 1) * 32;
+  // waves wholly outside the matrix stage operands but issue no products
+  const bool wlive = row0 + wr < row_end && col0 + wcn < n;
   if (tid < kG64TM) {
     const int gr = row0 + tid;
     aoff_s[tid] = gr < row_end ? (MODE == 0 ? rata[gr] * ld : (gr - k0) * kLuMaxJB) : -1;
@@ -1212,7 +1221,7 @@ __global__ __launch_bounds__(64 * NW) void k_lu_gemm_c128(const MatDesc* __restr
   // -L21 U12; MODE 1 starts from 0.
   const int tcomp = (lane >> 4) & 1, rbase = (lane >> 4) >> 1;
   doublex4 acc[MI][2];
-  if (MODE == 0) {
+  if (MODE == 0 && wlive) {
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -1250,6 +1259,7 @@ __global__ __launch_bounds__(64 * NW) void k_lu_gemm_c128(const MatDesc* __restr
   for (int kc = 0; kc < nk; ++kc) {
     const int buf = kc & 1;
     if (kc + 1 < nk) load_tile((kc + 1) * kG64KC);
+    if (wlive) {
 #pragma unroll
     for (int k2 = 0; k2 < kG64KC; k2 += 2) {
       double af[MI], bf[2];
@@ -1263,11 +1273,13 @@ __global__ __launch_bounds__(64 * NW) void k_lu_gemm_c128(const MatDesc* __restr
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
+    }
     if (kc + 1 < nk) {
       store_tile(buf ^ 1);
       __syncthreads();
     }
   }
+  if (!wlive) return;
   // epilogue: store-only
 #pragma unroll
   for (int i = 0; i < MI; ++i)
