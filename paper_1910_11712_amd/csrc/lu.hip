@@ -1070,11 +1070,15 @@ __global__ __launch_bounds__(64 * NW) void k_lu_part0_c64(const MatDesc* __restr
       base[(2 * kp + 1) * SC + 2 * r + 1] = aval[q] ? ra[q].w : 0.f;
     }
   };
+  // a wave whose rows all lie past the matrix stages its share of L21 but
+  // issues no products (uniform per wave; the tile's rows are consecutive)
+  const bool wlive = aoff_s[wr3] >= 0;
   floatx16 acc[MI3][2];
 #pragma unroll
   for (int i = 0; i < MI3; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
+      if (!wlive) continue;
       const int gcol = s0 + j * 32 + (lane & 31);
       const int gcl = min(gcol, ld - 1);
 #pragma unroll
@@ -1096,16 +1100,19 @@ __global__ __launch_bounds__(64 * NW) void k_lu_part0_c64(const MatDesc* __restr
     const int buf = kc & 1;
     if (kc + 1 < nk) load_chunk((kc + 1) * kP0KC);
     const float* base = Sa + (buf * kP0KC) * SC;
+    if (wlive) {
 #pragma unroll
-    for (int k = 0; k < kP0KC; ++k) {
-      float a[MI3];
+      for (int k = 0; k < kP0KC; ++k) {
+        float a[MI3];
 #pragma unroll
-      for (int i = 0; i < MI3; ++i) a[i] = -asign * base[k * SC + 2 * (wr3 + 16 * i + arow) + acomp];
+        for (int i = 0; i < MI3; ++i) a[i] = -asign * base[k * SC + 2 * (wr3 + 16 * i + arow) + acomp];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const float bb = Sb[kc * kP0KC + k][bu][j * 32 + bcol];
+        for (int j = 0; j < 2; ++j) {
+          const float bb = Sb[kc * kP0KC + k][bu][j * 32 + bcol];
 #pragma unroll
-        for (int i = 0; i < MI3; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], bb, acc[i][j], 0, 0, 0);
+          for (int i = 0; i < MI3; ++i)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], bb, acc[i][j], 0, 0, 0);
+        }
       }
     }
     if (kc + 1 < nk) {
@@ -1113,6 +1120,7 @@ __global__ __launch_bounds__(64 * NW) void k_lu_part0_c64(const MatDesc* __restr
       __syncthreads();
     }
   }
+  if (!wlive) return;
 #pragma unroll
   for (int i = 0; i < MI3; ++i)
 #pragma unroll
