@@ -13,11 +13,15 @@
 // Right-looking blocked algorithm, one step per panel of jb columns:
 //   k_lu_panel : one work-group per matrix factors the n-k0 by jb panel; leaves
 //                of W columns live in registers (one logical row per thread and
-//                slot), pivots are found by DPP wave reductions + LDS, modulus
-//                |Re|+|Im|, ties to the lowest row.  At its end the group
-//                inverts the unit lower block L11 (recursive doubling in LDS),
-//                used for U12 and, block by block, by the solves.
+//                slot), loaded and stored through LDS in whole-row pieces;
+//                pivots are found by DPP wave reductions and one LDS atomic
+//                max, modulus |Re|+|Im|, ties to the lowest row.  At its end
+//                the group inverts the unit lower block L11 (recursive
+//                doubling in LDS), used for U12 and, block by block, by the
+//                solves.
 //   k_lu_inv_u : inverses of the 64 x 64 diagonal blocks of U11 (FP64).
+//   k_lu_part0_c64: U12 and the update of the first 64 trailing columns (the
+//                next panel's) in one launch, complex FP32.
 //   k_lu_gemm<1>: U12 = L11^{-1} A12 on the matrix cores (block-row solve).
 //   k_lu_gemm<0>: A22 -= L21 U12 on the matrix cores.  Complex products use the
 //                real 2x2 embedding [ar -ai; ai ar] built in the operand
