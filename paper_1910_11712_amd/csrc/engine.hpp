@@ -98,7 +98,7 @@ hipError_t launch_assemble(const ProbDesc* pd, const int* prefix, const Table& t
                            cx<P>* T, const int* skip, hipStream_t st);
 hipError_t launch_moments(const ProbDesc* pd, const int* prefix, const Table& t, const NodeArrays& na,
                           const c128* Y, hipStream_t st);
-hipError_t launch_vnorm(const ProbDesc* pd, int nprob, IrState ir, hipStream_t st);
+hipError_t launch_vnorm(const ProbDesc* pd, int nprob, int L, IrState ir, hipStream_t st);  // L: columns (max over problems)
 
 template <typename P>
 hipError_t solve_run(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md, const NodeArrays& na,

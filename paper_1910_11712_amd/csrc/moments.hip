@@ -183,27 +183,25 @@ hipError_t launch_moments(const ProbDesc* pd, const int* prefix, const Table& t,
 }
 
 // ---------------------------------------------------------------------------
-// max |V| per probe column (one block per problem)
+// max |V| per probe column: one block per (problem, column), a wave max by
+// shuffles, then the four waves through LDS
 // ---------------------------------------------------------------------------
-__global__ void k_vnorm(const ProbDesc* __restrict__ pd, IrState ir) {
+__global__ __launch_bounds__(256) void k_vnorm(const ProbDesc* __restrict__ pd, IrState ir) {
   const ProbDesc& D = pd[blockIdx.x];
-  __shared__ double red[256];
-  for (int c = 0; c < D.L; ++c) {
-    double m = 0.0;
-    for (int r = threadIdx.x; r < D.n; r += blockDim.x) m = fmax(m, sqrt(norm2(D.V[(long long)c * D.n + r])));
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) ir.vnorm[blockIdx.x * 64 + c] = red[0];
-    __syncthreads();
-  }
+  const int c = blockIdx.y;
+  if (c >= D.L) return;  // uniform
+  const c128* __restrict__ v = D.V + (long long)c * D.n;
+  double m = 0.0;
+  for (int r = threadIdx.x; r < D.n; r += blockDim.x) m = fmax(m, sqrt(norm2(v[r])));
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) ir.vnorm[blockIdx.x * 64 + c] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
-hipError_t launch_vnorm(const ProbDesc* pd, int nprob, IrState ir, hipStream_t st) {
-  hipLaunchKernelGGL(k_vnorm, dim3(nprob), dim3(256), 0, st, pd, ir);
+hipError_t launch_vnorm(const ProbDesc* pd, int nprob, int L, IrState ir, hipStream_t st) {
+  hipLaunchKernelGGL(k_vnorm, dim3(nprob, L), dim3(256), 0, st, pd, ir);
   return hipGetLastError();
 }
 

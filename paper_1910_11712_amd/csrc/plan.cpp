@@ -382,7 +382,7 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
   int* rows = drows_.as<int>();
   int* info = dinfo_.as<int>();
   NEP_HIP(ir_reset(ir_, nnodes, st));
-  NEP_HIP(launch_vnorm(pd, nprob, ir_, st));
+  NEP_HIP(launch_vnorm(pd, nprob, opt.L, ir_, st));
   NEP_HIP(launch_coef(pd, na_, nnodes, ir_, st));
   NEP_HIP(launch_assemble<P>(pd, pre, pt_.assemble, na_, T, nullptr, st));
   cx<P>* Dinv = ddinv_.as<cx<P>>();
