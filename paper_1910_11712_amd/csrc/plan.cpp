@@ -382,9 +382,11 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
   int* rows = drows_.as<int>();
   int* info = dinfo_.as<int>();
   NEP_HIP(ir_reset(ir_, nnodes, st));
-  NEP_HIP(launch_vnorm(pd, nprob, opt.L, ir_, st));
   NEP_HIP(launch_coef(pd, na_, nnodes, ir_, st));
   NEP_HIP(launch_assemble<P>(pd, pre, pt_.assemble, na_, T, nullptr, st));
+  // the probe norms are first read by the refinement test; queued behind the
+  // assembly they start without a launch gap
+  NEP_HIP(launch_vnorm(pd, nprob, opt.L, ir_, st));
   cx<P>* Dinv = ddinv_.as<cx<P>>();
   const long long* doff = ddinv_off_.as<long long>();
   NEP_HIP(lu_run<P>(lu_, md, dlu_prefix_.as<int>(), T, rows, drows_snap_.as<int>(), rows_total_, info, nullptr,
