@@ -1,6 +1,6 @@
 """Benchmark of the contour-integral moment path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg1|cfg2|cfg0]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg1|cfg2|cfg0|cfg3]
 
 A step is one pass of the moment stage over the workload's problem: f_i at
 the nodes, assembly of T(z_j) for every node, batched complex LU, solves with
@@ -239,6 +239,9 @@ def main():
     import paper_1910_11712_amd as P
     P.binding.lib()
 
+    if args.workload == "cfg3":  # the 256-problem batch alone (graph replay), one JSON line
+        print(json.dumps({"workload": "cfg3_batch_graph", **_batch_run(P, steps=args.steps)}))
+        return
     cfg = _workload(args.workload)
     prob = cfg["problem"]
     op = P.SplitOperator.from_problem(prob)
