@@ -356,7 +356,16 @@ static void launch_trsv(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* 
                         const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off, const c128* R,
                         c128* Y, int rf, const int* conv, IrState ir, hipStream_t st) {
   const int nb = sp.nbig, nm = sp.nmid, ns = sp.nmat - sp.nbig - sp.nmid;
-  switch (sp.rpt) {
+  // many large matrices (several rounds of groups): 256-thread groups with
+  // twice the rows each, two per CU, so one group's barrier waits are
+  // covered by the other's work
+  // (complex FP32 with at most 8 columns per group: two such groups fit a CU's registers)
+  constexpr bool kPaired = sizeof(P) == 4 && LG <= 8;
+  if (kPaired && sp.rpt <= 2 && (long long)nb * sp.groups >= 2048) {
+    if constexpr (kPaired)
+      launch_trsv_class<P, LG, 4, kTrsvThreadsSmall>(sp, 0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir,
+                                                     st);
+  } else switch (sp.rpt) {
     case 1:
     case 2: launch_trsv_class<P, LG, 2, kTrsvThreads>(sp, 0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
     case 4: launch_trsv_class<P, LG, 4, kTrsvThreads>(sp, 0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
