@@ -40,6 +40,8 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPanelThreads = 512;
+constexpr int kPanelSmall = 256;      // threads of the panel groups of at most 256 rows
+constexpr int kSmallPanelsMin = 512;  // small panels in a step before they take the smaller groups
 constexpr int kMaxPanelRows = 4096;  // n - k0 held by one panel group
 
 // ---------------------------------------------------------------------------
@@ -254,20 +256,20 @@ __device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
 }
 
 // Leaf rows between the row-major factor and the LDS block S (one chunk of
-// kPanelThreads logical rows from rbase).  A row's W-column segment is 128
+// NT logical rows from rbase, NT the panel group's threads).  A row's W-column segment is 128
 // bytes (64 for the 8-rows-per-thread leaves) split into 16-byte pieces, one
 // per lane, so every load or store instruction of a wave covers whole rows
 // instead of one row per lane.  The segment start is 16-byte aligned (the
 // leading dimension is a multiple of 16 elements and c0 a multiple of W), and
 // a whole segment lies inside the padded row, so loads need no column bound;
 // stores stop at column c0 + wc.
-template <typename P, int W>
+template <typename P, int W, int NT = kPanelThreads>
 __device__ __forceinline__ void leaf_to_lds(const cx<P>* __restrict__ T, const int* rat, int ld, int k0, int c0,
-                                            int rbase, int nrow, cx<P> (&S)[kPanelThreads][W + 1]) {
+                                            int rbase, int nrow, cx<P> (&S)[NT][W + 1]) {
   constexpr int CP = 16 / (int)sizeof(cx<P>);  // elements per piece
   constexpr int LPR = W / CP;                   // pieces per row
-  constexpr int RPP = kPanelThreads / LPR;      // rows per pass
-  static_assert(W % CP == 0 && kPanelThreads % LPR == 0, "whole pieces per row");
+  constexpr int RPP = NT / LPR;      // rows per pass
+  static_assert(W % CP == 0 && NT % LPR == 0, "whole pieces per row");
   const int q = threadIdx.x % LPR, rr = threadIdx.x / LPR;
 #pragma unroll
   for (int p = 0; p < LPR; ++p) {
@@ -286,12 +288,12 @@ __device__ __forceinline__ void leaf_to_lds(const cx<P>* __restrict__ T, const i
   }
 }
 
-template <typename P, int W>
+template <typename P, int W, int NT = kPanelThreads>
 __device__ __forceinline__ void lds_to_leaf(cx<P>* __restrict__ T, const int* rat, int ld, int k0, int c0, int rbase,
-                                            int nrow, int wc, const cx<P> (&S)[kPanelThreads][W + 1]) {
+                                            int nrow, int wc, const cx<P> (&S)[NT][W + 1]) {
   constexpr int CP = 16 / (int)sizeof(cx<P>);
   constexpr int LPR = W / CP;
-  constexpr int RPP = kPanelThreads / LPR;
+  constexpr int RPP = NT / LPR;
   const int q = threadIdx.x % LPR, rr = threadIdx.x / LPR;
 #pragma unroll
   for (int p = 0; p < LPR; ++p) {
@@ -313,17 +315,17 @@ __device__ __forceinline__ void lds_to_leaf(cx<P>* __restrict__ T, const int* ra
 }
 
 // The end of a leaf (columns c0 .. c0+wc-1, held in registers as a[i][w] for
-// logical rows c0 + tid + i*kPanelThreads): the leaf's top rows make the
+// logical rows c0 + tid + i*NT): the leaf's top rows make the
 // panel columns right of it (c0+wc .. k0+jb-1) rows of U by a unit lower
-// solve with the leaf's top block; then, one chunk of kPanelThreads rows at a
+// solve with the leaf's top block; then, one chunk of NT rows at a
 // time, the chunk's leaf rows go to LDS, from there to the factor (coalesced),
 // and, as the L operand, into the rank-wc update of the right columns.  The
 // row map must hold the leaf's physical rows before the call.
-template <typename P, int W, int RPT>
+template <typename P, int W, int RPT, int NT = kPanelThreads>
 __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const int* rat, int ld, int n, int k0,
                                                    int jb, int c0, int wc, const cx<P> (&a)[RPT][W],
                                                    cx<P> (&Ltop)[W][W], cx<P> (&Utop)[W][kLuMaxJB],
-                                                   cx<P> (&Lc)[kPanelThreads][W + 1]) {
+                                                   cx<P> (&Lc)[NT][W + 1]) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // ---- update the panel columns right of the leaf
   const int rc0 = c0 + wc;
@@ -334,7 +336,7 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
       for (int w = 0; w < W; ++w) cput(Ltop[tid][w], cget(a[0][w]));
     }
     __syncthreads();
-    static_assert(kLuMaxJB <= kPanelThreads, "one thread per right-hand column of the panel");
+    static_assert(kLuMaxJB <= NT, "one thread per right-hand column of the panel");
     if (tid < nr) {  // nr < jb <= kLuMaxJB: one column per thread
       const int j = tid;
       cx<P> x[W];
@@ -355,11 +357,11 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
     // (the chunk loop's first barrier orders Utop before its readers)
   }
   // rows >= rc0: A[r][right] -= L[r][leaf] U[leaf][right], one chunk of
-  // kPanelThreads rows at a time, the chunk's L rows in LDS
+  // NT rows at a time, the chunk's L rows in LDS
   for (int i = 0; i < RPT; ++i) {
-    const int rbase = c0 + i * kPanelThreads;
+    const int rbase = c0 + i * NT;
     if (rbase >= n) break;  // uniform
-    const int nrow = min(kPanelThreads, n - rbase);
+    const int nrow = min(NT, n - rbase);
     // this thread's row of chunk i (selects: a[][] stays in registers)
 #pragma unroll
     for (int w = 0; w < W; ++w) {
@@ -369,7 +371,7 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
       cput(Lc[tid][w], w < wc ? v : cx<P>{P(0), P(0)});
     }
     __syncthreads();
-    lds_to_leaf<P, W>(T, rat, ld, k0, c0, rbase, nrow, wc, Lc);
+    lds_to_leaf<P, W, NT>(T, rat, ld, k0, c0, rbase, nrow, wc, Lc);
     if (nr > 0) {
       if constexpr (sizeof(P) == 4) {
         // Complex FP32: on the matrix cores.  A wave takes four 16-row blocks
@@ -388,7 +390,7 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
         const int rb_lo = max(0, rc0 - rbase) / RB;
         const int rb_hi = (nrow + RB - 1) / RB;
         const int nquad = (rb_hi - rb_lo + NRB - 1) / NRB;
-        for (int unit = wave; unit < nquad * ncb; unit += kPanelThreads / 64) {
+        for (int unit = wave; unit < nquad * ncb; unit += NT / 64) {
           const int cb = unit / nquad, rb0 = rb_lo + NRB * (unit - cb * nquad);
           const int col = rc0 + CB * cb + (lane & 31);
           const bool cok = col < k0 + jb;
@@ -443,7 +445,7 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
         // many); full leaves and full row batches run branch-free
         constexpr int kLeafWords = RPT * W * (int)sizeof(cx<P>) / 4;
         constexpr int kRows = kLeafWords >= 128 ? 2 : kLeafWords > 64 ? 4 : 8;
-        for (int r0 = rlo + wave * kRows; r0 < rhi; r0 += (kPanelThreads / 64) * kRows) {
+        for (int r0 = rlo + wave * kRows; r0 < rhi; r0 += (NT / 64) * kRows) {
           const int nrw = min(kRows, rhi - r0);
           for (int j = lane; j < nr; j += 64) {
             long long off[kRows];
@@ -481,8 +483,8 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
   }
 }
 
-template <typename P, int W, int RPT>
-__global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __restrict__ md, int k0, int jbmax,
+template <typename P, int W, int RPT, int NT = kPanelThreads>
+__global__ __launch_bounds__(NT) void k_lu_panel(const MatDesc* __restrict__ md, int k0, int jbmax,
                                                            cx<P>* __restrict__ Tb, const int* __restrict__ rsrc,
                                                            int* __restrict__ rdst, int* __restrict__ info,
                                                            const int* __restrict__ skip, cx<P>* __restrict__ Linv,
@@ -499,29 +501,30 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
   const int* __restrict__ rowg = rsrc + d.offRow;
   int* __restrict__ rowo = rdst + d.offRow;
 
-  __shared__ int rat[kMaxPanelRows];
+  // the row map of the panel's rows (at most NT * RPT below 512 threads)
+  __shared__ int rat[NT < kPanelThreads ? NT * RPT : kMaxPanelRows];
   // the column's best candidate, (key << 32) | ~row, by an LDS atomic max of
   // every wave's candidate; three slots in rotation, so that a slot is
   // cleared a column after its last read and a column before its next use
   __shared__ unsigned long long redm[3];
   __shared__ cx<P> xbuf[2][W];                    // row c, for the pivot row's owner
   __shared__ int xph[2];
-  __shared__ cx<P> wrow[2][kPanelThreads / 64][W];  // per wave: its candidate row
-  __shared__ int wph[2][kPanelThreads / 64];
+  __shared__ cx<P> wrow[2][NT / 64][W];  // per wave: its candidate row
+  __shared__ int wph[2][NT / 64];
   __shared__ cx<P> Ltop[W][W];
   __shared__ cx<P> Utop[W][kLuMaxJB];
   // the right update's L rows (+1: rows in distinct banks), and afterwards
   // the panel's diagonal block for its inverse
-  constexpr int kLcBytes = kPanelThreads * (W + 1) * (int)sizeof(cx<P>);
+  constexpr int kLcBytes = NT * (W + 1) * (int)sizeof(cx<P>);
   constexpr int kXBytes = kSolveBlkLu * (kSolveBlkLu + 1) * (int)sizeof(cx<P>);
   __shared__ __align__(16) unsigned char pool[kLcBytes > kXBytes ? kLcBytes : kXBytes];
-  auto& Lc = *reinterpret_cast<cx<P>(*)[kPanelThreads][W + 1]>(pool);
+  auto& Lc = *reinterpret_cast<cx<P>(*)[NT][W + 1]>(pool);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int m = n - k0;
-  for (int r = tid; r < m; r += kPanelThreads) rat[r] = rowg[k0 + r];
-  for (int r = tid; r < k0; r += kPanelThreads) rowo[r] = rowg[r];  // rows above the panel: unchanged
+  for (int r = tid; r < m; r += NT) rat[r] = rowg[k0 + r];
+  for (int r = tid; r < k0; r += NT) rowo[r] = rowg[r];  // rows above the panel: unchanged
   if (tid < 3) redm[tid] = 0ull;
   __syncthreads();
 
@@ -532,19 +535,19 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
     // the leaf: logical rows c0 + tid + i*512 with their physical rows ph;
     // row exchanges move data and physical row together, and the row map is
     // written once at the end of the leaf
-    // (staged through LDS one chunk of kPanelThreads rows at a time so that
+    // (staged through LDS one chunk of NT rows at a time so that
     // the loads are coalesced; columns from wc on are zero)
     cx<P> a[RPT][W];
     int ph[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int rbase = c0 + i * kPanelThreads, r = rbase + tid;
+      const int rbase = c0 + i * NT, r = rbase + tid;
 #pragma unroll
       for (int w = 0; w < W; ++w) a[i][w] = cx<P>{P(0), P(0)};
       ph[i] = 0;
       if (rbase < n) {  // uniform
         if (i > 0) __syncthreads();  // the previous chunk has been read
-        leaf_to_lds<P, W>(T, rat, ld, k0, c0, rbase, min(kPanelThreads, n - rbase), Lc);
+        leaf_to_lds<P, W, NT>(T, rat, ld, k0, c0, rbase, min(NT, n - rbase), Lc);
         __syncthreads();
         if (r < n) {
           ph[i] = rat[r - k0];
@@ -564,7 +567,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
         int row = INT_MAX;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-          const int r = c0 + tid + i * kPanelThreads;
+          const int r = c0 + tid + i * NT;
           const unsigned ki = (r >= c && r < n) ? pivot_key(abs1(cget(a[i][w]))) : 0u;
           const bool take = ki > key;  // rows ascend with i: ties keep the lower
           key = take ? ki : key;
@@ -577,7 +580,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
         if (lane == 0) atomicMax(&redm[slot], ((unsigned long long)wkey << 32) | (0xffffffffu - wr));
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-          if (wkey != 0u && c0 + tid + i * kPanelThreads == (int)wr) {
+          if (wkey != 0u && c0 + tid + i * NT == (int)wr) {
 #pragma unroll
             for (int v = 0; v < W; ++v) {  // component copies keep a[][] in registers
               wrow[par][wave][v].re = a[i][v].re;
@@ -599,7 +602,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
         if (tid == 0) redm[slot == 0 ? 2 : slot - 1] = 0ull;
         const int p = (int)(0xffffffffu - (unsigned)redm[slot]);
         slot = slot == 2 ? 0 : slot + 1;
-        const int wq = ((p - c0) & (kPanelThreads - 1)) >> 6;  // the wave that owns logical row p
+        const int wq = ((p - c0) & (NT - 1)) >> 6;  // the wave that owns logical row p
         const cx<P>* prow = wrow[par][wq];  // pivot row (LDS, read where used)
         // ---- exchange logical rows c and p (registers only)
         if (p != c) {  // uniform
@@ -613,7 +616,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
           }
 #pragma unroll
           for (int i = 0; i < RPT; ++i) {
-            if (c0 + tid + i * kPanelThreads == p) {  // the pivot row's owner takes row c
+            if (c0 + tid + i * NT == p) {  // the pivot row's owner takes row c
 #pragma unroll
               for (int v = 0; v < W; ++v) {
                 a[i][v].re = xbuf[par][v].re;
@@ -631,7 +634,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
         else inv = recip(pv);
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-          const int r = c0 + tid + i * kPanelThreads;
+          const int r = c0 + tid + i * NT;
           const bool below = r > c && r < n;
           const cx<P> l = cget(a[i][w]) * inv;
           const cx<P> lm = csel(below, l, cx<P>{P(0), P(0)});
@@ -648,14 +651,14 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
     // next barrier), then store the leaf and update the columns right of it
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int r = c0 + tid + i * kPanelThreads;
+      const int r = c0 + tid + i * NT;
       if (r < n) rat[r - k0] = ph[i];
     }
 
-    panel_right_update<P, W, RPT>(T, rat, ld, n, k0, jb, c0, wc, a, Ltop, Utop, Lc);
+    panel_right_update<P, W, RPT, NT>(T, rat, ld, n, k0, jb, c0, wc, a, Ltop, Utop, Lc);
   }
   __syncthreads();
-  for (int r = tid; r < m; r += kPanelThreads) rowo[k0 + r] = rat[r];
+  for (int r = tid; r < m; r += NT) rowo[k0 + r] = rat[r];
   if (tid == 0 && zp < n) atomicMin(&info[d.node], zp);
 
   // ---- inverse of the unit lower block L11 (recursive doubling in LDS):
@@ -665,23 +668,23 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(const MatDesc* __res
   {
     constexpr int B = kSolveBlkLu, lx = B + 1;
     cx<P>* X = reinterpret_cast<cx<P>*>(pool);
-    for (int e = tid; e < B * B; e += kPanelThreads) {
+    for (int e = tid; e < B * B; e += NT) {
       const int i = e / B, k = e - i * B;
       cx<P> v = {P(i == k ? 1 : 0), P(0)};
       if (i < jb && k < i) v = cget(T[(long long)rat[i] * ld + k0 + k]);
       cput(X[i * lx + k], v);
     }
     __syncthreads();
-    tri_inv_lds<P, false, kPanelThreads>(X, lx, B);
+    tri_inv_lds<P, false, NT>(X, lx, B);
     if (n - k0 - jb > 0) {
       cx<P>* __restrict__ Li = Linv + (long long)b * kLuMaxJB * kLuMaxJB;
-      for (int e = tid; e < jb * jb; e += kPanelThreads) {
+      for (int e = tid; e < jb * jb; e += NT) {
         const int i = e / jb, k = e - i * jb;
         cput(Li[(long long)i * kLuMaxJB + k], cget(X[i * lx + k]));
       }
     }
     cx<P>* __restrict__ out = Dinv + dinv_off[b] + ((long long)(k0 / B) * 2 + 0) * B * B;
-    for (int e = tid; e < B * B; e += kPanelThreads) cput(out[e], cget(X[(e / B) * lx + (e % B)]));
+    for (int e = tid; e < B * B; e += NT) cput(out[e], cget(X[(e / B) * lx + (e % B)]));
   }
 }
 
@@ -1314,22 +1317,25 @@ __global__ __launch_bounds__(64 * NW) void k_lu_gemm_c128(const MatDesc* __restr
 // Leaf width: complex FP32 panels of one row per thread take 16-column
 // leaves (half the passes over the panel's right part); otherwise 8 (c64) or
 // 4 (c128), which keeps the unrolled leaf in registers.
+// rpt 0: panels of at most kPanelSmall rows, one row per thread of a
+// kPanelSmall-thread group (several groups share a CU).
 template <typename P>
 static hipError_t launch_panel(int rpt, int nact, const MatDesc* md, int k0, int jb, cx<P>* T, const int* rsrc,
                                int* rdst, int* info, const int* skip, cx<P>* Linv, cx<P>* Dinv,
                                const long long* dinv_off, hipStream_t st) {
-  dim3 g(nact), blk(kPanelThreads);
+  dim3 g(nact), blk(rpt == 0 ? kPanelSmall : kPanelThreads);
   // leaf width: as wide as the registers allow (RPT rows x W complex per thread)
   constexpr bool f32 = sizeof(P) == 4;
   constexpr int W1 = f32 ? 16 : 8, W8 = f32 ? 8 : 4;
-#define NEP_PANEL(W, R)                                                                                    \
-  hipLaunchKernelGGL((k_lu_panel<P, W, R>), g, blk, 0, st, md, k0, jb, T, rsrc, rdst, info, skip, Linv, Dinv, \
+#define NEP_PANEL(W, R, NT)                                                                                    \
+  hipLaunchKernelGGL((k_lu_panel<P, W, R, NT>), g, blk, 0, st, md, k0, jb, T, rsrc, rdst, info, skip, Linv, Dinv, \
                      dinv_off)
   switch (rpt) {
-    case 1: NEP_PANEL(W1, 1); break;
-    case 2: NEP_PANEL(W1, 2); break;
-    case 4: NEP_PANEL(W1, 4); break;
-    default: NEP_PANEL(W8, 8); break;
+    case 0: NEP_PANEL(W1, 1, kPanelSmall); break;
+    case 1: NEP_PANEL(W1, 1, kPanelThreads); break;
+    case 2: NEP_PANEL(W1, 2, kPanelThreads); break;
+    case 4: NEP_PANEL(W1, 4, kPanelThreads); break;
+    default: NEP_PANEL(W8, 8, kPanelThreads); break;
   }
 #undef NEP_PANEL
   return hipGetLastError();
@@ -1354,6 +1360,8 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
     s.nact = nact;
     s.nwide = 0;
     while (s.nwide < nact && sorted[s.nwide].n - k0 > kPanelThreads) ++s.nwide;
+    s.nsmall = s.nwide;
+    while (s.nsmall < nact && sorted[s.nsmall].n - k0 > kPanelSmall) ++s.nsmall;
     int rmax = sorted[0].n - k0;
     s.rpt = rmax <= 512 ? 1 : rmax <= 1024 ? 2 : rmax <= 2048 ? 4 : 8;
     // tile prefixes of the block-row product (U12) and of the trailing
@@ -1415,9 +1423,21 @@ static hipError_t lu_panel_step(const LuPlan& plan, const LuPlan::Step& s, const
   if (s.nwide > 0 && (e = launch_panel<P>(s.rpt, s.nwide, d_md, s.k0, plan.jb, T, rsrc, rdst, info, skip, Linv, Dinv,
                                           dinv_off, st)) != hipSuccess)
     return e;
-  if (s.nwide < s.nact &&
-      (e = launch_panel<P>(1, s.nact - s.nwide, d_md + s.nwide, s.k0, plan.jb, T, rsrc, rdst, info, skip,
+  // panels of at most kPanelSmall rows take the kPanelSmall-thread groups
+  // when they are many (two groups share a CU; complex FP32 only, where two
+  // fit); the two variants give the same bits (per-row arithmetic and the
+  // inverse's per-element sums do not depend on the group size), so the
+  // choice by batch size does not change any matrix's factors
+  const bool small = sizeof(P) == 4 && s.nact - s.nsmall >= kSmallPanelsMin;
+  const int mid_end = small ? s.nsmall : s.nact;
+  if (s.nwide < mid_end &&
+      (e = launch_panel<P>(1, mid_end - s.nwide, d_md + s.nwide, s.k0, plan.jb, T, rsrc, rdst, info, skip,
                            Linv + (long long)s.nwide * kLuMaxJB * kLuMaxJB, Dinv, dinv_off + s.nwide, st)) !=
+          hipSuccess)
+    return e;
+  if (small &&
+      (e = launch_panel<P>(0, s.nact - s.nsmall, d_md + s.nsmall, s.k0, plan.jb, T, rsrc, rdst, info, skip,
+                           Linv + (long long)s.nsmall * kLuMaxJB * kLuMaxJB, Dinv, dinv_off + s.nsmall, st)) !=
           hipSuccess)
     return e;
   hipStream_t su = st;

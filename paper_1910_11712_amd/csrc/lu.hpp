@@ -19,6 +19,9 @@ struct LuPlan {
     // take the single-row panel, so the leaf width (and with it the rounding)
     // of a matrix's panel depends on that matrix alone, not on its batch
     int nwide;
+    // matrices [nsmall, nact) have at most 256 rows left: with enough of them
+    // (complex FP32), a 256-thread panel group each, two per CU
+    int nsmall;
     // tiles of the U12 product and of the trailing update; part 0 is the
     // first tile column (it holds the next panel), part 1 the rest
     int off_trsm[2], tot_trsm[2];
