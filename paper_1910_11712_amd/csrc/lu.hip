@@ -37,6 +37,7 @@
 namespace nep {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPanelThreads = 512;
@@ -381,15 +382,87 @@ __device__ __forceinline__ void panel_right_update(cx<P>* __restrict__ T, const 
         // and the blocks are stored back.  Rows of a block below rc0 or past n
         // compute discarded values.
         // four row blocks per unit; two where the leaf rows held in registers
-        // (RPT * W complex) leave too few for four blocks' accumulators
+        // (RPT * W complex) leave too few for four blocks' accumulators.
+        // A last column block of at most 16 columns (the right part is 48 or
+        // 16 columns wide after the first and third 16-column leaves) runs as
+        // 16-column units on v_mfma_f32_16x16x4f32 instead of half-empty
+        // 32-column ones, where the leaf registers leave room (panels of at
+        // most 2 * NT rows).
         constexpr int RB = 16, CB = 32, NRB = RPT * W > 32 ? 2 : 4;
-        const int ncb = (nr + CB - 1) / CB;
+        constexpr bool k16 = RPT * W <= 32;
+        static_assert(W % 2 == 0, "16-column units take the leaf's k in pairs");
+        const bool has16 = k16 && (nr & (CB - 1)) != 0 && (nr & (CB - 1)) <= 16;
+        const int ncb = has16 ? nr / CB : (nr + CB - 1) / CB;  // 32-column blocks
         const int at = lane & 1, au = lane >> 5, arow = (lane & 31) >> 1;
         const int acomp = at ^ au;
         const float asign = (at == 0 && au == 1) ? 1.f : -1.f;
         const int rb_lo = max(0, rc0 - rbase) / RB;
         const int rb_hi = (nrow + RB - 1) / RB;
         const int nquad = (rb_hi - rb_lo + NRB - 1) / NRB;
+        if (k16 && has16) {
+          // 16-column units: a 16-row block is two 8-complex-row MFMA blocks;
+          // lane l holds column l%16 of complex rows 2(l/16) and 2(l/16)+1 of
+          // a block (re, im, re, im), and feeds A row (l%16)/2, component
+          // l%2, and B/A k-slot l/16 = (complex k of the pair, component)
+          const int h0 = CB * ncb;  // first column of the block, relative to rc0
+          const int t16 = lane & 1, kq = lane >> 4, ka = kq >> 1, ku = kq & 1;
+          const int acomp16 = t16 ^ ku, arow16 = (lane & 15) >> 1;
+          const float asign16 = (t16 == 0 && ku == 1) ? 1.f : -1.f;
+          const int col = rc0 + h0 + (lane & 15);
+          const bool cok = col < k0 + jb;
+          const int cc = cok ? col : rc0;
+          const int ucol = min(h0, kLuMaxJB - 16) + (lane & 15);
+          // numbered after the 32-column units, dealt to the waves in turn
+          int u0 = (wave - nquad * ncb) % (NT / 64);
+          if (u0 < 0) u0 += NT / 64;
+          for (int unit = u0; unit < nquad; unit += NT / 64) {
+            const int rb0 = rb_lo + NRB * unit;
+            floatx4 acc[2 * NRB];
+            int roff[2 * NRB][2];
+            bool rok[2 * NRB][2];
+            int rbq[NRB];
+#pragma unroll
+            for (int q = 0; q < NRB; ++q) {
+              const bool vq = rb0 + q < rb_hi;  // uniform
+              rbq[q] = vq ? rb0 + q : rb0;
+#pragma unroll
+              for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                  const int r = rbase + RB * (rb0 + q) + 8 * h + 2 * kq + e;
+                  rok[2 * q + h][e] = vq && r >= rc0 && r < n;
+                  roff[2 * q + h][e] = rat[(rok[2 * q + h][e] ? r : rc0) - k0] * ld;
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < 2 * NRB; ++g)
+#pragma unroll
+              for (int e = 0; e < 2; ++e) {
+                const cx<P> cv = T[roff[g][e] + cc];
+                const bool ok = cok && rok[g][e];
+                acc[g][2 * e] = ok ? cv.re : 0.f;
+                acc[g][2 * e + 1] = ok ? cv.im : 0.f;
+              }
+#pragma unroll 2
+            for (int k = 0; k < W; k += 2) {
+              const cx<P> uv = Utop[k + ka][ucol];
+              const float bv = ku ? uv.im : uv.re;
+#pragma unroll
+              for (int g = 0; g < 2 * NRB; ++g) {
+                const cx<P> lv = Lc[RB * rbq[g >> 1] + 8 * (g & 1) + arow16][k + ka];
+                const float av = asign16 * (acomp16 ? lv.im : lv.re);
+                acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[g], 0, 0, 0);
+              }
+            }
+            if (cok) {
+#pragma unroll
+              for (int g = 0; g < 2 * NRB; ++g)
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+                  if (rok[g][e]) T[roff[g][e] + col] = cx<P>{acc[g][2 * e], acc[g][2 * e + 1]};
+            }
+          }
+        }
         for (int unit = wave; unit < nquad * ncb; unit += NT / 64) {
           const int cb = unit / nquad, rb0 = rb_lo + NRB * (unit - cb * nquad);
           const int col = rc0 + CB * cb + (lane & 31);
