@@ -9,6 +9,10 @@ resident in HBM before the timed region.  The eigenpair extraction of the
 config-2 workload (moments + block-Hankel SVD + eigenpairs + backward errors)
 is timed separately and reported under "extra".
 
+Launch shapes are chosen by the library's autotuner (nep_tune_set) when each
+plan is built, in the untimed warm-up; the timed steps run the chosen shapes
+and "extra" lists the candidates and their times (--no-tune: built-in shapes).
+
 Prints one JSON line.  Only one GPU is used; --gpus N > 1 exits with a message.
 """
 import argparse
@@ -137,7 +141,18 @@ def _eigs_run(P, steps=3):
     return out
 
 
-def _batch_run(P, steps=5):
+def _tune_summary(B):
+    rep = B.nep_tune_report()
+    c = rep["candidates"]
+    out = {"cached": rep["cached"],
+           "candidates_ms": [[d["lg"], d["paired"], d["small_min"], round(d["ms"], 4)] for d in c]}
+    if 0 <= rep["chosen"] < len(c):
+        d = c[rep["chosen"]]
+        out["chosen"] = {"lg": d["lg"], "paired": d["paired"], "small_min": d["small_min"]}
+    return out
+
+
+def _batch_run(P, steps=5, tune=True):
     """Config 3: 256 rational problems of uneven n (64..1024) in one plan,
     the whole launch sequence replayed from a HIP graph."""
     import torch
@@ -149,7 +164,10 @@ def _batch_run(P, steps=5):
     Ss = [torch.empty((2 * K, L, p.n), dtype=torch.complex128, device="cuda") for p in cfg["problems"]]
     B = P.binding
     o = B.opts_struct(N, L, K, "mixed")
+    B.nep_tune_set(tune, 2)  # tuned before the graph is captured
     b = B.nep_batch_create([op.h for op in ops], [con] * len(ops), o, Vs, Ss, use_graph=True)
+    B.nep_tune_set(False, 3)
+    tuned = _tune_summary(B)
     stats = B.nep_batch_run(b, len(ops))  # warm-up, synchronous
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -166,7 +184,7 @@ def _batch_run(P, steps=5):
     lu_flops = sum(N * (8.0 / 3.0) * p.n ** 3 for p in cfg["problems"])
     out = {"problems": len(ops), "n_range": [min(p.n for p in cfg["problems"]), max(p.n for p in cfg["problems"])],
            "ms_per_batch": dt * 1e3, "quadrature_solves_per_s": nsolve / dt,
-           "lu_tflops_effective": lu_flops / dt / 1e12, "graph": True,
+           "lu_tflops_effective": lu_flops / dt / 1e12, "graph": True, "tuning": tuned,
            "max_refine_sweeps": max(s["refine_sweeps"] for s in stats),
            "n_fallback": sum(s["n_fallback"] for s in stats)}
     for op in ops:
@@ -217,6 +235,7 @@ def main():
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="built-in launch shapes (no autotuning)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -240,7 +259,7 @@ def main():
     P.binding.lib()
 
     if args.workload == "cfg3":  # the 256-problem batch alone (graph replay), one JSON line
-        print(json.dumps({"workload": "cfg3_batch_graph", **_batch_run(P, steps=args.steps)}))
+        print(json.dumps({"workload": "cfg3_batch_graph", **_batch_run(P, steps=args.steps, tune=not args.no_tune)}))
         return
     cfg = _workload(args.workload)
     prob = cfg["problem"]
@@ -248,8 +267,13 @@ def main():
     Vd = P.device_probes(cfg["V"])
     S = torch.empty((2 * cfg["K"], cfg["L"], prob.n), dtype=torch.complex128, device="cuda")
 
+    # each precision's plan is built (and its launch shapes tuned) in its warm-up
+    P.binding.nep_tune_set(not args.no_tune, 3)
     t_mixed, st_mixed, prof = _time_moments(P, op, cfg, Vd, S, "mixed", args.steps, args.warmup, prof=True)
+    tune_mixed = _tune_summary(P.binding)
     t_fp64, st_fp64, prof64 = _time_moments(P, op, cfg, Vd, S, "fp64", max(2, args.steps // 2), 1, prof=True)
+    tune_fp64 = _tune_summary(P.binding)
+    P.binding.nep_tune_set(False, 3)
     N = cfg["N"]
     value = N / t_mixed
 
@@ -266,15 +290,16 @@ def main():
     extra = {
         "mixed": {"ms_per_step": t_mixed * 1e3, "refine_sweeps": st_mixed["refine_sweeps"],
                   "n_fallback": st_mixed["n_fallback"], "max_rel_residual": st_mixed["max_rel_residual"],
-                  "lu_tflops_effective": lu_flops / t_mixed / 1e12},
+                  "lu_tflops_effective": lu_flops / t_mixed / 1e12, "tuning": tune_mixed},
         "fp64": {"ms_per_step": t_fp64 * 1e3, "quadrature_solves_per_s": N / t_fp64,
                  "lu_tflops_effective": lu_flops / t_fp64 / 1e12,
-                 "gemm_tflops": (prof64[2] / (prof64[1] / 1e3) / 1e12) if prof64[1] > 0 else None},
+                 "gemm_tflops": (prof64[2] / (prof64[1] / 1e3) / 1e12) if prof64[1] > 0 else None,
+                 "tuning": tune_fp64},
         "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
     }
     if not args.no_extra:
         for key, fn in (("cfg2_end_to_end", lambda: _eigs_run(P)),
-                        ("cfg3_batch_graph", lambda: _batch_run(P)),
+                        ("cfg3_batch_graph", lambda: _batch_run(P, tune=not args.no_tune)),
                         ("cfg4_serving_mixed", lambda: _serve_run(P, "mixed")),
                         ("cfg4_serving_fp64", lambda: _serve_run(P, "fp64"))):
             try:

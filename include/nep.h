@@ -311,6 +311,43 @@ nep_status nep_server_destroy(nep_server* s);
 /* ------------------------------------------------------------------------ */
 
 /* ------------------------------------------------------------------------ */
+/* Autotuning of launch shapes                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Not an operation of the paper: batching every (problem, node) pair of the
+ * moment stage into shared launches leaves a few launch-shape choices whose
+ * best setting depends on the batch and the device, not on the arithmetic
+ * (every setting computes the same moments).  One setting: */
+typedef struct {
+  int lg;        /* right-hand columns per work-group of the triangular solves (4, 8 or 16) */
+  int paired;    /* large matrices as paired 256-thread solve groups: -1 when they make at
+                    least 2048 groups, 0 never, 1 always (complex FP32, lg <= 8, n <= 1024) */
+  int small_min; /* panels of at most 256 rows take 256-thread groups (two per CU) when at
+                    least small_min of them share an LU step (0 always; INT_MAX never) */
+  float ms;      /* median device time of one full moment pass with this setting */
+} nep_tune_cand;
+
+/* on = 1: every moments plan built afterwards (the plan of a nep_ciss_moments
+ * call whose shapes differ from the handle's last call, and nep_batch_create's,
+ * before its graph is captured) first times each candidate setting with reps
+ * full moment passes on its own buffers and the call's stream (so S is written
+ * more than once; the call then runs as usual) and keeps the fastest.  on = 0
+ * (the default): the built-in choice.  Either way a setting chosen earlier in
+ * the process for a plan with the same launch shapes (precision, N, L,
+ * sweeps, the multiset of sizes) is applied without timing.  Process-wide.
+ * Errors: NEP_ERR_ARG if reps is outside 1..64. */
+nep_status nep_tune_set(int on, int reps);
+
+/* The last plan built: *ncand candidates timed (0 when the setting came from
+ * the cache, with *cached = 1), the index of the one kept in *chosen, and the
+ * first min(max, *ncand) of them in cand (host array).  A plan with a single
+ * candidate reports it with ms = 0.  Errors: NEP_ERR_ARG on null outputs. */
+nep_status nep_tune_report(int max, nep_tune_cand* cand, int* ncand, int* chosen, int* cached);
+
+/* Forgets every cached setting. */
+nep_status nep_tune_clear(void);
+
+/* ------------------------------------------------------------------------ */
 /* Instrumentation                                                           */
 /* ------------------------------------------------------------------------ */
 

@@ -78,6 +78,13 @@ class nep_query_info(C.Structure):
                 ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
 
 
+class nep_tune_cand(C.Structure):
+    _fields_ = [("lg", C.c_int), ("paired", C.c_int), ("small_min", C.c_int), ("ms", C.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -121,6 +128,9 @@ def lib():
         L.nep_ciss_moments_batch.argtypes = [ip, C.POINTER(vp), C.POINTER(nep_contour), C.POINTER(nep_ciss_opts),
                                              C.POINTER(vp), C.POINTER(vp), C.POINTER(nep_ciss_stats)]
         L.nep_prof_enable.argtypes = [ip]
+        L.nep_tune_set.argtypes = [ip, ip]
+        L.nep_tune_report.argtypes = [ip, C.POINTER(nep_tune_cand), C.POINTER(ip), C.POINTER(ip), C.POINTER(ip)]
+        L.nep_tune_clear.argtypes = []
         L.nep_prof_read.argtypes = [ip, C.POINTER(ip), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.nep_server_create.argtypes = [C.POINTER(nep_server_opts), C.POINTER(vp)]
         L.nep_server_submit.argtypes = [vp, vp, C.POINTER(nep_contour), C.POINTER(nep_ciss_opts),
@@ -297,6 +307,23 @@ def nep_fn_eval(h, ell, z):
     check(lib().nep_fn_eval(h, m, zi.ctypes.data_as(C.POINTER(C.c_double)),
                             out.ctypes.data_as(C.POINTER(C.c_double))))
     return (out[0::2] + 1j * out[1::2]).reshape(ell, m)
+
+
+def nep_tune_set(on, reps=3):
+    check(lib().nep_tune_set(1 if on else 0, int(reps)))
+
+
+def nep_tune_report(max_cand=32):
+    """The last plan's tuning: {"candidates": [dict], "chosen": i, "cached": bool}."""
+    arr = (nep_tune_cand * max_cand)()
+    n, chosen, cached = C.c_int(), C.c_int(), C.c_int()
+    check(lib().nep_tune_report(max_cand, arr, C.byref(n), C.byref(chosen), C.byref(cached)))
+    return {"candidates": [arr[i].as_dict() for i in range(min(n.value, max_cand))],
+            "chosen": chosen.value, "cached": bool(cached.value)}
+
+
+def nep_tune_clear():
+    check(lib().nep_tune_clear())
 
 
 def nep_prof_enable(on):

@@ -217,6 +217,7 @@ nep_status Split::moments(const nep_contour* g, const nep_ciss_opts* o, const vo
       plan->opt.fallback != po.fallback) {
     plan = std::make_unique<MomentsPlan>();
     nep_status bs = plan->build(probs, po);
+    if (bs == NEP_OK) bs = tune_plan(*plan, s);
     if (bs != NEP_OK) {
       plan.reset();
       return bs;

@@ -80,7 +80,16 @@ struct SolvePlan {
   int rpt = 1;      // rows per thread of the 512-thread solve groups (n <= 512 * rpt)
   int nbig = 0;     // matrices of more than 512 rows (the first nbig in sorted order)
   int nmid = 0;     // then matrices of 257..512 rows; the rest have at most 256
+  // the large matrices as paired 256-thread groups (complex FP32, lg <= 8,
+  // rpt <= 2): -1 when they make 2048 groups or more, 0 never, 1 always
+  int paired = -1;
 };
+
+// Column-group widths the solve is built for (4, 8, 16) that fit the plan:
+// fewer than 2L columns (a wider group would be more than half empty) and
+// within the register budget of the accumulators.
+bool solve_lg_fits(const SolvePlan& sp, int lg, int L, int prec);
+void solve_set_lg(SolvePlan& sp, int lg, int L);
 
 struct ProblemTables {
   Table assemble;  // element tiles per problem

@@ -41,8 +41,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPanelThreads = 512;
-constexpr int kPanelSmall = 256;      // threads of the panel groups of at most 256 rows
-constexpr int kSmallPanelsMin = 512;  // small panels in a step before they take the smaller groups
+constexpr int kPanelSmall = 256;  // threads of the panel groups of at most 256 rows
 constexpr int kMaxPanelRows = 4096;  // n - k0 held by one panel group
 
 // ---------------------------------------------------------------------------
@@ -1501,7 +1500,7 @@ static hipError_t lu_panel_step(const LuPlan& plan, const LuPlan::Step& s, const
   // fit); the two variants give the same bits (per-row arithmetic and the
   // inverse's per-element sums do not depend on the group size), so the
   // choice by batch size does not change any matrix's factors
-  const bool small = sizeof(P) == 4 && s.nact - s.nsmall >= kSmallPanelsMin;
+  const bool small = sizeof(P) == 4 && s.nact > s.nsmall && s.nact - s.nsmall >= plan.small_min;
   const int mid_end = small ? s.nsmall : s.nact;
   if (s.nwide < mid_end &&
       (e = launch_panel<P>(1, mid_end - s.nwide, d_md + s.nwide, s.k0, plan.jb, T, rsrc, rdst, info, skip,

@@ -10,6 +10,9 @@ namespace nep {
 constexpr int kLuMaxJB = 128;
 constexpr int kSolveBlkLu = 64;  // diagonal-block size of the stored inverses (the solve's block)
 constexpr int kPart0Cols = 64;   // trailing columns updated first in each step (the next panel)
+// small panels (at most 256 rows left) in a step before they take the
+// 256-thread groups, by default
+constexpr int kSmallPanelsMin = 512;
 
 // Launch plan of a (possibly ragged) batch: matrices sorted by n, descending.
 struct LuPlan {
@@ -28,6 +31,10 @@ struct LuPlan {
     int off_gemm[2], tot_gemm[2];
   };
   int jb = 128, prec = NEP_PREC_C32_IR64, nmat = 0, nmax = 0;
+  // complex FP32: a step's small panels take the 256-thread groups when at
+  // least small_min of them share the step (0: always; INT_MAX: never);
+  // either group size gives the same bits, so this is a pure launch-shape knob
+  int small_min = kSmallPanelsMin;
   std::vector<Step> steps;
   std::vector<int> prefix;  // uploaded once; offsets above index into it
   std::vector<int> nvec;    // sizes of the sorted matrices

@@ -5,6 +5,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "engine.hpp"
@@ -129,6 +130,23 @@ class MomentsPlan {
   // Rebinds caller buffers (V, S) and contours without rebuilding.
   nep_status rebind(const std::vector<PlanProblem>& probs);
   bool matches(const std::vector<PlanProblem>& probs, const PlanOptions& o) const;
+
+  // Launch-shape knobs of the plan (see LuPlan::small_min, SolvePlan::lg and
+  // SolvePlan::paired); every setting computes the same moments.
+  struct Knobs {
+    int lg, paired, small_min;
+  };
+  Knobs knobs() const { return Knobs{sp_.lg, sp_.paired, lu_.small_min}; }
+  void apply(const Knobs& k);
+  // The candidate settings that differ for this plan's shapes: [0] is the
+  // built-in choice; LU candidates first, then the solve's.
+  void candidates(std::vector<Knobs>& lu, std::vector<Knobs>& solve) const;
+  // Identifies plans whose launches have the same shapes: precision, N, L,
+  // sweeps and the multiset of matrix sizes.
+  std::string signature() const;
+  // Time one full moment pass (fixed sweeps, no host read-back) per rep on st
+  // and return the median in ms (after one untimed pass).
+  nep_status time_pass(hipStream_t st, int reps, float& ms);
   size_t device_bytes() const { return total_bytes_; }
   static size_t estimate_bytes(int n, int N, int L, int prec);
 
@@ -172,5 +190,10 @@ class MomentsPlan {
 };
 
 nep_status configure_kernels();
+
+// Applies the cached launch-shape setting for the plan's signature, or, with
+// tuning on and none cached, times the candidates on st and keeps the fastest
+// (tune.cpp).
+nep_status tune_plan(MomentsPlan& plan, hipStream_t st);
 
 }  // namespace nep

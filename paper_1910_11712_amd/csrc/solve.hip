@@ -361,7 +361,7 @@ static void launch_trsv(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* 
   // covered by the other's work
   // (complex FP32 with at most 8 columns per group: two such groups fit a CU's registers)
   constexpr bool kPaired = sizeof(P) == 4 && LG <= 8;
-  if (kPaired && sp.rpt <= 2 && (long long)nb * sp.groups >= 2048) {
+  if (kPaired && sp.rpt <= 2 && nb > 0 && (sp.paired == 1 || (sp.paired < 0 && (long long)nb * sp.groups >= 2048))) {
     if constexpr (kPaired)
       launch_trsv_class<P, LG, 4, kTrsvThreadsSmall>(sp, 0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir,
                                                      st);
@@ -420,11 +420,9 @@ void SolvePlan_build(SolvePlan& sp, std::vector<int>& /*buf*/, const std::vector
     else if (m.n > kTrsvThreadsSmall) ++sp.nmid;
   }
   sp.lg = pick_lg(sp.nmat, L);
-  // accumulators live in registers: at most 32 complex FP32 (8 complex FP64)
-  // values per thread
-  const int cap = prec == NEP_PREC_FP64 ? 8 : 32;
-  while (sp.lg > 4 && sp.rpt * sp.lg > cap) sp.lg >>= 1;
+  while (sp.lg > 4 && !solve_lg_fits(sp, sp.lg, L, prec)) sp.lg >>= 1;
   sp.groups = ceil_div(L, sp.lg);
+  sp.paired = -1;
   dinv_off.clear();
   long long off = 0;
   for (const auto& m : sorted) {
@@ -433,6 +431,20 @@ void SolvePlan_build(SolvePlan& sp, std::vector<int>& /*buf*/, const std::vector
     off += (long long)nb * 2 * kSolveBlk * kSolveBlk;
   }
   dinv_elems = off;
+}
+
+bool solve_lg_fits(const SolvePlan& sp, int lg, int L, int prec) {
+  if (lg != 4 && lg != 8 && lg != 16) return false;
+  if (lg == 4) return true;  // the narrowest group always fits
+  // accumulators live in registers: at most 32 complex FP32 (8 complex FP64)
+  // values per thread
+  const int cap = prec == NEP_PREC_FP64 ? 8 : 32;
+  return lg < 2 * L && sp.rpt * lg <= cap;
+}
+
+void solve_set_lg(SolvePlan& sp, int lg, int L) {
+  sp.lg = lg;
+  sp.groups = ceil_div(L, lg);
 }
 
 hipError_t solve_configure() { return hipSuccess; }

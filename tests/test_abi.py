@@ -51,6 +51,23 @@ def test_last_error_after_bad_argument():
     assert L.nep_server_destroy(None) == B.NEP_ERR_ARG
 
 
+def test_tune_host_calls():
+    """The tuner's switches and report are host-only: argument checks, and an
+    empty report after the cache is cleared (no device work)."""
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("libnep.so not built")
+    L = B.lib()
+    assert L.nep_tune_set(1, 0) == B.NEP_ERR_ARG
+    assert L.nep_tune_set(1, 65) == B.NEP_ERR_ARG
+    n, ch, ca = C.c_int(), C.c_int(), C.c_int()
+    assert L.nep_tune_report(4, None, C.byref(n), C.byref(ch), C.byref(ca)) == B.NEP_ERR_ARG
+    assert L.nep_tune_report(0, None, None, C.byref(ch), C.byref(ca)) == B.NEP_ERR_ARG
+    B.nep_tune_set(True, 2)
+    B.nep_tune_set(False, 3)
+    B.nep_tune_clear()
+    assert B.nep_tune_report() == {"candidates": [], "chosen": -1, "cached": False}
+
+
 _LAYOUT_C = r"""
 #include <stddef.h>
 #include <stdio.h>
@@ -75,6 +92,8 @@ int main(void) {
   P(nep_server_opts, max_inflight) P(nep_server_opts, nstreams)
   printf("nep_query_info %zu\n", sizeof(nep_query_info));
   P(nep_query_info, n_inside) P(nep_query_info, t_submit) P(nep_query_info, t_done)
+  printf("nep_tune_cand %zu\n", sizeof(nep_tune_cand));
+  P(nep_tune_cand, paired) P(nep_tune_cand, small_min) P(nep_tune_cand, ms)
   return 0;
 }
 """
@@ -93,7 +112,7 @@ def test_ctypes_layouts_match_header(tmp_path):
     structs = {"nep_fn": B.nep_fn, "nep_mat": B.nep_mat, "nep_contour": B.nep_contour,
                "nep_ciss_opts": B.nep_ciss_opts, "nep_ciss_stats": B.nep_ciss_stats,
                "nep_extract_opts": B.nep_extract_opts, "nep_server_opts": B.nep_server_opts,
-               "nep_query_info": B.nep_query_info}
+               "nep_query_info": B.nep_query_info, "nep_tune_cand": B.nep_tune_cand}
     for key, val in ref.items():
         if "." in key:
             sname, field = key.split(".")

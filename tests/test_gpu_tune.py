@@ -1,0 +1,103 @@
+"""The launch-shape autotuner on the device: a tuned plan times its candidate
+settings, keeps one, caches it per plan signature, and still computes the
+oracle's moments (tolerances as in the parity tests: relative Frobenius error
+of every S_p at most 1e-10)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def nep():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1910_11712_amd as P
+    P.binding.lib()
+    return P
+
+
+@pytest.fixture
+def tuning(nep):
+    """Tuning on with an empty cache; off and empty again afterwards (the
+    switch and the cache are process-wide)."""
+    B = nep.binding
+    B.nep_tune_clear()
+    B.nep_tune_set(True, 2)
+    try:
+        yield B
+    finally:
+        B.nep_tune_set(False, 3)
+        B.nep_tune_clear()
+
+
+def _rel_fro(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _check_moments(Sg, So, tol=1e-10):
+    for p in range(So.shape[0]):
+        assert _rel_fro(Sg[p], So[p]) <= tol, (p, _rel_fro(Sg[p], So[p]))
+
+
+def _check_report(rep):
+    cands = rep["candidates"]
+    assert not rep["cached"] and len(cands) >= 2, rep
+    assert 0 <= rep["chosen"] < len(cands), rep
+    assert all(c["ms"] > 0.0 and c["lg"] in (4, 8, 16) for c in cands), rep
+    best = min(range(len(cands)), key=lambda i: cands[i]["ms"])
+    assert cands[rep["chosen"]]["ms"] == cands[best]["ms"], rep
+
+
+def test_tuned_call_matches_oracle_and_is_cached(nep, tuning):
+    B = tuning
+    cfg = wl.config0()
+    p, con, N, L, K = cfg["problem"], cfg["contour"], cfg["N"], cfg["L"], cfg["K"]
+    So = oracle.ciss_moments(p, con, N, K, cfg["V"])
+    op = nep.SplitOperator.from_problem(p)
+    S, st = op.moments(con, nep.device_probes(cfg["V"]), N, L, K, prec="mixed")
+    rep = B.nep_tune_report()
+    print(rep, st)
+    _check_report(rep)
+    _check_moments(nep.moments_to_numpy(S), So)
+    assert st["n_unconverged"] == 0
+    # same launch shapes, tuning off: the cached setting, no timing
+    B.nep_tune_set(False, 3)
+    op2 = nep.SplitOperator.from_problem(p)
+    S2, st2 = op2.moments(con, nep.device_probes(cfg["V"]), N, L, K, prec="mixed")
+    rep2 = B.nep_tune_report()
+    assert rep2["cached"] and rep2["candidates"] == [], rep2
+    _check_moments(nep.moments_to_numpy(S2), So)
+
+
+def test_tuned_batch_graph_matches_oracle(nep, tuning):
+    """A ragged batch tuned before its graph is captured: sizes across 512 rows
+    (so the paired solve groups are a candidate) and panels of at most 256
+    rows (so the small panel groups are one)."""
+    B = tuning
+    cfg = wl.config3(nprob=5, nmin=200, nmax=700)
+    con, N, L, K = cfg["contour"], cfg["N"], cfg["L"], cfg["K"]
+    probs = cfg["problems"]
+    ops = [nep.SplitOperator.from_problem(p) for p in probs]
+    Vs = [nep.device_probes(V) for V in cfg["V"]]
+    Ss = [torch.zeros((2 * K, L, p.n), dtype=torch.complex128, device="cuda") for p in probs]
+    b = B.nep_batch_create([op.h for op in ops], [con] * len(ops), B.opts_struct(N, L, K, "mixed"), Vs, Ss,
+                           use_graph=True)
+    rep = B.nep_tune_report()
+    print([p.n for p in probs], rep)
+    _check_report(rep)
+    for s in Ss:
+        s.zero_()
+    torch.cuda.synchronize()
+    stats = B.nep_batch_run(b, len(ops))
+    B.nep_batch_destroy(b)
+    assert all(s["n_unconverged"] == 0 for s in stats)
+    ns = np.array([p.n for p in probs])
+    for k in sorted({int(np.argmin(ns)), int(np.argmax(ns))}):
+        So = oracle.ciss_moments(probs[k], con, N, K, cfg["V"][k])
+        _check_moments(nep.moments_to_numpy(Ss[k]), So)
