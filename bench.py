@@ -145,10 +145,11 @@ def _tune_summary(B):
     rep = B.nep_tune_report()
     c = rep["candidates"]
     out = {"cached": rep["cached"],
-           "candidates_ms": [[d["lg"], d["paired"], d["small_min"], round(d["ms"], 4)] for d in c]}
+           "candidates_ms": [[d["lg"], d["paired"], d["small_min"], d["early_fork"], round(d["ms"], 4)] for d in c]}
     if 0 <= rep["chosen"] < len(c):
         d = c[rep["chosen"]]
-        out["chosen"] = {"lg": d["lg"], "paired": d["paired"], "small_min": d["small_min"]}
+        out["chosen"] = {"lg": d["lg"], "paired": d["paired"], "small_min": d["small_min"],
+                         "early_fork": d["early_fork"]}
     return out
 
 

@@ -324,6 +324,9 @@ typedef struct {
                     least 2048 groups, 0 never, 1 always (complex FP32, lg <= 8, n <= 1024) */
   int small_min; /* panels of at most 256 rows take 256-thread groups (two per CU) when at
                     least small_min of them share an LU step (0 always; INT_MAX never) */
+  int early_fork; /* the rest of an LU step's update starts on a second stream as soon as the
+                     panel is done (1) or after the next panel's columns are updated (0);
+                     -1: by precision (1 complex FP32, 0 complex FP64) */
   float ms;      /* median device time of one full moment pass with this setting */
 } nep_tune_cand;
 

@@ -1629,7 +1629,7 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
     const auto& s = plan.steps[k];
     const bool has_next = k + 1 < nsteps;
     const bool overlap = lookahead && has_next && (s.tot_gemm[1] > 0 || s.tot_trsm[1] > 0);
-    constexpr bool early = sizeof(P) == 4;  // fork before the first columns' update
+    const bool early = plan.early_fork >= 0 ? plan.early_fork != 0 : sizeof(P) == 4;  // fork before the first columns' update
     auto fork = [&]() -> hipError_t {
       hipError_t r;
       if ((r = hipEventRecord(ev_fork, st)) != hipSuccess) return r;

@@ -35,6 +35,10 @@ struct LuPlan {
   // least small_min of them share the step (0: always; INT_MAX: never);
   // either group size gives the same bits, so this is a pure launch-shape knob
   int small_min = kSmallPanelsMin;
+  // look-ahead fork point of the rest of a step's update: 1 as soon as the
+  // panel is done, 0 after the first columns' update, -1 by precision (1 in
+  // complex FP32, 0 in complex FP64); a pure scheduling knob
+  int early_fork = -1;
   std::vector<Step> steps;
   std::vector<int> prefix;  // uploaded once; offsets above index into it
   std::vector<int> nvec;    // sizes of the sorted matrices

@@ -131,12 +131,12 @@ class MomentsPlan {
   nep_status rebind(const std::vector<PlanProblem>& probs);
   bool matches(const std::vector<PlanProblem>& probs, const PlanOptions& o) const;
 
-  // Launch-shape knobs of the plan (see LuPlan::small_min, SolvePlan::lg and
-  // SolvePlan::paired); every setting computes the same moments.
+  // Launch-shape knobs of the plan (see LuPlan::small_min and early_fork,
+  // SolvePlan::lg and paired); every setting computes the same moments.
   struct Knobs {
-    int lg, paired, small_min;
+    int lg, paired, small_min, early_fork;
   };
-  Knobs knobs() const { return Knobs{sp_.lg, sp_.paired, lu_.small_min}; }
+  Knobs knobs() const { return Knobs{sp_.lg, sp_.paired, lu_.small_min, lu_.early_fork}; }
   void apply(const Knobs& k);
   // The candidate settings that differ for this plan's shapes: [0] is the
   // built-in choice; LU candidates first, then the solve's.

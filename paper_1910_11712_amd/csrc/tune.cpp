@@ -7,14 +7,20 @@
 //   * paired 256-thread solve groups (two per CU) for the large matrices,
 //     which cover each other's barrier waits when there are many of them;
 //   * 256-thread panel groups for panels of at most 256 rows (two per CU)
-//     against one 512-thread group per CU.
+//     against one 512-thread group per CU;
+//   * the LU's look-ahead fork point: the rest of a step's update starts as
+//     soon as the panel is done (best when the panels bound the time) or
+//     after the update of the next panel's columns (which then does not wait
+//     for CU slots behind the larger update).
 // Every setting computes the same moments (the panel variants the same bits).
 // The tuner times each candidate with full moment passes on the plan's own
 // buffers (HIP events on the caller's stream, median of a few passes), keeps
-// the fastest, and caches it per plan signature for the life of the process:
+// the fastest if it beats the built-in setting by more than 2% (the built-in
+// one otherwise), and caches it per plan signature for the life of the process:
 // a later plan with the same launch shapes applies the cached setting without
-// timing.  It searches coordinate-wise: the panel setting first (with the
-// built-in solve setting), then the solve settings with the winning panel one.
+// timing.  It searches coordinate-wise: the LU settings first (panel groups
+// by fork point, with the built-in solve setting), then the solve settings
+// with the winning LU one.
 #include <algorithm>
 #include <cfloat>
 #include <climits>
@@ -59,6 +65,7 @@ void MomentsPlan::apply(const Knobs& k) {
   solve_set_lg(sp_, k.lg, opt.L);
   sp_.paired = k.paired;
   lu_.small_min = k.small_min;
+  lu_.early_fork = k.early_fork;
 }
 
 void MomentsPlan::candidates(std::vector<Knobs>& lu, std::vector<Knobs>& solve) const {
@@ -66,6 +73,7 @@ void MomentsPlan::candidates(std::vector<Knobs>& lu, std::vector<Knobs>& solve) 
   lu.assign(1, base);
   solve.assign(1, base);
   const bool f32 = opt.prec == NEP_PREC_C32_IR64;
+  std::vector<int> smins{base.small_min};
   if (f32) {
     // the steps that take the small groups under a threshold; thresholds that
     // give the same steps are the same launches
@@ -79,11 +87,22 @@ void MomentsPlan::candidates(std::vector<Knobs>& lu, std::vector<Knobs>& solve) 
       auto v = steps_small(smin);
       if (std::find(seen.begin(), seen.end(), v) != seen.end()) continue;
       seen.push_back(v);
-      Knobs k = base;
-      k.small_min = smin;
-      lu.push_back(k);
+      smins.push_back(smin);
     }
   }
+  // the other fork point matters where a step forks at all (more than one
+  // step); the built-in one is the precision's
+  const int fork_base = f32 ? 1 : 0;
+  std::vector<int> forks{base.early_fork};
+  if (lu_.steps.size() > 1) forks.push_back(1 - fork_base);
+  for (int fk : forks)
+    for (int smin : smins) {
+      if (fk == base.early_fork && smin == base.small_min) continue;  // [0]
+      Knobs k = base;
+      k.small_min = smin;
+      k.early_fork = fk;
+      lu.push_back(k);
+    }
   std::vector<std::pair<int, int>> seen{{base.lg, eff_paired(sp_, opt.prec, base, opt.L)}};
   for (int lg : {4, 8, 16}) {
     if (!solve_lg_fits(sp_, lg, opt.L, opt.prec)) continue;
@@ -165,7 +184,7 @@ nep_status tune_plan(MomentsPlan& plan, hipStream_t st) {
       plan.apply(k);
       float ms = 0.f;
       NEP_TRY(plan.time_pass(st, reps, ms));
-      rec.push_back(nep_tune_cand{k.lg, k.paired, k.small_min, ms});
+      rec.push_back(nep_tune_cand{k.lg, k.paired, k.small_min, k.early_fork, ms});
       if (ms < best_ms) {
         best_ms = ms;
         best = k;
@@ -173,15 +192,30 @@ nep_status tune_plan(MomentsPlan& plan, hipStream_t st) {
       }
       return NEP_OK;
     };
+    // a setting replaces the built-in one only if it is faster by more than
+    // the passes' run-to-run spread (about 1%); within it, the built-in stays
+    constexpr float kMargin = 0.98f;
+    const MomentsPlan::Knobs builtin = lu[0];
     for (const auto& k : lu) NEP_TRY(measure(k));
-    // the built-in solve setting was timed with every panel setting above
+    const float builtin_ms = rec[0].ms;
+    auto settle = [&]() {
+      if (chosen != 0 && best_ms > kMargin * builtin_ms) {
+        best = builtin;
+        best_ms = builtin_ms;
+        chosen = 0;
+      }
+    };
+    settle();
+    // the built-in solve setting was timed with every LU setting above
     for (size_t i = 1; i < sv.size(); ++i) {
       MomentsPlan::Knobs k = sv[i];
       k.small_min = best.small_min;
+      k.early_fork = best.early_fork;
       NEP_TRY(measure(k));
     }
+    settle();
   } else {
-    rec.push_back(nep_tune_cand{best.lg, best.paired, best.small_min, 0.f});  // nothing to choose
+    rec.push_back(nep_tune_cand{best.lg, best.paired, best.small_min, best.early_fork, 0.f});  // nothing to choose
   }
   plan.apply(best);
   std::lock_guard<std::mutex> g(T.mu);

@@ -50,8 +50,12 @@ def _check_report(rep):
     assert not rep["cached"] and len(cands) >= 2, rep
     assert 0 <= rep["chosen"] < len(cands), rep
     assert all(c["ms"] > 0.0 and c["lg"] in (4, 8, 16) for c in cands), rep
+    # the fastest, unless it beats the built-in setting (timed first) by 2% or less
     best = min(range(len(cands)), key=lambda i: cands[i]["ms"])
-    assert cands[rep["chosen"]]["ms"] == cands[best]["ms"], rep
+    if cands[best]["ms"] > 0.98 * cands[0]["ms"]:
+        assert rep["chosen"] == 0, rep
+    else:
+        assert cands[rep["chosen"]]["ms"] == cands[best]["ms"], rep
 
 
 def test_tuned_call_matches_oracle_and_is_cached(nep, tuning):
