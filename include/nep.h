@@ -338,6 +338,9 @@ typedef struct {
  * (the default): the built-in choice.  Either way a setting chosen earlier in
  * the process for a plan with the same launch shapes (precision, N, L,
  * sweeps, the multiset of sizes) is applied without timing.  Process-wide.
+ * Timing synchronizes the call's stream, so a call that builds a plan with
+ * tuning on must not be made while that stream is being captured into a graph
+ * (the HIP error is returned as NEP_ERR_DEVICE).
  * Errors: NEP_ERR_ARG if reps is outside 1..64. */
 nep_status nep_tune_set(int on, int reps);
 
