@@ -12,6 +12,7 @@
 //   ||r_c||_inf <= tol (sum_i |f_i(z_j)| ||A_i||_inf ||y_c||_inf + ||v_c||_inf),
 // a normwise backward-error test (moduli of complex entries).  A node whose
 // scaled residual does not at least halve in a sweep is marked stalled.
+#include <algorithm>
 #include <climits>
 
 #include "engine.hpp"
@@ -338,11 +339,12 @@ hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, cons
 }
 
 // ---------------------------------------------------------------------------
-__global__ void k_ir_control(const ProbDesc* __restrict__ pd, NodeArrays na, IrState ir, int nnodes, int sweep,
-                             double tol) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nnodes) return;
-  if (ir.conv[g]) return;
+// One group over every node: the unconverged count is reduced in LDS and
+// stored once, so the counter needs no clearing launch before the sweep.
+constexpr int kIrControlThreads = 1024;
+
+__device__ __forceinline__ bool ir_control_node(const ProbDesc* __restrict__ pd, const NodeArrays& na,
+                                                const IrState& ir, int g, int sweep, double tol) {
   const int p = na.prob[g];
   const ProbDesc& D = pd[p];
   const double fn = na.fnorm[g];
@@ -361,10 +363,23 @@ __global__ void k_ir_control(const ProbDesc* __restrict__ pd, NodeArrays na, IrS
   ir.sweeps[g] = sweep + 1;
   if (rho <= tol) {
     ir.conv[g] = 1;
-  } else {
-    if (sweep > 0 && !(rho <= 0.5 * prev)) ir.stalled[g] = 1;
-    atomicAdd(&ir.counters[0], 1);
+    return false;
   }
+  if (sweep > 0 && !(rho <= 0.5 * prev)) ir.stalled[g] = 1;
+  return true;
+}
+
+__global__ __launch_bounds__(kIrControlThreads) void k_ir_control(const ProbDesc* __restrict__ pd, NodeArrays na,
+                                                                   IrState ir, int nnodes, int sweep, double tol) {
+  __shared__ int unconv;
+  if (threadIdx.x == 0) unconv = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int g = threadIdx.x; g < nnodes; g += blockDim.x)
+    if (!ir.conv[g] && ir_control_node(pd, na, ir, g, sweep, tol)) ++mine;
+  if (mine > 0) atomicAdd(&unconv, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) ir.counters[0] = unconv;
 }
 
 __global__ void k_ir_reset(IrState ir, int nnodes) {
@@ -387,15 +402,10 @@ __global__ void k_ir_reset(IrState ir, int nnodes) {
   }
 }
 
-__global__ void k_zero_int(int* p, int cnt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) p[i] = 0;
-}
-
 hipError_t ir_control(const ProbDesc* pd, const NodeArrays& na, IrState ir, int nnodes, int sweep, double tol,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, ir.counters, 1);
-  hipLaunchKernelGGL(k_ir_control, dim3(ceil_div(nnodes, 64)), dim3(64), 0, st, pd, na, ir, nnodes, sweep, tol);
+  const int nt = std::min(kIrControlThreads, std::max(64, ceil_div(nnodes, 64) * 64));
+  hipLaunchKernelGGL(k_ir_control, dim3(1), dim3(nt), 0, st, pd, na, ir, nnodes, sweep, tol);
   return hipGetLastError();
 }
 
