@@ -216,6 +216,32 @@ def test_batch_equals_single_calls(nep, use_graph):
     B.check(B.lib().nep_batch_destroy(C.byref(bh)))
 
 
+def test_small_panel_groups_same_bits(nep):
+    """17 problems of at most 256 rows put 544 panels in every LU step, so the
+    batch factors with the 256-thread panel groups, while a single call (32
+    panels a step) uses the 512-thread groups: the moments agree bitwise."""
+    import ctypes as C
+    cfg = wl.config3(nprob=17, nmin=64, nmax=256)
+    con, N, L, K = cfg["contour"], cfg["N"], cfg["L"], cfg["K"]
+    ops, Vs, Ss, singles = [], [], [], []
+    for p, V in zip(cfg["problems"], cfg["V"]):
+        op, S1, Sg1, st = _run_moments(nep, p, con, N, L, K, V, "mixed")
+        ops.append(op)
+        singles.append(Sg1)
+        Vs.append(nep.device_probes(V))
+        Ss.append(torch.zeros((2 * K, L, p.n), dtype=torch.complex128, device="cuda"))
+    assert len(ops) * N >= 512 and max(p.n for p in cfg["problems"]) <= 256
+    B = nep.binding
+    b = B.nep_batch_create([op.h for op in ops], [con] * len(ops), B.opts_struct(N, L, K, "mixed"), Vs, Ss,
+                           use_graph=False)
+    stats = B.nep_batch_run(b, len(ops))
+    B.nep_batch_destroy(b)
+    assert all(s["n_unconverged"] == 0 for s in stats)
+    for k in range(len(ops)):
+        Sg = nep.moments_to_numpy(Ss[k])
+        assert np.array_equal(Sg, singles[k]), (k, np.abs(Sg - singles[k]).max())
+
+
 def test_config3_full_batch_graph_sampled(nep):
     """The 256-problem ragged batch at full size, replayed from a HIP graph
     exactly as the benchmark runs it; every problem converges, and sampled
