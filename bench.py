@@ -113,8 +113,10 @@ def _cpu_baseline(cfg, budget_s=20.0):
                       f"{dt:.1f} s"}
 
 
-def _eigs_run(P, steps=3):
-    """Config 2 end to end: moments + extraction, eigenpairs/s at eta <= 1e-10."""
+def _eigs_run(P, steps=3, tune=True):
+    """Config 2 end to end: moments + extraction, eigenpairs/s at eta <= 1e-10
+    (each precision's plan is built, and its launch shapes tuned, in the
+    untimed first call)."""
     import torch
     import workloads as wl
     cfg = wl.config2()
@@ -124,7 +126,10 @@ def _eigs_run(P, steps=3):
     X = torch.zeros((64, cfg["problem"].n), dtype=torch.complex128, device="cuda")
     out = {}
     for prec in ("mixed", "fp64"):
+        P.binding.nep_tune_set(tune, 2)
         op.moments(cfg["contour"], Vd, cfg["N"], cfg["L"], cfg["K"], prec=prec, S=S)
+        P.binding.nep_tune_set(False, 3)
+        tuned = _tune_summary(P.binding)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -136,7 +141,8 @@ def _eigs_run(P, steps=3):
         out[prec] = {"s_per_step": dt, "quadrature_solves_per_s": cfg["N"] / dt, "eigenpairs_inside": int(r["inside"].sum()),
                      "eigenpairs_eta_le_1e-10": good, "eigenpairs_per_s": good / dt,
                      "max_eta_inside": float(np.max(r["eta"][r["inside"]])) if r["inside"].any() else None,
-                     "rank": int(r["m"]), "refine_sweeps": st["refine_sweeps"], "n_fallback": st["n_fallback"]}
+                     "rank": int(r["m"]), "refine_sweeps": st["refine_sweeps"], "n_fallback": st["n_fallback"],
+                     "tuning": tuned}
     op.close()
     return out
 
@@ -299,7 +305,7 @@ def main():
         "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
     }
     if not args.no_extra:
-        for key, fn in (("cfg2_end_to_end", lambda: _eigs_run(P)),
+        for key, fn in (("cfg2_end_to_end", lambda: _eigs_run(P, tune=not args.no_tune)),
                         ("cfg3_batch_graph", lambda: _batch_run(P, tune=not args.no_tune)),
                         ("cfg4_serving_mixed", lambda: _serve_run(P, "mixed")),
                         ("cfg4_serving_fp64", lambda: _serve_run(P, "fp64"))):
