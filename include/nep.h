@@ -345,8 +345,9 @@ typedef struct {
 nep_status nep_tune_set(int on, int reps);
 
 /* The last plan built: *ncand candidates timed (0 when the setting came from
- * the cache, with *cached = 1), the index of the one kept in *chosen, and the
- * first min(max, *ncand) of them in cand (host array).  A plan with a single
+ * the cache, with *cached = 1, or when tuning was off, with *cached = 0 and
+ * *chosen = -1), the index of the one kept in *chosen, and the first
+ * min(max, *ncand) of them in cand (host array).  A plan with a single
  * candidate reports it with ms = 0.  Errors: NEP_ERR_ARG on null outputs. */
 nep_status nep_tune_report(int max, nep_tune_cand* cand, int* ncand, int* chosen, int* cached);
 

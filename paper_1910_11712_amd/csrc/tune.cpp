@@ -170,7 +170,12 @@ nep_status tune_plan(MomentsPlan& plan, hipStream_t st) {
       T.last_cached = 1;
       return NEP_OK;
     }
-    if (!T.on) return NEP_OK;
+    if (!T.on) {  // the built-in setting, not timed
+      T.last.clear();
+      T.last_chosen = -1;
+      T.last_cached = 0;
+      return NEP_OK;
+    }
     reps = T.reps;
   }
   std::vector<MomentsPlan::Knobs> lu, sv;

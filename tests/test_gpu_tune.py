@@ -77,6 +77,12 @@ def test_tuned_call_matches_oracle_and_is_cached(nep, tuning):
     rep2 = B.nep_tune_report()
     assert rep2["cached"] and rep2["candidates"] == [], rep2
     _check_moments(nep.moments_to_numpy(S2), So)
+    # a new plan (other precision) with tuning off and nothing cached: the
+    # built-in setting, and a report that says so
+    B.nep_tune_clear()
+    S3, _ = op2.moments(con, nep.device_probes(cfg["V"]), N, L, K, prec="fp64")
+    assert B.nep_tune_report() == {"candidates": [], "chosen": -1, "cached": False}
+    _check_moments(nep.moments_to_numpy(S3), So)
 
 
 def test_tuned_batch_graph_matches_oracle(nep, tuning):
