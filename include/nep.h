@@ -162,7 +162,7 @@ typedef struct {
   int max_refine;    /* refinement sweeps (mixed); 0..20, default 5             */
   int fp64_fallback; /* 1: nodes whose refinement stalls are re-solved in FP64  */
   double refine_tol; /* stop when ||R||_inf <= tol (||T||_inf ||Y||_inf + ||V||_inf)
-                        per probe column; 0 selects 1e-14                     */
+                        per probe column; 0 selects 1e-15                     */
   void* stream;      /* NULL: the handle's stream                               */
 } nep_ciss_opts;
 
@@ -175,6 +175,12 @@ typedef struct {
   int bad_node;           /* first node on a pole/branch cut, or -1              */
   double max_rel_residual;/* max over nodes/columns of the final scaled residual */
   float ms_total;         /* device time of the call (events), if synchronous    */
+  float ms_lu;            /* device time from the first LU launch to the end of
+                             the factorizations (events; single calls and eager
+                             batch runs; 0 for graph replays)                    */
+  double min_abs_pivot;   /* smallest |u_kk| over the node factorizations in the
+                             path's precision (complex FP32 for the mixed path);
+                             0 with NEP_ERR_SINGULAR, NaN if a factor holds NaN  */
 } nep_ciss_stats;
 
 /* S_p = sum_j w_j zeta_j^p T(z_j)^{-1} V for p = 0..2K-1.
@@ -200,6 +206,9 @@ nep_status nep_ciss_wait(nep_split h, nep_ciss_stats* st);
 
 typedef struct {
   double rank_tol;  /* keep singular values > rank_tol * sigma_1; 0 -> 1e-12    */
+  double eta_tol;   /* convergence tolerance on the backward error eta of
+                       eq. (sressplit) (the paper's NEPSetTolerances tol, Table 1
+                       uses 1e-8 for most problems); 0 -> 1e-8                  */
   int max_eigs;     /* capacity of the output arrays (>= 1)                     */
 } nep_extract_opts;
 
@@ -211,7 +220,12 @@ typedef struct {
  *   X      : device, complex n x max_eigs column-major: eigenvectors,
  *            ||x||_2 = 1, largest-modulus entry real positive.
  *   eta    : host, max_eigs doubles: backward error eq. (sressplit), inf-norms.
- *   inside : host, max_eigs ints: 1 if the eigenvalue lies inside the contour.
+ *   inside : host, max_eigs ints: 1 if the eigenvalue lies inside the contour
+ *            and the pair has converged (eta <= eta_tol); 2 if it lies inside
+ *            but eta > eta_tol (not converged: a spurious pair from a rank
+ *            taken at the moments' noise floor, or one limited by the
+ *            quadrature); 0 if it lies outside (the region filter of
+ *            Section 3.2.4).
  *   sigma  : host, optional (may be NULL), K*L doubles: singular values of the
  *            block-Hankel matrix B0.
  * Synchronous.  NEP_ERR_RANK if every one of the K*L singular values is
@@ -250,8 +264,18 @@ nep_status nep_batch_create(int nprob, const nep_split* h,
                             int use_graph, void* stream, nep_batch* out);
 
 /* Runs the plan.  st (optional, nprob entries) as in nep_ciss_moments; if
- * non-NULL the call is synchronous. */
+ * non-NULL the call is synchronous (it ends with nep_batch_wait).  If NULL it
+ * returns after enqueueing; nep_batch_wait must then follow before the
+ * moments are used: the run does a fixed number of refinement sweeps on the
+ * device, and nodes still above the tolerance are re-solved in FP64 there. */
 nep_status nep_batch_run(nep_batch b, nep_ciss_stats* st);
+
+/* Waits for the last nep_batch_run, re-solves in FP64 the nodes its sweeps
+ * left above the refinement tolerance (mixed precision with fp64_fallback),
+ * and reports per-problem stats in st (optional, nprob entries) and the
+ * status: the most severe of NEP_ERR_NOT_HOLOMORPHIC, NEP_ERR_SINGULAR,
+ * NEP_ERR_REFINE over the problems.  NEP_ERR_ARG if no run is pending. */
+nep_status nep_batch_wait(nep_batch b, nep_ciss_stats* st);
 
 nep_status nep_batch_destroy(nep_batch* b);
 

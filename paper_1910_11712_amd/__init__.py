@@ -64,12 +64,13 @@ class SplitOperator:
     def wait(self):
         return nep_ciss_wait(self.h)
 
-    def extract(self, contour, S, N, L, K, prec="mixed", max_eigs=64, rank_tol=0.0, X=None, stream=None):
+    def extract(self, contour, S, N, L, K, prec="mixed", max_eigs=64, rank_tol=0.0, X=None, stream=None,
+                eta_tol=0.0):
         import torch
         if X is None:
             X = torch.zeros((max_eigs, self.n), dtype=torch.complex128, device=S.device)
         o = opts_struct(N, L, K, prec, None, True, 0.0, stream)
-        r = nep_extract(self.h, contour, o, S, X, max_eigs, rank_tol)
+        r = nep_extract(self.h, contour, o, S, X, max_eigs, rank_tol, eta_tol)
         r["X_dev"] = X
         r["X"] = X[: r["m"]].cpu().numpy().T.copy()
         return r
@@ -90,9 +91,10 @@ class Server:
         self.s = binding.nep_server_create(hbm_budget, max_inflight, nstreams)
         self._out = {}
 
-    def submit(self, op, contour, V, N, L, K, prec="mixed", max_eigs=64, want_X=False, rank_tol=0.0):
+    def submit(self, op, contour, V, N, L, K, prec="mixed", max_eigs=64, want_X=False, rank_tol=0.0,
+               eta_tol=0.0):
         o = binding.opts_struct(N, L, K, prec)
-        t, out = binding.nep_server_submit(self.s, op.h, contour, o, V, max_eigs, rank_tol, want_X)
+        t, out = binding.nep_server_submit(self.s, op.h, contour, o, V, max_eigs, rank_tol, want_X, eta_tol)
         self._out[t] = out
         return t
 

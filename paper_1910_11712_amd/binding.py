@@ -59,14 +59,15 @@ class nep_ciss_opts(C.Structure):
 class nep_ciss_stats(C.Structure):
     _fields_ = [("N", C.c_int), ("refine_sweeps", C.c_int), ("n_fallback", C.c_int),
                 ("n_unconverged", C.c_int), ("singular_node", C.c_int), ("bad_node", C.c_int),
-                ("max_rel_residual", C.c_double), ("ms_total", C.c_float)]
+                ("max_rel_residual", C.c_double), ("ms_total", C.c_float), ("ms_lu", C.c_float),
+                ("min_abs_pivot", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class nep_extract_opts(C.Structure):
-    _fields_ = [("rank_tol", C.c_double), ("max_eigs", C.c_int)]
+    _fields_ = [("rank_tol", C.c_double), ("eta_tol", C.c_double), ("max_eigs", C.c_int)]
 
 
 class nep_server_opts(C.Structure):
@@ -126,6 +127,7 @@ def lib():
                                        C.POINTER(vp), C.POINTER(vp), ip, vp, C.POINTER(vp)]
         L.nep_batch_run.argtypes = [vp, C.POINTER(nep_ciss_stats)]
         L.nep_batch_destroy.argtypes = [C.POINTER(vp)]
+        L.nep_batch_wait.argtypes = [vp, C.POINTER(nep_ciss_stats)]
         L.nep_ciss_moments_batch.argtypes = [ip, C.POINTER(vp), C.POINTER(nep_contour), C.POINTER(nep_ciss_opts),
                                              C.POINTER(vp), C.POINTER(vp), C.POINTER(nep_ciss_stats)]
         L.nep_prof_enable.argtypes = [ip]
@@ -266,9 +268,11 @@ def nep_ciss_wait(h):
     return st.as_dict()
 
 
-def nep_extract(h, contour, opts, S, X, max_eigs=64, rank_tol=0.0):
+def nep_extract(h, contour, opts, S, X, max_eigs=64, rank_tol=0.0, eta_tol=0.0):
+    """Returns m, lam, eta, inside (inside the contour and converged),
+    unconverged (inside with eta > eta_tol) and the singular values."""
     e = nep_extract_opts()
-    e.rank_tol, e.max_eigs = float(rank_tol), int(max_eigs)
+    e.rank_tol, e.eta_tol, e.max_eigs = float(rank_tol), float(eta_tol), int(max_eigs)
     m = C.c_int(0)
     lam = np.zeros(2 * max_eigs)
     eta = np.zeros(max_eigs)
@@ -285,7 +289,8 @@ def nep_extract(h, contour, opts, S, X, max_eigs=64, rank_tol=0.0):
         err.sigma = sig
         raise err
     lam_c = lam[0:2 * k:2] + 1j * lam[1:2 * k:2]
-    return {"m": k, "lam": lam_c, "eta": eta[:k].copy(), "inside": ins[:k].astype(bool), "sigma": sig}
+    return {"m": k, "lam": lam_c, "eta": eta[:k].copy(), "inside": ins[:k] == 1, "unconverged": ins[:k] == 2,
+            "sigma": sig}
 
 
 def nep_backward_error(h, lam, X):
@@ -349,12 +354,12 @@ def nep_server_create(hbm_budget, max_inflight=64, nstreams=4):
     return s
 
 
-def nep_server_submit(s, h, contour, opts, V, max_eigs=64, rank_tol=0.0, want_X=False):
+def nep_server_submit(s, h, contour, opts, V, max_eigs=64, rank_tol=0.0, want_X=False, eta_tol=0.0):
     """Queues a query.  V: host complex (n, L).  Returns (ticket, out) where
     out holds the host result arrays the server fills; keep it until the
     query is collected."""
     e = nep_extract_opts()
-    e.rank_tol, e.max_eigs = float(rank_tol), int(max_eigs)
+    e.rank_tol, e.eta_tol, e.max_eigs = float(rank_tol), float(eta_tol), int(max_eigs)
     Vf = np.asfortranarray(np.asarray(V, dtype=np.complex128))
     n = Vf.shape[0]
     out = {"V": Vf, "lam": np.zeros(2 * max_eigs), "eta": np.zeros(max_eigs),
@@ -376,7 +381,7 @@ def _query_result(info, out):
     r = {"status": info.status, "m": k, "n_inside": info.n_inside,
          "t_submit": info.t_submit, "t_start": info.t_start, "t_done": info.t_done,
          "lam": lam[0:2 * k:2] + 1j * lam[1:2 * k:2], "eta": out["eta"][:k].copy(),
-         "inside": out["inside"][:k].astype(bool)}
+         "inside": out["inside"][:k] == 1, "unconverged": out["inside"][:k] == 2}
     if out["X"] is not None:
         r["X"] = out["X"][:, :k].copy()
     return r
@@ -428,6 +433,16 @@ def nep_batch_run(b, nprob=None):
         return None
     st = (nep_ciss_stats * nprob)()
     check(lib().nep_batch_run(b, st))
+    return [s.as_dict() for s in st]
+
+
+def nep_batch_wait(b, nprob=None):
+    """Waits for the last run; with nprob returns the per-problem stats."""
+    if nprob is None:
+        check(lib().nep_batch_wait(b, None))
+        return None
+    st = (nep_ciss_stats * nprob)()
+    check(lib().nep_batch_wait(b, st))
     return [s.as_dict() for s in st]
 
 

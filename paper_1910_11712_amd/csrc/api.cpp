@@ -201,7 +201,7 @@ nep_status check_opts(const nep_ciss_opts* o, PlanOptions& po) {
   po.prec = o->prec;
   po.max_refine = o->max_refine;
   po.fallback = o->fp64_fallback ? 1 : 0;
-  po.tol = o->refine_tol > 0.0 ? o->refine_tol : 1e-14;
+  po.tol = o->refine_tol > 0.0 ? o->refine_tol : kDefaultRefineTol;
   return NEP_OK;
 }
 

@@ -13,6 +13,7 @@ struct Batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool use_graph = false;
+  bool pending = false;  // a run was enqueued and not yet finished
   ~Batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -78,10 +79,20 @@ nep_status nep_batch_run(nep_batch b, nep_ciss_stats* st) {
   } else {
     NEP_TRY(B.plan->enqueue(B.stream, false));
   }
+  B.pending = true;
   if (!st) return NEP_OK;
+  return nep_batch_wait(b, st);
+}
+
+nep_status nep_batch_wait(nep_batch b, nep_ciss_stats* st) {
+  NEP_CHECK(b != nullptr, NEP_ERR_ARG, "null batch");
+  Batch& B = b->impl;
+  NEP_CHECK(B.pending, NEP_ERR_ARG, "no batch run pending");
+  B.pending = false;
   RunResult rr;
   nep_status s = B.plan->finish(B.stream, rr, true);
-  for (int p = 0; p < B.plan->nprob && p < (int)rr.stats.size(); ++p) st[p] = rr.stats[p];
+  if (st)
+    for (int p = 0; p < B.plan->nprob && p < (int)rr.stats.size(); ++p) st[p] = rr.stats[p];
   return s;
 }
 

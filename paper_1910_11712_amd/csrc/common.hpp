@@ -63,6 +63,9 @@ __host__ __device__ __forceinline__ P abs1(cx<P> a) {  // |Re| + |Im|, +0 for si
 }
 template <typename P>
 __host__ __device__ __forceinline__ P norm2(cx<P> a) { return a.re * a.re + a.im * a.im; }
+// Maximum that keeps NaN (fmax drops it): a norm taken over values that hold a
+// NaN must come out NaN, so that tests on it can see the failure.
+__host__ __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
 // Reciprocal 1/a computed in double and rounded once to P.
 template <typename P>

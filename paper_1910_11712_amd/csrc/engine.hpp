@@ -16,6 +16,14 @@ constexpr int kSolveBlk = 64;    // triangular-solve block rows
 constexpr int kResidRealTM = 64, kResidRealTQ = 64;  // real-term residual tile: rows x real columns
 constexpr int kFallbackSweeps = 2;  // FP64 refinement sweeps after an FP64 re-solve
 constexpr int kNormStride = 64;  // per-node stride of the column-norm arrays (L <= 64)
+// Default stopping tolerance of the refinement (normwise backward error per
+// probe column).  1e-15 rather than 1e-14: the residual a stopped solve
+// leaves, mapped through T(z_j)^{-1}, lies along the eigenvectors of the
+// eigenvalues near the node, so it moves the extracted eigenvalues instead of
+// averaging out; at 1e-14 it moved them by up to a few 1e-11 (and lifted
+// noise singular values above the rank threshold), at 1e-15 by ~1e-11, the
+// level of the plain FP64 path.
+constexpr double kDefaultRefineTol = 1e-15;
 
 // Per-problem descriptor (device resident).
 struct ProbDesc {
@@ -122,6 +130,10 @@ hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, cons
 // status read-back block (see k_gather_status) and its size
 size_t status_bytes(int G);
 hipError_t gather_status(IrState ir, const int* info, const int* bad, int G, void* out, hipStream_t st);
+// smallest pivot modulus per node into the status block (after rho)
+template <typename P>
+hipError_t min_pivot(const MatDesc* md, int nmat, const cx<P>* T, const int* rows, int G, void* status,
+                     hipStream_t st);
 hipError_t ir_control(const ProbDesc* pd, const NodeArrays& na, IrState ir, int nnodes, int sweep, double tol,
                       hipStream_t st);
 hipError_t ir_reset(IrState ir, int nnodes, hipStream_t st);

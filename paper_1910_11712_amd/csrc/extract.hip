@@ -24,9 +24,11 @@
 namespace nep {
 
 struct ExtractWork {
-  DevMem B0, B1, tau, V0, P, smat, X0, Rt, norms;
+  DevMem B0, B1, tau, V0, P, smat, X0, Rt, norms, fz;
   size_t cap_rows = 0, cap_cols = 0;
 };
+
+std::shared_ptr<ExtractWork> make_extract_work() { return std::make_shared<ExtractWork>(); }
 
 // ---------------------------------------------------------------------------
 __global__ void k_hankel(const c128* __restrict__ S, int n, int L, int K, c128* __restrict__ B0,
@@ -231,16 +233,16 @@ __global__ void k_colmax2(const c128* __restrict__ Rt, const c128* __restrict__ 
   const int q = blockIdx.x;
   double a = 0.0, b = 0.0;
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
-    a = fmax(a, sqrt(norm2(Rt[(long long)q * n + r])));
-    b = fmax(b, sqrt(norm2(X[(long long)q * n + r])));
+    a = nanmax(a, sqrt(norm2(Rt[(long long)q * n + r])));
+    b = nanmax(b, sqrt(norm2(X[(long long)q * n + r])));
   }
   r1[threadIdx.x] = a;
   r2[threadIdx.x] = b;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
-      r1[threadIdx.x] = fmax(r1[threadIdx.x], r1[threadIdx.x + s]);
-      r2[threadIdx.x] = fmax(r2[threadIdx.x], r2[threadIdx.x + s]);
+      r1[threadIdx.x] = nanmax(r1[threadIdx.x], r1[threadIdx.x + s]);
+      r2[threadIdx.x] = nanmax(r2[threadIdx.x], r2[threadIdx.x + s]);
     }
     __syncthreads();
   }
@@ -257,12 +259,24 @@ static nep_status grow(DevMem& m, size_t bytes) {
 }
 
 // eta for m pairs: X device (n x m column-major), lambda host.
+hipError_t fn_points(const FnNode* nodes, const c128* coef, const int* roots, int ell, const c128* z, int m,
+                     c128* out, int* bad, hipStream_t st);
+
 static nep_status backward_errors(Split& h, int m, const std::vector<zc>& lam, const c128* X, std::vector<double>& eta,
                                   ExtractWork& w, hipStream_t st) {
   const int n = h.op.n, ell = h.op.ell;
-  std::vector<c128> fv;
-  std::vector<int> bad;
-  NEP_TRY(h.eval_fns(m, reinterpret_cast<const c128*>(lam.data()), fv, bad));
+  // f_i(lambda_q) on the device, in the workspace (grow-only: no device
+  // allocation or free once it is large enough)
+  std::vector<c128> fv((size_t)m * ell);
+  std::vector<int> bad(m);
+  NEP_TRY(grow(w.fz, sizeof(c128) * (size_t)m * (ell + 1) + sizeof(int) * (size_t)m));
+  c128* dz = w.fz.as<c128>();
+  c128* dfv = dz + m;
+  int* dbad = reinterpret_cast<int*>(dfv + (size_t)m * ell);
+  NEP_HIP(hipMemcpyAsync(dz, lam.data(), sizeof(c128) * m, hipMemcpyHostToDevice, st));
+  NEP_HIP(fn_points(h.op.dfn_nodes, h.op.dfn_coef, h.fn_roots.as<int>(), ell, dz, m, dfv, dbad, st));
+  NEP_HIP(hipMemcpyAsync(fv.data(), dfv, sizeof(c128) * (size_t)m * ell, hipMemcpyDeviceToHost, st));
+  NEP_HIP(hipMemcpyAsync(bad.data(), dbad, sizeof(int) * m, hipMemcpyDeviceToHost, st));
   NEP_TRY(grow(w.Rt, sizeof(c128) * (size_t)n * m));
   NEP_TRY(grow(w.norms, sizeof(double) * 2 * m + sizeof(c128) * (size_t)ell * m + sizeof(void*) * kMaxTerms +
                             sizeof(int) * kMaxTerms));
@@ -301,21 +315,25 @@ static nep_status backward_errors(Split& h, int m, const std::vector<zc>& lam, c
   return NEP_OK;
 }
 
-static nep_status extract(Split& h, const nep_contour* g, const nep_ciss_opts* o, const void* S,
-                          const nep_extract_opts* e, int* m_out, double* lambda, void* X, double* eta, int* inside,
-                          double* sigma) {
+nep_status extract(Split& h, const nep_contour* g, const nep_ciss_opts* o, const void* S,
+                   const nep_extract_opts* e, int* m_out, double* lambda, void* X, double* eta, int* inside,
+                   double* sigma, ExtractWork* wk) {
   NEP_TRY(check_contour(g));
   PlanOptions po;
   NEP_TRY(check_opts(o, po));
   NEP_CHECK(e != nullptr && e->max_eigs >= 1, NEP_ERR_ARG, "extract options: max_eigs must be >= 1");
+  NEP_CHECK(e->rank_tol >= 0.0 && e->eta_tol >= 0.0, NEP_ERR_ARG, "extract options: tolerances must be >= 0");
   NEP_CHECK(S != nullptr && X != nullptr && m_out && lambda && eta && inside, NEP_ERR_ARG, "null output array");
   const int n = h.op.n, L = po.L, K = po.K;
   const long long M = (long long)K * n;
   const int KL = K * L;
   NEP_CHECK(KL <= M, NEP_ERR_ARG, "K*L exceeds K*n");
   hipStream_t st = o->stream ? (hipStream_t)o->stream : h.stream;
-  if (!h.xw) h.xw = std::make_shared<ExtractWork>();
-  ExtractWork& w = *h.xw;
+  if (!wk) {
+    if (!h.xw) h.xw = std::make_shared<ExtractWork>();
+    wk = h.xw.get();
+  }
+  ExtractWork& w = *wk;
   NEP_TRY(grow(w.B0, sizeof(c128) * M * KL));
   NEP_TRY(grow(w.B1, sizeof(c128) * M * KL));
   NEP_TRY(grow(w.tau, sizeof(c128) * KL));
@@ -407,13 +425,20 @@ static nep_status extract(Split& h, const nep_contour* g, const nep_ciss_opts* o
   NEP_HIP(hipStreamSynchronize(st));
   std::vector<double> et;
   NEP_TRY(backward_errors(h, m, lam_s, (const c128*)X, et, w, st));
+  // The region filter (Section 3.2.4) keeps the eigenvalues inside the
+  // contour; of those, a pair counts as converged when its backward error is
+  // below the tolerance, the stopping test of the paper's solvers.  A pair
+  // inside but above it (typically a spurious one from a numerical rank taken
+  // at the moments' noise floor) is flagged apart.
+  const double etol = e->eta_tol > 0.0 ? e->eta_tol : 1e-8;
   for (int q = 0; q < m; ++q) {
     lambda[2 * q] = lam_s[q].real();
     lambda[2 * q + 1] = lam_s[q].imag();
     eta[q] = et[q];
     const zc mu_q = (lam_s[q] - c0) / g->rho;
-    inside[q] = g->kind == 0 ? (std::abs(mu_q) < 1.0)
-                             : (mu_q.real() * mu_q.real() + (mu_q.imag() / g->v) * (mu_q.imag() / g->v) < 1.0);
+    const bool in = g->kind == 0 ? (std::abs(mu_q) < 1.0)
+                                 : (mu_q.real() * mu_q.real() + (mu_q.imag() / g->v) * (mu_q.imag() / g->v) < 1.0);
+    inside[q] = !in ? 0 : (et[q] <= etol ? 1 : 2);
   }
   return NEP_OK;
 }
@@ -428,7 +453,7 @@ nep_status nep_extract(nep_split h, const nep_contour* g, const nep_ciss_opts* o
                        const nep_extract_opts* e, int* m, double* lambda, void* X, double* eta, int* inside,
                        double* sigma) {
   NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle");
-  return nep::extract(h->impl, g, o, S, e, m, lambda, X, eta, inside, sigma);
+  return nep::extract(h->impl, g, o, S, e, m, lambda, X, eta, inside, sigma, nullptr);
 }
 
 nep_status nep_backward_error(nep_split h, int m, const double* lambda, const void* X, double* eta) {

@@ -31,6 +31,14 @@ struct Split {
 nep_status check_contour(const nep_contour* g);
 nep_status check_opts(const nep_ciss_opts* o, PlanOptions& po);
 
+// Extraction (extract.hip).  wk: the workspace to use, or nullptr for the
+// handle's own.  A workspace grows and never shrinks; blocks allocated while
+// an ArenaScope is alive come from that arena.
+std::shared_ptr<ExtractWork> make_extract_work();
+nep_status extract(Split& h, const nep_contour* g, const nep_ciss_opts* o, const void* S,
+                   const nep_extract_opts* e, int* m_out, double* lambda, void* X, double* eta, int* inside,
+                   double* sigma, ExtractWork* wk);
+
 }  // namespace nep
 
 struct nep_split_s {

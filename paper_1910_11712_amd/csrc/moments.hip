@@ -192,12 +192,12 @@ __global__ __launch_bounds__(256) void k_vnorm(const ProbDesc* __restrict__ pd, 
   if (c >= D.L) return;  // uniform
   const c128* __restrict__ v = D.V + (long long)c * D.n;
   double m = 0.0;
-  for (int r = threadIdx.x; r < D.n; r += blockDim.x) m = fmax(m, sqrt(norm2(v[r])));
-  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  for (int r = threadIdx.x; r < D.n; r += blockDim.x) m = nanmax(m, sqrt(norm2(v[r])));
+  for (int o = 32; o >= 1; o >>= 1) m = nanmax(m, __shfl_xor(m, o, 64));
   __shared__ double red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  if (threadIdx.x == 0) ir.vnorm[blockIdx.x * 64 + c] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  if (threadIdx.x == 0) ir.vnorm[blockIdx.x * 64 + c] = nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3]));
 }
 
 hipError_t launch_vnorm(const ProbDesc* pd, int nprob, int L, IrState ir, hipStream_t st) {

@@ -327,6 +327,10 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
     NEP_HIP(hipHostMalloc((void**)&hstat_, hstat_bytes_, hipHostMallocDefault));
   }
   if (!ev_counter_) NEP_HIP(hipEventCreateWithFlags(&ev_counter_, hipEventDisableTiming));
+  if (!ev_lu_[0]) {
+    NEP_HIP(hipEventCreate(&ev_lu_[0]));
+    NEP_HIP(hipEventCreate(&ev_lu_[1]));
+  }
 
   {
     char* q = dnode_.as<char>();
@@ -389,8 +393,13 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
   NEP_HIP(launch_vnorm(pd, nprob, opt.L, ir_, st));
   cx<P>* Dinv = ddinv_.as<cx<P>>();
   const long long* doff = ddinv_off_.as<long long>();
+  if (eager) NEP_HIP(hipEventRecord(ev_lu_[0], st));
   NEP_HIP(lu_run<P>(lu_, md, dlu_prefix_.as<int>(), T, rows, drows_snap_.as<int>(), rows_total_, info, nullptr,
                     dlinv_.as<cx<P>>(), Dinv, doff, darrive_.as<int>(), st, ls_));
+  if (eager) {
+    NEP_HIP(hipEventRecord(ev_lu_[1], st));
+    lu_timed_ = true;
+  }
   NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, nullptr, Y, false, nullptr, ir_, st));
   sweeps_run_ = 0;
   if (opt.max_refine > 0) {
@@ -489,12 +498,20 @@ nep_status MomentsPlan::finish(hipStream_t st, RunResult& out, bool allow_fallba
   const int G = nnodes;
   std::vector<int> info(G), conv(G), sweeps(G), bad(G), counters(4);
   std::vector<double> rho(G);
+  std::vector<double> pmin(G);
   auto read_back = [&]() -> nep_status {  // one gathered block, one copy
     NEP_HIP(gather_status(ir_, dinfo_.as<int>(), na_.bad, G, dstat_.p, st));
+    if (opt.prec == NEP_PREC_FP64)
+      NEP_HIP(min_pivot<double>(dmd_.as<MatDesc>(), (int)sorted_.size(), dT_.as<c128>(), drows_.as<int>(), G,
+                                dstat_.p, st));
+    else
+      NEP_HIP(min_pivot<float>(dmd_.as<MatDesc>(), (int)sorted_.size(), dT_.as<c64>(), drows_.as<int>(), G,
+                               dstat_.p, st));
     NEP_HIP(hipMemcpyAsync(hstat_, dstat_.p, status_bytes(G), hipMemcpyDeviceToHost, st));
     NEP_HIP(hipStreamSynchronize(st));
-    const int* iv = reinterpret_cast<const int*>(hstat_ + (size_t)G * sizeof(double));
+    const int* iv = reinterpret_cast<const int*>(hstat_ + 2 * (size_t)G * sizeof(double));
     std::memcpy(rho.data(), hstat_, sizeof(double) * G);
+    std::memcpy(pmin.data(), hstat_ + (size_t)G * sizeof(double), sizeof(double) * G);
     std::memcpy(info.data(), iv, sizeof(int) * G);
     std::memcpy(conv.data(), iv + G, sizeof(int) * G);
     std::memcpy(sweeps.data(), iv + 2 * G, sizeof(int) * G);
@@ -505,33 +522,67 @@ nep_status MomentsPlan::finish(hipStream_t st, RunResult& out, bool allow_fallba
   NEP_TRY(read_back());
   const bool refined = opt.max_refine > 0;
   const bool mixed = opt.prec == NEP_PREC_C32_IR64;
-  if (allow_fallback && refined && mixed && opt.fallback && !fallback_pending_ && counters[1] == 0) {
-    // a fixed-sweep run left nodes unconverged: re-solve them in FP64 and
-    // recompute the moments (the eager path does this inside enqueue)
+  std::vector<int> excluded;  // unconverged nodes of problems that fail anyway
+  if (allow_fallback && refined && mixed && opt.fallback && !fallback_pending_) {
+    // A fixed-sweep run left nodes unconverged: re-solve them in FP64 and
+    // recompute the moments (the eager path does this inside enqueue).  The
+    // decision is per problem: a problem with a node on a pole or cut, or an
+    // exact zero pivot, fails whatever its other nodes do, so its nodes are
+    // left out, and the other problems of the batch are re-solved exactly
+    // as they would be alone.
+    std::vector<char> fails(nprob, 0);
+    for (int g = 0; g < G; ++g) {
+      const int p = na_prob_host_[g];
+      if (bad[g] || info[g] < hpd_[p].n) fails[p] = 1;
+    }
     bool any = false;
-    for (int g = 0; g < G; ++g) any |= (!conv[g] && info[g] >= hpd_[na_prob_host_[g]].n);
+    for (int g = 0; g < G; ++g) {
+      if (conv[g]) continue;
+      if (fails[na_prob_host_[g]]) excluded.push_back(g);
+      else any = true;
+    }
     // (if the FP64 workspace cannot be allocated the nodes stay unconverged
     // and their problems report NEP_ERR_REFINE)
-    if (any && run_fallback<double>(st) == NEP_OK) {
-      NEP_HIP(launch_moments(dpd_.as<ProbDesc>(), dprefix_.as<int>(), pt_.moments, na_, dY_.as<c128>(), st));
-      NEP_TRY(read_back());
+    if (any) {
+      if (!excluded.empty()) {  // the re-solve skips converged nodes: mark the left-out ones so
+        std::vector<int> skip(conv);
+        for (int g : excluded) skip[g] = 1;
+        NEP_HIP(hipMemcpyAsync(ir_.conv, skip.data(), sizeof(int) * G, hipMemcpyHostToDevice, st));
+        NEP_HIP(hipStreamSynchronize(st));
+      }
+      if (run_fallback<double>(st) == NEP_OK) {
+        NEP_HIP(launch_moments(dpd_.as<ProbDesc>(), dprefix_.as<int>(), pt_.moments, na_, dY_.as<c128>(), st));
+        NEP_TRY(read_back());
+        for (int g : excluded) conv[g] = 0;  // still unconverged, for the stats
+      }
     }
   }
   out.stats.assign(nprob, nep_ciss_stats{});
   out.pstatus.assign(nprob, NEP_OK);
   out.status = NEP_OK;
+  float lu_ms = 0.f;
+  if (lu_timed_) {
+    if (hipEventElapsedTime(&lu_ms, ev_lu_[0], ev_lu_[1]) != hipSuccess) {
+      (void)hipGetLastError();
+      lu_ms = 0.f;
+    }
+    lu_timed_ = false;
+  }
   for (int p = 0; p < nprob; ++p) {
     nep_ciss_stats& s = out.stats[p];
     s.N = opt.N;
     s.singular_node = -1;
     s.bad_node = -1;
     s.max_rel_residual = refined ? 0.0 : -1.0;
+    s.ms_lu = lu_ms;
+    s.min_abs_pivot = INFINITY;
     if (fallback_pending_) s.n_fallback = fallback_count_[p];
   }
   for (int g = 0; g < G; ++g) {
     const int p = na_prob_host_[g];
     nep_ciss_stats& s = out.stats[p];
     const int j = g - hpd_[p].node0;
+    if (!(pmin[g] >= s.min_abs_pivot)) s.min_abs_pivot = pmin[g];  // keeps a NaN
     if (bad[g] && s.bad_node < 0) s.bad_node = j;
     if (info[g] < hpd_[p].n && s.singular_node < 0) s.singular_node = j;
     if (refined) {

@@ -91,7 +91,7 @@ struct PlanProblem {
 struct PlanOptions {
   int N = 32, L = 8, K = 2, prec = NEP_PREC_C32_IR64;
   int max_refine = 5, fallback = 1;
-  double tol = 1e-14;
+  double tol = kDefaultRefineTol;
 };
 
 struct RunResult {
@@ -109,6 +109,8 @@ class MomentsPlan {
     if (hcounter_) pinned_give(hcounter_);
     if (hstat_) (void)hipHostFree(hstat_);
     if (ev_counter_) (void)hipEventDestroy(ev_counter_);
+    for (hipEvent_t e : ev_lu_)
+      if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : {ls_.ev_fork, ls_.ev_join, ls_.ev_side[0], ls_.ev_side[1], ls_.ev_side_done})
       if (e) (void)hipEventDestroy(e);
     if (ls_.aux) (void)hipStreamDestroy(ls_.aux);
@@ -176,6 +178,8 @@ class MomentsPlan {
   IrState ir_{};
   int* hcounter_ = nullptr;  // pinned host read-back
   hipEvent_t ev_counter_ = nullptr;  // marks the counter read-back of a sweep
+  hipEvent_t ev_lu_[2] = {nullptr, nullptr};  // around the LU of an eager pass (ms_lu)
+  bool lu_timed_ = false;
   DevMem dstat_;                     // status block gathered for finish()
   char* hstat_ = nullptr;            // its pinned host copy
   size_t hstat_bytes_ = 0;

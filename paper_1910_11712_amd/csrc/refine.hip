@@ -152,10 +152,10 @@ __global__ __launch_bounds__(256) void k_resid(const ProbDesc* __restrict__ pd, 
           Rd[(long long)gr * Q + q] = val;
         }
         const double other = __shfl_xor(val, 1, 64);
-        cm = fmax(cm, sqrt(val * val + other * other));
+        cm = nanmax(cm, sqrt(val * val + other * other));
       }
-    cm = fmax(cm, __shfl_xor(cm, 16, 64));
-    cm = fmax(cm, __shfl_xor(cm, 32, 64));
+    cm = nanmax(cm, __shfl_xor(cm, 16, 64));
+    cm = nanmax(cm, __shfl_xor(cm, 32, 64));
     if (lane < 16 && tcomp == 0 && q < Q)
       atomicMax(&ir.rnorm[(long long)(D.node0 + node) * kNormStride + c], (unsigned long long)__double_as_longlong(cm));
   }
@@ -309,10 +309,10 @@ __global__ __launch_bounds__(64 * WR * WQ) void k_resid_real(const ProbDesc* __r
           Rd[(long long)gr * Q + q] = val;
         }
         const double other = __shfl_xor(val, 1, 64);
-        cm = fmax(cm, sqrt(val * val + other * other));
+        cm = nanmax(cm, sqrt(val * val + other * other));
       }
-    cm = fmax(cm, __shfl_xor(cm, 16, 64));
-    cm = fmax(cm, __shfl_xor(cm, 32, 64));
+    cm = nanmax(cm, __shfl_xor(cm, 16, 64));
+    cm = nanmax(cm, __shfl_xor(cm, 32, 64));
     if (lane < 16 && tcomp == 0 && q < Q)
       atomicMax(&ir.rnorm[(long long)(D.node0 + node) * kNormStride + c], (unsigned long long)__double_as_longlong(cm));
   }
@@ -353,7 +353,10 @@ __device__ __forceinline__ bool ir_control_node(const ProbDesc* __restrict__ pd,
     const double rn = __longlong_as_double((long long)ir.rnorm[(long long)g * kNormStride + c]);
     const double yn = __longlong_as_double((long long)ir.ynorm[(long long)g * kNormStride + c]);
     const double den = fn * yn + ir.vnorm[p * 64 + c];
-    const double q = den > 0.0 ? rn / den : (rn > 0.0 ? 1e300 : 0.0);
+    // a non-finite residual, solution or scale (an overflow in the factor
+    // precision, a NaN anywhere) never counts as converged
+    const bool finite = isfinite(rn) && isfinite(yn) && isfinite(den);
+    const double q = !finite ? 1e300 : den > 0.0 ? rn / den : (rn > 0.0 ? 1e300 : 0.0);
     rho = fmax(rho, q);
     ir.rnorm[(long long)g * kNormStride + c] = 0ull;
     ir.ynorm[(long long)g * kNormStride + c] = 0ull;
@@ -410,13 +413,13 @@ hipError_t ir_control(const ProbDesc* pd, const NodeArrays& na, IrState ir, int 
 }
 
 // Per-node status for the host in one block (one copy instead of one per
-// array): rho[G] (double), then info, conv, sweeps, bad (int each), then the
-// four counters.
+// array): rho[G] and the smallest pivot modulus pmin[G] (double), then info,
+// conv, sweeps, bad (int each), then the four counters.
 __global__ void k_gather_status(IrState ir, const int* __restrict__ info, const int* __restrict__ bad, int G,
                                 char* __restrict__ out) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   double* rho = reinterpret_cast<double*>(out);
-  int* iv = reinterpret_cast<int*>(out + (size_t)G * sizeof(double));
+  int* iv = reinterpret_cast<int*>(out + 2 * (size_t)G * sizeof(double));
   if (g < G) {
     rho[g] = ir.rho[g];
     iv[g] = info[g];
@@ -427,7 +430,43 @@ __global__ void k_gather_status(IrState ir, const int* __restrict__ info, const 
   if (g < 4) iv[4 * G + g] = ir.counters[g];
 }
 
-size_t status_bytes(int G) { return (size_t)G * (sizeof(double) + 4 * sizeof(int)) + 4 * sizeof(int); }
+size_t status_bytes(int G) { return (size_t)G * (2 * sizeof(double) + 4 * sizeof(int)) + 4 * sizeof(int); }
+
+// Smallest pivot modulus |u_kk| of each node's factorization: logical row k
+// of a factor sits at the physical row rows[k], so u_kk is T[rows[k], k].
+// One group per matrix; a NaN pivot makes the minimum NaN.
+template <typename P>
+__global__ __launch_bounds__(256) void k_min_pivot(const MatDesc* __restrict__ md, const cx<P>* __restrict__ T,
+                                                   const int* __restrict__ rows, double* __restrict__ out) {
+  const MatDesc d = md[blockIdx.x];
+  double m = INFINITY;
+  for (int k = threadIdx.x; k < d.n; k += blockDim.x) {
+    const cx<P> u = T[d.offT + (long long)rows[d.offRow + k] * d.ld + k];
+    const double a = sqrt(double(u.re) * double(u.re) + double(u.im) * double(u.im));
+    m = (a < m || a != a) ? a : m;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double x = __shfl_xor(m, o, 64);
+    m = (x < m || x != x) ? x : m;
+  }
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) m = (red[w] < m || red[w] != red[w]) ? red[w] : m;
+    out[d.node] = (red[0] < m || red[0] != red[0]) ? red[0] : m;
+  }
+}
+
+template <typename P>
+hipError_t min_pivot(const MatDesc* md, int nmat, const cx<P>* T, const int* rows, int G, void* status,
+                     hipStream_t st) {
+  double* out = reinterpret_cast<double*>(static_cast<char*>(status) + (size_t)G * sizeof(double));
+  hipLaunchKernelGGL(k_min_pivot<P>, dim3(nmat), dim3(256), 0, st, md, T, rows, out);
+  return hipGetLastError();
+}
+template hipError_t min_pivot<float>(const MatDesc*, int, const c64*, const int*, int, void*, hipStream_t);
+template hipError_t min_pivot<double>(const MatDesc*, int, const c128*, const int*, int, void*, hipStream_t);
 
 hipError_t gather_status(IrState ir, const int* info, const int* bad, int G, void* out, hipStream_t st) {
   hipLaunchKernelGGL(k_gather_status, dim3(ceil_div(std::max(G, 4), 256)), dim3(256), 0, st, ir, info, bad, G,

@@ -7,10 +7,12 @@
 // budget and the in-flight limit allow, and runs their moments as one ragged
 // batch (one plan over every (query, node) pair) on that slot's stream.
 // New arrivals join the next free slot while earlier batches still run:
-// continuous batching.  When a slot's batch completes, the thread reads the
-// per-query status, runs the extraction of each query and copies the results
-// to the caller's host arrays.  Workspaces come from one device arena of the
-// budget's size, so recycling them never synchronizes the device.
+// continuous batching.  Each slot has a completion worker thread: it waits
+// for the slot's batch, reads the per-query status, runs the extraction of
+// each query and copies the results to the caller's host arrays, while the
+// dispatch thread keeps feeding the other slots.  Workspaces (plans, probes,
+// moments, and each slot's extraction workspace) come from one device arena
+// of the budget's size, so recycling them never synchronizes the device.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -56,8 +58,11 @@ struct Slot {
   std::unique_ptr<MomentsPlan> plan;
   std::vector<QueryPtr> q;
   std::vector<std::unique_ptr<QueryBuffers>> buf;
+  std::shared_ptr<ExtractWork> xw;  // extraction workspace (arena blocks)
   size_t bytes = 0;
-  bool busy = false;
+  bool busy = false;     // a batch is on the device or being completed
+  bool running = false;  // handed to the completion worker
+  std::thread worker;
 };
 
 bool same_batch(const Query& a, const Query& b) {
@@ -81,6 +86,7 @@ class Server {
 
  private:
   void loop();
+  void work(Slot& s);                    // completion worker of a slot
   bool dispatch(Slot& s);                // true if a batch was started
   void complete(Slot& s);                // the slot's batch has finished
   void fail(std::vector<QueryPtr>& qs, nep_status st);
@@ -92,7 +98,7 @@ class Server {
   int max_inflight_ = 1, inflight_ = 0, batch_cap_ = 1;
   std::vector<Slot> slots_;
   std::mutex mu_;
-  std::condition_variable cv_work_, cv_done_;
+  std::condition_variable cv_work_, cv_done_, cv_slot_;
   std::deque<QueryPtr> queue_;
   std::unordered_map<long long, QueryPtr> tickets_;
   long long next_ticket_ = 1;
@@ -127,6 +133,11 @@ nep_status Server::init(const nep_server_opts* o) {
   for (auto& s : slots_) {
     NEP_HIP(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
     NEP_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+    s.xw = make_extract_work();
+  }
+  for (auto& s : slots_) {
+    Slot* sp = &s;
+    s.worker = std::thread([this, sp] { work(*sp); });
   }
   th_ = std::thread([this] { loop(); });
   started_ = true;
@@ -191,10 +202,17 @@ void Server::shutdown() {
       stop_ = true;
     }
     cv_work_.notify_all();
-    th_.join();
+    th_.join();  // returns once the queue is drained and no slot is busy
+    cv_slot_.notify_all();
+    for (auto& s : slots_)
+      if (s.worker.joinable()) s.worker.join();
     started_ = false;
   }
   for (auto& s : slots_) {
+    {
+      ArenaScope scope(&arena_);  // the workspace's blocks go back to the arena
+      s.xw.reset();
+    }
     if (s.ev) (void)hipEventDestroy(s.ev);
     if (s.st) (void)hipStreamDestroy(s.st);
     s.ev = nullptr;
@@ -233,7 +251,10 @@ bool Server::dispatch(Slot& s) {
       batch.push_back(*it);
       it = queue_.erase(it);
     }
-    if (batch.empty()) return false;
+    if (batch.empty()) {  // the oldest query waits for a completion to free room
+      arena_full_ = true;
+      return false;
+    }
     inflight_ += (int)batch.size();
     inflight_bytes_ += bytes;
     const double t = clock();
@@ -270,16 +291,17 @@ bool Server::dispatch(Slot& s) {
     (void)hipStreamSynchronize(s.st);
     s.plan.reset();
     s.buf.clear();
+    std::unique_lock<std::mutex> lk(mu_);
     bool others_busy = false;
     for (auto& o : slots_) others_busy |= o.busy;
     if (others_busy) {
-      std::lock_guard<std::mutex> lk(mu_);
       for (auto it = batch.rbegin(); it != batch.rend(); ++it) queue_.push_front(*it);
       inflight_ -= (int)batch.size();
       inflight_bytes_ -= bytes;
       arena_full_ = true;
       return false;
     }
+    lk.unlock();
   }
   if (st != NEP_OK) {
     (void)hipStreamSynchronize(s.st);
@@ -291,7 +313,12 @@ bool Server::dispatch(Slot& s) {
   for (auto& q : batch) std::vector<c128>().swap(q->V);  // the device holds the probes now
   s.q = std::move(batch);
   s.bytes = bytes;
-  s.busy = true;
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    s.busy = true;
+    s.running = true;
+  }
+  cv_slot_.notify_all();
   return true;
 }
 
@@ -306,8 +333,11 @@ void Server::complete(Slot& s) {
     if (st == NEP_OK) {
       nep_ciss_opts o = q.o;
       o.stream = s.st;
-      ArenaScope off(nullptr);  // extraction workspaces belong to the handle
-      st = nep_extract(q.h, &q.g, &o, s.buf[k]->S.p, &q.e, &m, q.lambda, s.buf[k]->X.p, q.eta, q.inside, nullptr);
+      // the slot's own workspace, from the arena: no device allocation or
+      // free here, and no state of the handle is touched, so slots complete
+      // queries of the same operator concurrently
+      st = extract(q.h->impl, &q.g, &o, s.buf[k]->S.p, &q.e, &m, q.lambda, s.buf[k]->X.p, q.eta, q.inside, nullptr,
+                   s.xw.get());
       if (st == NEP_OK && q.X != nullptr && m > 0) {
         if (hipMemcpyAsync(q.X, s.buf[k]->X.p, sizeof(c128) * (size_t)q.n * m, hipMemcpyDeviceToHost, s.st) !=
                 hipSuccess ||
@@ -339,7 +369,39 @@ void Server::complete(Slot& s) {
   cv_done_.notify_all();
   s.q.clear();
   s.bytes = 0;
-  s.busy = false;
+}
+
+// Completion worker of a slot: waits (on this thread only) for the slot's
+// batch, completes it, and hands the slot back to the dispatch thread.
+void Server::work(Slot& s) {
+  (void)hipSetDevice(device_);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      cv_slot_.wait(lk, [&] { return s.running || (stop_ && !s.busy); });
+      if (!s.running) return;
+    }
+    const hipError_t e = hipEventSynchronize(s.ev);
+    if (e == hipSuccess) {
+      complete(s);
+    } else {
+      (void)hipGetLastError();
+      std::vector<QueryPtr> qs = std::move(s.q);
+      {
+        ArenaScope scope(&arena_);
+        s.plan.reset();
+        s.buf.clear();
+      }
+      s.bytes = 0;
+      fail(qs, NEP_ERR_DEVICE);
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      s.running = false;
+      s.busy = false;
+    }
+    cv_work_.notify_all();
+  }
 }
 
 void Server::loop() {
@@ -347,34 +409,31 @@ void Server::loop() {
   for (;;) {
     bool progress = false;
     for (auto& s : slots_) {
-      if (s.busy) {
-        const hipError_t e = hipEventQuery(s.ev);
-        if (e == hipSuccess) {
-          complete(s);
-          progress = true;
-        } else if (e != hipErrorNotReady) {
-          (void)hipGetLastError();
-          std::vector<QueryPtr> qs = std::move(s.q);
-          s.plan.reset();
-          s.buf.clear();
-          s.busy = false;
-          s.bytes = 0;
-          fail(qs, NEP_ERR_DEVICE);
-          progress = true;
-        }
+      bool free_slot;
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        free_slot = !s.busy;
       }
-      if (!s.busy && dispatch(s)) progress = true;
+      if (free_slot && dispatch(s)) progress = true;
     }
     if (progress) continue;
     std::unique_lock<std::mutex> lk(mu_);
     bool busy = false;
     for (auto& s : slots_) busy |= s.busy;
     if (stop_ && queue_.empty() && !busy) break;
-    if (busy)
-      cv_work_.wait_for(lk, std::chrono::microseconds(100));
-    else if (queue_.empty() || arena_full_)
-      cv_work_.wait(lk, [&] { return stop_ || (!queue_.empty() && !arena_full_); });
-    if (!busy && arena_full_) arena_full_ = false;  // nothing left to wait for
+    // wake on a submission or a completion (a slot freed, room back)
+    cv_work_.wait(lk, [&] {
+      bool free_now = false, busy_now = false;
+      for (auto& s : slots_) {
+        free_now |= !s.busy;
+        busy_now |= s.busy;
+      }
+      return (free_now && !queue_.empty() && !arena_full_) || (stop_ && queue_.empty() && !busy_now) ||
+             (!busy_now && arena_full_);
+    });
+    bool busy_now = false;
+    for (auto& s : slots_) busy_now |= s.busy;
+    if (!busy_now && arena_full_) arena_full_ = false;  // nothing left to wait for
   }
 }
 

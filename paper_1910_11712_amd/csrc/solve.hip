@@ -316,7 +316,7 @@ __global__ __launch_bounds__(NT) void k_trsv(const MatDesc* __restrict__ md, int
           c128 nv = {double(acc[i][c].re), double(acc[i][c].im)};
           if (refine) nv = y[c] + nv;
           y[c] = nv;
-          ymax[c] = fmax(ymax[c], sqrt(norm2(nv)));
+          ymax[c] = nanmax(ymax[c], sqrt(norm2(nv)));
         }
       }
     }
@@ -325,13 +325,13 @@ __global__ __launch_bounds__(NT) void k_trsv(const MatDesc* __restrict__ md, int
 #pragma unroll
   for (int c = 0; c < LG; ++c) {
     double m = ymax[c];
-    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    for (int o = 32; o >= 1; o >>= 1) m = nanmax(m, __shfl_xor(m, o, 64));
     if (lane == 0) cmax[wave][c] = m;
   }
   __syncthreads();
   if (tid < nc) {
     double m = 0.0;
-    for (int w = 0; w < NT / 64; ++w) m = fmax(m, cmax[w][tid]);
+    for (int w = 0; w < NT / 64; ++w) m = nanmax(m, cmax[w][tid]);
     atomicMax(&ir.ynorm[(long long)g * kNormStride + c0 + tid], (unsigned long long)__double_as_longlong(m));
   }
 }
