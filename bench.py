@@ -1,13 +1,17 @@
 """Benchmark of the contour-integral moment path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg1|cfg2|cfg0|cfg3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg1|cfg0|cfg3|cfg4]
 
 A step is one pass of the moment stage over the workload's problem: f_i at
 the nodes, assembly of T(z_j) for every node, batched complex LU, solves with
 the probe block, FP64 refinement, and the moments S_p.  Inputs (A_i, V) are
-resident in HBM before the timed region.  The eigenpair extraction of the
-config-2 workload (moments + block-Hankel SVD + eigenpairs + backward errors)
-is timed separately and reported under "extra".
+resident in HBM before the timed region.  The default workload is the
+square-root problem at n=4096 (N=64, L=32, K=2), the largest configuration
+that fits one GPU and the one whose eigenpairs the method resolves; its
+end-to-end eigenpair rate (moments + block-Hankel SVD + eigenpairs +
+backward errors) and the error of every result against the FP64 oracle's
+stored values go under "extra", beside the delay (n=1000), 256-problem batch
+and serving workloads.
 
 Launch shapes are chosen by the library's autotuner (nep_tune_set) when each
 plan is built, in the untimed warm-up; the timed steps run the chosen shapes
@@ -71,12 +75,14 @@ def _time_moments(P, op, cfg, Vd, S, prec, steps, warmup, prof=False):
     return max(ms_dev / 1e3, wall) / steps, stats, prof_out
 
 
-def _gemm_traffic():
-    """HBM bytes per launch of the trailing-update GEMM, as recorded from
-    rocprofv3 FETCH_SIZE/WRITE_SIZE counters (copy-calibrated) in profiles/;
-    None if the kernel source changed since the counters were taken."""
+def _gemm_traffic(workload):
+    """HBM bytes per launch of the trailing-update GEMM on this workload, as
+    recorded from rocprofv3 FETCH_SIZE/WRITE_SIZE counters (copy-calibrated)
+    in profiles/; None if there is no record or the kernel source changed
+    since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "lu_gemm_c64_delay_n1000_pmc.txt")
+    name = {"cfg1": "delay_n1000", "cfg2": "sqrt_n4096"}.get(workload, workload)
+    path = os.path.join(ROOT, "profiles", f"lu_gemm_c64_{name}_pmc.txt")
     src = os.path.join(ROOT, "paper_1910_11712_amd", "csrc", "lu.hip")
     try:
         rec = dict(l.split(":", 1) for l in open(path) if not l.startswith("#") and ":" in l)
@@ -88,14 +94,17 @@ def _gemm_traffic():
         return None
 
 
-def _cpu_baseline(cfg, budget_s=20.0):
-    """The oracle (numpy/LAPACK FP64) on a bounded sample of nodes."""
+def _cpu_baseline(cfg, budget_s=20.0, one_core=True):
+    """The oracle (numpy/LAPACK FP64) on a bounded sample of nodes: as many
+    node solves as fit in budget_s on every host core, then (one_core) one
+    node solve limited to a single thread."""
     import oracle
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         info = threadpool_info()
         cores = max([d.get("num_threads", 1) for d in info] or [os.cpu_count() or 1])
     except Exception:
+        threadpool_limits = None
         cores = os.cpu_count() or 1
     p, con, V = cfg["problem"], cfg["contour"], cfg["V"]
     t0 = time.perf_counter()
@@ -108,15 +117,60 @@ def _cpu_baseline(cfg, budget_s=20.0):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "quadrature solves/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{done} node solves (assemble + FP64 LU solve with {cfg['L']} probes) of {cfg['name']}, "
-                      f"{dt:.1f} s"}
+    out = {"value": done / dt, "unit": "quadrature solves/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"{done} node solves (assemble + FP64 LU solve with {cfg['L']} probes) of {cfg['name']}, "
+                     f"{dt:.1f} s on {cores} threads"}
+    if one_core and threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            oracle.node_solve(p, con, cfg["N"], 1, V)
+            d1 = time.perf_counter() - t1
+        out["one_core"] = {"value": 1.0 / d1, "unit": "quadrature solves/s", "cores": 1,
+                           "sample": f"1 node solve, {d1:.1f} s"}
+    return out
+
+
+def _golden(name):
+    """Oracle values stored by tests/golden/make_oracle_golden.py (written by
+    the FP64 oracle alone), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    return np.load(path, allow_pickle=False)
+
+
+def _errors_vs_oracle(g, con, Sg, r):
+    """Error of every result against the oracle's stored values: moments
+    element by element at the sampled rows (relative to each column's scale)
+    and |dl|/|l| of every eigenvalue inside the contour."""
+    q = Sg.shape[0]
+    e_s = max(float((np.abs(Sg[k][g["rows"]] - g["S_rows"][k]) / g["S_colmax"][k][None, :]).max())
+              for k in range(q))
+
+    def inside(lam):
+        mu = (np.asarray(lam) - con.c) / con.rho
+        rr = np.abs(mu) if con.kind == 0 else np.sqrt(mu.real ** 2 + (mu.imag / con.v) ** 2)
+        return (rr < 1.0) & (np.abs(rr - 1.0) > 1e-6)
+
+    ref = list(g["lam"][inside(g["lam"])])
+    got = list(r["lam"][inside(r["lam"])])
+    errs = []
+    for l in ref:
+        if not got:
+            errs.append(None)
+            continue
+        k = int(np.argmin([abs(x - l) for x in got]))
+        errs.append(float(abs(got[k] - l) / abs(l)))
+        got.pop(k)
+    return {"moments_max_elem_rel": e_s, "eigs_oracle": len(ref), "eigs_found": int(inside(r["lam"]).sum()),
+            "eig_rel_err": errs, "eig_rel_err_max": max((e for e in errs if e is not None), default=None)}
 
 
 def _eigs_run(P, steps=3, tune=True):
-    """Config 2 end to end: moments + extraction, eigenpairs/s at eta <= 1e-10
-    (each precision's plan is built, and its launch shapes tuned, in the
-    untimed first call)."""
+    """Square-root workload (n=4096) end to end: moments + extraction,
+    eigenpairs/s at eta <= 1e-10, and the error of every result against the
+    oracle (each precision's plan is built, and its launch shapes tuned, in
+    the untimed first call)."""
     import torch
     import workloads as wl
     cfg = wl.config2()
@@ -124,6 +178,7 @@ def _eigs_run(P, steps=3, tune=True):
     Vd = P.device_probes(cfg["V"])
     S = torch.empty((2 * cfg["K"], cfg["L"], cfg["problem"].n), dtype=torch.complex128, device="cuda")
     X = torch.zeros((64, cfg["problem"].n), dtype=torch.complex128, device="cuda")
+    g = _golden(cfg["name"])
     out = {}
     for prec in ("mixed", "fp64"):
         P.binding.nep_tune_set(tune, 2)
@@ -138,11 +193,14 @@ def _eigs_run(P, steps=3, tune=True):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         good = int(np.sum(r["inside"] & (r["eta"] <= 1e-10)))
-        out[prec] = {"s_per_step": dt, "quadrature_solves_per_s": cfg["N"] / dt, "eigenpairs_inside": int(r["inside"].sum()),
+        out[prec] = {"s_per_step": dt, "quadrature_solves_per_s": cfg["N"] / dt,
+                     "eigenpairs_inside": int(r["inside"].sum()),
                      "eigenpairs_eta_le_1e-10": good, "eigenpairs_per_s": good / dt,
                      "max_eta_inside": float(np.max(r["eta"][r["inside"]])) if r["inside"].any() else None,
                      "rank": int(r["m"]), "refine_sweeps": st["refine_sweeps"], "n_fallback": st["n_fallback"],
-                     "tuning": tuned}
+                     "max_rel_residual": st["max_rel_residual"], "tuning": tuned}
+        if g is not None:
+            out[prec]["vs_oracle"] = _errors_vs_oracle(g, cfg["contour"], P.moments_to_numpy(S), r)
     op.close()
     return out
 
@@ -183,6 +241,7 @@ def _batch_run(P, steps=5, tune=True):
     e0.record(st)
     for _ in range(steps):
         B.nep_batch_run(b)
+        B.nep_batch_wait(b)  # reads back status; FP64 re-solve of any node left above the tolerance
     e1.record(st)
     torch.cuda.synchronize()
     dt = max(e0.elapsed_time(e1) / 1e3, time.perf_counter() - t0) / steps
@@ -234,15 +293,25 @@ def _serve_run(P, prec, rate=200.0, duration=2.0, warmup=0.5):
             "status_counts": {P.binding.ERRORS.get(k, "NEP_OK"): v for k, v in codes.items()}}
 
 
+def _serve_full(P, rate, duration, warmup):
+    out = {}
+    for prec in ("mixed", "fp64"):
+        out[prec] = _serve_run(P, prec, rate=rate, duration=duration, warmup=warmup)
+        print(f"[bench] serving {prec} {rate} q/s done", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg1")
+    ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="built-in launch shapes (no autotuning)")
+    ap.add_argument("--rate", type=float, default=200.0, help="cfg4: offered queries/s")
+    ap.add_argument("--window", type=float, default=60.0, help="cfg4: measured seconds after the warm-up")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -268,6 +337,9 @@ def main():
     if args.workload == "cfg3":  # the 256-problem batch alone (graph replay), one JSON line
         print(json.dumps({"workload": "cfg3_batch_graph", **_batch_run(P, steps=args.steps, tune=not args.no_tune)}))
         return
+    if args.workload == "cfg4":  # the serving stream alone, both precisions, one JSON line
+        print(json.dumps({"workload": "cfg4_serving", **_serve_full(P, args.rate, args.window, 5.0)}))
+        return
     cfg = _workload(args.workload)
     prob = cfg["problem"]
     op = P.SplitOperator.from_problem(prob)
@@ -281,34 +353,48 @@ def main():
     t_fp64, st_fp64, prof64 = _time_moments(P, op, cfg, Vd, S, "fp64", max(2, args.steps // 2), 1, prof=True)
     tune_fp64 = _tune_summary(P.binding)
     P.binding.nep_tune_set(False, 3)
+    print(f"[bench] {cfg['name']} moments timed", file=sys.stderr, flush=True)
     N = cfg["N"]
     value = N / t_mixed
+    n = prob.n
+    lu_flops = N * (8.0 / 3.0) * n ** 3
 
     launches, ms, flops = prof
     achieved = flops / (ms / 1e3) / 1e12 if ms > 0 else 0.0
-    roof = {"kernel": "k_lu_gemm_c64 (trailing update, v_mfma_f32_32x32x2f32)", "bound": "mfma",
+    lu_ms = st_mixed.get("ms_lu", 0.0)
+    roof = {"kernel": "k_lu_gemm_c64<0> (LU trailing update, v_mfma_f32_32x32x2f32)", "bound": "mfma",
             "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": _gemm_traffic(),
+            "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": _gemm_traffic(args.workload),
             "launches_per_step": launches // max(1, args.steps),
             "avg_launch_ms": round(ms / max(1, launches), 5),
-            "flops_per_launch": flops / max(1, launches)}
-    n = prob.n
-    lu_flops = N * (8.0 / 3.0) * n ** 3
+            "flops_per_launch": flops / max(1, launches),
+            "lu_span": {"ms": round(lu_ms, 3),
+                        "tflops_effective": round(lu_flops / (lu_ms / 1e3) / 1e12, 3) if lu_ms > 0 else None,
+                        "frac": round(lu_flops / (lu_ms / 1e3) / 1e12 / PEAK_FP32_MFMA, 4) if lu_ms > 0 else None},
+            "step_frac": round(lu_flops / t_mixed / 1e12 / PEAK_FP32_MFMA, 4)}
     extra = {
         "mixed": {"ms_per_step": t_mixed * 1e3, "refine_sweeps": st_mixed["refine_sweeps"],
                   "n_fallback": st_mixed["n_fallback"], "max_rel_residual": st_mixed["max_rel_residual"],
+                  "min_abs_pivot": st_mixed["min_abs_pivot"], "ms_lu": st_mixed["ms_lu"],
                   "lu_tflops_effective": lu_flops / t_mixed / 1e12, "tuning": tune_mixed},
         "fp64": {"ms_per_step": t_fp64 * 1e3, "quadrature_solves_per_s": N / t_fp64,
-                 "lu_tflops_effective": lu_flops / t_fp64 / 1e12,
+                 "lu_tflops_effective": lu_flops / t_fp64 / 1e12, "ms_lu": st_fp64["ms_lu"],
                  "gemm_tflops": (prof64[2] / (prof64[1] / 1e3) / 1e12) if prof64[1] > 0 else None,
                  "tuning": tune_fp64},
         "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
     }
+    op.close()
+    del S
     if not args.no_extra:
-        for key, fn in (("cfg2_end_to_end", lambda: _eigs_run(P, tune=not args.no_tune)),
-                        ("cfg3_batch_graph", lambda: _batch_run(P, tune=not args.no_tune)),
-                        ("cfg4_serving_mixed", lambda: _serve_run(P, "mixed")),
-                        ("cfg4_serving_fp64", lambda: _serve_run(P, "fp64"))):
+        jobs = []
+        if args.workload == "cfg2":
+            jobs.append(("cfg2_end_to_end", lambda: _eigs_run(P, tune=not args.no_tune)))
+        if args.workload != "cfg1":
+            jobs.append(("cfg1_delay_n1000", lambda: _cfg1_run(P, args, tune=not args.no_tune)))
+        jobs += [("cfg3_batch_graph", lambda: _batch_run(P, tune=not args.no_tune)),
+                 ("cfg4_serving_mixed", lambda: _serve_run(P, "mixed")),
+                 ("cfg4_serving_fp64", lambda: _serve_run(P, "fp64"))]
+        for key, fn in jobs:
             try:
                 extra[key] = fn()
             except Exception as e:  # reported, not hidden
@@ -322,8 +408,34 @@ def main():
             "config": {"workload": cfg["name"], "n": n, "N": N, "L": cfg["L"], "K": cfg["K"],
                        "prec": "mixed", "terms": prob.ell},
             "roofline": roof, "cpu_baseline": cpu, "extra": extra}
+    if "cfg2_end_to_end" in extra and "mixed" in extra["cfg2_end_to_end"]:
+        e2e = extra["cfg2_end_to_end"]["mixed"]
+        line["eigenpairs_per_s"] = e2e.get("eigenpairs_per_s")
     print(json.dumps(line))
+
+
+def _cfg1_run(P, args, tune=True):
+    """Delay workload (n=1000, N=64, L=16, K=16): moment passes of both
+    precisions (its eigenvalues outnumber K*L, so no eigenpairs)."""
+    import torch
+    import workloads as wl
+    cfg = wl.config1()
+    op = P.SplitOperator.from_problem(cfg["problem"])
+    Vd = P.device_probes(cfg["V"])
+    S = torch.empty((2 * cfg["K"], cfg["L"], cfg["problem"].n), dtype=torch.complex128, device="cuda")
+    P.binding.nep_tune_set(tune, 3)
+    tm, stm, prof = _time_moments(P, op, cfg, Vd, S, "mixed", 20, 3, prof=True)
+    t64, st64, _ = _time_moments(P, op, cfg, Vd, S, "fp64", 10, 2)
+    P.binding.nep_tune_set(False, 3)
     op.close()
+    lu_flops = cfg["N"] * (8.0 / 3.0) * cfg["problem"].n ** 3
+    launches, ms, flops = prof
+    return {"mixed": {"ms_per_step": tm * 1e3, "quadrature_solves_per_s": cfg["N"] / tm,
+                      "ms_lu": stm["ms_lu"], "lu_tflops_effective": lu_flops / tm / 1e12,
+                      "refine_sweeps": stm["refine_sweeps"], "max_rel_residual": stm["max_rel_residual"],
+                      "gemm_tflops": flops / (ms / 1e3) / 1e12 if ms > 0 else None},
+            "fp64": {"ms_per_step": t64 * 1e3, "quadrature_solves_per_s": cfg["N"] / t64, "ms_lu": st64["ms_lu"]},
+            "speedup_mixed_vs_fp64": t64 / tm}
 
 
 if __name__ == "__main__":

@@ -17,6 +17,7 @@ import scipy.special
 
 import oracle
 import workloads as wl
+from closed_forms import string_secular_roots
 from workloads import Contour, Problem
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -298,43 +299,10 @@ def test_scalar_sqrt_closed_form():
     _match(r["lam"][r["inside"]], lam, 1e-10)
 
 
-def _string_secular_roots(n, sigma, lo, hi):
-    """P7: eigenvalues of A - l B + l/(l-sigma) e_n e_n^T from the secular
-    equation 1 + (l/(l-sigma)) sum_k c_k/(a_k - l b_k) = 0 in the sine basis."""
-    k = np.arange(1, n + 1)
-    th = k * np.pi / (n + 1)
-    ak = 2.0 * n * (1 - np.cos(th))
-    bk = (4 + 2 * np.cos(th)) / (6.0 * n)
-    ck = 2.0 / (n + 1) * np.sin(n * th) ** 2
-
-    def h(l):
-        return 1.0 + l / (l - sigma) * np.sum(ck / (ak - l * bk))
-
-    poles = np.sort(np.concatenate([[sigma], ak / bk]))
-    poles = poles[(poles > lo - 1e3) & (poles < hi + 1e3)]
-    roots = []
-    for p0, p1 in zip(poles[:-1], poles[1:]):
-        eps = 1e-9 * (p1 - p0)
-        xs = np.linspace(p0 + eps, p1 - eps, 4001)
-        hs = np.array([h(x) for x in xs])
-        for i in np.nonzero(np.sign(hs[:-1]) != np.sign(hs[1:]))[0]:
-            x0, x1 = xs[i], xs[i + 1]
-            for _ in range(200):
-                xm = 0.5 * (x0 + x1)
-                if np.sign(h(xm)) == np.sign(h(x0)):
-                    x0 = xm
-                else:
-                    x1 = xm
-                if x1 - x0 <= 4 * np.finfo(float).eps * abs(xm):
-                    break
-            roots.append(0.5 * (x0 + x1))
-    return np.array([r for r in roots if lo < r < hi])
-
-
 def test_config0_secular_equation():
     """P7: config 0 inside eigenvalues equal the secular-equation roots."""
     cfg = wl.config0()
-    roots = _string_secular_roots(200, 1.0, 10.0, 190.0)
+    roots = string_secular_roots(200, 1.0, 10.0, 190.0)
     assert len(roots) == 3
     S = oracle.ciss_moments(cfg["problem"], cfg["contour"], cfg["N"], cfg["K"], cfg["V"])
     r = oracle.extract(cfg["problem"], cfg["contour"], S, cfg["K"])
@@ -342,6 +310,54 @@ def test_config0_secular_equation():
     _match(got, roots, 1e-12)
     assert np.all(np.abs(got.imag) < 1e-9)          # real eigenvalues (Section 6)
     assert np.all(r["eta"][r["inside"]] < 1e-13)
+
+
+def test_secular_roots_scaled_string_vs_linearization():
+    """The scaled-string secular roots (A scale s != 1, sigma != 1, as in the
+    256-problem batch) equal the eigenvalues of the quadratic
+    (l - sigma)(sA - l B) + l C = 0, computed by SciPy's dense generalized
+    eig of its companion linearization (a third-party routine), and the
+    oracle's extraction inside circle(100, 90)."""
+    n, sigma, s = 64, 1.3, 0.7
+    p = wl.loaded_string(n, sigma=sigma, a_scale=s)
+    A, B, Cm = p.mats
+    # -B l^2 + (A + sigma B + C) l - sigma A = 0  ->  first companion form
+    M0, M1, M2 = -sigma * A, A + sigma * B + Cm, -B
+    Z, I = np.zeros((n, n)), np.eye(n)
+    lin_A = np.block([[Z, I], [-M0, -M1]])
+    lin_B = np.block([[I, Z], [Z, M2]])
+    ev = scipy.linalg.eigvals(lin_A, lin_B)
+    # multiplying by (l - sigma) adds sigma with multiplicity n - 1 (Q(sigma) =
+    # sigma C has rank one); those are not eigenvalues of T
+    ev = ev[np.isfinite(ev) & (np.abs(ev - sigma) > 1e-6)]
+    assert np.all(np.abs(ev.imag) < 1e-8 * np.abs(ev))
+    ev = np.sort(ev.real)
+    roots = string_secular_roots(n, sigma, 0.0, 400.0, a_scale=s)
+    ref = ev[(ev > 0.0) & (ev < 400.0)]
+    assert len(roots) == len(ref) >= 4
+    assert np.max(np.abs(roots - ref) / ref) < 1e-9
+    con = Contour.circle(100.0, 90.0)
+    S = oracle.ciss_moments(p, con, 32, 2, wl.probes(n, 8, 3))
+    r = oracle.extract(p, con, S, 2)
+    _match(r["lam"][r["inside"]], roots[(roots > 10.0) & (roots < 190.0)], 1e-10)
+
+
+def test_node_solve_diagonal_closed_form():
+    """oracle.node_solve at a diagonal linear problem T(z) = diag(d) - z I:
+    Y_j = V / (d - z_j) row by row, with z_j the half-offset trapezoid node
+    c + rho e^{i 2 pi (j + 1/2)/N}; and it equals the node solve inside the
+    moment loop."""
+    d = np.array([0.3 + 0.1j, -0.5, 2.0j, 4.0])
+    prob = _diag_linear(d)
+    con = Contour.circle(0.2 - 0.1j, 1.3)
+    N = 12
+    V = wl.probes(4, 3, 11)
+    _, Ys = oracle.ciss_moments(prob, con, N, 1, V, return_y=True)
+    for j in (0, 5, 11):
+        z = con.c + con.rho * np.exp(2j * np.pi * (j + 0.5) / N)
+        Y = oracle.node_solve(prob, con, N, j, V)
+        np.testing.assert_allclose(Y, V / (d - z)[:, None], rtol=1e-14, atol=0)
+        assert np.array_equal(Y, Ys[j])
 
 
 def test_config0_invariants():

@@ -103,6 +103,42 @@ def test_server_query_errors_are_isolated(nep):
     assert np.array_equal(r1["lam"], r3["lam"])
 
 
+def test_server_fallback_unaffected_by_failing_neighbour(nep):
+    """A query whose nodes need the FP64 re-solve (loaded string n=1912 at a
+    serving contour, kappa(T(z)) ~ 1e6) batched with a query whose contour
+    crosses a branch cut: the cut query fails alone, and the other is
+    re-solved exactly as when it runs alone (same bits)."""
+    from workloads.problems import _string_pencil_value
+    n, sig, s = 1912, 1.4132774252668214, 1.5572971183471138
+    prob = wl.loaded_string(n, sigma=sig, a_scale=s)
+    lam = [_string_pencil_value(n, j, s) for j in (2, 3, 4)]
+    con = Contour.circle(lam[1], 0.5 * min(lam[1] - lam[0], lam[2] - lam[1]))
+    N, L, K = 32, 8, 2
+    V = wl.probes(n, L, 330947230)
+    op = nep.SplitOperator.from_problem(prob)
+    alone = _alone(nep, op, con, V, N, L, K, "mixed", 16)
+    f = wl.fn_combine(wl.COMB_COMPOSE, wl.fn_rational([-1.0]), wl.fn_sqrt())  # sqrt(-1): on the cut everywhere
+    op_b = nep.SplitOperator.from_problem(Problem("cut", [np.eye(8), np.eye(8)], [wl.fn_rational([1.0]), f]))
+    srv = nep.Server(hbm_budget=8 << 30, max_inflight=8, nstreams=1)
+    try:
+        # the first query holds the only slot while the next two queue, so
+        # those two are dispatched together as one batch
+        t_first = srv.submit(op, con, V, N, L, K, max_eigs=16, want_X=True)
+        t_bad = srv.submit(op_b, Contour.circle(0.0, 1.0), wl.probes(8, 8, 0), N, L, K, max_eigs=16)
+        t_good = srv.submit(op, con, V, N, L, K, max_eigs=16, want_X=True)
+        r_first, r_bad, r_good = srv.wait(t_first), srv.wait(t_bad), srv.wait(t_good)
+    finally:
+        srv.close()
+    assert nep.binding.ERRORS[r_bad["status"]] == "NEP_ERR_NOT_HOLOMORPHIC"
+    assert r_bad["t_start"] == r_good["t_start"]  # one batch
+    for r in (r_first, r_good):
+        assert r["status"] == 0, nep.binding.ERRORS.get(r["status"])
+        assert r["m"] == alone["m"]
+        assert np.array_equal(r["lam"], alone["lam"])
+        assert np.array_equal(r["eta"], alone["eta"])
+        assert np.array_equal(r["X"], alone["X"])
+
+
 def test_server_budget(nep):
     """A query larger than the whole budget is refused at submit; a budget
     that holds one query at a time still serves every query."""
