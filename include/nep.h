@@ -242,6 +242,23 @@ nep_status nep_extract(nep_split h, const nep_contour* g, const nep_ciss_opts* o
 nep_status nep_backward_error(nep_split h, int m, const double* lambda,
                               const void* X, double* eta);
 
+/* nep_backward_error for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and results, with every device buffer it
+ * needs (function values, the n x m residual block, column maxima, term
+ * tables) in one library-owned scratch array of 4.125 MiB per GPU, held from
+ * the first call on that GPU until the process ends.  It calls no hipMalloc,
+ * hipFree or other allocating routine.
+ *   Limits: m <= 256 and n*m <= 262144; larger requests return NEP_ERR_ARG
+ *   before any device work.
+ *   Every call on a GPU uses that GPU's one scratch array, so calls that
+ *   overlap on one GPU (from several host threads, or on several streams
+ *   before the earlier call returned) race; calls are synchronous and each
+ *   overwrites everything it reads, so sequential calls are independent.
+ *   Runs on the handle's stream. */
+nep_status nep_backward_error_noalloc(nep_split h, int m, const double* lambda,
+                                      const void* X, double* eta);
+
 /* Values f_i(z) for ell functions at m host points (complex): out[i*m + k]
  * (host, ell*m complex).  Points on a pole or cut give NEP_ERR_NOT_HOLOMORPHIC. */
 nep_status nep_fn_eval(nep_split h, int m, const double* z, double* out);

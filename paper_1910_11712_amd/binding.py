@@ -122,6 +122,7 @@ def lib():
                                   C.POINTER(nep_extract_opts), C.POINTER(ip), C.POINTER(C.c_double), vp,
                                   C.POINTER(C.c_double), C.POINTER(ip), C.POINTER(C.c_double)]
         L.nep_backward_error.argtypes = [vp, ip, C.POINTER(C.c_double), vp, C.POINTER(C.c_double)]
+        L.nep_backward_error_noalloc.argtypes = [vp, ip, C.POINTER(C.c_double), vp, C.POINTER(C.c_double)]
         L.nep_fn_eval.argtypes = [vp, ip, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.nep_batch_create.argtypes = [ip, C.POINTER(vp), C.POINTER(nep_contour), C.POINTER(nep_ciss_opts),
                                        C.POINTER(vp), C.POINTER(vp), ip, vp, C.POINTER(vp)]
@@ -301,6 +302,18 @@ def nep_backward_error(h, lam, X):
     eta = np.zeros(m)
     check(lib().nep_backward_error(h, m, la.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(X.data_ptr()),
                                    eta.ctypes.data_as(C.POINTER(C.c_double))))
+    return eta
+
+
+def nep_backward_error_noalloc(h, lam, X):
+    """As nep_backward_error, with the library's fixed device scratch."""
+    lam = np.asarray(lam, dtype=np.complex128)
+    m = len(lam)
+    la = np.zeros(2 * m)
+    la[0::2], la[1::2] = lam.real, lam.imag
+    eta = np.zeros(m)
+    check(lib().nep_backward_error_noalloc(h, m, la.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(X.data_ptr()),
+                                           eta.ctypes.data_as(C.POINTER(C.c_double))))
     return eta
 
 

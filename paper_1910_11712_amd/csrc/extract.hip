@@ -16,6 +16,7 @@
 // of the paper's solvers, Section 5).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <numeric>
 
 #include "dense.hpp"
@@ -262,57 +263,152 @@ static nep_status grow(DevMem& m, size_t bytes) {
 hipError_t fn_points(const FnNode* nodes, const c128* coef, const int* roots, int ell, const c128* z, int m,
                      c128* out, int* bad, hipStream_t st);
 
-static nep_status backward_errors(Split& h, int m, const std::vector<zc>& lam, const c128* X, std::vector<double>& eta,
-                                  ExtractWork& w, hipStream_t st) {
+// Device buffers of one backward-error evaluation of m pairs.
+struct EtaBuffers {
+  c128* z;            // m points
+  c128* fv;           // f_i(lambda_q) at [i*m + q]
+  int* bad;           // m flags: lambda_q on a pole or cut
+  c128* Rt;           // n x m residuals T(lambda_q) x_q
+  double* norms;      // 2m: max |Rt[:, q]|, max |X[:, q]|
+  const double** dA;  // kMaxTerms term pointers
+  int* dcp;           // kMaxTerms complex-term flags
+};
+
+static size_t eta_small_bytes(int m, int ell) {  // everything but Rt, each part 256-byte aligned
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  return up(sizeof(c128) * m) + up(sizeof(c128) * (size_t)m * ell) + up(sizeof(int) * m) + up(sizeof(double) * 2 * m) +
+         up(sizeof(void*) * kMaxTerms) + up(sizeof(int) * kMaxTerms);
+}
+
+static EtaBuffers eta_carve(char* small, c128* Rt, int m, int ell) {
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  EtaBuffers b;
+  b.z = reinterpret_cast<c128*>(small);
+  small += up(sizeof(c128) * m);
+  b.fv = reinterpret_cast<c128*>(small);
+  small += up(sizeof(c128) * (size_t)m * ell);
+  b.bad = reinterpret_cast<int*>(small);
+  small += up(sizeof(int) * m);
+  b.norms = reinterpret_cast<double*>(small);
+  small += up(sizeof(double) * 2 * m);
+  b.dA = reinterpret_cast<const double**>(small);
+  small += up(sizeof(void*) * kMaxTerms);
+  b.dcp = reinterpret_cast<int*>(small);
+  b.Rt = Rt;
+  return b;
+}
+
+// eta of eq. (sressplit) with infinity norms for m pairs: lam host (m
+// complex), X device (n x m column-major).  The device computes f_i(lambda_q),
+// the split-form residuals T(lambda_q) x_q and the column maxima into b; the
+// host reads fv_h (m*ell), bad_h (m), hn_h (2m) back and forms
+// eta_q = max|T x| / (sum_i |f_i| ||A_i||_inf max|x|).
+static nep_status eta_run(Split& h, int m, const c128* lam, const c128* X, const EtaBuffers& b, c128* fv_h,
+                          int* bad_h, double* hn_h, double* eta, hipStream_t st) {
   const int n = h.op.n, ell = h.op.ell;
-  // f_i(lambda_q) on the device, in the workspace (grow-only: no device
-  // allocation or free once it is large enough)
-  std::vector<c128> fv((size_t)m * ell);
-  std::vector<int> bad(m);
-  NEP_TRY(grow(w.fz, sizeof(c128) * (size_t)m * (ell + 1) + sizeof(int) * (size_t)m));
-  c128* dz = w.fz.as<c128>();
-  c128* dfv = dz + m;
-  int* dbad = reinterpret_cast<int*>(dfv + (size_t)m * ell);
-  NEP_HIP(hipMemcpyAsync(dz, lam.data(), sizeof(c128) * m, hipMemcpyHostToDevice, st));
-  NEP_HIP(fn_points(h.op.dfn_nodes, h.op.dfn_coef, h.fn_roots.as<int>(), ell, dz, m, dfv, dbad, st));
-  NEP_HIP(hipMemcpyAsync(fv.data(), dfv, sizeof(c128) * (size_t)m * ell, hipMemcpyDeviceToHost, st));
-  NEP_HIP(hipMemcpyAsync(bad.data(), dbad, sizeof(int) * m, hipMemcpyDeviceToHost, st));
-  NEP_TRY(grow(w.Rt, sizeof(c128) * (size_t)n * m));
-  NEP_TRY(grow(w.norms, sizeof(double) * 2 * m + sizeof(c128) * (size_t)ell * m + sizeof(void*) * kMaxTerms +
-                            sizeof(int) * kMaxTerms));
-  char* base = w.norms.as<char>();
-  double* dnorm = reinterpret_cast<double*>(base);
-  c128* dcoef = reinterpret_cast<c128*>(base + sizeof(double) * 2 * m);
-  const double** dA = reinterpret_cast<const double**>(base + sizeof(double) * 2 * m + sizeof(c128) * ell * m);
-  int* dcp = reinterpret_cast<int*>(reinterpret_cast<char*>(dA) + sizeof(void*) * kMaxTerms);
   const double* hA[kMaxTerms];
   for (int i = 0; i < ell; ++i) hA[i] = reinterpret_cast<const double*>(h.op.dA[i]);
-  NEP_HIP(hipMemcpyAsync(dcoef, fv.data(), sizeof(c128) * ell * m, hipMemcpyHostToDevice, st));
-  NEP_HIP(hipMemcpyAsync(dA, hA, sizeof(void*) * ell, hipMemcpyHostToDevice, st));
-  NEP_HIP(hipMemcpyAsync(dcp, h.op.is_cplx, sizeof(int) * ell, hipMemcpyHostToDevice, st));
+  NEP_HIP(hipMemcpyAsync(b.z, lam, sizeof(c128) * m, hipMemcpyHostToDevice, st));
+  NEP_HIP(hipMemcpyAsync(b.dA, hA, sizeof(void*) * ell, hipMemcpyHostToDevice, st));
+  NEP_HIP(hipMemcpyAsync(b.dcp, h.op.is_cplx, sizeof(int) * ell, hipMemcpyHostToDevice, st));
+  NEP_HIP(fn_points(h.op.dfn_nodes, h.op.dfn_coef, h.fn_roots.as<int>(), ell, b.z, m, b.fv, b.bad, st));
   dim3 grid(ceil_div(n, 64), ceil_div(m, 16));
-  hipLaunchKernelGGL(k_split_apply, grid, dim3(256), 0, st, nullptr, n, ell, m, dA, dcp, dcoef, X, w.Rt.as<c128>());
+  hipLaunchKernelGGL(k_split_apply, grid, dim3(256), 0, st, nullptr, n, ell, m, b.dA, b.dcp, b.fv, X, b.Rt);
   NEP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_colmax2, dim3(m), dim3(256), 0, st, w.Rt.as<c128>(), X, n, dnorm);
+  hipLaunchKernelGGL(k_colmax2, dim3(m), dim3(256), 0, st, b.Rt, X, n, b.norms);
   NEP_HIP(hipGetLastError());
-  std::vector<double> hn(2 * m);
-  NEP_HIP(hipMemcpyAsync(hn.data(), dnorm, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, st));
+  NEP_HIP(hipMemcpyAsync(fv_h, b.fv, sizeof(c128) * (size_t)m * ell, hipMemcpyDeviceToHost, st));
+  NEP_HIP(hipMemcpyAsync(bad_h, b.bad, sizeof(int) * m, hipMemcpyDeviceToHost, st));
+  NEP_HIP(hipMemcpyAsync(hn_h, b.norms, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, st));
   NEP_HIP(hipStreamSynchronize(st));
-  eta.assign(m, 0.0);
   for (int q = 0; q < m; ++q) {
-    if (bad[q]) {
+    if (bad_h[q]) {
       eta[q] = NAN;
       continue;
     }
     double den = 0.0;
     for (int i = 0; i < ell; ++i) {
-      const c128 f = fv[(size_t)i * m + q];
+      const c128 f = fv_h[(size_t)i * m + q];
       den += std::sqrt(f.re * f.re + f.im * f.im) * h.op.normA[i];
     }
-    den *= hn[2 * q + 1];
-    eta[q] = den > 0.0 ? hn[2 * q] / den : NAN;
+    den *= hn_h[2 * q + 1];
+    eta[q] = den > 0.0 ? hn_h[2 * q] / den : NAN;
   }
   return NEP_OK;
+}
+
+static nep_status backward_errors(Split& h, int m, const std::vector<zc>& lam, const c128* X, std::vector<double>& eta,
+                                  ExtractWork& w, hipStream_t st) {
+  const int n = h.op.n, ell = h.op.ell;
+  // the workspace grows and never shrinks: no device allocation or free once
+  // it is large enough
+  NEP_TRY(grow(w.fz, eta_small_bytes(m, ell)));
+  NEP_TRY(grow(w.Rt, sizeof(c128) * (size_t)n * m));
+  const EtaBuffers b = eta_carve(w.fz.as<char>(), w.Rt.as<c128>(), m, ell);
+  std::vector<c128> fv((size_t)m * ell);
+  std::vector<int> bad(m);
+  std::vector<double> hn(2 * m);
+  eta.assign(m, 0.0);
+  return eta_run(h, m, reinterpret_cast<const c128*>(lam.data()), X, b, fv.data(), bad.data(), hn.data(), eta.data(),
+                 st);
+}
+
+// ---------------------------------------------------------------------------
+// Backward errors without allocation.  Callers that cannot allocate device
+// memory (code under HIP graph capture, tight serving loops) use
+// nep_backward_error_noalloc: its scratch is this file-scope device array, one
+// copy per GPU, held until the process ends.  Host code must not use the
+// array's name as a device address; each device's address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr int kNoAllocMaxPairs = 256;                       // m
+constexpr size_t kNoAllocMaxResid = (size_t)1 << 18;        // n * m complex entries (4 MiB)
+constexpr size_t kNoAllocSmall = 128 << 10;                 // points, f values, flags, maxima, term tables
+constexpr size_t kNoAllocBytes = kNoAllocMaxResid * sizeof(c128) + kNoAllocSmall;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+static nep_status scratch_address(void** out) {
+  int dev = 0;
+  NEP_HIP(hipGetDevice(&dev));
+  NEP_CHECK(dev >= 0 && dev < kMaxDevices, NEP_ERR_DEVICE, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      set_error("hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+      return NEP_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NEP_OK;
+}
+
+static nep_status backward_errors_noalloc(Split& h, int m, const double* lambda, const c128* X, double* eta) {
+  const int n = h.op.n, ell = h.op.ell;
+  NEP_CHECK(m <= kNoAllocMaxPairs, NEP_ERR_ARG, "at most %d pairs per call without allocation (got %d)",
+            kNoAllocMaxPairs, m);
+  NEP_CHECK((size_t)n * m <= kNoAllocMaxResid, NEP_ERR_ARG,
+            "n * m = %lld exceeds the %zu residual entries of the allocation-free scratch", (long long)n * m,
+            kNoAllocMaxResid);
+  static_assert(sizeof(c128) * kNoAllocMaxPairs + ((sizeof(c128) * kNoAllocMaxPairs * kMaxTerms + 255) / 256 * 256) +
+                        sizeof(int) * kNoAllocMaxPairs + sizeof(double) * 2 * kNoAllocMaxPairs + 4 * 256 <=
+                    kNoAllocSmall,
+                "small scratch region too small");
+  void* base = nullptr;
+  NEP_TRY(scratch_address(&base));
+  char* p = static_cast<char*>(base);
+  const EtaBuffers b = eta_carve(p + kNoAllocMaxResid * sizeof(c128), reinterpret_cast<c128*>(p), m, ell);
+  // host read-back space on the stack (bounded by the limits above)
+  c128 fv[kNoAllocMaxPairs * kMaxTerms];
+  int bad[kNoAllocMaxPairs];
+  double hn[2 * kNoAllocMaxPairs];
+  return eta_run(h, m, reinterpret_cast<const c128*>(lambda), X, b, fv, bad, hn, eta, h.stream);
 }
 
 nep_status extract(Split& h, const nep_contour* g, const nep_ciss_opts* o, const void* S,
@@ -454,6 +550,12 @@ nep_status nep_extract(nep_split h, const nep_contour* g, const nep_ciss_opts* o
                        double* sigma) {
   NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle");
   return nep::extract(h->impl, g, o, S, e, m, lambda, X, eta, inside, sigma, nullptr);
+}
+
+nep_status nep_backward_error_noalloc(nep_split h, int m, const double* lambda, const void* X, double* eta) {
+  NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle");
+  NEP_CHECK(m >= 1 && lambda && X && eta, NEP_ERR_ARG, "bad arguments");
+  return backward_errors_noalloc(h->impl, m, lambda, (const c128*)X, eta);
 }
 
 nep_status nep_backward_error(nep_split h, int m, const double* lambda, const void* X, double* eta) {
