@@ -6,12 +6,12 @@ Python binding) never imports, calls or links anything here, and shares no
 code with it: the only common dependency is the seeded input generator
 package `workloads`, which holds no arithmetic of the method.
 """
-from .ciss import (NotHolomorphic, SingularNode, RankSaturated, fn_value,
+from .ciss import (NotHolomorphic, SingularNode, RankSaturated, fn_value, fn_derivative,
                    quadrature, t_matrix, node_solve, ciss_moments,
                    block_hankel, extract, backward_error, relative_residual,
-                   inside_mask)
+                   inside_mask, t_derivative, rii_polish)
 
-__all__ = ["NotHolomorphic", "SingularNode", "RankSaturated", "fn_value",
+__all__ = ["NotHolomorphic", "SingularNode", "RankSaturated", "fn_value", "fn_derivative",
            "quadrature", "t_matrix", "node_solve", "ciss_moments",
            "block_hankel", "extract", "backward_error", "relative_residual",
-           "inside_mask"]
+           "inside_mask", "t_derivative", "rii_polish"]

@@ -23,6 +23,10 @@ What it computes, step by step, with the passage each step follows:
 * Backward error of eq. (sressplit) with infinity norms (Section 6).
 * Eigenvalues outside the region are flagged (RG filter, Section 3.2.4).
 
+* Eigenpair polish by residual inverse iteration (Section 4.1, Algorithm
+  "RII", eqs. (rii), (rii-scalar)) with the derivatives of the FN functions
+  (FNEvaluateDerivative, Section 3.2.2).
+
 Library primitives used as single steps: numpy.linalg.solve (one LU solve of
 T(z_j) Y = V), numpy.linalg.svd and numpy.linalg.eig.  No blocking or fusion.
 """
@@ -133,6 +137,67 @@ def fn_value(fn, z):
     return complex(fn["beta"]) * g
 
 
+def fn_derivative(fn, z):
+    """f'(z) for f(z) = beta * g(alpha * z): alpha * beta * g'(alpha * z)
+    (FNEvaluateDerivative, Section 3.2.2), by the rules of differentiation:
+    (p/q)' = (p' q - p q')/q^2 with p' from the coefficient list, exp' = exp,
+    log' = 1/x, sqrt' = 1/(2 sqrt x), (x^(-1/2))' = -x^(-3/2)/2,
+    phi_k' = phi_k - k phi_{k+1}, and the sum, product, quotient and chain
+    rules for combinations."""
+    a = complex(fn["alpha"])
+    x = a * complex(z)
+    t = fn["type"]
+    if t == "rational":
+        num, den = fn["num"], fn["den"]
+        dnum = [c * (len(num) - 1 - k) for k, c in enumerate(num[:-1])]
+        p, dp = _horner(num, x), _horner(dnum, x)
+        if den:
+            dden = [c * (len(den) - 1 - k) for k, c in enumerate(den[:-1])]
+            q, dq = _horner(den, x), _horner(dden, x)
+            if q == 0:
+                raise NotHolomorphic("pole of a rational function")
+            dg = (dp * q - p * dq) / (q * q)
+        else:
+            dg = dp
+    elif t == "exp":
+        dg = complex(np.exp(x))
+    elif t == "log":
+        if _on_cut(x):
+            raise NotHolomorphic("log branch cut")
+        dg = 1.0 / x
+    elif t == "sqrt":
+        if _on_cut(x):
+            raise NotHolomorphic("sqrt branch cut")
+        dg = 0.5 / complex(np.sqrt(x))
+    elif t == "invsqrt":
+        if _on_cut(x):
+            raise NotHolomorphic("inverse sqrt branch cut")
+        dg = -0.5 / (x * complex(np.sqrt(x)))
+    elif t == "phi":
+        k = int(fn["k"])
+        dg = _phi(k, x) - k * _phi(k + 1, x)
+    elif t == "combine":
+        op = fn["op"]
+        ga, da = fn_value(fn["a"], x), fn_derivative(fn["a"], x)
+        if op == COMB_COMPOSE:
+            dg = fn_derivative(fn["b"], ga) * da
+        else:
+            gb, db = fn_value(fn["b"], x), fn_derivative(fn["b"], x)
+            if op == COMB_ADD:
+                dg = da + db
+            elif op == COMB_MUL:
+                dg = da * gb + ga * db
+            elif op == COMB_DIV:
+                if gb == 0:
+                    raise NotHolomorphic("division by zero in combine")
+                dg = (da * gb - ga * db) / (gb * gb)
+            else:
+                raise ValueError("unknown combine op")
+    else:
+        raise ValueError(f"unknown FN type {t}")
+    return a * complex(fn["beta"]) * dg
+
+
 # ---------------------------------------------------------------------------
 # Contour and quadrature
 # ---------------------------------------------------------------------------
@@ -239,6 +304,54 @@ def extract(problem, contour, S, K, rank_tol=1e-12):
     eta = backward_error(problem, lam, X)
     return {"lam": lam, "X": X, "eta": eta,
             "inside": inside_mask(contour, lam), "sigma": sig, "m": m}
+
+
+# ---------------------------------------------------------------------------
+# Eigenpair polish: residual inverse iteration (Section 4.1, Algorithm "RII")
+# ---------------------------------------------------------------------------
+
+def t_derivative(problem, z):
+    """T'(z) = sum_i f_i'(z) A_i."""
+    T = np.zeros(problem.mats[0].shape, dtype=np.complex128)
+    for A, f in zip(problem.mats, problem.fns):
+        T += fn_derivative(f, z) * A
+    return T
+
+
+def rii_polish(problem, lam0, x0, tol, max_it=10, max_newton=30):
+    """Neumaier's residual inverse iteration as in Algorithm "RII": target
+    sigma = lam0 (the eigenvalue to polish), T(sigma) kept fixed, initial
+    vector x0.  Each outer step solves the scalar equation
+    x^* T(sigma)^{-1} T(z) x = 0 (eq. (rii-scalar)) by Newton's method,
+    mu = x^* T(sigma)^{-1} T(z) x / x^* T(sigma)^{-1} T'(z) x, stopping when
+    |mu|/|z| < sqrt(eps) (or after max_newton steps); then forms the residual
+    r = T(lambda) x, stops when eta(x, lambda) < tol, and otherwise updates
+    x <- (x - T(sigma)^{-1} r)/||x - T(sigma)^{-1} r||.  Returns (lambda, x,
+    eta, outer steps taken), x normalized as the extraction's eigenvectors."""
+    sigma = complex(lam0)
+    Ts = t_matrix(problem, sigma)
+    x = np.asarray(x0, dtype=np.complex128)
+    x = x / np.linalg.norm(x)
+    lam = sigma
+    eps = np.finfo(float).eps
+    eta = np.inf
+    k = 0
+    for k in range(max_it):
+        for _ in range(max_newton):
+            num = np.vdot(x, np.linalg.solve(Ts, t_matrix(problem, lam) @ x))
+            den = np.vdot(x, np.linalg.solve(Ts, t_derivative(problem, lam) @ x))
+            mu = num / den
+            lam = lam - mu
+            if abs(mu) < np.sqrt(eps) * abs(lam):
+                break
+        eta = backward_error(problem, [lam], x[:, None])[0]
+        if eta < tol:
+            break
+        r = t_matrix(problem, lam) @ x
+        v = np.linalg.solve(Ts, r)
+        x = x - v
+        x = x / np.linalg.norm(x)
+    return lam, _normalize(x[:, None])[:, 0], eta, k + 1
 
 
 # ---------------------------------------------------------------------------

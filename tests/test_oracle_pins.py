@@ -89,6 +89,57 @@ def test_phi_functions():
         assert abs(oracle.fn_value(wl.fn_phi(k), 1e-12) - 1 / math.factorial(k)) < 1e-11
 
 
+def _cauchy_derivative(f, z0, r, N=96):
+    """f'(z0) = (1/(2 pi i)) oint f(z)/(z - z0)^2 dz on |z - z0| = r, by the
+    trapezoid rule: uses only values of f (error ~ (r/R)^N for a function
+    holomorphic in |z - z0| < R)."""
+    th = 2 * np.pi * np.arange(N) / N
+    e = np.exp(1j * th)
+    vals = np.array([oracle.fn_value(f, z0 + r * ee) for ee in e])
+    return np.sum(vals / (r * e)) / N
+
+
+@pytest.mark.parametrize("fn,z0,r", [
+    (wl.fn_rational([1.0, -2.0, 3.0], [1.0, 0.5j]), 1.3 + 0.4j, 0.3),
+    (wl.fn_rational([1.0, 0.0], [1.0, -1.0]), 3.0 - 1.0j, 0.5),
+    (wl.fn_exp(alpha=-0.7 + 0.1j, beta=2.0), 0.4 - 0.2j, 0.5),
+    (wl.fn_log(), 2.0 + 1.0j, 0.5),
+    (wl.fn_sqrt(beta=1j), 3.0 - 2.0j, 0.8),
+    (wl.fn_invsqrt(alpha=2.0), 1.0 + 1.0j, 0.5),
+    (wl.fn_phi(0), 0.3 + 0.2j, 0.2),
+    (wl.fn_phi(1), 1.5 - 0.5j, 0.5),
+    (wl.fn_phi(3, alpha=0.01), 20.0 + 5.0j, 2.0),
+    (wl.fn_combine(wl.COMB_COMPOSE, wl.fn_rational([1.0, -108.8 ** 2]), wl.fn_sqrt(), beta=1j),
+     22600.0 + 300.0j, 200.0),
+    (wl.fn_combine(wl.COMB_DIV, wl.fn_exp(alpha=0.01), wl.fn_rational([1.0, 3.0])), 4.0 + 2.0j, 1.0),
+    (wl.fn_combine(wl.COMB_MUL, wl.fn_rational([-1.0, 0.0]), wl.fn_exp(alpha=-100.0)), -1.0 + 0.05j, 0.01),
+    (wl.fn_combine(wl.COMB_ADD, wl.fn_log(), wl.fn_sqrt()), 1.0 + 2.0j, 0.5),
+])
+def test_fn_derivative_cauchy_integral(fn, z0, r):
+    """FNEvaluateDerivative (Section 3.2.2): the oracle's derivative of every FN
+    type and combination equals Cauchy's integral formula evaluated from the
+    function values alone."""
+    ref = _cauchy_derivative(fn, z0, r)
+    got = oracle.fn_derivative(fn, z0)
+    assert abs(got - ref) <= 1e-11 * abs(ref), (got, ref)
+
+
+def test_fn_derivative_closed_forms():
+    """The derivatives of the workloads' functions in closed form: the delay
+    term e^{-tau z}, the gun-like i sqrt(z - s^2), the string's z/(z - sigma),
+    and phi_1."""
+    z = 0.7 - 1.3j
+    assert oracle.fn_derivative(wl.fn_exp(alpha=-1.0), z) == pytest.approx(-cmath.exp(-z), rel=1e-15)
+    f = wl.fn_combine(wl.COMB_COMPOSE, wl.fn_rational([1.0, -108.8 ** 2]), wl.fn_sqrt(), beta=1j)
+    zz = 22600.0 + 40.0j
+    assert oracle.fn_derivative(f, zz) == pytest.approx(0.5j / cmath.sqrt(zz - 108.8 ** 2), rel=1e-14)
+    sig = 1.4
+    g = wl.fn_rational([1.0, 0.0], [1.0, -sig])
+    assert oracle.fn_derivative(g, z) == pytest.approx(-sig / (z - sig) ** 2, rel=1e-14)
+    assert oracle.fn_derivative(wl.fn_phi(1), z) == pytest.approx(
+        (z * cmath.exp(z) - cmath.exp(z) + 1) / z ** 2, rel=1e-13)
+
+
 def test_combine_ops():
     a = wl.fn_rational([1.0, -3.0])            # x - 3
     b = wl.fn_exp(alpha=0.5)                    # exp(x/2)
