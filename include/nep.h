@@ -210,6 +210,10 @@ typedef struct {
                        eq. (sressplit) (the paper's NEPSetTolerances tol, Table 1
                        uses 1e-8 for most problems); 0 -> 1e-8                  */
   int max_eigs;     /* capacity of the output arrays (>= 1)                     */
+  int polish_its;   /* 0: off.  > 0: pairs inside the contour whose eta exceeds
+                       eta_tol are polished by residual inverse iteration (as
+                       nep_rii_polish, tol 1e-14) with at most polish_its outer
+                       steps before they are flagged                          */
 } nep_extract_opts;
 
 /* From S (as written by nep_ciss_moments with the same g and o) computes the
@@ -242,6 +246,26 @@ nep_status nep_extract(nep_split h, const nep_contour* g, const nep_ciss_opts* o
 nep_status nep_backward_error(nep_split h, int m, const double* lambda,
                               const void* X, double* eta);
 
+/* FP64 polish of m eigenpairs by residual inverse iteration (Section 4.1,
+ * Algorithm "RII", eqs. (rii), (rii-scalar)), all pairs at once.  For each
+ * pair the target sigma is its own eigenvalue; T(sigma) is assembled and
+ * factored in complex FP64 on the device once, and each outer step solves the
+ * scalar equation x^* T(sigma)^{-1} T(z) x = 0 by Newton's method with the
+ * FN derivatives (FNEvaluateDerivative, Section 3.2.2) to |mu|/|z| <
+ * sqrt(eps), stops when eta(x, lambda) < tol (eq. (sressplit), infinity
+ * norms), and otherwise corrects x <- (x - T(sigma)^{-1} r)/||.||, r = T(lambda) x.
+ *   lambda: host, 2m doubles (in/out); X: device, complex n x m column-major
+ *   (in/out; returned with ||x||_2 = 1 and the largest-modulus entry real
+ *   positive); eta: host, m doubles (out): the pairs' backward errors after
+ *   the call.  A pair is replaced only if its backward error decreased.
+ *   tol: 0 selects 1e-14.  max_it: 1..100 outer steps.
+ *   iters: host, m ints (optional): outer steps each pair took (0: left as
+ *   it was, e.g. sigma an eigenvalue to working precision).
+ * Synchronous, on the handle's stream.  Allocates device memory (factors of
+ * m matrices of size n in complex FP64). */
+nep_status nep_rii_polish(nep_split h, int m, double* lambda, void* X,
+                          double* eta, double tol, int max_it, int* iters);
+
 /* nep_backward_error for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same computation and results, with every device buffer it
@@ -258,6 +282,11 @@ nep_status nep_backward_error(nep_split h, int m, const double* lambda,
  *   Runs on the handle's stream. */
 nep_status nep_backward_error_noalloc(nep_split h, int m, const double* lambda,
                                       const void* X, double* eta);
+
+/* Derivatives f_i'(z) (FNEvaluateDerivative, Section 3.2.2) for the ell
+ * functions at m host points: out[i*m + k] (host, ell*m complex).  Points on
+ * a pole or cut give NEP_ERR_NOT_HOLOMORPHIC. */
+nep_status nep_fn_eval_derivative(nep_split h, int m, const double* z, double* out);
 
 /* Values f_i(z) for ell functions at m host points (complex): out[i*m + k]
  * (host, ell*m complex).  Points on a pole or cut give NEP_ERR_NOT_HOLOMORPHIC. */

@@ -65,12 +65,12 @@ class SplitOperator:
         return nep_ciss_wait(self.h)
 
     def extract(self, contour, S, N, L, K, prec="mixed", max_eigs=64, rank_tol=0.0, X=None, stream=None,
-                eta_tol=0.0):
+                eta_tol=0.0, polish_its=0):
         import torch
         if X is None:
             X = torch.zeros((max_eigs, self.n), dtype=torch.complex128, device=S.device)
         o = opts_struct(N, L, K, prec, None, True, 0.0, stream)
-        r = nep_extract(self.h, contour, o, S, X, max_eigs, rank_tol, eta_tol)
+        r = nep_extract(self.h, contour, o, S, X, max_eigs, rank_tol, eta_tol, polish_its)
         r["X_dev"] = X
         r["X"] = X[: r["m"]].cpu().numpy().T.copy()
         return r
@@ -78,8 +78,15 @@ class SplitOperator:
     def backward_error(self, lam, X):
         return nep_backward_error(self.h, lam, X)
 
+    def rii_polish(self, lam, X, tol=0.0, max_it=10):
+        """X: device tensor (m, n) holding the eigenvectors; polished in place."""
+        return binding.nep_rii_polish(self.h, lam, X, tol, max_it)
+
     def fn_eval(self, z):
         return nep_fn_eval(self.h, self.ell, z)
+
+    def fn_eval_derivative(self, z):
+        return binding.nep_fn_eval_derivative(self.h, self.ell, z)
 
 
 class Server:

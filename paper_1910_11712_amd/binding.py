@@ -67,7 +67,7 @@ class nep_ciss_stats(C.Structure):
 
 
 class nep_extract_opts(C.Structure):
-    _fields_ = [("rank_tol", C.c_double), ("eta_tol", C.c_double), ("max_eigs", C.c_int)]
+    _fields_ = [("rank_tol", C.c_double), ("eta_tol", C.c_double), ("max_eigs", C.c_int), ("polish_its", C.c_int)]
 
 
 class nep_server_opts(C.Structure):
@@ -123,7 +123,10 @@ def lib():
                                   C.POINTER(C.c_double), C.POINTER(ip), C.POINTER(C.c_double)]
         L.nep_backward_error.argtypes = [vp, ip, C.POINTER(C.c_double), vp, C.POINTER(C.c_double)]
         L.nep_backward_error_noalloc.argtypes = [vp, ip, C.POINTER(C.c_double), vp, C.POINTER(C.c_double)]
+        L.nep_rii_polish.argtypes = [vp, ip, C.POINTER(C.c_double), vp, C.POINTER(C.c_double), C.c_double, ip,
+                                     C.POINTER(ip)]
         L.nep_fn_eval.argtypes = [vp, ip, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.nep_fn_eval_derivative.argtypes = [vp, ip, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.nep_batch_create.argtypes = [ip, C.POINTER(vp), C.POINTER(nep_contour), C.POINTER(nep_ciss_opts),
                                        C.POINTER(vp), C.POINTER(vp), ip, vp, C.POINTER(vp)]
         L.nep_batch_run.argtypes = [vp, C.POINTER(nep_ciss_stats)]
@@ -269,11 +272,11 @@ def nep_ciss_wait(h):
     return st.as_dict()
 
 
-def nep_extract(h, contour, opts, S, X, max_eigs=64, rank_tol=0.0, eta_tol=0.0):
+def nep_extract(h, contour, opts, S, X, max_eigs=64, rank_tol=0.0, eta_tol=0.0, polish_its=0):
     """Returns m, lam, eta, inside (inside the contour and converged),
     unconverged (inside with eta > eta_tol) and the singular values."""
     e = nep_extract_opts()
-    e.rank_tol, e.eta_tol, e.max_eigs = float(rank_tol), float(eta_tol), int(max_eigs)
+    e.rank_tol, e.eta_tol, e.max_eigs, e.polish_its = float(rank_tol), float(eta_tol), int(max_eigs), int(polish_its)
     m = C.c_int(0)
     lam = np.zeros(2 * max_eigs)
     eta = np.zeros(max_eigs)
@@ -305,6 +308,21 @@ def nep_backward_error(h, lam, X):
     return eta
 
 
+def nep_rii_polish(h, lam, X, tol=0.0, max_it=10):
+    """Polishes the pairs (lam, columns of the device tensor X (m, n)) in
+    place on the device; returns (lam, eta, iters)."""
+    lam = np.asarray(lam, dtype=np.complex128)
+    m = len(lam)
+    la = np.zeros(2 * m)
+    la[0::2], la[1::2] = lam.real, lam.imag
+    eta = np.zeros(m)
+    its = np.zeros(m, dtype=np.int32)
+    check(lib().nep_rii_polish(h, m, la.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(X.data_ptr()),
+                               eta.ctypes.data_as(C.POINTER(C.c_double)), float(tol), int(max_it),
+                               its.ctypes.data_as(C.POINTER(C.c_int))))
+    return la[0::2] + 1j * la[1::2], eta, its
+
+
 def nep_backward_error_noalloc(h, lam, X):
     """As nep_backward_error, with the library's fixed device scratch."""
     lam = np.asarray(lam, dtype=np.complex128)
@@ -325,6 +343,17 @@ def nep_fn_eval(h, ell, z):
     out = np.zeros(2 * m * ell)
     check(lib().nep_fn_eval(h, m, zi.ctypes.data_as(C.POINTER(C.c_double)),
                             out.ctypes.data_as(C.POINTER(C.c_double))))
+    return (out[0::2] + 1j * out[1::2]).reshape(ell, m)
+
+
+def nep_fn_eval_derivative(h, ell, z):
+    z = np.asarray(z, dtype=np.complex128).ravel()
+    m = len(z)
+    zi = np.zeros(2 * m)
+    zi[0::2], zi[1::2] = z.real, z.imag
+    out = np.zeros(2 * m * ell)
+    check(lib().nep_fn_eval_derivative(h, m, zi.ctypes.data_as(C.POINTER(C.c_double)),
+                                       out.ctypes.data_as(C.POINTER(C.c_double))))
     return (out[0::2] + 1j * out[1::2]).reshape(ell, m)
 
 
@@ -367,12 +396,12 @@ def nep_server_create(hbm_budget, max_inflight=64, nstreams=4):
     return s
 
 
-def nep_server_submit(s, h, contour, opts, V, max_eigs=64, rank_tol=0.0, want_X=False, eta_tol=0.0):
+def nep_server_submit(s, h, contour, opts, V, max_eigs=64, rank_tol=0.0, want_X=False, eta_tol=0.0, polish_its=0):
     """Queues a query.  V: host complex (n, L).  Returns (ticket, out) where
     out holds the host result arrays the server fills; keep it until the
     query is collected."""
     e = nep_extract_opts()
-    e.rank_tol, e.eta_tol, e.max_eigs = float(rank_tol), float(eta_tol), int(max_eigs)
+    e.rank_tol, e.eta_tol, e.max_eigs, e.polish_its = float(rank_tol), float(eta_tol), int(max_eigs), int(polish_its)
     Vf = np.asfortranarray(np.asarray(V, dtype=np.complex128))
     n = Vf.shape[0]
     out = {"V": Vf, "lam": np.zeros(2 * max_eigs), "eta": np.zeros(max_eigs),

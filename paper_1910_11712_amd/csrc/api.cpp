@@ -161,14 +161,21 @@ nep_status Split::init(int n_, int ell_, const nep_mat* A, const nep_fn* f, hipS
   return NEP_OK;
 }
 
-nep_status Split::eval_fns(int m, const c128* zh, std::vector<c128>& out, std::vector<int>& bad) {
+hipError_t fn_points_d(const FnNode* nodes, const c128* coef, const int* roots, int ell, const c128* z, int m,
+                       c128* out, int* bad, hipStream_t st);
+
+nep_status Split::eval_fns(int m, const c128* zh, std::vector<c128>& out, std::vector<int>& bad, bool deriv) {
   DevMem dz, dout, dbad;
   NEP_TRY(dz.alloc(sizeof(c128) * m));
   NEP_TRY(dout.alloc(sizeof(c128) * m * op.ell));
   NEP_TRY(dbad.alloc(sizeof(int) * m));
   NEP_HIP(hipMemcpyAsync(dz.p, zh, sizeof(c128) * m, hipMemcpyHostToDevice, stream));
-  NEP_HIP(fn_points(op.dfn_nodes, op.dfn_coef, fn_roots.as<int>(), op.ell, dz.as<c128>(), m, dout.as<c128>(),
-                    dbad.as<int>(), stream));
+  if (deriv)
+    NEP_HIP(fn_points_d(op.dfn_nodes, op.dfn_coef, fn_roots.as<int>(), op.ell, dz.as<c128>(), m, dout.as<c128>(),
+                        dbad.as<int>(), stream));
+  else
+    NEP_HIP(fn_points(op.dfn_nodes, op.dfn_coef, fn_roots.as<int>(), op.ell, dz.as<c128>(), m, dout.as<c128>(),
+                      dbad.as<int>(), stream));
   out.resize((size_t)m * op.ell);
   bad.resize(m);
   NEP_HIP(hipMemcpyAsync(out.data(), dout.p, sizeof(c128) * m * op.ell, hipMemcpyDeviceToHost, stream));
@@ -312,12 +319,24 @@ nep_status nep_ciss_wait(nep_split h, nep_ciss_stats* st) {
   return h->impl.wait(st);
 }
 
+nep_status nep_fn_eval_derivative(nep_split h, int m, const double* z, double* out) {
+  NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle");
+  NEP_CHECK(m >= 1 && z != nullptr && out != nullptr, NEP_ERR_ARG, "bad point arrays");
+  std::vector<c128> vals;
+  std::vector<int> bad;
+  NEP_TRY(h->impl.eval_fns(m, reinterpret_cast<const c128*>(z), vals, bad, true));
+  std::memcpy(out, vals.data(), sizeof(c128) * vals.size());
+  for (int k = 0; k < m; ++k)
+    NEP_CHECK(bad[k] == 0, NEP_ERR_NOT_HOLOMORPHIC, "point %d lies on a pole or branch cut of some f_i", k);
+  return NEP_OK;
+}
+
 nep_status nep_fn_eval(nep_split h, int m, const double* z, double* out) {
   NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle");
   NEP_CHECK(m >= 1 && z != nullptr && out != nullptr, NEP_ERR_ARG, "bad point arrays");
   std::vector<c128> vals;
   std::vector<int> bad;
-  NEP_TRY(h->impl.eval_fns(m, reinterpret_cast<const c128*>(z), vals, bad));
+  NEP_TRY(h->impl.eval_fns(m, reinterpret_cast<const c128*>(z), vals, bad, false));
   std::memcpy(out, vals.data(), sizeof(c128) * vals.size());
   for (int k = 0; k < m; ++k)
     NEP_CHECK(bad[k] == 0, NEP_ERR_NOT_HOLOMORPHIC, "point %d lies on a pole or branch cut of some f_i", k);

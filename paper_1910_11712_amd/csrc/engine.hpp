@@ -49,6 +49,8 @@ struct ProbDesc {
   const c128* Adiag[kMaxTerms];
   const c128* V;          // caller probes, column-major n x L
   c128* S;                // caller moments, column-major n x L x KK
+  const c128* zpts;       // explicit points (N, device) instead of the contour's
+                          // nodes, or nullptr
 };
 
 // Per-node arrays (global node index g).

@@ -353,6 +353,25 @@ static nep_status backward_errors(Split& h, int m, const std::vector<zc>& lam, c
                  st);
 }
 
+// eta for m pairs (host points, device vectors) into host eta, with the given
+// workspace or the handle's own.
+nep_status backward_errors_dev(Split& h, int m, const c128* lam, const c128* X, double* eta, ExtractWork* w,
+                               hipStream_t st) {
+  if (!w) {
+    if (!h.xw) h.xw = std::make_shared<ExtractWork>();
+    w = h.xw.get();
+  }
+  std::vector<zc> lz(m);
+  for (int q = 0; q < m; ++q) lz[q] = zc(lam[q].re, lam[q].im);
+  std::vector<double> et;
+  NEP_TRY(backward_errors(h, m, lz, X, et, *w, st));
+  for (int q = 0; q < m; ++q) eta[q] = et[q];
+  return NEP_OK;
+}
+
+nep_status rii_polish(Split& h, int m, zc* lam, c128* X, double* eta, const char* sel, double tol, int max_it,
+                      int* iters, ExtractWork* w, hipStream_t st);
+
 // ---------------------------------------------------------------------------
 // Backward errors without allocation.  Callers that cannot allocate device
 // memory (code under HIP graph capture, tight serving loops) use
@@ -527,15 +546,64 @@ nep_status extract(Split& h, const nep_contour* g, const nep_ciss_opts* o, const
   // inside but above it (typically a spurious one from a numerical rank taken
   // at the moments' noise floor) is flagged apart.
   const double etol = e->eta_tol > 0.0 ? e->eta_tol : 1e-8;
+  auto in_region = [&](zc l) {
+    const zc mu_q = (l - c0) / g->rho;
+    return g->kind == 0 ? (std::abs(mu_q) < 1.0)
+                        : (mu_q.real() * mu_q.real() + (mu_q.imag() / g->v) * (mu_q.imag() / g->v) < 1.0);
+  };
+  if (e->polish_its > 0) {
+    // pairs inside but above the tolerance (limited by the quadrature or by
+    // the truncation of weakly filtered outside eigenvalues) are polished by
+    // residual inverse iteration (Section 4.1) in FP64
+    std::vector<char> sel(m, 0);
+    int cnt = 0;
+    for (int q = 0; q < m; ++q) {
+      sel[q] = in_region(lam_s[q]) && !(et[q] <= etol) && std::isfinite(et[q]);
+      cnt += sel[q];
+    }
+    if (cnt > 0) {
+      NEP_TRY(rii_polish(h, m, lam_s.data(), (c128*)X, et.data(), sel.data(), 1e-14, e->polish_its, nullptr, &w, st));
+      // keep the output sorted by (Re, Im): permute the eigenvectors if
+      // polishing changed the order
+      std::vector<int> ord2(m);
+      std::iota(ord2.begin(), ord2.end(), 0);
+      std::stable_sort(ord2.begin(), ord2.end(), [&](int a, int b) {
+        if (lam_s[a].real() != lam_s[b].real()) return lam_s[a].real() < lam_s[b].real();
+        return lam_s[a].imag() < lam_s[b].imag();
+      });
+      bool moved = false;
+      for (int q = 0; q < m; ++q) moved |= ord2[q] != q;
+      if (moved) {
+        NEP_TRY(grow(w.X0, sizeof(c128) * (size_t)n * m));
+        NEP_HIP(hipMemcpyAsync(w.X0.p, X, sizeof(c128) * (size_t)n * m, hipMemcpyDeviceToDevice, st));
+        for (int q = 0; q < m; ++q)
+          NEP_HIP(hipMemcpyAsync((c128*)X + (size_t)q * n, w.X0.as<c128>() + (size_t)ord2[q] * n, sizeof(c128) * n,
+                                 hipMemcpyDeviceToDevice, st));
+        NEP_HIP(hipStreamSynchronize(st));
+        std::vector<zc> l2(m);
+        std::vector<double> e2(m);
+        for (int q = 0; q < m; ++q) {
+          l2[q] = lam_s[ord2[q]];
+          e2[q] = et[ord2[q]];
+        }
+        lam_s.swap(l2);
+        et.swap(e2);
+      }
+    }
+  }
   for (int q = 0; q < m; ++q) {
     lambda[2 * q] = lam_s[q].real();
     lambda[2 * q + 1] = lam_s[q].imag();
     eta[q] = et[q];
-    const zc mu_q = (lam_s[q] - c0) / g->rho;
-    const bool in = g->kind == 0 ? (std::abs(mu_q) < 1.0)
-                                 : (mu_q.real() * mu_q.real() + (mu_q.imag() / g->v) * (mu_q.imag() / g->v) < 1.0);
-    inside[q] = !in ? 0 : (et[q] <= etol ? 1 : 2);
+    inside[q] = !in_region(lam_s[q]) ? 0 : (et[q] <= etol ? 1 : 2);
   }
+  // two converged pairs with one eigenvalue (a polished spurious pair can
+  // land on an eigenvalue another pair already holds): the one with the
+  // larger backward error is not counted
+  for (int a = 0; a < m; ++a)
+    for (int b = a + 1; b < m; ++b)
+      if (inside[a] == 1 && inside[b] == 1 && std::abs(lam_s[a] - lam_s[b]) <= 1e-8 * std::abs(lam_s[a]))
+        inside[et[a] <= et[b] ? b : a] = 2;
   return NEP_OK;
 }
 

@@ -25,7 +25,7 @@ struct Split {
   nep_status init(int n, int ell, const nep_mat* A, const nep_fn* f, hipStream_t st);
   nep_status moments(const nep_contour* g, const nep_ciss_opts* o, const void* V, void* S, nep_ciss_stats* st);
   nep_status wait(nep_ciss_stats* st);
-  nep_status eval_fns(int m, const c128* zh, std::vector<c128>& out, std::vector<int>& bad);
+  nep_status eval_fns(int m, const c128* zh, std::vector<c128>& out, std::vector<int>& bad, bool deriv);
 };
 
 nep_status check_contour(const nep_contour* g);

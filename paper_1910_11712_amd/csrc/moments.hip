@@ -24,9 +24,14 @@ __global__ void k_coef(const ProbDesc* __restrict__ pd, NodeArrays na, int nnode
   double s, c;
   sincos(th, &s, &c);
   const double v = P.kind == 1 ? P.v : 1.0;
-  const c128 zeta = {c, v * s};
-  const c128 z = {P.c.re + P.rho * zeta.re, P.c.im + P.rho * zeta.im};
-  const c128 w = {P.rho * v * c / P.N, P.rho * s / P.N};
+  c128 zeta = {c, v * s};
+  c128 z = {P.c.re + P.rho * zeta.re, P.c.im + P.rho * zeta.im};
+  c128 w = {P.rho * v * c / P.N, P.rho * s / P.N};
+  if (P.zpts != nullptr) {  // explicit points (shifted solves): no quadrature weights
+    z = P.zpts[j];
+    zeta = z;
+    w = {0.0, 0.0};
+  }
   na.z[g] = z;
   na.zeta[g] = zeta;
   na.w[g] = w;

@@ -204,6 +204,7 @@ nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs) {
     D.normA = q.op->dnormA;
     D.fn_nodes = q.op->dfn_nodes;
     D.fn_coef = q.op->dfn_coef;
+    D.zpts = q.zpts;
   }
   NEP_HIP(hipMemcpy(dpd_.p, hpd_.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice));
   return NEP_OK;
@@ -486,6 +487,37 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
   }
   fallback_pending_ = true;
   return NEP_OK;
+}
+
+template <typename P>
+nep_status MomentsPlan::factor_t(hipStream_t st) {
+  const ProbDesc* pd = dpd_.as<ProbDesc>();
+  NEP_HIP(ir_reset(ir_, nnodes, st));
+  NEP_HIP(launch_coef(pd, na_, nnodes, ir_, st));
+  NEP_HIP(launch_assemble<P>(pd, dprefix_.as<int>(), pt_.assemble, na_, dT_.as<cx<P>>(), nullptr, st));
+  NEP_HIP(lu_run<P>(lu_, dmd_.as<MatDesc>(), dlu_prefix_.as<int>(), dT_.as<cx<P>>(), drows_.as<int>(),
+                    drows_snap_.as<int>(), rows_total_, dinfo_.as<int>(), nullptr, dlinv_.as<cx<P>>(),
+                    ddinv_.as<cx<P>>(), ddinv_off_.as<long long>(), darrive_.as<int>(), st, ls_));
+  return NEP_OK;
+}
+
+template <typename P>
+nep_status MomentsPlan::solve_rhs_t(hipStream_t st) {
+  NEP_HIP(hipMemsetAsync(dY_.p, 0, sizeof(c128) * (size_t)y_elems_, st));
+  NEP_HIP(solve_run<P>(sp_, dpd_.as<ProbDesc>(), dmd_.as<MatDesc>(), na_, dT_.as<cx<P>>(), drows_.as<int>(),
+                       ddinv_.as<cx<P>>(), ddinv_off_.as<long long>(), dR_.as<c128>(), dY_.as<c128>(), true,
+                       nullptr, ir_, st));
+  return NEP_OK;
+}
+
+nep_status MomentsPlan::factor(hipStream_t st) {
+  if (opt.prec == NEP_PREC_FP64) return factor_t<double>(st);
+  return factor_t<float>(st);
+}
+
+nep_status MomentsPlan::solve_rhs(hipStream_t st) {
+  if (opt.prec == NEP_PREC_FP64) return solve_rhs_t<double>(st);
+  return solve_rhs_t<float>(st);
 }
 
 nep_status MomentsPlan::enqueue(hipStream_t st, bool eager) {

@@ -86,6 +86,7 @@ struct PlanProblem {
   nep_contour g;
   const c128* V;
   c128* S;
+  const c128* zpts = nullptr;  // explicit points (device, N) instead of g's nodes
 };
 
 struct PlanOptions {
@@ -129,6 +130,17 @@ class MomentsPlan {
   nep_status finish(hipStream_t st, RunResult& out, bool allow_fallback);
   // Device buffers shared with extraction and the server.
   const c128* Y() const { return dY_.as<c128>(); }
+  // Shifted solves on resident factors (a plan over explicit points or the
+  // contour's nodes): factor() assembles and factors T at every node;
+  // solve_rhs() then sets Y_j = T(z_j)^{-1} R_j for the right-hand sides the
+  // caller wrote into R (layout [row][node][column], n x N*L per problem),
+  // any number of times.
+  nep_status factor(hipStream_t st);
+  nep_status solve_rhs(hipStream_t st);
+  c128* R_mut() { return dR_.as<c128>(); }
+  c128* Y_mut() { return dY_.as<c128>(); }
+  const NodeArrays& nodes() const { return na_; }
+  const int* info() const { return dinfo_.as<int>(); }
   // Rebinds caller buffers (V, S) and contours without rebuilding.
   nep_status rebind(const std::vector<PlanProblem>& probs);
   bool matches(const std::vector<PlanProblem>& probs, const PlanOptions& o) const;
@@ -161,6 +173,10 @@ class MomentsPlan {
   nep_status enqueue_t(hipStream_t st, bool eager);
   template <typename P>
   nep_status run_fallback(hipStream_t st);
+  template <typename P>
+  nep_status factor_t(hipStream_t st);
+  template <typename P>
+  nep_status solve_rhs_t(hipStream_t st);
 
   std::vector<ProbDesc> hpd_;
   std::vector<MatDesc> sorted_;

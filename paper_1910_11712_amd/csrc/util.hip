@@ -85,4 +85,25 @@ hipError_t fn_points(const FnNode* nodes, const c128* coef, const int* roots, in
   return hipGetLastError();
 }
 
+// f_i'(z_k): out[i*m + k].
+__global__ void k_fn_points_d(const FnNode* __restrict__ nodes, const c128* __restrict__ coef,
+                              const int* __restrict__ roots, int ell, const c128* __restrict__ z, int m,
+                              c128* __restrict__ out, int* __restrict__ bad) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  int b = 0;
+  for (int i = 0; i < ell; ++i) {
+    c128 d;
+    (void)fn_eval_d(nodes, coef, roots[i], z[k], b, d);
+    out[(long long)i * m + k] = d;
+  }
+  bad[k] = b;
+}
+
+hipError_t fn_points_d(const FnNode* nodes, const c128* coef, const int* roots, int ell, const c128* z, int m,
+                       c128* out, int* bad, hipStream_t st) {
+  hipLaunchKernelGGL(k_fn_points_d, dim3(ceil_div(m, 64)), dim3(64), 0, st, nodes, coef, roots, ell, z, m, out, bad);
+  return hipGetLastError();
+}
+
 }  // namespace nep

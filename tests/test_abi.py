@@ -87,7 +87,7 @@ int main(void) {
   P(nep_ciss_stats, singular_node) P(nep_ciss_stats, bad_node) P(nep_ciss_stats, max_rel_residual)
   P(nep_ciss_stats, ms_total) P(nep_ciss_stats, ms_lu) P(nep_ciss_stats, min_abs_pivot)
   printf("nep_extract_opts %zu\n", sizeof(nep_extract_opts));
-  P(nep_extract_opts, eta_tol) P(nep_extract_opts, max_eigs)
+  P(nep_extract_opts, eta_tol) P(nep_extract_opts, max_eigs) P(nep_extract_opts, polish_its)
   printf("nep_server_opts %zu\n", sizeof(nep_server_opts));
   P(nep_server_opts, max_inflight) P(nep_server_opts, nstreams)
   printf("nep_query_info %zu\n", sizeof(nep_query_info));
