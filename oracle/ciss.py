@@ -307,6 +307,23 @@ def extract(problem, contour, S, K, rank_tol=1e-12):
 
 
 # ---------------------------------------------------------------------------
+# Eigenvalue count (argument principle)
+# ---------------------------------------------------------------------------
+
+def eigenvalue_count(problem, contour, N):
+    """Number of eigenvalues inside the contour as the winding number of
+    det T(z) along it: eigenvalues are the zeros of det T (eq. (nep)).  The
+    phase of det T(z_j) at the N trapezoid nodes (numpy.linalg.slogdet), the
+    steps between consecutive nodes taken in (-pi, pi], summed and divided
+    by 2 pi.  Returns (count, largest step, unrounded winding number)."""
+    z, _, _ = quadrature(contour, N)
+    ph = [np.angle(np.linalg.slogdet(t_matrix(problem, zz))[0]) for zz in z]
+    steps = [math.remainder(ph[(j + 1) % N] - ph[j], 2.0 * math.pi) for j in range(N)]
+    w = sum(steps) / (2.0 * math.pi)
+    return int(round(w)), max(abs(s) for s in steps), w
+
+
+# ---------------------------------------------------------------------------
 # Eigenpair polish: residual inverse iteration (Section 4.1, Algorithm "RII")
 # ---------------------------------------------------------------------------
 

@@ -411,6 +411,28 @@ def test_node_solve_diagonal_closed_form():
         assert np.array_equal(Y, Ys[j])
 
 
+def test_eigenvalue_count_argument_principle():
+    """Argument principle (zeros of det T, eq. (nep)): the oracle's winding
+    count equals the secular equation's number of roots inside cfg0's circle,
+    and SciPy's eigenvalue count of a random complex pencil inside a circle."""
+    cfg = wl.config0()
+    roots = string_secular_roots(200, 1.0, 10.0, 190.0)
+    for N in (32, 128):
+        cnt, step, w = oracle.eigenvalue_count(cfg["problem"], cfg["contour"], N)
+        assert cnt == len(roots) == 3 and abs(w - 3) < 1e-8, (N, cnt, w)
+    rng = np.random.default_rng(17)
+    n = 40
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    B = np.eye(n) + 0.1 * rng.standard_normal((n, n))
+    ev = scipy.linalg.eigvals(A, B)
+    prob = Problem("pencil", [A, B], [wl.fn_rational([1.0]), wl.fn_rational([-1.0, 0.0])])
+    con = Contour.circle(0.5 + 0.5j, 4.5)
+    d = np.abs(ev - con.c)
+    assert np.min(np.abs(d - con.rho)) > 0.05           # none on the contour
+    cnt, step, w = oracle.eigenvalue_count(prob, con, 512)
+    assert step < 2.0 and cnt == int(np.sum(d < con.rho)) >= 3, (cnt, int(np.sum(d < con.rho)), step)
+
+
 def test_config0_invariants():
     """P8: eigenvalues independent of V; conjugate symmetry of node solves."""
     cfg = wl.config0()
