@@ -200,6 +200,38 @@ nep_status nep_ciss_moments(nep_split h, const nep_contour* g,
 /* Waits for the last nep_ciss_moments on h and reports its status/stats. */
 nep_status nep_ciss_wait(nep_split h, nep_ciss_stats* st);
 
+/* Moments of further probes on the factors resident from the last
+ * nep_ciss_moments call on h (same contour, N, L, K and precision; no
+ * assembly and no factorization): solves, refinement and moments only.
+ *   V: device, complex n x L (the last call's L), column-major.
+ *   S: device; moment p (n x L column-major) is written at S + p*s_stride
+ *      complex entries (s_stride 0: n*L).  A stride of n*L_total with S
+ *      offset by j*n*L places the block as columns j*L.. of moments with
+ *      L_total columns, for probe augmentation.
+ *   st as in nep_ciss_moments (non-NULL: synchronous).
+ * Errors: NEP_ERR_ARG if there are no resident factors or a call is still
+ * pending; otherwise as nep_ciss_moments. */
+nep_status nep_ciss_moments_more(nep_split h, const void* V, void* S,
+                                 long long s_stride, nep_ciss_stats* st);
+
+/* Number of eigenvalues inside the contour by the argument principle:
+ * eigenvalues are the zeros of det T(z) (Section 2, eq. (nep)), so the
+ * count is the winding number of det T along the contour, read from the LU
+ * factors at the nodes (det T(z_j) = sign(P) prod_k u_kk) as the sum of the
+ * phase steps between consecutive nodes, each taken in (-pi, pi].  It is
+ * exact when det T turns by less than pi between neighbouring nodes:
+ * *max_step (radians) reports the largest step, *winding the unrounded sum
+ * over 2 pi.
+ *   nep_ciss_count: from the factors resident from the last nep_ciss_moments
+ *   call on h (its N quadrature nodes; no further factorization).
+ *   nep_count_eigs: factors T at N nodes of g itself (4 <= N <= 4096) in the
+ *   given precision, without solves (use N well above the count).
+ * Errors: NEP_ERR_NOT_HOLOMORPHIC (a node on a pole or cut),
+ * NEP_ERR_SINGULAR (det T(z_j) zero in the factor precision). */
+nep_status nep_ciss_count(nep_split h, int* count, double* max_step, double* winding);
+nep_status nep_count_eigs(nep_split h, const nep_contour* g, int N, int prec,
+                          int* count, double* max_step, double* winding);
+
 /* ------------------------------------------------------------------------ */
 /* Extraction (minimal invariant pair, Section 2)                            */
 /* ------------------------------------------------------------------------ */
@@ -239,6 +271,22 @@ nep_status nep_extract(nep_split h, const nep_contour* g, const nep_ciss_opts* o
                        const void* S, const nep_extract_opts* e, int* m,
                        double* lambda, void* X, double* eta, int* inside,
                        double* sigma);
+
+/* Eigenvalues inside the contour end to end, with probe augmentation:
+ * moments with the first L = o->L columns of V, extraction, and while the
+ * moments' rank saturates (NEP_ERR_RANK with every one of the K*L singular
+ * values significant) the next L columns are solved on the resident factors
+ * (nep_ciss_moments_more) and the extraction is repeated on the moments of
+ * all probes so far, up to Lmax columns.
+ *   V: device, complex n x Lmax column-major (the probe pool; Lmax a
+ *      multiple of L, <= 256).  Outputs as nep_extract, with sigma holding
+ *      K*Lmax doubles; *L_used: probe columns in the final moments; st: the
+ *      first moments call's stats (optional).
+ * Returns nep_extract's status for the last extraction. */
+nep_status nep_eigs(nep_split h, const nep_contour* g, const nep_ciss_opts* o,
+                    const nep_extract_opts* e, const void* V, int Lmax, int* m,
+                    double* lambda, void* X, double* eta, int* inside,
+                    double* sigma, int* L_used, nep_ciss_stats* st);
 
 /* Backward errors eq. (sressplit) (inf-norms) of m given pairs.
  *   lambda: host, m complex; X: device, complex n x m column-major;

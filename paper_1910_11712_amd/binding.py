@@ -118,6 +118,13 @@ def lib():
         L.nep_ciss_moments.argtypes = [vp, C.POINTER(nep_contour), C.POINTER(nep_ciss_opts), vp, vp,
                                        C.POINTER(nep_ciss_stats)]
         L.nep_ciss_wait.argtypes = [vp, C.POINTER(nep_ciss_stats)]
+        L.nep_ciss_moments_more.argtypes = [vp, vp, vp, C.c_longlong, C.POINTER(nep_ciss_stats)]
+        L.nep_ciss_count.argtypes = [vp, C.POINTER(ip), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.nep_count_eigs.argtypes = [vp, C.POINTER(nep_contour), ip, ip, C.POINTER(ip), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]
+        L.nep_eigs.argtypes = [vp, C.POINTER(nep_contour), C.POINTER(nep_ciss_opts), C.POINTER(nep_extract_opts), vp,
+                               ip, C.POINTER(ip), C.POINTER(C.c_double), vp, C.POINTER(C.c_double), C.POINTER(ip),
+                               C.POINTER(C.c_double), C.POINTER(ip), C.POINTER(nep_ciss_stats)]
         L.nep_extract.argtypes = [vp, C.POINTER(nep_contour), C.POINTER(nep_ciss_opts), vp,
                                   C.POINTER(nep_extract_opts), C.POINTER(ip), C.POINTER(C.c_double), vp,
                                   C.POINTER(C.c_double), C.POINTER(ip), C.POINTER(C.c_double)]
@@ -264,6 +271,53 @@ def nep_ciss_moments(h, contour, opts, V, S, sync=True):
                                   C.c_void_p(S.data_ptr()), C.byref(st) if st is not None else None)
     check(code)
     return st.as_dict() if st is not None else None
+
+
+def nep_ciss_moments_more(h, V, S, s_stride=0, offset=0):
+    """Moments of the probes V (device (L, n) tensor) on the resident
+    factors, written into S's storage from element `offset` with moment
+    blocks s_stride elements apart (0: n*L).  Synchronous; returns stats."""
+    st = nep_ciss_stats()
+    ptr = S.data_ptr() + 16 * int(offset)
+    check(lib().nep_ciss_moments_more(h, C.c_void_p(V.data_ptr()), C.c_void_p(ptr), int(s_stride), C.byref(st)))
+    return st.as_dict()
+
+
+def nep_ciss_count(h):
+    """(count, max_step, winding) from the resident factors."""
+    c, ms, w = C.c_int(0), C.c_double(0), C.c_double(0)
+    check(lib().nep_ciss_count(h, C.byref(c), C.byref(ms), C.byref(w)))
+    return c.value, ms.value, w.value
+
+
+def nep_count_eigs(h, contour, N, prec="mixed"):
+    c, ms, w = C.c_int(0), C.c_double(0), C.c_double(0)
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    check(lib().nep_count_eigs(h, C.byref(contour_struct(contour)), int(N), p, C.byref(c), C.byref(ms), C.byref(w)))
+    return c.value, ms.value, w.value
+
+
+def nep_eigs(h, contour, opts, V, Lmax, X, max_eigs=64, rank_tol=0.0, eta_tol=0.0, polish_its=0):
+    """End to end with probe augmentation.  V: device (Lmax, n) tensor."""
+    e = nep_extract_opts()
+    e.rank_tol, e.eta_tol, e.max_eigs, e.polish_its = float(rank_tol), float(eta_tol), int(max_eigs), int(polish_its)
+    m, lu = C.c_int(0), C.c_int(0)
+    lam = np.zeros(2 * max_eigs)
+    eta = np.zeros(max_eigs)
+    ins = np.zeros(max_eigs, dtype=np.int32)
+    sig = np.zeros(opts.K * Lmax)
+    st = nep_ciss_stats()
+    code = lib().nep_eigs(h, C.byref(contour_struct(contour)), C.byref(opts), C.byref(e), C.c_void_p(V.data_ptr()),
+                          int(Lmax), C.byref(m), lam.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(X.data_ptr()),
+                          eta.ctypes.data_as(C.POINTER(C.c_double)), ins.ctypes.data_as(C.POINTER(C.c_int)),
+                          sig.ctypes.data_as(C.POINTER(C.c_double)), C.byref(lu), C.byref(st))
+    k = m.value
+    if code != NEP_OK:
+        err = NepError(code, lib().nep_last_error().decode())
+        err.m, err.L_used = k, lu.value
+        raise err
+    return {"m": k, "lam": lam[0:2 * k:2] + 1j * lam[1:2 * k:2], "eta": eta[:k].copy(), "inside": ins[:k] == 1,
+            "unconverged": ins[:k] == 2, "sigma": sig, "L_used": lu.value, "stats": st.as_dict()}
 
 
 def nep_ciss_wait(h):

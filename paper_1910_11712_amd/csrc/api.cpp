@@ -1,4 +1,6 @@
 // C ABI of libnep: split-operator handles, moments, batches (see nep.h).
+#include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstring>
 #include <memory>
@@ -213,13 +215,15 @@ nep_status check_opts(const nep_ciss_opts* o, PlanOptions& po) {
 }
 
 nep_status Split::moments(const nep_contour* g, const nep_ciss_opts* o, const void* V, void* S,
-                          nep_ciss_stats* st) {
+                          nep_ciss_stats* st, long long s_stride) {
   NEP_TRY(check_contour(g));
   PlanOptions po;
   NEP_TRY(check_opts(o, po));
   NEP_CHECK(V != nullptr && S != nullptr, NEP_ERR_ARG, "null V or S");
+  NEP_CHECK(s_stride == 0 || s_stride >= (long long)op.n * po.L, NEP_ERR_ARG, "moment stride below n*L");
   hipStream_t s = o->stream ? (hipStream_t)o->stream : stream;
-  std::vector<PlanProblem> probs{PlanProblem{&op, *g, (const c128*)V, (c128*)S}};
+  std::vector<PlanProblem> probs{PlanProblem{&op, *g, (const c128*)V, (c128*)S, nullptr, s_stride}};
+  last_g = *g;
   if (!plan || !plan->matches(probs, po) || plan->opt.max_refine != po.max_refine ||
       plan->opt.fallback != po.fallback) {
     plan = std::make_unique<MomentsPlan>();
@@ -252,6 +256,35 @@ nep_status Split::moments(const nep_contour* g, const nep_ciss_opts* o, const vo
   (void)hipEventDestroy(e1);
   st->ms_total = ms;
   return ws;
+}
+
+nep_status Split::moments_more(const void* V, void* S, long long s_stride, void* strm, nep_ciss_stats* st) {
+  NEP_CHECK(plan != nullptr, NEP_ERR_ARG, "no resident factors: call nep_ciss_moments on this handle first");
+  NEP_CHECK(!pending, NEP_ERR_ARG, "the last moments call on this handle has not been waited for");
+  NEP_CHECK(V != nullptr && S != nullptr, NEP_ERR_ARG, "null V or S");
+  NEP_CHECK(s_stride == 0 || s_stride >= (long long)op.n * plan->opt.L, NEP_ERR_ARG, "moment stride below n*L");
+  hipStream_t s = strm ? (hipStream_t)strm : (last_stream ? last_stream : stream);
+  std::vector<PlanProblem> probs{PlanProblem{&op, last_g, (const c128*)V, (c128*)S, nullptr, s_stride}};
+  NEP_TRY(plan->rebind(probs));
+  last_stream = s;
+  NEP_TRY(plan->enqueue(s, true, false));
+  pending = true;
+  if (!st) return NEP_OK;
+  return wait(st);
+}
+
+void winding_count(const std::vector<double>& arg, int* count, double* max_step, double* winding) {
+  const int N = (int)arg.size();
+  double tot = 0.0, mx = 0.0;
+  for (int j = 0; j < N; ++j) {
+    const double d = std::remainder(arg[(j + 1) % N] - arg[j], 2.0 * M_PI);
+    tot += d;
+    mx = std::max(mx, std::fabs(d));
+  }
+  const double w = tot / (2.0 * M_PI);
+  if (count) *count = (int)std::lround(w);
+  if (max_step) *max_step = mx;
+  if (winding) *winding = w;
 }
 
 nep_status Split::wait(nep_ciss_stats* st) {

@@ -51,6 +51,7 @@ struct ProbDesc {
   c128* S;                // caller moments, column-major n x L x KK
   const c128* zpts;       // explicit points (N, device) instead of the contour's
                           // nodes, or nullptr
+  long long s_stride;     // elements between consecutive moment blocks of S (>= n*L)
 };
 
 // Per-node arrays (global node index g).

@@ -32,7 +32,7 @@ struct ExtractWork {
 std::shared_ptr<ExtractWork> make_extract_work() { return std::make_shared<ExtractWork>(); }
 
 // ---------------------------------------------------------------------------
-__global__ void k_hankel(const c128* __restrict__ S, int n, int L, int K, c128* __restrict__ B0,
+__global__ void k_hankel(const c128* __restrict__ S, int n, int L, int K, long long sstride, c128* __restrict__ B0,
                          c128* __restrict__ B1) {
   const long long M = (long long)K * n, KL = (long long)K * L;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -41,8 +41,8 @@ __global__ void k_hankel(const c128* __restrict__ S, int n, int L, int K, c128* 
   const int r = (int)(row / n), i = (int)(row - (long long)r * n);
   const int s = (int)(col / L), c = (int)(col - (long long)s * L);
   const long long off = (long long)c * n + i;
-  B0[e] = S[(long long)(r + s) * n * L + off];
-  B1[e] = S[(long long)(r + s + 1) * n * L + off];
+  B0[e] = S[(long long)(r + s) * sstride + off];
+  B1[e] = S[(long long)(r + s + 1) * sstride + off];
 }
 
 // block sum over 1024 threads
@@ -433,13 +433,22 @@ static nep_status backward_errors_noalloc(Split& h, int m, const double* lambda,
 nep_status extract(Split& h, const nep_contour* g, const nep_ciss_opts* o, const void* S,
                    const nep_extract_opts* e, int* m_out, double* lambda, void* X, double* eta, int* inside,
                    double* sigma, ExtractWork* wk) {
+  PlanOptions po;
+  NEP_TRY(check_opts(o, po));
+  return extract_strided(h, g, o, po.L, S, 0, e, m_out, lambda, X, eta, inside, sigma, wk);
+}
+
+nep_status extract_strided(Split& h, const nep_contour* g, const nep_ciss_opts* o, int L_eff, const void* S,
+                           long long sstride, const nep_extract_opts* e, int* m_out, double* lambda, void* X,
+                           double* eta, int* inside, double* sigma, ExtractWork* wk) {
   NEP_TRY(check_contour(g));
   PlanOptions po;
   NEP_TRY(check_opts(o, po));
   NEP_CHECK(e != nullptr && e->max_eigs >= 1, NEP_ERR_ARG, "extract options: max_eigs must be >= 1");
   NEP_CHECK(e->rank_tol >= 0.0 && e->eta_tol >= 0.0, NEP_ERR_ARG, "extract options: tolerances must be >= 0");
   NEP_CHECK(S != nullptr && X != nullptr && m_out && lambda && eta && inside, NEP_ERR_ARG, "null output array");
-  const int n = h.op.n, L = po.L, K = po.K;
+  const int n = h.op.n, L = L_eff, K = po.K;
+  if (sstride <= 0) sstride = (long long)n * L;
   const long long M = (long long)K * n;
   const int KL = K * L;
   NEP_CHECK(KL <= M, NEP_ERR_ARG, "K*L exceeds K*n");
@@ -456,8 +465,8 @@ nep_status extract(Split& h, const nep_contour* g, const nep_ciss_opts* o, const
   c128* B1 = w.B1.as<c128>();
   c128* tau = w.tau.as<c128>();
   const long long tot = M * KL;
-  hipLaunchKernelGGL(k_hankel, dim3((unsigned)ceil_div_ll(tot, 256)), dim3(256), 0, st, (const c128*)S, n, L, K, B0,
-                     B1);
+  hipLaunchKernelGGL(k_hankel, dim3((unsigned)ceil_div_ll(tot, 256)), dim3(256), 0, st, (const c128*)S, n, L, K,
+                     sstride, B0, B1);
   NEP_HIP(hipGetLastError());
   for (int k = 0; k < KL; ++k) {
     hipLaunchKernelGGL(k_house_vec, dim3(1), dim3(1024), 0, st, B0, M, k, tau);

@@ -21,9 +21,14 @@ struct Split {
   std::unique_ptr<MomentsPlan> plan;  // resident factors of the last call
   std::shared_ptr<ExtractWork> xw;
   bool pending = false;
+  nep_contour last_g{};               // contour of the last moments call
+  DevMem saug;                        // augmented moments of nep_eigs (grow-only)
 
   nep_status init(int n, int ell, const nep_mat* A, const nep_fn* f, hipStream_t st);
-  nep_status moments(const nep_contour* g, const nep_ciss_opts* o, const void* V, void* S, nep_ciss_stats* st);
+  nep_status moments(const nep_contour* g, const nep_ciss_opts* o, const void* V, void* S, nep_ciss_stats* st,
+                     long long s_stride = 0);
+  // moments of new probes on the factors resident from the last call
+  nep_status moments_more(const void* V, void* S, long long s_stride, void* stream, nep_ciss_stats* st);
   nep_status wait(nep_ciss_stats* st);
   nep_status eval_fns(int m, const c128* zh, std::vector<c128>& out, std::vector<int>& bad, bool deriv);
 };
@@ -38,6 +43,15 @@ std::shared_ptr<ExtractWork> make_extract_work();
 nep_status extract(Split& h, const nep_contour* g, const nep_ciss_opts* o, const void* S,
                    const nep_extract_opts* e, int* m_out, double* lambda, void* X, double* eta, int* inside,
                    double* sigma, ExtractWork* wk);
+// The same with L_eff probe columns in S and moment blocks sstride elements
+// apart (0: n * L_eff), for moments augmented by further probe blocks.
+nep_status extract_strided(Split& h, const nep_contour* g, const nep_ciss_opts* o, int L_eff, const void* S,
+                           long long sstride, const nep_extract_opts* e, int* m_out, double* lambda, void* X,
+                           double* eta, int* inside, double* sigma, ExtractWork* wk);
+// Winding number of det T(z) along the nodes' closed polygon from per-node
+// arguments in node order: count = round(total / 2 pi), with the largest
+// phase step.
+void winding_count(const std::vector<double>& arg, int* count, double* max_step, double* winding);
 
 }  // namespace nep
 

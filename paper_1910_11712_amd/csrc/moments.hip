@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kMomThreads) void k_moments(const ProbDesc* __restr
   }
 #pragma unroll
   for (int q = 0; q < kMomQ; ++q)
-    if (q0 + q < KK) D.S[(long long)(q0 + q) * nl + (long long)c * n + r] = acc[q];
+    if (q0 + q < KK) D.S[(long long)(q0 + q) * D.s_stride + (long long)c * n + r] = acc[q];
 }
 
 hipError_t launch_moments(const ProbDesc* pd, const int* prefix, const Table& t, const NodeArrays& na,

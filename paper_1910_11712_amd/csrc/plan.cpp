@@ -205,6 +205,7 @@ nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs) {
     D.fn_nodes = q.op->dfn_nodes;
     D.fn_coef = q.op->dfn_coef;
     D.zpts = q.zpts;
+    D.s_stride = q.s_stride > 0 ? q.s_stride : (long long)D.n * D.L;
   }
   NEP_HIP(hipMemcpy(dpd_.p, hpd_.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice));
   return NEP_OK;
@@ -377,7 +378,7 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
 }
 
 template <typename P>
-nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
+nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager, bool refactor) {
   const ProbDesc* pd = dpd_.as<ProbDesc>();
   const MatDesc* md = dmd_.as<MatDesc>();
   const int* pre = dprefix_.as<int>();
@@ -388,18 +389,20 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager) {
   int* info = dinfo_.as<int>();
   NEP_HIP(ir_reset(ir_, nnodes, st));
   NEP_HIP(launch_coef(pd, na_, nnodes, ir_, st));
-  NEP_HIP(launch_assemble<P>(pd, pre, pt_.assemble, na_, T, nullptr, st));
+  if (refactor) NEP_HIP(launch_assemble<P>(pd, pre, pt_.assemble, na_, T, nullptr, st));
   // the probe norms are first read by the refinement test; queued behind the
   // assembly they start without a launch gap
   NEP_HIP(launch_vnorm(pd, nprob, opt.L, ir_, st));
   cx<P>* Dinv = ddinv_.as<cx<P>>();
   const long long* doff = ddinv_off_.as<long long>();
-  if (eager) NEP_HIP(hipEventRecord(ev_lu_[0], st));
-  NEP_HIP(lu_run<P>(lu_, md, dlu_prefix_.as<int>(), T, rows, drows_snap_.as<int>(), rows_total_, info, nullptr,
-                    dlinv_.as<cx<P>>(), Dinv, doff, darrive_.as<int>(), st, ls_));
-  if (eager) {
-    NEP_HIP(hipEventRecord(ev_lu_[1], st));
-    lu_timed_ = true;
+  if (refactor) {  // otherwise the factors (and info) of the previous pass are reused
+    if (eager) NEP_HIP(hipEventRecord(ev_lu_[0], st));
+    NEP_HIP(lu_run<P>(lu_, md, dlu_prefix_.as<int>(), T, rows, drows_snap_.as<int>(), rows_total_, info, nullptr,
+                      dlinv_.as<cx<P>>(), Dinv, doff, darrive_.as<int>(), st, ls_));
+    if (eager) {
+      NEP_HIP(hipEventRecord(ev_lu_[1], st));
+      lu_timed_ = true;
+    }
   }
   NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, nullptr, Y, false, nullptr, ir_, st));
   sweeps_run_ = 0;
@@ -520,10 +523,30 @@ nep_status MomentsPlan::solve_rhs(hipStream_t st) {
   return solve_rhs_t<float>(st);
 }
 
-nep_status MomentsPlan::enqueue(hipStream_t st, bool eager) {
+nep_status MomentsPlan::enqueue(hipStream_t st, bool eager, bool refactor) {
   fallback_pending_ = false;
-  if (opt.prec == NEP_PREC_FP64) return enqueue_t<double>(st, eager);
-  return enqueue_t<float>(st, eager);
+  if (opt.prec == NEP_PREC_FP64) return enqueue_t<double>(st, eager, refactor);
+  return enqueue_t<float>(st, eager, refactor);
+}
+
+template <typename P>
+hipError_t logdet_run(const MatDesc* md, int nmat, const cx<P>* T, const int* rows, double* out, hipStream_t st);
+
+nep_status MomentsPlan::logdet(hipStream_t st, std::vector<double>& logabs, std::vector<double>& arg) {
+  DevMem out;
+  NEP_TRY(out.alloc(sizeof(double) * 2 * (size_t)nnodes));
+  if (opt.prec == NEP_PREC_FP64)
+    NEP_HIP(logdet_run<double>(dmd_.as<MatDesc>(), (int)sorted_.size(), dT_.as<c128>(), drows_.as<int>(),
+                               out.as<double>(), st));
+  else
+    NEP_HIP(logdet_run<float>(dmd_.as<MatDesc>(), (int)sorted_.size(), dT_.as<c64>(), drows_.as<int>(),
+                              out.as<double>(), st));
+  std::vector<double> h(2 * (size_t)nnodes);
+  NEP_HIP(hipMemcpyAsync(h.data(), out.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+  NEP_HIP(hipStreamSynchronize(st));
+  logabs.assign(h.begin(), h.begin() + nnodes);
+  arg.assign(h.begin() + nnodes, h.end());
+  return NEP_OK;
 }
 
 nep_status MomentsPlan::finish(hipStream_t st, RunResult& out, bool allow_fallback) {
@@ -665,7 +688,7 @@ nep_status configure_kernels() {
   return NEP_OK;
 }
 
-template nep_status MomentsPlan::enqueue_t<float>(hipStream_t, bool);
-template nep_status MomentsPlan::enqueue_t<double>(hipStream_t, bool);
+template nep_status MomentsPlan::enqueue_t<float>(hipStream_t, bool, bool);
+template nep_status MomentsPlan::enqueue_t<double>(hipStream_t, bool, bool);
 
 }  // namespace nep

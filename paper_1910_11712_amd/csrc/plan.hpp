@@ -87,6 +87,7 @@ struct PlanProblem {
   const c128* V;
   c128* S;
   const c128* zpts = nullptr;  // explicit points (device, N) instead of g's nodes
+  long long s_stride = 0;      // elements between moment blocks of S; 0: n*L
 };
 
 struct PlanOptions {
@@ -122,7 +123,7 @@ class MomentsPlan {
   // Enqueues the whole moment path on st.  eager=true lets the host stop the
   // refinement loop early (one small read-back per sweep); eager=false runs a
   // fixed number of sweeps with device-side skipping (graph capture safe).
-  nep_status enqueue(hipStream_t st, bool eager);
+  nep_status enqueue(hipStream_t st, bool eager, bool refactor = true);
   // Waits, reads back device status and fills per-problem stats.  With
   // allow_fallback, nodes that a fixed-sweep (non-eager) run left
   // unconverged are re-solved in FP64 and the moments recomputed (if the
@@ -141,6 +142,10 @@ class MomentsPlan {
   c128* Y_mut() { return dY_.as<c128>(); }
   const NodeArrays& nodes() const { return na_; }
   const int* info() const { return dinfo_.as<int>(); }
+  // Per node (global index): log|det T(z_g)| and arg det T(z_g) in (-pi, pi]
+  // from the resident factors (the product of the pivots and the sign of the
+  // row permutation), read back to host arrays of nnodes entries.
+  nep_status logdet(hipStream_t st, std::vector<double>& logabs, std::vector<double>& arg);
   // Rebinds caller buffers (V, S) and contours without rebuilding.
   nep_status rebind(const std::vector<PlanProblem>& probs);
   bool matches(const std::vector<PlanProblem>& probs, const PlanOptions& o) const;
@@ -170,7 +175,7 @@ class MomentsPlan {
  private:
   nep_status upload_problems(const std::vector<PlanProblem>& probs);
   template <typename P>
-  nep_status enqueue_t(hipStream_t st, bool eager);
+  nep_status enqueue_t(hipStream_t st, bool eager, bool refactor);
   template <typename P>
   nep_status run_fallback(hipStream_t st);
   template <typename P>

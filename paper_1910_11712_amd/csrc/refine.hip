@@ -466,6 +466,67 @@ hipError_t min_pivot(const MatDesc* md, int nmat, const cx<P>* T, const int* row
   return hipGetLastError();
 }
 template hipError_t min_pivot<float>(const MatDesc*, int, const c64*, const int*, int, void*, hipStream_t);
+
+// log|det T| and arg det T of each node's factorization P T = L U (unit L):
+// det T = sign(P) prod_k u_kk, with u_kk = T[rows[k], k] and sign(P) the
+// parity of the row map k -> rows[k], counted by walking its cycles (one
+// thread, an LDS bitmap of visited rows; n <= 4096).  out[node] = log|det|,
+// out[nnodes + node] = arg det in (-pi, pi].
+constexpr int kLogdetMaxN = 4096;
+
+template <typename P>
+__global__ __launch_bounds__(256) void k_logdet(const MatDesc* __restrict__ md, const cx<P>* __restrict__ T,
+                                                const int* __restrict__ rows, int nnodes, double* __restrict__ out) {
+  __shared__ unsigned seen[kLogdetMaxN / 32];
+  __shared__ double rla[256], rar[256];
+  __shared__ int parity;
+  const MatDesc d = md[blockIdx.x];
+  double la = 0.0, ar = 0.0;
+  for (int k = threadIdx.x; k < d.n; k += blockDim.x) {
+    const cx<P> u = T[d.offT + (long long)rows[d.offRow + k] * d.ld + k];
+    const double re = double(u.re), im = double(u.im);
+    la += log(hypot(re, im));
+    ar += atan2(im, re);
+  }
+  for (int w = threadIdx.x; w < kLogdetMaxN / 32; w += blockDim.x) seen[w] = 0u;
+  rla[threadIdx.x] = la;
+  rar[threadIdx.x] = ar;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int cycles = 0;
+    for (int s = 0; s < d.n; ++s) {
+      if (seen[s >> 5] & (1u << (s & 31))) continue;
+      ++cycles;
+      int k = s;
+      for (int step = 0; step < d.n && k >= 0 && k < d.n && !(seen[k >> 5] & (1u << (k & 31))); ++step) {
+        seen[k >> 5] |= 1u << (k & 31);
+        k = rows[d.offRow + k];
+      }
+    }
+    parity = (d.n - cycles) & 1;
+  }
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      rla[threadIdx.x] += rla[threadIdx.x + s];
+      rar[threadIdx.x] += rar[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double a = rar[0] + (parity ? M_PI : 0.0);
+    a = remainder(a, 2.0 * M_PI);  // into [-pi, pi]
+    out[d.node] = rla[0];
+    out[nnodes + d.node] = a;
+  }
+}
+
+template <typename P>
+hipError_t logdet_run(const MatDesc* md, int nmat, const cx<P>* T, const int* rows, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_logdet<P>, dim3(nmat), dim3(256), 0, st, md, T, rows, nmat, out);
+  return hipGetLastError();
+}
+template hipError_t logdet_run<float>(const MatDesc*, int, const c64*, const int*, double*, hipStream_t);
+template hipError_t logdet_run<double>(const MatDesc*, int, const c128*, const int*, double*, hipStream_t);
 template hipError_t min_pivot<double>(const MatDesc*, int, const c128*, const int*, int, void*, hipStream_t);
 
 hipError_t gather_status(IrState ir, const int* info, const int* bad, int G, void* out, hipStream_t st) {
