@@ -9,9 +9,11 @@ package `workloads`, which holds no arithmetic of the method.
 from .ciss import (NotHolomorphic, SingularNode, RankSaturated, fn_value, fn_derivative,
                    quadrature, t_matrix, node_solve, ciss_moments,
                    block_hankel, extract, backward_error, relative_residual,
-                   inside_mask, t_derivative, rii_polish, eigenvalue_count)
+                   inside_mask, t_derivative, rii_polish, eigenvalue_count,
+                   left_eigenvector, apply_resolvent)
 
 __all__ = ["NotHolomorphic", "SingularNode", "RankSaturated", "fn_value", "fn_derivative",
            "quadrature", "t_matrix", "node_solve", "ciss_moments",
            "block_hankel", "extract", "backward_error", "relative_residual",
-           "inside_mask", "t_derivative", "rii_polish", "eigenvalue_count"]
+           "inside_mask", "t_derivative", "rii_polish", "eigenvalue_count",
+           "left_eigenvector", "apply_resolvent"]

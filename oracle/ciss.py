@@ -372,6 +372,29 @@ def rii_polish(problem, lam0, x0, tol, max_it=10, max_newton=30):
 
 
 # ---------------------------------------------------------------------------
+# Left eigenvectors and the resolvent (Section 2, eqs. (nep-left), (resolvent))
+# ---------------------------------------------------------------------------
+
+def left_eigenvector(problem, lam):
+    """y with y^* T(lambda) = 0 (eq. (nep-left)): the left singular vector of
+    T(lambda) for its smallest singular value (numpy.linalg.svd), normalized
+    as the extraction's eigenvectors."""
+    U, s, Wh = np.linalg.svd(t_matrix(problem, lam))
+    return _normalize(U[:, -1:].copy())[:, 0]
+
+
+def apply_resolvent(problem, lam, X, Y, z, V):
+    """sum_i (z - lambda_i)^{-1} x_i y_i^* V / (y_i^* T'(lambda_i) x_i): the
+    sum of Keldysh's expansion (eq. (resolvent)) with its normalization
+    y_i^* T'(lambda_i) x_i = 1 applied explicitly."""
+    W = np.zeros(np.asarray(V).shape, dtype=np.complex128)
+    for l, x, y in zip(np.atleast_1d(lam), np.asarray(X).T, np.asarray(Y).T):
+        c = np.vdot(y, t_derivative(problem, l) @ x)
+        W += np.outer(x, y.conj() @ V) / ((z - l) * c)
+    return W
+
+
+# ---------------------------------------------------------------------------
 # Residuals
 # ---------------------------------------------------------------------------
 

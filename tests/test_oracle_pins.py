@@ -433,6 +433,43 @@ def test_eigenvalue_count_argument_principle():
     assert step < 2.0 and cnt == int(np.sum(d < con.rho)) >= 3, (cnt, int(np.sum(d < con.rho)), step)
 
 
+def _linear(A):
+    n = A.shape[0]
+    return Problem("linear", [A, np.eye(n)], [wl.fn_rational([1.0]), wl.fn_rational([-1.0, 0.0])])
+
+
+def test_left_eigenvectors_vs_scipy():
+    """eq. (nep-left): for T(z) = A - z I the oracle's left eigenvectors equal
+    SciPy's left eigenvectors of A (up to the common normalization)."""
+    rng = np.random.default_rng(23)
+    A = rng.standard_normal((15, 15)) + 1j * rng.standard_normal((15, 15))
+    w, vl = scipy.linalg.eig(A, left=True, right=False)
+    p = _linear(A)
+    for k in (0, 4, 9):
+        y = oracle.left_eigenvector(p, w[k])
+        ref = vl[:, k] / np.linalg.norm(vl[:, k])
+        j = int(np.argmax(np.abs(ref)))
+        ref = ref * np.conj(ref[j]) / abs(ref[j])
+        assert np.linalg.norm(y - ref) < 1e-10
+        assert np.abs(y.conj() @ oracle.t_matrix(p, w[k])).max() < 1e-12 * np.abs(A).sum()
+
+
+def test_keldysh_resolvent_exact_for_linear_full_spectrum():
+    """eq. (resolvent): for T(z) = A - z I with every eigenvalue included the
+    holomorphic remainder vanishes, so the Keldysh sum (normalization
+    y^* T'(lambda) x = 1) is (A - z I)^{-1} exactly."""
+    rng = np.random.default_rng(29)
+    n = 12
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    w, vl, vr = scipy.linalg.eig(A, left=True, right=True)
+    p = _linear(A)
+    z = 0.3 + 5.0j
+    V = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+    W = oracle.apply_resolvent(p, w, vr, vl, z, V)
+    ref = np.linalg.solve(A - z * np.eye(n), V)
+    assert np.linalg.norm(W - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
 def test_config0_invariants():
     """P8: eigenvalues independent of V; conjugate symmetry of node solves."""
     cfg = wl.config0()
