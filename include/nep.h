@@ -288,6 +288,56 @@ nep_status nep_eigs(nep_split h, const nep_contour* g, const nep_ciss_opts* o,
                     double* lambda, void* X, double* eta, int* inside,
                     double* sigma, int* L_used, nep_ciss_stats* st);
 
+/* ------------------------------------------------------------------------ */
+/* Left eigenvectors and the resolvent (Section 2, eqs. (nep-left),          */
+/* (resolvent); Section 3.2.5)                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Handle of the adjoint operator T^*(z) = T(conj z)^* = sum_i conj(f_i(conj z))
+ * A_i^* (conjugate-transposed matrices; functions with conjugated
+ * coefficients and scales).  Its right eigenpairs (y, conj(lambda)) are the
+ * left eigenpairs of T: "left eigenvectors can be computed as right
+ * eigenvectors of T^*" (Section 2).  Every call of this header applies to it;
+ * run the moments with the conjugated contour (centre conj(c)).  Destroy
+ * with nep_split_destroy. */
+nep_status nep_split_adjoint(nep_split h, nep_split* out);
+
+/* Left eigenvectors y^* T(lambda) = 0 for m given eigenvalues, by residual
+ * inverse iteration on T^* with the target conj(lambda) (as nep_rii_polish on
+ * the adjoint, made and kept inside h on first use).
+ *   lambda: host 2m doubles (in: the eigenvalues; out: refined from the
+ *           left problem), Y: device complex n x m column-major (in: start
+ *           vectors, e.g. random; out: ||y||_2 = 1, largest-modulus entry
+ *           real positive), eta: host m doubles (out): backward errors of
+ *           (y, conj(lambda)) for T^* (eq. (sressplit), inf-norms of A_i^*).
+ *   max_it: 1..100 outer steps. */
+nep_status nep_left_eigenvectors(nep_split h, int m, double* lambda, void* Y,
+                                 double* eta, int max_it);
+
+/* Action of the resolvent's eigen-part on L vectors (NEPApplyResolvent):
+ *   W = sum_q (z - lambda_q)^{-1} x_q y_q^* V / (y_q^* T'(lambda_q) x_q),
+ * Keldysh's expansion (eq. (resolvent)) without its holomorphic remainder
+ * R(z), with the normalization y^* T'(lambda) x = 1 applied explicitly (so x
+ * and y may have any scaling).  Exact for T^{-1}(z) when the pairs are all
+ * of T's (semisimple) eigenvalues and R = 0, e.g. a linear T with every
+ * eigenvalue given.
+ *   lambda: host 2m doubles; X, Y: device complex n x m (right and left
+ *   eigenvectors); z: host complex (2 doubles), not an eigenvalue;
+ *   V: device complex n x L; W: device complex n x L (out).
+ * Errors: NEP_ERR_ARG if some y^* T'(lambda) x = 0 (not a simple
+ * eigenvalue). */
+nep_status nep_apply_resolvent(nep_split h, int m, const double* lambda,
+                               const void* X, const void* Y, const double* z,
+                               int L, const void* V, void* W);
+
+/* T(z_k)^{-1} V at m points z_k (host, 2m doubles): the full resolvent,
+ * by assembly, LU and solves in the given precision (the mixed path refines
+ * in FP64 as the moments do).  V: device complex n x L (L <= 64);
+ * Y: device, m blocks of n x L column-major (block k at Y + k*n*L).
+ * st: optional stats (synchronous either way). */
+nep_status nep_solve_at(nep_split h, int m, const double* z, int L,
+                        const void* V, int prec, void* Y, nep_ciss_stats* st);
+
 /* Backward errors eq. (sressplit) (inf-norms) of m given pairs.
  *   lambda: host, m complex; X: device, complex n x m column-major;
  *   eta: host, m doubles. */

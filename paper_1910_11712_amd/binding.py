@@ -132,6 +132,10 @@ def lib():
         L.nep_backward_error_noalloc.argtypes = [vp, ip, C.POINTER(C.c_double), vp, C.POINTER(C.c_double)]
         L.nep_rii_polish.argtypes = [vp, ip, C.POINTER(C.c_double), vp, C.POINTER(C.c_double), C.c_double, ip,
                                      C.POINTER(ip)]
+        L.nep_split_adjoint.argtypes = [vp, C.POINTER(vp)]
+        L.nep_left_eigenvectors.argtypes = [vp, ip, C.POINTER(C.c_double), vp, C.POINTER(C.c_double), ip]
+        L.nep_apply_resolvent.argtypes = [vp, ip, C.POINTER(C.c_double), vp, vp, C.POINTER(C.c_double), ip, vp, vp]
+        L.nep_solve_at.argtypes = [vp, ip, C.POINTER(C.c_double), ip, vp, ip, vp, C.POINTER(nep_ciss_stats)]
         L.nep_fn_eval.argtypes = [vp, ip, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.nep_fn_eval_derivative.argtypes = [vp, ip, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.nep_batch_create.argtypes = [ip, C.POINTER(vp), C.POINTER(nep_contour), C.POINTER(nep_ciss_opts),
@@ -375,6 +379,51 @@ def nep_rii_polish(h, lam, X, tol=0.0, max_it=10):
                                eta.ctypes.data_as(C.POINTER(C.c_double)), float(tol), int(max_it),
                                its.ctypes.data_as(C.POINTER(C.c_int))))
     return la[0::2] + 1j * la[1::2], eta, its
+
+
+def _cplx_host(vals):
+    vals = np.asarray(vals, dtype=np.complex128).ravel()
+    a = np.zeros(2 * len(vals))
+    a[0::2], a[1::2] = vals.real, vals.imag
+    return a
+
+
+def nep_split_adjoint(h):
+    out = C.c_void_p()
+    check(lib().nep_split_adjoint(h, C.byref(out)))
+    return out
+
+
+def nep_left_eigenvectors(h, lam, Y, max_it=10):
+    """Y: device tensor (m, n) of start vectors, overwritten with the left
+    eigenvectors; returns (lam, eta)."""
+    la = _cplx_host(lam)
+    m = len(la) // 2
+    eta = np.zeros(m)
+    check(lib().nep_left_eigenvectors(h, m, la.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(Y.data_ptr()),
+                                      eta.ctypes.data_as(C.POINTER(C.c_double)), int(max_it)))
+    return la[0::2] + 1j * la[1::2], eta
+
+
+def nep_apply_resolvent(h, lam, X, Y, z, V, W):
+    """X, Y: device (m, n); V, W: device (L, n) tensors."""
+    la = _cplx_host(lam)
+    zz = _cplx_host([z])
+    L = V.shape[0]
+    check(lib().nep_apply_resolvent(h, len(la) // 2, la.ctypes.data_as(C.POINTER(C.c_double)),
+                                    C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
+                                    zz.ctypes.data_as(C.POINTER(C.c_double)), int(L), C.c_void_p(V.data_ptr()),
+                                    C.c_void_p(W.data_ptr())))
+
+
+def nep_solve_at(h, z, V, Y, prec="fp64"):
+    """V: device (L, n); Y: device (m, L, n) tensor; returns stats."""
+    zz = _cplx_host(z)
+    st = nep_ciss_stats()
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    check(lib().nep_solve_at(h, len(zz) // 2, zz.ctypes.data_as(C.POINTER(C.c_double)), int(V.shape[0]),
+                             C.c_void_p(V.data_ptr()), p, C.c_void_p(Y.data_ptr()), C.byref(st)))
+    return st.as_dict()
 
 
 def nep_backward_error_noalloc(h, lam, X):

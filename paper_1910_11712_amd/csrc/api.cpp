@@ -107,6 +107,8 @@ nep_status Split::init(int n_, int ell_, const nep_mat* A, const nep_fn* f, hipS
   NEP_HIP(hipMemcpy(fn_roots.p, op.fn_root, sizeof(int) * kMaxTerms, hipMemcpyHostToDevice));
   op.dfn_nodes = fn_nodes.as<FnNode>();
   op.dfn_coef = fn_coef.as<c128>();
+  h_fn_nodes = nodes;
+  h_fn_coef = coef;
   // matrices: upload column-major, convert to row-major on the device
   NEP_TRY(norms.alloc(sizeof(double) * kMaxTerms + sizeof(unsigned long long) * 2));
   op.dnormA = norms.as<double>();
@@ -165,6 +167,67 @@ nep_status Split::init(int n_, int ell_, const nep_mat* A, const nep_fn* f, hipS
 
 hipError_t fn_points_d(const FnNode* nodes, const c128* coef, const int* roots, int ell, const c128* z, int m,
                        c128* out, int* bad, hipStream_t st);
+
+hipError_t adjoint_copy(const void* src, int n, int cplx, void* dst, hipStream_t st);
+hipError_t conj_copy(const c128* src, int n, c128* dst, hipStream_t st);
+
+Split::~Split() {
+  if (adj) {
+    nep_split a = adj;
+    adj = nullptr;
+    (void)nep_split_destroy(&a);
+  }
+}
+
+nep_status Split::init_adjoint(const Split& src) {
+  stream = src.stream;
+  op.n = src.op.n;
+  op.ell = src.op.ell;
+  // f^*(z) = conj(f(conj z)) = conj(beta) g^*(conj(alpha) z), g^* the same
+  // function with conjugated coefficients (exp, log, sqrt, 1/sqrt and phi_k
+  // have real coefficients and cuts symmetric about the real axis)
+  h_fn_nodes = src.h_fn_nodes;
+  h_fn_coef = src.h_fn_coef;
+  for (auto& nd : h_fn_nodes) {
+    nd.alpha.im = -nd.alpha.im;
+    nd.beta.im = -nd.beta.im;
+  }
+  for (auto& c : h_fn_coef) c.im = -c.im;
+  NEP_TRY(fn_nodes.alloc(sizeof(FnNode) * h_fn_nodes.size()));
+  NEP_TRY(fn_coef.alloc(sizeof(c128) * h_fn_coef.size()));
+  NEP_TRY(fn_roots.alloc(sizeof(int) * kMaxTerms));
+  NEP_HIP(hipMemcpy(fn_nodes.p, h_fn_nodes.data(), sizeof(FnNode) * h_fn_nodes.size(), hipMemcpyHostToDevice));
+  NEP_HIP(hipMemcpy(fn_coef.p, h_fn_coef.data(), sizeof(c128) * h_fn_coef.size(), hipMemcpyHostToDevice));
+  for (int i = 0; i < kMaxTerms; ++i) op.fn_root[i] = src.op.fn_root[i];
+  NEP_HIP(hipMemcpy(fn_roots.p, op.fn_root, sizeof(int) * kMaxTerms, hipMemcpyHostToDevice));
+  op.dfn_nodes = fn_nodes.as<FnNode>();
+  op.dfn_coef = fn_coef.as<c128>();
+  NEP_TRY(norms.alloc(sizeof(double) * kMaxTerms + sizeof(unsigned long long) * 2));
+  op.dnormA = norms.as<double>();
+  unsigned long long* scratch = reinterpret_cast<unsigned long long*>(norms.as<char>() + sizeof(double) * kMaxTerms);
+  op.a_cplx = src.op.a_cplx;
+  const int n = op.n;
+  for (int i = 0; i < op.ell; ++i) {
+    const int cplx = src.op.is_cplx[i];
+    op.is_cplx[i] = cplx;
+    mats[i] = std::make_unique<DevMem>();
+    NEP_TRY(mats[i]->alloc((size_t)n * n * (cplx ? 2 : 1) * sizeof(double)));
+    NEP_HIP(adjoint_copy(src.op.dA[i], n, cplx, mats[i]->p, stream));
+    if (src.op.is_diag[i]) {
+      diags[i] = std::make_unique<DevMem>();
+      NEP_TRY(diags[i]->alloc(sizeof(c128) * n));
+      NEP_HIP(conj_copy(src.op.dDiag[i], n, diags[i]->as<c128>(), stream));
+      op.is_diag[i] = 1;
+      op.dDiag[i] = diags[i]->as<c128>();
+    }
+    NEP_HIP(inf_norm(mats[i]->p, n, cplx, scratch, norms.as<double>() + i, stream));
+    NEP_HIP(hipStreamSynchronize(stream));
+    op.dA[i] = mats[i]->p;
+  }
+  op.normA.assign(op.ell, 0.0);
+  NEP_HIP(hipMemcpy(op.normA.data(), op.dnormA, sizeof(double) * op.ell, hipMemcpyDeviceToHost));
+  return NEP_OK;
+}
 
 nep_status Split::eval_fns(int m, const c128* zh, std::vector<c128>& out, std::vector<int>& bad, bool deriv) {
   DevMem dz, dout, dbad;

@@ -23,6 +23,13 @@ struct Split {
   bool pending = false;
   nep_contour last_g{};               // contour of the last moments call
   DevMem saug;                        // augmented moments of nep_eigs (grow-only)
+  std::vector<FnNode> h_fn_nodes;     // host copies of the function tree
+  std::vector<c128> h_fn_coef;
+  struct nep_split_s* adj = nullptr;  // the adjoint operator T^*, made on demand
+  ~Split();
+  // T^*(z) = T(conj z)^*: conjugate-transposed A_i, functions with conjugated
+  // parameters (f^*(z) = conj(f(conj z)))
+  nep_status init_adjoint(const Split& src);
 
   nep_status init(int n, int ell, const nep_mat* A, const nep_fn* f, hipStream_t st);
   nep_status moments(const nep_contour* g, const nep_ciss_opts* o, const void* V, void* S, nep_ciss_stats* st,

@@ -73,6 +73,13 @@ __global__ __launch_bounds__(256) void k_term_apply(int n, int ell, int P, const
     }
 }
 
+hipError_t term_apply(int n, int ell, int P, const double* const* A, const int* cplx, const c128* X, c128* R,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_term_apply, dim3(ceil_div(n, 64), ceil_div(P, 16), ell), dim3(256), 0, st, n, ell, P, A, cplx,
+                     X, R);
+  return hipGetLastError();
+}
+
 __device__ __forceinline__ c128 block_sum256(c128 v, c128* red) {
   for (int o = 32; o >= 1; o >>= 1) {
     v.re += __shfl_xor(v.re, o, 64);

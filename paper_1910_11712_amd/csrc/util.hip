@@ -69,6 +69,50 @@ hipError_t inf_norm(const void* A, int n, int cplx, unsigned long long* scratch,
   return hipGetLastError();
 }
 
+// dst = src^* (conjugate transpose) of a row-major n x n matrix, real or
+// complex, through 32 x 32 LDS tiles.
+__global__ void k_adjoint_copy(const double* __restrict__ src, int n, int cplx, double* __restrict__ dst) {
+  __shared__ double tre[32][33], tim[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int r = by + k, c = bx + threadIdx.x;
+    if (r < n && c < n) {
+      const long long e = (long long)r * n + c;
+      tre[k][threadIdx.x] = cplx ? src[2 * e] : src[e];
+      tim[k][threadIdx.x] = cplx ? src[2 * e + 1] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int r = bx + k, c = by + threadIdx.x;  // dst[r][c] = conj(src[c][r])
+    if (r < n && c < n) {
+      const long long e = (long long)r * n + c;
+      if (cplx) {
+        dst[2 * e] = tre[threadIdx.x][k];
+        dst[2 * e + 1] = -tim[threadIdx.x][k];
+      } else {
+        dst[e] = tre[threadIdx.x][k];
+      }
+    }
+  }
+}
+
+hipError_t adjoint_copy(const void* src, int n, int cplx, void* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_adjoint_copy, dim3(ceil_div(n, 32), ceil_div(n, 32)), dim3(32, 8), 0, st,
+                     static_cast<const double*>(src), n, cplx, static_cast<double*>(dst));
+  return hipGetLastError();
+}
+
+__global__ void k_conj_copy(const c128* __restrict__ src, int n, c128* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = conj(src[i]);
+}
+
+hipError_t conj_copy(const c128* src, int n, c128* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_conj_copy, dim3(ceil_div(n, 256)), dim3(256), 0, st, src, n, dst);
+  return hipGetLastError();
+}
+
 // f_i(z_k) for k < m, i < ell; out[i*m + k]; bad flags per point.
 __global__ void k_fn_points(const FnNode* __restrict__ nodes, const c128* __restrict__ coef, const int* __restrict__ roots,
                             int ell, const c128* __restrict__ z, int m, c128* __restrict__ out, int* __restrict__ bad) {
