@@ -76,6 +76,7 @@ nep_status nep_batch_run(nep_batch b, nep_ciss_stats* st) {
   Batch& B = b->impl;
   if (B.use_graph) {
     NEP_HIP(hipGraphLaunch(B.exec, B.stream));
+    B.plan->replayed();
   } else {
     NEP_TRY(B.plan->enqueue(B.stream, false));
   }

@@ -124,6 +124,12 @@ class MomentsPlan {
   // refinement loop early (one small read-back per sweep); eager=false runs a
   // fixed number of sweeps with device-side skipping (graph capture safe).
   nep_status enqueue(hipStream_t st, bool eager, bool refactor = true);
+  // A replay of a captured enqueue was launched: the next finish() starts
+  // from the graph's own state (no FP64 re-solve of this run done yet).
+  void replayed() {
+    fallback_pending_ = false;
+    lu_timed_ = false;
+  }
   // Waits, reads back device status and fills per-problem stats.  With
   // allow_fallback, nodes that a fixed-sweep (non-eager) run left
   // unconverged are re-solved in FP64 and the moments recomputed (if the
