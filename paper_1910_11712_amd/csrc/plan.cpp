@@ -265,7 +265,6 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
 
   lu_.build(sorted_, o.prec);
   const bool mixed = o.prec == NEP_PREC_C32_IR64;
-  if (mixed && o.fallback) lu64_.build(sorted_, NEP_PREC_FP64);
 
   hprefix_.clear();
   SolvePlan_build(sp_, hprefix_, sorted_, o.L, o.prec, dinv_off_, dinv_elems_);
@@ -296,7 +295,6 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   NEP_TRY(A(dmd_, sizeof(MatDesc) * sorted_.size()));
   NEP_TRY(A(dprefix_, sizeof(int) * hprefix_.size()));
   NEP_TRY(A(dlu_prefix_, sizeof(int) * std::max<size_t>(1, lu_.prefix.size())));
-  if (mixed && o.fallback) NEP_TRY(A(dlu64_prefix_, sizeof(int) * std::max<size_t>(1, lu64_.prefix.size())));
   NEP_TRY(A(dT_, es * (size_t)t_elems_));
   NEP_TRY(A(drows_, sizeof(int) * (size_t)rows_total_));
   NEP_TRY(A(drows_snap_, sizeof(int) * (size_t)rows_total_));
@@ -364,9 +362,6 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   NEP_HIP(hipMemcpy(dprefix_.p, hprefix_.data(), sizeof(int) * hprefix_.size(), hipMemcpyHostToDevice));
   if (!lu_.prefix.empty())
     NEP_HIP(hipMemcpy(dlu_prefix_.p, lu_.prefix.data(), sizeof(int) * lu_.prefix.size(), hipMemcpyHostToDevice));
-  if (mixed && o.fallback && !lu64_.prefix.empty())
-    NEP_HIP(hipMemcpy(dlu64_prefix_.p, lu64_.prefix.data(), sizeof(int) * lu64_.prefix.size(),
-                      hipMemcpyHostToDevice));
   NEP_HIP(hipMemcpy(ddinv_off_.p, dinv_off_.data(), sizeof(long long) * dinv_off_.size(), hipMemcpyHostToDevice));
   NEP_HIP(hipMemcpy(na_.prob, hprob.data(), sizeof(int) * G, hipMemcpyHostToDevice));
   na_prob_host_ = hprob;
@@ -474,8 +469,36 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
   NEP_HIP(launch_assemble<double>(pd, pre, pt_.assemble, na_, T, skip, st));
   c128* Dinv = ddinv64_.as<c128>();
   const long long* doff = ddinv_off_.as<long long>();
-  NEP_HIP(lu_run<double>(lu64_, md, dlu64_prefix_.as<int>(), T, drows_.as<int>(), drows_snap_.as<int>(), rows_total_,
-                         dinfo_.as<int>(), skip, dlinv64_.as<c128>(), Dinv, doff, darrive_.as<int>(), st, ls_));
+  {
+    // factor only the unconverged matrices: a compact plan over them (in the
+    // size order of the full plan), whose diagonal-block inverses land where
+    // the full plan's solve looks for them
+    std::vector<int> conv(nnodes);
+    NEP_HIP(hipMemcpy(conv.data(), ir_.conv, sizeof(int) * nnodes, hipMemcpyDeviceToHost));
+    std::vector<MatDesc> sub;
+    std::vector<long long> sub_off;
+    for (size_t b = 0; b < sorted_.size(); ++b)
+      if (!conv[sorted_[b].node]) {
+        sub.push_back(sorted_[b]);
+        sub_off.push_back(dinv_off_[b]);
+      }
+    if (!sub.empty()) {
+      LuPlan lsub;
+      lsub.build(sub, NEP_PREC_FP64);
+      DevMem dmd, dpre, doff_sub;
+      NEP_TRY(dmd.alloc(sizeof(MatDesc) * sub.size()));
+      NEP_TRY(dpre.alloc(sizeof(int) * std::max<size_t>(1, lsub.prefix.size())));
+      NEP_TRY(doff_sub.alloc(sizeof(long long) * sub_off.size()));
+      NEP_HIP(hipMemcpy(dmd.p, sub.data(), sizeof(MatDesc) * sub.size(), hipMemcpyHostToDevice));
+      if (!lsub.prefix.empty())
+        NEP_HIP(hipMemcpy(dpre.p, lsub.prefix.data(), sizeof(int) * lsub.prefix.size(), hipMemcpyHostToDevice));
+      NEP_HIP(hipMemcpy(doff_sub.p, sub_off.data(), sizeof(long long) * sub_off.size(), hipMemcpyHostToDevice));
+      NEP_HIP(lu_run<double>(lsub, dmd.as<MatDesc>(), dpre.as<int>(), T, drows_.as<int>(), drows_snap_.as<int>(),
+                             rows_total_, dinfo_.as<int>(), nullptr, dlinv64_.as<c128>(), Dinv,
+                             doff_sub.as<long long>(), darrive_.as<int>(), st, ls_));
+      NEP_HIP(hipStreamSynchronize(st));  // the compact tables leave scope
+    }
+  }
   NEP_HIP(solve_run<double>(sp_, pd, md, na_, T, drows_.as<int>(), Dinv, doff, nullptr, dY_.as<c128>(), false,
                             skip, ir_, st));
   for (int s = 0;; ++s) {

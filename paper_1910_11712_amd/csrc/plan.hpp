@@ -192,11 +192,11 @@ class MomentsPlan {
   std::vector<ProbDesc> hpd_;
   std::vector<MatDesc> sorted_;
   std::vector<int> prob_of_sorted_;
-  LuPlan lu_, lu64_;
+  LuPlan lu_;
   SolvePlan sp_;
   ProblemTables pt_;
   std::vector<int> hprefix_;
-  DevMem dpd_, dmd_, dprefix_, dlu_prefix_, dlu64_prefix_;
+  DevMem dpd_, dmd_, dprefix_, dlu_prefix_;
   DevMem dT_, drows_, drows_snap_, dinfo_, dY_, dR_, dnode_, dir_, dT64_;
   DevMem ddinv_, ddinv_off_, ddinv64_, dlinv_, dlinv64_, darrive_;
   std::vector<long long> dinv_off_;

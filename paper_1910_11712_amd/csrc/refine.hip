@@ -10,8 +10,9 @@
 //
 // Control: a node is converged when, for every probe column c,
 //   ||r_c||_inf <= tol (sum_i |f_i(z_j)| ||A_i||_inf ||y_c||_inf + ||v_c||_inf),
-// a normwise backward-error test (moduli of complex entries).  A node whose
-// scaled residual does not at least halve in a sweep is marked stalled.
+// a normwise backward-error test (moduli of complex entries), or when its
+// scaled residual stops halving within 10 tol.  A node whose scaled residual
+// does not at least halve in a sweep above that is marked stalled.
 #include <algorithm>
 #include <climits>
 
@@ -364,11 +365,15 @@ __device__ __forceinline__ bool ir_control_node(const ProbDesc* __restrict__ pd,
   const double prev = ir.rho[g];
   ir.rho[g] = rho;
   ir.sweeps[g] = sweep + 1;
-  if (rho <= tol) {
+  const bool stalls = sweep > 0 && !(rho <= 0.5 * prev);
+  // converged: below the tolerance, or stalled within 10x of it (the level
+  // the factor's contraction reaches at this node; further sweeps or an FP64
+  // re-solve would not change the moments beyond that)
+  if (rho <= tol || (stalls && rho <= 10.0 * tol)) {
     ir.conv[g] = 1;
     return false;
   }
-  if (sweep > 0 && !(rho <= 0.5 * prev)) ir.stalled[g] = 1;
+  if (stalls) ir.stalled[g] = 1;
   return true;
 }
 
