@@ -3,7 +3,8 @@
 Tolerances: moments ||S_gpu - S_oracle||_F / ||S_oracle||_F <= 1e-10 for every
 p (both precisions); eigenvalues |dl|/|l| <= 1e-10 with eta <= 1e-10 for the
 pairs inside the contour.  The mixed path refines every node to a normwise
-backward error of 1e-14, so its moments carry the error of FP64 solves.
+backward error of 1e-15 by default (1e-14 where the residual stops halving),
+so its moments carry the error of FP64 solves.
 
 Where a problem is ill-conditioned at some node (the random dense cases
 below), a solve with normwise backward error b has forward error up to
