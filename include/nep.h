@@ -446,10 +446,24 @@ typedef struct {
   int status;            /* nep_status of the query                            */
   int m;                 /* eigenpairs returned                                */
   int n_inside;          /* of which inside the contour                        */
+  int reused;            /* 1: ran on resident factors (no assembly or LU)     */
   double t_submit, t_start, t_done;  /* seconds on the server clock            */
 } nep_query_info;
 
 nep_status nep_server_create(const nep_server_opts* o, nep_server* out);
+
+/* Factors stay resident after a query completes, keyed by (handle,
+ * contour, N, L, K, precision, refinement options).  A later query with the
+ * same key runs on them: its probes are solved, refined and reduced to
+ * moments without assembling or factoring T again (the results are those a
+ * new factorization would give, bit for bit), and its info reports
+ * reused = 1.  Queued queries with the key of one already dispatched wait for
+ * its factors instead of factoring the same matrices again.  Resident
+ * factors count against hbm_budget and are evicted least recently used when
+ * a new batch needs the room; those of a destroyed handle are never used
+ * again (handles carry a process-unique id) and are freed on eviction or by
+ * nep_server_destroy.  A handle must stay alive while it has queries queued
+ * or running. */
 
 /* Queues a query: moments and extraction of h inside g.
  *   V: host, complex n x L column-major (copied before the call returns).

@@ -75,7 +75,7 @@ class nep_server_opts(C.Structure):
 
 
 class nep_query_info(C.Structure):
-    _fields_ = [("status", C.c_int), ("m", C.c_int), ("n_inside", C.c_int),
+    _fields_ = [("status", C.c_int), ("m", C.c_int), ("n_inside", C.c_int), ("reused", C.c_int),
                 ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
 
 
@@ -523,7 +523,7 @@ def nep_server_submit(s, h, contour, opts, V, max_eigs=64, rank_tol=0.0, want_X=
 def _query_result(info, out):
     k = info.m
     lam = out["lam"]
-    r = {"status": info.status, "m": k, "n_inside": info.n_inside,
+    r = {"status": info.status, "m": k, "n_inside": info.n_inside, "reused": bool(info.reused),
          "t_submit": info.t_submit, "t_start": info.t_start, "t_done": info.t_done,
          "lam": lam[0:2 * k:2] + 1j * lam[1:2 * k:2], "eta": out["eta"][:k].copy(),
          "inside": out["inside"][:k] == 1, "unconverged": out["inside"][:k] == 2}

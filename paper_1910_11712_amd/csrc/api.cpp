@@ -1,5 +1,6 @@
 // C ABI of libnep: split-operator handles, moments, batches (see nep.h).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -334,6 +335,11 @@ nep_status Split::moments_more(const void* V, void* S, long long s_stride, void*
   pending = true;
   if (!st) return NEP_OK;
   return wait(st);
+}
+
+unsigned long long Split::next_uid() {
+  static std::atomic<unsigned long long> counter{1};
+  return counter.fetch_add(1);
 }
 
 void winding_count(const std::vector<double>& arg, int* count, double* max_step, double* winding) {

@@ -52,6 +52,8 @@ struct ProbDesc {
   const c128* zpts;       // explicit points (N, device) instead of the contour's
                           // nodes, or nullptr
   long long s_stride;     // elements between consecutive moment blocks of S (>= n*L)
+  int active;             // 0: the problem sits out this pass on resident factors (its
+                          // nodes count as converged, its V and S are not touched)
 };
 
 // Per-node arrays (global node index g).

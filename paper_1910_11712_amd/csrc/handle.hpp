@@ -13,6 +13,10 @@ struct ExtractWork;  // extraction workspace (extract.cpp)
 
 struct Split {
   SplitOperator op;
+  // unique over the process (never reused, unlike the handle's address):
+  // keys the server's resident factors
+  unsigned long long uid = next_uid();
+  static unsigned long long next_uid();
   hipStream_t stream = nullptr;
   hipStream_t last_stream = nullptr;
   std::unique_ptr<DevMem> mats[kMaxTerms];

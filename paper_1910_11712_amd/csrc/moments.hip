@@ -20,6 +20,11 @@ __global__ void k_coef(const ProbDesc* __restrict__ pd, NodeArrays na, int nnode
   if (g >= nnodes) return;
   const int p = na.prob[g], j = na.jnode[g];
   const ProbDesc& P = pd[p];
+  if (!P.active) {  // sits out this pass: nothing of its operator is read
+    na.bad[g] = 0;
+    ir.conv[g] = 1;
+    return;
+  }
   const double th = 2.0 * M_PI * (j + 0.5) / P.N;
   double s, c;
   sincos(th, &s, &c);
@@ -153,6 +158,7 @@ __global__ __launch_bounds__(kMomThreads) void k_moments(const ProbDesc* __restr
   if (v < 0) return;
   const int p = find_slot(prefix, cnt, v);
   const ProbDesc& D = pd[p];
+  if (!D.active) return;
   const int n = D.n, L = D.L, NL = D.N * D.L, KK = D.KK, N = D.N, node0 = D.node0;
   const int ngrp = (KK + kMomQ - 1) / kMomQ;
   const int nl = n * L;
@@ -194,7 +200,7 @@ hipError_t launch_moments(const ProbDesc* pd, const int* prefix, const Table& t,
 __global__ __launch_bounds__(256) void k_vnorm(const ProbDesc* __restrict__ pd, IrState ir) {
   const ProbDesc& D = pd[blockIdx.x];
   const int c = blockIdx.y;
-  if (c >= D.L) return;  // uniform
+  if (c >= D.L || !D.active) return;  // uniform
   const c128* __restrict__ v = D.V + (long long)c * D.n;
   double m = 0.0;
   for (int r = threadIdx.x; r < D.n; r += blockDim.x) m = nanmax(m, sqrt(norm2(v[r])));

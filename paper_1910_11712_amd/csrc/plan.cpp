@@ -206,6 +206,7 @@ nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs) {
     D.fn_coef = q.op->dfn_coef;
     D.zpts = q.zpts;
     D.s_stride = q.s_stride > 0 ? q.s_stride : (long long)D.n * D.L;
+    D.active = 1;
   }
   NEP_HIP(hipMemcpy(dpd_.p, hpd_.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice));
   return NEP_OK;
@@ -214,6 +215,31 @@ nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs) {
 nep_status MomentsPlan::rebind(const std::vector<PlanProblem>& probs) {
   NEP_CHECK((int)probs.size() == nprob, NEP_ERR_ARG, "rebind: problem count changed");
   return upload_problems(probs);
+}
+
+nep_status MomentsPlan::rebind_members(const std::vector<int>& member, const std::vector<const c128*>& V,
+                                       const std::vector<c128*>& S, hipStream_t st) {
+  NEP_CHECK(member.size() == V.size() && member.size() == S.size(), NEP_ERR_ARG, "rebind: size mismatch");
+  for (auto& D : hpd_) D.active = 0;
+  for (size_t k = 0; k < member.size(); ++k) {
+    const int p = member[k];
+    NEP_CHECK(p >= 0 && p < nprob, NEP_ERR_ARG, "rebind: member %d out of range", p);
+    NEP_CHECK(!hpd_[p].active, NEP_ERR_ARG, "rebind: member %d bound twice", p);
+    ProbDesc& D = hpd_[p];
+    D.active = 1;
+    D.V = V[k];
+    D.S = S[k];
+    D.zpts = nullptr;
+    D.s_stride = (long long)D.n * D.L;
+  }
+  NEP_HIP(hipMemcpyAsync(dpd_.p, hpd_.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice, st));
+  return NEP_OK;
+}
+
+void MomentsPlan::release_fallback() {
+  dT64_.release();
+  ddinv64_.release();
+  dlinv64_.release();
 }
 
 nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanOptions& o) {
@@ -399,7 +425,8 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager, bool refactor) {
       lu_timed_ = true;
     }
   }
-  NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, nullptr, Y, false, nullptr, ir_, st));
+  // nodes of problems sitting out the pass are marked converged by k_coef
+  NEP_HIP(solve_run<P>(sp_, pd, md, na_, T, rows, Dinv, doff, nullptr, Y, false, ir_.conv, ir_, st));
   sweeps_run_ = 0;
   if (opt.max_refine > 0) {
     // The correction solve of each sweep is queued before the host reads the

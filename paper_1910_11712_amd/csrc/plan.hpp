@@ -154,6 +154,14 @@ class MomentsPlan {
   nep_status logdet(hipStream_t st, std::vector<double>& logabs, std::vector<double>& arg);
   // Rebinds caller buffers (V, S) and contours without rebuilding.
   nep_status rebind(const std::vector<PlanProblem>& probs);
+  // For a pass on resident factors (enqueue with refactor=false): the listed
+  // problems take new probes V and moment buffers S (s_stride n*L), every
+  // other problem sits out the pass (nothing of its operator is read, its
+  // previous buffers are not touched).  The descriptor upload is queued on st.
+  nep_status rebind_members(const std::vector<int>& member, const std::vector<const c128*>& V,
+                            const std::vector<c128*>& S, hipStream_t st);
+  // Frees the FP64 re-solve buffers (allocated again if a later pass needs them).
+  void release_fallback();
   bool matches(const std::vector<PlanProblem>& probs, const PlanOptions& o) const;
 
   // Launch-shape knobs of the plan (see LuPlan::small_min and early_fork,

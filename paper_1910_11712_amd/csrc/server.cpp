@@ -13,6 +13,18 @@
 // dispatch thread keeps feeding the other slots.  Workspaces (plans, probes,
 // moments, and each slot's extraction workspace) come from one device arena
 // of the budget's size, so recycling them never synchronizes the device.
+//
+// Factors stay resident: a finished batch's plan (its LU factors of every
+// node of every query) is kept, keyed per query by (operator, contour, N, L,
+// K, precision, refinement options).  A later query with the key of a
+// resident member runs on those factors: probes, solves, refinement and
+// moments only, no assembly or factorization (the factors are the same
+// bits a new factorization would give).  Several such queries on members of
+// one resident plan run as one pass; the plan's other members sit out.
+// Resident plans count against the budget and are evicted least recently
+// used when a new batch needs the room.  A queued query whose key repeats a
+// query already in the batch being formed waits and then runs on the
+// resident factors instead of factoring the same matrices twice.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -29,8 +41,23 @@ namespace nep {
 
 namespace {
 
+// What makes two queries' factors identical.
+struct Key {
+  unsigned long long uid = 0;  // operator (Split::uid)
+  nep_contour g{};
+  int N = 0, L = 0, K = 0, prec = 0, max_refine = 0, fallback = 0;
+  double tol = 0.0;
+};
+
+bool same_key(const Key& a, const Key& b) {
+  return a.uid == b.uid && a.g.kind == b.g.kind && a.g.c[0] == b.g.c[0] && a.g.c[1] == b.g.c[1] &&
+         a.g.rho == b.g.rho && (a.g.kind != 1 || a.g.v == b.g.v) && a.N == b.N && a.L == b.L && a.K == b.K &&
+         a.prec == b.prec && a.max_refine == b.max_refine && a.fallback == b.fallback && a.tol == b.tol;
+}
+
 struct Query {
   long long ticket = 0;
+  Key key;
   nep_split h = nullptr;
   nep_contour g{};
   nep_ciss_opts o{};
@@ -42,11 +69,22 @@ struct Query {
   double* eta = nullptr;
   int* inside = nullptr;
   void* X = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;   // a query with its own factors (plan, probes, moments, vectors)
+  size_t fbytes = 0;  // a query on resident factors (probes, moments, vectors)
   nep_query_info info{};
   bool done = false;
 };
 using QueryPtr = std::shared_ptr<Query>;
+
+// A finished batch's plan kept with its factors.
+struct Resident {
+  std::unique_ptr<MomentsPlan> plan;
+  std::vector<Key> keys;    // per plan problem
+  std::vector<char> valid;  // the member's last query succeeded
+  size_t bytes = 0;         // counted against the budget
+  double last_use = 0.0;
+  bool out = false;         // a slot runs a pass on it
+};
 
 struct QueryBuffers {
   DevMem V, S, X;
@@ -55,8 +93,11 @@ struct QueryBuffers {
 struct Slot {
   hipStream_t st = nullptr;
   hipEvent_t ev = nullptr;
-  std::unique_ptr<MomentsPlan> plan;
+  std::unique_ptr<MomentsPlan> own;  // a new plan (factored in this batch)
+  Resident* res = nullptr;           // or the resident plan the batch runs on
+  MomentsPlan* plan = nullptr;       // the one in use
   std::vector<QueryPtr> q;
+  std::vector<int> member;           // on a resident plan: each query's plan problem
   std::vector<std::unique_ptr<QueryBuffers>> buf;
   std::shared_ptr<ExtractWork> xw;  // extraction workspace (arena blocks)
   size_t bytes = 0;
@@ -91,6 +132,12 @@ class Server {
   void complete(Slot& s);                // the slot's batch has finished
   void fail(std::vector<QueryPtr>& qs, nep_status st);
   static size_t query_bytes(const Query& q);
+  static size_t query_buffer_bytes(const Query& q);
+  // resident_ helpers (mu_ held)
+  Resident* find_resident(const Key& k, int* member);
+  void evict_lru(size_t need, std::vector<std::unique_ptr<Resident>>& out);
+  void keep_resident(Slot& s, const std::vector<nep_status>& status);
+  void release_slot_plan(Slot& s, bool drop_resident);
 
   Arena arena_;
   int device_ = 0;
@@ -100,6 +147,8 @@ class Server {
   std::mutex mu_;
   std::condition_variable cv_work_, cv_done_, cv_slot_;
   std::deque<QueryPtr> queue_;
+  std::vector<std::unique_ptr<Resident>> resident_;
+  size_t resident_bytes_ = 0;
   std::unordered_map<long long, QueryPtr> tickets_;
   long long next_ticket_ = 1;
   bool stop_ = false, started_ = false;
@@ -110,12 +159,43 @@ class Server {
 
 Server::~Server() { shutdown(); }
 
-size_t Server::query_bytes(const Query& q) {
+size_t Server::query_buffer_bytes(const Query& q) {
   const size_t c = sizeof(c128);
-  size_t b = MomentsPlan::estimate_bytes(q.n, q.po.N, q.po.L, q.po.prec);
-  b += (size_t)q.n * q.po.L * c * (1 + 2 * q.po.K);  // V and S
-  b += (size_t)q.n * q.e.max_eigs * c;               // X
-  return b + (1u << 20);                              // tables, alignment
+  size_t b = (size_t)q.n * q.po.L * c * (1 + 2 * q.po.K);  // V and S
+  b += (size_t)q.n * q.e.max_eigs * c;                     // X
+  return b + (1u << 16);                                    // alignment
+}
+
+size_t Server::query_bytes(const Query& q) {
+  return MomentsPlan::estimate_bytes(q.n, q.po.N, q.po.L, q.po.prec) + query_buffer_bytes(q) +
+         (1u << 20);  // tables, alignment
+}
+
+Resident* Server::find_resident(const Key& k, int* member) {
+  for (auto& r : resident_) {
+    if (r->out) continue;
+    for (size_t m = 0; m < r->keys.size(); ++m)
+      if (r->valid[m] && same_key(r->keys[m], k)) {
+        *member = (int)m;
+        return r.get();
+      }
+  }
+  return nullptr;
+}
+
+// Removes least recently used resident plans that no slot runs on until
+// need more bytes fit the budget (or none is left); the caller destroys them
+// with mu_ released.
+void Server::evict_lru(size_t need, std::vector<std::unique_ptr<Resident>>& out) {
+  while (inflight_bytes_ + resident_bytes_ + need > budget_) {
+    int best = -1;
+    for (int i = 0; i < (int)resident_.size(); ++i)
+      if (!resident_[i]->out && (best < 0 || resident_[i]->last_use < resident_[best]->last_use)) best = i;
+    if (best < 0) return;
+    resident_bytes_ -= resident_[best]->bytes;
+    out.push_back(std::move(resident_[best]));
+    resident_.erase(resident_.begin() + best);
+  }
 }
 
 nep_status Server::init(const nep_server_opts* o) {
@@ -158,6 +238,16 @@ nep_status Server::submit(nep_split h, const nep_contour* g, const nep_ciss_opts
   q->o = *o;
   q->e = *e;
   q->n = h->impl.op.n;
+  q->key.uid = h->impl.uid;
+  q->key.g = *g;
+  q->key.N = q->po.N;
+  q->key.L = q->po.L;
+  q->key.K = q->po.K;
+  q->key.prec = q->po.prec;
+  q->key.max_refine = q->po.max_refine;
+  q->key.fallback = q->po.fallback;
+  q->key.tol = q->po.tol;
+  q->fbytes = query_buffer_bytes(*q);
   q->lambda = lambda;
   q->eta = eta;
   q->inside = inside;
@@ -208,6 +298,11 @@ void Server::shutdown() {
       if (s.worker.joinable()) s.worker.join();
     started_ = false;
   }
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    resident_.clear();  // every slot is idle: no resident plan is in use
+    resident_bytes_ = 0;
+  }
   for (auto& s : slots_) {
     {
       ArenaScope scope(&arena_);  // the workspace's blocks go back to the arena
@@ -234,35 +329,110 @@ void Server::fail(std::vector<QueryPtr>& qs, nep_status st) {
 
 bool Server::dispatch(Slot& s) {
   std::vector<QueryPtr> batch;
+  std::vector<int> member;  // on resident factors: the plan problem of each query
+  Resident* res = nullptr;
   size_t bytes = 0;
+  std::vector<std::unique_ptr<Resident>> evicted;  // destroyed with mu_ released
+  bool started = false, return_now = false;
   {
     std::lock_guard<std::mutex> lk(mu_);
     if (queue_.empty() || arena_full_) return false;
-    const QueryPtr head = queue_.front();
-    for (auto it = queue_.begin(); it != queue_.end() && (int)batch.size() < batch_cap_;) {
-      const Query& q = **it;
-      const bool fits = inflight_ + (int)batch.size() < max_inflight_ && inflight_bytes_ + bytes + q.bytes <= budget_;
-      if (batch.empty() && !fits) break;  // the oldest query waits for room: it is never overtaken
-      if (!fits || !same_batch(q, *head)) {
-        ++it;
-        continue;
+    // the oldest query that has resident factors, with every other queued
+    // query on a member of the same resident plan (each member once per
+    // pass), runs on them; such passes are short, so they go first
+    QueryPtr head;
+    for (auto& q : queue_) {
+      int m0 = -1;
+      if ((res = find_resident(q->key, &m0)) != nullptr) {
+        head = q;
+        break;
       }
-      bytes += q.bytes;
-      batch.push_back(*it);
-      it = queue_.erase(it);
     }
-    if (batch.empty()) {  // the oldest query waits for a completion to free room
-      arena_full_ = true;
-      return false;
+    if (res != nullptr) {
+      res->out = true;
+      evict_lru(head->fbytes, evicted);
+      std::vector<char> taken(res->keys.size(), 0);
+      for (auto it = queue_.begin(); it != queue_.end() && (int)batch.size() < batch_cap_;) {
+        const Query& q = **it;
+        int m = -1;
+        for (size_t k = 0; k < res->keys.size() && m < 0; ++k)
+          if (res->valid[k] && !taken[k] && same_key(res->keys[k], q.key)) m = (int)k;
+        const bool fits = inflight_ + (int)batch.size() < max_inflight_ &&
+                          inflight_bytes_ + resident_bytes_ + bytes + q.fbytes <= budget_;
+        if (batch.empty() && m >= 0 && !fits) break;
+        if (m < 0 || !fits) {
+          ++it;
+          continue;
+        }
+        taken[m] = 1;
+        member.push_back(m);
+        bytes += q.fbytes;
+        batch.push_back(*it);
+        it = queue_.erase(it);
+      }
+      if (batch.empty()) {
+        res->out = false;
+        if (inflight_ == 0) {  // no room beside this plan even with nothing running: give it up
+          for (size_t i = 0; i < resident_.size(); ++i)
+            if (resident_[i].get() == res) {
+              resident_bytes_ -= res->bytes;
+              evicted.push_back(std::move(resident_[i]));
+              resident_.erase(resident_.begin() + i);
+              break;
+            }
+          res = nullptr;
+          return_now = true;  // retried at once as a new batch
+        }
+      }
+    } else {
+      // a new batch: queries sharing the first one's options; a query whose
+      // key repeats one already taken, or names a member of a resident plan
+      // that a slot is running, waits and then runs on resident factors
+      const Query* first = nullptr;
+      for (auto it = queue_.begin(); it != queue_.end() && (int)batch.size() < batch_cap_;) {
+        const Query& q = **it;
+        bool wait = false;
+        for (auto& r : resident_)
+          for (size_t k = 0; k < r->keys.size() && !wait; ++k) wait = r->valid[k] && same_key(r->keys[k], q.key);
+        for (auto& b : batch) wait |= same_key(b->key, q.key);
+        if (wait) {
+          ++it;
+          continue;
+        }
+        if (first == nullptr) evict_lru(q.bytes, evicted);
+        const bool fits = inflight_ + (int)batch.size() < max_inflight_ &&
+                          inflight_bytes_ + resident_bytes_ + bytes + q.bytes <= budget_;
+        if (first == nullptr && !fits) break;  // the oldest query waits for room: it is never overtaken
+        if (!fits || (first != nullptr && !same_batch(q, *first))) {
+          ++it;
+          continue;
+        }
+        if (first == nullptr) first = &q;
+        bytes += q.bytes;
+        batch.push_back(*it);
+        it = queue_.erase(it);
+      }
     }
-    inflight_ += (int)batch.size();
-    inflight_bytes_ += bytes;
-    const double t = clock();
-    for (auto& q : batch) q->info.t_start = t;
+    if (batch.empty()) {  // nothing runs before a completion frees room or a plan
+      if (!return_now) arena_full_ = true;
+    } else {
+      inflight_ += (int)batch.size();
+      inflight_bytes_ += bytes;
+      const double t = clock();
+      for (auto& q : batch) {
+        q->info.t_start = t;
+        q->info.reused = res != nullptr ? 1 : 0;
+      }
+      started = true;
+    }
   }
-  // workspaces and the plan come from the arena
+  evicted.clear();  // their blocks go back to the arena before this batch allocates
+  if (!started) return return_now;
+
+  // workspaces and a new plan come from the arena
   ArenaScope scope(&arena_);
   s.buf.clear();
+  s.res = res;  // the slot holds the resident plan (checked out) from here on
   std::vector<PlanProblem> probs;
   nep_status st = NEP_OK;
   for (auto& q : batch) {
@@ -280,38 +450,63 @@ bool Server::dispatch(Slot& s) {
     probs.push_back(PlanProblem{&q->h->impl.op, q->g, b->V.as<c128>(), b->S.as<c128>()});
     s.buf.push_back(std::move(b));
   }
-  if (st == NEP_OK) {
-    s.plan = std::make_unique<MomentsPlan>();
+  bool enqueued = false;
+  if (st == NEP_OK && res != nullptr) {
+    s.plan = res->plan.get();
+    std::vector<const c128*> Vs;
+    std::vector<c128*> Ss;
+    for (auto& b : s.buf) {
+      Vs.push_back(b->V.as<c128>());
+      Ss.push_back(b->S.as<c128>());
+    }
+    st = s.plan->rebind_members(member, Vs, Ss, s.st);
+    if (st == NEP_OK) {
+      enqueued = true;
+      st = s.plan->enqueue(s.st, false, false);
+    }
+  } else if (st == NEP_OK) {
+    s.own = std::make_unique<MomentsPlan>();
+    s.plan = s.own.get();
     st = s.plan->build(probs, batch.front()->po);
+    if (st == NEP_OK) {
+      enqueued = true;
+      st = s.plan->enqueue(s.st, false);
+    }
   }
-  if (st == NEP_OK) st = s.plan->enqueue(s.st, false);
   if (st == NEP_OK && hipEventRecord(s.ev, s.st) != hipSuccess) st = NEP_ERR_DEVICE;
-  if (st == NEP_ERR_OOM) {
-    // the arena is fragmented or the estimate was short: requeue in order
+  if (st == NEP_ERR_OOM && !enqueued) {
+    // the arena is fragmented or the estimate was short: requeue in order,
+    // with every idle resident plan evicted
     (void)hipStreamSynchronize(s.st);
-    s.plan.reset();
+    release_slot_plan(s, false);
     s.buf.clear();
     std::unique_lock<std::mutex> lk(mu_);
+    for (auto it = batch.rbegin(); it != batch.rend(); ++it) queue_.push_front(*it);
+    inflight_ -= (int)batch.size();
+    inflight_bytes_ -= bytes;
+    evict_lru(budget_, evicted);
     bool others_busy = false;
     for (auto& o : slots_) others_busy |= o.busy;
-    if (others_busy) {
-      for (auto it = batch.rbegin(); it != batch.rend(); ++it) queue_.push_front(*it);
-      inflight_ -= (int)batch.size();
-      inflight_bytes_ -= bytes;
-      arena_full_ = true;
-      return false;
-    }
+    const bool freed = !evicted.empty();
+    if (others_busy && !freed) arena_full_ = true;
     lk.unlock();
+    evicted.clear();
+    if (others_busy || freed) return freed;
+    lk.lock();  // nothing else holds the arena: this batch fails below
+    for (size_t k = 0; k < batch.size(); ++k) queue_.pop_front();
+    inflight_ += (int)batch.size();
+    inflight_bytes_ += bytes;
   }
   if (st != NEP_OK) {
     (void)hipStreamSynchronize(s.st);
-    s.plan.reset();
+    release_slot_plan(s, enqueued);
     s.buf.clear();
     fail(batch, st);
     return true;
   }
   for (auto& q : batch) std::vector<c128>().swap(q->V);  // the device holds the probes now
   s.q = std::move(batch);
+  s.member = std::move(member);
   s.bytes = bytes;
   {
     std::lock_guard<std::mutex> lk(mu_);
@@ -322,13 +517,70 @@ bool Server::dispatch(Slot& s) {
   return true;
 }
 
+// The slot's plan after its batch: a resident plan goes back to the cache
+// (or, with drop, out of it: its state is unknown after a failed pass), a
+// new one is destroyed.
+void Server::release_slot_plan(Slot& s, bool drop) {
+  std::unique_ptr<Resident> gone;
+  if (s.res != nullptr) {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (size_t i = 0; i < resident_.size(); ++i)
+      if (resident_[i].get() == s.res) {
+        if (drop) {
+          resident_bytes_ -= s.res->bytes;
+          gone = std::move(resident_[i]);
+          resident_.erase(resident_.begin() + i);
+        } else {
+          s.res->out = false;
+        }
+        break;
+      }
+  }
+  s.res = nullptr;
+  s.own.reset();
+  s.plan = nullptr;
+}
+
+// After a completed batch: a new plan becomes resident (if any of its
+// queries succeeded), a resident one returns to the cache with its members'
+// validity updated.
+void Server::keep_resident(Slot& s, const std::vector<nep_status>& status) {
+  std::lock_guard<std::mutex> lk(mu_);
+  const double t = clock();
+  if (s.res != nullptr) {
+    for (size_t k = 0; k < s.member.size(); ++k) s.res->valid[s.member[k]] = status[k] == NEP_OK;
+    s.res->out = false;
+    s.res->last_use = t;
+    s.res = nullptr;
+    s.plan = nullptr;
+    return;
+  }
+  bool any = false;
+  for (nep_status x : status) any |= x == NEP_OK;
+  if (!any || !s.own) return;  // destroyed by the caller
+  auto r = std::make_unique<Resident>();
+  for (size_t k = 0; k < s.q.size(); ++k) {
+    r->keys.push_back(s.q[k]->key);
+    r->valid.push_back(status[k] == NEP_OK);
+    r->bytes += s.q[k]->bytes - s.q[k]->fbytes;
+  }
+  s.own->release_fallback();
+  r->plan = std::move(s.own);
+  r->last_use = t;
+  resident_bytes_ += r->bytes;
+  resident_.push_back(std::move(r));
+  s.plan = nullptr;
+}
+
 void Server::complete(Slot& s) {
   ArenaScope scope(&arena_);  // a fallback re-solve allocates from the arena
   RunResult rr;
   (void)s.plan->finish(s.st, rr, true);
+  std::vector<nep_status> status(s.q.size());
   for (size_t k = 0; k < s.q.size(); ++k) {
     Query& q = *s.q[k];
-    nep_status st = k < rr.pstatus.size() ? rr.pstatus[k] : NEP_ERR_DEVICE;
+    const size_t pk = s.res != nullptr ? (size_t)s.member[k] : k;  // the query's plan problem
+    nep_status st = pk < rr.pstatus.size() ? rr.pstatus[pk] : NEP_ERR_DEVICE;
     int m = 0, nin = 0;
     if (st == NEP_OK) {
       nep_ciss_opts o = q.o;
@@ -349,12 +601,17 @@ void Server::complete(Slot& s) {
       if (st == NEP_OK)
         for (int i = 0; i < m; ++i) nin += q.inside[i] ? 1 : 0;
     }
+    // the factors' own verdict decides residency (an extraction failure,
+    // such as a saturated rank, does not make them invalid)
+    status[k] = pk < rr.pstatus.size() ? rr.pstatus[pk] : NEP_ERR_DEVICE;
     q.info.status = st;
     q.info.m = m;
     q.info.n_inside = nin;
   }
-  s.plan.reset();
+  keep_resident(s, status);
+  s.own.reset();
   s.buf.clear();
+  s.member.clear();
   {
     std::lock_guard<std::mutex> lk(mu_);
     const double t = clock();
@@ -389,8 +646,9 @@ void Server::work(Slot& s) {
       std::vector<QueryPtr> qs = std::move(s.q);
       {
         ArenaScope scope(&arena_);
-        s.plan.reset();
+        release_slot_plan(s, true);
         s.buf.clear();
+        s.member.clear();
       }
       s.bytes = 0;
       fail(qs, NEP_ERR_DEVICE);

@@ -122,8 +122,11 @@ def test_server_fallback_unaffected_by_failing_neighbour(nep):
     srv = nep.Server(hbm_budget=8 << 30, max_inflight=8, nstreams=1)
     try:
         # the first query holds the only slot while the next two queue, so
-        # those two are dispatched together as one batch
-        t_first = srv.submit(op, con, V, N, L, K, max_eigs=16, want_X=True)
+        # those two are dispatched together as one batch (the first runs on
+        # another handle of the same problem, so the third cannot run on
+        # the first's resident factors instead)
+        op_first = nep.SplitOperator.from_problem(prob)
+        t_first = srv.submit(op_first, con, V, N, L, K, max_eigs=16, want_X=True)
         t_bad = srv.submit(op_b, Contour.circle(0.0, 1.0), wl.probes(8, 8, 0), N, L, K, max_eigs=16)
         t_good = srv.submit(op, con, V, N, L, K, max_eigs=16, want_X=True)
         r_first, r_bad, r_good = srv.wait(t_first), srv.wait(t_bad), srv.wait(t_good)
@@ -165,3 +168,58 @@ def test_server_budget(nep):
     spans = sorted((r["t_start"], r["t_done"]) for r in rs)
     for a, b in zip(spans, spans[1:]):
         assert b[0] >= a[1]
+
+
+def test_server_follow_up_runs_on_resident_factors(nep):
+    """A query with the operator, contour and options of a finished one runs
+    on the factors that query left resident (no assembly or LU): reused is
+    set and the result equals a fresh run of the same probes bit for bit.
+    Other N, another handle of the same problem, or an evicted plan mean new
+    factors.  A small budget holds one plan at a time: a larger query evicts
+    the resident one."""
+    p = wl.loaded_string(200, sigma=1.0, a_scale=1.0)
+    con = Contour.circle(100.0, 90.0)
+    N, L, K, me = 32, 8, 2, 16
+    op = nep.SplitOperator.from_problem(p)
+    V1, V2, V3 = (wl.probes(200, L, s) for s in (41, 42, 43))
+    alone2 = _alone(nep, op, con, V2, N, L, K, "mixed", me)
+    alone3 = _alone(nep, op, con, V3, N, L, K, "mixed", me)
+    srv = nep.Server(hbm_budget=1 << 30, max_inflight=8, nstreams=2)
+    try:
+        r1 = srv.wait(srv.submit(op, con, V1, N, L, K, max_eigs=me, want_X=True))
+        r2 = srv.wait(srv.submit(op, con, V2, N, L, K, max_eigs=me, want_X=True))
+        r3 = srv.wait(srv.submit(op, con, V3, 64, L, K, max_eigs=me, want_X=True))
+        op_b = nep.SplitOperator.from_problem(p)  # same data, another handle
+        r4 = srv.wait(srv.submit(op_b, con, V3, N, L, K, max_eigs=me, want_X=True))
+        # two follow-ups queued together: one pass on the resident plan runs
+        # the first, the second waits for it (one member, one pass)
+        ta = srv.submit(op, con, V2, N, L, K, max_eigs=me, want_X=True)
+        tb = srv.submit(op, con, V3, N, L, K, max_eigs=me, want_X=True)
+        ra, rb = srv.wait(ta), srv.wait(tb)
+    finally:
+        srv.close()
+    assert [r["status"] for r in (r1, r2, r3, r4, ra, rb)] == [0] * 6
+    assert not r1["reused"] and r2["reused"] and not r3["reused"] and not r4["reused"]
+    assert ra["reused"] and rb["reused"]
+    for r, a in ((r2, alone2), (ra, alone2), (r4, alone3), (rb, alone3)):
+        assert r["m"] == a["m"]
+        assert np.array_equal(r["lam"], a["lam"])
+        assert np.array_equal(r["eta"], a["eta"])
+        assert np.array_equal(r["X"], a["X"])
+    print("first", r1["t_done"] - r1["t_start"], "on resident factors", r2["t_done"] - r2["t_start"])
+
+    # eviction: a 140 MB budget holds the n=200 plan (about 30 MB) or the
+    # n=600 one (about 130 MB), not both
+    q = wl.loaded_string(600, sigma=1.0, a_scale=1.0)
+    op_q = nep.SplitOperator.from_problem(q)
+    srv = nep.Server(hbm_budget=140 << 20, max_inflight=4, nstreams=1)
+    try:
+        s1 = srv.wait(srv.submit(op, con, V1, N, L, K, max_eigs=me))
+        s2 = srv.wait(srv.submit(op_q, con, wl.probes(600, L, 5), N, L, K, max_eigs=me))
+        s3 = srv.wait(srv.submit(op, con, V2, N, L, K, max_eigs=me))
+        s4 = srv.wait(srv.submit(op, con, V3, N, L, K, max_eigs=me))
+    finally:
+        srv.close()
+    assert [r["status"] for r in (s1, s2, s3, s4)] == [0] * 4
+    assert [r["reused"] for r in (s1, s2, s3, s4)] == [False, False, False, True]
+    assert np.array_equal(s3["lam"], alone2["lam"]) and np.array_equal(s4["lam"], alone3["lam"])
