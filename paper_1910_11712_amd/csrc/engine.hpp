@@ -96,7 +96,14 @@ struct SolvePlan {
   // the large matrices as paired 256-thread groups (complex FP32, lg <= 8,
   // rpt <= 2): -1 when they make 2048 groups or more, 0 never, 1 always
   int paired = -1;
+  // complex FP32: the first nblk matrices (at least kSolveBlockedMinN rows)
+  // take the blocked solve (solve_blk.hip) over big blocks of nbk rows, with
+  // right-hand sides in the work buffer W (npad x L complex FP32 per matrix,
+  // npad the largest n rounded up to 64); the rest take k_trsv
+  int nblk = 0, nbk = 256, npad = 0, L = 0;
+  c64* W = nullptr;
 };
+constexpr int kSolveBlockedMinN = 1024;
 
 // Column-group widths the solve is built for (4, 8, 16) that fit the plan:
 // fewer than 2L columns (a wider group would be more than half empty) and
@@ -126,6 +133,10 @@ template <typename P>
 hipError_t solve_run(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md, const NodeArrays& na,
                      const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off,
                      const c128* R, c128* Y, bool refine, const int* conv, IrState ir, hipStream_t st);
+// Blocked solve of the first sp.nblk matrices (solve_blk.hip).
+hipError_t solve_blocked(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md, const NodeArrays& na,
+                         const c64* T, const int* rows, const c64* Dinv, const long long* dinv_off,
+                         const c128* R, c128* Y, bool refine, const int* conv, IrState ir, hipStream_t st);
 void SolvePlan_build(SolvePlan& sp, std::vector<int>& buf, const std::vector<MatDesc>& sorted, int L, int prec,
                      std::vector<long long>& dinv_off, long long& dinv_elems);
 hipError_t solve_configure();

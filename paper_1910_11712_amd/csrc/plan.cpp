@@ -169,6 +169,8 @@ size_t MomentsPlan::estimate_bytes(int n, int N, int L, int prec) {
   b += (size_t)N * ((n + 63) / 64) * 2 * 64 * 64 * elem_size(prec);  // diagonal-block inverses
   b += 2 * (size_t)N * kLuMaxJB * kLuMaxJB * elem_size(prec);        // panel inverses (two halves)
   b += 2 * (size_t)n * N * L * sizeof(c128);               // Y, R
+  if (prec != NEP_PREC_FP64 && n >= kSolveBlockedMinN)     // blocked-solve right-hand sides
+    b += (size_t)N * ((n + 63) / 64 * 64) * L * sizeof(c64);
   b += (size_t)N * (kMaxTerms + kMaxMoments + 8) * sizeof(c128) + (size_t)N * kNormStride * 16;
   return b;
 }
@@ -322,6 +324,13 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   NEP_TRY(A(dprefix_, sizeof(int) * hprefix_.size()));
   NEP_TRY(A(dlu_prefix_, sizeof(int) * std::max<size_t>(1, lu_.prefix.size())));
   NEP_TRY(A(dT_, es * (size_t)t_elems_));
+  if (sp_.nblk > 0) {  // right-hand sides of the blocked solve
+    NEP_TRY(A(dW_, sizeof(c64) * (size_t)sp_.nblk * sp_.npad * sp_.L));
+    sp_.W = dW_.as<c64>();
+  } else {
+    dW_.release();
+    sp_.W = nullptr;
+  }
   NEP_TRY(A(drows_, sizeof(int) * (size_t)rows_total_));
   NEP_TRY(A(drows_snap_, sizeof(int) * (size_t)rows_total_));
   if (!ls_.aux) {

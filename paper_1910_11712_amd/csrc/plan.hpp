@@ -205,7 +205,7 @@ class MomentsPlan {
   ProblemTables pt_;
   std::vector<int> hprefix_;
   DevMem dpd_, dmd_, dprefix_, dlu_prefix_;
-  DevMem dT_, drows_, drows_snap_, dinfo_, dY_, dR_, dnode_, dir_, dT64_;
+  DevMem dT_, drows_, drows_snap_, dinfo_, dY_, dR_, dnode_, dir_, dT64_, dW_;
   DevMem ddinv_, ddinv_off_, ddinv64_, dlinv_, dlinv64_, darrive_;
   std::vector<long long> dinv_off_;
   long long dinv_elems_ = 0;

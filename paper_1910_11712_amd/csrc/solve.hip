@@ -355,7 +355,9 @@ template <typename P, int LG>
 static void launch_trsv(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md, const NodeArrays& na,
                         const cx<P>* T, const int* rows, const cx<P>* Dinv, const long long* dinv_off, const c128* R,
                         c128* Y, int rf, const int* conv, IrState ir, hipStream_t st) {
-  const int nb = sp.nbig, nm = sp.nmid, ns = sp.nmat - sp.nbig - sp.nmid;
+  // the first nblk matrices took the blocked solve (complex FP32 only)
+  const int b0 = sizeof(P) == 4 ? sp.nblk : 0;
+  const int nb = sp.nbig - b0, nm = sp.nmid, ns = sp.nmat - sp.nbig - sp.nmid;
   // many large matrices (several rounds of groups): 256-thread groups with
   // twice the rows each, two per CU, so one group's barrier waits are
   // covered by the other's work
@@ -363,17 +365,18 @@ static void launch_trsv(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* 
   constexpr bool kPaired = sizeof(P) == 4 && LG <= 8;
   if (kPaired && sp.rpt <= 2 && nb > 0 && (sp.paired == 1 || (sp.paired < 0 && (long long)nb * sp.groups >= 2048))) {
     if constexpr (kPaired)
-      launch_trsv_class<P, LG, 4, kTrsvThreadsSmall>(sp, 0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir,
-                                                     st);
+      launch_trsv_class<P, LG, 4, kTrsvThreadsSmall>(sp, b0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv,
+                                                     ir, st);
   } else switch (sp.rpt) {
     case 1:
-    case 2: launch_trsv_class<P, LG, 2, kTrsvThreads>(sp, 0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
-    case 4: launch_trsv_class<P, LG, 4, kTrsvThreads>(sp, 0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
-    default: launch_trsv_class<P, LG, 8, kTrsvThreads>(sp, 0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
+    case 2: launch_trsv_class<P, LG, 2, kTrsvThreads>(sp, b0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
+    case 4: launch_trsv_class<P, LG, 4, kTrsvThreads>(sp, b0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
+    default: launch_trsv_class<P, LG, 8, kTrsvThreads>(sp, b0, nb, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
   }
-  launch_trsv_class<P, LG, 2, kTrsvThreadsSmall>(sp, nb, nm, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st);
-  launch_trsv_class<P, LG, 1, kTrsvThreadsSmall>(sp, nb + nm, ns, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir,
+  launch_trsv_class<P, LG, 2, kTrsvThreadsSmall>(sp, sp.nbig, nm, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir,
                                                  st);
+  launch_trsv_class<P, LG, 1, kTrsvThreadsSmall>(sp, sp.nbig + nm, ns, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf,
+                                                 conv, ir, st);
 }
 
 template <typename P>
@@ -382,6 +385,13 @@ hipError_t solve_run(const SolvePlan& sp, const ProbDesc* pd, const MatDesc* md,
                      const c128* R, c128* Y, bool refine, const int* conv, IrState ir, hipStream_t st) {
   if (sp.nmat == 0) return hipSuccess;
   const int rf = refine ? 1 : 0;
+  if constexpr (sizeof(P) == 4) {
+    if (sp.nblk > 0) {
+      const hipError_t e = solve_blocked(sp, pd, md, na, T, rows, Dinv, dinv_off, R, Y, refine, conv, ir, st);
+      if (e != hipSuccess) return e;
+      if (sp.nblk == sp.nmat) return hipSuccess;
+    }
+  }
   switch (sp.lg) {
     case 4: launch_trsv<P, 4>(sp, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
     case 8: launch_trsv<P, 8>(sp, pd, md, na, T, rows, Dinv, dinv_off, R, Y, rf, conv, ir, st); break;
@@ -419,7 +429,16 @@ void SolvePlan_build(SolvePlan& sp, std::vector<int>& /*buf*/, const std::vector
     if (m.n > 2 * kTrsvThreadsSmall) ++sp.nbig;
     else if (m.n > kTrsvThreadsSmall) ++sp.nmid;
   }
-  sp.lg = pick_lg(sp.nmat, L);
+  // complex FP32 with an even number (at most 64) of right-hand sides: the
+  // matrices of at least kSolveBlockedMinN rows take the blocked solve
+  sp.nblk = 0;
+  sp.L = L;
+  if (prec != NEP_PREC_FP64 && L % 2 == 0 && L <= 64)
+    while (sp.nblk < sp.nmat && sorted[sp.nblk].n >= kSolveBlockedMinN) ++sp.nblk;
+  sp.npad = sp.nblk > 0 ? ceil_div(sorted[0].n, kSolveBlk) * kSolveBlk : 0;
+  sp.nbk = 256;
+  sp.W = nullptr;
+  sp.lg = pick_lg(sp.nmat - sp.nblk, L);
   while (sp.lg > 4 && !solve_lg_fits(sp, sp.lg, L, prec)) sp.lg >>= 1;
   sp.groups = ceil_div(L, sp.lg);
   sp.paired = -1;
