@@ -14,6 +14,7 @@ constexpr int kMaxTerms = 16;
 constexpr int kMaxMoments = 32;  // 2K
 constexpr int kSolveBlk = 64;    // triangular-solve block rows
 constexpr int kResidRealTM = 64, kResidRealTQ = 64;  // real-term residual tile: rows x real columns
+constexpr int kResidBigTM = 128, kResidBigTQ = 128;  // the same when the big tiles still fill the device
 constexpr int kFallbackSweeps = 2;  // FP64 refinement sweeps after an FP64 re-solve
 constexpr int kNormStride = 64;  // per-node stride of the column-norm arrays (L <= 64)
 // Default stopping tolerance of the refinement (normwise backward error per
@@ -114,7 +115,9 @@ void solve_set_lg(SolvePlan& sp, int lg, int L);
 struct ProblemTables {
   Table assemble;  // element tiles per problem
   Table resid;       // residual GEMM tiles per problem with complex terms (64 x 64)
-  Table resid_real;  // residual GEMM tiles per problem with real terms only (kResidRealTM x kResidRealTQ)
+  Table resid_real;  // residual GEMM tiles per problem with real terms only (kResidRealTM x kResidRealTQ,
+                     // or kResidBigTM x kResidBigTQ with resid_big)
+  int resid_big = 0;
   Table moments;   // n*L tiles per problem
 };
 
@@ -141,7 +144,7 @@ void SolvePlan_build(SolvePlan& sp, std::vector<int>& buf, const std::vector<Mat
                      std::vector<long long>& dinv_off, long long& dinv_elems);
 hipError_t solve_configure();
 
-hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const Table& tr, const NodeArrays& na,
+hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const Table& tr, int resid_big, const NodeArrays& na,
                      const c128* Y, c128* R, IrState ir, int nnodes, hipStream_t st);
 // status read-back block (see k_gather_status) and its size
 size_t status_bytes(int G);

@@ -298,12 +298,20 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   SolvePlan_build(sp_, hprefix_, sorted_, o.L, o.prec, dinv_off_, dinv_elems_);
   {
     std::vector<int> ca, cr, crr, cm;
+    // real-term residual tiles: the big ones when they still give every CU
+    // two groups (they halve the operand traffic per product)
+    long long big_tiles = 0;
+    for (int p = 0; p < nprob; ++p)
+      if (probs[p].op->a_cplx == 0)
+        big_tiles += (long long)ceil_div(hpd_[p].n, kResidBigTM) * ceil_div(2 * o.N * o.L, kResidBigTQ);
+    pt_.resid_big = big_tiles >= 512 ? 1 : 0;
+    const int rtm = pt_.resid_big ? kResidBigTM : kResidRealTM, rtq = pt_.resid_big ? kResidBigTQ : kResidRealTQ;
     for (int p = 0; p < nprob; ++p) {
       const long long n = hpd_[p].n;
       const bool cplx = probs[p].op->a_cplx != 0;
       ca.push_back((int)ceil_div_ll(n * n, 256));
       cr.push_back(cplx ? ceil_div((int)n, 64) * ceil_div(2 * o.N * o.L, 64) : 0);
-      crr.push_back(cplx ? 0 : ceil_div((int)n, kResidRealTM) * ceil_div(2 * o.N * o.L, kResidRealTQ));
+      crr.push_back(cplx ? 0 : ceil_div((int)n, rtm) * ceil_div(2 * o.N * o.L, rtq));
       cm.push_back(ceil_div((int)n * o.L, 256) * ceil_div(2 * o.K, 8));  // (row, column) blocks x moment groups
     }
     build_prefix(hprefix_, pt_.assemble, ca);
@@ -443,7 +451,7 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager, bool refactor) {
     // trip; nodes already converged skip the solve, which makes it a no-op
     // when the count turns out to be zero.
     for (int s = 0; s <= opt.max_refine; ++s) {
-      NEP_HIP(resid_run(pd, pre, pt_.resid, pt_.resid_real, na_, Y, R, ir_, nnodes, st));
+      NEP_HIP(resid_run(pd, pre, pt_.resid, pt_.resid_real, pt_.resid_big, na_, Y, R, ir_, nnodes, st));
       NEP_HIP(ir_control(pd, na_, ir_, nnodes, s, opt.tol, st));
       sweeps_run_ = s;
       if (eager) {
@@ -538,7 +546,7 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
   NEP_HIP(solve_run<double>(sp_, pd, md, na_, T, drows_.as<int>(), Dinv, doff, nullptr, dY_.as<c128>(), false,
                             skip, ir_, st));
   for (int s = 0;; ++s) {
-    NEP_HIP(resid_run(pd, pre, pt_.resid, pt_.resid_real, na_, dY_.as<c128>(), dR_.as<c128>(), ir_, nnodes, st));
+    NEP_HIP(resid_run(pd, pre, pt_.resid, pt_.resid_real, pt_.resid_big, na_, dY_.as<c128>(), dR_.as<c128>(), ir_, nnodes, st));
     NEP_HIP(ir_control(pd, na_, ir_, nnodes, opt.max_refine + 1 + s, opt.tol, st));
     if (s == kFallbackSweeps) break;
     NEP_HIP(hipMemcpyAsync(hcounter_, ir_.counters, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -168,10 +168,8 @@ __global__ __launch_bounds__(256) void k_resid(const ProbDesc* __restrict__ pd, 
 // v_mfma_f64_16x16x4f64.  The next stage's A and f_i(z_j) Y tiles are loaded
 // into registers while the current stage runs from LDS (double-buffered).
 // ---------------------------------------------------------------------------
-constexpr int kR2KC = 32;
-
-template <int TM, int TQ, int WR, int WQ>
-__global__ __launch_bounds__(64 * WR * WQ) void k_resid_real(const ProbDesc* __restrict__ pd,
+template <int TM, int TQ, int WR, int WQ, int kR2KC>
+__global__ __launch_bounds__(64 * WR * WQ, 4) void k_resid_real(const ProbDesc* __restrict__ pd,
                                                               const int* __restrict__ prefix, int cnt, int total,
                                                               NodeArrays na, const c128* __restrict__ Y,
                                                               c128* __restrict__ R, IrState ir) {
@@ -320,14 +318,20 @@ __global__ __launch_bounds__(64 * WR * WQ) void k_resid_real(const ProbDesc* __r
 }
 
 // t: tiles of the complex-term kernel (64 x 64); tr: tiles of the real-term
-// kernel (128 x 64).  A problem counts in exactly one of them.
-hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const Table& tr, const NodeArrays& na,
-                     const c128* Y, c128* R, IrState ir, int /*nnodes*/, hipStream_t st) {
+// kernel (resid_big: kResidBigTM x kResidBigTQ, else kResidRealTM x
+// kResidRealTQ).  A problem counts in exactly one of them.  Every tile shape
+// issues the same products in the same order for each element (terms in
+// order, k ascending in steps of 4), so the choice does not change results.
+hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const Table& tr, int resid_big,
+                     const NodeArrays& na, const c128* Y, c128* R, IrState ir, int /*nnodes*/, hipStream_t st) {
   if (tr.total > 0) {
-    constexpr int WR = 4, WQ = 2;  // 8 waves of 16 x 32
-    hipLaunchKernelGGL((k_resid_real<kResidRealTM, kResidRealTQ, WR, WQ>), dim3(xcd_grid(tr.total)), dim3(64 * WR * WQ),
-                       0, st, pd, prefix + tr.off, tr.cnt,
-                       tr.total, na, Y, R, ir);
+    constexpr int WR = 4, WQ = 2;  // 8 waves
+    if (resid_big)  // waves of 32 x 64: twice the reuse of each staged element
+      hipLaunchKernelGGL((k_resid_real<kResidBigTM, kResidBigTQ, WR, WQ, 8>), dim3(xcd_grid(tr.total)),
+                         dim3(64 * WR * WQ), 0, st, pd, prefix + tr.off, tr.cnt, tr.total, na, Y, R, ir);
+    else  // waves of 16 x 32
+      hipLaunchKernelGGL((k_resid_real<kResidRealTM, kResidRealTQ, WR, WQ, 32>), dim3(xcd_grid(tr.total)),
+                         dim3(64 * WR * WQ), 0, st, pd, prefix + tr.off, tr.cnt, tr.total, na, Y, R, ir);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
