@@ -567,7 +567,7 @@ __global__ __launch_bounds__(NT) void k_lu_panel(const MatDesc* __restrict__ md,
   const int n = d.n;
   if (k0 >= n) return;
   if (skip != nullptr && skip[d.node]) return;
-  const int jb = min(jbmax, n - k0);  // jbmax <= kSolveBlkLu
+  const int jb = min(jbmax, n - k0);  // jbmax <= kLuMaxJB, a multiple of kSolveBlkLu
   cx<P>* __restrict__ T = Tb + d.offT;
   const int ld = d.ld;
   const int* __restrict__ rowg = rsrc + d.offRow;
@@ -733,30 +733,92 @@ __global__ __launch_bounds__(NT) void k_lu_panel(const MatDesc* __restrict__ md,
   for (int r = tid; r < m; r += NT) rowo[k0 + r] = rat[r];
   if (tid == 0 && zp < n) atomicMin(&info[d.node], zp);
 
-  // ---- inverse of the unit lower block L11 (recursive doubling in LDS):
-  // inv(L11) for the U12 product when trailing columns follow, and the 64 x 64
-  // diagonal-block inverse of L that the triangular solves use (Dinv layout
-  // per matrix: [blk][0: L, 1: U][64][64], row-major, identity-padded)
+  // ---- inverses of the unit lower 64 x 64 diagonal blocks of L11
+  // (recursive doubling in LDS): the 64 x 64 diagonal-block inverses of L
+  // that the triangular solves use (Dinv layout per matrix: [blk][0: L, 1:
+  // U][64][64], row-major, identity-padded) and, when trailing columns
+  // follow, the diagonal blocks of inv(L11) for the U12 product (a 128-wide
+  // panel's off-diagonal block of inv(L11) is formed by k_lu_linv_pair)
   {
     constexpr int B = kSolveBlkLu, lx = B + 1;
     cx<P>* X = reinterpret_cast<cx<P>*>(pool);
-    for (int e = tid; e < B * B; e += NT) {
-      const int i = e / B, k = e - i * B;
-      cx<P> v = {P(i == k ? 1 : 0), P(0)};
-      if (i < jb && k < i) v = cget(T[(long long)rat[i] * ld + k0 + k]);
-      cput(X[i * lx + k], v);
-    }
-    __syncthreads();
-    tri_inv_lds<P, false, NT>(X, lx, B);
-    if (n - k0 - jb > 0) {
-      cx<P>* __restrict__ Li = Linv + (long long)b * kLuMaxJB * kLuMaxJB;
-      for (int e = tid; e < jb * jb; e += NT) {
-        const int i = e / jb, k = e - i * jb;
-        cput(Li[(long long)i * kLuMaxJB + k], cget(X[i * lx + k]));
+    for (int q0 = 0; q0 < jb; q0 += B) {
+      const int nb = min(B, jb - q0);
+      __syncthreads();  // the pool is free
+      for (int e = tid; e < B * B; e += NT) {
+        const int i = e / B, k = e - i * B;
+        cx<P> v = {P(i == k ? 1 : 0), P(0)};
+        if (i < nb && k < i) v = cget(T[(long long)rat[q0 + i] * ld + k0 + q0 + k]);
+        cput(X[i * lx + k], v);
       }
+      __syncthreads();
+      tri_inv_lds<P, false, NT>(X, lx, B);
+      if (n - k0 - jb > 0) {
+        cx<P>* __restrict__ Li = Linv + (long long)b * kLuMaxJB * kLuMaxJB + (long long)q0 * kLuMaxJB + q0;
+        for (int e = tid; e < nb * nb; e += NT) {
+          const int i = e / nb, k = e - i * nb;
+          cput(Li[(long long)i * kLuMaxJB + k], cget(X[i * lx + k]));
+        }
+      }
+      cx<P>* __restrict__ out = Dinv + dinv_off[b] + ((long long)((k0 + q0) / B) * 2 + 0) * B * B;
+      for (int e = tid; e < B * B; e += NT) cput(out[e], cget(X[(e / B) * lx + (e % B)]));
     }
-    cx<P>* __restrict__ out = Dinv + dinv_off[b] + ((long long)(k0 / B) * 2 + 0) * B * B;
-    for (int e = tid; e < B * B; e += NT) cput(out[e], cget(X[(e / B) * lx + (e % B)]));
+  }
+}
+
+// inv(L11) of a 128-wide panel: [A 0; C B] (unit lower, 64 x 64 blocks) has
+// the inverse [inv(A) 0; -inv(B) C inv(A) inv(B)].  The panel stored inv(A)
+// and inv(B); this forms the off-diagonal block in FP64 (two 64 x 64 x 64
+// products, rounded once) and zeroes the upper one.  One group per matrix
+// with trailing columns.
+template <typename P>
+__global__ __launch_bounds__(256) void k_lu_linv_pair(const MatDesc* __restrict__ md, int k0,
+                                                      const cx<P>* __restrict__ Tb, const int* __restrict__ rowb,
+                                                      cx<P>* __restrict__ Linv, const int* __restrict__ skip) {
+  constexpr int B = kSolveBlkLu, J = kLuMaxJB;
+  const int b = blockIdx.x;
+  const MatDesc d = md[b];
+  if (skip != nullptr && skip[d.node]) return;
+  if (d.n - k0 - J <= 0) return;  // no trailing block: inv(L11) is not used
+  const cx<P>* __restrict__ T = Tb + d.offT;
+  const int* __restrict__ rat = rowb + d.offRow;
+  cx<P>* __restrict__ Li = Linv + (long long)b * J * J;
+  __shared__ cx<P> Ms[B][B + 1];   // inv(A), then inv(B)
+  __shared__ cx<P> Cs[B][B + 1];   // C
+  __shared__ c128 Ys[B][B + 1];    // C inv(A)
+  const int tid = threadIdx.x;
+  for (int e = tid; e < B * B; e += 256) {
+    const int i = e / B, k = e - i * B;
+    Ms[i][k] = Li[(long long)i * J + k];
+    Cs[i][k] = T[(long long)rat[k0 + B + i] * d.ld + k0 + k];
+  }
+  __syncthreads();
+  // thread: row i = tid / 4, columns j = tid % 4 + 4 u
+  const int i = tid >> 2, j0 = tid & 3;
+  for (int u = 0; u < B / 4; ++u) {
+    const int j = j0 + 4 * u;
+    c128 acc = {0.0, 0.0};
+    for (int k = j; k < B; ++k) {  // inv(A) is lower triangular
+      const cx<P> c = Cs[i][k], m = Ms[k][j];
+      acc = acc + c128{double(c.re), double(c.im)} * c128{double(m.re), double(m.im)};
+    }
+    Ys[i][j] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < B * B; e += 256) {
+    const int r = e / B, k = e - r * B;
+    Ms[r][k] = Li[(long long)(B + r) * J + B + k];
+  }
+  __syncthreads();
+  for (int u = 0; u < B / 4; ++u) {
+    const int j = j0 + 4 * u;
+    c128 acc = {0.0, 0.0};
+    for (int k = 0; k <= i; ++k) {  // inv(B) is lower triangular
+      const cx<P> m = Ms[i][k];
+      acc = acc + c128{double(m.re), double(m.im)} * Ys[k][j];
+    }
+    Li[(long long)(B + i) * J + j] = cx<P>{P(-acc.re), P(-acc.im)};
+    Li[(long long)i * J + B + j] = cx<P>{P(0), P(0)};
   }
 }
 
@@ -1015,7 +1077,7 @@ __global__ __launch_bounds__(64 * NW) void k_lu_gemm_c64(const MatDesc* __restri
 // other group has read A12 by then.
 // Grid: the row tiles of all active matrices (prefix table).  Operand lane
 // roles and the accumulator layout are those of k_lu_gemm_c64.
-constexpr int kP0TM = 128, kP0TN = kPart0Cols, kP0KC = 16;
+constexpr int kP0TM = 128, kP0TN = kPart0Cols, kP0KC = 16;  // (64-wide panels only)
 constexpr int kP0Waves = 8;  // waves per group
 
 template <int NW>
@@ -1413,11 +1475,16 @@ static hipError_t launch_panel(int rpt, int nact, const MatDesc* md, int k0, int
   return hipGetLastError();
 }
 
-int lu_jb(int /*prec*/) { return 64; }  // panel width (both precisions)
+// Panel width: 128 in complex FP32 when every matrix has at least
+// kLuWideMinN rows (the trailing update then runs with k = 128, half the C
+// traffic per product), else 64.  A matrix's factors depend on the width, so
+// a matrix factors identically in every plan of the same width.
+int lu_jb(int prec, int nmin) { return prec != NEP_PREC_FP64 && nmin >= kLuWideMinN ? 128 : 64; }
 
 void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
   prec = prec_;
-  jb = lu_jb(prec);
+  jb = lu_jb(prec, sorted.empty() ? 0 : sorted.back().n);
+  const int p0cols = jb;  // part 0: the columns of the next panel
   nmat = (int)sorted.size();
   nvec.clear();
   for (const auto& m : sorted) nvec.push_back(m.n);
@@ -1437,13 +1504,15 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
     int rmax = sorted[0].n - k0;
     s.rpt = rmax <= 512 ? 1 : rmax <= 1024 ? 2 : rmax <= 2048 ? 4 : 8;
     // tile prefixes of the block-row product (U12) and of the trailing
-    // update, each in two parts: part 0 = the first kPart0Cols trailing
-    // columns (they hold the next panel), part 1 = the rest.  Complex FP32
-    // runs part 0 as one fused kernel (128-row tiles, U12 formed in each).
+    // update, each in two parts: part 0 = the first jb trailing columns
+    // (they hold the next panel), part 1 = the rest.  Complex FP32 with
+    // 64-wide panels runs part 0 as one fused kernel (128-row tiles, U12
+    // formed in each); 128-wide panels take the two products.
     const bool f32 = prec != NEP_PREC_FP64;
+    const bool fused0 = f32 && jb == kPart0Cols;
     const int TM = f32 ? kG32TM : kG64TM;
     for (int part = 0; part < 2; ++part) {
-      const int TN = part == 0 ? kPart0Cols : (f32 ? kG32TN : kG64TN);
+      const int TN = part == 0 ? p0cols : (f32 ? kG32TN : kG64TN);
       for (int kind = 0; kind < 2; ++kind) {  // 0: U12 product, 1: trailing update
         int& off = kind == 0 ? s.off_trsm[part] : s.off_gemm[part];
         int& tot = kind == 0 ? s.tot_trsm[part] : s.tot_gemm[part];
@@ -1452,9 +1521,9 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
         prefix.push_back(0);
         for (int b = 0; b < nact; ++b) {
           const int n = sorted[b].n, jbb = std::min(jb, n - k0), mt = n - k0 - jbb;
-          const int ncols = part == 0 ? std::min(mt, kPart0Cols) : std::max(0, mt - kPart0Cols);
+          const int ncols = part == 0 ? std::min(mt, p0cols) : std::max(0, mt - p0cols);
           const int ntn = ncols > 0 ? ceil_div(ncols, TN) : 0;
-          if (kind == 0) acc += (f32 && part == 0) ? 0 : ntn;
+          if (kind == 0) acc += (fused0 && part == 0) ? 0 : ntn;
           else acc += (mt > 0 ? ceil_div(mt, TM) : 0) * ntn;
           prefix.push_back(acc);
         }
@@ -1512,6 +1581,12 @@ static hipError_t lu_panel_step(const LuPlan& plan, const LuPlan::Step& s, const
                            Linv + (long long)s.nsmall * kLuMaxJB * kLuMaxJB, Dinv, dinv_off + s.nsmall, st)) !=
           hipSuccess)
     return e;
+  if constexpr (sizeof(P) == 4) {  // 128-wide panels (complex FP32 only): the off-diagonal block of inv(L11)
+    if (plan.jb > kSolveBlkLu) {
+      hipLaunchKernelGGL(k_lu_linv_pair<P>, dim3(s.nact), dim3(256), 0, st, d_md, s.k0, T, rdst, Linv, skip);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
   hipStream_t su = st;
   if (side != nullptr) {
     if ((e = hipEventRecord(ev_side, st)) != hipSuccess) return e;
@@ -1528,9 +1603,9 @@ template <typename P>
 static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int part, const MatDesc* d_md,
                                  const int* d_prefix, cx<P>* T, const int* rows, const int* rows_ac, const int* skip,
                                  const cx<P>* Linv, int* arrivals, hipStream_t st) {
-  const int coff = part == 0 ? 0 : kPart0Cols, ntn = part == 0 ? 1 : INT_MAX;
+  const int coff = part == 0 ? 0 : plan.jb, ntn = part == 0 ? 1 : INT_MAX;
   if constexpr (sizeof(P) == 4) {
-    if (part == 0) {  // fused U12 product and update of the first columns
+    if (part == 0 && plan.jb == kPart0Cols) {  // fused U12 product and update of the first columns
       if (s.tot_gemm[0] > 0) {
         hipLaunchKernelGGL((k_lu_part0_c64<kP0Waves>), dim3(xcd_grid(s.tot_gemm[0])), dim3(64 * kP0Waves), 0, st, d_md,
                            d_prefix + s.off_gemm[0], s.nact, s.tot_gemm[0], s.k0, plan.jb, T, rows, skip, Linv,
@@ -1575,7 +1650,7 @@ static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int 
       for (int b = 0; b < s.nact; ++b) {
         const int n = plan.nvec[b], jbb = std::min(plan.jb, n - s.k0), mt = n - s.k0 - jbb;
         if (mt <= 0) continue;
-        const int c_lo = part == 0 ? 0 : std::min(mt, kPart0Cols), c_hi = part == 0 ? std::min(mt, kPart0Cols) : mt;
+        const int c_lo = part == 0 ? 0 : std::min(mt, plan.jb), c_hi = part == 0 ? std::min(mt, plan.jb) : mt;
         flops += 8.0 * mt * (double)(c_hi - c_lo) * jbb;
       }
       g_prof.add(sizeof(P) == 4 ? 0 : 1, ev0, ev1, flops);
@@ -1615,7 +1690,10 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int nsteps = (int)plan.steps.size();
   if (nsteps == 0) return hipSuccess;
-  if (plan.jb > kSolveBlkLu) return hipErrorInvalidValue;  // the panel inverts one 64 x 64 block
+  // panels of 64 or 128 columns (64-column diagonal blocks; the part-0 tile
+  // column of the complex-FP64 update is 64 wide)
+  if (plan.jb % kSolveBlkLu != 0 || plan.jb > kLuMaxJB || (sizeof(P) == 8 && plan.jb != kSolveBlkLu))
+    return hipErrorInvalidValue;
   const bool lookahead = aux != nullptr && rows_alt != nullptr;
   int* const R[2] = {rows, lookahead ? rows_alt : rows};
   auto map = [&](int k) { return R[(k + 1) & 1]; };  // map of step k (map -1: the initial one)
@@ -1629,7 +1707,11 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
     const auto& s = plan.steps[k];
     const bool has_next = k + 1 < nsteps;
     const bool overlap = lookahead && has_next && (s.tot_gemm[1] > 0 || s.tot_trsm[1] > 0);
-    const bool early = plan.early_fork >= 0 ? plan.early_fork != 0 : sizeof(P) == 4;  // fork before the first columns' update
+    // fork before the first columns' update: built in for 64-wide complex
+    // FP32 panels; with 128-wide panels the late fork lets the next panel
+    // start before the update takes the CUs (n = 4096: 172.8 against 206.1 ms
+    // per moment pass)
+    const bool early = plan.early_fork >= 0 ? plan.early_fork != 0 : (sizeof(P) == 4 && plan.jb == kSolveBlkLu);
     auto fork = [&]() -> hipError_t {
       hipError_t r;
       if ((r = hipEventRecord(ev_fork, st)) != hipSuccess) return r;

@@ -13,6 +13,9 @@ constexpr int kPart0Cols = 64;   // trailing columns updated first in each step 
 // small panels (at most 256 rows left) in a step before they take the
 // 256-thread groups, by default
 constexpr int kSmallPanelsMin = 512;
+// complex FP32 plans whose matrices all have at least this many rows take
+// 128-wide panels
+constexpr int kLuWideMinN = 2048;
 
 // Launch plan of a (possibly ragged) batch: matrices sorted by n, descending.
 struct LuPlan {
@@ -36,8 +39,8 @@ struct LuPlan {
   // either group size gives the same bits, so this is a pure launch-shape knob
   int small_min = kSmallPanelsMin;
   // look-ahead fork point of the rest of a step's update: 1 as soon as the
-  // panel is done, 0 after the first columns' update, -1 by precision (1 in
-  // complex FP32, 0 in complex FP64); a pure scheduling knob
+  // panel is done, 0 after the first columns' update, -1 built in (1 for
+  // 64-wide complex FP32 panels, else 0); a pure scheduling knob
   int early_fork = -1;
   std::vector<Step> steps;
   std::vector<int> prefix;  // uploaded once; offsets above index into it
@@ -58,7 +61,7 @@ struct KernelProf {
 };
 KernelProf& kernel_prof();
 
-int lu_jb(int prec);
+int lu_jb(int prec, int nmin);
 hipError_t lu_configure();
 
 // Linv: workspace of 2 * nmat * kLuMaxJB^2 elements (inverses of the L11 blocks,
