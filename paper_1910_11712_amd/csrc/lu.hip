@@ -737,11 +737,16 @@ __global__ __launch_bounds__(NT) void k_lu_panel(const MatDesc* __restrict__ md,
   // (recursive doubling in LDS): the 64 x 64 diagonal-block inverses of L
   // that the triangular solves use (Dinv layout per matrix: [blk][0: L, 1:
   // U][64][64], row-major, identity-padded) and, when trailing columns
-  // follow, the diagonal blocks of inv(L11) for the U12 product (a 128-wide
-  // panel's off-diagonal block of inv(L11) is formed by k_lu_linv_pair)
+  // follow, inv(L11) for the U12 product.  A 128-wide panel's L11 = [A 0; C B]
+  // has the inverse [inv(A) 0; -inv(B) C inv(A)  inv(B)]: with inv(A) still
+  // in LDS, Y = C inv(A) goes (FP64 sums, rounded once) to the block of Linv
+  // that -inv(B) Y later replaces.
   {
     constexpr int B = kSolveBlkLu, lx = B + 1;
+    constexpr int YPT = B * B / NT;  // off-diagonal entries per thread
     cx<P>* X = reinterpret_cast<cx<P>*>(pool);
+    const bool trailing = n - k0 - jb > 0;
+    cx<P>* __restrict__ Li0 = Linv + (long long)b * kLuMaxJB * kLuMaxJB;
     for (int q0 = 0; q0 < jb; q0 += B) {
       const int nb = min(B, jb - q0);
       __syncthreads();  // the pool is free
@@ -753,8 +758,8 @@ __global__ __launch_bounds__(NT) void k_lu_panel(const MatDesc* __restrict__ md,
       }
       __syncthreads();
       tri_inv_lds<P, false, NT>(X, lx, B);
-      if (n - k0 - jb > 0) {
-        cx<P>* __restrict__ Li = Linv + (long long)b * kLuMaxJB * kLuMaxJB + (long long)q0 * kLuMaxJB + q0;
+      if (trailing) {
+        cx<P>* __restrict__ Li = Li0 + (long long)q0 * kLuMaxJB + q0;
         for (int e = tid; e < nb * nb; e += NT) {
           const int i = e / nb, k = e - i * nb;
           cput(Li[(long long)i * kLuMaxJB + k], cget(X[i * lx + k]));
@@ -762,63 +767,39 @@ __global__ __launch_bounds__(NT) void k_lu_panel(const MatDesc* __restrict__ md,
       }
       cx<P>* __restrict__ out = Dinv + dinv_off[b] + ((long long)((k0 + q0) / B) * 2 + 0) * B * B;
       for (int e = tid; e < B * B; e += NT) cput(out[e], cget(X[(e / B) * lx + (e % B)]));
+      if (trailing && q0 == 0 && jb > B) {  // Y = C inv(A) into Linv[B.., 0..B)
+        __syncthreads();  // inv(A) in X is complete
+        for (int u = 0; u < YPT; ++u) {
+          const int e = tid + NT * u, i = e / B, j = e - i * B;
+          const cx<P>* __restrict__ crow = T + (long long)rat[B + i] * ld + k0;
+          c128 acc = {0.0, 0.0};
+          for (int k = j; k < B; ++k) {  // inv(A) is lower triangular
+            const cx<P> c = crow[k], m = cget(X[k * lx + j]);
+            acc = acc + c128{double(c.re), double(c.im)} * c128{double(m.re), double(m.im)};
+          }
+          Li0[(long long)(B + i) * kLuMaxJB + j] = cx<P>{P(acc.re), P(acc.im)};
+        }
+      }
     }
-  }
-}
-
-// inv(L11) of a 128-wide panel: [A 0; C B] (unit lower, 64 x 64 blocks) has
-// the inverse [inv(A) 0; -inv(B) C inv(A) inv(B)].  The panel stored inv(A)
-// and inv(B); this forms the off-diagonal block in FP64 (two 64 x 64 x 64
-// products, rounded once) and zeroes the upper one.  One group per matrix
-// with trailing columns.
-template <typename P>
-__global__ __launch_bounds__(256) void k_lu_linv_pair(const MatDesc* __restrict__ md, int k0,
-                                                      const cx<P>* __restrict__ Tb, const int* __restrict__ rowb,
-                                                      cx<P>* __restrict__ Linv, const int* __restrict__ skip) {
-  constexpr int B = kSolveBlkLu, J = kLuMaxJB;
-  const int b = blockIdx.x;
-  const MatDesc d = md[b];
-  if (skip != nullptr && skip[d.node]) return;
-  if (d.n - k0 - J <= 0) return;  // no trailing block: inv(L11) is not used
-  const cx<P>* __restrict__ T = Tb + d.offT;
-  const int* __restrict__ rat = rowb + d.offRow;
-  cx<P>* __restrict__ Li = Linv + (long long)b * J * J;
-  __shared__ cx<P> Ms[B][B + 1];   // inv(A), then inv(B)
-  __shared__ cx<P> Cs[B][B + 1];   // C
-  __shared__ c128 Ys[B][B + 1];    // C inv(A)
-  const int tid = threadIdx.x;
-  for (int e = tid; e < B * B; e += 256) {
-    const int i = e / B, k = e - i * B;
-    Ms[i][k] = Li[(long long)i * J + k];
-    Cs[i][k] = T[(long long)rat[k0 + B + i] * d.ld + k0 + k];
-  }
-  __syncthreads();
-  // thread: row i = tid / 4, columns j = tid % 4 + 4 u
-  const int i = tid >> 2, j0 = tid & 3;
-  for (int u = 0; u < B / 4; ++u) {
-    const int j = j0 + 4 * u;
-    c128 acc = {0.0, 0.0};
-    for (int k = j; k < B; ++k) {  // inv(A) is lower triangular
-      const cx<P> c = Cs[i][k], m = Ms[k][j];
-      acc = acc + c128{double(c.re), double(c.im)} * c128{double(m.re), double(m.im)};
+    if (trailing && jb > B) {  // X = -inv(B) Y (inv(B) in LDS), the upper block zero
+      __syncthreads();  // Y is in Linv for every thread
+      cx<P> xo[YPT];
+      for (int u = 0; u < YPT; ++u) {
+        const int e = tid + NT * u, i = e / B, j = e - i * B;
+        c128 acc = {0.0, 0.0};
+        for (int k = 0; k <= i; ++k) {  // inv(B) is lower triangular
+          const cx<P> m = cget(X[i * lx + k]), y = Li0[(long long)(B + k) * kLuMaxJB + j];
+          acc = acc + c128{double(m.re), double(m.im)} * c128{double(y.re), double(y.im)};
+        }
+        xo[u] = cx<P>{P(-acc.re), P(-acc.im)};
+      }
+      __syncthreads();  // every thread has read Y
+      for (int u = 0; u < YPT; ++u) {
+        const int e = tid + NT * u, i = e / B, j = e - i * B;
+        Li0[(long long)(B + i) * kLuMaxJB + j] = xo[u];
+        Li0[(long long)i * kLuMaxJB + B + j] = cx<P>{P(0), P(0)};
+      }
     }
-    Ys[i][j] = acc;
-  }
-  __syncthreads();
-  for (int e = tid; e < B * B; e += 256) {
-    const int r = e / B, k = e - r * B;
-    Ms[r][k] = Li[(long long)(B + r) * J + B + k];
-  }
-  __syncthreads();
-  for (int u = 0; u < B / 4; ++u) {
-    const int j = j0 + 4 * u;
-    c128 acc = {0.0, 0.0};
-    for (int k = 0; k <= i; ++k) {  // inv(B) is lower triangular
-      const cx<P> m = Ms[i][k];
-      acc = acc + c128{double(m.re), double(m.im)} * Ys[k][j];
-    }
-    Li[(long long)(B + i) * J + j] = cx<P>{P(-acc.re), P(-acc.im)};
-    Li[(long long)i * J + B + j] = cx<P>{P(0), P(0)};
   }
 }
 
@@ -1581,12 +1562,6 @@ static hipError_t lu_panel_step(const LuPlan& plan, const LuPlan::Step& s, const
                            Linv + (long long)s.nsmall * kLuMaxJB * kLuMaxJB, Dinv, dinv_off + s.nsmall, st)) !=
           hipSuccess)
     return e;
-  if constexpr (sizeof(P) == 4) {  // 128-wide panels (complex FP32 only): the off-diagonal block of inv(L11)
-    if (plan.jb > kSolveBlkLu) {
-      hipLaunchKernelGGL(k_lu_linv_pair<P>, dim3(s.nact), dim3(256), 0, st, d_md, s.k0, T, rdst, Linv, skip);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-  }
   hipStream_t su = st;
   if (side != nullptr) {
     if ((e = hipEventRecord(ev_side, st)) != hipSuccess) return e;
