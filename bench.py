@@ -284,19 +284,38 @@ def _serve_run(P, prec, rate=200.0, duration=2.0, warmup=0.5):
     ok = [r for _, r in meas if r["status"] == 0]
     span = max(r["t_done"] for _, r in meas) - min(r["t_submit"] for _, r in meas)
     good = sum(int(np.sum(r["inside"] & (r["eta"] <= 1e-10))) for r in ok)
+    reused = sum(1 for _, r in meas if r.get("reused"))
     codes = {}
     for _, r in meas:
         codes[r["status"]] = codes.get(r["status"], 0) + 1
     return {"prec": prec, "rate_qps": rate, "window_s": duration, "queries": len(meas),
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "queries_per_s": len(meas) / span, "eigenpairs_eta_le_1e-10_per_s": good / span,
+            "reused": reused,
             "status_counts": {P.binding.ERRORS.get(k, "NEP_OK"): v for k, v in codes.items()}}
 
 
-def _serve_full(P, rate, duration, warmup):
+def _serve_full(P, rate, duration, warmup, rates=()):
+    """The serving stream at `rate` for warmup + duration seconds in both
+    precisions; with `rates`, first a sweep of shorter runs (3 s warm-up, 15 s
+    measured) at each offered rate.  The sustainable rate is the highest
+    offered rate of the sweep that is served in full (served >= 97% of
+    offered) with p99 under 2 s."""
     out = {}
     for prec in ("mixed", "fp64"):
-        out[prec] = _serve_run(P, prec, rate=rate, duration=duration, warmup=warmup)
+        sweep = []
+        for r in rates:
+            x = _serve_run(P, prec, rate=r, duration=15.0, warmup=3.0)
+            sweep.append({k: x[k] for k in ("rate_qps", "queries", "queries_per_s", "p50_ms", "p99_ms",
+                                            "reused", "status_counts")})
+            print(f"[bench] serving {prec} sweep {r} q/s: {x['queries_per_s']:.1f} q/s served, "
+                  f"p99 {x['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
+        ok = [x["rate_qps"] for x in sweep if x["queries_per_s"] >= 0.97 * x["rate_qps"] and x["p99_ms"] < 2000.0]
+        res = _serve_run(P, prec, rate=rate, duration=duration, warmup=warmup)
+        if rates:
+            res["sweep"] = sweep
+            res["sustainable_qps"] = max(ok) if ok else None
+        out[prec] = res
         print(f"[bench] serving {prec} {rate} q/s done", file=sys.stderr, flush=True)
     return out
 
@@ -312,6 +331,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="built-in launch shapes (no autotuning)")
     ap.add_argument("--rate", type=float, default=200.0, help="cfg4: offered queries/s")
     ap.add_argument("--window", type=float, default=60.0, help="cfg4: measured seconds after the warm-up")
+    ap.add_argument("--rates", default="", help="cfg4: comma-separated offered rates of a sustainable-rate sweep")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -338,7 +358,8 @@ def main():
         print(json.dumps({"workload": "cfg3_batch_graph", **_batch_run(P, steps=args.steps, tune=not args.no_tune)}))
         return
     if args.workload == "cfg4":  # the serving stream alone, both precisions, one JSON line
-        print(json.dumps({"workload": "cfg4_serving", **_serve_full(P, args.rate, args.window, 5.0)}))
+        rates = [float(x) for x in args.rates.split(",") if x.strip()]
+        print(json.dumps({"workload": "cfg4_serving", **_serve_full(P, args.rate, args.window, 5.0, rates)}))
         return
     cfg = _workload(args.workload)
     prob = cfg["problem"]
