@@ -258,15 +258,19 @@ def _batch_run(P, steps=5, tune=True):
     return out
 
 
-def _serve_run(P, prec, rate=200.0, duration=2.0, warmup=0.5):
+def _serve_run(P, prec, rate=200.0, duration=2.0, warmup=0.5, srv=None, ops=None):
     """Config 4 (shortened): Poisson arrivals of mixed queries served with
-    continuous batching; latency = result on the host - submission."""
+    continuous batching; latency = result on the host - submission.  With srv
+    and ops given, the run uses that server (and its resident factors) and
+    those operators and leaves them open."""
     import workloads as wl
     cfg = wl.config4_stream(rate=rate, duration=duration, warmup=warmup)
-    ops = [P.SplitOperator.from_problem(wl.build_operator(o)) for o in cfg["ops"]]
+    own = srv is None
+    if own:
+        ops = [P.SplitOperator.from_problem(wl.build_operator(o)) for o in cfg["ops"]]
+        srv = P.Server(hbm_budget=96 << 30, max_inflight=64, nstreams=4)
     qs = cfg["queries"]
     Vs = [wl.probes(cfg["ops"][q["op"]][1], q["L"], q["vseed"]) for q in qs]
-    srv = P.Server(hbm_budget=96 << 30, max_inflight=64, nstreams=4)
     tickets = []
     t0 = time.perf_counter()
     for q, V in zip(qs, Vs):
@@ -276,9 +280,10 @@ def _serve_run(P, prec, rate=200.0, duration=2.0, warmup=0.5):
         tickets.append(srv.submit(ops[q["op"]], q["contour"], V, q["N"], q["L"], q["K"], prec=prec,
                                   max_eigs=q["K"] * q["L"]))
     res = [srv.wait(t) for t in tickets]
-    srv.close()
-    for op in ops:
-        op.close()
+    if own:
+        srv.close()
+        for op in ops:
+            op.close()
     meas = [(q, r) for q, r in zip(qs, res) if not q["warm"]]
     lat = np.array([r["t_done"] - r["t_submit"] for _, r in meas])
     ok = [r for _, r in meas if r["status"] == 0]
@@ -301,22 +306,34 @@ def _serve_full(P, rate, duration, warmup, rates=()):
     measured) at each offered rate.  The sustainable rate is the highest
     offered rate of the sweep that is served in full (served >= 97% of
     offered) with p99 under 2 s."""
+    import workloads as wl
     out = {}
+    # one server (and one operator pool) per precision for the sweep and the
+    # long run: the HIP runtime bundled with torch keeps the device block of a
+    # destroyed server's arena, so a process cannot create many 96 GB servers
+    # one after another (the system runtime returns it); resident factors
+    # therefore carry over from run to run, as in a long-running server
+    ops = [P.SplitOperator.from_problem(wl.build_operator(o))
+           for o in wl.config4_stream(rate=rate, duration=0.1, warmup=0.0)["ops"]]
     for prec in ("mixed", "fp64"):
+        srv = P.Server(hbm_budget=96 << 30, max_inflight=64, nstreams=4) if prec == "mixed" else srv
         sweep = []
         for r in rates:
-            x = _serve_run(P, prec, rate=r, duration=15.0, warmup=3.0)
+            x = _serve_run(P, prec, rate=r, duration=15.0, warmup=3.0, srv=srv, ops=ops)
             sweep.append({k: x[k] for k in ("rate_qps", "queries", "queries_per_s", "p50_ms", "p99_ms",
                                             "reused", "status_counts")})
             print(f"[bench] serving {prec} sweep {r} q/s: {x['queries_per_s']:.1f} q/s served, "
                   f"p99 {x['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
         ok = [x["rate_qps"] for x in sweep if x["queries_per_s"] >= 0.97 * x["rate_qps"] and x["p99_ms"] < 2000.0]
-        res = _serve_run(P, prec, rate=rate, duration=duration, warmup=warmup)
+        res = _serve_run(P, prec, rate=rate, duration=duration, warmup=warmup, srv=srv, ops=ops)
         if rates:
             res["sweep"] = sweep
             res["sustainable_qps"] = max(ok) if ok else None
         out[prec] = res
         print(f"[bench] serving {prec} {rate} q/s done", file=sys.stderr, flush=True)
+    srv.close()
+    for op in ops:
+        op.close()
     return out
 
 

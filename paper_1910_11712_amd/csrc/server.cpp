@@ -138,6 +138,7 @@ class Server {
   void evict_lru(size_t need, std::vector<std::unique_ptr<Resident>>& out);
   void keep_resident(Slot& s, const std::vector<nep_status>& status);
   void release_slot_plan(Slot& s, bool drop_resident);
+  bool evict_one();  // destroys the least recently used idle resident plan (mu_ not held)
 
   Arena arena_;
   int device_ = 0;
@@ -517,6 +518,21 @@ bool Server::dispatch(Slot& s) {
   return true;
 }
 
+bool Server::evict_one() {
+  std::unique_ptr<Resident> gone;
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    int best = -1;
+    for (int i = 0; i < (int)resident_.size(); ++i)
+      if (!resident_[i]->out && (best < 0 || resident_[i]->last_use < resident_[best]->last_use)) best = i;
+    if (best < 0) return false;
+    resident_bytes_ -= resident_[best]->bytes;
+    gone = std::move(resident_[best]);
+    resident_.erase(resident_.begin() + best);
+  }
+  return true;  // its blocks go back to the arena here
+}
+
 // The slot's plan after its batch: a resident plan goes back to the cache
 // (or, with drop, out of it: its state is unknown after a failed pass), a
 // new one is destroyed.
@@ -590,6 +606,13 @@ void Server::complete(Slot& s) {
       // queries of the same operator concurrently
       st = extract(q.h->impl, &q.g, &o, s.buf[k]->S.p, &q.e, &m, q.lambda, s.buf[k]->X.p, q.eta, q.inside, nullptr,
                    s.xw.get());
+      // the extraction workspace grows from the arena: without room, idle
+      // resident plans give theirs up, least recently used first
+      while (st == NEP_ERR_OOM && evict_one()) {
+        (void)hipGetLastError();
+        st = extract(q.h->impl, &q.g, &o, s.buf[k]->S.p, &q.e, &m, q.lambda, s.buf[k]->X.p, q.eta, q.inside,
+                     nullptr, s.xw.get());
+      }
       if (st == NEP_OK && q.X != nullptr && m > 0) {
         if (hipMemcpyAsync(q.X, s.buf[k]->X.p, sizeof(c128) * (size_t)q.n * m, hipMemcpyDeviceToHost, s.st) !=
                 hipSuccess ||
