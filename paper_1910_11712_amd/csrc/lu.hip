@@ -1456,11 +1456,11 @@ static hipError_t launch_panel(int rpt, int nact, const MatDesc* md, int k0, int
   return hipGetLastError();
 }
 
-// Panel width: 128 in complex FP32 when every matrix has at least
-// kLuWideMinN rows (the trailing update then runs with k = 128, half the C
-// traffic per product), else 64.  A matrix's factors depend on the width, so
-// a matrix factors identically in every plan of the same width.
-int lu_jb(int prec, int nmin) { return prec != NEP_PREC_FP64 && nmin >= kLuWideMinN ? 128 : 64; }
+// Panel width: 128 when every matrix has at least kLuWideMinN rows (the
+// trailing update then runs with k = 128, half the C traffic per product),
+// else 64.  A matrix's factors depend on the width, so a matrix factors
+// identically in every plan of the same width.
+int lu_jb(int /*prec*/, int nmin) { return nmin >= kLuWideMinN ? 128 : 64; }
 
 void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
   prec = prec_;
@@ -1493,7 +1493,9 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
     const bool fused0 = f32 && jb == kPart0Cols;
     const int TM = f32 ? kG32TM : kG64TM;
     for (int part = 0; part < 2; ++part) {
-      const int TN = part == 0 ? p0cols : (f32 ? kG32TN : kG64TN);
+      // part 0 covers the next panel's columns: one 128-column tile column
+      // (complex FP32), or p0cols / 64 of the complex-FP64 update's tiles
+      const int TN = part == 0 ? (f32 ? p0cols : kG64TN) : (f32 ? kG32TN : kG64TN);
       for (int kind = 0; kind < 2; ++kind) {  // 0: U12 product, 1: trailing update
         int& off = kind == 0 ? s.off_trsm[part] : s.off_gemm[part];
         int& tot = kind == 0 ? s.tot_trsm[part] : s.tot_gemm[part];
@@ -1578,7 +1580,8 @@ template <typename P>
 static hipError_t lu_update_part(const LuPlan& plan, const LuPlan::Step& s, int part, const MatDesc* d_md,
                                  const int* d_prefix, cx<P>* T, const int* rows, const int* rows_ac, const int* skip,
                                  const cx<P>* Linv, int* arrivals, hipStream_t st) {
-  const int coff = part == 0 ? 0 : plan.jb, ntn = part == 0 ? 1 : INT_MAX;
+  const int coff = part == 0 ? 0 : plan.jb;
+  const int ntn = part == 0 ? (sizeof(P) == 4 ? 1 : plan.jb / kG64TN) : INT_MAX;  // part 0: the next panel's columns
   if constexpr (sizeof(P) == 4) {
     if (part == 0 && plan.jb == kPart0Cols) {  // fused U12 product and update of the first columns
       if (s.tot_gemm[0] > 0) {
@@ -1665,10 +1668,8 @@ hipError_t lu_run(const LuPlan& plan, const MatDesc* d_md, const int* d_prefix, 
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int nsteps = (int)plan.steps.size();
   if (nsteps == 0) return hipSuccess;
-  // panels of 64 or 128 columns (64-column diagonal blocks; the part-0 tile
-  // column of the complex-FP64 update is 64 wide)
-  if (plan.jb % kSolveBlkLu != 0 || plan.jb > kLuMaxJB || (sizeof(P) == 8 && plan.jb != kSolveBlkLu))
-    return hipErrorInvalidValue;
+  // panels of 64 or 128 columns (64-column diagonal blocks)
+  if (plan.jb % kSolveBlkLu != 0 || plan.jb > kLuMaxJB) return hipErrorInvalidValue;
   const bool lookahead = aux != nullptr && rows_alt != nullptr;
   int* const R[2] = {rows, lookahead ? rows_alt : rows};
   auto map = [&](int k) { return R[(k + 1) & 1]; };  // map of step k (map -1: the initial one)

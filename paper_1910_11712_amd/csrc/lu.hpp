@@ -13,8 +13,7 @@ constexpr int kPart0Cols = 64;   // trailing columns updated first in each step 
 // small panels (at most 256 rows left) in a step before they take the
 // 256-thread groups, by default
 constexpr int kSmallPanelsMin = 512;
-// complex FP32 plans whose matrices all have at least this many rows take
-// 128-wide panels
+// plans whose matrices all have at least this many rows take 128-wide panels
 constexpr int kLuWideMinN = 2048;
 
 // Launch plan of a (possibly ragged) batch: matrices sorted by n, descending.
