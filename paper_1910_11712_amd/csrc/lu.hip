@@ -1478,12 +1478,14 @@ void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
     int nact = 0;
     while (nact < nmat && sorted[nact].n > k0) ++nact;
     s.nact = nact;
-    s.nwide = 0;
+    s.n8 = 0;
+    while (s.n8 < nact && sorted[s.n8].n - k0 > 4 * kPanelThreads) ++s.n8;
+    s.n4 = s.n8;
+    while (s.n4 < nact && sorted[s.n4].n - k0 > 2 * kPanelThreads) ++s.n4;
+    s.nwide = s.n4;
     while (s.nwide < nact && sorted[s.nwide].n - k0 > kPanelThreads) ++s.nwide;
     s.nsmall = s.nwide;
     while (s.nsmall < nact && sorted[s.nsmall].n - k0 > kPanelSmall) ++s.nsmall;
-    int rmax = sorted[0].n - k0;
-    s.rpt = rmax <= 512 ? 1 : rmax <= 1024 ? 2 : rmax <= 2048 ? 4 : 8;
     // tile prefixes of the block-row product (U12) and of the trailing
     // update, each in two parts: part 0 = the first jb trailing columns
     // (they hold the next panel), part 1 = the rest.  Complex FP32 with
@@ -1544,9 +1546,13 @@ static hipError_t lu_panel_step(const LuPlan& plan, const LuPlan::Step& s, const
                                 const int* rsrc, int* rdst, int* info, const int* skip, cx<P>* Linv, cx<P>* Dinv,
                                 const long long* dinv_off, hipStream_t st, hipStream_t side, hipEvent_t ev_side) {
   hipError_t e;
-  if (s.nwide > 0 && (e = launch_panel<P>(s.rpt, s.nwide, d_md, s.k0, plan.jb, T, rsrc, rdst, info, skip, Linv, Dinv,
-                                          dinv_off, st)) != hipSuccess)
-    return e;
+  // the multi-row classes: 8, 4 and 2 rows per thread
+  const int wb[4] = {0, s.n8, s.n4, s.nwide}, wr[3] = {8, 4, 2};
+  for (int c = 0; c < 3; ++c)
+    if (wb[c + 1] > wb[c] &&
+        (e = launch_panel<P>(wr[c], wb[c + 1] - wb[c], d_md + wb[c], s.k0, plan.jb, T, rsrc, rdst, info, skip,
+                             Linv + (long long)wb[c] * kLuMaxJB * kLuMaxJB, Dinv, dinv_off + wb[c], st)) != hipSuccess)
+      return e;
   // panels of at most kPanelSmall rows take the kPanelSmall-thread groups
   // when they are many (two groups share a CU; complex FP32 only, where two
   // fit); the two variants give the same bits (per-row arithmetic and the

@@ -19,11 +19,14 @@ constexpr int kLuWideMinN = 2048;
 // Launch plan of a (possibly ragged) batch: matrices sorted by n, descending.
 struct LuPlan {
   struct Step {
-    int k0, nact, rpt;
+    int k0, nact;
     // matrices [0, nwide) have more than one panel row per thread; the rest
-    // take the single-row panel, so the leaf width (and with it the rounding)
-    // of a matrix's panel depends on that matrix alone, not on its batch
-    int nwide;
+    // take the single-row panel.  Within [0, nwide) the matrices of more
+    // than 2048 and 1024 rows left end at n8 and n4: each range takes the
+    // rows per thread (and with it the leaf width and the rounding) the
+    // matrix would get alone, so a matrix's panel depends on that matrix
+    // only, not on its batch
+    int nwide, n8, n4;
     // matrices [nsmall, nact) have at most 256 rows left: with enough of them
     // (complex FP32), a 256-thread panel group each, two per CU
     int nsmall;

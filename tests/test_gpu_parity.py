@@ -374,6 +374,47 @@ def test_ragged_batch_large_sizes(nep, prec):
         _check_mixed_vs_fp64(nep.moments_to_numpy(Ss[1]), S64, So)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_ragged_batch_wide_panels(nep, prec):
+    """A ragged batch whose matrices all have 2048 rows or more takes
+    128-wide panels (and, in complex FP32, the blocked solve), including a
+    size that is not a multiple of 64 and a last panel narrower than 64:
+    every problem equals its single call bitwise, and the odd size matches the
+    oracle."""
+    sizes = [2600, 2048, 2111]
+    con, N, L, K = Contour.circle(-1.0 + 0.3j, 0.5), 8, 2, 1
+    probs, Vs = [], []
+    for i, n in enumerate(sizes):
+        rng = np.random.default_rng(300 + i)
+        A0 = 2.0 * rng.standard_normal((n, n)) / np.sqrt(n)
+        A2 = rng.standard_normal((n, n)) / np.sqrt(n)
+        probs.append(Problem("delay", [A0, np.eye(n), A2],
+                             [wl.fn_rational([1.0]), wl.fn_rational([-1.0, 0.0]), wl.fn_exp(alpha=-1.0)]))
+        Vs.append(wl.probes(n, L, 400 + i))
+    ops, singles = [], []
+    for p, V in zip(probs, Vs):
+        op, _, Sg, st = _run_moments(nep, p, con, N, L, K, V, prec)
+        ops.append(op)
+        singles.append(Sg)
+        assert st["n_unconverged"] == 0, st
+    B = nep.binding
+    Vd = [nep.device_probes(V) for V in Vs]
+    Ss = [torch.zeros((2 * K, L, p.n), dtype=torch.complex128, device="cuda") for p in probs]
+    b = B.nep_batch_create([op.h for op in ops], [con] * len(ops), B.opts_struct(N, L, K, prec), Vd, Ss,
+                           use_graph=False)
+    stats = B.nep_batch_run(b, len(ops))
+    B.nep_batch_destroy(b)
+    for k in range(len(ops)):
+        Sg = nep.moments_to_numpy(Ss[k])
+        assert np.array_equal(Sg, singles[k]), (k, sizes[k], np.abs(Sg - singles[k]).max(), stats[k])
+    So = oracle.ciss_moments(probs[2], con, N, K, Vs[2])
+    if prec == "fp64":
+        _check_moments(nep.moments_to_numpy(Ss[2]), So)
+    else:
+        _, _, S64, _ = _run_moments(nep, probs[2], con, N, L, K, Vs[2], "fp64")
+        _check_mixed_vs_fp64(nep.moments_to_numpy(Ss[2]), S64, So)
+
+
 def test_mixed_fallback_refined_on_ill_conditioned_nodes(nep):
     """Loaded string n=1912 (sigma 1.413, A scale 1.557) with the serving
     contour around its third eigenvalue: FP32-factor refinement stalls at
