@@ -209,11 +209,12 @@ def _tune_summary(B):
     rep = B.nep_tune_report()
     c = rep["candidates"]
     out = {"cached": rep["cached"],
-           "candidates_ms": [[d["lg"], d["paired"], d["small_min"], d["early_fork"], round(d["ms"], 4)] for d in c]}
+           "candidates_ms": [[d["lg"], d["paired"], d["small_min"], d["early_fork"], d["jb"], round(d["ms"], 4)]
+                             for d in c]}
     if 0 <= rep["chosen"] < len(c):
         d = c[rep["chosen"]]
         out["chosen"] = {"lg": d["lg"], "paired": d["paired"], "small_min": d["small_min"],
-                         "early_fork": d["early_fork"]}
+                         "early_fork": d["early_fork"], "jb": d["jb"]}
     return out
 
 

@@ -498,8 +498,9 @@ nep_status nep_server_destroy(nep_server* s);
 
 /* Not an operation of the paper: batching every (problem, node) pair of the
  * moment stage into shared launches leaves a few launch-shape choices whose
- * best setting depends on the batch and the device, not on the arithmetic
- * (every setting computes the same moments).  One setting: */
+ * best setting depends on the batch and the device.  Every setting computes
+ * the moments to the same accuracy; all but the panel width also give the same
+ * bits (the panel width changes the rounding of the factors).  One setting: */
 typedef struct {
   int lg;        /* right-hand columns per work-group of the triangular solves (4, 8 or 16) */
   int paired;    /* large matrices as paired 256-thread solve groups: -1 when they make at
@@ -508,7 +509,9 @@ typedef struct {
                     least small_min of them share an LU step (0 always; INT_MAX never) */
   int early_fork; /* the rest of an LU step's update starts on a second stream as soon as the
                      panel is done (1) or after the next panel's columns are updated (0);
-                     -1: by precision (1 complex FP32, 0 complex FP64) */
+                     -1: built in (1 for 64-wide complex-FP32 panels, else 0) */
+  int jb;        /* LU panel width, 64 or 128 (built in: 128 when every matrix of the plan
+                    has at least 2048 rows) */
   float ms;      /* median device time of one full moment pass with this setting */
 } nep_tune_cand;
 

@@ -81,7 +81,7 @@ class nep_query_info(C.Structure):
 
 class nep_tune_cand(C.Structure):
     _fields_ = [("lg", C.c_int), ("paired", C.c_int), ("small_min", C.c_int), ("early_fork", C.c_int),
-                ("ms", C.c_float)]
+                ("jb", C.c_int), ("ms", C.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -1462,9 +1462,9 @@ static hipError_t launch_panel(int rpt, int nact, const MatDesc* md, int k0, int
 // identically in every plan of the same width.
 int lu_jb(int /*prec*/, int nmin) { return nmin >= kLuWideMinN ? 128 : 64; }
 
-void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_) {
+void LuPlan::build(const std::vector<MatDesc>& sorted, int prec_, int jb_force) {
   prec = prec_;
-  jb = lu_jb(prec, sorted.empty() ? 0 : sorted.back().n);
+  jb = jb_force > 0 ? jb_force : lu_jb(prec, sorted.empty() ? 0 : sorted.back().n);
   const int p0cols = jb;  // part 0: the columns of the next panel
   nmat = (int)sorted.size();
   nvec.clear();

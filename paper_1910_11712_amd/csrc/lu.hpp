@@ -47,7 +47,8 @@ struct LuPlan {
   std::vector<Step> steps;
   std::vector<int> prefix;  // uploaded once; offsets above index into it
   std::vector<int> nvec;    // sizes of the sorted matrices
-  void build(const std::vector<MatDesc>& sorted, int prec);
+  // jb_force: the panel width (64 or 128), 0 for the built-in choice
+  void build(const std::vector<MatDesc>& sorted, int prec, int jb_force = 0);
 };
 
 // Event timing of the trailing-update GEMM launches (kind 0: c64, 1: c128).

@@ -167,10 +167,12 @@ class MomentsPlan {
   // Launch-shape knobs of the plan (see LuPlan::small_min and early_fork,
   // SolvePlan::lg and paired); every setting computes the same moments.
   struct Knobs {
-    int lg, paired, small_min, early_fork;
+    int lg, paired, small_min, early_fork, jb;
   };
-  Knobs knobs() const { return Knobs{sp_.lg, sp_.paired, lu_.small_min, lu_.early_fork}; }
-  void apply(const Knobs& k);
+  Knobs knobs() const { return Knobs{sp_.lg, sp_.paired, lu_.small_min, lu_.early_fork, lu_.jb}; }
+  // applies k; a different panel width rebuilds the LU schedule and its
+  // device prefix table
+  nep_status apply(const Knobs& k);
   // The candidate settings that differ for this plan's shapes: [0] is the
   // built-in choice; LU candidates first, then the solve's.
   void candidates(std::vector<Knobs>& lu, std::vector<Knobs>& solve) const;

@@ -11,8 +11,11 @@
 //   * the LU's look-ahead fork point: the rest of a step's update starts as
 //     soon as the panel is done (best when the panels bound the time) or
 //     after the update of the next panel's columns (which then does not wait
-//     for CU slots behind the larger update).
-// Every setting computes the same moments (the panel variants the same bits).
+//     for CU slots behind the larger update);
+//   * the LU's panel width, 64 or 128: wider panels give the trailing update
+//     twice the products per C byte but lengthen the panel chain.
+// Every setting computes the moments to the same accuracy; all but the panel
+// width give the same bits (the panel width changes the factors' rounding).
 // The tuner times each candidate with full moment passes on the plan's own
 // buffers (HIP events on the caller's stream, median of a few passes), keeps
 // the fastest if it beats the built-in setting by more than 2% (the built-in
@@ -61,11 +64,20 @@ int eff_paired(const SolvePlan& sp, int prec, const MomentsPlan::Knobs& k, int L
 
 }  // namespace
 
-void MomentsPlan::apply(const Knobs& k) {
+nep_status MomentsPlan::apply(const Knobs& k) {
   solve_set_lg(sp_, k.lg, opt.L);
   sp_.paired = k.paired;
+  if (k.jb != lu_.jb) {  // another panel width: a new LU schedule and prefix table
+    NEP_CHECK(k.jb == 64 || k.jb == 128, NEP_ERR_ARG, "panel width %d", k.jb);
+    lu_.build(sorted_, opt.prec, k.jb);
+    const size_t need = sizeof(int) * std::max<size_t>(1, lu_.prefix.size());
+    if (dlu_prefix_.bytes < need) NEP_TRY(dlu_prefix_.alloc(need));
+    if (!lu_.prefix.empty())
+      NEP_HIP(hipMemcpy(dlu_prefix_.p, lu_.prefix.data(), sizeof(int) * lu_.prefix.size(), hipMemcpyHostToDevice));
+  }
   lu_.small_min = k.small_min;
   lu_.early_fork = k.early_fork;
+  return NEP_OK;
 }
 
 void MomentsPlan::candidates(std::vector<Knobs>& lu, std::vector<Knobs>& solve) const {
@@ -90,19 +102,26 @@ void MomentsPlan::candidates(std::vector<Knobs>& lu, std::vector<Knobs>& solve) 
       smins.push_back(smin);
     }
   }
-  // the other fork point matters where a step forks at all (more than one
-  // step); the built-in one is the precision's
-  const int fork_base = f32 ? 1 : 0;
-  std::vector<int> forks{base.early_fork};
-  if (lu_.steps.size() > 1) forks.push_back(1 - fork_base);
-  for (int fk : forks)
-    for (int smin : smins) {
-      if (fk == base.early_fork && smin == base.small_min) continue;  // [0]
-      Knobs k = base;
-      k.small_min = smin;
-      k.early_fork = fk;
-      lu.push_back(k);
-    }
+  // panel widths: the built-in one, and the other where it differs (a plan
+  // whose largest matrix has more than 64 rows); the other fork point
+  // matters where a step forks at all (more than one step), the built-in one
+  // being early for 64-wide complex-FP32 panels and late otherwise
+  std::vector<int> jbs{base.jb};
+  if (!sorted_.empty() && sorted_[0].n > 64) jbs.push_back(base.jb == 64 ? 128 : 64);
+  for (int jb : jbs) {
+    const int fork_base = f32 && jb == 64 ? 1 : 0;
+    std::vector<int> forks{base.early_fork};
+    if ((sorted_.empty() ? 0 : sorted_[0].n) > jb) forks.push_back(1 - fork_base);
+    for (int fk : forks)
+      for (int smin : smins) {
+        if (jb == base.jb && fk == base.early_fork && smin == base.small_min) continue;  // [0]
+        Knobs k = base;
+        k.small_min = smin;
+        k.early_fork = fk;
+        k.jb = jb;
+        lu.push_back(k);
+      }
+  }
   std::vector<std::pair<int, int>> seen{{base.lg, eff_paired(sp_, opt.prec, base, opt.L)}};
   for (int lg : {4, 8, 16}) {
     if (!solve_lg_fits(sp_, lg, opt.L, opt.prec)) continue;
@@ -164,7 +183,7 @@ nep_status tune_plan(MomentsPlan& plan, hipStream_t st) {
     std::lock_guard<std::mutex> g(T.mu);
     auto it = T.cache.find(sig);
     if (it != T.cache.end()) {
-      plan.apply(it->second);
+      NEP_TRY(plan.apply(it->second));
       T.last.clear();
       T.last_chosen = -1;
       T.last_cached = 1;
@@ -186,10 +205,10 @@ nep_status tune_plan(MomentsPlan& plan, hipStream_t st) {
   if (lu.size() + sv.size() > 2) {
     float best_ms = FLT_MAX;
     auto measure = [&](const MomentsPlan::Knobs& k) -> nep_status {
-      plan.apply(k);
+      NEP_TRY(plan.apply(k));
       float ms = 0.f;
       NEP_TRY(plan.time_pass(st, reps, ms));
-      rec.push_back(nep_tune_cand{k.lg, k.paired, k.small_min, k.early_fork, ms});
+      rec.push_back(nep_tune_cand{k.lg, k.paired, k.small_min, k.early_fork, k.jb, ms});
       if (ms < best_ms) {
         best_ms = ms;
         best = k;
@@ -216,13 +235,14 @@ nep_status tune_plan(MomentsPlan& plan, hipStream_t st) {
       MomentsPlan::Knobs k = sv[i];
       k.small_min = best.small_min;
       k.early_fork = best.early_fork;
+      k.jb = best.jb;
       NEP_TRY(measure(k));
     }
     settle();
   } else {
-    rec.push_back(nep_tune_cand{best.lg, best.paired, best.small_min, best.early_fork, 0.f});  // nothing to choose
+    rec.push_back(nep_tune_cand{best.lg, best.paired, best.small_min, best.early_fork, best.jb, 0.f});  // nothing to choose
   }
-  plan.apply(best);
+  NEP_TRY(plan.apply(best));
   std::lock_guard<std::mutex> g(T.mu);
   T.cache[sig] = best;
   T.last = rec;

@@ -93,7 +93,7 @@ int main(void) {
   printf("nep_query_info %zu\n", sizeof(nep_query_info));
   P(nep_query_info, n_inside) P(nep_query_info, reused) P(nep_query_info, t_submit) P(nep_query_info, t_done)
   printf("nep_tune_cand %zu\n", sizeof(nep_tune_cand));
-  P(nep_tune_cand, paired) P(nep_tune_cand, small_min) P(nep_tune_cand, early_fork) P(nep_tune_cand, ms)
+  P(nep_tune_cand, paired) P(nep_tune_cand, small_min) P(nep_tune_cand, early_fork) P(nep_tune_cand, jb) P(nep_tune_cand, ms)
   return 0;
 }
 """

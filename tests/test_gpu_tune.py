@@ -111,3 +111,20 @@ def test_tuned_batch_graph_matches_oracle(nep, tuning):
     for k in sorted({int(np.argmin(ns)), int(np.argmax(ns))}):
         So = oracle.ciss_moments(probs[k], con, N, K, cfg["V"][k])
         _check_moments(nep.moments_to_numpy(Ss[k]), So)
+
+
+def test_tuned_fp64_plan_times_its_fork_points(nep, tuning):
+    """A plain-FP64 plan tuned with tuning on: the late (built-in) and early
+    look-ahead fork points are both timed, so the FP64 early-fork schedule
+    runs, and the kept setting computes the oracle's moments."""
+    B = tuning
+    cfg = wl.config0()
+    p, con, N, L, K = cfg["problem"], cfg["contour"], cfg["N"], cfg["L"], cfg["K"]
+    So = oracle.ciss_moments(p, con, N, K, cfg["V"])
+    op = nep.SplitOperator.from_problem(p)
+    S, st = op.moments(con, nep.device_probes(cfg["V"]), N, L, K, prec="fp64")
+    rep = B.nep_tune_report()
+    print(rep, st)
+    forks = {c["early_fork"] for c in rep["candidates"]}
+    assert 1 in forks and (0 in forks or -1 in forks), rep
+    _check_moments(nep.moments_to_numpy(S), So)
