@@ -1,4 +1,5 @@
-"""FP64 CPU oracle for the contour-integral moment path -- TEST INFRASTRUCTURE.
+"""FP64 CPU oracle for the contour-integral moment path and for NLEIGS
+(submodule `oracle.nleigs`) -- TEST INFRASTRUCTURE.
 
 Only the test suite, the smoke check and the CPU-baseline leg of the
 benchmark may import this package.  The product path (the HIP library and its
