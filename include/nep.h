@@ -391,6 +391,79 @@ nep_status nep_fn_eval_derivative(nep_split h, int m, const double* z, double* o
 nep_status nep_fn_eval(nep_split h, int m, const double* z, double* out);
 
 /* ------------------------------------------------------------------------ */
+/* NLEIGS: rational interpolation and Krylov (Section 4.5)                   */
+/* ------------------------------------------------------------------------ */
+
+/* The interpolant R_d(z) = sum_j b_j(z) D_j of eq. (nleigsq) in the rational
+ * Newton basis of eq. (nleigsbj) (b_0 = 1, each b_j scaled to maximum modulus
+ * 1 on the discretized boundary), with D_j = sum_i d_i^j A_i (eq.
+ * (nleigsdsplit)).  Nodes and poles are Leja--Bagby points (eq.
+ * (nleigsleja)): sigma_0 is the boundary point at angle 0 of the region g
+ * (the target set), the boundary is discretized at npts points
+ * c + rho (cos t + i v sin t), t = 2 pi k / npts, and the poles are chosen
+ * among the nxi given points of the singularity set (each at most once; the
+ * rest infinite).  Greedy ties go to the lowest index within a relative 1e-10.
+ * The scalar divided differences d_i^j follow the interpolation conditions of
+ * eq. (nleigsdd); the degree d is the first j >= 2 with
+ * max_i |d_i^j| < tol max_i |d_i^0| (at most dmax), and the last pole is then
+ * set to infinity (the form of eq. (nleigsmatlin)). */
+typedef struct {
+  double sigma[2];  /* shift of the shift-and-invert Arnoldi (eq. (nleigssinvert)) */
+  int k;            /* Arnoldi steps, 1..256                                  */
+  int dmax;         /* largest degree, 2..100 (0: 50)                         */
+  int npts;         /* boundary points, 8..16384 (0: 1024)                    */
+  double tol;       /* degree tolerance (0: 1e-12)                            */
+  int nxi;          /* points of the singularity set (0: every pole infinite) */
+  const double* xi; /* host, nxi complex                                       */
+  double eta_tol;   /* pairs returned have backward error <= eta_tol (0: 1e-10) */
+  int max_eigs;     /* capacity of lambda, X and eta (>= 1)                   */
+} nep_nleigs_opts;
+
+typedef struct {
+  int d;            /* interpolation degree                                   */
+  int met;          /* 1 if the degree test was met (else d = dmax)           */
+  int k_done;       /* Arnoldi steps taken (fewer than k on an invariant subspace) */
+  int basis;        /* columns of the TOAR basis U (k_done + d unless a new
+                       vector was linearly dependent)                          */
+  double h_last;    /* |h_{k+1,k}|                                            */
+  float ms_lu;      /* device time of the assembly and LU of R_d(sigma)       */
+  float ms_krylov;  /* wall time of the Arnoldi steps                         */
+  float ms_total;   /* wall time of the call                                  */
+} nep_nleigs_info;
+
+/* The interpolant alone: d, met, and host arrays of dmax+1 entries (entries
+ * beyond d are zero): sigma (complex), xi (complex; an infinite pole has an
+ * infinite real part, xi[0] is unused), beta (real), and dd (ell x (dmax+1)
+ * complex, d_i^j at dd[i*(dmax+1) + j]).  Evaluates the f_i at the nodes on
+ * the device (synchronous).  NEP_ERR_NOT_HOLOMORPHIC if a node lies on a
+ * pole or cut of some f_i. */
+nep_status nep_nleigs_interp(nep_split h, const nep_contour* g, const nep_nleigs_opts* o, int* d, int* met,
+                             double* sigma, double* xi, double* beta, double* dd);
+
+/* Eigenpairs of T inside the region g near the shift, by NLEIGS: the
+ * interpolant above, one complex FP64 factorization of R_d(sigma) on the
+ * device, and k steps of Arnoldi on (A - sigma B)^{-1} B of the
+ * linearization pencil (A, B) of eq. (nleigsmatlin) in the TOAR
+ * representation (Algorithm "Arnoldi for NLEIGS with TOAR representation",
+ * eqs. (nleigs-toar1)--(nleigs-toar4); classical Gram--Schmidt with one
+ * reorthogonalization).  No restart.  Ritz values lambda = sigma + 1/theta of
+ * the k x k Hessenberg matrix inside g whose Ritz vectors x (the first block,
+ * 2-norm 1, largest entry real positive) have backward error (eq.
+ * (sressplit), infinity norms) <= eta_tol are returned, sorted by real then
+ * imaginary part.
+ *   W0: device, complex n x dmax column-major: the first d columns are the d
+ *       parts w^0..w^{d-1} of the starting vector (they must be linearly
+ *       independent).
+ *   m: number returned (<= max_eigs); lambda: host, 2*max_eigs doubles;
+ *   X: device, complex n x max_eigs column-major; eta: host, max_eigs.
+ *   H: optional host (k+1) x k complex column-major: the Hessenberg matrix
+ *      (columns beyond k_done are zero).  info: optional.
+ * Synchronous, on the handle's stream.  Allocates device memory (the factors
+ * of one matrix, the basis: n x (d + k + 1) complex). */
+nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* o, const void* W0, int* m,
+                      double* lambda, void* X, double* eta, double* H, nep_nleigs_info* info);
+
+/* ------------------------------------------------------------------------ */
 /* Batched moments: many problems of uneven n in one plan                    */
 /* ------------------------------------------------------------------------ */
 

@@ -82,6 +82,15 @@ class SplitOperator:
         """X: device tensor (m, n) holding the eigenvectors; polished in place."""
         return binding.nep_rii_polish(self.h, lam, X, tol, max_it)
 
+    def nleigs_interp(self, contour, dmax=50, npts=1024, tol=0.0, xi=()):
+        return binding.nep_nleigs_interp(self.h, contour, dmax, npts, tol, xi)
+
+    def nleigs(self, contour, W0, X, sigma, k, dmax=50, npts=1024, tol=0.0, xi=(), eta_tol=0.0, max_eigs=64,
+               want_H=False):
+        """NLEIGS eigenpairs near sigma inside contour (see nep_nleigs)."""
+        return binding.nep_nleigs(self.h, contour, W0, X, sigma, k, dmax, npts, tol, xi, eta_tol, max_eigs,
+                                  want_H)
+
     def fn_eval(self, z):
         return nep_fn_eval(self.h, self.ell, z)
 

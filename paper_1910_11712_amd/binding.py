@@ -87,6 +87,21 @@ class nep_tune_cand(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class nep_nleigs_opts(C.Structure):
+    _fields_ = [("sigma", C.c_double * 2), ("k", C.c_int), ("dmax", C.c_int), ("npts", C.c_int),
+                ("tol", C.c_double), ("nxi", C.c_int), ("xi", C.POINTER(C.c_double)),
+                ("eta_tol", C.c_double), ("max_eigs", C.c_int)]
+
+
+class nep_nleigs_info(C.Structure):
+    _fields_ = [("d", C.c_int), ("met", C.c_int), ("k_done", C.c_int), ("basis", C.c_int),
+                ("h_last", C.c_double), ("ms_lu", C.c_float), ("ms_krylov", C.c_float),
+                ("ms_total", C.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -159,6 +174,11 @@ def lib():
         L.nep_server_clock.argtypes = [vp]
         L.nep_server_clock.restype = C.c_double
         L.nep_server_destroy.argtypes = [C.POINTER(vp)]
+        dp = C.POINTER(C.c_double)
+        L.nep_nleigs_interp.argtypes = [vp, C.POINTER(nep_contour), C.POINTER(nep_nleigs_opts), C.POINTER(ip),
+                                        C.POINTER(ip), dp, dp, dp, dp]
+        L.nep_nleigs.argtypes = [vp, C.POINTER(nep_contour), C.POINTER(nep_nleigs_opts), vp, C.POINTER(ip), dp,
+                                 vp, dp, dp, C.POINTER(nep_nleigs_info)]
         _lib = L
     return _lib
 
@@ -593,3 +613,60 @@ def nep_batch_wait(b, nprob=None):
 
 def nep_batch_destroy(b):
     check(lib().nep_batch_destroy(C.byref(b)))
+
+
+def _nleigs_opts(sigma, k, dmax, npts, tol, xi, eta_tol, max_eigs):
+    xa = _cplx_host(xi) if xi is not None and len(xi) else None
+    o = nep_nleigs_opts()
+    o.sigma[0], o.sigma[1] = complex(sigma).real, complex(sigma).imag
+    o.k, o.dmax, o.npts, o.tol = int(k), int(dmax), int(npts), float(tol)
+    o.nxi = 0 if xa is None else len(xa) // 2
+    o.xi = None if xa is None else xa.ctypes.data_as(C.POINTER(C.c_double))
+    o.eta_tol, o.max_eigs = float(eta_tol), int(max_eigs)
+    return o, xa
+
+
+def nep_nleigs_interp(h, contour, dmax=50, npts=1024, tol=0.0, xi=()):
+    """The NLEIGS interpolant: dict with d, met, sigma, xi, beta (d+1 each)
+    and dd (ell x (d+1))."""
+    o, xa = _nleigs_opts(0.0, 1, dmax, npts, tol, xi, 0.0, 1)
+    D = dmax if dmax > 0 else 50
+    n_, ell = C.c_int(), C.c_int()
+    check(lib().nep_split_info(h, C.byref(n_), C.byref(ell)))
+    sig = np.zeros(2 * (D + 1))
+    xo = np.zeros(2 * (D + 1))
+    beta = np.zeros(D + 1)
+    dd = np.zeros(2 * ell.value * (D + 1))
+    d, met = C.c_int(), C.c_int()
+    dp = C.POINTER(C.c_double)
+    check(lib().nep_nleigs_interp(h, C.byref(contour_struct(contour)), C.byref(o), C.byref(d), C.byref(met),
+                                  sig.ctypes.data_as(dp), xo.ctypes.data_as(dp), beta.ctypes.data_as(dp),
+                                  dd.ctypes.data_as(dp)))
+    del xa
+    n = d.value + 1
+    ddc = (dd[0::2] + 1j * dd[1::2]).reshape(ell.value, D + 1)[:, :n]
+    return {"d": d.value, "met": met.value, "sigma": (sig[0::2] + 1j * sig[1::2])[:n],
+            "xi": (xo[0::2] + 1j * xo[1::2])[:n], "beta": beta[:n], "dd": ddc}
+
+
+def nep_nleigs(h, contour, W0, X, sigma, k, dmax=50, npts=1024, tol=0.0, xi=(), eta_tol=0.0, max_eigs=64,
+               want_H=False):
+    """NLEIGS eigenpairs.  W0: device tensor (dmax, n) complex128 (row q =
+    part w^q of the starting vector); X: device tensor (max_eigs, n) for the
+    eigenvectors.  Returns (lam, eta, info dict[, H])."""
+    o, xa = _nleigs_opts(sigma, k, dmax, npts, tol, xi, eta_tol, max_eigs)
+    m = C.c_int()
+    lam = np.zeros(2 * max_eigs)
+    eta = np.zeros(max_eigs)
+    H = np.zeros(2 * (k + 1) * k) if want_H else None
+    info = nep_nleigs_info()
+    dp = C.POINTER(C.c_double)
+    check(lib().nep_nleigs(h, C.byref(contour_struct(contour)), C.byref(o), C.c_void_p(W0.data_ptr()),
+                           C.byref(m), lam.ctypes.data_as(dp), C.c_void_p(X.data_ptr()),
+                           eta.ctypes.data_as(dp), None if H is None else H.ctypes.data_as(dp), C.byref(info)))
+    del xa
+    q = m.value
+    out = ((lam[0::2] + 1j * lam[1::2])[:q], eta[:q], info.as_dict())
+    if want_H:
+        out = out + ((H[0::2] + 1j * H[1::2]).reshape(k, k + 1).T,)
+    return out

@@ -55,6 +55,8 @@ struct ProbDesc {
   long long s_stride;     // elements between consecutive moment blocks of S (>= n*L)
   int active;             // 0: the problem sits out this pass on resident factors (its
                           // nodes count as converged, its V and S are not touched)
+  const c128* fpts;       // with zpts: given coefficients in place of f_i(z_j), at
+                          // fpts[j*ell + i] (device), or nullptr
 };
 
 // Per-node arrays (global node index g).

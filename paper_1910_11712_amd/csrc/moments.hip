@@ -43,7 +43,7 @@ __global__ void k_coef(const ProbDesc* __restrict__ pd, NodeArrays na, int nnode
   int bad = 0;
   double fn = 0.0;
   for (int i = 0; i < P.ell; ++i) {
-    const c128 f = fn_eval(P.fn_nodes, P.fn_coef, P.fn_root[i], z, bad);
+    const c128 f = P.fpts != nullptr ? P.fpts[j * P.ell + i] : fn_eval(P.fn_nodes, P.fn_coef, P.fn_root[i], z, bad);
     na.fz[g * kMaxTerms + i] = f;
     fn += sqrt(norm2(f)) * P.normA[i];
   }

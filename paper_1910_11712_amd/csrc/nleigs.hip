@@ -1,0 +1,716 @@
+// NLEIGS (Section 4.5).  The split operator is replaced by a rational
+// interpolant R_d in the rational Newton basis (eqs. (nleigsbj), (nleigsq))
+// whose nodes and poles are Leja--Bagby points (eq. (nleigsleja)); the
+// eigenvalues near a shift sigma are those of the linearization pencil of
+// eq. (nleigsmatlin), found by Arnoldi on its shift-and-invert operator
+// (eq. (nleigssinvert)) with the Krylov basis in the TOAR representation
+// (Algorithm "Arnoldi for NLEIGS with TOAR representation").
+//
+// Work split.  The host takes the scalar set-up (boundary discretization,
+// greedy Leja--Bagby selection, basis scaling, divided differences, degree)
+// and the coefficient recurrences of the TOAR representation, which act on
+// vectors of length k + d.  The device takes everything of size n: the
+// function values at the nodes, the assembly and LU of
+// R_d(sigma) = sum_i rho_i A_i with the moment plan's kernels (explicit
+// coefficients rho_i in place of f_i(z)), and per Arnoldi step the
+// reconstruction U q_i of the vector that multiplies each A_i, the split-form
+// product -sum_i A_i (U q_i), the solve with the resident factors of
+// R_d(sigma), and classical Gram--Schmidt with one reorthogonalization of the
+// new vector against U.  A step reads every A_i once and the factors once, so
+// it is bound by HBM bandwidth.
+//
+// The divided-difference matrices D_j are never formed (Section 4.5): with
+// q_i = sum_{j<d-1} d_i^j g~^{j+1} + (d_i^d / beta_d) g^{d-1}, the right-hand
+// side -sum_j D_j y^{j+1} - D_d v^{d-1} / beta_d of eq. (nleigs-toar2) is
+// -sum_i A_i U q_i.
+//
+// Readings where the text leaves a choice: b_0 = 1 (so beta_0 = 1); sigma_0
+// is the boundary point at angle 0; ties of the greedy selections go to the
+// lowest index among candidates within a relative 1e-10 of the extreme;
+// |s_j| is infinite at a point already taken as a pole, so each point of the
+// singularity set serves at most once and the remaining poles are infinite;
+// the degree is the first j >= 2 with max_i |d_i^j| / max_i |d_i^0| < tol; the
+// last pole is then set to infinity and beta_d, d_i^d recomputed.  The scalar
+// divided differences follow the interpolation recurrence of eq. (nleigsdd)
+// applied to each f_i (the quantity eq. (nleigsfdd) evaluates through a
+// matrix function).  No Krylov--Schur restart: one Arnoldi run of k steps.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <numeric>
+#include <vector>
+
+#include "dense.hpp"
+#include "handle.hpp"
+
+namespace nep {
+
+namespace {
+
+constexpr int kNlMaxK = 256;       // Arnoldi steps
+constexpr int kNlMaxDeg = 100;     // interpolation degree
+constexpr int kNlMaxPts = 16384;   // boundary discretization
+constexpr double kNlTie = 1e-10;   // relative tie window of the greedy selections
+constexpr double kNlDep = 1e-12;   // a new vector this small after Gram--Schmidt
+                                   // (relative) does not extend U
+
+// ---------------------------------------------------------------------------
+// Device kernels
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ c128 wave_sum(c128 v) {
+  for (int o = 32; o >= 1; o >>= 1) {
+    v.re += __shfl_xor(v.re, o, 64);
+    v.im += __shfl_xor(v.im, o, 64);
+  }
+  return v;
+}
+
+// Sum over a 256-thread group; every thread gets the total.
+__device__ __forceinline__ c128 group_sum(c128 v, c128* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  c128 s = red[0];
+  for (int i = 1; i < 4; ++i) s = s + red[i];
+  __syncthreads();
+  return s;
+}
+
+// Z[:, c] = U[:, 0:m] Q[:, c] (sub = 0) or Z[:, c] -= U[:, 0:m] Q[:, c]
+// (sub = 1), c < ncol.  U column-major with leading dimension n, Q
+// column-major with leading dimension m.  One thread per row.
+__global__ __launch_bounds__(256) void k_nl_comb(int n, int m, const c128* __restrict__ U,
+                                                 const c128* __restrict__ Q, int ncol, c128* __restrict__ Z,
+                                                 int sub) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int c = 0; c < ncol; ++c) {
+    c128 acc = {0.0, 0.0};
+    for (int t = 0; t < m; ++t) acc = acc + U[(long long)t * n + r] * Q[(long long)c * m + t];
+    c128* z = Z + (long long)c * n + r;
+    *z = sub ? *z - acc : acc;
+  }
+}
+
+struct NlTerms {
+  const void* A[kMaxTerms];     // row-major n x n, double or complex
+  const c128* diag[kMaxTerms];  // diagonal of a diagonal A_i
+  int cplx[kMaxTerms];
+  int isdiag[kMaxTerms];
+};
+
+// out[r] = -sum_i (A_i Z[:, i])[r].  One wavefront per row (lanes stride the
+// row, so each load of a wavefront is 64 consecutive entries), four rows per
+// group; a diagonal A_i contributes d_r z_r.
+__global__ __launch_bounds__(256) void k_nl_splitmv(int n, int ell, NlTerms T, const c128* __restrict__ Z,
+                                                    c128* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= n) return;
+  c128 acc = {0.0, 0.0};
+  for (int i = 0; i < ell; ++i) {
+    const c128* z = Z + (long long)i * n;
+    if (T.isdiag[i]) {
+      if (lane == 0) acc = acc + T.diag[i][r] * z[r];
+    } else if (T.cplx[i]) {
+      const c128* a = reinterpret_cast<const c128*>(T.A[i]) + (long long)r * n;
+#pragma unroll 4
+      for (int c = lane; c < n; c += 64) acc = acc + a[c] * z[c];
+    } else {
+      const double* a = reinterpret_cast<const double*>(T.A[i]) + (long long)r * n;
+#pragma unroll 4
+      for (int c = lane; c < n; c += 64) {
+        const double v = a[c];
+        const c128 zc = z[c];
+        acc.re += v * zc.re;
+        acc.im += v * zc.im;
+      }
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) out[r] = -acc;
+}
+
+// h[t] = U[:, t]^H y, t < m: one group per column.
+__global__ __launch_bounds__(256) void k_nl_dots(int n, const c128* __restrict__ U, const c128* __restrict__ y,
+                                                 c128* __restrict__ h) {
+  __shared__ c128 red[4];
+  const c128* u = U + (long long)blockIdx.x * n;
+  c128 acc = {0.0, 0.0};
+  for (int r = threadIdx.x; r < n; r += 256) acc = acc + conj(u[r]) * y[r];
+  const c128 s = group_sum(acc, red);
+  if (threadIdx.x == 0) h[blockIdx.x] = s;
+}
+
+// out = ||y||_2 (one group).
+__global__ __launch_bounds__(256) void k_nl_norm(int n, const c128* __restrict__ y, double* __restrict__ out) {
+  __shared__ c128 red[4];
+  double acc = 0.0;
+  for (int r = threadIdx.x; r < n; r += 256) acc += norm2(y[r]);
+  const c128 s = group_sum(c128{acc, 0.0}, red);
+  if (threadIdx.x == 0) *out = sqrt(s.re);
+}
+
+// u = y / nrm (nrm read on the device; 0 leaves u = 0).
+// (y and u may be the same vector.)
+__global__ __launch_bounds__(256) void k_nl_store(int n, const c128* y, const double* nrm, c128* u) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double s = *nrm > 0.0 ? 1.0 / *nrm : 0.0;
+  u[r] = s * y[r];
+}
+
+// X[:, q] = U[:, 0:m] S[:, q], scaled to 2-norm 1 with its largest-modulus
+// entry (lowest index among equals) real and positive.  One group per column.
+__global__ __launch_bounds__(256) void k_nl_vectors(int n, int m, const c128* __restrict__ U,
+                                                    const c128* __restrict__ S, c128* __restrict__ X) {
+  __shared__ c128 red[4];
+  __shared__ double wmax[4];
+  __shared__ int widx[4];
+  const int q = blockIdx.x;
+  c128* x = X + (long long)q * n;
+  double ss = 0.0, bm = -1.0;
+  int bi = 0x7fffffff;
+  for (int r = threadIdx.x; r < n; r += 256) {
+    c128 acc = {0.0, 0.0};
+    for (int t = 0; t < m; ++t) acc = acc + U[(long long)t * n + r] * S[(long long)q * m + t];
+    x[r] = acc;
+    const double a2 = norm2(acc);
+    ss += a2;
+    if (a2 > bm) {
+      bm = a2;
+      bi = r;
+    }
+  }
+  const c128 tot = group_sum(c128{ss, 0.0}, red);
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double ov = __shfl_xor(bm, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ov > bm || (ov == bm && oi < bi)) {
+      bm = ov;
+      bi = oi;
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    wmax[threadIdx.x >> 6] = bm;
+    widx[threadIdx.x >> 6] = bi;
+  }
+  __syncthreads();
+  bm = wmax[0];
+  bi = widx[0];
+  for (int w = 1; w < 4; ++w)
+    if (wmax[w] > bm || (wmax[w] == bm && widx[w] < bi)) {
+      bm = wmax[w];
+      bi = widx[w];
+    }
+  const c128 piv = x[bi];
+  const double ap = sqrt(norm2(piv)), nrm = sqrt(tot.re);
+  const c128 sc = (ap > 0.0 && nrm > 0.0) ? c128{piv.re / (ap * nrm), -piv.im / (ap * nrm)} : c128{0.0, 0.0};
+  __syncthreads();
+  for (int r = threadIdx.x; r < n; r += 256) x[r] = sc * x[r];
+}
+
+// ---------------------------------------------------------------------------
+// Host set-up: Leja--Bagby points, basis scaling, divided differences
+// ---------------------------------------------------------------------------
+
+using zc = std::complex<double>;
+
+struct Interp {
+  int d = 0, met = 0;
+  std::vector<zc> sigma, xi;   // d + 1 each (xi[0] unused, infinite)
+  std::vector<double> beta;    // d + 1
+  std::vector<zc> dd;          // ell x (d + 1): dd[i * (d + 1) + j] = d_i^j
+};
+
+bool inf_pole(zc x) { return std::isinf(x.real()) || std::isinf(x.imag()); }
+zc pole_factor(zc z, zc xi) { return inf_pole(xi) ? zc(1.0, 0.0) : zc(1.0, 0.0) - z / xi; }
+
+int argmax_tie(const std::vector<double>& a) {
+  const double m = *std::max_element(a.begin(), a.end());
+  for (size_t k = 0; k < a.size(); ++k)
+    if (a[k] >= m * (1.0 - kNlTie)) return (int)k;
+  return 0;
+}
+
+// -1 when every value is infinite
+int argmin_tie(const std::vector<double>& a) {
+  double m = INFINITY;
+  for (double v : a) m = std::min(m, v);
+  if (!std::isfinite(m)) return -1;
+  for (size_t k = 0; k < a.size(); ++k)
+    if (a[k] <= m * (1.0 + kNlTie)) return (int)k;
+  return -1;
+}
+
+double mag(zc x) {
+  const double a = std::abs(x);
+  return std::isnan(a) ? INFINITY : a;
+}
+
+nep_status interp_build(Split& s, const nep_contour& g, const nep_nleigs_opts& o, Interp& it) {
+  const int npts = o.npts > 0 ? o.npts : 1024;
+  const int dmax = o.dmax > 0 ? o.dmax : 50;
+  const double tol = o.tol > 0.0 ? o.tol : 1e-12;
+  const int ell = s.op.ell;
+  // boundary of the region
+  const double v = g.kind == 1 ? g.v : 1.0;
+  std::vector<zc> zb(npts);
+  for (int k = 0; k < npts; ++k) {
+    const double t = 2.0 * M_PI * k / npts;
+    zb[k] = zc(g.c[0] + g.rho * std::cos(t), g.c[1] + g.rho * v * std::sin(t));
+  }
+  std::vector<zc> xs(o.nxi);
+  for (int k = 0; k < o.nxi; ++k) xs[k] = zc(o.xi[2 * k], o.xi[2 * k + 1]);
+  // Leja--Bagby: s_j kept on the candidates, rescaled every step (the
+  // selections only compare values)
+  std::vector<int> idx{0};
+  std::vector<zc> sig{zb[0]}, xi{zc(INFINITY, 0.0)};
+  std::vector<zc> sb(npts), sx(xs.size());
+  for (int k = 0; k < npts; ++k) sb[k] = zb[k] - sig[0];
+  for (size_t k = 0; k < xs.size(); ++k) sx[k] = xs[k] - sig[0];
+  std::vector<double> a(npts), ax(xs.size());
+  std::vector<char> used(xs.size(), 0);  // |s_j| is infinite at a pole
+  for (int j = 0; j < dmax; ++j) {
+    double sc = 0.0;
+    for (int k = 0; k < npts; ++k) sc = std::max(sc, std::abs(sb[k]));
+    for (int k = 0; k < npts; ++k) {
+      sb[k] /= sc;
+      a[k] = std::abs(sb[k]);
+    }
+    for (size_t k = 0; k < xs.size(); ++k) {
+      sx[k] /= sc;
+      ax[k] = used[k] ? INFINITY : mag(sx[k]);
+    }
+    const int kb = argmax_tie(a);
+    idx.push_back(kb);
+    sig.push_back(zb[kb]);
+    const int kx = xs.empty() ? -1 : argmin_tie(ax);
+    const zc xn = kx >= 0 ? xs[kx] : zc(INFINITY, 0.0);
+    if (kx >= 0)
+      for (size_t k = 0; k < xs.size(); ++k) used[k] |= xs[k] == xn;
+    xi.push_back(xn);
+    for (int k = 0; k < npts; ++k) sb[k] = sb[k] * (zb[k] - sig.back()) / pole_factor(zb[k], xn);
+    for (size_t k = 0; k < xs.size(); ++k)
+      if (!used[k]) sx[k] = sx[k] * (xs[k] - sig.back()) / pole_factor(xs[k], xn);
+  }
+  // f_i at the nodes (device evaluation of the FN trees)
+  std::vector<c128> zn(dmax + 1), fv;
+  std::vector<int> bad;
+  for (int j = 0; j <= dmax; ++j) zn[j] = c128{sig[j].real(), sig[j].imag()};
+  NEP_TRY(s.eval_fns(dmax + 1, zn.data(), fv, bad, false));
+  for (int j = 0; j <= dmax; ++j)
+    NEP_CHECK(!bad[j], NEP_ERR_NOT_HOLOMORPHIC, "interpolation node %d lies on a pole or branch cut", j);
+  auto f = [&](int i, int j) { return zc(fv[(size_t)i * (dmax + 1) + j].re, fv[(size_t)i * (dmax + 1) + j].im); };
+  // b_j on the boundary points, beta_j scaling max |b_j| to 1
+  std::vector<zc> bb((size_t)(dmax + 1) * npts);
+  std::vector<double> beta(dmax + 1, 1.0);
+  for (int k = 0; k < npts; ++k) bb[k] = zc(1.0, 0.0);
+  std::vector<zc> t(npts);
+  for (int j = 1; j <= dmax; ++j) {
+    double mx = 0.0;
+    for (int k = 0; k < npts; ++k) {
+      t[k] = bb[(size_t)(j - 1) * npts + k] * (zb[k] - sig[j - 1]) / pole_factor(zb[k], xi[j]);
+      mx = std::max(mx, std::abs(t[k]));
+    }
+    beta[j] = mx;
+    for (int k = 0; k < npts; ++k) bb[(size_t)j * npts + k] = t[k] / mx;
+  }
+  auto B = [&](int j, int k) { return bb[(size_t)j * npts + k]; };
+  // divided differences by the interpolation conditions
+  std::vector<zc> dd((size_t)ell * (dmax + 1));
+  for (int i = 0; i < ell; ++i)
+    for (int j = 0; j <= dmax; ++j) {
+      zc acc = f(i, j);
+      for (int q = 0; q < j; ++q) acc -= B(q, idx[j]) * dd[(size_t)i * (dmax + 1) + q];
+      dd[(size_t)i * (dmax + 1) + j] = acc / B(j, idx[j]);
+    }
+  std::vector<double> delta(dmax + 1, 0.0);
+  for (int j = 0; j <= dmax; ++j)
+    for (int i = 0; i < ell; ++i) delta[j] = std::max(delta[j], std::abs(dd[(size_t)i * (dmax + 1) + j]));
+  int d = dmax, met = 0;
+  for (int j = 2; j <= dmax; ++j)
+    if (delta[j] / delta[0] < tol) {
+      d = j;
+      met = 1;
+      break;
+    }
+  // last pole at infinity
+  double mx = 0.0;
+  for (int k = 0; k < npts; ++k) {
+    t[k] = B(d - 1, k) * (zb[k] - sig[d - 1]);
+    mx = std::max(mx, std::abs(t[k]));
+  }
+  beta[d] = mx;
+  const zc bd = t[idx[d]] / mx;
+  it.d = d;
+  it.met = met;
+  it.sigma.assign(sig.begin(), sig.begin() + d + 1);
+  it.xi.assign(xi.begin(), xi.begin() + d + 1);
+  it.xi[d] = zc(INFINITY, 0.0);
+  it.beta.assign(beta.begin(), beta.begin() + d + 1);
+  it.dd.assign((size_t)ell * (d + 1), zc());
+  for (int i = 0; i < ell; ++i) {
+    for (int j = 0; j < d; ++j) it.dd[(size_t)i * (d + 1) + j] = dd[(size_t)i * (dmax + 1) + j];
+    zc acc = f(i, d);
+    for (int q = 0; q < d; ++q) acc -= B(q, idx[d]) * dd[(size_t)i * (dmax + 1) + q];
+    it.dd[(size_t)i * (d + 1) + d] = acc / bd;
+  }
+  return NEP_OK;
+}
+
+// b_0(z)..b_d(z) of the interpolant
+std::vector<zc> basis_at(const Interp& it, zc z) {
+  std::vector<zc> b(it.d + 1);
+  b[0] = zc(1.0, 0.0);
+  for (int j = 1; j <= it.d; ++j) b[j] = b[j - 1] * (z - it.sigma[j - 1]) / (it.beta[j] * pole_factor(z, it.xi[j]));
+  return b;
+}
+
+nep_status check_nleigs_opts(const nep_nleigs_opts* o) {
+  NEP_CHECK(o != nullptr, NEP_ERR_ARG, "null options");
+  NEP_CHECK(o->dmax == 0 || (o->dmax >= 2 && o->dmax <= kNlMaxDeg), NEP_ERR_ARG, "need 2 <= dmax <= %d", kNlMaxDeg);
+  NEP_CHECK(o->npts == 0 || (o->npts >= 8 && o->npts <= kNlMaxPts), NEP_ERR_ARG, "need 8 <= npts <= %d", kNlMaxPts);
+  NEP_CHECK(o->tol >= 0.0 && o->tol < 1.0, NEP_ERR_ARG, "need 0 <= tol < 1");
+  NEP_CHECK(o->nxi >= 0 && o->nxi <= 65536 && (o->nxi == 0 || o->xi != nullptr), NEP_ERR_ARG,
+            "bad singularity set");
+  return NEP_OK;
+}
+
+}  // namespace
+
+}  // namespace nep
+
+using namespace nep;
+
+extern "C" {
+
+nep_status nep_nleigs_interp(nep_split h, const nep_contour* g, const nep_nleigs_opts* o, int* d, int* met,
+                             double* sigma, double* xi, double* beta, double* dd) {
+  NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle");
+  NEP_TRY(check_contour(g));
+  NEP_TRY(check_nleigs_opts(o));
+  NEP_CHECK(d && met && sigma && xi && beta && dd, NEP_ERR_ARG, "null output");
+  Split& s = h->impl;
+  Interp it;
+  NEP_TRY(interp_build(s, *g, *o, it));
+  const int dmax = o->dmax > 0 ? o->dmax : 50;
+  *d = it.d;
+  *met = it.met;
+  for (int j = 0; j <= dmax; ++j) {
+    const bool in = j <= it.d;
+    sigma[2 * j] = in ? it.sigma[j].real() : 0.0;
+    sigma[2 * j + 1] = in ? it.sigma[j].imag() : 0.0;
+    xi[2 * j] = in ? it.xi[j].real() : 0.0;
+    xi[2 * j + 1] = in ? it.xi[j].imag() : 0.0;
+    beta[j] = in ? it.beta[j] : 0.0;
+    for (int i = 0; i < s.op.ell; ++i) {
+      const zc v = in ? it.dd[(size_t)i * (it.d + 1) + j] : zc();
+      dd[2 * ((size_t)i * (dmax + 1) + j)] = v.real();
+      dd[2 * ((size_t)i * (dmax + 1) + j) + 1] = v.imag();
+    }
+  }
+  return NEP_OK;
+}
+
+nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* o, const void* W0, int* m_out,
+                      double* lambda, void* X, double* eta, double* Hout, nep_nleigs_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  NEP_CHECK(h != nullptr, NEP_ERR_ARG, "null handle");
+  NEP_TRY(check_contour(g));
+  NEP_TRY(check_nleigs_opts(o));
+  NEP_CHECK(o->k >= 1 && o->k <= kNlMaxK, NEP_ERR_ARG, "need 1 <= k <= %d", kNlMaxK);
+  NEP_CHECK(o->max_eigs >= 1, NEP_ERR_ARG, "need max_eigs >= 1");
+  NEP_CHECK(o->eta_tol >= 0.0, NEP_ERR_ARG, "need eta_tol >= 0");
+  NEP_CHECK(W0 && m_out && lambda && X && eta, NEP_ERR_ARG, "null argument");
+  Split& s = h->impl;
+  const int n = s.op.n, ell = s.op.ell, k = o->k;
+  const hipStream_t st = s.stream;
+  const zc sg(o->sigma[0], o->sigma[1]);
+  const double eta_tol = o->eta_tol > 0.0 ? o->eta_tol : 1e-10;
+
+  Interp it;
+  NEP_TRY(interp_build(s, *g, *o, it));
+  const int d = it.d;
+  for (int j = 0; j < d; ++j)
+    NEP_CHECK(it.sigma[j] != sg, NEP_ERR_ARG, "the shift equals interpolation node %d", j);
+  for (int j = 1; j <= d; ++j)
+    NEP_CHECK(inf_pole(it.xi[j]) || it.xi[j] != sg, NEP_ERR_ARG, "the shift equals pole %d", j);
+  const std::vector<zc> bs = basis_at(it, sg);
+  auto DD = [&](int i, int j) { return it.dd[(size_t)i * (d + 1) + j]; };
+  std::vector<c128> rho(ell);
+  for (int i = 0; i < ell; ++i) {
+    zc acc;
+    for (int j = 0; j <= d; ++j) acc += bs[j] * DD(i, j);
+    rho[i] = c128{acc.real(), acc.imag()};
+  }
+  // coefficient recurrences of eqs. (nleigstoarreca), (nleigs-toar1)
+  std::vector<zc> xr(d + 1), om(d + 1);
+  for (int j = 1; j <= d; ++j) {
+    xr[j] = inf_pole(it.xi[j]) ? zc() : it.beta[j] / it.xi[j];
+    om[j] = inf_pole(it.xi[j]) ? zc(1.0, 0.0) : zc(1.0, 0.0) - sg / it.xi[j];
+  }
+
+  // device buffers
+  const int mmax = d + k;  // basis columns at most
+  DevMem dU, dZ, dQ, dsc, dsig, drho;
+  NEP_TRY(dU.alloc(sizeof(c128) * (size_t)n * (mmax + 1)));
+  NEP_TRY(dZ.alloc(sizeof(c128) * (size_t)n * std::max(ell, 1)));
+  NEP_TRY(dQ.alloc(sizeof(c128) * (size_t)(mmax + 1) * std::max(ell, k)));
+  NEP_TRY(dsc.alloc(sizeof(c128) * (size_t)(2 * (mmax + 1) + 2)));
+  NEP_TRY(dsig.alloc(sizeof(c128)));
+  NEP_TRY(drho.alloc(sizeof(c128) * ell));
+  c128* U = dU.as<c128>();
+  c128* h1 = dsc.as<c128>();
+  c128* h2 = h1 + (mmax + 1);
+  double* nrm = reinterpret_cast<double*>(h2 + (mmax + 1));  // [0]: before, [1]: after Gram--Schmidt
+  const c128 csg{sg.real(), sg.imag()};
+  NEP_HIP(hipMemcpyAsync(dsig.p, &csg, sizeof(c128), hipMemcpyHostToDevice, st));
+  NEP_HIP(hipMemcpyAsync(drho.p, rho.data(), sizeof(c128) * ell, hipMemcpyHostToDevice, st));
+
+  NlTerms terms{};
+  for (int i = 0; i < ell; ++i) {
+    terms.A[i] = s.op.dA[i];
+    terms.diag[i] = s.op.dDiag[i];
+    terms.cplx[i] = s.op.is_cplx[i];
+    terms.isdiag[i] = s.op.is_diag[i];
+  }
+
+  // R_d(sigma) = sum_i rho_i A_i: assembly and LU in complex FP64
+  MomentsPlan plan;
+  nep_contour g0{};
+  g0.kind = 0;
+  g0.rho = 1.0;
+  g0.v = 1.0;
+  PlanOptions po;
+  po.N = 1;
+  po.L = 1;
+  po.K = 1;
+  po.prec = NEP_PREC_FP64;
+  po.max_refine = 0;
+  po.fallback = 0;
+  PlanProblem pp{&s.op, g0, nullptr, nullptr, dsig.as<c128>()};
+  pp.fpts = drho.as<c128>();
+  std::vector<PlanProblem> probs{pp};
+  NEP_TRY(plan.build(probs, po));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  NEP_HIP(hipEventCreate(&e0));
+  NEP_HIP(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evg{e0, e1};
+  NEP_HIP(hipEventRecord(e0, st));
+  NEP_TRY(plan.factor(st));
+  NEP_HIP(hipEventRecord(e1, st));
+  int pinfo = 0;
+  NEP_HIP(hipMemcpyAsync(&pinfo, plan.info(), sizeof(int), hipMemcpyDeviceToHost, st));
+  NEP_HIP(hipStreamSynchronize(st));
+  NEP_CHECK(pinfo >= n, NEP_ERR_SINGULAR, "R_d(sigma) is exactly singular (zero pivot at step %d)", pinfo);
+  float ms_lu = 0.0f;
+  NEP_HIP(hipEventElapsedTime(&ms_lu, e0, e1));
+  const auto t1 = std::chrono::steady_clock::now();
+  c128* Rv = plan.R_mut();
+  c128* Yv = plan.Y_mut();
+  const dim3 grow(ceil_div(n, 256)), g256(256);
+
+  // Gram--Schmidt of y against U[:, 0:m] with one reorthogonalization; the
+  // normalized remainder goes to U[:, m].  Returns the coefficients and the
+  // norms before and after.
+  std::vector<c128> hb(2 * (mmax + 1) + 2);
+  auto orth = [&](c128* y, int m, std::vector<zc>& coef, double& n0, double& n1) -> nep_status {
+    hipLaunchKernelGGL(k_nl_norm, dim3(1), g256, 0, st, n, y, nrm);
+    if (m > 0) {
+      hipLaunchKernelGGL(k_nl_dots, dim3(m), g256, 0, st, n, U, y, h1);
+      hipLaunchKernelGGL(k_nl_comb, grow, g256, 0, st, n, m, U, h1, 1, y, 1);
+      hipLaunchKernelGGL(k_nl_dots, dim3(m), g256, 0, st, n, U, y, h2);
+      hipLaunchKernelGGL(k_nl_comb, grow, g256, 0, st, n, m, U, h2, 1, y, 1);
+    }
+    hipLaunchKernelGGL(k_nl_norm, dim3(1), g256, 0, st, n, y, nrm + 1);
+    hipLaunchKernelGGL(k_nl_store, grow, g256, 0, st, n, y, nrm + 1, U + (long long)m * n);
+    NEP_HIP(hipGetLastError());
+    NEP_HIP(hipMemcpyAsync(hb.data(), dsc.p, sizeof(c128) * hb.size(), hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipStreamSynchronize(st));
+    coef.assign(m, zc());
+    for (int t = 0; t < m; ++t)
+      coef[t] = zc(hb[t].re + hb[(mmax + 1) + t].re, hb[t].im + hb[(mmax + 1) + t].im);
+    const double* hn = reinterpret_cast<const double*>(hb.data() + 2 * (mmax + 1));
+    n0 = hn[0];
+    n1 = hn[1];
+    return NEP_OK;
+  };
+
+  // starting block: QR of [w^0 .. w^{d-1}] by Gram--Schmidt, g_1 = vec(R)/||vec(R)||
+  NEP_HIP(hipMemcpyAsync(U, W0, sizeof(c128) * (size_t)n * d, hipMemcpyDeviceToDevice, st));
+  // G: column j holds g_{j+1}, block i (length mmax) at offset i * mmax
+  std::vector<std::vector<zc>> G;
+  G.emplace_back((size_t)d * mmax, zc());
+  {
+    std::vector<zc> c;
+    double n0 = 0.0, n1 = 0.0, fro = 0.0;
+    for (int q = 0; q < d; ++q) {
+      NEP_TRY(orth(U + (long long)q * n, q, c, n0, n1));
+      NEP_CHECK(n1 > kNlDep * n0 && n0 > 0.0, NEP_ERR_ARG, "starting block column %d is linearly dependent", q);
+      for (int t = 0; t < q; ++t) G[0][(size_t)q * mmax + t] = c[t];
+      G[0][(size_t)q * mmax + q] = n1;
+    }
+    for (const zc& v : G[0]) fro += std::norm(v);
+    fro = std::sqrt(fro);
+    for (zc& v : G[0]) v /= fro;
+  }
+  int m = d;
+  std::vector<zc> H((size_t)(k + 1) * k, zc());  // column-major (k+1) x k
+  std::vector<c128> Qh((size_t)(mmax + 1) * std::max(ell, 1));
+  int kd = 0;
+  double hlast = 0.0;
+  std::vector<std::vector<zc>> gt(d, std::vector<zc>(mmax));
+  std::vector<zc> c;
+  for (int j = 0; j < k; ++j) {
+    const std::vector<zc>& gj = G[j];
+    auto gb = [&](int i, int t) { return gj[(size_t)i * mmax + t]; };
+    // eq. (nleigs-toar1)
+    for (int t = 0; t < m; ++t)
+      gt[d - 1][t] = (gb(d - 2, t) + xr[d - 1] * gb(d - 1, t)) / (it.sigma[d - 2] - sg);
+    for (int i = d - 2; i >= 1; --i)
+      for (int t = 0; t < m; ++t)
+        gt[i][t] = (gb(i - 1, t) + xr[i] * gb(i, t) - it.beta[i] * om[i] * gt[i + 1][t]) / (it.sigma[i - 1] - sg);
+    // q_i, so that the right-hand side of eq. (nleigs-toar2) is -sum_i A_i U q_i
+    for (int i = 0; i < ell; ++i)
+      for (int t = 0; t < m; ++t) {
+        zc acc = DD(i, d) / it.beta[d] * gb(d - 1, t);
+        for (int q = 0; q + 1 < d; ++q) acc += DD(i, q) * gt[q + 1][t];
+        Qh[(size_t)i * m + t] = c128{acc.real(), acc.imag()};
+      }
+    NEP_HIP(hipMemcpyAsync(dQ.p, Qh.data(), sizeof(c128) * (size_t)m * ell, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_nl_comb, grow, g256, 0, st, n, m, U, dQ.as<c128>(), ell, dZ.as<c128>(), 0);
+    hipLaunchKernelGGL(k_nl_splitmv, dim3(ceil_div(n, 4)), g256, 0, st, n, ell, terms, dZ.as<c128>(), Rv);
+    NEP_HIP(hipGetLastError());
+    NEP_TRY(plan.solve_rhs(st));  // y^0 = R_d(sigma)^{-1} rhs
+    double n0 = 0.0, n1 = 0.0;
+    NEP_TRY(orth(Yv, m, c, n0, n1));
+    const bool grow_u = n1 > kNlDep * n0;
+    const int mn = m + (grow_u ? 1 : 0);
+    // y^0 = U_{mn} g~^0; eq. (nleigs-toar4)
+    std::vector<zc> g0v(mn, zc());
+    for (int t = 0; t < m; ++t) g0v[t] = c[t];
+    if (grow_u) g0v[m] = n1;
+    std::vector<zc> v((size_t)d * mmax, zc());
+    for (int i = 0; i + 1 < d; ++i)
+      for (int t = 0; t < mn; ++t) v[(size_t)i * mmax + t] = (t < m ? gt[i + 1][t] : zc()) + bs[i] * g0v[t];
+    for (int t = 0; t < mn; ++t) v[(size_t)(d - 1) * mmax + t] = bs[d - 1] * g0v[t];
+    // Gram--Schmidt against g_1..g_{j+1} with one reorthogonalization
+    std::vector<zc> hh(j + 1, zc());
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<zc> hp(j + 1, zc());
+      for (int q = 0; q <= j; ++q) {
+        zc acc;
+        for (size_t e = 0; e < v.size(); ++e) acc += std::conj(G[q][e]) * v[e];
+        hp[q] = acc;
+      }
+      for (int q = 0; q <= j; ++q) {
+        for (size_t e = 0; e < v.size(); ++e) v[e] -= G[q][e] * hp[q];
+        hh[q] += hp[q];
+      }
+    }
+    double nv = 0.0;
+    for (const zc& e : v) nv += std::norm(e);
+    nv = std::sqrt(nv);
+    for (int q = 0; q <= j; ++q) H[(size_t)j * (k + 1) + q] = hh[q];
+    H[(size_t)j * (k + 1) + j + 1] = nv;
+    m = mn;
+    kd = j + 1;
+    hlast = nv;
+    if (!(nv > 0.0)) break;  // invariant subspace
+    for (zc& e : v) e /= nv;
+    G.push_back(std::move(v));
+  }
+  const float ms_krylov = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t1).count();
+
+  // Ritz pairs: theta of H_k, lambda = sigma + 1/theta, x = U G^0 s
+  std::vector<zc> Hk((size_t)kd * kd), th, S;
+  for (int q = 0; q < kd; ++q)
+    for (int r = 0; r < kd; ++r) Hk[(size_t)q * kd + r] = H[(size_t)q * (k + 1) + r];
+  NEP_CHECK(eig_general(kd, Hk, th, S), NEP_ERR_DEVICE, "eigenvalues of the Hessenberg matrix did not converge");
+  std::vector<int> cand;
+  std::vector<zc> lam(kd);
+  const double vv = g->kind == 1 ? g->v : 1.0;
+  for (int q = 0; q < kd; ++q) {
+    if (th[q] == zc(0.0, 0.0)) continue;
+    lam[q] = sg + 1.0 / th[q];
+    const zc mu = (lam[q] - zc(g->c[0], g->c[1])) / g->rho;
+    const double r2 = mu.real() * mu.real() + (mu.imag() / vv) * (mu.imag() / vv);
+    if (r2 < 1.0 && std::isfinite(r2)) cand.push_back(q);
+  }
+  int mret = 0;
+  std::vector<double> et;
+  if (!cand.empty()) {
+    const int nc = (int)cand.size();
+    std::vector<c128> Sx((size_t)m * nc);
+    for (int a = 0; a < nc; ++a) {
+      const int q = cand[a];
+      double sn = 0.0;
+      for (int r = 0; r < kd; ++r) sn += std::norm(S[(size_t)q * kd + r]);
+      sn = std::sqrt(sn);
+      for (int t = 0; t < m; ++t) {
+        zc acc;
+        for (int r = 0; r < kd; ++r) acc += G[r][t] * S[(size_t)q * kd + r];
+        acc /= sn;
+        Sx[(size_t)a * m + t] = c128{acc.real(), acc.imag()};
+      }
+    }
+    DevMem dS, dX;
+    NEP_TRY(dS.alloc(sizeof(c128) * Sx.size()));
+    NEP_TRY(dX.alloc(sizeof(c128) * (size_t)n * nc));
+    NEP_HIP(hipMemcpyAsync(dS.p, Sx.data(), sizeof(c128) * Sx.size(), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_nl_vectors, dim3(nc), g256, 0, st, n, m, U, dS.as<c128>(), dX.as<c128>());
+    NEP_HIP(hipGetLastError());
+    std::vector<double> lh(2 * nc), eh(nc);
+    for (int a = 0; a < nc; ++a) {
+      lh[2 * a] = lam[cand[a]].real();
+      lh[2 * a + 1] = lam[cand[a]].imag();
+    }
+    NEP_TRY(nep_backward_error(h, nc, lh.data(), dX.p, eh.data()));
+    std::vector<int> keep;
+    for (int a = 0; a < nc; ++a)
+      if (eh[a] <= eta_tol) keep.push_back(a);
+    std::sort(keep.begin(), keep.end(), [&](int x, int y) {
+      const zc lx = lam[cand[x]], ly = lam[cand[y]];
+      return lx.real() != ly.real() ? lx.real() < ly.real() : lx.imag() < ly.imag();
+    });
+    mret = std::min((int)keep.size(), o->max_eigs);
+    for (int a = 0; a < mret; ++a) {
+      const int b = keep[a];
+      lambda[2 * a] = lh[2 * b];
+      lambda[2 * a + 1] = lh[2 * b + 1];
+      eta[a] = eh[b];
+      NEP_HIP(hipMemcpyAsync(reinterpret_cast<c128*>(X) + (size_t)a * n, dX.as<c128>() + (size_t)b * n,
+                             sizeof(c128) * n, hipMemcpyDeviceToDevice, st));
+    }
+    NEP_HIP(hipStreamSynchronize(st));
+  }
+  *m_out = mret;
+  if (Hout)
+    for (size_t e = 0; e < H.size(); ++e) {
+      Hout[2 * e] = H[e].real();
+      Hout[2 * e + 1] = H[e].imag();
+    }
+  if (info) {
+    info->d = d;
+    info->met = it.met;
+    info->k_done = kd;
+    info->basis = m;
+    info->h_last = hlast;
+    info->ms_lu = ms_lu;
+    info->ms_krylov = ms_krylov;
+    info->ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return NEP_OK;
+}
+
+}  // extern "C"

@@ -207,6 +207,7 @@ nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs) {
     D.fn_nodes = q.op->dfn_nodes;
     D.fn_coef = q.op->dfn_coef;
     D.zpts = q.zpts;
+    D.fpts = q.zpts != nullptr ? q.fpts : nullptr;
     D.s_stride = q.s_stride > 0 ? q.s_stride : (long long)D.n * D.L;
     D.active = 1;
   }
@@ -232,6 +233,7 @@ nep_status MomentsPlan::rebind_members(const std::vector<int>& member, const std
     D.V = V[k];
     D.S = S[k];
     D.zpts = nullptr;
+    D.fpts = nullptr;
     D.s_stride = (long long)D.n * D.L;
   }
   NEP_HIP(hipMemcpyAsync(dpd_.p, hpd_.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice, st));

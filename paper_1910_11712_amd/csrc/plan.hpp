@@ -88,6 +88,10 @@ struct PlanProblem {
   c128* S;
   const c128* zpts = nullptr;  // explicit points (device, N) instead of g's nodes
   long long s_stride = 0;      // elements between moment blocks of S; 0: n*L
+  // with zpts: coefficients c_ji (device, N x ell, at j*ell + i) that take the
+  // place of f_i(z_j), so the plan factors sum_i c_ji A_i (e.g. a rational
+  // interpolant of T evaluated at a shift)
+  const c128* fpts = nullptr;
 };
 
 struct PlanOptions {
