@@ -375,6 +375,10 @@ def main():
     if args.workload == "cfg3":  # the 256-problem batch alone (graph replay), one JSON line
         print(json.dumps({"workload": "cfg3_batch_graph", **_batch_run(P, steps=args.steps, tune=not args.no_tune)}))
         return
+    if args.workload == "nleigs":  # NLEIGS on the square-root workload alone, one JSON line
+        print(json.dumps({"workload": "nleigs_sqrt_n4096", **_nleigs_run(P, steps=args.steps,
+                                                                         warmup=args.warmup)}))
+        return
     if args.workload == "cfg4":  # the serving stream alone, both precisions, one JSON line
         rates = [float(x) for x in args.rates.split(",") if x.strip()]
         print(json.dumps({"workload": "cfg4_serving", **_serve_full(P, args.rate, args.window, 5.0, rates)}))
@@ -428,6 +432,7 @@ def main():
         jobs = []
         if args.workload == "cfg2":
             jobs.append(("cfg2_end_to_end", lambda: _eigs_run(P, tune=not args.no_tune)))
+            jobs.append(("nleigs_sqrt_n4096", lambda: _nleigs_run(P)))
         if args.workload != "cfg1":
             jobs.append(("cfg1_delay_n1000", lambda: _cfg1_run(P, args, tune=not args.no_tune)))
         jobs += [("cfg3_batch_graph", lambda: _batch_run(P, tune=not args.no_tune)),
@@ -451,6 +456,47 @@ def main():
         e2e = extra["cfg2_end_to_end"]["mixed"]
         line["eigenpairs_per_s"] = e2e.get("eigenpairs_per_s")
     print(json.dumps(line))
+
+
+def _nleigs_run(P, steps=3, warmup=1, k=100, dmax=40):
+    """NLEIGS (Section 4.5) on the square-root workload n=4096: the
+    interpolant on the ellipse with poles from 100 points of the branch cut
+    (-inf, s2^2], one complex FP64 factorization of R_d(sigma) at the centre,
+    k Arnoldi steps; wall time per call and the eigenpairs it returns (eta <=
+    1e-10, inside), checked against the oracle's eigenvalues of T stored in
+    tests/golden."""
+    import torch
+    import workloads as wl
+    cfg = wl.config2()
+    p, con = cfg["problem"], cfg["contour"]
+    cut = 108.8 ** 2 - np.logspace(-3, 6, 100)
+    op = P.SplitOperator.from_problem(p)
+    W0 = torch.from_numpy(np.ascontiguousarray(wl.probes(p.n, dmax, 5).T)).to("cuda")
+    X = torch.zeros((64, p.n), dtype=torch.complex128, device="cuda")
+    times, res = [], None
+    for it in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = op.nleigs(con, W0, X, con.c, k, dmax=dmax, tol=1e-12, xi=cut, eta_tol=1e-10, max_eigs=64)
+        torch.cuda.synchronize()
+        if it >= warmup:
+            times.append(time.perf_counter() - t0)
+    op.close()
+    lam, eta, info = res
+    t = float(np.median(times))
+    out = {"n": p.n, "k": k, "degree": info["d"], "basis": info["basis"], "ms_per_call": t * 1e3,
+           "ms_lu": info["ms_lu"], "ms_krylov": info["ms_krylov"], "ms_per_arnoldi_step": info["ms_krylov"] / k,
+           "eigenpairs": int(len(lam)), "eigenpairs_per_s": len(lam) / t,
+           "max_eta": float(np.max(eta)) if len(lam) else None}
+    try:
+        g = np.load(os.path.join(ROOT, "tests", "golden", "cfg2_sqrt_n4096_oracle.npz"))
+        gold = g["lam"][g["inside"].astype(bool)]
+        out["oracle_inside"] = int(len(gold))
+        out["max_rel_dlambda_vs_oracle"] = float(max(np.min(np.abs(gold - z)) / abs(z) for z in lam)) \
+            if len(lam) else None
+    except OSError:
+        pass
+    return out
 
 
 def _cfg1_run(P, args, tune=True):

@@ -80,19 +80,212 @@ __device__ __forceinline__ c128 group_sum(c128 v, c128* red) {
 }
 
 // Z[:, c] = U[:, 0:m] Q[:, c] (sub = 0) or Z[:, c] -= U[:, 0:m] Q[:, c]
-// (sub = 1), c < ncol.  U column-major with leading dimension n, Q
-// column-major with leading dimension m.  One thread per row.
-__global__ __launch_bounds__(256) void k_nl_comb(int n, int m, const c128* __restrict__ U,
-                                                 const c128* __restrict__ Q, int ncol, c128* __restrict__ Z,
-                                                 int sub) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// (sub = 1).  U column-major with leading dimension n, Q column-major with
+// leading dimension m.  One thread per row, one grid row per column c.
+__global__ __launch_bounds__(64) void k_nl_comb(int n, int m, const c128* __restrict__ U,
+                                                const c128* __restrict__ Q, c128* __restrict__ Z, int sub) {
+  const int r = blockIdx.x * 64 + threadIdx.x, c = blockIdx.y;
   if (r >= n) return;
-  for (int c = 0; c < ncol; ++c) {
-    c128 acc = {0.0, 0.0};
-    for (int t = 0; t < m; ++t) acc = acc + U[(long long)t * n + r] * Q[(long long)c * m + t];
-    c128* z = Z + (long long)c * n + r;
-    *z = sub ? *z - acc : acc;
+  const c128* q = Q + (long long)c * m;
+  c128 a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
+  int t = 0;
+  for (; t + 1 < m; t += 2) {  // two independent chains keep two loads in flight
+    a0 = a0 + U[(long long)t * n + r] * q[t];
+    a1 = a1 + U[(long long)(t + 1) * n + r] * q[t + 1];
   }
+  if (t < m) a0 = a0 + U[(long long)t * n + r] * q[t];
+  const c128 acc = a0 + a1;
+  c128* z = Z + (long long)c * n + r;
+  *z = sub ? *z - acc : acc;
+}
+
+// ---------------------------------------------------------------------------
+// Triangular solves with the factors of one matrix, one right-hand side.
+//
+// The batched solve kernels give a whole matrix to one group, which suits
+// many matrices and probe columns; a Krylov step solves with one matrix and
+// one vector, so here the 64-row blocks of the triangle go to separate
+// groups (n/64 of them) and each group streams its own block row of the
+// factor while the solutions of the blocks before it appear:
+//   y_q = Dinv_q (b_q - sum_{c<q} L_qc y_c)   (forward; U backwards)
+// with the stored inverses of the 64 x 64 diagonal blocks.  Thread (wave w,
+// lane l) owns rows 16w..16w+15 of the block and column l of every column
+// block (coalesced row segments); its 16 partial sums are reduced over the
+// wave once, at the end.  A group takes its block from a ticket counter, so
+// blocks are taken in launch order and a group only waits for blocks already
+// held by running groups; the waits are bounded (a wait that runs out sets
+// *err and the group finishes with wrong values instead of hanging).  Block
+// solutions are published by a release store of the solve's epoch into the
+// block's flag; readers acquire it at agent scope before loading the block.
+// ---------------------------------------------------------------------------
+constexpr int kNlBlk = 64;
+constexpr int kNlSpinMax = 1 << 22;  // polls of one wait (about 0.3 s)
+
+// Waits until *flag == epoch (relaxed polls; the caller's acquire fence
+// follows the wait once).  Once any wait has run out (*err set), no group
+// waits any more, so a failed solve costs one bound, not one per block.
+__device__ __forceinline__ void wait_flag(const int* flag, int epoch, int* err) {
+  int it = 0;
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+    if (++it > kNlSpinMax || ((it & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+      atomicExch(err, 1);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// UPPER = 0: out = L^{-1} P b with b gathered through the row map (b in
+// physical row order); UPPER = 1: out = U^{-1} b.  T: row-major factor with
+// leading dimension ld, rat: the row map, Di: the diagonal-block inverses.
+// A group of 512 threads owns two consecutive 64-row blocks: waves 0-3 the
+// one solved first (the lower-indexed for L, the higher for U), waves 4-7 the
+// other, whose coupling to the first is applied inside the group (LDS and a
+// barrier instead of a flag round trip through memory), so the chain of
+// cross-group waits is n/128 long.
+template <bool UPPER>
+__global__ __launch_bounds__(512) void k_nl_tri(int n, int ld, const c128* __restrict__ T,
+                                                const int* __restrict__ rat, const c128* __restrict__ Di,
+                                                const c128* __restrict__ b, c128* out, int* flags, int* ticket,
+                                                int epoch, int* err) {
+  constexpr int B = kNlBlk;
+  __shared__ c128 Dsh[2][B][B + 1];
+  __shared__ c128 tq[2][B];
+  __shared__ c128 ysh[2][B];
+  __shared__ int s_t;
+  const int nblk = (n + B - 1) / B, npair = (nblk + 1) / 2;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int half = w >> 2;            // 0: the block solved first, 1: the other
+  const int hw = w & 3, htid = tid & 255;
+  if (tid == 0) s_t = atomicAdd(ticket, 1) - (epoch - 1) * npair;
+  __syncthreads();
+  const int tk = s_t;
+  if (tk < 0 || tk >= npair) return;  // not reached with npair groups per epoch
+  const int pr = UPPER ? npair - 1 - tk : tk;
+  // the group's blocks in solve order; the higher one may lie past n (odd nblk)
+  const int qf = UPPER ? min(2 * pr + 1, nblk - 1) : 2 * pr;
+  const int qs = UPPER ? (2 * pr + 1 < nblk ? 2 * pr : -1) : (2 * pr + 1 < nblk ? 2 * pr + 1 : -1);
+  const int qmine = half == 0 ? qf : qs;  // this wave's block (-1: none)
+  // the diagonal-block inverses (identity past n)
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int qq = h == 0 ? qf : qs;
+    if (qq < 0) continue;
+    const c128* D = Di + ((long long)qq * 2 + (UPPER ? 1 : 0)) * B * B;
+    for (int e = tid; e < B * B; e += 512) Dsh[h][e / B][e % B] = D[e];
+  }
+  // physical rows of this thread's 16 logical rows
+  long long roff[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int r = qmine < 0 ? n : qmine * B + 16 * hw + i;
+    roff[i] = r < n ? (long long)rat[r] * ld : -1;
+  }
+  c128 acc[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = c128{0.0, 0.0};
+  // this wave's 16 right-hand-side entries, loaded now (they do not depend on
+  // the chain): lane i < 16 holds row 16 hw + i
+  c128 rhs_mine = {0.0, 0.0};
+  if (lane < 16 && qmine >= 0) {
+    const int r = qmine * B + 16 * hw + lane;
+    if (r < n) rhs_mine = UPPER ? b[r] : b[rat[r]];
+  }
+  // column blocks solved by other groups, in the order they appear
+  const int c_first = UPPER ? nblk - 1 : 0;
+  const int ncb = UPPER ? max(0, nblk - 1 - max(qf, qs)) : 2 * pr;
+  auto cb = [&](int s) { return UPPER ? c_first - s : c_first + s; };
+  c128 seg[16];
+  auto load_seg = [&](int c) {
+    const int col = c * B + lane;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) seg[i] = (roff[i] >= 0 && col < n) ? T[roff[i] + col] : c128{0.0, 0.0};
+  };
+  // waves 4-7 also need the segment of the first block (their coupling)
+  const int nseg = ncb + (half == 1 ? 1 : 0);
+  auto seg_col = [&](int s) { return s < ncb ? cb(s) : qf; };
+  if (nseg > 0) load_seg(seg_col(0));
+  // Blocks are published in the order cb(0), cb(1), ... (a group publishes
+  // only after consuming every block before its own), so once the flag of
+  // cb(ncb - 1) is seen, every block this group needs is there: one wait and
+  // one acquire cover them all, and each block's solution can be loaded one
+  // block ahead like the factor segments.
+  int known = 0;  // blocks cb(0..known-1) are acquired
+  c128 ynext = {0.0, 0.0};
+  for (int s = 0; s < ncb; ++s) {
+    const int c = cb(s);
+    const int col = c * B + lane;
+    c128 yc;
+    if (s >= known) {
+      int kn = s + 1;
+      if (lane == 0) {
+        wait_flag(flags + c, epoch, err);
+        if (s + 1 < ncb &&
+            __hip_atomic_load(flags + cb(ncb - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch)
+          kn = ncb;
+      }
+      known = __shfl(kn, 0, 64);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      yc = col < n ? out[col] : c128{0.0, 0.0};
+    } else {
+      yc = ynext;
+    }
+    if (s + 1 < known) {
+      const int ncol = cb(s + 1) * B + lane;
+      ynext = ncol < n ? out[ncol] : c128{0.0, 0.0};
+    }
+    c128 cur[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) cur[i] = seg[i];
+    if (s + 1 < nseg) load_seg(seg_col(s + 1));  // the next segment loads during this one's use
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = acc[i] + cur[i] * yc;
+  }
+  // solve the group's blocks in order: t_q = b_q - row sums, y_q = Dinv_q t_q
+  auto publish_sums = [&](int h) {  // waves of half h
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = wave_sum(acc[i]);
+    if (lane < 16) {
+      c128 v = {0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (i == lane) v = acc[i];
+      tq[h][16 * hw + lane] = rhs_mine - v;
+    }
+  };
+  auto apply_inverse = [&](int h) {  // the 256 threads of half h: four per row
+    const int i = htid >> 2, k0 = (htid & 3) * 16;
+    c128 y = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) y = y + Dsh[h][i][k0 + k] * tq[h][k0 + k];
+    y.re += __shfl_xor(y.re, 1, 64);
+    y.im += __shfl_xor(y.im, 1, 64);
+    y.re += __shfl_xor(y.re, 2, 64);
+    y.im += __shfl_xor(y.im, 2, 64);
+    if ((htid & 3) == 0) ysh[h][i] = y;
+  };
+  auto store_publish = [&](int h, int q) {  // one wave: its release orders its own stores before the flag
+    if (q * B + lane < n) out[q * B + lane] = ysh[h][lane];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) __hip_atomic_store(flags + q, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  if (half == 0) publish_sums(0);
+  __syncthreads();
+  if (half == 0) apply_inverse(0);
+  __syncthreads();
+  if (w == 0) store_publish(0, qf);
+  if (qs < 0) return;  // wave-uniform: no second block
+  if (half == 1) {
+    // coupling to the first block: seg holds its segment
+    const c128 yc = ysh[0][lane];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = acc[i] + seg[i] * yc;
+    publish_sums(1);
+  }
+  __syncthreads();
+  if (half == 1) apply_inverse(1);
+  __syncthreads();
+  if (w == 4) store_publish(1, qs);
 }
 
 struct NlTerms {
@@ -370,6 +563,40 @@ std::vector<zc> basis_at(const Interp& it, zc z) {
   return b;
 }
 
+// complex product without the library's inf/nan recovery (the operands
+// here are finite)
+inline zc cmul(zc a, zc b) {
+  return zc(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real());
+}
+
+// sum over d blocks (stride ld, first len entries) of conj(a) b, and
+// v -= h g over the same entries: plain real arithmetic (these loops run
+// on the host once per Arnoldi step over (k + d) d entries per vector)
+zc dot_blocks(const zc* a, const zc* b, int d, int ld, int len) {
+  double sr = 0.0, si = 0.0;
+  for (int i = 0; i < d; ++i) {
+    const double* x = reinterpret_cast<const double*>(a + (size_t)i * ld);
+    const double* y = reinterpret_cast<const double*>(b + (size_t)i * ld);
+    for (int t = 0; t < 2 * len; t += 2) {
+      sr += x[t] * y[t] + x[t + 1] * y[t + 1];
+      si += x[t] * y[t + 1] - x[t + 1] * y[t];
+    }
+  }
+  return zc(sr, si);
+}
+
+void axpy_blocks(zc* v, const zc* g, zc h, int d, int ld, int len) {
+  const double hr = h.real(), hi = h.imag();
+  for (int i = 0; i < d; ++i) {
+    double* x = reinterpret_cast<double*>(v + (size_t)i * ld);
+    const double* y = reinterpret_cast<const double*>(g + (size_t)i * ld);
+    for (int t = 0; t < 2 * len; t += 2) {
+      x[t] -= y[t] * hr - y[t + 1] * hi;
+      x[t + 1] -= y[t] * hi + y[t + 1] * hr;
+    }
+  }
+}
+
 nep_status check_nleigs_opts(const nep_nleigs_opts* o) {
   NEP_CHECK(o != nullptr, NEP_ERR_ARG, "null options");
   NEP_CHECK(o->dmax == 0 || (o->dmax >= 2 && o->dmax <= kNlMaxDeg), NEP_ERR_ARG, "need 2 <= dmax <= %d", kNlMaxDeg);
@@ -461,6 +688,7 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
   NEP_TRY(dZ.alloc(sizeof(c128) * (size_t)n * std::max(ell, 1)));
   NEP_TRY(dQ.alloc(sizeof(c128) * (size_t)(mmax + 1) * std::max(ell, k)));
   NEP_TRY(dsc.alloc(sizeof(c128) * (size_t)(2 * (mmax + 1) + 2)));
+  NEP_HIP(hipMemsetAsync(dsc.p, 0, dsc.bytes, st));
   NEP_TRY(dsig.alloc(sizeof(c128)));
   NEP_TRY(drho.alloc(sizeof(c128) * ell));
   c128* U = dU.as<c128>();
@@ -519,6 +747,35 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
   c128* Rv = plan.R_mut();
   c128* Yv = plan.Y_mut();
   const dim3 grow(ceil_div(n, 256)), g256(256);
+  // y = R_d(sigma)^{-1} rhs with the resident factors: forward then backward,
+  // n/64 groups each (flags and tickets zeroed once; each solve has its epoch)
+  const MatDesc md0 = plan.mat0();
+  NEP_CHECK(md0.n == n, NEP_ERR_DEVICE, "factor plan holds a matrix of size %d, expected %d", md0.n, n);
+  const int nblk = ceil_div(n, kNlBlk);
+  DevMem dflag;
+  NEP_TRY(dflag.alloc(sizeof(int) * (2 * (size_t)nblk + 4)));
+  NEP_HIP(hipMemsetAsync(dflag.p, 0, dflag.bytes, st));
+  int* fl_l = dflag.as<int>();
+  int* fl_u = fl_l + nblk;
+  int* tick = fl_u + nblk;  // [0]: forward, [1]: backward
+  // set when a solve's wait ran out; read back with every step's coefficients
+  int* overrun_flag = reinterpret_cast<int*>(h1 + 2 * (mmax + 1) + 1);
+  const c128* Tf = reinterpret_cast<const c128*>(plan.factor_base()) + md0.offT;
+  const int* rat = plan.row_map() + md0.offRow;
+  const c128* Dv = reinterpret_cast<const c128*>(plan.dinv0());
+  DevMem dyf;
+  NEP_TRY(dyf.alloc(sizeof(c128) * (size_t)n));
+  int epoch = 0;
+  auto solve = [&](const c128* rhs, c128* x) -> nep_status {
+    ++epoch;
+    const dim3 gp((nblk + 1) / 2), g512(512);
+    hipLaunchKernelGGL(k_nl_tri<false>, gp, g512, 0, st, n, md0.ld, Tf, rat, Dv, rhs, dyf.as<c128>(), fl_l, tick,
+                       epoch, overrun_flag);
+    hipLaunchKernelGGL(k_nl_tri<true>, gp, g512, 0, st, n, md0.ld, Tf, rat, Dv, dyf.as<c128>(), x, fl_u,
+                       tick + 1, epoch, overrun_flag);
+    NEP_HIP(hipGetLastError());
+    return NEP_OK;
+  };
 
   // Gram--Schmidt of y against U[:, 0:m] with one reorthogonalization; the
   // normalized remainder goes to U[:, m].  Returns the coefficients and the
@@ -528,9 +785,9 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
     hipLaunchKernelGGL(k_nl_norm, dim3(1), g256, 0, st, n, y, nrm);
     if (m > 0) {
       hipLaunchKernelGGL(k_nl_dots, dim3(m), g256, 0, st, n, U, y, h1);
-      hipLaunchKernelGGL(k_nl_comb, grow, g256, 0, st, n, m, U, h1, 1, y, 1);
+      hipLaunchKernelGGL(k_nl_comb, dim3(ceil_div(n, 64), 1), dim3(64), 0, st, n, m, U, h1, y, 1);
       hipLaunchKernelGGL(k_nl_dots, dim3(m), g256, 0, st, n, U, y, h2);
-      hipLaunchKernelGGL(k_nl_comb, grow, g256, 0, st, n, m, U, h2, 1, y, 1);
+      hipLaunchKernelGGL(k_nl_comb, dim3(ceil_div(n, 64), 1), dim3(64), 0, st, n, m, U, h2, y, 1);
     }
     hipLaunchKernelGGL(k_nl_norm, dim3(1), g256, 0, st, n, y, nrm + 1);
     hipLaunchKernelGGL(k_nl_store, grow, g256, 0, st, n, y, nrm + 1, U + (long long)m * n);
@@ -543,6 +800,8 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
     const double* hn = reinterpret_cast<const double*>(hb.data() + 2 * (mmax + 1));
     n0 = hn[0];
     n1 = hn[1];
+    NEP_CHECK(*reinterpret_cast<const int*>(hb.data() + 2 * (mmax + 1) + 1) == 0, NEP_ERR_DEVICE,
+              "a triangular-solve group ran out of its wait bound");
     return NEP_OK;
   };
 
@@ -571,27 +830,36 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
   double hlast = 0.0;
   std::vector<std::vector<zc>> gt(d, std::vector<zc>(mmax));
   std::vector<zc> c;
+  // per-step constants: 1/(sigma_{i-1} - sigma), beta_i (1 - sigma/xi_i),
+  // d_i^d / beta_d
+  std::vector<zc> rds(d), bom(d), ddl(ell);
+  for (int i = 1; i < d; ++i) {
+    rds[i] = 1.0 / (it.sigma[i - 1] - sg);
+    bom[i] = it.beta[i] * om[i];
+  }
+  for (int i = 0; i < ell; ++i) ddl[i] = DD(i, d) / it.beta[d];
   for (int j = 0; j < k; ++j) {
     const std::vector<zc>& gj = G[j];
     auto gb = [&](int i, int t) { return gj[(size_t)i * mmax + t]; };
     // eq. (nleigs-toar1)
     for (int t = 0; t < m; ++t)
-      gt[d - 1][t] = (gb(d - 2, t) + xr[d - 1] * gb(d - 1, t)) / (it.sigma[d - 2] - sg);
+      gt[d - 1][t] = cmul(gb(d - 2, t) + cmul(xr[d - 1], gb(d - 1, t)), rds[d - 1]);
     for (int i = d - 2; i >= 1; --i)
       for (int t = 0; t < m; ++t)
-        gt[i][t] = (gb(i - 1, t) + xr[i] * gb(i, t) - it.beta[i] * om[i] * gt[i + 1][t]) / (it.sigma[i - 1] - sg);
+        gt[i][t] = cmul(gb(i - 1, t) + cmul(xr[i], gb(i, t)) - cmul(bom[i], gt[i + 1][t]), rds[i]);
     // q_i, so that the right-hand side of eq. (nleigs-toar2) is -sum_i A_i U q_i
     for (int i = 0; i < ell; ++i)
       for (int t = 0; t < m; ++t) {
-        zc acc = DD(i, d) / it.beta[d] * gb(d - 1, t);
-        for (int q = 0; q + 1 < d; ++q) acc += DD(i, q) * gt[q + 1][t];
+        zc acc = cmul(ddl[i], gb(d - 1, t));
+        for (int q = 0; q + 1 < d; ++q) acc += cmul(DD(i, q), gt[q + 1][t]);
         Qh[(size_t)i * m + t] = c128{acc.real(), acc.imag()};
       }
     NEP_HIP(hipMemcpyAsync(dQ.p, Qh.data(), sizeof(c128) * (size_t)m * ell, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_nl_comb, grow, g256, 0, st, n, m, U, dQ.as<c128>(), ell, dZ.as<c128>(), 0);
+    hipLaunchKernelGGL(k_nl_comb, dim3(ceil_div(n, 64), ell), dim3(64), 0, st, n, m, U, dQ.as<c128>(),
+                       dZ.as<c128>(), 0);
     hipLaunchKernelGGL(k_nl_splitmv, dim3(ceil_div(n, 4)), g256, 0, st, n, ell, terms, dZ.as<c128>(), Rv);
     NEP_HIP(hipGetLastError());
-    NEP_TRY(plan.solve_rhs(st));  // y^0 = R_d(sigma)^{-1} rhs
+    NEP_TRY(solve(Rv, Yv));  // y^0 = R_d(sigma)^{-1} rhs
     double n0 = 0.0, n1 = 0.0;
     NEP_TRY(orth(Yv, m, c, n0, n1));
     const bool grow_u = n1 > kNlDep * n0;
@@ -602,25 +870,20 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
     if (grow_u) g0v[m] = n1;
     std::vector<zc> v((size_t)d * mmax, zc());
     for (int i = 0; i + 1 < d; ++i)
-      for (int t = 0; t < mn; ++t) v[(size_t)i * mmax + t] = (t < m ? gt[i + 1][t] : zc()) + bs[i] * g0v[t];
-    for (int t = 0; t < mn; ++t) v[(size_t)(d - 1) * mmax + t] = bs[d - 1] * g0v[t];
-    // Gram--Schmidt against g_1..g_{j+1} with one reorthogonalization
+      for (int t = 0; t < mn; ++t) v[(size_t)i * mmax + t] = (t < m ? gt[i + 1][t] : zc()) + cmul(bs[i], g0v[t]);
+    for (int t = 0; t < mn; ++t) v[(size_t)(d - 1) * mmax + t] = cmul(bs[d - 1], g0v[t]);
+    // Gram--Schmidt against g_1..g_{j+1} with one reorthogonalization (the
+    // blocks hold mn meaningful entries each; the rest are zero)
     std::vector<zc> hh(j + 1, zc());
     for (int pass = 0; pass < 2; ++pass) {
       std::vector<zc> hp(j + 1, zc());
+      for (int q = 0; q <= j; ++q) hp[q] = dot_blocks(G[q].data(), v.data(), d, mmax, mn);
       for (int q = 0; q <= j; ++q) {
-        zc acc;
-        for (size_t e = 0; e < v.size(); ++e) acc += std::conj(G[q][e]) * v[e];
-        hp[q] = acc;
-      }
-      for (int q = 0; q <= j; ++q) {
-        for (size_t e = 0; e < v.size(); ++e) v[e] -= G[q][e] * hp[q];
+        axpy_blocks(v.data(), G[q].data(), hp[q], d, mmax, mn);
         hh[q] += hp[q];
       }
     }
-    double nv = 0.0;
-    for (const zc& e : v) nv += std::norm(e);
-    nv = std::sqrt(nv);
+    const double nv = std::sqrt(dot_blocks(v.data(), v.data(), d, mmax, mn).real());
     for (int q = 0; q <= j; ++q) H[(size_t)j * (k + 1) + q] = hh[q];
     H[(size_t)j * (k + 1) + j + 1] = nv;
     m = mn;

@@ -151,6 +151,13 @@ class MomentsPlan {
   c128* R_mut() { return dR_.as<c128>(); }
   c128* Y_mut() { return dY_.as<c128>(); }
   const NodeArrays& nodes() const { return na_; }
+  // The factors of the plan's first (largest) matrix, for solves outside the
+  // batched solve kernels: its descriptor, the factor buffer, the row map and
+  // its diagonal-block inverses ([block][0: L, 1: U][64][64], row-major).
+  const MatDesc& mat0() const { return sorted_[0]; }
+  const void* factor_base() const { return dT_.p; }
+  const int* row_map() const { return drows_.as<int>(); }
+  const void* dinv0() const { return ddinv_.as<char>() + dinv_off_[0] * (opt.prec == NEP_PREC_FP64 ? 16 : 8); }
   const int* info() const { return dinfo_.as<int>(); }
   // Per node (global index): log|det T(z_g)| and arg det T(z_g) in (-pi, pi]
   // from the resident factors (the product of the pivots and the sign of the
