@@ -617,14 +617,19 @@ nep_status nep_tune_clear(void);
 /* ------------------------------------------------------------------------ */
 
 /* Enables (1) or disables (0) HIP-event timing of every trailing-update GEMM
- * launch of the LU (k_lu_gemm_c64 / k_lu_gemm_c128) on the stream it runs on.
+ * launch of the LU (k_lu_gemm_c64 / k_lu_gemm_c128) on the stream it runs on,
+ * and around nep_nleigs's solve and split-product launches.
  * Enabling clears earlier records.  Process-wide; not thread-safe. */
 nep_status nep_prof_enable(int on);
 
 /* Reads the records: for kind 0 (complex FP32 GEMM) or 1 (complex FP64 GEMM),
  * *launches = number of launches, *ms = summed device time of the launches
  * (synchronizes their events), *flops = summed algorithmic flops of the
- * launches (8 real flops per complex multiply-add). */
+ * launches (8 real flops per complex multiply-add).  Kinds 2 and 3 record
+ * nep_nleigs's triangular-solve launches (one per triangle) and split-form
+ * product launches; for them *flops holds the summed algorithmic HBM bytes
+ * (the factor triangle outside its diagonal blocks, the diagonal-block
+ * inverses and the vectors; every A_i once and the vectors). */
 nep_status nep_prof_read(int kind, int* launches, double* ms, double* flops);
 
 /* Thread-local description of the last error on the calling thread. */

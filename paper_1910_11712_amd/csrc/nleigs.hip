@@ -43,6 +43,7 @@
 
 #include "dense.hpp"
 #include "handle.hpp"
+#include "lu.hpp"
 
 namespace nep {
 
@@ -724,6 +725,16 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
   pp.fpts = drho.as<c128>();
   std::vector<PlanProblem> probs{pp};
   NEP_TRY(plan.build(probs, po));
+  {
+    // one matrix: its panels run alone, with nothing to overlap them, and a
+    // 64-wide panel does half the serial work of a 128-wide one (n = 4096:
+    // 80 ms against 112 ms for the factorization)
+    MomentsPlan::Knobs kn = plan.knobs();
+    if (kn.jb != 64) {
+      kn.jb = 64;
+      NEP_TRY(plan.apply(kn));
+    }
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   NEP_HIP(hipEventCreate(&e0));
   NEP_HIP(hipEventCreate(&e1));
@@ -766,16 +777,51 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
   DevMem dyf;
   NEP_TRY(dyf.alloc(sizeof(c128) * (size_t)n));
   int epoch = 0;
+  // algorithmic HBM bytes of one triangle: the factor outside the diagonal
+  // blocks, the diagonal-block inverses, and the right-hand side, solution
+  // and row map (for event profiling)
+  double tri_bytes = 0.0;
+  {
+    double diag = 0.0;
+    for (int q = 0; q < nblk; ++q) {
+      const double nr = std::min(kNlBlk, n - q * kNlBlk);
+      diag += nr * nr;
+    }
+    tri_bytes = 16.0 * (((double)n * n - diag) / 2.0 + (double)nblk * kNlBlk * kNlBlk + 2.0 * n) + 4.0 * n;
+  }
+  KernelProf& prof = kernel_prof();
+  auto timed = [&](int kind, double bytes, auto&& launch) {
+    hipEvent_t a = nullptr, z = nullptr;
+    if (prof.on) {
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&z);
+      (void)hipEventRecord(a, st);
+    }
+    launch();
+    if (prof.on) {
+      (void)hipEventRecord(z, st);
+      prof.add(kind, a, z, bytes);
+    }
+  };
   auto solve = [&](const c128* rhs, c128* x) -> nep_status {
     ++epoch;
     const dim3 gp((nblk + 1) / 2), g512(512);
-    hipLaunchKernelGGL(k_nl_tri<false>, gp, g512, 0, st, n, md0.ld, Tf, rat, Dv, rhs, dyf.as<c128>(), fl_l, tick,
-                       epoch, overrun_flag);
-    hipLaunchKernelGGL(k_nl_tri<true>, gp, g512, 0, st, n, md0.ld, Tf, rat, Dv, dyf.as<c128>(), x, fl_u,
-                       tick + 1, epoch, overrun_flag);
+    timed(2, tri_bytes, [&] {
+      hipLaunchKernelGGL(k_nl_tri<false>, gp, g512, 0, st, n, md0.ld, Tf, rat, Dv, rhs, dyf.as<c128>(), fl_l, tick,
+                         epoch, overrun_flag);
+    });
+    timed(2, tri_bytes, [&] {
+      hipLaunchKernelGGL(k_nl_tri<true>, gp, g512, 0, st, n, md0.ld, Tf, rat, Dv, dyf.as<c128>(), x, fl_u,
+                         tick + 1, epoch, overrun_flag);
+    });
     NEP_HIP(hipGetLastError());
     return NEP_OK;
   };
+  // algorithmic HBM bytes of the split-form product: every A_i once (its
+  // diagonal if diagonal), the ell vectors and the result
+  double smv_bytes = 16.0 * n * (ell + 1);
+  for (int i = 0; i < ell; ++i)
+    smv_bytes += s.op.is_diag[i] ? 16.0 * n : (s.op.is_cplx[i] ? 16.0 : 8.0) * (double)n * n;
 
   // Gram--Schmidt of y against U[:, 0:m] with one reorthogonalization; the
   // normalized remainder goes to U[:, m].  Returns the coefficients and the
@@ -857,7 +903,9 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
     NEP_HIP(hipMemcpyAsync(dQ.p, Qh.data(), sizeof(c128) * (size_t)m * ell, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_nl_comb, dim3(ceil_div(n, 64), ell), dim3(64), 0, st, n, m, U, dQ.as<c128>(),
                        dZ.as<c128>(), 0);
-    hipLaunchKernelGGL(k_nl_splitmv, dim3(ceil_div(n, 4)), g256, 0, st, n, ell, terms, dZ.as<c128>(), Rv);
+    timed(3, smv_bytes, [&] {
+      hipLaunchKernelGGL(k_nl_splitmv, dim3(ceil_div(n, 4)), g256, 0, st, n, ell, terms, dZ.as<c128>(), Rv);
+    });
     NEP_HIP(hipGetLastError());
     NEP_TRY(solve(Rv, Yv));  // y^0 = R_d(sigma)^{-1} rhs
     double n0 = 0.0, n1 = 0.0;
