@@ -463,6 +463,24 @@ nep_status nep_nleigs_interp(nep_split h, const nep_contour* g, const nep_nleigs
 nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* o, const void* W0, int* m,
                       double* lambda, void* X, double* eta, double* H, nep_nleigs_info* info);
 
+/* nep_nleigs over nprob problems at once: every problem's own interpolant,
+ * shift and starting block, with the factorizations of the R_d(sigma_p) in
+ * one batched complex FP64 LU and each Arnoldi step's solves for all problems
+ * in one batched solve (the moment plan's kernels over one node per problem);
+ * the split products, Gram--Schmidt and Ritz vectors are batched over the
+ * problems too.  The pairs returned per problem are those nep_nleigs returns.
+ *   h, g, o, W0, X: arrays of nprob (1..4096); o[p].k and o[p].max_eigs must
+ *     equal o[0]'s.  W0[p]: device, complex n_p x dmax_p (as in nep_nleigs).
+ *   m: host, nprob ints.  lambda: host, 2 * nprob * max_eigs doubles, problem
+ *     p's at lambda + 2 p max_eigs.  eta: host, nprob * max_eigs, problem p's
+ *     at eta + p max_eigs.  X[p]: device, complex n_p x max_eigs.
+ *   info: optional, nprob entries (the ms fields are the whole call's).
+ * Errors name the problem.  Runs on the first handle's stream; synchronous.
+ * Allocates device memory. */
+nep_status nep_nleigs_batch(int nprob, const nep_split* h, const nep_contour* g, const nep_nleigs_opts* o,
+                            const void* const* W0, int* m, double* lambda, void* const* X, double* eta,
+                            nep_nleigs_info* info);
+
 /* ------------------------------------------------------------------------ */
 /* Batched moments: many problems of uneven n in one plan                    */
 /* ------------------------------------------------------------------------ */

@@ -179,6 +179,9 @@ def lib():
                                         C.POINTER(ip), dp, dp, dp, dp]
         L.nep_nleigs.argtypes = [vp, C.POINTER(nep_contour), C.POINTER(nep_nleigs_opts), vp, C.POINTER(ip), dp,
                                  vp, dp, dp, C.POINTER(nep_nleigs_info)]
+        L.nep_nleigs_batch.argtypes = [ip, C.POINTER(vp), C.POINTER(nep_contour), C.POINTER(nep_nleigs_opts),
+                                       C.POINTER(vp), C.POINTER(ip), dp, C.POINTER(vp), dp,
+                                       C.POINTER(nep_nleigs_info)]
         _lib = L
     return _lib
 
@@ -669,4 +672,38 @@ def nep_nleigs(h, contour, W0, X, sigma, k, dmax=50, npts=1024, tol=0.0, xi=(), 
     out = ((lam[0::2] + 1j * lam[1::2])[:q], eta[:q], info.as_dict())
     if want_H:
         out = out + ((H[0::2] + 1j * H[1::2]).reshape(k, k + 1).T,)
+    return out
+
+
+def nep_nleigs_batch(hs, contours, W0s, Xs, sigmas, k, dmax=50, npts=1024, tol=0.0, xis=None, eta_tol=0.0,
+                     max_eigs=16):
+    """NLEIGS over many problems in one call.  hs: handles; contours, sigmas,
+    xis (singularity points per problem, or None), W0s (device tensors
+    (dmax, n_p)) and Xs (device tensors (max_eigs, n_p)) per problem.
+    Returns a list of (lam, eta, info dict) per problem."""
+    P = len(hs)
+    xis = xis if xis is not None else [()] * P
+    opts = (nep_nleigs_opts * P)()
+    keep = []
+    for p in range(P):
+        o, xa = _nleigs_opts(sigmas[p], k, dmax, npts, tol, xis[p], eta_tol, max_eigs)
+        opts[p] = o
+        keep.append(xa)
+    harr = (C.c_void_p * P)(*[hh.value if isinstance(hh, C.c_void_p) else hh for hh in hs])
+    garr = (nep_contour * P)(*[contour_struct(c) for c in contours])
+    warr = (C.c_void_p * P)(*[w.data_ptr() for w in W0s])
+    xarr = (C.c_void_p * P)(*[x.data_ptr() for x in Xs])
+    m = (C.c_int * P)()
+    lam = np.zeros(2 * P * max_eigs)
+    eta = np.zeros(P * max_eigs)
+    info = (nep_nleigs_info * P)()
+    dp = C.POINTER(C.c_double)
+    check(lib().nep_nleigs_batch(P, harr, garr, opts, warr, m, lam.ctypes.data_as(dp), xarr,
+                                 eta.ctypes.data_as(dp), info))
+    del keep
+    out = []
+    for p in range(P):
+        q = m[p]
+        lp = lam[2 * p * max_eigs:2 * (p + 1) * max_eigs]
+        out.append(((lp[0::2] + 1j * lp[1::2])[:q], eta[p * max_eigs:p * max_eigs + q].copy(), info[p].as_dict()))
     return out

@@ -39,9 +39,11 @@
 #include <cmath>
 #include <complex>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "dense.hpp"
+#include "fn_device.hpp"
 #include "handle.hpp"
 #include "lu.hpp"
 
@@ -357,20 +359,18 @@ __global__ __launch_bounds__(256) void k_nl_store(int n, const c128* y, const do
   u[r] = s * y[r];
 }
 
-// X[:, q] = U[:, 0:m] S[:, q], scaled to 2-norm 1 with its largest-modulus
-// entry (lowest index among equals) real and positive.  One group per column.
-__global__ __launch_bounds__(256) void k_nl_vectors(int n, int m, const c128* __restrict__ U,
-                                                    const c128* __restrict__ S, c128* __restrict__ X) {
+// x = U[:, 0:m] s, scaled to 2-norm 1 with its largest-modulus entry (lowest
+// index among equals) real and positive: the body of one 256-thread group.
+__device__ void nl_vector(int n, int m, const c128* __restrict__ U, const c128* __restrict__ s,
+                          c128* __restrict__ x) {
   __shared__ c128 red[4];
   __shared__ double wmax[4];
   __shared__ int widx[4];
-  const int q = blockIdx.x;
-  c128* x = X + (long long)q * n;
   double ss = 0.0, bm = -1.0;
   int bi = 0x7fffffff;
   for (int r = threadIdx.x; r < n; r += 256) {
     c128 acc = {0.0, 0.0};
-    for (int t = 0; t < m; ++t) acc = acc + U[(long long)t * n + r] * S[(long long)q * m + t];
+    for (int t = 0; t < m; ++t) acc = acc + U[(long long)t * n + r] * s[t];
     x[r] = acc;
     const double a2 = norm2(acc);
     ss += a2;
@@ -405,6 +405,246 @@ __global__ __launch_bounds__(256) void k_nl_vectors(int n, int m, const c128* __
   const c128 sc = (ap > 0.0 && nrm > 0.0) ? c128{piv.re / (ap * nrm), -piv.im / (ap * nrm)} : c128{0.0, 0.0};
   __syncthreads();
   for (int r = threadIdx.x; r < n; r += 256) x[r] = sc * x[r];
+}
+
+// X[:, q] = U[:, 0:m] S[:, q] (normalized as above): one group per column
+__global__ __launch_bounds__(256) void k_nl_vectors(int n, int m, const c128* __restrict__ U,
+                                                    const c128* __restrict__ S, c128* __restrict__ X) {
+  nl_vector(n, m, U, S + (long long)blockIdx.x * m, X + (long long)blockIdx.x * n);
+}
+
+// ---------------------------------------------------------------------------
+// Batched NLEIGS: one run over many problems at once.  Every problem has its
+// own basis U_p, terms and sizes (descriptor below); the per-step basis size
+// m_p comes from a device array (negative: the problem takes no part).  The
+// factorizations and solves are the moment plan's batched LU and solve
+// kernels over one node per problem.
+// ---------------------------------------------------------------------------
+struct NlbProb {
+  int n, ell;
+  long long offU;  // U_p: column-major n x (mmax+1) at U + offU
+  long long offZ;  // U_p q_i: n x ell at Z + offZ
+  long long offY;  // right-hand side (R) and solution (Y) in the plan's buffers
+  NlTerms t;
+  const double* normA;  // ell infinity norms
+  const FnNode* fn_nodes;
+  const c128* fn_coef;
+  int fn_root[kMaxTerms];
+};
+
+// Z_p[:, c] = U_p[:, 0:m_p] Q_p[:, c], c < ell_p; Q_p at Q + p * qstride
+__global__ __launch_bounds__(64) void k_nlb_rhs(const NlbProb* __restrict__ pb, const int* __restrict__ dm,
+                                                const c128* __restrict__ U, const c128* __restrict__ Q,
+                                                long long qstride, c128* __restrict__ Z) {
+  const int p = blockIdx.z, c = blockIdx.y, r = blockIdx.x * 64 + threadIdx.x;
+  const NlbProb& P = pb[p];
+  const int m = dm[p];
+  if (m < 0 || c >= P.ell || r >= P.n) return;
+  const c128* u = U + P.offU + r;
+  const c128* q = Q + p * qstride + (long long)c * m;
+  c128 a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
+  int t = 0;
+  for (; t + 1 < m; t += 2) {
+    a0 = a0 + u[(long long)t * P.n] * q[t];
+    a1 = a1 + u[(long long)(t + 1) * P.n] * q[t + 1];
+  }
+  if (t < m) a0 = a0 + u[(long long)t * P.n] * q[t];
+  Z[P.offZ + (long long)c * P.n + r] = a0 + a1;
+}
+
+// R_p = -sum_i A_i Z_p[:, i]: one wavefront per row, four rows per group
+__global__ __launch_bounds__(256) void k_nlb_splitmv(const NlbProb* __restrict__ pb, const int* __restrict__ dm,
+                                                     const c128* __restrict__ Z, c128* __restrict__ R) {
+  const int p = blockIdx.y;
+  const NlbProb& P = pb[p];
+  const int lane = threadIdx.x & 63, r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (dm[p] < 0 || r >= P.n) return;
+  const int n = P.n;
+  c128 acc = {0.0, 0.0};
+  for (int i = 0; i < P.ell; ++i) {
+    const c128* z = Z + P.offZ + (long long)i * n;
+    if (P.t.isdiag[i]) {
+      if (lane == 0) acc = acc + P.t.diag[i][r] * z[r];
+    } else if (P.t.cplx[i]) {
+      const c128* a = reinterpret_cast<const c128*>(P.t.A[i]) + (long long)r * n;
+      for (int c = lane; c < n; c += 64) acc = acc + a[c] * z[c];
+    } else {
+      const double* a = reinterpret_cast<const double*>(P.t.A[i]) + (long long)r * n;
+      for (int c = lane; c < n; c += 64) {
+        const double v = a[c];
+        const c128 zc = z[c];
+        acc.re += v * zc.re;
+        acc.im += v * zc.im;
+      }
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) R[P.offY + r] = -acc;
+}
+
+// h_p[t] = U_p[:, t]^H y_p, t < m_p: one group per (column, problem)
+__global__ __launch_bounds__(256) void k_nlb_dots(const NlbProb* __restrict__ pb, const int* __restrict__ dm,
+                                                  const c128* __restrict__ U, c128* const* __restrict__ yp,
+                                                  c128* __restrict__ h, long long hstride) {
+  __shared__ c128 red[4];
+  const int p = blockIdx.y, t = blockIdx.x;
+  const NlbProb& P = pb[p];
+  if (t >= dm[p]) return;  // group-uniform (dm < 0: done)
+  const c128* u = U + P.offU + (long long)t * P.n;
+  const c128* y = yp[p];
+  c128 acc = {0.0, 0.0};
+  for (int r = threadIdx.x; r < P.n; r += 256) acc = acc + conj(u[r]) * y[r];
+  const c128 sum = group_sum(acc, red);
+  if (threadIdx.x == 0) h[p * hstride + t] = sum;
+}
+
+// y_p -= U_p[:, 0:m_p] h_p
+__global__ __launch_bounds__(64) void k_nlb_sub(const NlbProb* __restrict__ pb, const int* __restrict__ dm,
+                                                const c128* __restrict__ U, const c128* __restrict__ h,
+                                                long long hstride, c128* const* __restrict__ yp) {
+  const int p = blockIdx.y, r = blockIdx.x * 64 + threadIdx.x;
+  const NlbProb& P = pb[p];
+  const int m = dm[p];
+  if (m <= 0 || r >= P.n) return;
+  const c128* u = U + P.offU + r;
+  const c128* q = h + p * hstride;
+  c128 a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
+  int t = 0;
+  for (; t + 1 < m; t += 2) {
+    a0 = a0 + u[(long long)t * P.n] * q[t];
+    a1 = a1 + u[(long long)(t + 1) * P.n] * q[t + 1];
+  }
+  if (t < m) a0 = a0 + u[(long long)t * P.n] * q[t];
+  c128* y = yp[p] + r;
+  *y = *y - (a0 + a1);
+}
+
+// nrm[p * nstride + slot] = ||y_p||_2: one group per problem
+__global__ __launch_bounds__(256) void k_nlb_norm(const NlbProb* __restrict__ pb, const int* __restrict__ dm,
+                                                  c128* const* __restrict__ yp, double* __restrict__ nrm,
+                                                  long long nstride, int slot) {
+  __shared__ c128 red[4];
+  const int p = blockIdx.x;
+  const NlbProb& P = pb[p];
+  if (dm[p] < 0) return;
+  const c128* y = yp[p];
+  double acc = 0.0;
+  for (int r = threadIdx.x; r < P.n; r += 256) acc += norm2(y[r]);
+  const c128 sum = group_sum(c128{acc, 0.0}, red);
+  if (threadIdx.x == 0) nrm[p * nstride + slot] = sqrt(sum.re);
+}
+
+// U_p[:, m_p] = y_p / nrm (y_p may be that column)
+__global__ __launch_bounds__(256) void k_nlb_store(const NlbProb* __restrict__ pb, const int* __restrict__ dm,
+                                                   c128* U, c128* const* __restrict__ yp, const double* __restrict__ nrm,
+                                                   long long nstride) {
+  const int p = blockIdx.y, r = blockIdx.x * 256 + threadIdx.x;
+  const NlbProb& P = pb[p];
+  const int m = dm[p];
+  if (m < 0 || r >= P.n) return;
+  const double v = nrm[p * nstride + 1];
+  const double sc = v > 0.0 ? 1.0 / v : 0.0;
+  U[P.offU + (long long)m * P.n + r] = sc * yp[p][r];
+}
+
+// One Ritz pair of a batched run: its problem, eigenvalue, the offset of its
+// coefficients on U_p and of its vector in the work buffer.
+struct NlbPair {
+  int p, m;
+  c128 lam;
+  long long soff, xoff;
+};
+
+// X[:, a] = U_p S_a, scaled to 2-norm 1 with its largest-modulus entry (lowest
+// index among equals) real and positive; one group per pair
+__global__ __launch_bounds__(256) void k_nlb_vectors(const NlbProb* __restrict__ pb, const NlbPair* __restrict__ pr,
+                                                     const c128* __restrict__ U, const c128* __restrict__ S,
+                                                     c128* __restrict__ X) {
+  const NlbPair a = pr[blockIdx.x];
+  nl_vector(pb[a.p].n, a.m, U + pb[a.p].offU, S + a.soff, X + a.xoff);
+}
+
+// Backward error of eq. (sressplit) for one pair per group: the row maxima of
+// |T(lambda) x| and |x| and sum_i |f_i(lambda)| ||A_i||_inf (f_i on the
+// device, NaN if lambda lies on a pole or cut)
+__global__ __launch_bounds__(256) void k_nlb_eta(const NlbProb* __restrict__ pb, const NlbPair* __restrict__ pr,
+                                                 const c128* __restrict__ X, double* __restrict__ eta) {
+  __shared__ double red[4];
+  __shared__ double xr_[4];
+  const NlbPair a = pr[blockIdx.x];
+  const NlbProb& P = pb[a.p];
+  const int n = P.n, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  c128 f[kMaxTerms];
+  int bad = 0;
+  double den = 0.0;
+  for (int i = 0; i < P.ell; ++i) {
+    f[i] = fn_eval(P.fn_nodes, P.fn_coef, P.fn_root[i], a.lam, bad);
+    den += sqrt(norm2(f[i])) * P.normA[i];
+  }
+  const c128* x = X + a.xoff;
+  double rmax = 0.0, xmax = 0.0;
+  for (int r = w; r < n; r += 4) {
+    c128 acc = {0.0, 0.0};
+    for (int i = 0; i < P.ell; ++i) {
+      c128 ai = {0.0, 0.0};
+      if (P.t.isdiag[i]) {
+        if (lane == 0) ai = P.t.diag[i][r] * x[r];
+      } else if (P.t.cplx[i]) {
+        const c128* A = reinterpret_cast<const c128*>(P.t.A[i]) + (long long)r * n;
+        for (int c = lane; c < n; c += 64) ai = ai + A[c] * x[c];
+      } else {
+        const double* A = reinterpret_cast<const double*>(P.t.A[i]) + (long long)r * n;
+        for (int c = lane; c < n; c += 64) {
+          const double v = A[c];
+          ai.re += v * x[c].re;
+          ai.im += v * x[c].im;
+        }
+      }
+      acc = acc + f[i] * ai;
+    }
+    acc = wave_sum(acc);
+    rmax = nanmax(rmax, sqrt(norm2(acc)));
+    if (lane == 0) xmax = nanmax(xmax, sqrt(norm2(x[r])));
+  }
+  if (lane == 0) {
+    red[w] = rmax;
+    xr_[w] = xmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double rm = 0.0, xm = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      rm = nanmax(rm, red[i]);
+      xm = nanmax(xm, xr_[i]);
+    }
+    const double dd = den * xm;
+    eta[blockIdx.x] = (bad || !(dd > 0.0)) ? NAN : rm / dd;
+  }
+}
+
+// f_i(z_pj) for every problem p and node j < stride, one thread each:
+// out[(p * kMaxTerms + i) * stride + j], bad[p * stride + j]
+__global__ __launch_bounds__(64) void k_nlb_fn(const NlbProb* __restrict__ pb, int nprob, int stride,
+                                               const c128* __restrict__ z, c128* __restrict__ out,
+                                               int* __restrict__ bad) {
+  const int e = blockIdx.x * 64 + threadIdx.x;
+  const int p = e / stride, j = e - p * stride;
+  if (p >= nprob) return;
+  const NlbProb& P = pb[p];
+  int b = 0;
+  for (int i = 0; i < P.ell; ++i)
+    out[((long long)p * kMaxTerms + i) * stride + j] = fn_eval(P.fn_nodes, P.fn_coef, P.fn_root[i], z[e], b);
+  bad[e] = b;
+}
+
+// Y_dst[a] = X[:, a] for the kept pairs: one group per pair
+__global__ __launch_bounds__(256) void k_nlb_gather(const NlbPair* __restrict__ pr, const int* __restrict__ keep,
+                                                    c128* const* __restrict__ dst, const c128* __restrict__ X,
+                                                    const NlbProb* __restrict__ pb) {
+  const NlbPair a = pr[keep[blockIdx.x]];
+  const int n = pb[a.p].n;
+  c128* out = dst[blockIdx.x];
+  for (int r = threadIdx.x; r < n; r += 256) out[r] = X[a.xoff + r];
 }
 
 // ---------------------------------------------------------------------------
@@ -445,11 +685,22 @@ double mag(zc x) {
   return std::isnan(a) ? INFINITY : a;
 }
 
-nep_status interp_build(Split& s, const nep_contour& g, const nep_nleigs_opts& o, Interp& it) {
+// The interpolant in two phases around the evaluation of the f_i at the
+// nodes (done on the device, for one problem or for a batch at once).
+struct InterpWork {
+  int npts = 0, dmax = 0;
+  double tol = 0.0;
+  std::vector<zc> zb, sig, xi;
+  std::vector<int> idx;
+};
+
+// Leja--Bagby nodes and poles (host)
+void interp_nodes(const nep_contour& g, const nep_nleigs_opts& o, InterpWork& w) {
   const int npts = o.npts > 0 ? o.npts : 1024;
   const int dmax = o.dmax > 0 ? o.dmax : 50;
-  const double tol = o.tol > 0.0 ? o.tol : 1e-12;
-  const int ell = s.op.ell;
+  w.npts = npts;
+  w.dmax = dmax;
+  w.tol = o.tol > 0.0 ? o.tol : 1e-12;
   // boundary of the region
   const double v = g.kind == 1 ? g.v : 1.0;
   std::vector<zc> zb(npts);
@@ -491,11 +742,21 @@ nep_status interp_build(Split& s, const nep_contour& g, const nep_nleigs_opts& o
     for (size_t k = 0; k < xs.size(); ++k)
       if (!used[k]) sx[k] = sx[k] * (xs[k] - sig.back()) / pole_factor(xs[k], xn);
   }
-  // f_i at the nodes (device evaluation of the FN trees)
-  std::vector<c128> zn(dmax + 1), fv;
-  std::vector<int> bad;
-  for (int j = 0; j <= dmax; ++j) zn[j] = c128{sig[j].real(), sig[j].imag()};
-  NEP_TRY(s.eval_fns(dmax + 1, zn.data(), fv, bad, false));
+  w.zb = std::move(zb);
+  w.sig = std::move(sig);
+  w.xi = std::move(xi);
+  w.idx = std::move(idx);
+}
+
+// basis scaling, divided differences from f_i at the nodes (fv: ell x
+// (dmax+1), fv[i * (dmax+1) + j] = f_i(sigma_j)), degree, last pole at infinity
+nep_status interp_finish(const InterpWork& w, int ell, const c128* fv, const int* bad, Interp& it) {
+  const int npts = w.npts, dmax = w.dmax;
+  const double tol = w.tol;
+  const std::vector<zc>& zb = w.zb;
+  const std::vector<zc>& sig = w.sig;
+  const std::vector<zc>& xi = w.xi;
+  const std::vector<int>& idx = w.idx;
   for (int j = 0; j <= dmax; ++j)
     NEP_CHECK(!bad[j], NEP_ERR_NOT_HOLOMORPHIC, "interpolation node %d lies on a pole or branch cut", j);
   auto f = [&](int i, int j) { return zc(fv[(size_t)i * (dmax + 1) + j].re, fv[(size_t)i * (dmax + 1) + j].im); };
@@ -556,6 +817,16 @@ nep_status interp_build(Split& s, const nep_contour& g, const nep_nleigs_opts& o
   return NEP_OK;
 }
 
+nep_status interp_build(Split& s, const nep_contour& g, const nep_nleigs_opts& o, Interp& it) {
+  InterpWork w;
+  interp_nodes(g, o, w);
+  std::vector<c128> zn(w.dmax + 1), fv;
+  std::vector<int> bad;
+  for (int j = 0; j <= w.dmax; ++j) zn[j] = c128{w.sig[j].real(), w.sig[j].imag()};
+  NEP_TRY(s.eval_fns(w.dmax + 1, zn.data(), fv, bad, false));
+  return interp_finish(w, s.op.ell, fv.data(), bad.data(), it);
+}
+
 // b_0(z)..b_d(z) of the interpolant
 std::vector<zc> basis_at(const Interp& it, zc z) {
   std::vector<zc> b(it.d + 1);
@@ -596,6 +867,170 @@ void axpy_blocks(zc* v, const zc* g, zc h, int d, int ld, int len) {
       x[t + 1] -= y[t] * hi + y[t + 1] * hr;
     }
   }
+}
+
+// fn(p) for p < count on a few host threads (the per-problem coefficient work
+// of a batched run)
+template <typename F>
+void parallel_for(int count, F&& fn) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nt = std::min<int>({16, (int)hw, (count + 7) / 8});
+  if (nt <= 1) {
+    for (int p = 0; p < count; ++p) fn(p);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(nt);
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t] {
+      for (int p = t; p < count; p += nt) fn(p);
+    });
+  for (auto& x : th) x.join();
+}
+
+// Host side of Arnoldi in the TOAR representation for one problem: the
+// coefficient recurrences of eqs. (nleigs-toar1), (nleigs-toar4), the
+// coefficients of the right-hand side of eq. (nleigs-toar2) per term, and the
+// Gram--Schmidt of the coefficient vectors (Algorithm "Arnoldi for NLEIGS with
+// TOAR representation").  G holds g_1, g_2, ...: d blocks of mmax entries
+// (the first m meaningful), H the (k+1) x k Hessenberg matrix.
+struct ToarHost {
+  int d = 0, k = 0, ell = 0, mmax = 0, m = 0, kd = 0;
+  double hlast = 0.0;
+  bool done = false;  // breakdown (invariant subspace) or k steps
+  zc sg;
+  std::vector<zc> bs, xr, rds, bom, ddl, dd;
+  std::vector<std::vector<zc>> G, gt;
+  std::vector<zc> H;
+
+  void init(const Interp& it, zc sigma, int nterms, int ksteps) {
+    d = it.d;
+    k = ksteps;
+    ell = nterms;
+    mmax = d + k;
+    sg = sigma;
+    bs = basis_at(it, sg);
+    dd = it.dd;
+    xr.assign(d + 1, zc());
+    rds.assign(d, zc());
+    bom.assign(d, zc());
+    ddl.assign(ell, zc());
+    for (int j = 1; j <= d; ++j) {
+      const zc om = inf_pole(it.xi[j]) ? zc(1.0, 0.0) : zc(1.0, 0.0) - sg / it.xi[j];
+      xr[j] = inf_pole(it.xi[j]) ? zc() : it.beta[j] / it.xi[j];
+      if (j < d) {
+        rds[j] = 1.0 / (it.sigma[j - 1] - sg);
+        bom[j] = it.beta[j] * om;
+      }
+    }
+    for (int i = 0; i < ell; ++i) ddl[i] = dd[(size_t)i * (d + 1) + d] / it.beta[d];
+    gt.assign(d, std::vector<zc>(mmax));
+    H.assign((size_t)(k + 1) * k, zc());
+    G.clear();
+  }
+  // coefficients rho_i of R_d(sigma) = sum_i rho_i A_i
+  void rho(c128* out) const {
+    for (int i = 0; i < ell; ++i) {
+      zc acc;
+      for (int j = 0; j <= d; ++j) acc += bs[j] * dd[(size_t)i * (d + 1) + j];
+      out[i] = c128{acc.real(), acc.imag()};
+    }
+  }
+  // g_1 = vec(R) / ||vec(R)|| from the Gram--Schmidt QR of the starting
+  // block: R[q * d + t] = coefficient of w^q on basis vector t
+  void start(const std::vector<zc>& R) {
+    G.assign(1, std::vector<zc>((size_t)d * mmax, zc()));
+    double fro = 0.0;
+    for (const zc& v : R) fro += std::norm(v);
+    fro = std::sqrt(fro);
+    for (int q = 0; q < d; ++q)
+      for (int t = 0; t < d; ++t) G[0][(size_t)q * mmax + t] = R[(size_t)q * d + t] / fro;
+    m = d;
+  }
+  // step j: Q (m x ell, column-major) such that the right-hand side of eq.
+  // (nleigs-toar2) is -sum_i A_i U q_i
+  void rhs(int j, c128* Q) {
+    const std::vector<zc>& gj = G[j];
+    auto gb = [&](int i, int t) { return gj[(size_t)i * mmax + t]; };
+    for (int t = 0; t < m; ++t)
+      gt[d - 1][t] = cmul(gb(d - 2, t) + cmul(xr[d - 1], gb(d - 1, t)), rds[d - 1]);
+    for (int i = d - 2; i >= 1; --i)
+      for (int t = 0; t < m; ++t)
+        gt[i][t] = cmul(gb(i - 1, t) + cmul(xr[i], gb(i, t)) - cmul(bom[i], gt[i + 1][t]), rds[i]);
+    for (int i = 0; i < ell; ++i)
+      for (int t = 0; t < m; ++t) {
+        zc acc = cmul(ddl[i], gb(d - 1, t));
+        for (int q = 0; q + 1 < d; ++q) acc += cmul(dd[(size_t)i * (d + 1) + q], gt[q + 1][t]);
+        Q[(size_t)i * m + t] = c128{acc.real(), acc.imag()};
+      }
+  }
+  // step j: y^0 = U c + n1 u (u the new basis vector unless y^0 was
+  // dependent); forms g (eq. (nleigs-toar4)), orthogonalizes it against
+  // g_1..g_{j+1} and appends g_{j+2} and column j of H
+  void absorb(int j, const std::vector<zc>& c, double n0, double n1) {
+    const bool grow_u = n1 > kNlDep * n0;
+    const int mn = m + (grow_u ? 1 : 0);
+    std::vector<zc> g0v(mn, zc());
+    for (int t = 0; t < m; ++t) g0v[t] = c[t];
+    if (grow_u) g0v[m] = n1;
+    std::vector<zc> v((size_t)d * mmax, zc());
+    for (int i = 0; i + 1 < d; ++i)
+      for (int t = 0; t < mn; ++t) v[(size_t)i * mmax + t] = (t < m ? gt[i + 1][t] : zc()) + cmul(bs[i], g0v[t]);
+    for (int t = 0; t < mn; ++t) v[(size_t)(d - 1) * mmax + t] = cmul(bs[d - 1], g0v[t]);
+    std::vector<zc> hh(j + 1, zc());
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<zc> hp(j + 1, zc());
+      for (int q = 0; q <= j; ++q) hp[q] = dot_blocks(G[q].data(), v.data(), d, mmax, mn);
+      for (int q = 0; q <= j; ++q) {
+        axpy_blocks(v.data(), G[q].data(), hp[q], d, mmax, mn);
+        hh[q] += hp[q];
+      }
+    }
+    const double nv = std::sqrt(dot_blocks(v.data(), v.data(), d, mmax, mn).real());
+    for (int q = 0; q <= j; ++q) H[(size_t)j * (k + 1) + q] = hh[q];
+    H[(size_t)j * (k + 1) + j + 1] = nv;
+    m = mn;
+    kd = j + 1;
+    hlast = nv;
+    if (!(nv > 0.0) || kd == k) {  // invariant subspace, or the last step
+      done = true;
+      if (!(nv > 0.0)) return;
+    }
+    for (zc& e : v) e /= nv;
+    G.push_back(std::move(v));
+  }
+  // Ritz values lambda = sigma + 1/theta of H_kd; S: the eigenvectors
+  // (kd x kd, column-major)
+  bool ritz(std::vector<zc>& lam, std::vector<zc>& S) const {
+    std::vector<zc> Hk((size_t)kd * kd), th;
+    for (int q = 0; q < kd; ++q)
+      for (int r = 0; r < kd; ++r) Hk[(size_t)q * kd + r] = H[(size_t)q * (k + 1) + r];
+    if (!eig_general(kd, Hk, th, S)) return false;
+    lam.assign(kd, zc(INFINITY, 0.0));
+    for (int q = 0; q < kd; ++q)
+      if (th[q] != zc(0.0, 0.0)) lam[q] = sg + 1.0 / th[q];
+    return true;
+  }
+  // coefficients of the first block of Ritz vector q on U: G^0 s / ||s||
+  void ritz_coeffs(const std::vector<zc>& S, int q, c128* out) const {
+    double sn = 0.0;
+    for (int r = 0; r < kd; ++r) sn += std::norm(S[(size_t)q * kd + r]);
+    sn = std::sqrt(sn);
+    for (int t = 0; t < m; ++t) {
+      zc acc;
+      for (int r = 0; r < kd; ++r) acc += cmul(G[r][t], S[(size_t)q * kd + r]);
+      acc /= sn;
+      out[t] = c128{acc.real(), acc.imag()};
+    }
+  }
+};
+
+// inside the region g (circle or ellipse)
+bool inside_region(const nep_contour& g, zc z) {
+  const double v = g.kind == 1 ? g.v : 1.0;
+  const zc mu = (z - zc(g.c[0], g.c[1])) / g.rho;
+  const double r2 = mu.real() * mu.real() + (mu.imag() / v) * (mu.imag() / v);
+  return std::isfinite(r2) && r2 < 1.0;
 }
 
 nep_status check_nleigs_opts(const nep_nleigs_opts* o) {
@@ -667,20 +1102,10 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
     NEP_CHECK(it.sigma[j] != sg, NEP_ERR_ARG, "the shift equals interpolation node %d", j);
   for (int j = 1; j <= d; ++j)
     NEP_CHECK(inf_pole(it.xi[j]) || it.xi[j] != sg, NEP_ERR_ARG, "the shift equals pole %d", j);
-  const std::vector<zc> bs = basis_at(it, sg);
-  auto DD = [&](int i, int j) { return it.dd[(size_t)i * (d + 1) + j]; };
+  ToarHost tz;
+  tz.init(it, sg, ell, k);
   std::vector<c128> rho(ell);
-  for (int i = 0; i < ell; ++i) {
-    zc acc;
-    for (int j = 0; j <= d; ++j) acc += bs[j] * DD(i, j);
-    rho[i] = c128{acc.real(), acc.imag()};
-  }
-  // coefficient recurrences of eqs. (nleigstoarreca), (nleigs-toar1)
-  std::vector<zc> xr(d + 1), om(d + 1);
-  for (int j = 1; j <= d; ++j) {
-    xr[j] = inf_pole(it.xi[j]) ? zc() : it.beta[j] / it.xi[j];
-    om[j] = inf_pole(it.xi[j]) ? zc(1.0, 0.0) : zc(1.0, 0.0) - sg / it.xi[j];
-  }
+  tz.rho(rho.data());
 
   // device buffers
   const int mmax = d + k;  // basis columns at most
@@ -853,53 +1278,22 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
 
   // starting block: QR of [w^0 .. w^{d-1}] by Gram--Schmidt, g_1 = vec(R)/||vec(R)||
   NEP_HIP(hipMemcpyAsync(U, W0, sizeof(c128) * (size_t)n * d, hipMemcpyDeviceToDevice, st));
-  // G: column j holds g_{j+1}, block i (length mmax) at offset i * mmax
-  std::vector<std::vector<zc>> G;
-  G.emplace_back((size_t)d * mmax, zc());
   {
-    std::vector<zc> c;
-    double n0 = 0.0, n1 = 0.0, fro = 0.0;
+    std::vector<zc> c, R((size_t)d * d, zc());
+    double n0 = 0.0, n1 = 0.0;
     for (int q = 0; q < d; ++q) {
       NEP_TRY(orth(U + (long long)q * n, q, c, n0, n1));
       NEP_CHECK(n1 > kNlDep * n0 && n0 > 0.0, NEP_ERR_ARG, "starting block column %d is linearly dependent", q);
-      for (int t = 0; t < q; ++t) G[0][(size_t)q * mmax + t] = c[t];
-      G[0][(size_t)q * mmax + q] = n1;
+      for (int t = 0; t < q; ++t) R[(size_t)q * d + t] = c[t];
+      R[(size_t)q * d + q] = n1;
     }
-    for (const zc& v : G[0]) fro += std::norm(v);
-    fro = std::sqrt(fro);
-    for (zc& v : G[0]) v /= fro;
+    tz.start(R);
   }
-  int m = d;
-  std::vector<zc> H((size_t)(k + 1) * k, zc());  // column-major (k+1) x k
   std::vector<c128> Qh((size_t)(mmax + 1) * std::max(ell, 1));
-  int kd = 0;
-  double hlast = 0.0;
-  std::vector<std::vector<zc>> gt(d, std::vector<zc>(mmax));
   std::vector<zc> c;
-  // per-step constants: 1/(sigma_{i-1} - sigma), beta_i (1 - sigma/xi_i),
-  // d_i^d / beta_d
-  std::vector<zc> rds(d), bom(d), ddl(ell);
-  for (int i = 1; i < d; ++i) {
-    rds[i] = 1.0 / (it.sigma[i - 1] - sg);
-    bom[i] = it.beta[i] * om[i];
-  }
-  for (int i = 0; i < ell; ++i) ddl[i] = DD(i, d) / it.beta[d];
-  for (int j = 0; j < k; ++j) {
-    const std::vector<zc>& gj = G[j];
-    auto gb = [&](int i, int t) { return gj[(size_t)i * mmax + t]; };
-    // eq. (nleigs-toar1)
-    for (int t = 0; t < m; ++t)
-      gt[d - 1][t] = cmul(gb(d - 2, t) + cmul(xr[d - 1], gb(d - 1, t)), rds[d - 1]);
-    for (int i = d - 2; i >= 1; --i)
-      for (int t = 0; t < m; ++t)
-        gt[i][t] = cmul(gb(i - 1, t) + cmul(xr[i], gb(i, t)) - cmul(bom[i], gt[i + 1][t]), rds[i]);
-    // q_i, so that the right-hand side of eq. (nleigs-toar2) is -sum_i A_i U q_i
-    for (int i = 0; i < ell; ++i)
-      for (int t = 0; t < m; ++t) {
-        zc acc = cmul(ddl[i], gb(d - 1, t));
-        for (int q = 0; q + 1 < d; ++q) acc += cmul(DD(i, q), gt[q + 1][t]);
-        Qh[(size_t)i * m + t] = c128{acc.real(), acc.imag()};
-      }
+  for (int j = 0; j < k && !tz.done; ++j) {
+    const int m = tz.m;
+    tz.rhs(j, Qh.data());
     NEP_HIP(hipMemcpyAsync(dQ.p, Qh.data(), sizeof(c128) * (size_t)m * ell, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_nl_comb, dim3(ceil_div(n, 64), ell), dim3(64), 0, st, n, m, U, dQ.as<c128>(),
                        dZ.as<c128>(), 0);
@@ -910,71 +1304,23 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
     NEP_TRY(solve(Rv, Yv));  // y^0 = R_d(sigma)^{-1} rhs
     double n0 = 0.0, n1 = 0.0;
     NEP_TRY(orth(Yv, m, c, n0, n1));
-    const bool grow_u = n1 > kNlDep * n0;
-    const int mn = m + (grow_u ? 1 : 0);
-    // y^0 = U_{mn} g~^0; eq. (nleigs-toar4)
-    std::vector<zc> g0v(mn, zc());
-    for (int t = 0; t < m; ++t) g0v[t] = c[t];
-    if (grow_u) g0v[m] = n1;
-    std::vector<zc> v((size_t)d * mmax, zc());
-    for (int i = 0; i + 1 < d; ++i)
-      for (int t = 0; t < mn; ++t) v[(size_t)i * mmax + t] = (t < m ? gt[i + 1][t] : zc()) + cmul(bs[i], g0v[t]);
-    for (int t = 0; t < mn; ++t) v[(size_t)(d - 1) * mmax + t] = cmul(bs[d - 1], g0v[t]);
-    // Gram--Schmidt against g_1..g_{j+1} with one reorthogonalization (the
-    // blocks hold mn meaningful entries each; the rest are zero)
-    std::vector<zc> hh(j + 1, zc());
-    for (int pass = 0; pass < 2; ++pass) {
-      std::vector<zc> hp(j + 1, zc());
-      for (int q = 0; q <= j; ++q) hp[q] = dot_blocks(G[q].data(), v.data(), d, mmax, mn);
-      for (int q = 0; q <= j; ++q) {
-        axpy_blocks(v.data(), G[q].data(), hp[q], d, mmax, mn);
-        hh[q] += hp[q];
-      }
-    }
-    const double nv = std::sqrt(dot_blocks(v.data(), v.data(), d, mmax, mn).real());
-    for (int q = 0; q <= j; ++q) H[(size_t)j * (k + 1) + q] = hh[q];
-    H[(size_t)j * (k + 1) + j + 1] = nv;
-    m = mn;
-    kd = j + 1;
-    hlast = nv;
-    if (!(nv > 0.0)) break;  // invariant subspace
-    for (zc& e : v) e /= nv;
-    G.push_back(std::move(v));
+    tz.absorb(j, c, n0, n1);
   }
   const float ms_krylov = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t1).count();
 
   // Ritz pairs: theta of H_k, lambda = sigma + 1/theta, x = U G^0 s
-  std::vector<zc> Hk((size_t)kd * kd), th, S;
-  for (int q = 0; q < kd; ++q)
-    for (int r = 0; r < kd; ++r) Hk[(size_t)q * kd + r] = H[(size_t)q * (k + 1) + r];
-  NEP_CHECK(eig_general(kd, Hk, th, S), NEP_ERR_DEVICE, "eigenvalues of the Hessenberg matrix did not converge");
+  std::vector<zc> lam, S;
+  NEP_CHECK(tz.ritz(lam, S), NEP_ERR_DEVICE, "eigenvalues of the Hessenberg matrix did not converge");
+  const int kd = tz.kd, m = tz.m;
   std::vector<int> cand;
-  std::vector<zc> lam(kd);
-  const double vv = g->kind == 1 ? g->v : 1.0;
-  for (int q = 0; q < kd; ++q) {
-    if (th[q] == zc(0.0, 0.0)) continue;
-    lam[q] = sg + 1.0 / th[q];
-    const zc mu = (lam[q] - zc(g->c[0], g->c[1])) / g->rho;
-    const double r2 = mu.real() * mu.real() + (mu.imag() / vv) * (mu.imag() / vv);
-    if (r2 < 1.0 && std::isfinite(r2)) cand.push_back(q);
-  }
+  for (int q = 0; q < kd; ++q)
+    if (inside_region(*g, lam[q])) cand.push_back(q);
   int mret = 0;
   std::vector<double> et;
   if (!cand.empty()) {
     const int nc = (int)cand.size();
     std::vector<c128> Sx((size_t)m * nc);
-    for (int a = 0; a < nc; ++a) {
-      const int q = cand[a];
-      double sn = 0.0;
-      for (int r = 0; r < kd; ++r) sn += std::norm(S[(size_t)q * kd + r]);
-      sn = std::sqrt(sn);
-      for (int t = 0; t < m; ++t) {
-        zc acc;
-        for (int r = 0; r < kd; ++r) acc += G[r][t] * S[(size_t)q * kd + r];
-        acc /= sn;
-        Sx[(size_t)a * m + t] = c128{acc.real(), acc.imag()};
-      }
-    }
+    for (int a = 0; a < nc; ++a) tz.ritz_coeffs(S, cand[a], Sx.data() + (size_t)a * m);
     DevMem dS, dX;
     NEP_TRY(dS.alloc(sizeof(c128) * Sx.size()));
     NEP_TRY(dX.alloc(sizeof(c128) * (size_t)n * nc));
@@ -1007,19 +1353,378 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
   }
   *m_out = mret;
   if (Hout)
-    for (size_t e = 0; e < H.size(); ++e) {
-      Hout[2 * e] = H[e].real();
-      Hout[2 * e + 1] = H[e].imag();
+    for (size_t e = 0; e < tz.H.size(); ++e) {
+      Hout[2 * e] = tz.H[e].real();
+      Hout[2 * e + 1] = tz.H[e].imag();
     }
   if (info) {
     info->d = d;
     info->met = it.met;
     info->k_done = kd;
     info->basis = m;
-    info->h_last = hlast;
+    info->h_last = tz.hlast;
     info->ms_lu = ms_lu;
     info->ms_krylov = ms_krylov;
     info->ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return NEP_OK;
+}
+
+
+nep_status nep_nleigs_batch(int nprob, const nep_split* h, const nep_contour* g, const nep_nleigs_opts* o,
+                            const void* const* W0, int* m_out, double* lambda, void* const* X, double* eta,
+                            nep_nleigs_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  NEP_CHECK(nprob >= 1 && nprob <= 4096, NEP_ERR_ARG, "need 1 <= nprob <= 4096");
+  NEP_CHECK(h && g && o && W0 && m_out && lambda && X && eta, NEP_ERR_ARG, "null argument");
+  const int P = nprob, k = o[0].k, maxe = o[0].max_eigs;
+  NEP_CHECK(k >= 1 && k <= kNlMaxK, NEP_ERR_ARG, "need 1 <= k <= %d", kNlMaxK);
+  NEP_CHECK(maxe >= 1, NEP_ERR_ARG, "need max_eigs >= 1");
+  for (int p = 0; p < P; ++p) {
+    NEP_CHECK(h[p] != nullptr && W0[p] && X[p], NEP_ERR_ARG, "problem %d: null handle or buffer", p);
+    NEP_TRY(check_contour(&g[p]));
+    NEP_TRY(check_nleigs_opts(&o[p]));
+    NEP_CHECK(o[p].k == k && o[p].max_eigs == maxe, NEP_ERR_ARG, "problem %d: k and max_eigs must match problem 0's",
+              p);
+    NEP_CHECK(o[p].eta_tol >= 0.0, NEP_ERR_ARG, "need eta_tol >= 0");
+  }
+  const hipStream_t st = h[0]->impl.stream;
+  // per-problem descriptors (offsets filled in below)
+  std::vector<NlbProb> hpb(P);
+  for (int p = 0; p < P; ++p) {
+    const SplitOperator& op = h[p]->impl.op;
+    NlbProb& B = hpb[p];
+    B = NlbProb{};
+    B.n = op.n;
+    B.ell = op.ell;
+    for (int i = 0; i < op.ell; ++i) {
+      B.t.A[i] = op.dA[i];
+      B.t.diag[i] = op.dDiag[i];
+      B.t.cplx[i] = op.is_cplx[i];
+      B.t.isdiag[i] = op.is_diag[i];
+      B.fn_root[i] = op.fn_root[i];
+    }
+    B.normA = op.dnormA;
+    B.fn_nodes = op.dfn_nodes;
+    B.fn_coef = op.dfn_coef;
+  }
+  DevMem dpb;
+  NEP_TRY(dpb.alloc(sizeof(NlbProb) * P));
+  NEP_HIP(hipMemcpyAsync(dpb.p, hpb.data(), sizeof(NlbProb) * P, hipMemcpyHostToDevice, st));
+  const NlbProb* pb = dpb.as<NlbProb>();
+  // interpolants: nodes on the host, every problem's f_i at its nodes in one
+  // launch, divided differences on the host
+  std::vector<InterpWork> iw(P);
+  parallel_for(P, [&](int p) { interp_nodes(g[p], o[p], iw[p]); });
+  int fstride = 1;
+  for (int p = 0; p < P; ++p) fstride = std::max(fstride, iw[p].dmax + 1);
+  std::vector<Interp> its(P);
+  {
+    std::vector<c128> zh((size_t)P * fstride, c128{0.0, 0.0});
+    for (int p = 0; p < P; ++p)
+      for (int j = 0; j <= iw[p].dmax; ++j) zh[(size_t)p * fstride + j] = c128{iw[p].sig[j].real(), iw[p].sig[j].imag()};
+    DevMem dz, dfv, dbad;
+    NEP_TRY(dz.alloc(sizeof(c128) * zh.size()));
+    NEP_TRY(dfv.alloc(sizeof(c128) * zh.size() * kMaxTerms));
+    NEP_TRY(dbad.alloc(sizeof(int) * zh.size()));
+    NEP_HIP(hipMemcpyAsync(dz.p, zh.data(), sizeof(c128) * zh.size(), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_nlb_fn, dim3(ceil_div(P * fstride, 64)), dim3(64), 0, st, pb, P, fstride, dz.as<c128>(),
+                       dfv.as<c128>(), dbad.as<int>());
+    NEP_HIP(hipGetLastError());
+    std::vector<c128> fv(zh.size() * kMaxTerms);
+    std::vector<int> bad(zh.size());
+    NEP_HIP(hipMemcpyAsync(fv.data(), dfv.p, sizeof(c128) * fv.size(), hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipMemcpyAsync(bad.data(), dbad.p, sizeof(int) * bad.size(), hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipStreamSynchronize(st));
+    std::vector<nep_status> rs(P, NEP_OK);
+    parallel_for(P, [&](int p) {
+      const int ell = hpb[p].ell, dm1 = iw[p].dmax + 1;
+      std::vector<c128> f((size_t)ell * dm1);
+      for (int i = 0; i < ell; ++i)
+        for (int j = 0; j < dm1; ++j) f[(size_t)i * dm1 + j] = fv[((size_t)p * kMaxTerms + i) * fstride + j];
+      rs[p] = interp_finish(iw[p], ell, f.data(), bad.data() + (size_t)p * fstride, its[p]);
+    });
+    for (int p = 0; p < P; ++p)
+      NEP_CHECK(rs[p] == NEP_OK, rs[p], "problem %d: an interpolation node lies on a pole or branch cut", p);
+  }
+  std::vector<ToarHost> tz(P);
+  int mmax = 0, ellmax = 1, nmax = 1, dmaxd = 0;
+  for (int p = 0; p < P; ++p) {
+    Split& s = h[p]->impl;
+    const zc sg(o[p].sigma[0], o[p].sigma[1]);
+    for (int j = 0; j < its[p].d; ++j)
+      NEP_CHECK(its[p].sigma[j] != sg, NEP_ERR_ARG, "problem %d: the shift equals interpolation node %d", p, j);
+    for (int j = 1; j <= its[p].d; ++j)
+      NEP_CHECK(inf_pole(its[p].xi[j]) || its[p].xi[j] != sg, NEP_ERR_ARG, "problem %d: the shift equals pole %d",
+                p, j);
+    tz[p].init(its[p], sg, s.op.ell, k);
+    mmax = std::max(mmax, its[p].d + k);
+    ellmax = std::max(ellmax, s.op.ell);
+    nmax = std::max(nmax, s.op.n);
+    dmaxd = std::max(dmaxd, its[p].d);
+  }
+  // device buffers: bases, products, coefficients, Gram--Schmidt results
+  std::vector<long long> offU(P), offZ(P);
+  long long totU = 0, totZ = 0;
+  for (int p = 0; p < P; ++p) {
+    const int n = h[p]->impl.op.n;
+    offU[p] = totU;
+    offZ[p] = totZ;
+    totU += (long long)n * (mmax + 1);
+    totZ += (long long)n * ellmax;
+  }
+  const long long qstride = (long long)(mmax + 1) * ellmax;
+  const long long hs = 2LL * (mmax + 1) + 1;  // per problem: h1, h2, two norms
+  DevMem dU, dZ, dQ, dsc, dm, dyp, dsig, drho;
+  NEP_TRY(dU.alloc(sizeof(c128) * (size_t)totU));
+  NEP_TRY(dZ.alloc(sizeof(c128) * (size_t)totZ));
+  NEP_TRY(dQ.alloc(sizeof(c128) * (size_t)(qstride * P)));
+  NEP_TRY(dsc.alloc(sizeof(c128) * (size_t)(hs * P)));
+  NEP_TRY(dm.alloc(sizeof(int) * P));
+  NEP_TRY(dyp.alloc(sizeof(c128*) * P));
+  NEP_TRY(dsig.alloc(sizeof(c128) * P));
+  NEP_TRY(drho.alloc(sizeof(c128) * (size_t)P * kMaxTerms));
+  c128* U = dU.as<c128>();
+  std::vector<c128> hsig(P), hrho((size_t)P * kMaxTerms);
+  for (int p = 0; p < P; ++p) {
+    hsig[p] = c128{o[p].sigma[0], o[p].sigma[1]};
+    tz[p].rho(hrho.data() + (size_t)p * kMaxTerms);
+  }
+  NEP_HIP(hipMemcpyAsync(dsig.p, hsig.data(), sizeof(c128) * P, hipMemcpyHostToDevice, st));
+  NEP_HIP(hipMemcpyAsync(drho.p, hrho.data(), sizeof(c128) * hrho.size(), hipMemcpyHostToDevice, st));
+
+  // R_d(sigma_p) for every problem: one batched assembly and LU in complex FP64
+  MomentsPlan plan;
+  nep_contour g0{};
+  g0.kind = 0;
+  g0.rho = 1.0;
+  g0.v = 1.0;
+  PlanOptions po;
+  po.N = 1;
+  po.L = 1;
+  po.K = 1;
+  po.prec = NEP_PREC_FP64;
+  po.max_refine = 0;
+  po.fallback = 0;
+  std::vector<PlanProblem> probs;
+  probs.reserve(P);
+  for (int p = 0; p < P; ++p) {
+    PlanProblem pp{&h[p]->impl.op, g0, nullptr, nullptr, dsig.as<c128>() + p};
+    pp.fpts = drho.as<c128>() + (size_t)p * kMaxTerms;
+    probs.push_back(pp);
+  }
+  NEP_TRY(plan.build(probs, po));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  NEP_HIP(hipEventCreate(&e0));
+  NEP_HIP(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evg{e0, e1};
+  NEP_HIP(hipEventRecord(e0, st));
+  NEP_TRY(plan.factor(st));
+  NEP_HIP(hipEventRecord(e1, st));
+  {
+    std::vector<int> pinfo(P);
+    NEP_HIP(hipMemcpyAsync(pinfo.data(), plan.info(), sizeof(int) * P, hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipStreamSynchronize(st));
+    for (int p = 0; p < P; ++p)
+      NEP_CHECK(pinfo[p] >= h[p]->impl.op.n, NEP_ERR_SINGULAR, "problem %d: R_d(sigma) is exactly singular", p);
+  }
+  float ms_lu = 0.0f;
+  NEP_HIP(hipEventElapsedTime(&ms_lu, e0, e1));
+  const auto t1 = std::chrono::steady_clock::now();
+  c128* Rb = plan.R_mut();
+  c128* Yb = plan.Y_mut();
+  for (int p = 0; p < P; ++p) {
+    hpb[p].offU = offU[p];
+    hpb[p].offZ = offZ[p];
+    hpb[p].offY = plan.y_offset(p);
+  }
+  NEP_HIP(hipMemcpyAsync(dpb.p, hpb.data(), sizeof(NlbProb) * P, hipMemcpyHostToDevice, st));
+  int* dms = dm.as<int>();
+  c128** yp = dyp.as<c128*>();
+  c128* hbase = dsc.as<c128>();
+  double* nbase = reinterpret_cast<double*>(hbase + 2 * (mmax + 1));
+  const long long nstride = 2 * hs;  // doubles
+  const dim3 g256(256), g64(64);
+  std::vector<int> hm(P);
+  std::vector<c128*> hy(P);
+  std::vector<c128> hb((size_t)(hs * P));
+  // Gram--Schmidt of every y_p against U_p[:, 0:m_p] (m_p < 0: skipped), as
+  // in the single-problem run; results read back in one copy
+  auto orth = [&]() -> nep_status {
+    NEP_HIP(hipMemcpyAsync(dms, hm.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
+    NEP_HIP(hipMemcpyAsync(yp, hy.data(), sizeof(c128*) * P, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_nlb_norm, dim3(P), g256, 0, st, pb, dms, yp, nbase, nstride, 0);
+    hipLaunchKernelGGL(k_nlb_dots, dim3(mmax, P), g256, 0, st, pb, dms, U, yp, hbase, hs);
+    hipLaunchKernelGGL(k_nlb_sub, dim3(ceil_div(nmax, 64), P), g64, 0, st, pb, dms, U, hbase, hs, yp);
+    hipLaunchKernelGGL(k_nlb_dots, dim3(mmax, P), g256, 0, st, pb, dms, U, yp, hbase + (mmax + 1), hs);
+    hipLaunchKernelGGL(k_nlb_sub, dim3(ceil_div(nmax, 64), P), g64, 0, st, pb, dms, U, hbase + (mmax + 1), hs, yp);
+    hipLaunchKernelGGL(k_nlb_norm, dim3(P), g256, 0, st, pb, dms, yp, nbase, nstride, 1);
+    hipLaunchKernelGGL(k_nlb_store, dim3(ceil_div(nmax, 256), P), g256, 0, st, pb, dms, U, yp, nbase, nstride);
+    NEP_HIP(hipGetLastError());
+    NEP_HIP(hipMemcpyAsync(hb.data(), dsc.p, sizeof(c128) * hb.size(), hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipStreamSynchronize(st));
+    return NEP_OK;
+  };
+  auto coef = [&](int p, int m, std::vector<zc>& c, double& n0, double& n1) {
+    const c128* b = hb.data() + (size_t)p * hs;
+    c.assign(m, zc());
+    for (int t = 0; t < m; ++t) c[t] = zc(b[t].re + b[(mmax + 1) + t].re, b[t].im + b[(mmax + 1) + t].im);
+    const double* nn = reinterpret_cast<const double*>(b + 2 * (mmax + 1));
+    n0 = nn[0];
+    n1 = nn[1];
+  };
+
+  // starting blocks: QR of [w^0 .. w^{d-1}] per problem by Gram--Schmidt
+  for (int p = 0; p < P; ++p)
+    NEP_HIP(hipMemcpyAsync(U + offU[p], W0[p], sizeof(c128) * (size_t)h[p]->impl.op.n * its[p].d,
+                           hipMemcpyDeviceToDevice, st));
+  {
+    std::vector<std::vector<zc>> R(P);
+    for (int p = 0; p < P; ++p) R[p].assign((size_t)its[p].d * its[p].d, zc());
+    std::vector<zc> c;
+    for (int q = 0; q < dmaxd; ++q) {
+      for (int p = 0; p < P; ++p) {
+        hm[p] = q < its[p].d ? q : -1;
+        hy[p] = U + offU[p] + (long long)q * h[p]->impl.op.n;
+      }
+      NEP_TRY(orth());
+      for (int p = 0; p < P; ++p) {
+        if (q >= its[p].d) continue;
+        double n0 = 0.0, n1 = 0.0;
+        coef(p, q, c, n0, n1);
+        NEP_CHECK(n1 > kNlDep * n0 && n0 > 0.0, NEP_ERR_ARG, "problem %d: starting block column %d is linearly "
+                  "dependent", p, q);
+        const int d = its[p].d;
+        for (int t = 0; t < q; ++t) R[p][(size_t)q * d + t] = c[t];
+        R[p][(size_t)q * d + q] = n1;
+      }
+    }
+    for (int p = 0; p < P; ++p) tz[p].start(R[p]);
+  }
+  // Arnoldi steps, all problems together
+  std::vector<c128> Qh((size_t)(qstride * P));
+  for (int p = 0; p < P; ++p) hy[p] = Yb + hpb[p].offY;
+  for (int j = 0; j < k; ++j) {
+    bool any = false;
+    for (int p = 0; p < P; ++p) any |= !tz[p].done;
+    if (!any) break;
+    parallel_for(P, [&](int p) {
+      hm[p] = tz[p].done ? -1 : tz[p].m;
+      if (!tz[p].done) tz[p].rhs(j, Qh.data() + p * qstride);
+    });
+    NEP_HIP(hipMemcpyAsync(dms, hm.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
+    NEP_HIP(hipMemcpyAsync(dQ.p, Qh.data(), sizeof(c128) * Qh.size(), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_nlb_rhs, dim3(ceil_div(nmax, 64), ellmax, P), g64, 0, st, pb, dms, U, dQ.as<c128>(), qstride,
+                       dZ.as<c128>());
+    hipLaunchKernelGGL(k_nlb_splitmv, dim3(ceil_div(nmax, 4), P), g256, 0, st, pb, dms, dZ.as<c128>(), Rb);
+    NEP_HIP(hipGetLastError());
+    NEP_TRY(plan.solve_rhs(st));  // y^0_p = R_d(sigma_p)^{-1} rhs_p, every problem
+    NEP_TRY(orth());
+    parallel_for(P, [&](int p) {
+      if (hm[p] < 0) return;
+      std::vector<zc> c;
+      double n0 = 0.0, n1 = 0.0;
+      coef(p, hm[p], c, n0, n1);
+      tz[p].absorb(j, c, n0, n1);
+    });
+  }
+  const float ms_krylov = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t1).count();
+
+  // Ritz pairs inside each region, their vectors and backward errors
+  std::vector<NlbPair> pairs;
+  std::vector<c128> Sx;
+  long long xtot = 0;
+  std::vector<std::vector<zc>> lams(P), Ss(P);
+  std::vector<char> rok(P, 1);
+  parallel_for(P, [&](int p) { rok[p] = tz[p].ritz(lams[p], Ss[p]) ? 1 : 0; });
+  for (int p = 0; p < P; ++p) {
+    NEP_CHECK(rok[p], NEP_ERR_DEVICE, "problem %d: eigenvalues of the Hessenberg matrix did not converge", p);
+    const std::vector<zc>& lam = lams[p];
+    const std::vector<zc>& S = Ss[p];
+    for (int q = 0; q < tz[p].kd; ++q) {
+      if (!inside_region(g[p], lam[q])) continue;
+      NlbPair a{};
+      a.p = p;
+      a.m = tz[p].m;
+      a.lam = c128{lam[q].real(), lam[q].imag()};
+      a.soff = (long long)Sx.size();
+      a.xoff = xtot;
+      Sx.resize(Sx.size() + tz[p].m);
+      tz[p].ritz_coeffs(S, q, Sx.data() + a.soff);
+      xtot += h[p]->impl.op.n;
+      pairs.push_back(a);
+    }
+  }
+  const int npair = (int)pairs.size();
+  std::vector<double> et(npair);
+  std::vector<std::vector<int>> keep(P);
+  DevMem dpr, dS, dX, deta, dkeep, ddst;
+  if (npair > 0) {
+    NEP_TRY(dpr.alloc(sizeof(NlbPair) * npair));
+    NEP_TRY(dS.alloc(sizeof(c128) * Sx.size()));
+    NEP_TRY(dX.alloc(sizeof(c128) * (size_t)xtot));
+    NEP_TRY(deta.alloc(sizeof(double) * npair));
+    NEP_HIP(hipMemcpyAsync(dpr.p, pairs.data(), sizeof(NlbPair) * npair, hipMemcpyHostToDevice, st));
+    NEP_HIP(hipMemcpyAsync(dS.p, Sx.data(), sizeof(c128) * Sx.size(), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_nlb_vectors, dim3(npair), g256, 0, st, pb, dpr.as<NlbPair>(), U, dS.as<c128>(),
+                       dX.as<c128>());
+    hipLaunchKernelGGL(k_nlb_eta, dim3(npair), g256, 0, st, pb, dpr.as<NlbPair>(), dX.as<c128>(), deta.as<double>());
+    NEP_HIP(hipGetLastError());
+    NEP_HIP(hipMemcpyAsync(et.data(), deta.p, sizeof(double) * npair, hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipStreamSynchronize(st));
+    for (int a = 0; a < npair; ++a) {
+      const int p = pairs[a].p;
+      const double tol = o[p].eta_tol > 0.0 ? o[p].eta_tol : 1e-10;
+      if (et[a] <= tol) keep[p].push_back(a);
+    }
+  }
+  std::vector<int> kept;
+  std::vector<c128*> dst;
+  for (int p = 0; p < P; ++p) {
+    auto& kp = keep[p];
+    std::sort(kp.begin(), kp.end(), [&](int x, int y) {
+      const c128 lx = pairs[x].lam, ly = pairs[y].lam;
+      return lx.re != ly.re ? lx.re < ly.re : lx.im < ly.im;
+    });
+    const int mr = std::min((int)kp.size(), maxe);
+    m_out[p] = mr;
+    for (int a = 0; a < mr; ++a) {
+      const NlbPair& pr = pairs[kp[a]];
+      lambda[2 * ((size_t)p * maxe + a)] = pr.lam.re;
+      lambda[2 * ((size_t)p * maxe + a) + 1] = pr.lam.im;
+      eta[(size_t)p * maxe + a] = et[kp[a]];
+      kept.push_back(kp[a]);
+      dst.push_back(reinterpret_cast<c128*>(X[p]) + (size_t)a * h[p]->impl.op.n);
+    }
+  }
+  if (!kept.empty()) {
+    NEP_TRY(dkeep.alloc(sizeof(int) * kept.size()));
+    NEP_TRY(ddst.alloc(sizeof(c128*) * dst.size()));
+    NEP_HIP(hipMemcpyAsync(dkeep.p, kept.data(), sizeof(int) * kept.size(), hipMemcpyHostToDevice, st));
+    NEP_HIP(hipMemcpyAsync(ddst.p, dst.data(), sizeof(c128*) * dst.size(), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_nlb_gather, dim3((unsigned)kept.size()), g256, 0, st, dpr.as<NlbPair>(), dkeep.as<int>(),
+                       ddst.as<c128*>(), dX.as<c128>(), pb);
+    NEP_HIP(hipGetLastError());
+  }
+  NEP_HIP(hipStreamSynchronize(st));
+  if (info) {
+    const float ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int p = 0; p < P; ++p) {
+      info[p].d = its[p].d;
+      info[p].met = its[p].met;
+      info[p].k_done = tz[p].kd;
+      info[p].basis = tz[p].m;
+      info[p].h_last = tz[p].hlast;
+      info[p].ms_lu = ms_lu;
+      info[p].ms_krylov = ms_krylov;
+      info[p].ms_total = ms_total;
+    }
   }
   return NEP_OK;
 }

@@ -155,6 +155,8 @@ class MomentsPlan {
   // batched solve kernels: its descriptor, the factor buffer, the row map and
   // its diagonal-block inverses ([block][0: L, 1: U][64][64], row-major).
   const MatDesc& mat0() const { return sorted_[0]; }
+  // element offset of problem p's block in the R and Y buffers
+  long long y_offset(int p) const { return hpd_[p].offY; }
   const void* factor_base() const { return dT_.p; }
   const int* row_map() const { return drows_.as<int>(); }
   const void* dinv0() const { return ddinv_.as<char>() + dinv_off_[0] * (opt.prec == NEP_PREC_FP64 ? 16 : 8); }
