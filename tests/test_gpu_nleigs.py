@@ -277,7 +277,7 @@ def test_batch_rational_256(nep):
             eo = oracle.backward_error(p, lam, Xh)
             eo_max = max(eo_max, float(np.max(eo)))
             assert np.max(eo) <= 1e-10
-            assert np.max(np.abs(eo - eta) / eo) < 1e-2   # the device's eta of the same pairs
+            assert np.all(np.abs(eo - eta) <= 1e-2 * eo + 1e-14)   # the device's eta of the same pairs
     print(f"oracle eta of every returned pair <= {eo_max:.2e}")
     for op in ops:
         op.close()
