@@ -38,6 +38,10 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <atomic>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <numeric>
 #include <thread>
 #include <vector>
@@ -888,6 +892,68 @@ void parallel_for(int count, F&& fn) {
   for (auto& x : th) x.join();
 }
 
+// A few host threads kept for the length of a batched run: run(count, fn)
+// calls fn(p) for every p < count across them and the calling thread (the
+// per-problem coefficient work of each Arnoldi step, without starting threads
+// every step).
+class HostPool {
+ public:
+  explicit HostPool(int nworkers) {
+    for (int t = 0; t < nworkers; ++t)
+      th_.emplace_back([this] {
+        unsigned seen = 0;
+        for (;;) {
+          {
+            std::unique_lock<std::mutex> lk(mu_);
+            cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+            if (stop_) return;
+            seen = gen_;
+          }
+          drain();
+          std::lock_guard<std::mutex> lk(mu_);
+          if (--busy_ == 0) done_.notify_all();
+        }
+      });
+  }
+  HostPool(const HostPool&) = delete;
+  HostPool& operator=(const HostPool&) = delete;
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  void run(int count, std::function<void(int)> fn) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = std::move(fn);
+      count_ = count;
+      next_ = 0;
+      busy_ = (int)th_.size();
+      ++gen_;
+    }
+    cv_.notify_all();
+    drain();
+    std::unique_lock<std::mutex> lk(mu_);
+    done_.wait(lk, [&] { return busy_ == 0; });
+  }
+
+ private:
+  void drain() {
+    for (int p; (p = next_.fetch_add(1)) < count_;) job_(p);
+  }
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_;
+  std::function<void(int)> job_;
+  int count_ = 0, busy_ = 0;
+  std::atomic<int> next_{0};
+  unsigned gen_ = 0;
+  bool stop_ = false;
+};
+
 // Host side of Arnoldi in the TOAR representation for one problem: the
 // coefficient recurrences of eqs. (nleigs-toar1), (nleigs-toar4), the
 // coefficients of the right-hand side of eq. (nleigs-toar2) per term, and the
@@ -1610,11 +1676,13 @@ nep_status nep_nleigs_batch(int nprob, const nep_split* h, const nep_contour* g,
   // Arnoldi steps, all problems together
   std::vector<c128> Qh((size_t)(qstride * P));
   for (int p = 0; p < P; ++p) hy[p] = Yb + hpb[p].offY;
+  const unsigned hwc = std::max(1u, std::thread::hardware_concurrency());
+  HostPool pool(std::max(0, std::min<int>({15, (int)hwc - 1, P / 8})));
   for (int j = 0; j < k; ++j) {
     bool any = false;
     for (int p = 0; p < P; ++p) any |= !tz[p].done;
     if (!any) break;
-    parallel_for(P, [&](int p) {
+    pool.run(P, [&](int p) {
       hm[p] = tz[p].done ? -1 : tz[p].m;
       if (!tz[p].done) tz[p].rhs(j, Qh.data() + p * qstride);
     });
@@ -1626,7 +1694,7 @@ nep_status nep_nleigs_batch(int nprob, const nep_split* h, const nep_contour* g,
     NEP_HIP(hipGetLastError());
     NEP_TRY(plan.solve_rhs(st));  // y^0_p = R_d(sigma_p)^{-1} rhs_p, every problem
     NEP_TRY(orth());
-    parallel_for(P, [&](int p) {
+    pool.run(P, [&](int p) {
       if (hm[p] < 0) return;
       std::vector<zc> c;
       double n0 = 0.0, n1 = 0.0;
