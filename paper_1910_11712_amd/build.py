@@ -20,6 +20,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", INCLUDE, "-Wno-unused-result"]
+# host code whose std::complex products and quotients are hot and whose
+# operands stay far from overflow (small dense eigenproblems, the NLEIGS
+# set-up): the textbook product and quotient instead of the library's
+# inf/NaN-recovering ones (2.7x faster on the 40 x 40 Hessenberg QR)
+EXTRA = {"dense.cpp": ["-fcx-limited-range"], "nleigs.hip": ["-fcx-limited-range"]}
 
 
 def _sources():
@@ -36,7 +41,7 @@ def _compile(src, force):
     if not force and os.path.exists(obj):
         if os.path.getmtime(obj) >= max(os.path.getmtime(src), _headers_mtime()):
             return obj, None
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         return obj, r.stderr
