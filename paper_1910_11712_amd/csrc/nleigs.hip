@@ -17,7 +17,11 @@
 // product -sum_i A_i (U q_i), the solve with the resident factors of
 // R_d(sigma), and classical Gram--Schmidt with one reorthogonalization of the
 // new vector against U.  A step reads every A_i once and the factors once, so
-// it is bound by HBM bandwidth.
+// it is bound by HBM bandwidth (for one large matrix, by the latency of the
+// solve's chain of 64-row blocks).  nep_nleigs_batch runs many problems at
+// once: one batched LU of every R_d(sigma_p), and each step's products,
+// solves (the moment plan's batched solve) and Gram--Schmidt as single launches
+// over all problems, with the per-problem host work on a thread pool.
 //
 // The divided-difference matrices D_j are never formed (Section 4.5): with
 // q_i = sum_{j<d-1} d_i^j g~^{j+1} + (d_i^d / beta_d) g^{d-1}, the right-hand
