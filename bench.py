@@ -506,7 +506,8 @@ def _nleigs_run(P, steps=3, warmup=1, k=100, dmax=40):
            "eigenpairs": int(len(lam)), "eigenpairs_per_s": len(lam) / t,
            "max_eta": float(np.max(eta)) if len(lam) else None,
            "roofline": hbm(tri, "k_nl_tri (one triangle of a solve with the factors of R_d(sigma))"),
-           "split_product": hbm(smv, "k_nl_splitmv (-sum_i A_i (U q_i))")}
+           "split_product": hbm(smv, "k_nl_splitmv (-sum_i A_i (U q_i))"),
+           "arnoldi_steps_per_s": k / (info["ms_krylov"] / 1e3)}
     try:
         g = np.load(os.path.join(ROOT, "tests", "golden", "cfg2_sqrt_n4096_oracle.npz"))
         gold = g["lam"][g["inside"].astype(bool)]
