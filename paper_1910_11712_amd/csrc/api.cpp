@@ -103,9 +103,12 @@ nep_status Split::init(int n_, int ell_, const nep_mat* A, const nep_fn* f, hipS
   NEP_TRY(fn_nodes.alloc(sizeof(FnNode) * nodes.size()));
   NEP_TRY(fn_coef.alloc(sizeof(c128) * coef.size()));
   NEP_TRY(fn_roots.alloc(sizeof(int) * kMaxTerms));
-  NEP_HIP(hipMemcpy(fn_nodes.p, nodes.data(), sizeof(FnNode) * nodes.size(), hipMemcpyHostToDevice));
-  NEP_HIP(hipMemcpy(fn_coef.p, coef.data(), sizeof(c128) * coef.size(), hipMemcpyHostToDevice));
-  NEP_HIP(hipMemcpy(fn_roots.p, op.fn_root, sizeof(int) * kMaxTerms, hipMemcpyHostToDevice));
+  // uploads on the handle's stream, which the end of creation waits for: an
+  // upload through the null stream is not ordered before work on a
+  // non-blocking stream
+  NEP_HIP(hipMemcpyAsync(fn_nodes.p, nodes.data(), sizeof(FnNode) * nodes.size(), hipMemcpyHostToDevice, stream));
+  NEP_HIP(hipMemcpyAsync(fn_coef.p, coef.data(), sizeof(c128) * coef.size(), hipMemcpyHostToDevice, stream));
+  NEP_HIP(hipMemcpyAsync(fn_roots.p, op.fn_root, sizeof(int) * kMaxTerms, hipMemcpyHostToDevice, stream));
   op.dfn_nodes = fn_nodes.as<FnNode>();
   op.dfn_coef = fn_coef.as<c128>();
   h_fn_nodes = nodes;
@@ -152,7 +155,7 @@ nep_status Split::init(int n_, int ell_, const nep_mat* A, const nep_fn* f, hipS
         }
         diags[i] = std::make_unique<DevMem>();
         NEP_TRY(diags[i]->alloc(sizeof(c128) * n_));
-        NEP_HIP(hipMemcpy(diags[i]->p, dv.data(), sizeof(c128) * n_, hipMemcpyHostToDevice));
+        NEP_HIP(hipMemcpyAsync(diags[i]->p, dv.data(), sizeof(c128) * n_, hipMemcpyHostToDevice, stream));
         op.is_diag[i] = 1;
         op.dDiag[i] = diags[i]->as<c128>();
       }
@@ -162,7 +165,8 @@ nep_status Split::init(int n_, int ell_, const nep_mat* A, const nep_fn* f, hipS
     op.dA[i] = mats[i]->p;
   }
   op.normA.assign(ell_, 0.0);
-  NEP_HIP(hipMemcpy(op.normA.data(), op.dnormA, sizeof(double) * ell_, hipMemcpyDeviceToHost));
+  NEP_HIP(hipMemcpyAsync(op.normA.data(), op.dnormA, sizeof(double) * ell_, hipMemcpyDeviceToHost, stream));
+  NEP_HIP(hipStreamSynchronize(stream));
   return NEP_OK;
 }
 
@@ -197,10 +201,12 @@ nep_status Split::init_adjoint(const Split& src) {
   NEP_TRY(fn_nodes.alloc(sizeof(FnNode) * h_fn_nodes.size()));
   NEP_TRY(fn_coef.alloc(sizeof(c128) * h_fn_coef.size()));
   NEP_TRY(fn_roots.alloc(sizeof(int) * kMaxTerms));
-  NEP_HIP(hipMemcpy(fn_nodes.p, h_fn_nodes.data(), sizeof(FnNode) * h_fn_nodes.size(), hipMemcpyHostToDevice));
-  NEP_HIP(hipMemcpy(fn_coef.p, h_fn_coef.data(), sizeof(c128) * h_fn_coef.size(), hipMemcpyHostToDevice));
+  NEP_HIP(hipMemcpyAsync(fn_nodes.p, h_fn_nodes.data(), sizeof(FnNode) * h_fn_nodes.size(), hipMemcpyHostToDevice,
+                         stream));
+  NEP_HIP(hipMemcpyAsync(fn_coef.p, h_fn_coef.data(), sizeof(c128) * h_fn_coef.size(), hipMemcpyHostToDevice,
+                         stream));
   for (int i = 0; i < kMaxTerms; ++i) op.fn_root[i] = src.op.fn_root[i];
-  NEP_HIP(hipMemcpy(fn_roots.p, op.fn_root, sizeof(int) * kMaxTerms, hipMemcpyHostToDevice));
+  NEP_HIP(hipMemcpyAsync(fn_roots.p, op.fn_root, sizeof(int) * kMaxTerms, hipMemcpyHostToDevice, stream));
   op.dfn_nodes = fn_nodes.as<FnNode>();
   op.dfn_coef = fn_coef.as<c128>();
   NEP_TRY(norms.alloc(sizeof(double) * kMaxTerms + sizeof(unsigned long long) * 2));
@@ -226,7 +232,8 @@ nep_status Split::init_adjoint(const Split& src) {
     op.dA[i] = mats[i]->p;
   }
   op.normA.assign(op.ell, 0.0);
-  NEP_HIP(hipMemcpy(op.normA.data(), op.dnormA, sizeof(double) * op.ell, hipMemcpyDeviceToHost));
+  NEP_HIP(hipMemcpyAsync(op.normA.data(), op.dnormA, sizeof(double) * op.ell, hipMemcpyDeviceToHost, stream));
+  NEP_HIP(hipStreamSynchronize(stream));
   return NEP_OK;
 }
 
@@ -291,7 +298,7 @@ nep_status Split::moments(const nep_contour* g, const nep_ciss_opts* o, const vo
   if (!plan || !plan->matches(probs, po) || plan->opt.max_refine != po.max_refine ||
       plan->opt.fallback != po.fallback) {
     plan = std::make_unique<MomentsPlan>();
-    nep_status bs = plan->build(probs, po);
+    nep_status bs = plan->build(probs, po, s);
     if (bs == NEP_OK) bs = tune_plan(*plan, s);
     if (bs != NEP_OK) {
       plan.reset();
@@ -299,7 +306,7 @@ nep_status Split::moments(const nep_contour* g, const nep_ciss_opts* o, const vo
     }
   } else {
     plan->opt.tol = po.tol;
-    NEP_TRY(plan->rebind(probs));
+    NEP_TRY(plan->rebind(probs, s));
   }
   last_stream = s;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -329,7 +336,7 @@ nep_status Split::moments_more(const void* V, void* S, long long s_stride, void*
   NEP_CHECK(s_stride == 0 || s_stride >= (long long)op.n * plan->opt.L, NEP_ERR_ARG, "moment stride below n*L");
   hipStream_t s = strm ? (hipStream_t)strm : (last_stream ? last_stream : stream);
   std::vector<PlanProblem> probs{PlanProblem{&op, last_g, (const c128*)V, (c128*)S, nullptr, s_stride}};
-  NEP_TRY(plan->rebind(probs));
+  NEP_TRY(plan->rebind(probs, s));
   last_stream = s;
   NEP_TRY(plan->enqueue(s, true, false));
   pending = true;

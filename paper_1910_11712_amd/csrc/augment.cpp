@@ -71,7 +71,7 @@ nep_status nep_count_eigs(nep_split h, const nep_contour* g, int N, int prec, in
   po.max_refine = 0;
   po.fallback = 0;
   std::vector<PlanProblem> probs{PlanProblem{&s.op, *g, nullptr, nullptr}};
-  NEP_TRY(plan.build(probs, po));
+  NEP_TRY(plan.build(probs, po, s.stream));
   NEP_TRY(plan.factor(s.stream));
   return count_from_plan(plan, s.op.n, s.stream, count, max_step, winding);
 }

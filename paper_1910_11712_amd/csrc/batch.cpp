@@ -47,7 +47,7 @@ nep_status nep_batch_create(int nprob, const nep_split* h, const nep_contour* g,
   auto b = std::make_unique<nep_batch_s>();
   b->impl.stream = (hipStream_t)stream;
   b->impl.plan = std::make_unique<MomentsPlan>();
-  NEP_TRY(b->impl.plan->build(probs, po));
+  NEP_TRY(b->impl.plan->build(probs, po, b->impl.stream));
   NEP_TRY(tune_plan(*b->impl.plan, (hipStream_t)stream));
   b->impl.use_graph = use_graph != 0;
   if (b->impl.use_graph) {

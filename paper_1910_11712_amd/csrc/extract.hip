@@ -25,7 +25,7 @@
 namespace nep {
 
 struct ExtractWork {
-  DevMem B0, B1, tau, V0, P, smat, X0, Rt, norms, fz;
+  DevMem B0, B1, tau, V0, P, smat, X0, Rt, norms, fz, Rp;
   size_t cap_rows = 0, cap_cols = 0;
 };
 
@@ -43,6 +43,15 @@ __global__ void k_hankel(const c128* __restrict__ S, int n, int L, int K, long l
   const long long off = (long long)c * n + i;
   B0[e] = S[(long long)(r + s) * sstride + off];
   B1[e] = S[(long long)(r + s + 1) * sstride + off];
+}
+
+// R's leading KL x KL block (column-major, leading dimension M) into a
+// contiguous KL x KL array, for one plain read-back
+__global__ void k_pack_r(const c128* __restrict__ B, long long M, int KL, c128* __restrict__ R) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)KL * KL) return;
+  const long long j = e / KL, i = e - j * KL;
+  R[e] = B[j * M + i];
 }
 
 // block sum over 1024 threads
@@ -461,6 +470,7 @@ nep_status extract_strided(Split& h, const nep_contour* g, const nep_ciss_opts* 
   NEP_TRY(grow(w.B0, sizeof(c128) * M * KL));
   NEP_TRY(grow(w.B1, sizeof(c128) * M * KL));
   NEP_TRY(grow(w.tau, sizeof(c128) * KL));
+  NEP_TRY(grow(w.Rp, sizeof(c128) * (size_t)KL * KL));
   c128* B0 = w.B0.as<c128>();
   c128* B1 = w.B1.as<c128>();
   c128* tau = w.tau.as<c128>();
@@ -477,11 +487,16 @@ nep_status extract_strided(Split& h, const nep_contour* g, const nep_ciss_opts* 
     }
   }
   // R (upper KL x KL) to host
+  // (packed on the device and read back in one plain copy: a pitched
+  // device-to-host copy read back zeros in a process where a profiler had
+  // loaded a second HSA runtime beside the HIP runtime's own)
   std::vector<zc> R((size_t)KL * KL, zc(0.0, 0.0));
   {
     std::vector<zc> tmp((size_t)KL * KL);
-    NEP_HIP(hipMemcpy2DAsync(tmp.data(), sizeof(zc) * KL, B0, sizeof(c128) * M, sizeof(zc) * KL, KL,
-                             hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(k_pack_r, dim3((unsigned)ceil_div_ll((long long)KL * KL, 256)), dim3(256), 0, st, B0, M, KL,
+                       w.Rp.as<c128>());
+    NEP_HIP(hipGetLastError());
+    NEP_HIP(hipMemcpyAsync(tmp.data(), w.Rp.p, sizeof(c128) * (size_t)KL * KL, hipMemcpyDeviceToHost, st));
     NEP_HIP(hipStreamSynchronize(st));
     for (int j = 0; j < KL; ++j)
       for (int i = 0; i <= j; ++i) R[(size_t)j * KL + i] = tmp[(size_t)j * KL + i];

@@ -218,7 +218,7 @@ nep_status nep_solve_at(nep_split h, int m, const double* z, int L, const void* 
   po.max_refine = prec == NEP_PREC_FP64 ? 0 : 5;
   po.fallback = 1;
   std::vector<PlanProblem> probs{PlanProblem{&s.op, g0, (const c128*)V, dS.as<c128>(), dz.as<c128>()}};
-  NEP_TRY(plan.build(probs, po));
+  NEP_TRY(plan.build(probs, po, st));
   NEP_TRY(plan.enqueue(st, true));
   RunResult rr;
   const nep_status rs = plan.finish(st, rr, true);

@@ -1219,7 +1219,7 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
   PlanProblem pp{&s.op, g0, nullptr, nullptr, dsig.as<c128>()};
   pp.fpts = drho.as<c128>();
   std::vector<PlanProblem> probs{pp};
-  NEP_TRY(plan.build(probs, po));
+  NEP_TRY(plan.build(probs, po, st));
   {
     // one matrix: its panels run alone, with nothing to overlap them, and a
     // 64-wide panel does half the serial work of a 128-wide one (n = 4096:
@@ -1227,7 +1227,7 @@ nep_status nep_nleigs(nep_split h, const nep_contour* g, const nep_nleigs_opts* 
     MomentsPlan::Knobs kn = plan.knobs();
     if (kn.jb != 64) {
       kn.jb = 64;
-      NEP_TRY(plan.apply(kn));
+      NEP_TRY(plan.apply(kn, st));
     }
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1583,7 +1583,7 @@ nep_status nep_nleigs_batch(int nprob, const nep_split* h, const nep_contour* g,
     pp.fpts = drho.as<c128>() + (size_t)p * kMaxTerms;
     probs.push_back(pp);
   }
-  NEP_TRY(plan.build(probs, po));
+  NEP_TRY(plan.build(probs, po, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   NEP_HIP(hipEventCreate(&e0));
   NEP_HIP(hipEventCreate(&e1));

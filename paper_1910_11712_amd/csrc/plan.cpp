@@ -184,7 +184,7 @@ bool MomentsPlan::matches(const std::vector<PlanProblem>& probs, const PlanOptio
   return true;
 }
 
-nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs) {
+nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs, hipStream_t st) {
   for (int p = 0; p < nprob; ++p) {
     ProbDesc& D = hpd_[p];
     const PlanProblem& q = probs[p];
@@ -211,13 +211,13 @@ nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs) {
     D.s_stride = q.s_stride > 0 ? q.s_stride : (long long)D.n * D.L;
     D.active = 1;
   }
-  NEP_HIP(hipMemcpy(dpd_.p, hpd_.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice));
+  NEP_HIP(hipMemcpyAsync(dpd_.p, hpd_.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice, st));
   return NEP_OK;
 }
 
-nep_status MomentsPlan::rebind(const std::vector<PlanProblem>& probs) {
+nep_status MomentsPlan::rebind(const std::vector<PlanProblem>& probs, hipStream_t st) {
   NEP_CHECK((int)probs.size() == nprob, NEP_ERR_ARG, "rebind: problem count changed");
-  return upload_problems(probs);
+  return upload_problems(probs, st);
 }
 
 nep_status MomentsPlan::rebind_members(const std::vector<int>& member, const std::vector<const c128*>& V,
@@ -246,7 +246,7 @@ void MomentsPlan::release_fallback() {
   dlinv64_.release();
 }
 
-nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanOptions& o) {
+nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanOptions& o, hipStream_t st) {
   opt = o;
   nprob = (int)probs.size();
   Lmax = o.L;
@@ -353,7 +353,7 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
   NEP_TRY(A(ddinv_, es * (size_t)dinv_elems_));
   NEP_TRY(A(dlinv_, 2 * es * (size_t)sorted_.size() * kLuMaxJB * kLuMaxJB));
   NEP_TRY(A(darrive_, sizeof(int) * std::max<size_t>(1, sorted_.size())));
-  NEP_HIP(hipMemset(darrive_.p, 0, sizeof(int) * std::max<size_t>(1, sorted_.size())));
+  NEP_HIP(hipMemsetAsync(darrive_.p, 0, sizeof(int) * std::max<size_t>(1, sorted_.size()), st));
   NEP_TRY(A(ddinv_off_, sizeof(long long) * dinv_off_.size()));
   NEP_TRY(A(dY_, sizeof(c128) * (size_t)y_elems_));
   NEP_TRY(A(dR_, sizeof(c128) * (size_t)y_elems_));
@@ -403,18 +403,21 @@ nep_status MomentsPlan::build(const std::vector<PlanProblem>& probs, const PlanO
     NEP_CHECK(hcounter_ != nullptr, NEP_ERR_OOM, "no pinned read-back slot left");
   }
 
-  NEP_HIP(hipMemcpy(dmd_.p, sorted_.data(), sizeof(MatDesc) * sorted_.size(), hipMemcpyHostToDevice));
-  NEP_HIP(hipMemcpy(dprefix_.p, hprefix_.data(), sizeof(int) * hprefix_.size(), hipMemcpyHostToDevice));
+  // pageable sources: each copy has taken its bytes when the call returns
+  NEP_HIP(hipMemcpyAsync(dmd_.p, sorted_.data(), sizeof(MatDesc) * sorted_.size(), hipMemcpyHostToDevice, st));
+  NEP_HIP(hipMemcpyAsync(dprefix_.p, hprefix_.data(), sizeof(int) * hprefix_.size(), hipMemcpyHostToDevice, st));
   if (!lu_.prefix.empty())
-    NEP_HIP(hipMemcpy(dlu_prefix_.p, lu_.prefix.data(), sizeof(int) * lu_.prefix.size(), hipMemcpyHostToDevice));
-  NEP_HIP(hipMemcpy(ddinv_off_.p, dinv_off_.data(), sizeof(long long) * dinv_off_.size(), hipMemcpyHostToDevice));
-  NEP_HIP(hipMemcpy(na_.prob, hprob.data(), sizeof(int) * G, hipMemcpyHostToDevice));
+    NEP_HIP(hipMemcpyAsync(dlu_prefix_.p, lu_.prefix.data(), sizeof(int) * lu_.prefix.size(),
+                           hipMemcpyHostToDevice, st));
+  NEP_HIP(hipMemcpyAsync(ddinv_off_.p, dinv_off_.data(), sizeof(long long) * dinv_off_.size(),
+                         hipMemcpyHostToDevice, st));
+  NEP_HIP(hipMemcpyAsync(na_.prob, hprob.data(), sizeof(int) * G, hipMemcpyHostToDevice, st));
   na_prob_host_ = hprob;
-  NEP_HIP(hipMemcpy(na_.jnode, hj.data(), sizeof(int) * G, hipMemcpyHostToDevice));
+  NEP_HIP(hipMemcpyAsync(na_.jnode, hj.data(), sizeof(int) * G, hipMemcpyHostToDevice, st));
   dT64_.release();
   ddinv64_.release();
   dlinv64_.release();
-  return upload_problems(probs);
+  return upload_problems(probs, st);
 }
 
 template <typename P>
@@ -507,7 +510,8 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
   const int* skip = ir_.conv;
   {
     std::vector<int> conv(nnodes);
-    NEP_HIP(hipMemcpy(conv.data(), ir_.conv, sizeof(int) * nnodes, hipMemcpyDeviceToHost));
+    NEP_HIP(hipMemcpyAsync(conv.data(), ir_.conv, sizeof(int) * nnodes, hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipStreamSynchronize(st));
     fallback_count_.assign(nprob, 0);
     for (int p = 0; p < nprob; ++p)
       for (int j = 0; j < opt.N; ++j) fallback_count_[p] += conv[hpd_[p].node0 + j] ? 0 : 1;
@@ -520,7 +524,8 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
     // size order of the full plan), whose diagonal-block inverses land where
     // the full plan's solve looks for them
     std::vector<int> conv(nnodes);
-    NEP_HIP(hipMemcpy(conv.data(), ir_.conv, sizeof(int) * nnodes, hipMemcpyDeviceToHost));
+    NEP_HIP(hipMemcpyAsync(conv.data(), ir_.conv, sizeof(int) * nnodes, hipMemcpyDeviceToHost, st));
+    NEP_HIP(hipStreamSynchronize(st));
     std::vector<MatDesc> sub;
     std::vector<long long> sub_off;
     for (size_t b = 0; b < sorted_.size(); ++b)
@@ -535,10 +540,12 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
       NEP_TRY(dmd.alloc(sizeof(MatDesc) * sub.size()));
       NEP_TRY(dpre.alloc(sizeof(int) * std::max<size_t>(1, lsub.prefix.size())));
       NEP_TRY(doff_sub.alloc(sizeof(long long) * sub_off.size()));
-      NEP_HIP(hipMemcpy(dmd.p, sub.data(), sizeof(MatDesc) * sub.size(), hipMemcpyHostToDevice));
+      NEP_HIP(hipMemcpyAsync(dmd.p, sub.data(), sizeof(MatDesc) * sub.size(), hipMemcpyHostToDevice, st));
       if (!lsub.prefix.empty())
-        NEP_HIP(hipMemcpy(dpre.p, lsub.prefix.data(), sizeof(int) * lsub.prefix.size(), hipMemcpyHostToDevice));
-      NEP_HIP(hipMemcpy(doff_sub.p, sub_off.data(), sizeof(long long) * sub_off.size(), hipMemcpyHostToDevice));
+        NEP_HIP(hipMemcpyAsync(dpre.p, lsub.prefix.data(), sizeof(int) * lsub.prefix.size(), hipMemcpyHostToDevice,
+                               st));
+      NEP_HIP(hipMemcpyAsync(doff_sub.p, sub_off.data(), sizeof(long long) * sub_off.size(), hipMemcpyHostToDevice,
+                             st));
       NEP_HIP(lu_run<double>(lsub, dmd.as<MatDesc>(), dpre.as<int>(), T, drows_.as<int>(), drows_snap_.as<int>(),
                              rows_total_, dinfo_.as<int>(), nullptr, dlinv64_.as<c128>(), Dinv,
                              doff_sub.as<long long>(), darrive_.as<int>(), st, ls_));

@@ -123,7 +123,11 @@ class MomentsPlan {
     if (ls_.side) (void)hipStreamDestroy(ls_.side);
   }
   // Builds layout, tables and buffers.  Problems may differ in n (ragged).
-  nep_status build(const std::vector<PlanProblem>& probs, const PlanOptions& o);
+  // The device tables are uploaded on st, the stream the plan's passes run
+  // on, so they are in place for the first pass on any kind of stream (an
+  // upload through the null stream is not ordered before work on a
+  // non-blocking stream).
+  nep_status build(const std::vector<PlanProblem>& probs, const PlanOptions& o, hipStream_t st);
   // Enqueues the whole moment path on st.  eager=true lets the host stop the
   // refinement loop early (one small read-back per sweep); eager=false runs a
   // fixed number of sweeps with device-side skipping (graph capture safe).
@@ -165,8 +169,9 @@ class MomentsPlan {
   // from the resident factors (the product of the pivots and the sign of the
   // row permutation), read back to host arrays of nnodes entries.
   nep_status logdet(hipStream_t st, std::vector<double>& logabs, std::vector<double>& arg);
-  // Rebinds caller buffers (V, S) and contours without rebuilding.
-  nep_status rebind(const std::vector<PlanProblem>& probs);
+  // Rebinds caller buffers (V, S) and contours without rebuilding; the
+  // descriptor upload is queued on st.
+  nep_status rebind(const std::vector<PlanProblem>& probs, hipStream_t st);
   // For a pass on resident factors (enqueue with refactor=false): the listed
   // problems take new probes V and moment buffers S (s_stride n*L), every
   // other problem sits out the pass (nothing of its operator is read, its
@@ -184,8 +189,8 @@ class MomentsPlan {
   };
   Knobs knobs() const { return Knobs{sp_.lg, sp_.paired, lu_.small_min, lu_.early_fork, lu_.jb}; }
   // applies k; a different panel width rebuilds the LU schedule and its
-  // device prefix table
-  nep_status apply(const Knobs& k);
+  // device prefix table (uploaded on st)
+  nep_status apply(const Knobs& k, hipStream_t st);
   // The candidate settings that differ for this plan's shapes: [0] is the
   // built-in choice; LU candidates first, then the solve's.
   void candidates(std::vector<Knobs>& lu, std::vector<Knobs>& solve) const;
@@ -202,7 +207,7 @@ class MomentsPlan {
   int nprob = 0, nnodes = 0, Lmax = 0;
 
  private:
-  nep_status upload_problems(const std::vector<PlanProblem>& probs);
+  nep_status upload_problems(const std::vector<PlanProblem>& probs, hipStream_t st);
   template <typename P>
   nep_status enqueue_t(hipStream_t st, bool eager, bool refactor);
   template <typename P>

@@ -306,7 +306,7 @@ nep_status rii_polish(Split& h, int m, zc* lam, c128* X, double* eta, const char
   po.max_refine = 0;
   po.fallback = 0;
   std::vector<PlanProblem> probs{PlanProblem{&h.op, g0, nullptr, nullptr, dz.as<c128>()}};
-  NEP_TRY(plan.build(probs, po));
+  NEP_TRY(plan.build(probs, po, st));
   NEP_TRY(plan.factor(st));
   std::vector<int> info(P), active(P, 1), upd(P, 0), bad(P), steps(P);
   NEP_HIP(hipMemcpyAsync(info.data(), plan.info(), sizeof(int) * P, hipMemcpyDeviceToHost, st));

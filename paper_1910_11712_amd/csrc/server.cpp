@@ -468,7 +468,7 @@ bool Server::dispatch(Slot& s) {
   } else if (st == NEP_OK) {
     s.own = std::make_unique<MomentsPlan>();
     s.plan = s.own.get();
-    st = s.plan->build(probs, batch.front()->po);
+    st = s.plan->build(probs, batch.front()->po, s.st);
     if (st == NEP_OK) {
       enqueued = true;
       st = s.plan->enqueue(s.st, false);

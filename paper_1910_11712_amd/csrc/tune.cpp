@@ -64,7 +64,7 @@ int eff_paired(const SolvePlan& sp, int prec, const MomentsPlan::Knobs& k, int L
 
 }  // namespace
 
-nep_status MomentsPlan::apply(const Knobs& k) {
+nep_status MomentsPlan::apply(const Knobs& k, hipStream_t st) {
   solve_set_lg(sp_, k.lg, opt.L);
   sp_.paired = k.paired;
   if (k.jb != lu_.jb) {  // another panel width: a new LU schedule and prefix table
@@ -73,7 +73,8 @@ nep_status MomentsPlan::apply(const Knobs& k) {
     const size_t need = sizeof(int) * std::max<size_t>(1, lu_.prefix.size());
     if (dlu_prefix_.bytes < need) NEP_TRY(dlu_prefix_.alloc(need));
     if (!lu_.prefix.empty())
-      NEP_HIP(hipMemcpy(dlu_prefix_.p, lu_.prefix.data(), sizeof(int) * lu_.prefix.size(), hipMemcpyHostToDevice));
+      NEP_HIP(hipMemcpyAsync(dlu_prefix_.p, lu_.prefix.data(), sizeof(int) * lu_.prefix.size(),
+                             hipMemcpyHostToDevice, st));
   }
   lu_.small_min = k.small_min;
   lu_.early_fork = k.early_fork;
@@ -183,7 +184,7 @@ nep_status tune_plan(MomentsPlan& plan, hipStream_t st) {
     std::lock_guard<std::mutex> g(T.mu);
     auto it = T.cache.find(sig);
     if (it != T.cache.end()) {
-      NEP_TRY(plan.apply(it->second));
+      NEP_TRY(plan.apply(it->second, st));
       T.last.clear();
       T.last_chosen = -1;
       T.last_cached = 1;
@@ -205,7 +206,7 @@ nep_status tune_plan(MomentsPlan& plan, hipStream_t st) {
   if (lu.size() + sv.size() > 2) {
     float best_ms = FLT_MAX;
     auto measure = [&](const MomentsPlan::Knobs& k) -> nep_status {
-      NEP_TRY(plan.apply(k));
+      NEP_TRY(plan.apply(k, st));
       float ms = 0.f;
       NEP_TRY(plan.time_pass(st, reps, ms));
       rec.push_back(nep_tune_cand{k.lg, k.paired, k.small_min, k.early_fork, k.jb, ms});
@@ -242,7 +243,7 @@ nep_status tune_plan(MomentsPlan& plan, hipStream_t st) {
   } else {
     rec.push_back(nep_tune_cand{best.lg, best.paired, best.small_min, best.early_fork, best.jb, 0.f});  // nothing to choose
   }
-  NEP_TRY(plan.apply(best));
+  NEP_TRY(plan.apply(best, st));
   std::lock_guard<std::mutex> g(T.mu);
   T.cache[sig] = best;
   T.last = rec;
