@@ -539,6 +539,8 @@ typedef struct {
   int n_inside;          /* of which inside the contour                        */
   int reused;            /* 1: ran on resident factors (no assembly or LU)     */
   double t_submit, t_start, t_done;  /* seconds on the server clock            */
+  int L_used;            /* probe columns in the final moments (L, or more     */
+                         /* after augmentation from a probe pool)              */
 } nep_query_info;
 
 nep_status nep_server_create(const nep_server_opts* o, nep_server* out);
@@ -567,6 +569,22 @@ nep_status nep_server_submit(nep_server s, nep_split h, const nep_contour* g,
                              const nep_ciss_opts* o, const nep_extract_opts* e,
                              const void* V, double* lambda, double* eta,
                              int* inside, void* X, long long* ticket);
+
+/* As nep_server_submit, with a probe pool for rank saturation (Section 2:
+ * the moments resolve at most K*L eigenvalues; the count of eigenvalues
+ * inside is the number of roots of det T(z) there, eq. (nep)).
+ *   V: host, complex n x Lmax column-major, Lmax a multiple of L, at most
+ *   256 and at most n (copied before the call returns).  The query runs on
+ *   the first L columns; while its extraction finds the moment rank equal
+ *   to K*L_used and columns are left, the next L columns are solved on the
+ *   same factors (no assembly or LU), their moments join the others and the
+ *   extraction runs again on all L_used columns, as nep_eigs does on a
+ *   handle.  nep_query_info.L_used reports the columns used.  Lmax = L is
+ *   nep_server_submit. */
+nep_status nep_server_submit_pool(nep_server s, nep_split h, const nep_contour* g,
+                                  const nep_ciss_opts* o, const nep_extract_opts* e,
+                                  const void* V, int Lmax, double* lambda, double* eta,
+                                  int* inside, void* X, long long* ticket);
 
 /* Non-blocking: returns 1 in *done when the query has finished. */
 nep_status nep_server_poll(nep_server s, long long ticket, int* done,

@@ -76,7 +76,7 @@ class nep_server_opts(C.Structure):
 
 class nep_query_info(C.Structure):
     _fields_ = [("status", C.c_int), ("m", C.c_int), ("n_inside", C.c_int), ("reused", C.c_int),
-                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double), ("L_used", C.c_int)]
 
 
 class nep_tune_cand(C.Structure):
@@ -169,6 +169,9 @@ def lib():
         L.nep_server_submit.argtypes = [vp, vp, C.POINTER(nep_contour), C.POINTER(nep_ciss_opts),
                                         C.POINTER(nep_extract_opts), vp, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double), C.POINTER(ip), vp, C.POINTER(C.c_longlong)]
+        L.nep_server_submit_pool.argtypes = [vp, vp, C.POINTER(nep_contour), C.POINTER(nep_ciss_opts),
+                                             C.POINTER(nep_extract_opts), vp, C.c_int, C.POINTER(C.c_double),
+                                             C.POINTER(C.c_double), C.POINTER(ip), vp, C.POINTER(C.c_longlong)]
         L.nep_server_poll.argtypes = [vp, C.c_longlong, C.POINTER(ip), C.POINTER(nep_query_info)]
         L.nep_server_wait.argtypes = [vp, C.c_longlong, C.POINTER(nep_query_info)]
         L.nep_server_clock.argtypes = [vp]
@@ -523,9 +526,11 @@ def nep_server_create(hbm_budget, max_inflight=64, nstreams=4):
 
 
 def nep_server_submit(s, h, contour, opts, V, max_eigs=64, rank_tol=0.0, want_X=False, eta_tol=0.0, polish_its=0):
-    """Queues a query.  V: host complex (n, L).  Returns (ticket, out) where
-    out holds the host result arrays the server fills; keep it until the
-    query is collected."""
+    """Queues a query.  V: host complex (n, L), or (n, Lmax) with Lmax a
+    multiple of L: a probe pool whose further blocks of L columns are used
+    when the moment rank saturates (nep_server_submit_pool).  Returns (ticket,
+    out) where out holds the host result arrays the server fills; keep it
+    until the query is collected."""
     e = nep_extract_opts()
     e.rank_tol, e.eta_tol, e.max_eigs, e.polish_its = float(rank_tol), float(eta_tol), int(max_eigs), int(polish_its)
     Vf = np.asfortranarray(np.asarray(V, dtype=np.complex128))
@@ -536,17 +541,21 @@ def nep_server_submit(s, h, contour, opts, V, max_eigs=64, rank_tol=0.0, want_X=
            "opts": opts, "eopts": e, "contour": contour_struct(contour)}
     t = C.c_longlong(0)
     xp = C.c_void_p(out["X"].ctypes.data) if want_X else None
-    check(lib().nep_server_submit(s, h, C.byref(out["contour"]), C.byref(opts), C.byref(e),
-                                  C.c_void_p(Vf.ctypes.data), out["lam"].ctypes.data_as(C.POINTER(C.c_double)),
-                                  out["eta"].ctypes.data_as(C.POINTER(C.c_double)),
-                                  out["inside"].ctypes.data_as(C.POINTER(C.c_int)), xp, C.byref(t)))
+    res = (out["lam"].ctypes.data_as(C.POINTER(C.c_double)), out["eta"].ctypes.data_as(C.POINTER(C.c_double)),
+           out["inside"].ctypes.data_as(C.POINTER(C.c_int)), xp, C.byref(t))
+    if Vf.shape[1] == opts.L:
+        check(lib().nep_server_submit(s, h, C.byref(out["contour"]), C.byref(opts), C.byref(e),
+                                      C.c_void_p(Vf.ctypes.data), *res))
+    else:
+        check(lib().nep_server_submit_pool(s, h, C.byref(out["contour"]), C.byref(opts), C.byref(e),
+                                           C.c_void_p(Vf.ctypes.data), int(Vf.shape[1]), *res))
     return t.value, out
 
 
 def _query_result(info, out):
     k = info.m
     lam = out["lam"]
-    r = {"status": info.status, "m": k, "n_inside": info.n_inside, "reused": bool(info.reused),
+    r = {"status": info.status, "m": k, "n_inside": info.n_inside, "reused": bool(info.reused), "L_used": info.L_used,
          "t_submit": info.t_submit, "t_start": info.t_start, "t_done": info.t_done,
          "lam": lam[0:2 * k:2] + 1j * lam[1:2 * k:2], "eta": out["eta"][:k].copy(),
          "inside": out["inside"][:k] == 1, "unconverged": out["inside"][:k] == 2}

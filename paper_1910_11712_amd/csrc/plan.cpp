@@ -221,8 +221,10 @@ nep_status MomentsPlan::rebind(const std::vector<PlanProblem>& probs, hipStream_
 }
 
 nep_status MomentsPlan::rebind_members(const std::vector<int>& member, const std::vector<const c128*>& V,
-                                       const std::vector<c128*>& S, hipStream_t st) {
+                                       const std::vector<c128*>& S, hipStream_t st,
+                                       const std::vector<long long>* s_stride) {
   NEP_CHECK(member.size() == V.size() && member.size() == S.size(), NEP_ERR_ARG, "rebind: size mismatch");
+  NEP_CHECK(s_stride == nullptr || s_stride->size() == member.size(), NEP_ERR_ARG, "rebind: stride count");
   for (auto& D : hpd_) D.active = 0;
   for (size_t k = 0; k < member.size(); ++k) {
     const int p = member[k];
@@ -234,7 +236,8 @@ nep_status MomentsPlan::rebind_members(const std::vector<int>& member, const std
     D.S = S[k];
     D.zpts = nullptr;
     D.fpts = nullptr;
-    D.s_stride = (long long)D.n * D.L;
+    D.s_stride = s_stride != nullptr ? (*s_stride)[k] : (long long)D.n * D.L;
+    NEP_CHECK(D.s_stride >= (long long)D.n * D.L, NEP_ERR_ARG, "rebind: moment stride below n*L");
   }
   NEP_HIP(hipMemcpyAsync(dpd_.p, hpd_.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice, st));
   return NEP_OK;

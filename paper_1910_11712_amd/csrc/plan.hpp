@@ -176,8 +176,10 @@ class MomentsPlan {
   // problems take new probes V and moment buffers S (s_stride n*L), every
   // other problem sits out the pass (nothing of its operator is read, its
   // previous buffers are not touched).  The descriptor upload is queued on st.
+  // s_stride: elements between the moment blocks of each S (nullptr: n*L).
   nep_status rebind_members(const std::vector<int>& member, const std::vector<const c128*>& V,
-                            const std::vector<c128*>& S, hipStream_t st);
+                            const std::vector<c128*>& S, hipStream_t st,
+                            const std::vector<long long>* s_stride = nullptr);
   // Frees the FP64 re-solve buffers (allocated again if a later pass needs them).
   void release_fallback();
   bool matches(const std::vector<PlanProblem>& probs, const PlanOptions& o) const;

@@ -64,7 +64,8 @@ struct Query {
   nep_extract_opts e{};
   PlanOptions po;
   int n = 0;
-  std::vector<c128> V;  // host copy of the probes, freed at dispatch
+  int Lmax = 0;         // probe columns available: L, or a pool for rank augmentation
+  std::vector<c128> V;  // host copy of the probes (n x Lmax); freed at dispatch unless Lmax > L
   double* lambda = nullptr;
   double* eta = nullptr;
   int* inside = nullptr;
@@ -118,7 +119,7 @@ class Server {
   ~Server();
   nep_status init(const nep_server_opts* o);
   nep_status submit(nep_split h, const nep_contour* g, const nep_ciss_opts* o, const nep_extract_opts* e,
-                    const void* V, double* lambda, double* eta, int* inside, void* X, long long* ticket);
+                    const void* V, int Lmax, double* lambda, double* eta, int* inside, void* X, long long* ticket);
   nep_status poll(long long ticket, int* done, nep_query_info* info, bool block);
   double clock() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
@@ -162,7 +163,7 @@ Server::~Server() { shutdown(); }
 
 size_t Server::query_buffer_bytes(const Query& q) {
   const size_t c = sizeof(c128);
-  size_t b = (size_t)q.n * q.po.L * c * (1 + 2 * q.po.K);  // V and S
+  size_t b = (size_t)q.n * q.po.L * c + (size_t)q.n * q.Lmax * c * 2 * q.po.K;  // V (one block) and S
   b += (size_t)q.n * q.e.max_eigs * c;                     // X
   return b + (1u << 16);                                    // alignment
 }
@@ -226,7 +227,8 @@ nep_status Server::init(const nep_server_opts* o) {
 }
 
 nep_status Server::submit(nep_split h, const nep_contour* g, const nep_ciss_opts* o, const nep_extract_opts* e,
-                          const void* V, double* lambda, double* eta, int* inside, void* X, long long* ticket) {
+                          const void* V, int Lmax, double* lambda, double* eta, int* inside, void* X,
+                          long long* ticket) {
   NEP_CHECK(h != nullptr && ticket != nullptr, NEP_ERR_ARG, "null handle or ticket");
   NEP_CHECK(V != nullptr && lambda != nullptr && eta != nullptr && inside != nullptr, NEP_ERR_ARG,
             "null probe or result array");
@@ -239,6 +241,9 @@ nep_status Server::submit(nep_split h, const nep_contour* g, const nep_ciss_opts
   q->o = *o;
   q->e = *e;
   q->n = h->impl.op.n;
+  q->Lmax = Lmax > 0 ? Lmax : q->po.L;
+  NEP_CHECK(q->Lmax >= q->po.L && q->Lmax % q->po.L == 0 && q->Lmax <= 256 && q->Lmax <= q->n, NEP_ERR_ARG,
+            "probe pool of %d columns: a multiple of L=%d, at most 256 and at most n", q->Lmax, q->po.L);
   q->key.uid = h->impl.uid;
   q->key.g = *g;
   q->key.N = q->po.N;
@@ -256,13 +261,14 @@ nep_status Server::submit(nep_split h, const nep_contour* g, const nep_ciss_opts
   q->bytes = query_bytes(*q);
   NEP_CHECK(q->bytes <= budget_, NEP_ERR_BUSY, "query needs %zu bytes, more than the server's HBM budget %zu",
             q->bytes, budget_);
-  const size_t cnt = (size_t)q->n * q->po.L;
+  const size_t cnt = (size_t)q->n * q->Lmax;
   q->V.assign(static_cast<const c128*>(V), static_cast<const c128*>(V) + cnt);
   {
     std::lock_guard<std::mutex> lk(mu_);
     NEP_CHECK(!stop_, NEP_ERR_ARG, "server is shutting down");
     q->ticket = next_ticket_++;
     q->info.status = NEP_OK;
+    q->info.L_used = q->po.L;
     q->info.t_submit = clock();
     tickets_[q->ticket] = q;
     queue_.push_back(q);
@@ -440,7 +446,7 @@ bool Server::dispatch(Slot& s) {
     auto b = std::make_unique<QueryBuffers>();
     const size_t c = sizeof(c128), nl = (size_t)q->n * q->po.L;
     st = b->V.alloc(nl * c);
-    if (st == NEP_OK) st = b->S.alloc(nl * 2 * q->po.K * c);
+    if (st == NEP_OK) st = b->S.alloc((size_t)q->n * q->Lmax * 2 * q->po.K * c);
     if (st == NEP_OK) st = b->X.alloc((size_t)q->n * q->e.max_eigs * c);
     if (st != NEP_OK) break;
     if (hipMemcpyAsync(b->V.p, q->V.data(), nl * c, hipMemcpyHostToDevice, s.st) != hipSuccess) {
@@ -448,7 +454,8 @@ bool Server::dispatch(Slot& s) {
       st = NEP_ERR_DEVICE;
       break;
     }
-    probs.push_back(PlanProblem{&q->h->impl.op, q->g, b->V.as<c128>(), b->S.as<c128>()});
+    probs.push_back(PlanProblem{&q->h->impl.op, q->g, b->V.as<c128>(), b->S.as<c128>(), nullptr,
+                                (long long)q->n * q->Lmax});
     s.buf.push_back(std::move(b));
   }
   bool enqueued = false;
@@ -456,11 +463,13 @@ bool Server::dispatch(Slot& s) {
     s.plan = res->plan.get();
     std::vector<const c128*> Vs;
     std::vector<c128*> Ss;
-    for (auto& b : s.buf) {
-      Vs.push_back(b->V.as<c128>());
-      Ss.push_back(b->S.as<c128>());
+    std::vector<long long> strides;
+    for (size_t k = 0; k < s.buf.size(); ++k) {
+      Vs.push_back(s.buf[k]->V.as<c128>());
+      Ss.push_back(s.buf[k]->S.as<c128>());
+      strides.push_back((long long)batch[k]->n * batch[k]->Lmax);
     }
-    st = s.plan->rebind_members(member, Vs, Ss, s.st);
+    st = s.plan->rebind_members(member, Vs, Ss, s.st, &strides);
     if (st == NEP_OK) {
       enqueued = true;
       st = s.plan->enqueue(s.st, false, false);
@@ -505,7 +514,8 @@ bool Server::dispatch(Slot& s) {
     fail(batch, st);
     return true;
   }
-  for (auto& q : batch) std::vector<c128>().swap(q->V);  // the device holds the probes now
+  for (auto& q : batch)  // the device holds the probes now; a pool keeps its further blocks
+    if (q->Lmax == q->po.L) std::vector<c128>().swap(q->V);
   s.q = std::move(batch);
   s.member = std::move(member);
   s.bytes = bytes;
@@ -604,15 +614,49 @@ void Server::complete(Slot& s) {
       // the slot's own workspace, from the arena: no device allocation or
       // free here, and no state of the handle is touched, so slots complete
       // queries of the same operator concurrently
-      st = extract(q.h->impl, &q.g, &o, s.buf[k]->S.p, &q.e, &m, q.lambda, s.buf[k]->X.p, q.eta, q.inside, nullptr,
-                   s.xw.get());
-      // the extraction workspace grows from the arena: without room, idle
-      // resident plans give theirs up, least recently used first
-      while (st == NEP_ERR_OOM && evict_one()) {
-        (void)hipGetLastError();
-        st = extract(q.h->impl, &q.g, &o, s.buf[k]->S.p, &q.e, &m, q.lambda, s.buf[k]->X.p, q.eta, q.inside,
-                     nullptr, s.xw.get());
+      const long long sstride = (long long)q.n * q.Lmax;
+      int Lcur = q.po.L;
+      auto run_extract = [&]() {
+        nep_status r = extract_strided(q.h->impl, &q.g, &o, Lcur, s.buf[k]->S.p, sstride, &q.e, &m, q.lambda,
+                                       s.buf[k]->X.p, q.eta, q.inside, nullptr, s.xw.get());
+        // the extraction workspace grows from the arena: without room, idle
+        // resident plans give theirs up, least recently used first
+        while (r == NEP_ERR_OOM && evict_one()) {
+          (void)hipGetLastError();
+          r = extract_strided(q.h->impl, &q.g, &o, Lcur, s.buf[k]->S.p, sstride, &q.e, &m, q.lambda,
+                              s.buf[k]->X.p, q.eta, q.inside, nullptr, s.xw.get());
+        }
+        return r;
+      };
+      st = run_extract();
+      // Rank saturation (m = K * L) with probe columns left in the pool: the
+      // next block of probes is solved on the same factors (no assembly or
+      // LU), its moments land beside the others in S, and the extraction
+      // runs again on all probes so far, as nep_eigs does on a handle.
+      while (st == NEP_ERR_RANK && m == q.po.K * Lcur && Lcur < q.Lmax) {
+        const size_t blk = (size_t)q.n * q.po.L;
+        const size_t off = (size_t)(Lcur / q.po.L) * blk;
+        c128* Sb = s.buf[k]->S.as<c128>() + off;
+        const std::vector<long long> stv{sstride};
+        if (hipMemcpyAsync(s.buf[k]->V.p, q.V.data() + off, sizeof(c128) * blk, hipMemcpyHostToDevice, s.st) !=
+            hipSuccess) {
+          (void)hipGetLastError();
+          st = NEP_ERR_DEVICE;
+          break;
+        }
+        st = s.plan->rebind_members({(int)pk}, {s.buf[k]->V.as<c128>()}, {Sb}, s.st, &stv);
+        if (st == NEP_OK) st = s.plan->enqueue(s.st, false, false);
+        if (st == NEP_OK) {
+          // the pass's verdict for this problem (the others sat it out)
+          RunResult ra;
+          const nep_status fs = s.plan->finish(s.st, ra, true);
+          st = pk < ra.pstatus.size() ? ra.pstatus[pk] : (fs != NEP_OK ? fs : NEP_ERR_DEVICE);
+        }
+        if (st != NEP_OK) break;
+        Lcur += q.po.L;
+        st = run_extract();
       }
+      q.info.L_used = Lcur;
       if (st == NEP_OK && q.X != nullptr && m > 0) {
         if (hipMemcpyAsync(q.X, s.buf[k]->X.p, sizeof(c128) * (size_t)q.n * m, hipMemcpyDeviceToHost, s.st) !=
                 hipSuccess ||
@@ -741,7 +785,15 @@ nep_status nep_server_submit(nep_server s, nep_split h, const nep_contour* g, co
                              const nep_extract_opts* e, const void* V, double* lambda, double* eta, int* inside,
                              void* X, long long* ticket) {
   NEP_CHECK(s != nullptr, NEP_ERR_ARG, "null server");
-  return s->impl.submit(h, g, o, e, V, lambda, eta, inside, X, ticket);
+  return s->impl.submit(h, g, o, e, V, 0, lambda, eta, inside, X, ticket);
+}
+
+nep_status nep_server_submit_pool(nep_server s, nep_split h, const nep_contour* g, const nep_ciss_opts* o,
+                                  const nep_extract_opts* e, const void* V, int Lmax, double* lambda, double* eta,
+                                  int* inside, void* X, long long* ticket) {
+  NEP_CHECK(s != nullptr, NEP_ERR_ARG, "null server");
+  NEP_CHECK(Lmax >= 1, NEP_ERR_ARG, "Lmax must be >= 1");
+  return s->impl.submit(h, g, o, e, V, Lmax, lambda, eta, inside, X, ticket);
 }
 
 nep_status nep_server_poll(nep_server s, long long ticket, int* done, nep_query_info* info) {

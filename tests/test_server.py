@@ -223,3 +223,49 @@ def test_server_follow_up_runs_on_resident_factors(nep):
     assert [r["status"] for r in (s1, s2, s3, s4)] == [0] * 4
     assert [r["reused"] for r in (s1, s2, s3, s4)] == [False, False, False, True]
     assert np.array_equal(s3["lam"], alone2["lam"]) and np.array_equal(s4["lam"], alone3["lam"])
+
+
+def test_server_probe_pool_augments_saturated_query(nep):
+    """Delay problem with 9 eigenvalues inside circle(-1, 0.6) and K = 2: 8 and
+    16 probes saturate the moments' rank.  Submitted with a pool of 32 probe
+    columns, the query solves further blocks of 8 on the same factors until 24
+    resolve the rank, and returns what nep_eigs returns on a handle, bit for
+    bit, also when a second submission runs on the resident factors and
+    beside other queries.  Without a pool the query reports the saturation;
+    queries whose rank does not saturate use their first L columns only."""
+    B = nep.binding
+    p = wl.delay_problem(120, tau=1.0, seed=7)
+    con = Contour.circle(-1.0, 0.6)
+    N, L, K, Lmax = 32, 8, 2, 32
+    V = wl.probes(120, Lmax, 20)
+    op = nep.SplitOperator.from_problem(p)
+    X = torch.zeros((64, 120), dtype=torch.complex128, device="cuda")
+    ref = B.nep_eigs(op.h, con, B.opts_struct(N, L, K, "mixed"), nep.device_probes(V), Lmax, X, max_eigs=64)
+    assert ref["L_used"] == 24
+    others = [c for c in _mix_cases() if c[2] == N][:2]  # rational, same N, L, K: they share the batch
+    oops = [nep.SplitOperator.from_problem(c[0]) for c in others]
+    alone = [_alone(nep, o, c[1], c[5], c[2], c[3], c[4], "mixed", 32) for o, c in zip(oops, others)]
+    srv = nep.Server(hbm_budget=1 << 30, max_inflight=16, nstreams=2)
+    try:
+        tickets = [srv.submit(op, con, V, N, L, K, max_eigs=64)]
+        tickets += [srv.submit(o, c[1], np.hstack([c[5], wl.probes(c[0].n, L, 77)]), c[2], c[3], c[4],
+                               max_eigs=32) for o, c in zip(oops, others)]
+        res = [srv.wait(t) for t in tickets]
+        # after completion, the same key runs on the resident factors
+        res.append(srv.wait(srv.submit(op, con, V, N, L, K, max_eigs=64)))
+        res.append(srv.wait(srv.submit(op, con, V[:, :L], N, L, K, max_eigs=64)))  # no pool
+    finally:
+        srv.close()
+    for r in (res[0], res[3]):
+        assert r["status"] == 0 and r["L_used"] == 24 and r["m"] == ref["m"], (r["status"], r["L_used"], r["m"])
+        assert np.array_equal(r["lam"], ref["lam"])
+        assert np.array_equal(r["eta"], ref["eta"])
+        assert np.array_equal(r["inside"], ref["inside"])
+    assert res[3]["reused"] and res[4]["reused"]
+    assert B.ERRORS.get(res[4]["status"]) == "NEP_ERR_RANK" and res[4]["L_used"] == L
+    for r, a in zip(res[1:3], alone):
+        assert r["status"] == 0 and r["L_used"] == L
+        assert np.array_equal(r["lam"], a["lam"]) and np.array_equal(r["eta"], a["eta"])
+    for o in oops:
+        o.close()
+    op.close()
