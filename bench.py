@@ -34,6 +34,7 @@ METRIC = "quadrature solves/sec and eigenpairs/sec at 1e-10 rel residual; p50/p9
 PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6    # TFLOP/s, MI355X dense FP64 matrix
 HBM_PEAK = 8000.0        # GB/s
+POOL = 3                 # serving: probe blocks per query (augmentation on rank saturation)
 
 
 def _workload(name):
@@ -271,7 +272,9 @@ def _serve_run(P, prec, rate=200.0, duration=2.0, warmup=0.5, srv=None, ops=None
         ops = [P.SplitOperator.from_problem(wl.build_operator(o)) for o in cfg["ops"]]
         srv = P.Server(hbm_budget=96 << 30, max_inflight=64, nstreams=4)
     qs = cfg["queries"]
-    Vs = [wl.probes(cfg["ops"][q["op"]][1], q["L"], q["vseed"]) for q in qs]
+    # each query brings a pool of POOL probe blocks: the first is its L probes,
+    # the others are solved on the same factors only if the moment rank saturates
+    Vs = [np.hstack([wl.probes(cfg["ops"][q["op"]][1], q["L"], q["vseed"] + b) for b in range(POOL)]) for q in qs]
     tickets = []
     t0 = time.perf_counter()
     for q, V in zip(qs, Vs):
@@ -279,7 +282,7 @@ def _serve_run(P, prec, rate=200.0, duration=2.0, warmup=0.5, srv=None, ops=None
         if dt > 0:
             time.sleep(dt)
         tickets.append(srv.submit(ops[q["op"]], q["contour"], V, q["N"], q["L"], q["K"], prec=prec,
-                                  max_eigs=q["K"] * q["L"]))
+                                  max_eigs=q["K"] * q["L"] * POOL))
     res = [srv.wait(t) for t in tickets]
     if own:
         srv.close()
@@ -291,13 +294,14 @@ def _serve_run(P, prec, rate=200.0, duration=2.0, warmup=0.5, srv=None, ops=None
     span = max(r["t_done"] for _, r in meas) - min(r["t_submit"] for _, r in meas)
     good = sum(int(np.sum(r["inside"] & (r["eta"] <= 1e-10))) for r in ok)
     reused = sum(1 for _, r in meas if r.get("reused"))
+    augmented = sum(1 for q, r in meas if r.get("L_used", q["L"]) > q["L"])
     codes = {}
     for _, r in meas:
         codes[r["status"]] = codes.get(r["status"], 0) + 1
     return {"prec": prec, "rate_qps": rate, "window_s": duration, "queries": len(meas),
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "queries_per_s": len(meas) / span, "eigenpairs_eta_le_1e-10_per_s": good / span,
-            "reused": reused,
+            "reused": reused, "augmented": augmented, "probe_pool_blocks": POOL,
             "status_counts": {P.binding.ERRORS.get(k, "NEP_OK"): v for k, v in codes.items()}}
 
 

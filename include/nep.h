@@ -579,7 +579,9 @@ nep_status nep_server_submit(nep_server s, nep_split h, const nep_contour* g,
  *   to K*L_used and columns are left, the next L columns are solved on the
  *   same factors (no assembly or LU), their moments join the others and the
  *   extraction runs again on all L_used columns, as nep_eigs does on a
- *   handle.  nep_query_info.L_used reports the columns used.  Lmax = L is
+ *   handle.  nep_query_info.L_used reports the columns used.  The rank can
+ *   reach K*L_used, so max_eigs of K*Lmax holds every case (a larger rank
+ *   than max_eigs ends the query with NEP_ERR_ARG).  Lmax = L is
  *   nep_server_submit. */
 nep_status nep_server_submit_pool(nep_server s, nep_split h, const nep_contour* g,
                                   const nep_ciss_opts* o, const nep_extract_opts* e,
