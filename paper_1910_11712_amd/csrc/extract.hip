@@ -71,8 +71,8 @@ __device__ __forceinline__ c128 block_sum(c128 v, c128* red) {
 
 // Householder vector of column k (zlarfg convention): H^H x = beta e_1 with
 // H = I - tau v v^H, v_0 = 1, beta real.  v overwrites x below the diagonal.
-__global__ __launch_bounds__(1024) void k_house_vec(c128* __restrict__ B, long long M, int k, c128* __restrict__ tau) {
-  __shared__ c128 red[16];
+// One group of 1024 threads.
+__device__ void house_vec(c128* __restrict__ B, long long M, int k, c128* __restrict__ tau, c128* red) {
   c128* x = B + (long long)k * M;
   double ss = 0.0;
   for (long long i = k + 1 + threadIdx.x; i < M; i += blockDim.x) ss += norm2(x[i]);
@@ -95,9 +95,16 @@ __global__ __launch_bounds__(1024) void k_house_vec(c128* __restrict__ B, long l
   }
 }
 
-// b <- H^H b = b - conj(tau) v (v^H b) for columns k+1.. (one group each)
+__global__ __launch_bounds__(1024) void k_house_vec(c128* __restrict__ B, long long M, int k, c128* __restrict__ tau) {
+  __shared__ c128 red[16];
+  house_vec(B, M, k, tau, red);
+}
+
+// b <- H^H b = b - conj(tau) v (v^H b) for columns k+1.. (one group each).
+// The group of column k+1 then forms that column's Householder vector (the
+// next step's), so a step is one launch: only this group writes column k+1.
 __global__ __launch_bounds__(1024) void k_house_apply(c128* __restrict__ B, long long M, int k, int ncol,
-                                                      const c128* __restrict__ tau) {
+                                                      c128* __restrict__ tau) {
   __shared__ c128 red[16];
   const int col = k + 1 + blockIdx.x;
   if (col >= ncol) return;
@@ -110,6 +117,10 @@ __global__ __launch_bounds__(1024) void k_house_apply(c128* __restrict__ B, long
   const c128 f = conj(tau[k]) * w;
   if (threadIdx.x == 0) b[k] = b[k] - f;
   for (long long i = k + 1 + threadIdx.x; i < M; i += blockDim.x) b[i] = b[i] - v[i] * f;
+  if (blockIdx.x == 0) {
+    __syncthreads();  // the group's updates of column k+1 are visible to all its threads
+    house_vec(B, M, col, tau, red);
+  }
 }
 
 // X <- Q X = H_0 H_1 ... H_{r-1} X, one group per column of X (M x m)
@@ -478,13 +489,13 @@ nep_status extract_strided(Split& h, const nep_contour* g, const nep_ciss_opts* 
   hipLaunchKernelGGL(k_hankel, dim3((unsigned)ceil_div_ll(tot, 256)), dim3(256), 0, st, (const c128*)S, n, L, K,
                      sstride, B0, B1);
   NEP_HIP(hipGetLastError());
-  for (int k = 0; k < KL; ++k) {
-    hipLaunchKernelGGL(k_house_vec, dim3(1), dim3(1024), 0, st, B0, M, k, tau);
+  // column 0's vector, then one launch per step: H_k applied to columns
+  // k+1.., whose first group then forms column k+1's vector
+  hipLaunchKernelGGL(k_house_vec, dim3(1), dim3(1024), 0, st, B0, M, 0, tau);
+  NEP_HIP(hipGetLastError());
+  for (int k = 0; k + 1 < KL; ++k) {
+    hipLaunchKernelGGL(k_house_apply, dim3(KL - k - 1), dim3(1024), 0, st, B0, M, k, KL, tau);
     NEP_HIP(hipGetLastError());
-    if (k + 1 < KL) {
-      hipLaunchKernelGGL(k_house_apply, dim3(KL - k - 1), dim3(1024), 0, st, B0, M, k, KL, tau);
-      NEP_HIP(hipGetLastError());
-    }
   }
   // R (upper KL x KL) to host
   // (packed on the device and read back in one plain copy: a pitched
