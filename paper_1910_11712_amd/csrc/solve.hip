@@ -62,8 +62,12 @@ __device__ __forceinline__ void load_seg(const cx<P>* __restrict__ s, cx<P> (&v)
   }
 }
 
+// 256-thread groups with four rows per thread (the large class of big
+// batches, two or more groups per CU) are held to three waves per SIMD: 168
+// registers with a small spill, three groups per CU instead of two (the
+// 256-problem batch 204.4 -> 203.1 ms)
 template <typename P, int LG, int RPT, int NT>
-__global__ __launch_bounds__(NT) void k_trsv(const MatDesc* __restrict__ md, int nmat, int groups,
+__global__ __launch_bounds__(NT, (NT == 256 && RPT == 4) ? 3 : 1) void k_trsv(const MatDesc* __restrict__ md, int nmat, int groups,
                                                       const ProbDesc* __restrict__ pd, NodeArrays na,
                                                       const cx<P>* __restrict__ Tb, const int* __restrict__ rows,
                                                       const cx<P>* __restrict__ Dinv,
