@@ -197,55 +197,48 @@ __global__ __launch_bounds__(256) void k_eigvec(const c128* __restrict__ V0, lon
 }
 
 // Rt[row, q] = sum_i coef[i*m + q] (A_i x_q)[row]  (split-form T(lambda_q) x_q)
-// One group per (row tile of 64, q tile of 16); A tile staged through LDS.
-__global__ __launch_bounds__(256) void k_split_apply(const ProbDesc* __restrict__ pd_unused, int n, int ell, int m,
+// A and x tiles staged through LDS.
+__global__ __launch_bounds__(512) void k_split_apply(const ProbDesc* __restrict__ pd_unused, int n, int ell, int m,
                                                      const double* const* __restrict__ A, const int* __restrict__ cplx,
                                                      const c128* __restrict__ coef, const c128* __restrict__ X,
                                                      c128* __restrict__ Rt) {
-  __shared__ c128 As[64][33];
-  __shared__ c128 Xs[32][17];
-  const int row0 = blockIdx.x * 64, q0 = blockIdx.y * 16;
-  const int tr = threadIdx.x >> 2, tq = (threadIdx.x & 3) * 4;  // 64 rows x 4 groups of 4 columns
-  c128 out[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  // one group per 16 rows x 32 pairs, one output per thread: every A_i row
+  // is read by one group only, and n/16 groups keep the CUs busy; each
+  // output sums over k in ascending order
+  constexpr int RB = 16, QB = 32, KC = 64;
+  __shared__ c128 As[RB][KC + 1];
+  __shared__ c128 Xs[KC][QB + 1];
+  const int row0 = blockIdx.x * RB, q0 = blockIdx.y * QB;
+  const int tr = threadIdx.x >> 5, tq = threadIdx.x & 31;
+  c128 out = {0.0, 0.0};
   for (int i = 0; i < ell; ++i) {
-    c128 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-    for (int s0 = 0; s0 < n; s0 += 32) {
-      for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-        const int r = e >> 5, s = e & 31;
-        const int gr = row0 + r, gs = s0 + s;
+    c128 acc = {0.0, 0.0};
+    for (int s0 = 0; s0 < n; s0 += KC) {
+      for (int e = threadIdx.x; e < RB * KC; e += 512) {
+        const int r = e / KC, k = e - r * KC;
+        const int gr = row0 + r, gs = s0 + k;
         c128 a = {0.0, 0.0};
         if (gr < n && gs < n) {
           if (cplx[i]) a = reinterpret_cast<const c128*>(A[i])[(long long)gr * n + gs];
           else a.re = A[i][(long long)gr * n + gs];
         }
-        As[r][s] = a;
+        As[r][k] = a;
       }
-      for (int e = threadIdx.x; e < 32 * 16; e += 256) {
-        const int s = e >> 4, q = e & 15;
-        const int gs = s0 + s, gq = q0 + q;
-        Xs[s][q] = (gs < n && gq < m) ? X[(long long)gq * n + gs] : c128{0.0, 0.0};
-      }
-      __syncthreads();
-      for (int s = 0; s < 32; ++s) {
-        const c128 a = As[tr][s];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] = acc[u] + a * Xs[s][tq + u];
+      for (int e = threadIdx.x; e < KC * QB; e += 512) {
+        const int q = e / KC, k = e - q * KC;
+        const int gs = s0 + k, gq = q0 + q;
+        Xs[k][q] = (gs < n && gq < m) ? X[(long long)gq * n + gs] : c128{0.0, 0.0};
       }
       __syncthreads();
+#pragma unroll 8
+      for (int k = 0; k < KC; ++k) acc = acc + As[tr][k] * Xs[k][tq];
+      __syncthreads();
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int gq = q0 + tq + u;
-      if (gq < m) out[u] = out[u] + coef[(long long)i * m + gq] * acc[u];
-    }
+    const int gq = q0 + tq;
+    if (gq < m) out = out + coef[(long long)i * m + gq] * acc;
   }
-  const int gr = row0 + tr;
-  if (gr < n)
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int gq = q0 + tq + u;
-      if (gq < m) Rt[(long long)gq * n + gr] = out[u];
-    }
+  const int gr = row0 + tr, gq = q0 + tq;
+  if (gr < n && gq < m) Rt[(long long)gq * n + gr] = out;
 }
 
 // per column: max |Rt|, max |X|
@@ -332,8 +325,8 @@ static nep_status eta_run(Split& h, int m, const c128* lam, const c128* X, const
   NEP_HIP(hipMemcpyAsync(b.dA, hA, sizeof(void*) * ell, hipMemcpyHostToDevice, st));
   NEP_HIP(hipMemcpyAsync(b.dcp, h.op.is_cplx, sizeof(int) * ell, hipMemcpyHostToDevice, st));
   NEP_HIP(fn_points(h.op.dfn_nodes, h.op.dfn_coef, h.fn_roots.as<int>(), ell, b.z, m, b.fv, b.bad, st));
-  dim3 grid(ceil_div(n, 64), ceil_div(m, 16));
-  hipLaunchKernelGGL(k_split_apply, grid, dim3(256), 0, st, nullptr, n, ell, m, b.dA, b.dcp, b.fv, X, b.Rt);
+  dim3 grid(ceil_div(n, 16), ceil_div(m, 32));
+  hipLaunchKernelGGL(k_split_apply, grid, dim3(512), 0, st, nullptr, n, ell, m, b.dA, b.dcp, b.fv, X, b.Rt);
   NEP_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_colmax2, dim3(m), dim3(256), 0, st, b.Rt, X, n, b.norms);
   NEP_HIP(hipGetLastError());
