@@ -225,7 +225,8 @@ def test_server_follow_up_runs_on_resident_factors(nep):
     assert np.array_equal(s3["lam"], alone2["lam"]) and np.array_equal(s4["lam"], alone3["lam"])
 
 
-def test_server_probe_pool_augments_saturated_query(nep):
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_server_probe_pool_augments_saturated_query(nep, prec):
     """Delay problem with 9 eigenvalues inside circle(-1, 0.6) and K = 2: 8 and
     16 probes saturate the moments' rank.  Submitted with a pool of 32 probe
     columns, the query solves further blocks of 8 on the same factors until 24
@@ -240,20 +241,20 @@ def test_server_probe_pool_augments_saturated_query(nep):
     V = wl.probes(120, Lmax, 20)
     op = nep.SplitOperator.from_problem(p)
     X = torch.zeros((64, 120), dtype=torch.complex128, device="cuda")
-    ref = B.nep_eigs(op.h, con, B.opts_struct(N, L, K, "mixed"), nep.device_probes(V), Lmax, X, max_eigs=64)
+    ref = B.nep_eigs(op.h, con, B.opts_struct(N, L, K, prec), nep.device_probes(V), Lmax, X, max_eigs=64)
     assert ref["L_used"] == 24
     others = [c for c in _mix_cases() if c[2] == N][:2]  # rational, same N, L, K: they share the batch
     oops = [nep.SplitOperator.from_problem(c[0]) for c in others]
-    alone = [_alone(nep, o, c[1], c[5], c[2], c[3], c[4], "mixed", 32) for o, c in zip(oops, others)]
+    alone = [_alone(nep, o, c[1], c[5], c[2], c[3], c[4], prec, 32) for o, c in zip(oops, others)]
     srv = nep.Server(hbm_budget=1 << 30, max_inflight=16, nstreams=2)
     try:
-        tickets = [srv.submit(op, con, V, N, L, K, max_eigs=64)]
+        tickets = [srv.submit(op, con, V, N, L, K, prec=prec, max_eigs=64)]
         tickets += [srv.submit(o, c[1], np.hstack([c[5], wl.probes(c[0].n, L, 77)]), c[2], c[3], c[4],
-                               max_eigs=32) for o, c in zip(oops, others)]
+                               prec=prec, max_eigs=32) for o, c in zip(oops, others)]
         res = [srv.wait(t) for t in tickets]
         # after completion, the same key runs on the resident factors
-        res.append(srv.wait(srv.submit(op, con, V, N, L, K, max_eigs=64)))
-        res.append(srv.wait(srv.submit(op, con, V[:, :L], N, L, K, max_eigs=64)))  # no pool
+        res.append(srv.wait(srv.submit(op, con, V, N, L, K, prec=prec, max_eigs=64)))
+        res.append(srv.wait(srv.submit(op, con, V[:, :L], N, L, K, prec=prec, max_eigs=64)))  # no pool
     finally:
         srv.close()
     for r in (res[0], res[3]):
