@@ -219,9 +219,10 @@ def _tune_summary(B):
     return out
 
 
-def _batch_run(P, steps=5, tune=True):
+def _batch_run(P, steps=5, tune=True, prec="mixed"):
     """Config 3: 256 rational problems of uneven n (64..1024) in one plan,
-    the whole launch sequence replayed from a HIP graph."""
+    the whole launch sequence replayed from a HIP graph (prec: "mixed" or
+    "fp64")."""
     import torch
     import workloads as wl
     cfg = wl.config3()
@@ -230,7 +231,7 @@ def _batch_run(P, steps=5, tune=True):
     Vs = [P.device_probes(V) for V in cfg["V"]]
     Ss = [torch.empty((2 * K, L, p.n), dtype=torch.complex128, device="cuda") for p in cfg["problems"]]
     B = P.binding
-    o = B.opts_struct(N, L, K, "mixed")
+    o = B.opts_struct(N, L, K, prec)
     B.nep_tune_set(tune, 2)  # tuned before the graph is captured
     b = B.nep_batch_create([op.h for op in ops], [con] * len(ops), o, Vs, Ss, use_graph=True)
     B.nep_tune_set(False, 3)
@@ -444,6 +445,7 @@ def main():
         if args.workload != "cfg1":
             jobs.append(("cfg1_delay_n1000", lambda: _cfg1_run(P, args, tune=not args.no_tune)))
         jobs += [("cfg3_batch_graph", lambda: _batch_run(P, tune=not args.no_tune)),
+                 ("cfg3_batch_graph_fp64", lambda: _batch_run(P, steps=3, tune=not args.no_tune, prec="fp64")),
                  ("nleigs_batch_rational_256", lambda: _nleigs_batch_run(P)),
                  ("cfg4_serving_mixed", lambda: _serve_run(P, "mixed")),
                  ("cfg4_serving_fp64", lambda: _serve_run(P, "fp64"))]
@@ -453,6 +455,9 @@ def main():
             except Exception as e:  # reported, not hidden
                 extra[key] = {"error": repr(e)}
             print(f"[bench] {key} done", file=sys.stderr, flush=True)
+    b3, b3d = extra.get("cfg3_batch_graph", {}), extra.get("cfg3_batch_graph_fp64", {})
+    if "ms_per_batch" in b3 and "ms_per_batch" in b3d:
+        extra["cfg3_speedup_mixed_vs_fp64"] = b3d["ms_per_batch"] / b3["ms_per_batch"]
     cpu = None if args.no_cpu else _cpu_baseline(cfg)
     line = {"metric": METRIC, "value": round(value, 3), "unit": "quadrature solves/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_mixed * 1e3, 4),
