@@ -159,6 +159,29 @@ nep_status Split::init(int n_, int ell_, const nep_mat* A, const nep_fn* f, hipS
         op.is_diag[i] = 1;
         op.dDiag[i] = diags[i]->as<c128>();
       }
+      if (!diag && !cplx) {  // real banded terms: the residual applies their band rows
+        long long w = 0;
+        for (long long c = 0; c < n_ && w <= kBandMax; ++c)
+          for (long long r = 0; r < n_; ++r) {
+            const long long d = r > c ? r - c : c - r;
+            if (d > w && h[r + c * A[i].ld] != 0.0) w = d;
+          }
+        if (w >= 1 && w <= kBandMax) {
+          const int ww = (int)w, bwid = 2 * ww + 1;
+          std::vector<double> band((size_t)n_ * bwid, 0.0);
+          for (long long r = 0; r < n_; ++r)
+            for (int o = -ww; o <= ww; ++o) {
+              const long long c = r + o;
+              if (c >= 0 && c < n_) band[(size_t)r * bwid + (o + ww)] = h[r + c * A[i].ld];
+            }
+          bands[i] = std::make_unique<DevMem>();
+          NEP_TRY(bands[i]->alloc(sizeof(double) * band.size()));
+          NEP_HIP(hipMemcpyAsync(bands[i]->p, band.data(), sizeof(double) * band.size(), hipMemcpyHostToDevice,
+                                 stream));
+          op.band_w[i] = ww;
+          op.dBand[i] = bands[i]->as<double>();
+        }
+      }
     }
     NEP_HIP(inf_norm(mats[i]->p, n_, cplx, scratch, norms.as<double>() + i, stream));
     NEP_HIP(hipStreamSynchronize(stream));  // staging is released at scope end

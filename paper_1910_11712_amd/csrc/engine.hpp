@@ -11,6 +11,7 @@
 namespace nep {
 
 constexpr int kMaxTerms = 16;
+constexpr int kBandMax = 64;  // widest half-bandwidth kept in band form
 constexpr int kMaxMoments = 32;  // 2K
 constexpr int kSolveBlk = 64;    // triangular-solve block rows
 constexpr int kResidRealTM = 64, kResidRealTQ = 64;  // real-term residual tile: rows x real columns
@@ -48,6 +49,8 @@ struct ProbDesc {
   int a_is_cplx[kMaxTerms];
   int a_is_diag[kMaxTerms];        // diagonal A_i: residual applies d_r f_i y_r
   const c128* Adiag[kMaxTerms];
+  int a_bw[kMaxTerms];             // real banded A_i (half-bandwidth, 0: not banded):
+  const double* Aband[kMaxTerms];  // the real-term residual applies its band rows
   const c128* V;          // caller probes, column-major n x L
   c128* S;                // caller moments, column-major n x L x KK
   const c128* zpts;       // explicit points (N, device) instead of the contour's

@@ -201,6 +201,8 @@ nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs, h
       D.a_is_cplx[i] = i < q.op->ell ? q.op->is_cplx[i] : 0;
       D.a_is_diag[i] = i < q.op->ell ? q.op->is_diag[i] : 0;
       D.Adiag[i] = i < q.op->ell ? q.op->dDiag[i] : nullptr;
+      D.a_bw[i] = i < q.op->ell ? q.op->band_w[i] : 0;
+      D.Aband[i] = i < q.op->ell ? q.op->dBand[i] : nullptr;
       D.fn_root[i] = i < q.op->ell ? q.op->fn_root[i] : 0;
     }
     D.normA = q.op->dnormA;

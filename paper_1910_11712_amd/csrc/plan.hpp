@@ -74,6 +74,10 @@ struct SplitOperator {
   const void* dA[kMaxTerms] = {nullptr};  // device row-major copies
   int is_diag[kMaxTerms] = {0};           // A_i diagonal (detected at creation)
   const c128* dDiag[kMaxTerms] = {nullptr};  // its diagonal (n complex)
+  // real banded A_i (detected at creation, half-bandwidth 1..kBandMax): row r
+  // holds A[r][r-w .. r+w] at dBand[i][r*(2w+1)], zero outside the matrix
+  int band_w[kMaxTerms] = {0};
+  const double* dBand[kMaxTerms] = {nullptr};
   const double* dnormA = nullptr;
   std::vector<double> normA;
   const FnNode* dfn_nodes = nullptr;

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(64 * WR * WQ, 4) void k_resid_real(const ProbDesc* 
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
 
   for (int term = 0; term < D.ell; ++term) {
-    if (D.a_is_diag[term]) continue;  // applied in the epilogue
+    if (D.a_is_diag[term] || D.a_bw[term] > 0) continue;  // applied in the epilogue
     const double* __restrict__ A = reinterpret_cast<const double*>(D.A[term]);
     const c128 f = bcol_ok ? na.fz[(long long)(D.node0 + bnode) * kMaxTerms + term] : c128{0.0, 0.0};
     double ra[AU][2];
@@ -302,6 +302,21 @@ __global__ __launch_bounds__(64 * WR * WQ, 4) void k_resid_real(const ProbDesc* 
             const c128 y = {Yd[2 * ((long long)gr * NL + cc)], Yd[2 * ((long long)gr * NL + cc) + 1]};
             const c128 fz = na.fz[(long long)(D.node0 + node) * kMaxTerms + term];
             const c128 dy = (fz * D.Adiag[term][gr]) * y;
+            s += tcomp ? dy.im : dy.re;
+          }
+          // banded terms: f_i times the band row of A_i against y, s ascending
+          for (int term = 0; term < D.ell; ++term) {
+            const int w = D.a_bw[term];
+            if (w == 0) continue;
+            const double* __restrict__ brow = D.Aband[term] + (long long)gr * (2 * w + 1);
+            c128 ay = {0.0, 0.0};
+            const int s_lo = max(0, gr - w), s_hi = min(n - 1, gr + w);
+            for (int s2 = s_lo; s2 <= s_hi; ++s2) {
+              const double a = brow[s2 - gr + w];
+              ay.re += a * Yd[2 * ((long long)s2 * NL + cc)];
+              ay.im += a * Yd[2 * ((long long)s2 * NL + cc) + 1];
+            }
+            const c128 dy = na.fz[(long long)(D.node0 + node) * kMaxTerms + term] * ay;
             s += tcomp ? dy.im : dy.re;
           }
           val = (tcomp ? vv.im : vv.re) - s;
