@@ -4,6 +4,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <functional>
+#include <random>
+#include <thread>
 #include <memory>
 #include <string>
 #include <vector>
@@ -90,6 +93,133 @@ hipError_t inf_norm(const void* A, int n, int cplx, unsigned long long* scratch,
 hipError_t fn_points(const FnNode* nodes, const c128* coef, const int* roots, int ell, const c128* z, int m,
                      c128* out, int* bad, hipStream_t st);
 
+// Low-rank detection of a real n x n term (column-major h, leading dimension
+// ld), by a randomized range finder: Y = A Omega with k = rmax + 8 Gaussian
+// columns, Householder QR of Y, numerical rank r from R's diagonal, Q_r, and
+// H = A^T Q_r, so that A ~ Q_r H^T.  The factorization is kept only if four
+// random probes z give ||A z - Q_r (H^T z)|| <= 1e-15 ||A||_F ||z||: the
+// approximation error is then at the level of the entries' own rounding.
+// Returns r (0: not low rank); G = Q_r and H are n x r row-major.
+static void par_for(int n, const std::function<void(int, int)>& body) {
+  const int nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  const int chunk = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    const int a = t * chunk, b = std::min(n, a + chunk);
+    if (a < b) th.emplace_back(body, a, b);
+  }
+  for (auto& x : th) x.join();
+}
+
+static int detect_low_rank(int n, const double* h, long long ld, int rmax, std::vector<double>& G,
+                           std::vector<double>& H) {
+  const int k = rmax + 8;
+  if (n < 4 * k) return 0;
+  std::mt19937_64 gen(12345);
+  std::normal_distribution<double> nd;
+  std::vector<double> Om((size_t)n * k);  // row c: Omega[c][0..k)
+  for (auto& x : Om) x = nd(gen);
+  std::vector<double> Y((size_t)k * n, 0.0);  // column j of Y at Y[j*n]
+  par_for(n, [&](int r0, int r1) {
+    for (int c = 0; c < n; ++c) {
+      const double* a = h + (long long)c * ld;
+      const double* om = &Om[(size_t)c * k];
+      for (int j = 0; j < k; ++j) {
+        const double w = om[j];
+        double* y = &Y[(size_t)j * n];
+        for (int r = r0; r < r1; ++r) y[r] += a[r] * w;
+      }
+    }
+  });
+  // Householder QR of Y (n x k), reflectors kept in place
+  std::vector<double> tau(k, 0.0), diag(k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    double* x = &Y[(size_t)j * n];
+    double s2 = 0.0;
+    for (int r = j + 1; r < n; ++r) s2 += x[r] * x[r];
+    const double alpha = x[j];
+    const double nrm = std::sqrt(alpha * alpha + s2);
+    if (nrm == 0.0) { diag[j] = 0.0; continue; }
+    const double beta = alpha >= 0.0 ? -nrm : nrm;
+    tau[j] = (beta - alpha) / beta;
+    const double scal = 1.0 / (alpha - beta);
+    for (int r = j + 1; r < n; ++r) x[r] *= scal;
+    x[j] = beta;
+    diag[j] = std::fabs(beta);
+    for (int jj = j + 1; jj < k; ++jj) {
+      double* b = &Y[(size_t)jj * n];
+      double w = b[j];
+      for (int r = j + 1; r < n; ++r) w += x[r] * b[r];
+      w *= tau[j];
+      b[j] -= w;
+      for (int r = j + 1; r < n; ++r) b[r] -= x[r] * w;
+    }
+  }
+  int rk = 0;
+  while (rk < k && diag[rk] > 1e-11 * diag[0]) ++rk;
+  if (rk == 0 || rk > rmax) return 0;
+  // Q_r = H_0 ... H_{k-1} applied to the first rk unit columns
+  std::vector<double> Q((size_t)rk * n, 0.0);
+  for (int j = 0; j < rk; ++j) {
+    double* q = &Q[(size_t)j * n];
+    q[j] = 1.0;
+    for (int i = k - 1; i >= 0; --i) {
+      if (tau[i] == 0.0) continue;
+      const double* v = &Y[(size_t)i * n];
+      double w = q[i];
+      for (int r = i + 1; r < n; ++r) w += v[r] * q[r];
+      w *= tau[i];
+      q[i] -= w;
+      for (int r = i + 1; r < n; ++r) q[r] -= v[r] * w;
+    }
+  }
+  // H = A^T Q_r: H[c][j] = column c of A against q_j
+  H.assign((size_t)n * rk, 0.0);
+  par_for(n, [&](int c0, int c1) {
+    for (int c = c0; c < c1; ++c) {
+      const double* a = h + (long long)c * ld;
+      for (int j = 0; j < rk; ++j) {
+        const double* q = &Q[(size_t)j * n];
+        double d = 0.0;
+        for (int r = 0; r < n; ++r) d += a[r] * q[r];
+        H[(size_t)c * rk + j] = d;
+      }
+    }
+  });
+  // a posteriori check with random probes
+  double fro2 = 0.0;
+  for (int c = 0; c < n; ++c)
+    for (int r = 0; r < n; ++r) fro2 += h[(long long)c * ld + r] * h[(long long)c * ld + r];
+  const double fro = std::sqrt(fro2);
+  std::vector<double> z(n), az(n), hz(rk);
+  for (int t = 0; t < 4; ++t) {
+    double zn = 0.0;
+    for (auto& x : z) { x = nd(gen); zn += x * x; }
+    zn = std::sqrt(zn);
+    std::fill(az.begin(), az.end(), 0.0);
+    for (int c = 0; c < n; ++c) {
+      const double* a = h + (long long)c * ld;
+      for (int r = 0; r < n; ++r) az[r] += a[r] * z[c];
+    }
+    for (int j = 0; j < rk; ++j) {
+      double d = 0.0;
+      for (int c = 0; c < n; ++c) d += H[(size_t)c * rk + j] * z[c];
+      hz[j] = d;
+    }
+    double e2 = 0.0;
+    for (int r = 0; r < n; ++r) {
+      double g = 0.0;
+      for (int j = 0; j < rk; ++j) g += Q[(size_t)j * n + r] * hz[j];
+      e2 += (az[r] - g) * (az[r] - g);
+    }
+    if (!(std::sqrt(e2) <= 1e-15 * fro * zn)) return 0;
+  }
+  G.assign((size_t)n * rk, 0.0);
+  for (int j = 0; j < rk; ++j)
+    for (int r = 0; r < n; ++r) G[(size_t)r * rk + j] = Q[(size_t)j * n + r];
+  return rk;
+}
+
 nep_status Split::init(int n_, int ell_, const nep_mat* A, const nep_fn* f, hipStream_t st) {
   stream = st;
   op.n = n_;
@@ -159,7 +289,7 @@ nep_status Split::init(int n_, int ell_, const nep_mat* A, const nep_fn* f, hipS
         op.is_diag[i] = 1;
         op.dDiag[i] = diags[i]->as<c128>();
       }
-      if (!diag && !cplx) {  // real banded terms: the residual applies their band rows
+      if (!diag && !cplx) {  // real banded terms: the residual runs over their band only
         long long w = 0;
         for (long long c = 0; c < n_ && w <= kBandMax; ++c)
           for (long long r = 0; r < n_; ++r) {
@@ -167,19 +297,21 @@ nep_status Split::init(int n_, int ell_, const nep_mat* A, const nep_fn* f, hipS
             if (d > w && h[r + c * A[i].ld] != 0.0) w = d;
           }
         if (w >= 1 && w <= kBandMax) {
-          const int ww = (int)w, bwid = 2 * ww + 1;
-          std::vector<double> band((size_t)n_ * bwid, 0.0);
-          for (long long r = 0; r < n_; ++r)
-            for (int o = -ww; o <= ww; ++o) {
-              const long long c = r + o;
-              if (c >= 0 && c < n_) band[(size_t)r * bwid + (o + ww)] = h[r + c * A[i].ld];
-            }
-          bands[i] = std::make_unique<DevMem>();
-          NEP_TRY(bands[i]->alloc(sizeof(double) * band.size()));
-          NEP_HIP(hipMemcpyAsync(bands[i]->p, band.data(), sizeof(double) * band.size(), hipMemcpyHostToDevice,
-                                 stream));
-          op.band_w[i] = ww;
-          op.dBand[i] = bands[i]->as<double>();
+          op.band_w[i] = (int)w;
+        } else if (w > kBandMax) {  // real low-rank terms: the residual applies G (H^T y)
+          std::vector<double> hG, hH;
+          const int rk = detect_low_rank(n_, h, A[i].ld, std::min(kLowRankMax, n_ / 8), hG, hH);
+          if (rk > 0) {
+            lrG[i] = std::make_unique<DevMem>();
+            lrH[i] = std::make_unique<DevMem>();
+            NEP_TRY(lrG[i]->alloc(sizeof(double) * hG.size()));
+            NEP_TRY(lrH[i]->alloc(sizeof(double) * hH.size()));
+            NEP_HIP(hipMemcpyAsync(lrG[i]->p, hG.data(), sizeof(double) * hG.size(), hipMemcpyHostToDevice, stream));
+            NEP_HIP(hipMemcpyAsync(lrH[i]->p, hH.data(), sizeof(double) * hH.size(), hipMemcpyHostToDevice, stream));
+            op.lr_rank[i] = rk;
+            op.dLrG[i] = lrG[i]->as<double>();
+            op.dLrH[i] = lrH[i]->as<double>();
+          }
         }
       }
     }

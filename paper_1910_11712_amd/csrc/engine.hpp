@@ -12,6 +12,7 @@ namespace nep {
 
 constexpr int kMaxTerms = 16;
 constexpr int kBandMax = 64;  // widest half-bandwidth kept in band form
+constexpr int kLowRankMax = 96;  // largest rank kept in factored form
 constexpr int kMaxMoments = 32;  // 2K
 constexpr int kSolveBlk = 64;    // triangular-solve block rows
 constexpr int kResidRealTM = 64, kResidRealTQ = 64;  // real-term residual tile: rows x real columns
@@ -49,8 +50,11 @@ struct ProbDesc {
   int a_is_cplx[kMaxTerms];
   int a_is_diag[kMaxTerms];        // diagonal A_i: residual applies d_r f_i y_r
   const c128* Adiag[kMaxTerms];
-  int a_bw[kMaxTerms];             // real banded A_i (half-bandwidth, 0: not banded):
-  const double* Aband[kMaxTerms];  // the real-term residual applies its band rows
+  int a_bw[kMaxTerms];             // real banded A_i (half-bandwidth, 0: not banded): the
+                                   // real-term residual runs over the band's k only
+  int a_lr[kMaxTerms];             // real low-rank A_i = G H^T (rank, 0: not factored):
+  const double* LrG[kMaxTerms];    // the real-term residual applies G (H^T Y), with
+  c128* LrZ[kMaxTerms];            // Z = H^T Y (rank x N*L) formed before it
   const c128* V;          // caller probes, column-major n x L
   c128* S;                // caller moments, column-major n x L x KK
   const c128* zpts;       // explicit points (N, device) instead of the contour's
@@ -149,8 +153,16 @@ void SolvePlan_build(SolvePlan& sp, std::vector<int>& buf, const std::vector<Mat
                      std::vector<long long>& dinv_off, long long& dinv_elems);
 hipError_t solve_configure();
 
+// One low-rank term of one problem: Z = H^T Y (rank x N*L) for the residual.
+struct LrJob {
+  const double* H;  // n x r row-major
+  c128* Z;          // r x NL row-major
+  long long offY;   // the problem's Y block
+  int n, r, NL;
+};
 hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const Table& tr, int resid_big, const NodeArrays& na,
-                     const c128* Y, c128* R, IrState ir, int nnodes, hipStream_t st);
+                     const c128* Y, c128* R, IrState ir, int nnodes, hipStream_t st, const LrJob* lr = nullptr,
+                     int nlr = 0);
 // status read-back block (see k_gather_status) and its size
 size_t status_bytes(int G);
 hipError_t gather_status(IrState ir, const int* info, const int* bad, int G, void* out, hipStream_t st);

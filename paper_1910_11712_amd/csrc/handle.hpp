@@ -21,7 +21,7 @@ struct Split {
   hipStream_t last_stream = nullptr;
   std::unique_ptr<DevMem> mats[kMaxTerms];
   std::unique_ptr<DevMem> diags[kMaxTerms];
-  std::unique_ptr<DevMem> bands[kMaxTerms];
+  std::unique_ptr<DevMem> lrG[kMaxTerms], lrH[kMaxTerms];
   DevMem norms, fn_nodes, fn_coef, fn_roots;
   std::unique_ptr<MomentsPlan> plan;  // resident factors of the last call
   std::shared_ptr<ExtractWork> xw;

@@ -185,9 +185,28 @@ bool MomentsPlan::matches(const std::vector<PlanProblem>& probs, const PlanOptio
 }
 
 nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs, hipStream_t st) {
+  // Z blocks of the low-rank terms of real problems (the complex-term
+  // residual multiplies every term densely)
+  size_t zelems = 0;
+  for (int p = 0; p < nprob; ++p)
+    if (!probs[p].op->a_cplx)
+      for (int i = 0; i < probs[p].op->ell; ++i) zelems += (size_t)probs[p].op->lr_rank[i] * opt.N * opt.L;
+  if (zelems > 0 && dlrz_.bytes < sizeof(c128) * zelems) NEP_TRY(dlrz_.alloc(sizeof(c128) * zelems));
+  lr_jobs_.clear();
+  size_t zoff = 0;
   for (int p = 0; p < nprob; ++p) {
     ProbDesc& D = hpd_[p];
     const PlanProblem& q = probs[p];
+    for (int i = 0; i < kMaxTerms; ++i) {
+      const int rk = (i < q.op->ell && !q.op->a_cplx) ? q.op->lr_rank[i] : 0;
+      D.a_lr[i] = rk;
+      D.LrG[i] = rk > 0 ? q.op->dLrG[i] : nullptr;
+      D.LrZ[i] = rk > 0 ? dlrz_.as<c128>() + zoff : nullptr;
+      if (rk > 0) {
+        lr_jobs_.push_back(LrJob{q.op->dLrH[i], dlrz_.as<c128>() + zoff, D.offY, D.n, rk, opt.N * opt.L});
+        zoff += (size_t)rk * opt.N * opt.L;
+      }
+    }
     D.kind = q.g.kind;
     D.c = c128{q.g.c[0], q.g.c[1]};
     D.rho = q.g.rho;
@@ -202,7 +221,6 @@ nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs, h
       D.a_is_diag[i] = i < q.op->ell ? q.op->is_diag[i] : 0;
       D.Adiag[i] = i < q.op->ell ? q.op->dDiag[i] : nullptr;
       D.a_bw[i] = i < q.op->ell ? q.op->band_w[i] : 0;
-      D.Aband[i] = i < q.op->ell ? q.op->dBand[i] : nullptr;
       D.fn_root[i] = i < q.op->ell ? q.op->fn_root[i] : 0;
     }
     D.normA = q.op->dnormA;
@@ -461,7 +479,8 @@ nep_status MomentsPlan::enqueue_t(hipStream_t st, bool eager, bool refactor) {
     // trip; nodes already converged skip the solve, which makes it a no-op
     // when the count turns out to be zero.
     for (int s = 0; s <= opt.max_refine; ++s) {
-      NEP_HIP(resid_run(pd, pre, pt_.resid, pt_.resid_real, pt_.resid_big, na_, Y, R, ir_, nnodes, st));
+      NEP_HIP(resid_run(pd, pre, pt_.resid, pt_.resid_real, pt_.resid_big, na_, Y, R, ir_, nnodes, st,
+                        lr_jobs_.data(), (int)lr_jobs_.size()));
       NEP_HIP(ir_control(pd, na_, ir_, nnodes, s, opt.tol, st));
       sweeps_run_ = s;
       if (eager) {
@@ -560,7 +579,8 @@ nep_status MomentsPlan::run_fallback(hipStream_t st) {
   NEP_HIP(solve_run<double>(sp_, pd, md, na_, T, drows_.as<int>(), Dinv, doff, nullptr, dY_.as<c128>(), false,
                             skip, ir_, st));
   for (int s = 0;; ++s) {
-    NEP_HIP(resid_run(pd, pre, pt_.resid, pt_.resid_real, pt_.resid_big, na_, dY_.as<c128>(), dR_.as<c128>(), ir_, nnodes, st));
+    NEP_HIP(resid_run(pd, pre, pt_.resid, pt_.resid_real, pt_.resid_big, na_, dY_.as<c128>(), dR_.as<c128>(), ir_, nnodes, st,
+                      lr_jobs_.data(), (int)lr_jobs_.size()));
     NEP_HIP(ir_control(pd, na_, ir_, nnodes, opt.max_refine + 1 + s, opt.tol, st));
     if (s == kFallbackSweeps) break;
     NEP_HIP(hipMemcpyAsync(hcounter_, ir_.counters, sizeof(int), hipMemcpyDeviceToHost, st));

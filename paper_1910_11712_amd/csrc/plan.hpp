@@ -74,10 +74,14 @@ struct SplitOperator {
   const void* dA[kMaxTerms] = {nullptr};  // device row-major copies
   int is_diag[kMaxTerms] = {0};           // A_i diagonal (detected at creation)
   const c128* dDiag[kMaxTerms] = {nullptr};  // its diagonal (n complex)
-  // real banded A_i (detected at creation, half-bandwidth 1..kBandMax): row r
-  // holds A[r][r-w .. r+w] at dBand[i][r*(2w+1)], zero outside the matrix
+  // real banded A_i (detected at creation, half-bandwidth 1..kBandMax): the
+  // real-term residual runs each tile over its rows' band only
   int band_w[kMaxTerms] = {0};
-  const double* dBand[kMaxTerms] = {nullptr};
+  // real low-rank A_i = G H^T (detected at creation, rank 1..kLowRankMax):
+  // G and H n x r row-major (device)
+  int lr_rank[kMaxTerms] = {0};
+  const double* dLrG[kMaxTerms] = {nullptr};
+  const double* dLrH[kMaxTerms] = {nullptr};
   const double* dnormA = nullptr;
   std::vector<double> normA;
   const FnNode* dfn_nodes = nullptr;
@@ -224,6 +228,8 @@ class MomentsPlan {
   nep_status solve_rhs_t(hipStream_t st);
 
   std::vector<ProbDesc> hpd_;
+  std::vector<LrJob> lr_jobs_;  // low-rank terms of real problems (Z = H^T Y per residual)
+  DevMem dlrz_;                 // their Z blocks
   std::vector<MatDesc> sorted_;
   std::vector<int> prob_of_sorted_;
   LuPlan lu_;

@@ -218,8 +218,17 @@ __global__ __launch_bounds__(64 * WR * WQ, 4) void k_resid_real(const ProbDesc* 
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
 
   for (int term = 0; term < D.ell; ++term) {
-    if (D.a_is_diag[term] || D.a_bw[term] > 0) continue;  // applied in the epilogue
-    const double* __restrict__ A = reinterpret_cast<const double*>(D.A[term]);
+    if (D.a_is_diag[term]) continue;  // applied in the epilogue
+    // a low-rank term G H^T runs as the product of G (n x r) with Z = H^T Y
+    // (r x N*L, formed before this kernel): the same loop over k < r; a
+    // banded term of half-width w runs over the k of the tile rows' band
+    // only, [row0 - w, row0 + TM + w) (the other products are by zeros)
+    const int lr = D.a_lr[term], bw = D.a_bw[term];
+    const double* __restrict__ A = lr > 0 ? D.LrG[term] : reinterpret_cast<const double*>(D.A[term]);
+    const int lda = lr > 0 ? lr : n;
+    const int kend = lr > 0 ? lr : (bw > 0 ? min(n, row0 + TM + bw) : n);
+    const int kbeg = (lr == 0 && bw > 0) ? (max(0, row0 - bw) / kR2KC) * kR2KC : 0;
+    const c128* __restrict__ Bsrc = lr > 0 ? D.LrZ[term] : Yp;
     const c128 f = bcol_ok ? na.fz[(long long)(D.node0 + bnode) * kMaxTerms + term] : c128{0.0, 0.0};
     double ra[AU][2];
     c128 rb[BU];
@@ -227,16 +236,16 @@ __global__ __launch_bounds__(64 * WR * WQ, 4) void k_resid_real(const ProbDesc* 
 #pragma unroll
       for (int u = 0; u < AU; ++u) {
         const int gr = row0 + tid / KP + (NT / KP) * u, gk = k0 + 2 * akp;
-        const double* src = A + (long long)min(gr, n - 1) * n;
-        const double a0 = src[min(gk, n - 1)], a1 = src[min(gk + 1, n - 1)];
-        ra[u][0] = (gr < n && gk < n) ? a0 : 0.0;
-        ra[u][1] = (gr < n && gk + 1 < n) ? a1 : 0.0;
+        const double* src = A + (long long)min(gr, n - 1) * lda;
+        const double a0 = src[min(gk, kend - 1)], a1 = src[min(gk + 1, kend - 1)];
+        ra[u][0] = (gr < n && gk < kend) ? a0 : 0.0;
+        ra[u][1] = (gr < n && gk + 1 < kend) ? a1 : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < BU; ++u) {
         const int s = k0 + tid / (TQ / 2) + (2 * NT / TQ) * u;
-        const c128 y = Yp[(long long)min(s, n - 1) * NL + (bcol_ok ? bcc : 0)];
-        rb[u] = (s < n && bcol_ok) ? f * y : c128{0.0, 0.0};
+        const c128 y = Bsrc[(long long)min(s, kend - 1) * NL + (bcol_ok ? bcc : 0)];
+        rb[u] = (s < kend && bcol_ok) ? f * y : c128{0.0, 0.0};
       }
     };
     auto store = [&](int buf) {
@@ -253,13 +262,13 @@ __global__ __launch_bounds__(64 * WR * WQ, 4) void k_resid_real(const ProbDesc* 
         Bs[buf][k][2 * bcl + 1] = rb[u].im;
       }
     };
-    const int nk = (n + kR2KC - 1) / kR2KC;
-    load(0);
+    const int nk = (kend - kbeg + kR2KC - 1) / kR2KC;
+    load(kbeg);
     store(0);
     __syncthreads();
     for (int ks = 0; ks < nk; ++ks) {
       const int buf = ks & 1;
-      if (ks + 1 < nk) load((ks + 1) * kR2KC);
+      if (ks + 1 < nk) load(kbeg + (ks + 1) * kR2KC);
 #pragma unroll
       for (int kk = 0; kk < kR2KC; kk += 4) {
         double af[MI], bf[MJ];
@@ -304,21 +313,6 @@ __global__ __launch_bounds__(64 * WR * WQ, 4) void k_resid_real(const ProbDesc* 
             const c128 dy = (fz * D.Adiag[term][gr]) * y;
             s += tcomp ? dy.im : dy.re;
           }
-          // banded terms: f_i times the band row of A_i against y, s ascending
-          for (int term = 0; term < D.ell; ++term) {
-            const int w = D.a_bw[term];
-            if (w == 0) continue;
-            const double* __restrict__ brow = D.Aband[term] + (long long)gr * (2 * w + 1);
-            c128 ay = {0.0, 0.0};
-            const int s_lo = max(0, gr - w), s_hi = min(n - 1, gr + w);
-            for (int s2 = s_lo; s2 <= s_hi; ++s2) {
-              const double a = brow[s2 - gr + w];
-              ay.re += a * Yd[2 * ((long long)s2 * NL + cc)];
-              ay.im += a * Yd[2 * ((long long)s2 * NL + cc) + 1];
-            }
-            const c128 dy = na.fz[(long long)(D.node0 + node) * kMaxTerms + term] * ay;
-            s += tcomp ? dy.im : dy.re;
-          }
           val = (tcomp ? vv.im : vv.re) - s;
           Rd[(long long)gr * Q + q] = val;
         }
@@ -332,13 +326,52 @@ __global__ __launch_bounds__(64 * WR * WQ, 4) void k_resid_real(const ProbDesc* 
   }
 }
 
+// Z = H^T Y for one low-rank term of one problem: H n x r (row-major, real),
+// Y n x NL (row-major, complex), Z r x NL.  One group per 16 rows of Z by 16
+// columns, one output per thread, s ascending in chunks of 64.
+__global__ __launch_bounds__(256) void k_lr_z(const double* __restrict__ H, const c128* __restrict__ Y,
+                                              c128* __restrict__ Z, int n, int r, int NL) {
+  constexpr int KC = 64;
+  __shared__ double Hs[KC][17];
+  __shared__ c128 Ys[KC][17];
+  const int k0 = blockIdx.x * 16, c0 = blockIdx.y * 16;
+  const int tk = threadIdx.x >> 4, tc = threadIdx.x & 15;
+  c128 acc = {0.0, 0.0};
+  for (int s0 = 0; s0 < n; s0 += KC) {
+    for (int e = threadIdx.x; e < KC * 16; e += 256) {
+      const int s = e >> 4, j = e & 15;
+      const int gs = s0 + s;
+      Hs[s][j] = (gs < n && k0 + j < r) ? H[(long long)gs * r + k0 + j] : 0.0;
+      Ys[s][j] = (gs < n && c0 + j < NL) ? Y[(long long)gs * NL + c0 + j] : c128{0.0, 0.0};
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int s = 0; s < KC; ++s) {
+      const double h = Hs[s][tk];
+      const c128 y = Ys[s][tc];
+      acc.re += h * y.re;
+      acc.im += h * y.im;
+    }
+    __syncthreads();
+  }
+  if (k0 + tk < r && c0 + tc < NL) Z[(long long)(k0 + tk) * NL + c0 + tc] = acc;
+}
+
 // t: tiles of the complex-term kernel (64 x 64); tr: tiles of the real-term
 // kernel (resid_big: kResidBigTM x kResidBigTQ, else kResidRealTM x
 // kResidRealTQ).  A problem counts in exactly one of them.  Every tile shape
 // issues the same products in the same order for each element (terms in
 // order, k ascending in steps of 4), so the choice does not change results.
 hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const Table& tr, int resid_big,
-                     const NodeArrays& na, const c128* Y, c128* R, IrState ir, int /*nnodes*/, hipStream_t st) {
+                     const NodeArrays& na, const c128* Y, c128* R, IrState ir, int /*nnodes*/, hipStream_t st,
+                     const LrJob* lr, int nlr) {
+  for (int j = 0; j < nlr; ++j) {  // Z = H^T Y of every low-rank term, before the products that use it
+    const LrJob& J = lr[j];
+    hipLaunchKernelGGL(k_lr_z, dim3((J.r + 15) / 16, (J.NL + 15) / 16), dim3(256), 0, st, J.H, Y + J.offY, J.Z, J.n,
+                       J.r, J.NL);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (tr.total > 0) {
     constexpr int WR = 4, WQ = 2;  // 8 waves
     if (resid_big)  // waves of 32 x 64: twice the reuse of each staged element
