@@ -97,8 +97,9 @@ hipError_t fn_points(const FnNode* nodes, const c128* coef, const int* roots, in
 // ld), by a randomized range finder: Y = A Omega with k = rmax + 8 Gaussian
 // columns, Householder QR of Y, numerical rank r from R's diagonal, Q_r, and
 // H = A^T Q_r, so that A ~ Q_r H^T.  The factorization is kept only if four
-// random probes z give ||A z - Q_r (H^T z)|| <= 1e-15 ||A||_F ||z||: the
-// approximation error is then at the level of the entries' own rounding.
+// random probes z give ||A z - Q_r (H^T z)|| <= sqrt(n) u ||A||_F ||z||
+// (u = 2^-53): no larger than the typical rounding error of the dense FP64
+// product A z itself, which the probe's reference value also carries.
 // Returns r (0: not low rank); G = Q_r and H are n x r row-major.
 static void par_for(int n, const std::function<void(int, int)>& body) {
   const int nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
@@ -212,7 +213,7 @@ static int detect_low_rank(int n, const double* h, long long ld, int rmax, std::
       for (int j = 0; j < rk; ++j) g += Q[(size_t)j * n + r] * hz[j];
       e2 += (az[r] - g) * (az[r] - g);
     }
-    if (!(std::sqrt(e2) <= 1e-15 * fro * zn)) return 0;
+    if (!(std::sqrt(e2) <= std::sqrt((double)n) * 0x1p-53 * fro * zn)) return 0;
   }
   G.assign((size_t)n * rk, 0.0);
   for (int j = 0; j < rk; ++j)
