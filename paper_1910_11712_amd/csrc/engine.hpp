@@ -159,6 +159,8 @@ struct LrJob {
   c128* Z;          // r x NL row-major
   long long offY;   // the problem's Y block
   int n, r, NL;
+  c128* Zp;         // S partial sums of Z (S x r x NL), used when S > 1
+  int S, srows;     // the sum over s cut into S ranges of srows rows
 };
 hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, const Table& tr, int resid_big, const NodeArrays& na,
                      const c128* Y, c128* R, IrState ir, int nnodes, hipStream_t st, const LrJob* lr = nullptr,

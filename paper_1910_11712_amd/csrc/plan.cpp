@@ -192,6 +192,24 @@ nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs, h
     if (!probs[p].op->a_cplx)
       for (int i = 0; i < probs[p].op->ell; ++i) zelems += (size_t)probs[p].op->lr_rank[i] * opt.N * opt.L;
   if (zelems > 0 && dlrz_.bytes < sizeof(c128) * zelems) NEP_TRY(dlrz_.alloc(sizeof(c128) * zelems));
+  // Z = H^T Y sums over the problem's n rows: cut into S ranges (at most 8,
+  // at least 512 rows each, a multiple of 64) so that enough groups run;
+  // the partial sums of one job at a time live in dlrzp_.
+  auto lr_split = [](int n, int& S, int& srows) {
+    S = std::max(1, std::min(8, n / 512));
+    srows = ((n + S - 1) / S + 63) / 64 * 64;
+    S = (n + srows - 1) / srows;
+  };
+  size_t pelems = 0;
+  for (int p = 0; p < nprob; ++p)
+    if (!probs[p].op->a_cplx)
+      for (int i = 0; i < probs[p].op->ell; ++i) {
+        int S, srows;
+        lr_split(probs[p].op->n, S, srows);
+        if (probs[p].op->lr_rank[i] > 0 && S > 1)
+          pelems = std::max(pelems, (size_t)S * probs[p].op->lr_rank[i] * opt.N * opt.L);
+      }
+  if (pelems > 0 && dlrzp_.bytes < sizeof(c128) * pelems) NEP_TRY(dlrzp_.alloc(sizeof(c128) * pelems));
   lr_jobs_.clear();
   size_t zoff = 0;
   for (int p = 0; p < nprob; ++p) {
@@ -203,7 +221,10 @@ nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs, h
       D.LrG[i] = rk > 0 ? q.op->dLrG[i] : nullptr;
       D.LrZ[i] = rk > 0 ? dlrz_.as<c128>() + zoff : nullptr;
       if (rk > 0) {
-        lr_jobs_.push_back(LrJob{q.op->dLrH[i], dlrz_.as<c128>() + zoff, D.offY, D.n, rk, opt.N * opt.L});
+        int S, srows;
+        lr_split(D.n, S, srows);
+        lr_jobs_.push_back(LrJob{q.op->dLrH[i], dlrz_.as<c128>() + zoff, D.offY, D.n, rk, opt.N * opt.L,
+                                 S > 1 ? dlrzp_.as<c128>() : nullptr, S, srows});
         zoff += (size_t)rk * opt.N * opt.L;
       }
     }

@@ -230,6 +230,7 @@ class MomentsPlan {
   std::vector<ProbDesc> hpd_;
   std::vector<LrJob> lr_jobs_;  // low-rank terms of real problems (Z = H^T Y per residual)
   DevMem dlrz_;                 // their Z blocks
+  DevMem dlrzp_;                // partial sums of one Z block (the jobs run in turn on one stream)
   std::vector<MatDesc> sorted_;
   std::vector<int> prob_of_sorted_;
   LuPlan lu_;

@@ -327,22 +327,34 @@ __global__ __launch_bounds__(64 * WR * WQ, 4) void k_resid_real(const ProbDesc* 
 }
 
 // Z = H^T Y for one low-rank term of one problem: H n x r (row-major, real),
-// Y n x NL (row-major, complex), Z r x NL.  One group per 16 rows of Z by 16
-// columns, one output per thread, s ascending in chunks of 64.
+// Y n x NL (row-major, complex), Z r x NL.  Tiles of 16 rows of Z by 16
+// columns, one output per thread; the sum over s is cut into S ranges of
+// srows rows (a multiple of 64, s ascending in chunks of 64 inside each), one
+// group per tile and range, writing its partial sum to slice sp of Zp (Z
+// itself when S == 1); k_lr_zsum then adds the S slices in order, so the
+// result does not depend on scheduling.  The row tiles of one column tile
+// and range read the same Y rows and are consecutive virtual ids: they run
+// on one XCD and the repeats come from its L2.
 __global__ __launch_bounds__(256) void k_lr_z(const double* __restrict__ H, const c128* __restrict__ Y,
-                                              c128* __restrict__ Z, int n, int r, int NL) {
+                                              c128* __restrict__ Zp, int n, int r, int NL, int S, int srows,
+                                              int total) {
   constexpr int KC = 64;
   __shared__ double Hs[KC][17];
   __shared__ c128 Ys[KC][17];
-  const int k0 = blockIdx.x * 16, c0 = blockIdx.y * 16;
+  const int v = xcd_remap(blockIdx.x, gridDim.x, total);
+  if (v < 0) return;
+  const int rb = (r + 15) / 16;
+  const int pair = v / rb, sp = pair % S;
+  const int k0 = (v % rb) * 16, c0 = (pair / S) * 16;
+  const int sbeg = sp * srows, send = min(n, sbeg + srows);
   const int tk = threadIdx.x >> 4, tc = threadIdx.x & 15;
   c128 acc = {0.0, 0.0};
-  for (int s0 = 0; s0 < n; s0 += KC) {
+  for (int s0 = sbeg; s0 < send; s0 += KC) {
     for (int e = threadIdx.x; e < KC * 16; e += 256) {
       const int s = e >> 4, j = e & 15;
       const int gs = s0 + s;
-      Hs[s][j] = (gs < n && k0 + j < r) ? H[(long long)gs * r + k0 + j] : 0.0;
-      Ys[s][j] = (gs < n && c0 + j < NL) ? Y[(long long)gs * NL + c0 + j] : c128{0.0, 0.0};
+      Hs[s][j] = (gs < send && k0 + j < r) ? H[(long long)gs * r + k0 + j] : 0.0;
+      Ys[s][j] = (gs < send && c0 + j < NL) ? Y[(long long)gs * NL + c0 + j] : c128{0.0, 0.0};
     }
     __syncthreads();
 #pragma unroll 8
@@ -354,7 +366,21 @@ __global__ __launch_bounds__(256) void k_lr_z(const double* __restrict__ H, cons
     }
     __syncthreads();
   }
-  if (k0 + tk < r && c0 + tc < NL) Z[(long long)(k0 + tk) * NL + c0 + tc] = acc;
+  if (k0 + tk < r && c0 + tc < NL) Zp[(long long)sp * r * NL + (long long)(k0 + tk) * NL + c0 + tc] = acc;
+}
+
+// Z[i] = sum over sp = 0..S-1 of Zp[sp m + i], in that order.
+__global__ __launch_bounds__(256) void k_lr_zsum(const c128* __restrict__ Zp, c128* __restrict__ Z, int S,
+                                                 long long m) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  c128 a = Zp[i];
+  for (int sp = 1; sp < S; ++sp) {
+    const c128 b = Zp[(long long)sp * m + i];
+    a.re += b.re;
+    a.im += b.im;
+  }
+  Z[i] = a;
 }
 
 // t: tiles of the complex-term kernel (64 x 64); tr: tiles of the real-term
@@ -367,10 +393,17 @@ hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, cons
                      const LrJob* lr, int nlr) {
   for (int j = 0; j < nlr; ++j) {  // Z = H^T Y of every low-rank term, before the products that use it
     const LrJob& J = lr[j];
-    hipLaunchKernelGGL(k_lr_z, dim3((J.r + 15) / 16, (J.NL + 15) / 16), dim3(256), 0, st, J.H, Y + J.offY, J.Z, J.n,
-                       J.r, J.NL);
+    const int total = ((J.r + 15) / 16) * ((J.NL + 15) / 16) * J.S;
+    hipLaunchKernelGGL(k_lr_z, dim3(xcd_grid(total)), dim3(256), 0, st, J.H, Y + J.offY, J.S > 1 ? J.Zp : J.Z, J.n,
+                       J.r, J.NL, J.S, J.srows, total);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (J.S > 1) {
+      const long long m = (long long)J.r * J.NL;
+      hipLaunchKernelGGL(k_lr_zsum, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, J.Zp, J.Z, J.S, m);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
   if (tr.total > 0) {
     constexpr int WR = 4, WQ = 2;  // 8 waves
