@@ -192,12 +192,12 @@ nep_status MomentsPlan::upload_problems(const std::vector<PlanProblem>& probs, h
     if (!probs[p].op->a_cplx)
       for (int i = 0; i < probs[p].op->ell; ++i) zelems += (size_t)probs[p].op->lr_rank[i] * opt.N * opt.L;
   if (zelems > 0 && dlrz_.bytes < sizeof(c128) * zelems) NEP_TRY(dlrz_.alloc(sizeof(c128) * zelems));
-  // Z = H^T Y sums over the problem's n rows: cut into S ranges (at most 8,
-  // at least 512 rows each, a multiple of 64) so that enough groups run;
+  // Z = H^T Y sums over the problem's n rows: cut into S ranges (at most 16,
+  // at least 256 rows each, a multiple of 32) so that enough groups run;
   // the partial sums of one job at a time live in dlrzp_.
   auto lr_split = [](int n, int& S, int& srows) {
-    S = std::max(1, std::min(8, n / 512));
-    srows = ((n + S - 1) / S + 63) / 64 * 64;
+    S = std::max(1, std::min(16, n / 256));
+    srows = ((n + S - 1) / S + 31) / 32 * 32;
     S = (n + srows - 1) / srows;
   };
   size_t pelems = 0;

@@ -327,46 +327,67 @@ __global__ __launch_bounds__(64 * WR * WQ, 4) void k_resid_real(const ProbDesc* 
 }
 
 // Z = H^T Y for one low-rank term of one problem: H n x r (row-major, real),
-// Y n x NL (row-major, complex), Z r x NL.  Tiles of 16 rows of Z by 16
-// columns, one output per thread; the sum over s is cut into S ranges of
-// srows rows (a multiple of 64, s ascending in chunks of 64 inside each), one
-// group per tile and range, writing its partial sum to slice sp of Zp (Z
-// itself when S == 1); k_lr_zsum then adds the S slices in order, so the
-// result does not depend on scheduling.  The row tiles of one column tile
-// and range read the same Y rows and are consecutive virtual ids: they run
-// on one XCD and the repeats come from its L2.
+// Y n x NL (row-major, complex), Z r x NL.  Tiles of 64 rows of Z by 32
+// columns, 4 x 2 outputs per thread (rows 4 tk .. 4 tk + 3, columns tc and
+// tc + 16), so that each value read from LDS feeds several products; the sum
+// over s is cut into S ranges of srows rows (a multiple of 32, s ascending
+// in chunks of 32 inside each), one group per tile and range, writing its
+// partial sum to slice sp of Zp (Z itself when S == 1); k_lr_zsum then adds
+// the S slices in order, so the result does not depend on scheduling.  The
+// row tiles of one column tile and range read the same Y rows and are
+// consecutive virtual ids: they run on one XCD and share its L2.
 __global__ __launch_bounds__(256) void k_lr_z(const double* __restrict__ H, const c128* __restrict__ Y,
                                               c128* __restrict__ Zp, int n, int r, int NL, int S, int srows,
                                               int total) {
-  constexpr int KC = 64;
-  __shared__ double Hs[KC][17];
-  __shared__ c128 Ys[KC][17];
+  constexpr int KC = 32;
+  __shared__ __align__(16) double Hs[KC][66];
+  __shared__ c128 Ys[KC][33];
   const int v = xcd_remap(blockIdx.x, gridDim.x, total);
   if (v < 0) return;
-  const int rb = (r + 15) / 16;
+  const int rb = (r + 63) / 64;
   const int pair = v / rb, sp = pair % S;
-  const int k0 = (v % rb) * 16, c0 = (pair / S) * 16;
+  const int k0 = (v % rb) * 64, c0 = (pair / S) * 32;
   const int sbeg = sp * srows, send = min(n, sbeg + srows);
   const int tk = threadIdx.x >> 4, tc = threadIdx.x & 15;
-  c128 acc = {0.0, 0.0};
+  c128 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i][0] = acc[i][1] = c128{0.0, 0.0};
   for (int s0 = sbeg; s0 < send; s0 += KC) {
-    for (int e = threadIdx.x; e < KC * 16; e += 256) {
-      const int s = e >> 4, j = e & 15;
+    for (int e = threadIdx.x; e < KC * 64; e += 256) {
+      const int s = e >> 6, j = e & 63;
       const int gs = s0 + s;
       Hs[s][j] = (gs < send && k0 + j < r) ? H[(long long)gs * r + k0 + j] : 0.0;
+    }
+    for (int e = threadIdx.x; e < KC * 32; e += 256) {
+      const int s = e >> 5, j = e & 31;
+      const int gs = s0 + s;
       Ys[s][j] = (gs < send && c0 + j < NL) ? Y[(long long)gs * NL + c0 + j] : c128{0.0, 0.0};
     }
     __syncthreads();
-#pragma unroll 8
+#pragma unroll 4
     for (int s = 0; s < KC; ++s) {
-      const double h = Hs[s][tk];
-      const c128 y = Ys[s][tc];
-      acc.re += h * y.re;
-      acc.im += h * y.im;
+      const double2 ha = *reinterpret_cast<const double2*>(&Hs[s][4 * tk]);
+      const double2 hb = *reinterpret_cast<const double2*>(&Hs[s][4 * tk + 2]);
+      const c128 y0 = Ys[s][tc], y1 = Ys[s][tc + 16];
+      const double h[4] = {ha.x, ha.y, hb.x, hb.y};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        acc[i][0].re += h[i] * y0.re;
+        acc[i][0].im += h[i] * y0.im;
+        acc[i][1].re += h[i] * y1.re;
+        acc[i][1].im += h[i] * y1.im;
+      }
     }
     __syncthreads();
   }
-  if (k0 + tk < r && c0 + tc < NL) Zp[(long long)sp * r * NL + (long long)(k0 + tk) * NL + c0 + tc] = acc;
+  c128* out = Zp + (long long)sp * r * NL;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int k = k0 + 4 * tk + i;
+    if (k >= r) break;
+    if (c0 + tc < NL) out[(long long)k * NL + c0 + tc] = acc[i][0];
+    if (c0 + tc + 16 < NL) out[(long long)k * NL + c0 + tc + 16] = acc[i][1];
+  }
 }
 
 // Z[i] = sum over sp = 0..S-1 of Zp[sp m + i], in that order.
@@ -393,7 +414,7 @@ hipError_t resid_run(const ProbDesc* pd, const int* prefix, const Table& t, cons
                      const LrJob* lr, int nlr) {
   for (int j = 0; j < nlr; ++j) {  // Z = H^T Y of every low-rank term, before the products that use it
     const LrJob& J = lr[j];
-    const int total = ((J.r + 15) / 16) * ((J.NL + 15) / 16) * J.S;
+    const int total = ((J.r + 63) / 64) * ((J.NL + 31) / 32) * J.S;
     hipLaunchKernelGGL(k_lr_z, dim3(xcd_grid(total)), dim3(256), 0, st, J.H, Y + J.offY, J.S > 1 ? J.Zp : J.Z, J.n,
                        J.r, J.NL, J.S, J.srows, total);
     hipError_t e = hipGetLastError();
